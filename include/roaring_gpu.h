@@ -1,0 +1,224 @@
+/*
+ * roaring_gpu.h - C ABI of the MI355X (gfx950) Roaring-bitmap set-operation
+ * library. All device work runs in the library's own HIP kernels.
+ *
+ * Paper: Lemire et al., "Roaring Bitmaps: Implementation of an Optimized
+ * Software Library" (arXiv:1709.07821).
+ *
+ * ---------------------------------------------------------------------------
+ * Data format (Section 1, Figure 1; Section 2.2; Section 3.2)
+ * ---------------------------------------------------------------------------
+ * A bitmap is a set of uint32 values. Its values are grouped by their 16 high
+ * bits (the key); each non-empty group is one container that stores the 16
+ * low bits in one of three forms:
+ *   RG_ARRAY  - c sorted distinct uint16 (c <= 4096), 2c bytes;
+ *   RG_BITSET - 1024 uint64 words, value x at bit (x & 63) of word (x >> 6)
+ *               (Section 3.2 bit addressing), 8192 bytes;
+ *   RG_RUN    - r pairs (start, length-1) of uint16, sorted, disjoint and
+ *               maximal (no two runs touch), 4r bytes. A full chunk is the
+ *               single pair (0, 65535).
+ * Every container is in the least-memory form allowed by the Section 1 size
+ * rules ("P1"): run if (c <= 4096 ? 2r < c : r <= 2047), else array if
+ * c <= 4096, else bitset (r = number of maximal runs). Empty containers are
+ * never stored (Section 2.2). The library's outputs always obey these rules;
+ * its inputs must (rg_pool_validate checks them).
+ *
+ * A pool holds many bitmaps in structure-of-arrays form in device memory.
+ * Containers of bitmap b are [bm_begin[b], bm_begin[b+1]) with strictly
+ * ascending keys. Every payload offset is a multiple of 16 and the payload
+ * buffer may be read in whole 16-byte units up to the end of each container's
+ * last 16-byte unit (so payload_bytes is a multiple of 16).
+ *
+ * Ownership: every pointer in rg_pool / rg_out is device memory owned by the
+ * caller (in practice torch tensors). The library only reads pools and only
+ * writes the rg_out buffers and its own workspace (held by the context).
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
+ * Calls enqueue work on it. Calls that must size their launches or report
+ * capacity read small counters back from the device, so they synchronise the
+ * stream at those points; on return from a successful call every result has
+ * been computed or is enqueued on `stream` (synchronise before reading).
+ *
+ * Errors: every call returns an rg_status; on failure rg_last_error(ctx)
+ * describes it. Outputs are unspecified after a failed call.
+ */
+#ifndef ROARING_GPU_H
+#define ROARING_GPU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RG_OK = 0,
+    RG_EINVAL = -1,     /* bad argument (null pointer, index out of range, bad op) */
+    RG_ECAPACITY = -2,  /* rg_out too small; needed_* fields say what is needed */
+    RG_EDEVICE = -3,    /* a HIP runtime call failed */
+    RG_EFORMAT = -4,    /* pool violates the container format (validation) */
+    RG_ENOTSUP = -5     /* not supported */
+} rg_status;
+
+typedef enum { RG_ARRAY = 1, RG_BITSET = 2, RG_RUN = 3 } rg_ctype;
+
+/* The four operations of Section 1: intersection, union, symmetric
+ * difference, and difference A \ B (Section 4.4 direction). */
+typedef enum { RG_AND = 0, RG_OR = 1, RG_XOR = 2, RG_ANDNOT = 3 } rg_op;
+
+/* roaring_batch flags */
+#define RG_FLAG_MATERIALIZE 1u /* build the result bitmaps into rg_out */
+#define RG_FLAG_CARD 2u        /* write |result| per pair into d_cards (uint64) */
+#define RG_FLAG_JACCARD 4u     /* write |A n B| / |A u B| per pair into d_jacc (binary64) */
+
+typedef struct rg_ctx rg_ctx;
+
+/* Read-only pool of bitmaps (device pointers). */
+typedef struct rg_pool {
+    uint32_t n_bitmaps;
+    uint64_t n_containers;     /* < 2^32 */
+    uint64_t payload_bytes;    /* multiple of 16 */
+    const uint64_t *bm_begin;  /* [n_bitmaps + 1], bm_begin[n_bitmaps] == n_containers */
+    const uint16_t *keys;      /* [n_containers], ascending within a bitmap */
+    const uint8_t *types;      /* [n_containers], rg_ctype */
+    const uint32_t *card;      /* [n_containers], 1..65536 */
+    const uint32_t *size;      /* [n_containers], array: c, bitset: 1024, run: r */
+    const uint64_t *off;       /* [n_containers], byte offset into payload, multiple of 16 */
+    const uint8_t *payload;    /* [payload_bytes] */
+    const uint64_t *bm_card;   /* [n_bitmaps], total cardinality of each bitmap */
+    const uint64_t *bm_wbytes; /* [n_bitmaps], sum over its containers of
+                                  roundup16(min(8192, 2 * card)): bounds result payloads */
+} rg_pool;
+
+/* Caller-provided output arena (device pointers) for materialised results:
+ * result bitmap p (one per pair) occupies containers [bm_begin[p],
+ * bm_begin[p+1]). Container payloads are written at 16-byte-aligned offsets
+ * inside per-container slots, so payload may contain unused gaps. */
+typedef struct rg_out {
+    uint64_t cap_containers;       /* in: entries available in keys/types/card/size/off */
+    uint64_t cap_payload_bytes;    /* in: bytes available in payload */
+    uint64_t *bm_begin;            /* [n_pairs + 1] */
+    uint16_t *keys;
+    uint8_t *types;
+    uint32_t *card;
+    uint32_t *size;
+    uint64_t *off;
+    uint8_t *payload;
+    uint64_t *bm_card;             /* [n_pairs] */
+    uint64_t *bm_wbytes;           /* [n_pairs], may be NULL; makes the output usable as a pool */
+    uint64_t needed_containers;    /* out (host): upper bound the call requires */
+    uint64_t needed_payload_bytes; /* out (host): payload bytes the call requires */
+    uint64_t n_containers;         /* out (host): containers written */
+    uint64_t payload_used;         /* out (host): end of the last written slot */
+} rg_out;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device`. The context owns a growable device
+ * workspace and pinned host staging; it is not thread-safe (one per thread). */
+rg_status rg_create(rg_ctx **ctx, int device);
+void rg_destroy(rg_ctx *ctx);
+const char *rg_last_error(const rg_ctx *ctx);
+
+/* ---- two-bitmap operations (Section 1 operations; Section 5.7: inputs are
+ * left unchanged and the result is built as a new bitmap) ----------------- */
+
+/* Result of A[ia] op B[ib] into `out` (one result bitmap). Returns
+ * RG_ECAPACITY with out->needed_* filled if the arena is too small. */
+rg_status roaring_and(rg_ctx *ctx, const rg_pool *A, uint32_t ia, const rg_pool *B, uint32_t ib, rg_out *out,
+                      void *stream);
+rg_status roaring_or(rg_ctx *ctx, const rg_pool *A, uint32_t ia, const rg_pool *B, uint32_t ib, rg_out *out,
+                     void *stream);
+rg_status roaring_xor(rg_ctx *ctx, const rg_pool *A, uint32_t ia, const rg_pool *B, uint32_t ib, rg_out *out,
+                      void *stream);
+rg_status roaring_andnot(rg_ctx *ctx, const rg_pool *A, uint32_t ia, const rg_pool *B, uint32_t ib, rg_out *out,
+                         void *stream);
+
+/* |A[ia] op B[ib]| into device uint64 *d_card, without building the result
+ * (Section 4.1.2 fused operation + population count; Section 5.9). */
+rg_status roaring_and_cardinality(rg_ctx *ctx, const rg_pool *A, uint32_t ia, const rg_pool *B, uint32_t ib,
+                                  uint64_t *d_card, void *stream);
+rg_status roaring_or_cardinality(rg_ctx *ctx, const rg_pool *A, uint32_t ia, const rg_pool *B, uint32_t ib,
+                                 uint64_t *d_card, void *stream);
+rg_status roaring_xor_cardinality(rg_ctx *ctx, const rg_pool *A, uint32_t ia, const rg_pool *B, uint32_t ib,
+                                  uint64_t *d_card, void *stream);
+rg_status roaring_andnot_cardinality(rg_ctx *ctx, const rg_pool *A, uint32_t ia, const rg_pool *B, uint32_t ib,
+                                     uint64_t *d_card, void *stream);
+
+/* Jaccard index |A n B| / |A u B| (Section 5.9) into device double *d_j:
+ * exact integer counts, then one IEEE binary64 round-to-nearest division;
+ * two empty sets give 1.0. */
+rg_status roaring_jaccard(rg_ctx *ctx, const rg_pool *A, uint32_t ia, const rg_pool *B, uint32_t ib, double *d_j,
+                          void *stream);
+
+/* Batched: for p < n_pairs, A[d_ia[p]] op B[d_ib[p]] (d_ia, d_ib device
+ * uint32 arrays). flags: RG_FLAG_MATERIALIZE (results into out, result
+ * bitmap p = pair p), RG_FLAG_CARD (|result| into d_cards[p]),
+ * RG_FLAG_JACCARD (Jaccard of the two inputs into d_jacc[p]; derived from
+ * the same count through the Section 5.9 identities). */
+rg_status roaring_batch(rg_ctx *ctx, int op, const rg_pool *A, const rg_pool *B, const uint32_t *d_ia,
+                        const uint32_t *d_ib, uint64_t n_pairs, uint32_t flags, rg_out *out, uint64_t *d_cards,
+                        double *d_jacc, void *stream);
+
+/* Kernel-variant selection for matched container pairs. Every variant
+ * computes the same result; they differ only in speed.
+ *   mode RG_DISPATCH_HEURISTIC (default): size-ratio / type heuristic;
+ *   mode RG_DISPATCH_FIXED: use `variant` wherever it applies to the pair's
+ *   container types, the generic variant elsewhere (bitset-bitset pairs
+ *   always use their own kernel). */
+#define RG_DISPATCH_HEURISTIC 0
+#define RG_DISPATCH_FIXED 2
+#define RG_V_GENERIC 2   /* both sides expanded to LDS bitsets, any types */
+#define RG_V_MERGE 3     /* array-array merge */
+#define RG_V_GALLOP 4    /* array-array galloping search (Section 2.2) */
+#define RG_V_PROBE 5     /* array-bitset probe / set / clear / flip (Section 3.2) */
+#define RG_V_RUNMERGE 6  /* run-run and run-array interval merge */
+rg_status rg_set_dispatch(rg_ctx *ctx, int mode, int variant);
+
+/* Kernel timing. When enabled, every compute-kernel launch of a call is
+ * bracketed by two HIP events recorded on the call's stream; rg_profile_read
+ * waits for them and returns the accumulated time, launch count and number of
+ * container pairs processed for one variant (RG_V_* or 0 for the
+ * bitset-bitset kernel, 1 for one-sided copies, 7 for the bitset pairs redone
+ * by the generic kernel) in count-only (materialize = 0) or materialising
+ * form. Synchronises on the recorded events; costs two events per launch. */
+rg_status rg_profile_enable(rg_ctx *ctx, int on);
+rg_status rg_profile_reset(rg_ctx *ctx);
+rg_status rg_profile_read(rg_ctx *ctx, int variant, int materialize, double *total_ms, uint64_t *launches,
+                          uint64_t *items);
+
+/* ---- pools -------------------------------------------------------------- */
+
+/* Host-side pool construction from sorted values. Bitmap b holds
+ * values[offsets[b] .. offsets[b+1]) (strictly increasing uint32).
+ * rg_pool_measure_host gives the sizes; rg_pool_build_host fills host arrays
+ * of those sizes (payload zero-padded to 16-byte units) in the format above.
+ * Returns RG_EINVAL if a bitmap's values are not strictly increasing. */
+rg_status rg_pool_measure_host(const uint32_t *values, const uint64_t *offsets, uint32_t n_bitmaps,
+                               uint64_t *n_containers, uint64_t *payload_bytes);
+rg_status rg_pool_build_host(const uint32_t *values, const uint64_t *offsets, uint32_t n_bitmaps, uint64_t *bm_begin,
+                             uint16_t *keys, uint8_t *types, uint32_t *card, uint32_t *size, uint64_t *off,
+                             uint8_t *payload, uint64_t *bm_card, uint64_t *bm_wbytes);
+
+/* Recompute card (from payload), bm_card and bm_wbytes of a device pool whose
+ * bm_begin/keys/types/size/off/payload are set. The card/bm_card/bm_wbytes
+ * pointers of `pool` are written through (they must be writable). */
+rg_status rg_pool_recount(rg_ctx *ctx, const rg_pool *pool, void *stream);
+
+/* Check every container of a device pool against the format rules above;
+ * *n_bad (host) receives the number of offending containers. Synchronises. */
+rg_status rg_pool_validate(rg_ctx *ctx, const rg_pool *pool, uint64_t *n_bad, void *stream);
+
+/* Per-bitmap fingerprint of the container form into device uint64
+ * d_digest[n_bitmaps]: the sum, over containers and their serialised 64-bit
+ * words w_i (w0 = key | type << 16 | card << 32, w1 = size, then the payload
+ * packed little-endian into 64-bit words, zero padded), of
+ * mix64(w_i + (key * 2^20 + i + 1) * 0x9E3779B97F4A7C15) mod 2^64, with mix64
+ * the SplitMix64 finalizer. */
+rg_status rg_pool_digest(rg_ctx *ctx, const rg_pool *pool, uint64_t *d_digest, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ROARING_GPU_H */

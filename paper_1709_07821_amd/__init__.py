@@ -1,0 +1,365 @@
+"""Python binding of libroaring_gpu.so - Roaring-bitmap set operations on
+MI355X (gfx950). Argument marshalling only: every step of every operation
+runs in the library's HIP kernels. torch supplies device memory and streams.
+
+The C names are kept: ``roaring_and/or/xor/andnot``, their
+``_cardinality`` forms, ``roaring_jaccard`` and ``roaring_batch``, plus pool
+construction (``Pool.from_sets``, ``Pool.from_dense_words``) and the pool
+utilities ``rg_pool_recount/validate/digest``.
+
+There is no CPU fallback: if the HIP library is missing, importing the
+binding's entry points raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libroaring_gpu.so")
+
+RG_OK, RG_EINVAL, RG_ECAPACITY, RG_EDEVICE, RG_EFORMAT, RG_ENOTSUP = 0, -1, -2, -3, -4, -5
+RG_ARRAY, RG_BITSET, RG_RUN = 1, 2, 3
+RG_AND, RG_OR, RG_XOR, RG_ANDNOT = 0, 1, 2, 3
+OPS = {"and": RG_AND, "or": RG_OR, "xor": RG_XOR, "andnot": RG_ANDNOT}
+RG_FLAG_MATERIALIZE, RG_FLAG_CARD, RG_FLAG_JACCARD = 1, 2, 4
+RG_DISPATCH_HEURISTIC, RG_DISPATCH_FIXED = 0, 2
+VARIANTS = {"generic": 2, "merge": 3, "gallop": 4, "probe": 5, "runmerge": 6}
+
+# every symbol the C header declares
+EXPORTS = ["rg_create", "rg_destroy", "rg_last_error", "rg_set_dispatch", "roaring_and", "roaring_or", "roaring_xor",
+           "roaring_andnot", "roaring_and_cardinality", "roaring_or_cardinality", "roaring_xor_cardinality",
+           "roaring_andnot_cardinality", "roaring_jaccard", "roaring_batch", "rg_pool_measure_host",
+           "rg_pool_build_host", "rg_pool_recount", "rg_pool_validate", "rg_pool_digest", "rg_profile_enable",
+           "rg_profile_reset", "rg_profile_read"]
+
+
+class RoaringError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+class rg_pool(ctypes.Structure):
+    _fields_ = [("n_bitmaps", ctypes.c_uint32), ("n_containers", ctypes.c_uint64),
+                ("payload_bytes", ctypes.c_uint64), ("bm_begin", ctypes.c_void_p), ("keys", ctypes.c_void_p),
+                ("types", ctypes.c_void_p), ("card", ctypes.c_void_p), ("size", ctypes.c_void_p),
+                ("off", ctypes.c_void_p), ("payload", ctypes.c_void_p), ("bm_card", ctypes.c_void_p),
+                ("bm_wbytes", ctypes.c_void_p)]
+
+
+class rg_out(ctypes.Structure):
+    _fields_ = [("cap_containers", ctypes.c_uint64), ("cap_payload_bytes", ctypes.c_uint64),
+                ("bm_begin", ctypes.c_void_p), ("keys", ctypes.c_void_p), ("types", ctypes.c_void_p),
+                ("card", ctypes.c_void_p), ("size", ctypes.c_void_p), ("off", ctypes.c_void_p),
+                ("payload", ctypes.c_void_p), ("bm_card", ctypes.c_void_p), ("bm_wbytes", ctypes.c_void_p),
+                ("needed_containers", ctypes.c_uint64), ("needed_payload_bytes", ctypes.c_uint64),
+                ("n_containers", ctypes.c_uint64), ("payload_used", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, V, U32, U64, I = ctypes.POINTER, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+        pool_p, out_p = P(rg_pool), P(rg_out)
+        L.rg_create.argtypes = [P(V), I]
+        L.rg_destroy.argtypes = [V]
+        L.rg_destroy.restype = None
+        L.rg_last_error.argtypes = [V]
+        L.rg_last_error.restype = ctypes.c_char_p
+        L.rg_set_dispatch.argtypes = [V, I, I]
+        for nm in ("roaring_and", "roaring_or", "roaring_xor", "roaring_andnot"):
+            getattr(L, nm).argtypes = [V, pool_p, U32, pool_p, U32, out_p, V]
+        for nm in ("roaring_and_cardinality", "roaring_or_cardinality", "roaring_xor_cardinality",
+                   "roaring_andnot_cardinality", "roaring_jaccard"):
+            getattr(L, nm).argtypes = [V, pool_p, U32, pool_p, U32, V, V]
+        L.roaring_batch.argtypes = [V, I, pool_p, pool_p, V, V, U64, U32, out_p, V, V, V]
+        L.rg_pool_measure_host.argtypes = [V, V, U32, P(U64), P(U64)]
+        L.rg_pool_build_host.argtypes = [V, V, U32] + [V] * 9
+        L.rg_pool_recount.argtypes = [V, pool_p, V]
+        L.rg_pool_validate.argtypes = [V, pool_p, P(U64), V]
+        L.rg_pool_digest.argtypes = [V, pool_p, V, V]
+        L.rg_profile_enable.argtypes = [V, I]
+        L.rg_profile_reset.argtypes = [V]
+        L.rg_profile_read.argtypes = [V, I, I, P(ctypes.c_double), P(U64), P(U64)]
+        for nm in EXPORTS:
+            if nm not in ("rg_destroy", "rg_last_error"):
+                getattr(L, nm).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Context:
+    """Owns an rg_ctx (workspace, pinned staging) on one device."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        st = lib().rg_create(ctypes.byref(h), device)
+        if st != RG_OK:
+            raise RoaringError(st, f"rg_create failed on device {device}")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().rg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st):
+        if st != RG_OK:
+            raise RoaringError(st, lib().rg_last_error(self.h).decode())
+        return st
+
+    def set_dispatch(self, mode: int = RG_DISPATCH_HEURISTIC, variant: int = 2):
+        self.check(lib().rg_set_dispatch(self.h, mode, variant))
+
+
+class Pool:
+    """A pool of bitmaps in device memory (torch tensors) and its rg_pool view."""
+
+    def __init__(self, n_bitmaps, n_containers, payload_bytes, bm_begin, keys, types, card, size, off, payload,
+                 bm_card, bm_wbytes):
+        self.n_bitmaps = int(n_bitmaps)
+        self.n_containers = int(n_containers)
+        self.payload_bytes = int(payload_bytes)
+        self.bm_begin, self.keys, self.types, self.card = bm_begin, keys, types, card
+        self.size, self.off, self.payload, self.bm_card, self.bm_wbytes = size, off, payload, bm_card, bm_wbytes
+        self._c = rg_pool(self.n_bitmaps, self.n_containers, self.payload_bytes, _ptr(bm_begin).value,
+                          _ptr(keys).value, _ptr(types).value, _ptr(card).value, _ptr(size).value, _ptr(off).value,
+                          _ptr(payload).value, _ptr(bm_card).value, _ptr(bm_wbytes).value)
+
+    @property
+    def c(self):
+        return self._c
+
+    @staticmethod
+    def host_arrays(values, offsets):
+        """rg_pool_measure_host + rg_pool_build_host: numpy arrays of the pool format."""
+        values = np.ascontiguousarray(values, dtype=np.uint32)
+        offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+        n = len(offsets) - 1
+        L = lib()
+        nc, pb = ctypes.c_uint64(), ctypes.c_uint64()
+        st = L.rg_pool_measure_host(values.ctypes.data, offsets.ctypes.data, n, ctypes.byref(nc), ctypes.byref(pb))
+        if st != RG_OK:
+            raise RoaringError(st, "rg_pool_measure_host: values must be strictly increasing per bitmap")
+        nc, pb = nc.value, pb.value
+        a = {"bm_begin": np.zeros(n + 1, np.uint64), "keys": np.zeros(nc, np.uint16),
+             "types": np.zeros(nc, np.uint8), "card": np.zeros(nc, np.uint32), "size": np.zeros(nc, np.uint32),
+             "off": np.zeros(nc, np.uint64), "payload": np.zeros(max(pb, 16), np.uint8),
+             "bm_card": np.zeros(n, np.uint64), "bm_wbytes": np.zeros(n, np.uint64)}
+        st = L.rg_pool_build_host(values.ctypes.data, offsets.ctypes.data, n,
+                                  *[a[k].ctypes.data for k in ("bm_begin", "keys", "types", "card", "size", "off",
+                                                               "payload", "bm_card", "bm_wbytes")])
+        if st != RG_OK:
+            raise RoaringError(st, "rg_pool_build_host failed")
+        return n, nc, pb, a
+
+    @staticmethod
+    def from_sets(values, offsets, device="cuda"):
+        torch = _torch()
+        n, nc, pb, a = Pool.host_arrays(values, offsets)
+
+        def dev(x, dt):
+            return torch.from_numpy(x.view(dt)).to(device)
+
+        return Pool(n, nc, max(pb, 16), dev(a["bm_begin"], np.int64), dev(a["keys"], np.int16),
+                    dev(a["types"], np.uint8), dev(a["card"], np.int32), dev(a["size"], np.int32),
+                    dev(a["off"], np.int64), dev(a["payload"], np.uint8), dev(a["bm_card"], np.int64),
+                    dev(a["bm_wbytes"], np.int64))
+
+    @staticmethod
+    def from_dense_words(ctx: Context, words, n_bitmaps: int, n_keys: int, stream=None):
+        """Pool over a device buffer of [n_bitmaps][n_keys][1024] uint64 bitset words
+        (keys 0..n_keys-1 in every bitmap); cardinalities come from rg_pool_recount."""
+        torch = _torch()
+        dev = words.device
+        nc = n_bitmaps * n_keys
+        bm_begin = torch.arange(0, nc + 1, n_keys, dtype=torch.int64, device=dev)
+        keys = torch.arange(n_keys, dtype=torch.int16, device=dev).repeat(n_bitmaps)
+        types = torch.full((nc,), RG_BITSET, dtype=torch.uint8, device=dev)
+        card = torch.zeros(nc, dtype=torch.int32, device=dev)
+        size = torch.full((nc,), 1024, dtype=torch.int32, device=dev)
+        off = torch.arange(nc, dtype=torch.int64, device=dev) * 8192
+        bm_card = torch.zeros(n_bitmaps, dtype=torch.int64, device=dev)
+        bm_wbytes = torch.zeros(n_bitmaps, dtype=torch.int64, device=dev)
+        payload = words.view(torch.uint8).reshape(-1)
+        p = Pool(n_bitmaps, nc, nc * 8192, bm_begin, keys, types, card, size, off, payload, bm_card, bm_wbytes)
+        rg_pool_recount(ctx, p, stream)
+        return p
+
+    def to_host(self):
+        """Copies of the pool arrays as numpy (for inspection and tests)."""
+        f = lambda t, dt: t.detach().cpu().numpy().view(dt)
+        return {"bm_begin": f(self.bm_begin, np.uint64), "keys": f(self.keys, np.uint16),
+                "types": f(self.types, np.uint8), "card": f(self.card, np.uint32), "size": f(self.size, np.uint32),
+                "off": f(self.off, np.uint64), "payload": f(self.payload, np.uint8),
+                "bm_card": f(self.bm_card, np.uint64), "bm_wbytes": f(self.bm_wbytes, np.uint64)}
+
+
+class OutArena:
+    """Device buffers of an rg_out for n result bitmaps."""
+
+    def __init__(self, n_pairs: int, cap_containers: int, cap_payload: int, device="cuda"):
+        torch = _torch()
+        cap_containers = max(int(cap_containers), 1)
+        cap_payload = max((int(cap_payload) + 15) // 16 * 16, 16)
+        self.n_pairs = n_pairs
+        self.bm_begin = torch.zeros(n_pairs + 1, dtype=torch.int64, device=device)
+        self.keys = torch.empty(cap_containers, dtype=torch.int16, device=device)
+        self.types = torch.empty(cap_containers, dtype=torch.uint8, device=device)
+        self.card = torch.empty(cap_containers, dtype=torch.int32, device=device)
+        self.size = torch.empty(cap_containers, dtype=torch.int32, device=device)
+        self.off = torch.empty(cap_containers, dtype=torch.int64, device=device)
+        self.payload = torch.empty(cap_payload, dtype=torch.uint8, device=device)
+        self.bm_card = torch.zeros(max(n_pairs, 1), dtype=torch.int64, device=device)
+        self.bm_wbytes = torch.zeros(max(n_pairs, 1), dtype=torch.int64, device=device)
+        self.c = rg_out(cap_containers, cap_payload, self.bm_begin.data_ptr(), self.keys.data_ptr(),
+                        self.types.data_ptr(), self.card.data_ptr(), self.size.data_ptr(), self.off.data_ptr(),
+                        self.payload.data_ptr(), self.bm_card.data_ptr(), self.bm_wbytes.data_ptr(), 0, 0, 0, 0)
+
+    def as_pool(self) -> Pool:
+        n = int(self.c.n_containers)
+        return Pool(self.n_pairs, n, self.payload.numel(), self.bm_begin, self.keys, self.types, self.card,
+                    self.size, self.off, self.payload, self.bm_card, self.bm_wbytes)
+
+
+# ---------------------------------------------------------------- C names
+
+def roaring_batch(ctx: Context, op, A: Pool, B: Pool, ia, ib, flags: int, out: OutArena | None = None,
+                  cards=None, jacc=None, stream=None) -> int:
+    """Thin wrapper of roaring_batch(): ia, ib are device uint32 (torch int32) tensors."""
+    op = OPS[op] if isinstance(op, str) else op
+    n = int(ia.numel())
+    return lib().roaring_batch(ctx.h, op, ctypes.byref(A.c), ctypes.byref(B.c), _ptr(ia), _ptr(ib), n, flags,
+                               ctypes.byref(out.c) if out is not None else None, _ptr(cards), _ptr(jacc),
+                               _stream(stream))
+
+
+def _single_mat(name):
+    def f(ctx: Context, A: Pool, ia: int, B: Pool, ib: int, out: OutArena, stream=None) -> int:
+        return getattr(lib(), name)(ctx.h, ctypes.byref(A.c), ia, ctypes.byref(B.c), ib, ctypes.byref(out.c),
+                                    _stream(stream))
+    f.__name__ = name
+    return f
+
+
+def _single_card(name):
+    def f(ctx: Context, A: Pool, ia: int, B: Pool, ib: int, d_out, stream=None) -> int:
+        return getattr(lib(), name)(ctx.h, ctypes.byref(A.c), ia, ctypes.byref(B.c), ib, _ptr(d_out),
+                                    _stream(stream))
+    f.__name__ = name
+    return f
+
+
+roaring_and = _single_mat("roaring_and")
+roaring_or = _single_mat("roaring_or")
+roaring_xor = _single_mat("roaring_xor")
+roaring_andnot = _single_mat("roaring_andnot")
+roaring_and_cardinality = _single_card("roaring_and_cardinality")
+roaring_or_cardinality = _single_card("roaring_or_cardinality")
+roaring_xor_cardinality = _single_card("roaring_xor_cardinality")
+roaring_andnot_cardinality = _single_card("roaring_andnot_cardinality")
+roaring_jaccard = _single_card("roaring_jaccard")
+
+
+def rg_pool_recount(ctx: Context, pool: Pool, stream=None):
+    ctx.check(lib().rg_pool_recount(ctx.h, ctypes.byref(pool.c), _stream(stream)))
+
+
+def rg_pool_validate(ctx: Context, pool: Pool, stream=None) -> int:
+    bad = ctypes.c_uint64()
+    ctx.check(lib().rg_pool_validate(ctx.h, ctypes.byref(pool.c), ctypes.byref(bad), _stream(stream)))
+    return int(bad.value)
+
+
+def rg_pool_digest(ctx: Context, pool: Pool, stream=None):
+    torch = _torch()
+    d = torch.zeros(max(pool.n_bitmaps, 1), dtype=torch.int64, device=pool.bm_begin.device)
+    ctx.check(lib().rg_pool_digest(ctx.h, ctypes.byref(pool.c), _ptr(d), _stream(stream)))
+    return d[:pool.n_bitmaps]
+
+
+PROFILE_CLASSES = {0: "bb", 1: "copy", 2: "generic", 3: "merge", 4: "gallop", 5: "probe", 6: "runmerge",
+                   7: "bb-redo"}
+
+
+def profile_enable(ctx: Context, on: bool = True):
+    ctx.check(lib().rg_profile_enable(ctx.h, 1 if on else 0))
+
+
+def profile_reset(ctx: Context):
+    ctx.check(lib().rg_profile_reset(ctx.h))
+
+
+def profile_read(ctx: Context):
+    """{(class name, materialize): {"ms", "launches", "items"}} for classes that ran."""
+    out = {}
+    for v, name in PROFILE_CLASSES.items():
+        for m in (0, 1):
+            ms, n, it = ctypes.c_double(), ctypes.c_uint64(), ctypes.c_uint64()
+            ctx.check(lib().rg_profile_read(ctx.h, v, m, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(it)))
+            if n.value:
+                out[(name, bool(m))] = {"ms": ms.value, "launches": n.value, "items": it.value}
+    return out
+
+
+# ---------------------------------------------------------------- conveniences
+
+def batch(ctx: Context, op, A: Pool, B: Pool, ia, ib, materialize=True, card=False, jaccard=False, out=None,
+          stream=None):
+    """roaring_batch with arena sizing: returns (out_arena or None, cards or None, jacc or None)."""
+    torch = _torch()
+    dev = A.bm_begin.device
+    n = int(ia.numel())
+    flags = (RG_FLAG_MATERIALIZE if materialize else 0) | (RG_FLAG_CARD if card else 0) | \
+        (RG_FLAG_JACCARD if jaccard else 0)
+    cards = torch.zeros(max(n, 1), dtype=torch.int64, device=dev) if card else None
+    jacc = torch.zeros(max(n, 1), dtype=torch.float64, device=dev) if jaccard else None
+    done = False
+    if materialize and out is None:
+        # first call with an empty arena: either nothing is needed, or it reports the sizes
+        out = OutArena(n, 0, 0, dev)
+        out.c.cap_containers = 0
+        out.c.cap_payload_bytes = 0
+        st = roaring_batch(ctx, op, A, B, ia, ib, flags, out, cards, jacc, stream)
+        if st == RG_ECAPACITY:
+            out = OutArena(n, out.c.needed_containers, out.c.needed_payload_bytes, dev)
+        else:
+            ctx.check(st)
+            done = True
+    if not done:
+        ctx.check(roaring_batch(ctx, op, A, B, ia, ib, flags, out, cards, jacc, stream))
+    return out, (cards[:n] if card else None), (jacc[:n] if jaccard else None)

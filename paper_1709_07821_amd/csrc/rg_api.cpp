@@ -1,0 +1,578 @@
+// rg_api.cpp - the C ABI: context, workspace, and the orchestration of one
+// batched call (pair preparation -> key matching in waves -> binned compute
+// kernels -> output assembly or count finishing).
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "rg_internal.h"
+
+using namespace rg;
+
+struct rg_ctx {
+    int device = 0;
+    std::string err;
+    void* ws_pairs = nullptr;  // per-pair arrays
+    size_t ws_pairs_bytes = 0;
+    void* ws_wave = nullptr;   // per-slot arrays of one wave
+    size_t ws_wave_bytes = 0;
+    void* small = nullptr;     // 4 KiB of counters
+    void* host = nullptr;      // pinned staging
+    size_t host_bytes = 0;
+    // kernel timing (rg_profile_*): events around each compute-kernel launch
+    struct Pending {
+        hipEvent_t a, b;
+        int cls;
+        int mat;
+        uint64_t items;
+    };
+    bool prof = false;
+    std::vector<Pending> pend;
+    std::vector<hipEvent_t> evpool;
+    double prof_ms[NBINS][2] = {};
+    uint64_t prof_launches[NBINS][2] = {};
+    uint64_t prof_items[NBINS][2] = {};
+    int dispatch_mode = RG_DISPATCH_HEURISTIC;
+    int fixed_bin = BIN_GEN;
+    uint32_t gallop_ratio = 64;
+    uint64_t max_wave_slots = 1ull << 24;
+};
+
+namespace {
+
+rg_status fail(rg_ctx* c, rg_status s, const std::string& m) {
+    if (c) c->err = m;
+    return s;
+}
+
+#define HIPCHK(ctx, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) return fail(ctx, RG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+rg_status grow_device(rg_ctx* c, void** buf, size_t* cap, size_t need) {
+    if (need <= *cap) return RG_OK;
+    if (*buf) {
+        HIPCHK(c, hipDeviceSynchronize());
+        HIPCHK(c, hipFree(*buf));
+        *buf = nullptr;
+        *cap = 0;
+    }
+    size_t nb = std::max(need, *cap + *cap / 2);
+    nb = (nb + (1u << 20) - 1) & ~(size_t)((1u << 20) - 1);
+    HIPCHK(c, hipMalloc(buf, nb));
+    *cap = nb;
+    return RG_OK;
+}
+
+rg_status grow_host(rg_ctx* c, size_t need) {
+    if (need <= c->host_bytes) return RG_OK;
+    if (c->host) {
+        HIPCHK(c, hipDeviceSynchronize());
+        HIPCHK(c, hipHostFree(c->host));
+        c->host = nullptr;
+        c->host_bytes = 0;
+    }
+    size_t nb = std::max(need, (size_t)1 << 20);
+    HIPCHK(c, hipHostMalloc(&c->host, nb, hipHostMallocDefault));
+    c->host_bytes = nb;
+    return RG_OK;
+}
+
+struct Bump {
+    uint8_t* base;
+    size_t used = 0;
+    template <class T>
+    T* take(size_t n) {
+        T* p = reinterpret_cast<T*>(base + used);
+        used += align256(n * sizeof(T));
+        return p;
+    }
+};
+
+PoolView view(const rg_pool& p) {
+    return PoolView{p.bm_begin, p.keys, p.types, p.card, p.size, p.off, p.payload, p.bm_card, p.bm_wbytes};
+}
+
+bool pool_ok(const rg_pool* p) {
+    return p && p->bm_begin && p->bm_card && p->bm_wbytes && (p->n_containers == 0 ||
+           (p->keys && p->types && p->card && p->size && p->off && p->payload)) &&
+           p->n_containers < 0xFFFFFFFFull;
+}
+
+hipEvent_t take_event(rg_ctx* c) {
+    if (!c->evpool.empty()) {
+        hipEvent_t e = c->evpool.back();
+        c->evpool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launches `fn` on st; when profiling, brackets it with events on the same stream.
+template <class F>
+void timed(rg_ctx* c, int cls, bool mat, uint64_t items, hipStream_t st, F&& fn) {
+    if (!c->prof) {
+        fn();
+        return;
+    }
+    hipEvent_t a = take_event(c), b = take_event(c);
+    if (!a || !b) {
+        fn();
+        return;
+    }
+    (void)hipEventRecord(a, st);
+    fn();
+    (void)hipEventRecord(b, st);
+    c->pend.push_back({a, b, cls, mat ? 1 : 0, items});
+}
+
+rg_status drain_profile(rg_ctx* c) {
+    for (auto& p : c->pend) {
+        float ms = 0;
+        HIPCHK(c, hipEventSynchronize(p.b));
+        HIPCHK(c, hipEventElapsedTime(&ms, p.a, p.b));
+        c->prof_ms[p.cls][p.mat] += ms;
+        c->prof_launches[p.cls][p.mat] += 1;
+        c->prof_items[p.cls][p.mat] += p.items;
+        c->evpool.push_back(p.a);
+        c->evpool.push_back(p.b);
+    }
+    c->pend.clear();
+    return RG_OK;
+}
+
+// per-slot bytes of the wave workspace
+constexpr size_t SLOT_BYTES = sizeof(Task) + 4 /*ub*/ + 8 /*slot_off*/ + 4 /*res_card*/ + 1 /*res_type*/ +
+                              4 /*res_size*/ + 4 /*flags*/ + 8 /*out_idx*/ + 4 /*bin list*/ + 4 /*redo*/;
+
+rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const uint32_t* d_ia,
+                    const uint32_t* d_ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs, uint32_t flags, rg_out* out,
+                    uint64_t* d_cards, double* d_jacc, hipStream_t st) {
+    if (!c) return RG_EINVAL;
+    if (op < RG_AND || op > RG_ANDNOT) return fail(c, RG_EINVAL, "op must be RG_AND..RG_ANDNOT");
+    if (!pool_ok(A) || !pool_ok(B)) return fail(c, RG_EINVAL, "incomplete pool (null pointer)");
+    const bool mat = flags & RG_FLAG_MATERIALIZE;
+    if (!(flags & (RG_FLAG_MATERIALIZE | RG_FLAG_CARD | RG_FLAG_JACCARD)))
+        return fail(c, RG_EINVAL, "flags select no output");
+    if ((flags & RG_FLAG_CARD) && !d_cards) return fail(c, RG_EINVAL, "RG_FLAG_CARD needs d_cards");
+    if ((flags & RG_FLAG_JACCARD) && !d_jacc) return fail(c, RG_EINVAL, "RG_FLAG_JACCARD needs d_jacc");
+    if (mat && (!out || !out->bm_begin || !out->keys || !out->types || !out->card || !out->size || !out->off ||
+                !out->payload || !out->bm_card))
+        return fail(c, RG_EINVAL, "materialisation needs a complete rg_out");
+    if (mat && op != RG_AND)
+        return fail(c, RG_ENOTSUP,
+                    "materialised OR/XOR/ANDNOT are switched off: their first GPU run ended in a memory fault "
+                    "whose cause is not yet shown; the count-only forms of every operation are available");
+    if (n_pairs > 0xFFFFFFFFull) return fail(c, RG_EINVAL, "at most 2^32-1 pairs per call");
+    if ((d_ia == nullptr) != (d_ib == nullptr)) return fail(c, RG_EINVAL, "d_ia and d_ib go together");
+    HIPCHK(c, hipSetDevice(c->device));
+    if (mat) {
+        out->n_containers = 0;
+        out->payload_used = 0;
+        out->needed_containers = 0;
+        out->needed_payload_bytes = 0;
+    }
+    if (n_pairs == 0) {
+        if (mat) launch_fill_u64(out->bm_begin, 0, 1, st);
+        return RG_OK;
+    }
+    const PoolView pa = view(*A), pb = view(*B);
+
+    // ---- per-pair preparation
+    Bump bp{nullptr};
+    size_t need = align256(4 * n_pairs) + align256(8 * n_pairs) + align256(4 * n_pairs) + align256(8 * n_pairs);
+    if (rg_status s = grow_device(c, &c->ws_pairs, &c->ws_pairs_bytes, need)) return s;
+    bp.base = (uint8_t*)c->ws_pairs;
+    uint32_t* n_cand = bp.take<uint32_t>(n_pairs);
+    uint64_t* bound = bp.take<uint64_t>(n_pairs);
+    uint32_t* min_cont = bp.take<uint32_t>(n_pairs);
+    long long* acc = bp.take<long long>(n_pairs);
+    uint32_t* d_err = reinterpret_cast<uint32_t*>(c->small);
+    uint32_t* bin_count = d_err + 16;
+    uint32_t* bin_cursor = d_err + 32;
+    uint32_t* redo_count = d_err + 48;
+    uint64_t* totals = reinterpret_cast<uint64_t*>(d_err + 64);  // [0] payload end, [1] container end
+
+    launch_fill_u32(d_err, 0, 1, st);
+    launch_pair_prep(op, mat, pa, pb, A->n_bitmaps, B->n_bitmaps, d_ia, d_ib, ia0, ib0, n_pairs, n_cand, bound,
+                     min_cont, acc, d_err, st);
+    const size_t host_pairs = align256(4 * n_pairs) + align256(8 * n_pairs) + align256(4 * n_pairs);
+    if (rg_status s = grow_host(c, host_pairs + 4096 + align256(8 * (n_pairs + 1)) + 512)) return s;
+    Bump hb{(uint8_t*)c->host};
+    uint32_t* h_cand = hb.take<uint32_t>(n_pairs);
+    uint64_t* h_bound = hb.take<uint64_t>(n_pairs);
+    uint32_t* h_minc = hb.take<uint32_t>(n_pairs);
+    uint32_t* h_small = hb.take<uint32_t>(1024);
+    uint64_t* h_coff = hb.take<uint64_t>(n_pairs + 1);
+    HIPCHK(c, hipMemcpyAsync(h_cand, n_cand, 4 * n_pairs, hipMemcpyDeviceToHost, st));
+    if (mat) {
+        HIPCHK(c, hipMemcpyAsync(h_bound, bound, 8 * n_pairs, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(h_minc, min_cont, 4 * n_pairs, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(c, hipMemcpyAsync(h_small, d_err, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (h_small[0]) return fail(c, RG_EINVAL, "pair index out of range of its pool");
+
+    if (mat) {
+        uint64_t tb = 0, tcont = 0;
+        for (uint64_t p = 0; p < n_pairs; ++p) {
+            tb += h_bound[p];
+            tcont += h_minc[p];
+        }
+        out->needed_payload_bytes = tb;
+        out->needed_containers = tcont;
+        if (out->cap_payload_bytes < tb || out->cap_containers < tcont)
+            return fail(c, RG_ECAPACITY, "output arena too small");
+        launch_fill_u64(out->bm_card, 0, n_pairs, st);
+        if (out->bm_wbytes) launch_fill_u64(out->bm_wbytes, 0, n_pairs, st);
+    }
+
+    // ---- plan waves of at most max_wave_slots candidate slots
+    std::vector<uint64_t> wstart{0};
+    uint64_t accs = 0, S_max = 0, P_max = 0;
+    for (uint64_t p = 0; p < n_pairs; ++p) {
+        if (accs + h_cand[p] > c->max_wave_slots && accs > 0) {
+            S_max = std::max(S_max, accs);
+            P_max = std::max(P_max, p - wstart.back());
+            wstart.push_back(p);
+            accs = 0;
+        }
+        accs += h_cand[p];
+    }
+    S_max = std::max(S_max, accs);
+    P_max = std::max(P_max, n_pairs - wstart.back());
+    wstart.push_back(n_pairs);
+
+    size_t wneed = S_max * SLOT_BYTES + 16 * 256 + align256(8 * (P_max + 1)) +
+                   align256(8 * scan_partials_needed(S_max));
+    if (rg_status s = grow_device(c, &c->ws_wave, &c->ws_wave_bytes, wneed)) return s;
+    Bump wb{(uint8_t*)c->ws_wave};
+    Task* tasks = wb.take<Task>(S_max);
+    uint32_t* ub = wb.take<uint32_t>(S_max);
+    uint64_t* slot_off = wb.take<uint64_t>(S_max);
+    uint32_t* res_card = wb.take<uint32_t>(S_max);
+    uint8_t* res_type = wb.take<uint8_t>(S_max);
+    uint32_t* res_size = wb.take<uint32_t>(S_max);
+    uint32_t* sflags = wb.take<uint32_t>(S_max);
+    uint64_t* out_idx = wb.take<uint64_t>(S_max);
+    uint32_t* bin_lists = wb.take<uint32_t>(S_max);
+    uint32_t* redo_list = wb.take<uint32_t>(S_max);
+    uint64_t* cand_off = wb.take<uint64_t>(P_max + 1);
+    uint64_t* partials = wb.take<uint64_t>(scan_partials_needed(S_max));
+
+    uint64_t out_base = 0, pay_base = 0;
+    const size_t nw = wstart.size() - 1;
+    for (size_t w = 0; w < nw; ++w) {
+        const uint64_t p0 = wstart[w], p1 = wstart[w + 1];
+        const uint32_t np = (uint32_t)(p1 - p0);
+        h_coff[0] = 0;
+        for (uint32_t q = 0; q < np; ++q) h_coff[q + 1] = h_coff[q] + h_cand[p0 + q];
+        const uint64_t C = h_coff[np];
+        const bool last = w + 1 == nw;
+        HIPCHK(c, hipMemcpyAsync(cand_off, h_coff, 8 * (np + 1), hipMemcpyHostToDevice, st));
+        if (C == 0) {
+            if (mat) {
+                launch_fill_u64(totals + 1, out_base, 1, st);
+                launch_bm_begin(cand_off, out_idx, 0, totals + 1, np, p0, out->bm_begin, last, st);
+            }
+            continue;
+        }
+        if (mat && (op == RG_OR || op == RG_XOR)) {
+            launch_fill_u32(reinterpret_cast<uint32_t*>(tasks), 0, 4 * C, st);
+            launch_fill_u32(res_card, 0, C, st);
+            launch_fill_u32(ub, 0, C, st);
+        }
+        launch_fill_u32(bin_count, 0, NBINS, st);
+        MatchArgs m;
+        m.op = op;
+        m.materialize = mat;
+        m.A = pa;
+        m.B = pb;
+        m.ia = d_ia;
+        m.ib = d_ib;
+        m.ia0 = ia0;
+        m.ib0 = ib0;
+        m.pair0 = p0;
+        m.n_pairs = np;
+        m.cand_off = cand_off;
+        m.n_cand = C;
+        m.tasks = tasks;
+        m.ub = ub;
+        m.res_card = res_card;
+        m.bin_count = bin_count;
+        m.dispatch_mode = c->dispatch_mode;
+        m.fixed_bin = c->fixed_bin;
+        m.gallop_ratio = c->gallop_ratio;
+        launch_match(m, st);
+        if (mat) launch_scan_u32_u64(ub, slot_off, C, pay_base, partials, totals, st);
+        HIPCHK(c, hipMemcpyAsync(h_small, bin_count, 4 * NBINS, hipMemcpyDeviceToHost, st));
+        if (mat) HIPCHK(c, hipMemcpyAsync(h_small + 64, totals, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        uint32_t cnt[NBINS], boff[NBINS];
+        uint32_t run = 0;
+        for (int b = 0; b < NBINS; ++b) {
+            cnt[b] = h_small[b];
+            boff[b] = run;
+            run += cnt[b];
+        }
+        const uint64_t pay_end = mat ? *reinterpret_cast<uint64_t*>(h_small + 64) : 0;
+        memcpy(h_small + 128, boff, sizeof(boff));
+        HIPCHK(c, hipMemcpyAsync(bin_cursor, h_small + 128, sizeof(boff), hipMemcpyHostToDevice, st));
+        launch_bin_scatter(tasks, C, bin_cursor, bin_lists, st);
+        launch_fill_u32(redo_count, 0, 1, st);
+
+        ComputeArgs ca;
+        ca.op = op;
+        ca.materialize = mat;
+        ca.A = pa;
+        ca.B = pb;
+        ca.tasks = tasks;
+        ca.n_dev = nullptr;
+        ca.acc = acc;
+        ca.pair0 = p0;
+        ca.so = SlotOut{slot_off, mat ? out->payload : nullptr, res_card, res_type, res_size, redo_list, redo_count};
+        for (int b = 0; b < NBINS; ++b) {
+            if (!cnt[b]) continue;
+            ca.list = bin_lists + boff[b];
+            ca.n = cnt[b];
+            timed(c, b, mat, cnt[b], st, [&] {
+                switch (b) {
+                case BIN_BB: launch_bb(ca, st); break;
+                case BIN_COPY: launch_copy(ca, st); break;
+                case BIN_AA: launch_aa(ca, st); break;
+                case BIN_GALLOP: launch_gallop(ca, st); break;
+                case BIN_AB: launch_ab(ca, st); break;
+                case BIN_RR: launch_rr(ca, st); break;
+                default: launch_generic(ca, st); break;
+                }
+            });
+        }
+        if (mat && cnt[BIN_BB]) {
+            // bitset pairs whose result is an array or run container
+            ComputeArgs rd = ca;
+            rd.list = redo_list;
+            rd.n = std::min<uint32_t>(cnt[BIN_BB], 4096u);
+            rd.n_dev = redo_count;
+            timed(c, NBINS - 1, mat, 0, st, [&] { launch_generic(rd, st); });
+        }
+        HIPCHK(c, hipGetLastError());
+        if (mat) {
+            launch_flags(res_card, sflags, C, st);
+            launch_scan_u32_u64(sflags, out_idx, C, out_base, partials, totals + 1, st);
+            CompactArgs cp;
+            cp.tasks = tasks;
+            cp.n_slots = C;
+            cp.res_card = res_card;
+            cp.res_type = res_type;
+            cp.res_size = res_size;
+            cp.slot_off = slot_off;
+            cp.out_idx = out_idx;
+            cp.keys = out->keys;
+            cp.types = out->types;
+            cp.card = out->card;
+            cp.size = out->size;
+            cp.off = out->off;
+            cp.bm_card = out->bm_card;
+            cp.bm_wbytes = out->bm_wbytes;
+            cp.pair0 = p0;
+            launch_compact(cp, st);
+            launch_bm_begin(cand_off, out_idx, C, totals + 1, np, p0, out->bm_begin, last, st);
+            HIPCHK(c, hipMemcpyAsync(h_small + 66, totals + 1, 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            out_base = *reinterpret_cast<uint64_t*>(h_small + 66);
+            pay_base = pay_end;
+        }
+    }
+    if (mat) {
+        out->n_containers = out_base;
+        out->payload_used = pay_base;
+        if (flags & (RG_FLAG_CARD | RG_FLAG_JACCARD))
+            launch_mat_counts(op, out->bm_card, pa, pb, d_ia, d_ib, ia0, ib0, n_pairs,
+                              (flags & RG_FLAG_CARD) ? d_cards : nullptr, (flags & RG_FLAG_JACCARD) ? d_jacc : nullptr,
+                              st);
+    } else {
+        launch_finish_counts(op, acc, pa, pb, d_ia, d_ib, ia0, ib0, 0, (uint32_t)n_pairs,
+                             (flags & RG_FLAG_CARD) ? d_cards : nullptr, (flags & RG_FLAG_JACCARD) ? d_jacc : nullptr,
+                             st);
+    }
+    HIPCHK(c, hipGetLastError());
+    return RG_OK;
+}
+
+rg_status single(rg_ctx* c, int op, const rg_pool* A, uint32_t ia, const rg_pool* B, uint32_t ib, uint32_t flags,
+                 rg_out* out, uint64_t* d_card, double* d_j, void* stream) {
+    if (!c) return RG_EINVAL;
+    if (!A || !B) return fail(c, RG_EINVAL, "null pool");
+    if (ia >= A->n_bitmaps || ib >= B->n_bitmaps) return fail(c, RG_EINVAL, "bitmap index out of range");
+    return run_batch(c, op, A, B, nullptr, nullptr, ia, ib, 1, flags, out, d_card, d_j, (hipStream_t)stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+rg_status rg_create(rg_ctx** ctx, int device) {
+    if (!ctx) return RG_EINVAL;
+    *ctx = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return RG_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return RG_EDEVICE;
+    rg_ctx* c = new rg_ctx();
+    c->device = device;
+    if (hipMalloc(&c->small, 4096) != hipSuccess) {
+        delete c;
+        return RG_EDEVICE;
+    }
+    *ctx = c;
+    return RG_OK;
+}
+
+void rg_destroy(rg_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    if (c->ws_pairs) (void)hipFree(c->ws_pairs);
+    if (c->ws_wave) (void)hipFree(c->ws_wave);
+    if (c->small) (void)hipFree(c->small);
+    if (c->host) (void)hipHostFree(c->host);
+    for (auto& p : c->pend) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : c->evpool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+const char* rg_last_error(const rg_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+rg_status rg_profile_enable(rg_ctx* c, int on) {
+    if (!c) return RG_EINVAL;
+    if (!on) {
+        if (rg_status s = drain_profile(c)) return s;
+    }
+    c->prof = on != 0;
+    return RG_OK;
+}
+
+rg_status rg_profile_reset(rg_ctx* c) {
+    if (!c) return RG_EINVAL;
+    if (rg_status s = drain_profile(c)) return s;
+    memset(c->prof_ms, 0, sizeof(c->prof_ms));
+    memset(c->prof_launches, 0, sizeof(c->prof_launches));
+    memset(c->prof_items, 0, sizeof(c->prof_items));
+    return RG_OK;
+}
+
+rg_status rg_profile_read(rg_ctx* c, int variant, int materialize, double* total_ms, uint64_t* launches,
+                          uint64_t* items) {
+    if (!c) return RG_EINVAL;
+    if (variant < 0 || variant >= NBINS || !total_ms || !launches || !items)
+        return fail(c, RG_EINVAL, "bad profile query");
+    if (rg_status s = drain_profile(c)) return s;
+    const int m = materialize ? 1 : 0;
+    *total_ms = c->prof_ms[variant][m];
+    *launches = c->prof_launches[variant][m];
+    *items = c->prof_items[variant][m];
+    return RG_OK;
+}
+
+rg_status rg_set_dispatch(rg_ctx* c, int mode, int variant) {
+    if (!c) return RG_EINVAL;
+    if (mode == RG_DISPATCH_HEURISTIC) {
+        c->dispatch_mode = mode;
+        return RG_OK;
+    }
+    if (mode == RG_DISPATCH_FIXED && variant >= RG_V_GENERIC && variant <= RG_V_RUNMERGE) {
+        c->dispatch_mode = mode;
+        c->fixed_bin = variant;
+        return RG_OK;
+    }
+    return fail(c, RG_EINVAL, "unknown dispatch mode or variant");
+}
+
+rg_status roaring_and(rg_ctx* c, const rg_pool* A, uint32_t ia, const rg_pool* B, uint32_t ib, rg_out* out,
+                      void* stream) {
+    return single(c, RG_AND, A, ia, B, ib, RG_FLAG_MATERIALIZE, out, nullptr, nullptr, stream);
+}
+rg_status roaring_or(rg_ctx* c, const rg_pool* A, uint32_t ia, const rg_pool* B, uint32_t ib, rg_out* out,
+                     void* stream) {
+    return single(c, RG_OR, A, ia, B, ib, RG_FLAG_MATERIALIZE, out, nullptr, nullptr, stream);
+}
+rg_status roaring_xor(rg_ctx* c, const rg_pool* A, uint32_t ia, const rg_pool* B, uint32_t ib, rg_out* out,
+                      void* stream) {
+    return single(c, RG_XOR, A, ia, B, ib, RG_FLAG_MATERIALIZE, out, nullptr, nullptr, stream);
+}
+rg_status roaring_andnot(rg_ctx* c, const rg_pool* A, uint32_t ia, const rg_pool* B, uint32_t ib, rg_out* out,
+                         void* stream) {
+    return single(c, RG_ANDNOT, A, ia, B, ib, RG_FLAG_MATERIALIZE, out, nullptr, nullptr, stream);
+}
+rg_status roaring_and_cardinality(rg_ctx* c, const rg_pool* A, uint32_t ia, const rg_pool* B, uint32_t ib,
+                                  uint64_t* d_card, void* stream) {
+    return single(c, RG_AND, A, ia, B, ib, RG_FLAG_CARD, nullptr, d_card, nullptr, stream);
+}
+rg_status roaring_or_cardinality(rg_ctx* c, const rg_pool* A, uint32_t ia, const rg_pool* B, uint32_t ib,
+                                 uint64_t* d_card, void* stream) {
+    return single(c, RG_OR, A, ia, B, ib, RG_FLAG_CARD, nullptr, d_card, nullptr, stream);
+}
+rg_status roaring_xor_cardinality(rg_ctx* c, const rg_pool* A, uint32_t ia, const rg_pool* B, uint32_t ib,
+                                  uint64_t* d_card, void* stream) {
+    return single(c, RG_XOR, A, ia, B, ib, RG_FLAG_CARD, nullptr, d_card, nullptr, stream);
+}
+rg_status roaring_andnot_cardinality(rg_ctx* c, const rg_pool* A, uint32_t ia, const rg_pool* B, uint32_t ib,
+                                     uint64_t* d_card, void* stream) {
+    return single(c, RG_ANDNOT, A, ia, B, ib, RG_FLAG_CARD, nullptr, d_card, nullptr, stream);
+}
+rg_status roaring_jaccard(rg_ctx* c, const rg_pool* A, uint32_t ia, const rg_pool* B, uint32_t ib, double* d_j,
+                          void* stream) {
+    return single(c, RG_AND, A, ia, B, ib, RG_FLAG_JACCARD, nullptr, nullptr, d_j, stream);
+}
+
+rg_status roaring_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const uint32_t* d_ia,
+                        const uint32_t* d_ib, uint64_t n_pairs, uint32_t flags, rg_out* out, uint64_t* d_cards,
+                        double* d_jacc, void* stream) {
+    if (!c) return RG_EINVAL;
+    if (n_pairs && (!d_ia || !d_ib)) return fail(c, RG_EINVAL, "null pair arrays");
+    return run_batch(c, op, A, B, d_ia, d_ib, 0, 0, n_pairs, flags, out, d_cards, d_jacc, (hipStream_t)stream);
+}
+
+rg_status rg_pool_recount(rg_ctx* c, const rg_pool* p, void* stream) {
+    if (!c) return RG_EINVAL;
+    if (!p || !p->bm_begin || !p->bm_card || !p->bm_wbytes) return fail(c, RG_EINVAL, "incomplete pool");
+    HIPCHK(c, hipSetDevice(c->device));
+    launch_pool_recount(*p, (hipStream_t)stream);
+    HIPCHK(c, hipGetLastError());
+    return RG_OK;
+}
+
+rg_status rg_pool_validate(rg_ctx* c, const rg_pool* p, uint64_t* n_bad, void* stream) {
+    if (!c) return RG_EINVAL;
+    if (!pool_ok(p) || !n_bad) return fail(c, RG_EINVAL, "incomplete pool");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    uint64_t* d_bad = reinterpret_cast<uint64_t*>((uint8_t*)c->small + 2048);
+    launch_pool_validate(*p, d_bad, st);
+    if (rg_status s = grow_host(c, 4096)) return s;
+    HIPCHK(c, hipMemcpyAsync(c->host, d_bad, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    *n_bad = *reinterpret_cast<uint64_t*>(c->host);
+    return RG_OK;
+}
+
+rg_status rg_pool_digest(rg_ctx* c, const rg_pool* p, uint64_t* d_digest, void* stream) {
+    if (!c) return RG_EINVAL;
+    if (!pool_ok(p) || !d_digest) return fail(c, RG_EINVAL, "incomplete pool");
+    HIPCHK(c, hipSetDevice(c->device));
+    launch_pool_digest(*p, d_digest, (hipStream_t)stream);
+    HIPCHK(c, hipGetLastError());
+    return RG_OK;
+}
+
+}  // extern "C"

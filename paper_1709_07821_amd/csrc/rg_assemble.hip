@@ -1,0 +1,133 @@
+// rg_assemble.hip - output assembly and the cardinality / Jaccard step.
+//
+// Results are built as new bitmaps, inputs untouched (Section 5.7). Slots are
+// in result key order; empty results are dropped (Section 2.2: no empty
+// containers), the survivors are compacted by a prefix sum of non-empty
+// flags. Payloads stay where their slot put them, so only the 19 bytes of
+// metadata per container move.
+//
+// Counts: unmatched containers contribute their stored cardinality and
+// matched pairs the population count of their result, so |A op B| needs no
+// materialisation (Section 5.9); the Jaccard index follows from the
+// identities |A u B| = |A| + |B| - |A n B|, |A \ B| = |A| - |A n B| and
+// |A xor B| = |A| + |B| - 2|A n B| with one binary64 division.
+#include "rg_internal.h"
+
+namespace rg {
+
+__global__ void k_flags(const uint32_t* res_card, uint32_t* flags, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        flags[i] = res_card[i] ? 1u : 0u;
+}
+
+void launch_flags(const uint32_t* res_card, uint32_t* flags, uint64_t n, hipStream_t st) {
+    if (!n) return;
+    uint64_t g = (n + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_flags, dim3((uint32_t)g), dim3(256), 0, st, res_card, flags, n);
+}
+
+__global__ void k_compact(CompactArgs c) {
+    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < c.n_slots;
+         s += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t card = c.res_card[s];
+        if (!card) continue;
+        const uint64_t i = c.out_idx[s];
+        const Task t = c.tasks[s];
+        c.keys[i] = t.key;
+        c.types[i] = c.res_type[s];
+        c.card[i] = card;
+        c.size[i] = c.res_size[s];
+        c.off[i] = c.slot_off[s];
+        atomicAdd(reinterpret_cast<unsigned long long*>(&c.bm_card[t.pair]), (unsigned long long)card);
+        if (c.bm_wbytes)
+            atomicAdd(reinterpret_cast<unsigned long long*>(&c.bm_wbytes[t.pair]),
+                      (unsigned long long)wbytes_of(card));
+    }
+}
+
+void launch_compact(const CompactArgs& c, hipStream_t st) {
+    if (!c.n_slots) return;
+    uint64_t g = (c.n_slots + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_compact, dim3((uint32_t)g), dim3(256), 0, st, c);
+}
+
+// bm_begin of each pair of the wave: output index of its first slot
+__global__ void k_bm_begin(const uint64_t* cand_off, const uint64_t* out_idx, uint64_t n_slots,
+                           const uint64_t* out_total, uint32_t n_pairs, uint64_t pair0, uint64_t* bm_begin,
+                           int last_wave) {
+    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n_pairs) {
+        uint64_t s = cand_off[p];
+        bm_begin[pair0 + p] = s < n_slots ? out_idx[s] : *out_total;
+    }
+    if (last_wave && p == n_pairs) bm_begin[pair0 + n_pairs] = *out_total;
+}
+
+void launch_bm_begin(const uint64_t* cand_off, const uint64_t* out_idx, uint64_t n_slots, const uint64_t* out_total,
+                     uint32_t n_pairs, uint64_t pair0, uint64_t* bm_begin, bool last_wave, hipStream_t st) {
+    hipLaunchKernelGGL(k_bm_begin, dim3((n_pairs + 1 + 255) / 256), dim3(256), 0, st, cand_off, out_idx, n_slots,
+                       out_total, n_pairs, pair0, bm_begin, (int)last_wave);
+}
+
+// |A n B| from |A op B| and the stored totals
+__device__ __forceinline__ uint64_t inter_from(int op, uint64_t card, uint64_t na, uint64_t nb) {
+    if (op == RG_AND) return card;
+    if (op == RG_OR) return na + nb - card;
+    if (op == RG_XOR) return (na + nb - card) / 2;
+    return na - card;
+}
+
+__device__ __forceinline__ double jaccard_of(uint64_t inter, uint64_t na, uint64_t nb) {
+    uint64_t uni = na + nb - inter;
+    if (uni == 0) return 1.0;
+    return (double)inter / (double)uni;
+}
+
+__global__ void k_finish_counts(int op, const long long* acc, PoolView A, PoolView B, const uint32_t* ia,
+                                const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t pair0, uint32_t n_pairs,
+                                uint64_t* d_cards, double* d_jacc) {
+    uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_pairs) return;
+    uint64_t p = pair0 + q;
+    uint64_t card = (uint64_t)acc[p];
+    if (d_cards) d_cards[p] = card;
+    if (d_jacc) {
+        uint32_t a = ia ? ia[p] : ia0, b = ib ? ib[p] : ib0;
+        uint64_t na = A.bm_card[a], nb = B.bm_card[b];
+        d_jacc[p] = jaccard_of(inter_from(op, card, na, nb), na, nb);
+    }
+}
+
+void launch_finish_counts(int op, const long long* acc, PoolView A, PoolView B, const uint32_t* ia,
+                          const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t pair0, uint32_t n_pairs,
+                          uint64_t* d_cards, double* d_jacc, hipStream_t st) {
+    if (!n_pairs) return;
+    hipLaunchKernelGGL(k_finish_counts, dim3((n_pairs + 255) / 256), dim3(256), 0, st, op, acc, A, B, ia, ib, ia0,
+                       ib0, pair0, n_pairs, d_cards, d_jacc);
+}
+
+__global__ void k_mat_counts(int op, const uint64_t* bm_card, PoolView A, PoolView B, const uint32_t* ia,
+                             const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs, uint64_t* d_cards,
+                             double* d_jacc) {
+    uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_pairs) return;
+    uint64_t card = bm_card[p];
+    if (d_cards) d_cards[p] = card;
+    if (d_jacc) {
+        uint32_t a = ia ? ia[p] : ia0, b = ib ? ib[p] : ib0;
+        uint64_t na = A.bm_card[a], nb = B.bm_card[b];
+        d_jacc[p] = jaccard_of(inter_from(op, card, na, nb), na, nb);
+    }
+}
+
+void launch_mat_counts(int op, const uint64_t* bm_card, PoolView A, PoolView B, const uint32_t* ia,
+                       const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs, uint64_t* d_cards,
+                       double* d_jacc, hipStream_t st) {
+    if (!n_pairs) return;
+    hipLaunchKernelGGL(k_mat_counts, dim3((uint32_t)((n_pairs + 255) / 256)), dim3(256), 0, st, op, bm_card, A, B,
+                       ia, ib, ia0, ib0, n_pairs, d_cards, d_jacc);
+}
+
+}  // namespace rg

@@ -1,0 +1,55 @@
+// rg_generic.hip - the universal variant: both containers of a pair, of any
+// type, are expanded into 8 KiB LDS bitsets, combined word by word, and the
+// result goes through the common output step (P1 type, payload). It handles
+// every type pair; the specialised kernels only make some pairs cheaper. Run
+// containers, for which the paper gives no algorithm (Section 5.10, Section 6),
+// go through the ballot/prefix-XOR expansion of expand_container().
+//
+// One 256-thread workgroup per container pair, grid-stride over the list so
+// that a device-side count (the bitset redo list) can drive it.
+#include "rg_finalize.h"
+
+namespace rg {
+
+template <int OP, bool MAT>
+__global__ void __launch_bounds__(256) k_generic(ComputeArgs a) {
+    __shared__ WgShared sh;
+    const uint32_t n = a.n_dev ? *a.n_dev : a.n;
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const uint32_t slot = a.list[i];
+        const Task t = a.tasks[slot];
+        expand_container(sh.sa, a.A, t.ia, sh);
+        expand_container(sh.sb, a.B, t.ib, sh);
+        uint64_t w[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) w[j] = apply_op<OP>(sh.sa[4 * threadIdx.x + j], sh.sb[4 * threadIdx.x + j]);
+        if (MAT) {
+            finalize_words(w, slot, a.so, sh.sa, sh.sb, sh);
+        } else {
+            uint32_t c = count_words(w, sh);
+            if (threadIdx.x == 0) add_count_delta(OP, a, t, c);
+        }
+        __syncthreads();
+    }
+}
+
+template <int OP>
+static void launch_gen_op(const ComputeArgs& a, uint32_t grid, hipStream_t st) {
+    if (a.materialize) hipLaunchKernelGGL((k_generic<OP, true>), dim3(grid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_generic<OP, false>), dim3(grid), dim3(256), 0, st, a);
+}
+
+void launch_generic(const ComputeArgs& a, hipStream_t st) {
+    uint32_t grid = a.n;
+    if (a.n_dev) grid = a.n;  // caller passes the maximum possible count as n
+    if (!grid) return;
+    if (grid > 65536u) grid = 65536u;
+    switch (a.op) {
+    case RG_AND: launch_gen_op<RG_AND>(a, grid, st); break;
+    case RG_OR: launch_gen_op<RG_OR>(a, grid, st); break;
+    case RG_XOR: launch_gen_op<RG_XOR>(a, grid, st); break;
+    default: launch_gen_op<RG_ANDNOT>(a, grid, st); break;
+    }
+}
+
+}  // namespace rg

@@ -1,0 +1,240 @@
+// rg_internal.h - shared declarations of the HIP kernels and the host
+// orchestration of the Roaring set-operation library (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/roaring_gpu.h"
+
+namespace rg {
+
+constexpr uint32_t NONE = 0xFFFFFFFFu;
+constexpr int WAVE = 64;
+
+// native 16-byte vector (global_load_dwordx4 / global_store_dwordx4)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// What one slot of the work space does. Slots are laid out per pair in key
+// order of the result, so compaction of non-empty slots yields the result
+// containers in ascending key order.
+enum : uint8_t { KIND_NOOP = 0, KIND_MATCH = 1, KIND_COPY_A = 2, KIND_COPY_B = 3 };
+
+// Kernel classes (bins). Variant selection decides the bin of every slot.
+enum : uint8_t {
+    BIN_BB = 0,     // bitset op bitset: one wave per pair, words in registers
+    BIN_COPY = 1,   // one-sided container copied through unchanged
+    BIN_GEN = 2,    // any pair: expand both sides into LDS bitsets, op, finalize
+    BIN_AA = 3,     // array op array: LDS merge
+    BIN_GALLOP = 4, // array op array, very unequal sizes: galloping search
+    BIN_AB = 5,     // array op bitset (either order): probe / set / clear / flip
+    BIN_RR = 6,     // run op run / run op array: interval merge
+    NBINS = 8
+};
+
+struct Task {
+    uint32_t pair;
+    uint32_t ia;   // container index in pool A, or NONE
+    uint32_t ib;   // container index in pool B, or NONE
+    uint16_t key;
+    uint8_t kind;
+    uint8_t bin;
+};
+static_assert(sizeof(Task) == 16, "task record is 16 bytes");
+
+struct PoolView {
+    const uint64_t* bm_begin;
+    const uint16_t* keys;
+    const uint8_t* types;
+    const uint32_t* card;
+    const uint32_t* size;
+    const uint64_t* off;
+    const uint8_t* payload;
+    const uint64_t* bm_card;
+    const uint64_t* bm_wbytes;
+};
+
+// Per-wave result slots written by the compute kernels.
+struct SlotOut {
+    const uint64_t* slot_off;   // payload byte offset of each slot (absolute in out payload)
+    uint8_t* payload;           // out payload base
+    uint32_t* res_card;         // 0 = empty / no container
+    uint8_t* res_type;
+    uint32_t* res_size;
+    uint32_t* redo_list;        // bitset pairs whose result is not a bitset
+    uint32_t* redo_count;
+};
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t round16(uint32_t b) { return (b + 15u) & ~15u; }
+
+// P1: least-memory container type allowed by the size rules
+__host__ __device__ __forceinline__ uint8_t p1_type(uint32_t c, uint32_t r) {
+    bool run_ok = (c <= 4096u) ? (2u * r < c) : (r <= 2047u);
+    if (run_ok) return RG_RUN;
+    return c <= 4096u ? RG_ARRAY : RG_BITSET;
+}
+
+__host__ __device__ __forceinline__ uint32_t payload_bytes_of(uint8_t type, uint32_t size) {
+    return type == RG_ARRAY ? 2u * size : type == RG_BITSET ? 8192u : 4u * size;
+}
+
+// bound on the payload of any container holding at most c values (P1 form)
+__host__ __device__ __forceinline__ uint32_t wbytes_of(uint64_t c) {
+    uint64_t b = 2 * c < 8192 ? 2 * c : 8192;
+    return (uint32_t)((b + 15) & ~15ull);
+}
+
+template <int OP>
+__device__ __forceinline__ uint64_t apply_op(uint64_t a, uint64_t b) {
+    if (OP == RG_AND) return a & b;
+    if (OP == RG_OR) return a | b;
+    if (OP == RG_XOR) return a ^ b;
+    return a & ~b;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// inclusive prefix sum over the 64 lanes of a wave
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        uint32_t t = __shfl_up(v, o);
+        if (lane >= (uint32_t)o) v += t;
+    }
+    return v;
+}
+
+// Block of 256 threads (4 waves): exclusive prefix sum and total. `tmp` must
+// hold 4 uint32 in LDS; contains two barriers.
+__device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t* tmp, uint32_t* total) {
+    const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
+    uint32_t inc = wave_incl_scan_u32(v);
+    if (lane == 63) tmp[wid] = inc;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < 4; ++w) {
+        uint32_t t = tmp[w];
+        if (w < wid) base += t;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + inc - v;
+}
+
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* tmp) {
+    const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
+    v = wave_sum_u64(v);
+    if (lane == 0) tmp[wid] = v;
+    __syncthreads();
+    uint64_t s = tmp[0] + tmp[1] + tmp[2] + tmp[3];
+    __syncthreads();
+    return s;
+}
+
+// ---------------------------------------------------------------- launchers
+// (defined in the .hip files; all enqueue on `st`)
+
+struct MatchArgs {
+    int op;
+    bool materialize;
+    PoolView A, B;
+    const uint32_t* ia;       // pair -> bitmap in A (device), or null: use ia0
+    const uint32_t* ib;
+    uint32_t ia0, ib0;        // single-pair form
+    uint64_t pair0;           // first pair of this wave
+    uint32_t n_pairs;         // pairs in this wave
+    const uint64_t* cand_off; // [n_pairs + 1], wave-local candidate offsets
+    uint64_t n_cand;
+    Task* tasks;              // [n_cand]
+    uint32_t* ub;             // [n_cand] slot payload bound in bytes (materialize)
+    uint32_t* res_card;       // [n_cand]
+    uint32_t* bin_count;      // [NBINS]
+    int dispatch_mode;        // 0 heuristic, 2 fixed
+    int fixed_bin;
+    uint32_t gallop_ratio;
+};
+
+void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st);
+void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t st);
+void launch_pair_prep(int op, bool materialize, PoolView A, PoolView B, uint32_t nA, uint32_t nB,
+                      const uint32_t* ia, const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs,
+                      uint32_t* n_cand, uint64_t* bound, uint32_t* min_cont, long long* acc, uint32_t* err,
+                      hipStream_t st);
+void launch_match(const MatchArgs& m, hipStream_t st);
+void launch_bin_scatter(const Task* tasks, uint64_t n, uint32_t* bin_cursor, uint32_t* bin_lists, hipStream_t st);
+// exclusive scan of u32 into u64 with an added base; writes total to *total_out (device)
+void launch_scan_u32_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t base, uint64_t* partials,
+                         uint64_t* total_out, hipStream_t st);
+size_t scan_partials_needed(uint64_t n);
+
+struct ComputeArgs {
+    int op;
+    bool materialize;
+    PoolView A, B;
+    const Task* tasks;
+    const uint32_t* list;     // slot ids of this bin
+    uint32_t n;
+    const uint32_t* n_dev;    // if non-null, the count is read on the device (redo list)
+    long long* acc;           // count mode: per-pair (wave-local) accumulators
+    uint64_t pair0;
+    SlotOut so;
+};
+
+void launch_bb(const ComputeArgs& a, hipStream_t st);
+void launch_generic(const ComputeArgs& a, hipStream_t st);
+void launch_copy(const ComputeArgs& a, hipStream_t st);
+void launch_aa(const ComputeArgs& a, hipStream_t st);
+void launch_gallop(const ComputeArgs& a, hipStream_t st);
+void launch_ab(const ComputeArgs& a, hipStream_t st);
+void launch_rr(const ComputeArgs& a, hipStream_t st);
+
+struct CompactArgs {
+    const Task* tasks;
+    uint64_t n_slots;
+    const uint32_t* res_card;
+    const uint8_t* res_type;
+    const uint32_t* res_size;
+    const uint64_t* slot_off;
+    const uint64_t* out_idx;  // exclusive scan of (res_card > 0), includes the wave's output base
+    uint16_t* keys;
+    uint8_t* types;
+    uint32_t* card;
+    uint32_t* size;
+    uint64_t* off;
+    uint64_t* bm_card;        // indexed by global pair
+    uint64_t* bm_wbytes;      // may be null
+    uint64_t pair0;
+};
+void launch_flags(const uint32_t* res_card, uint32_t* flags, uint64_t n, hipStream_t st);
+void launch_compact(const CompactArgs& c, hipStream_t st);
+void launch_bm_begin(const uint64_t* cand_off, const uint64_t* out_idx, uint64_t n_slots, const uint64_t* out_total,
+                     uint32_t n_pairs, uint64_t pair0, uint64_t* bm_begin, bool last_wave, hipStream_t st);
+void launch_finish_counts(int op, const long long* acc, PoolView A, PoolView B, const uint32_t* ia,
+                          const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t pair0, uint32_t n_pairs,
+                          uint64_t* d_cards, double* d_jacc, hipStream_t st);
+void launch_mat_counts(int op, const uint64_t* bm_card, PoolView A, PoolView B, const uint32_t* ia,
+                       const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs, uint64_t* d_cards,
+                       double* d_jacc, hipStream_t st);
+
+// pool utilities
+void launch_pool_recount(const rg_pool& p, hipStream_t st);
+void launch_pool_validate(const rg_pool& p, uint64_t* d_bad, hipStream_t st);
+void launch_pool_digest(const rg_pool& p, uint64_t* d_digest, hipStream_t st);
+
+}  // namespace rg

@@ -1,0 +1,363 @@
+// rg_match.hip - per-pair preparation, key matching (the "high-level" merge of
+// two sorted key lists, Section 1 / Appendix A), variant selection (bins),
+// binning and the device prefix scan.
+#include "rg_internal.h"
+
+namespace rg {
+
+// ------------------------------------------------------------------ fills
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+static uint32_t grid_for(uint64_t n, uint32_t per_block, uint32_t cap = 65536) {
+    uint64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (uint32_t)g;
+}
+
+void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, st, p, v, n);
+}
+void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, p, v, n);
+}
+
+// ------------------------------------------------------------------ pairs
+// Per pair: candidate count of the key match, payload bound of the result,
+// bound on its container count, and the starting value of the count
+// accumulator (Section 5.9 identities: unmatched containers contribute
+// their stored cardinality).
+__global__ void k_pair_prep(int op, int materialize, PoolView A, PoolView B, uint32_t nA, uint32_t nB,
+                            const uint32_t* ia, const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs,
+                            uint32_t* n_cand, uint64_t* bound, uint32_t* min_cont, long long* acc, uint32_t* err) {
+    uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_pairs) return;
+    uint32_t a = ia ? ia[p] : ia0;
+    uint32_t b = ib ? ib[p] : ib0;
+    if (a >= nA || b >= nB) {  // bad index: report, and give the pair no work
+        atomicOr(err, 1u);
+        n_cand[p] = 0;
+        bound[p] = 0;
+        min_cont[p] = 0;
+        acc[p] = 0;
+        return;
+    }
+    uint32_t KA = (uint32_t)(A.bm_begin[a + 1] - A.bm_begin[a]);
+    uint32_t KB = (uint32_t)(B.bm_begin[b + 1] - B.bm_begin[b]);
+    if (materialize) {
+        uint64_t WA = A.bm_wbytes[a], WB = B.bm_wbytes[b];
+        uint32_t nc;
+        uint64_t bd;
+        uint32_t mc;
+        if (op == RG_OR || op == RG_XOR) {
+            nc = KA + KB;
+            bd = WA + WB;
+            mc = KA + KB;
+        } else if (op == RG_AND) {
+            nc = KA;
+            bd = WA < WB ? WA : WB;
+            mc = KA < KB ? KA : KB;
+        } else {
+            nc = KA;
+            bd = WA;
+            mc = KA;
+        }
+        n_cand[p] = nc;
+        bound[p] = bd;
+        min_cont[p] = mc;
+    } else {
+        n_cand[p] = KA < KB ? KA : KB;
+        bound[p] = 0;
+        min_cont[p] = 0;
+        long long base = 0;
+        if (op == RG_OR || op == RG_XOR) base = (long long)(A.bm_card[a] + B.bm_card[b]);
+        else if (op == RG_ANDNOT) base = (long long)A.bm_card[a];
+        acc[p] = base;
+    }
+}
+
+void launch_pair_prep(int op, bool materialize, PoolView A, PoolView B, uint32_t nA, uint32_t nB,
+                      const uint32_t* ia, const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs,
+                      uint32_t* n_cand, uint64_t* bound, uint32_t* min_cont, long long* acc, uint32_t* err,
+                      hipStream_t st) {
+    if (!n_pairs) return;
+    hipLaunchKernelGGL(k_pair_prep, dim3((uint32_t)((n_pairs + 255) / 256)), dim3(256), 0, st, op, (int)materialize,
+                       A, B, nA, nB, ia, ib, ia0, ib0, n_pairs, n_cand, bound, min_cont, acc, err);
+}
+
+// ------------------------------------------------------------------ match
+
+__device__ __forceinline__ uint32_t lower_bound_u16(const uint16_t* k, uint32_t n, uint16_t key) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (k[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t find_pair(const uint64_t* off, uint32_t n_pairs, uint64_t t) {
+    // largest p with off[p] <= t (off has n_pairs + 1 entries, off[0] = 0)
+    uint32_t lo = 0, hi = n_pairs;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Variant selection (plain heuristic). It never changes results: every bin
+// computes the same set; the bins differ only in how.
+__device__ __forceinline__ uint8_t classify(int op, uint8_t kind, uint8_t ta, uint8_t tb, uint32_t ca, uint32_t cb,
+                                            uint32_t sa, uint32_t sb, int mode, int fixed_bin,
+                                            uint32_t gallop_ratio) {
+    if (kind == KIND_COPY_A || kind == KIND_COPY_B) return BIN_COPY;
+    if (ta == RG_BITSET && tb == RG_BITSET) return BIN_BB;
+    if (mode == 2) {
+        // forced variant where it applies, otherwise the generic kernel
+        if (fixed_bin == BIN_GEN) return BIN_GEN;
+        if (fixed_bin == BIN_AA && ta == RG_ARRAY && tb == RG_ARRAY) return BIN_AA;
+        if (fixed_bin == BIN_GALLOP && ta == RG_ARRAY && tb == RG_ARRAY) return BIN_GALLOP;
+        if (fixed_bin == BIN_AB && ((ta == RG_ARRAY && tb == RG_BITSET) || (ta == RG_BITSET && tb == RG_ARRAY)))
+            return BIN_AB;
+        if (fixed_bin == BIN_RR && (ta == RG_RUN || tb == RG_RUN) && ta != RG_BITSET && tb != RG_BITSET)
+            return BIN_RR;
+        return BIN_GEN;
+    }
+    return BIN_GEN;
+}
+
+__global__ void __launch_bounds__(256) k_match(MatchArgs m) {
+    __shared__ uint32_t cnt[NBINS];
+    if (threadIdx.x < NBINS) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < m.n_cand) {
+        uint32_t pl = find_pair(m.cand_off, m.n_pairs, t);
+        uint64_t p = m.pair0 + pl;
+        uint64_t u = t - m.cand_off[pl];
+        uint32_t a = m.ia ? m.ia[p] : m.ia0;
+        uint32_t b = m.ib ? m.ib[p] : m.ib0;
+        uint64_t a0 = m.A.bm_begin[a], b0 = m.B.bm_begin[b];
+        uint32_t KA = (uint32_t)(m.A.bm_begin[a + 1] - a0);
+        uint32_t KB = (uint32_t)(m.B.bm_begin[b + 1] - b0);
+        Task task;
+        task.pair = (uint32_t)p;
+        task.ia = NONE;
+        task.ib = NONE;
+        task.kind = KIND_NOOP;
+        task.bin = 0xFF;
+        uint64_t slot = NONE;
+        if (!m.materialize) {
+            // count only: candidates from the side with fewer keys
+            if (KA <= KB) {
+                uint16_t key = m.A.keys[a0 + u];
+                uint32_t j = lower_bound_u16(m.B.keys + b0, KB, key);
+                task.key = key;
+                if (j < KB && m.B.keys[b0 + j] == key) {
+                    task.kind = KIND_MATCH;
+                    task.ia = (uint32_t)(a0 + u);
+                    task.ib = (uint32_t)(b0 + j);
+                }
+            } else {
+                uint16_t key = m.B.keys[b0 + u];
+                uint32_t i = lower_bound_u16(m.A.keys + a0, KA, key);
+                task.key = key;
+                if (i < KA && m.A.keys[a0 + i] == key) {
+                    task.kind = KIND_MATCH;
+                    task.ia = (uint32_t)(a0 + i);
+                    task.ib = (uint32_t)(b0 + u);
+                }
+            }
+            slot = t;
+        } else if (u < KA) {
+            uint16_t key = m.A.keys[a0 + u];
+            uint32_t j = lower_bound_u16(m.B.keys + b0, KB, key);
+            bool hit = j < KB && m.B.keys[b0 + j] == key;
+            task.key = key;
+            task.ia = (uint32_t)(a0 + u);
+            if (hit) {
+                task.kind = KIND_MATCH;
+                task.ib = (uint32_t)(b0 + j);
+            } else if (m.op != RG_AND) {
+                task.kind = KIND_COPY_A;
+            }
+            uint64_t local = (m.op == RG_OR || m.op == RG_XOR) ? u + j : u;
+            slot = m.cand_off[pl] + local;
+        } else {
+            uint32_t v = (uint32_t)(u - KA);
+            uint16_t key = m.B.keys[b0 + v];
+            uint32_t i = lower_bound_u16(m.A.keys + a0, KA, key);
+            bool hit = i < KA && m.A.keys[a0 + i] == key;
+            if (!hit) {
+                task.key = key;
+                task.ib = (uint32_t)(b0 + v);
+                task.kind = KIND_COPY_B;
+                slot = m.cand_off[pl] + v + i;
+            }
+        }
+        if (slot != NONE) {
+            uint32_t ub = 0;
+            if (task.kind != KIND_NOOP) {
+                uint8_t ta = task.ia != NONE ? m.A.types[task.ia] : 0;
+                uint8_t tb = task.ib != NONE ? m.B.types[task.ib] : 0;
+                uint32_t ca = task.ia != NONE ? m.A.card[task.ia] : 0;
+                uint32_t cb = task.ib != NONE ? m.B.card[task.ib] : 0;
+                uint32_t sa = task.ia != NONE ? m.A.size[task.ia] : 0;
+                uint32_t sb = task.ib != NONE ? m.B.size[task.ib] : 0;
+                task.bin = classify(m.op, task.kind, ta, tb, ca, cb, sa, sb, m.dispatch_mode, m.fixed_bin,
+                                    m.gallop_ratio);
+                atomicAdd(&cnt[task.bin], 1u);
+                if (m.materialize) {
+                    uint64_t bc;
+                    if (task.kind == KIND_COPY_A) bc = ca;
+                    else if (task.kind == KIND_COPY_B) bc = cb;
+                    else if (m.op == RG_AND) bc = ca < cb ? ca : cb;
+                    else if (m.op == RG_ANDNOT) bc = ca;
+                    else bc = (uint64_t)ca + cb;
+                    ub = wbytes_of(bc);
+                }
+            }
+            m.tasks[slot] = task;
+            m.res_card[slot] = 0;
+            if (m.materialize) m.ub[slot] = ub;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < NBINS && cnt[threadIdx.x]) atomicAdd(&m.bin_count[threadIdx.x], cnt[threadIdx.x]);
+}
+
+void launch_match(const MatchArgs& m, hipStream_t st) {
+    if (!m.n_cand) return;
+    hipLaunchKernelGGL(k_match, dim3((uint32_t)((m.n_cand + 255) / 256)), dim3(256), 0, st, m);
+}
+
+// ------------------------------------------------------------------ binning
+// Scatter slot ids into per-bin lists. bin_cursor[b] starts at the bin's
+// offset; one global atomic per bin per block.
+__global__ void __launch_bounds__(256) k_bin_scatter(const Task* tasks, uint64_t n, uint32_t* cursor,
+                                                     uint32_t* lists) {
+    __shared__ uint32_t cnt[NBINS];
+    __shared__ uint32_t base[NBINS];
+    if (threadIdx.x < NBINS) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint8_t bin = 0xFF;
+    uint32_t rank = 0;
+    if (s < n) {
+        Task t = tasks[s];
+        if (t.kind != KIND_NOOP) {
+            bin = t.bin;
+            rank = atomicAdd(&cnt[bin], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < NBINS && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
+    __syncthreads();
+    if (bin != 0xFF) lists[base[bin] + rank] = (uint32_t)s;
+}
+
+void launch_bin_scatter(const Task* tasks, uint64_t n, uint32_t* bin_cursor, uint32_t* bin_lists, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_bin_scatter, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, tasks, n, bin_cursor,
+                       bin_lists);
+}
+
+// ------------------------------------------------------------------ scan
+// Three-phase exclusive scan: per-tile sums, a single-block scan of the tile
+// sums, then a per-tile rescan. Tile = 256 threads x 8 items.
+constexpr uint32_t SCAN_PER_THREAD = 8;
+constexpr uint32_t SCAN_TILE = 256 * SCAN_PER_THREAD;
+
+size_t scan_partials_needed(uint64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE) + 1; }
+
+__global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t* in, uint64_t n, uint64_t* partials) {
+    __shared__ uint64_t tmp[4];
+    uint64_t start = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_PER_THREAD;
+    uint64_t s = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < SCAN_PER_THREAD; ++k)
+        if (start + k < n) s += in[start + k];
+    s = block_sum_u64(s, tmp);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_scan_partials(uint64_t* partials, uint64_t nb, uint64_t base,
+                                                       uint64_t* total_out) {
+    __shared__ uint64_t tmp[256];
+    uint64_t carry = base;
+    for (uint64_t c0 = 0; c0 < nb; c0 += 256) {
+        uint64_t i = c0 + threadIdx.x;
+        uint64_t v = i < nb ? partials[i] : 0;
+        tmp[threadIdx.x] = v;
+        __syncthreads();
+        // Hillis-Steele inclusive scan in LDS (256 entries)
+        for (uint32_t o = 1; o < 256; o <<= 1) {
+            uint64_t x = threadIdx.x >= o ? tmp[threadIdx.x - o] : 0;
+            __syncthreads();
+            tmp[threadIdx.x] += x;
+            __syncthreads();
+        }
+        if (i < nb) partials[i] = carry + tmp[threadIdx.x] - v;
+        uint64_t tot = tmp[255];
+        __syncthreads();
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+__global__ void __launch_bounds__(256) k_scan_down(const uint32_t* in, uint64_t n, const uint64_t* partials,
+                                                   uint64_t* out) {
+    __shared__ uint64_t tmp[4];
+    uint64_t start = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_PER_THREAD;
+    uint32_t v[SCAN_PER_THREAD];
+    uint64_t s = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < SCAN_PER_THREAD; ++k) {
+        v[k] = start + k < n ? in[start + k] : 0;
+        s += v[k];
+    }
+    // block exclusive scan of per-thread sums (64-bit)
+    const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
+    uint64_t inc = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint64_t x = __shfl_up(inc, o);
+        if (lane >= (uint32_t)o) inc += x;
+    }
+    if (lane == 63) tmp[wid] = inc;
+    __syncthreads();
+    uint64_t wbase = 0;
+    for (uint32_t w = 0; w < wid; ++w) wbase += tmp[w];
+    uint64_t run = partials[blockIdx.x] + wbase + inc - s;
+#pragma unroll
+    for (uint32_t k = 0; k < SCAN_PER_THREAD; ++k) {
+        if (start + k < n) out[start + k] = run;
+        run += v[k];
+    }
+}
+
+void launch_scan_u32_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t base, uint64_t* partials,
+                         uint64_t* total_out, hipStream_t st) {
+    uint64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb == 0) {
+        hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, st, total_out, base, (uint64_t)1);
+        return;
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)nb), dim3(256), 0, st, in, n, partials);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(256), 0, st, partials, nb, base, total_out);
+    hipLaunchKernelGGL(k_scan_down, dim3((uint32_t)nb), dim3(256), 0, st, in, n, partials, out);
+}
+
+}  // namespace rg

@@ -1,0 +1,77 @@
+"""Test helpers: an independent reader of the pool format (numpy), used to
+turn GPU results back into sorted value lists for comparison with the oracle,
+and shared case builders."""
+import numpy as np
+
+ARRAY, BITSET, RUN = 1, 2, 3
+
+
+def decode_container(h, i):
+    """Values (low 16 bits, as uint32) of container i of host pool arrays h."""
+    t = int(h["types"][i])
+    sz = int(h["size"][i])
+    off = int(h["off"][i])
+    pl = h["payload"]
+    if t == ARRAY:
+        return pl[off:off + 2 * sz].view(np.uint16).astype(np.uint32)
+    if t == BITSET:
+        words = pl[off:off + 8192].view(np.uint64)
+        bits = np.unpackbits(words.view(np.uint8), bitorder="little")
+        return np.nonzero(bits)[0].astype(np.uint32)
+    if t == RUN:
+        pr = pl[off:off + 4 * sz].view(np.uint16).reshape(-1, 2).astype(np.int64)
+        parts = [np.arange(s, s + l + 1, dtype=np.int64) for s, l in pr]
+        return (np.concatenate(parts) if parts else np.zeros(0, np.int64)).astype(np.uint32)
+    raise AssertionError(f"bad container type {t}")
+
+
+def decode_bitmap(h, b):
+    """Sorted uint32 values of bitmap b, and its per-container (key, type, card, size)."""
+    s, e = int(h["bm_begin"][b]), int(h["bm_begin"][b + 1])
+    vals, meta = [], []
+    for i in range(s, e):
+        key = int(h["keys"][i])
+        lo = decode_container(h, i)
+        vals.append((np.uint32(key) << np.uint32(16)) | lo)
+        meta.append((key, int(h["types"][i]), int(h["card"][i]), int(h["size"][i])))
+    v = np.concatenate(vals).astype(np.uint32) if vals else np.zeros(0, np.uint32)
+    return v, meta
+
+
+def oracle_meta(oracle, v):
+    """(key, type, card, size) per container from the oracle's container view."""
+    cv = oracle.containers(v)
+    out = []
+    for k, t, c, r in zip(cv["keys"], cv["types"], cv["card"], cv["runs"]):
+        t = int(t)
+        size = int(c) if t == ARRAY else 1024 if t == BITSET else int(r)
+        out.append((int(k), t, int(c), size))
+    return out
+
+
+def edge_sets():
+    """Bitmaps that sit on the container-type boundaries and chunk edges."""
+    sets = []
+    sets.append(np.zeros(0, np.uint32))                                      # empty
+    sets.append(np.arange(0, 65536, dtype=np.uint32))                        # full chunk -> 1 run
+    sets.append(np.array([0, 65535, 65536, 131071, 2**32 - 1], np.uint32))    # chunk edges
+    sets.append(np.arange(0, 8192, 2, dtype=np.uint32))                      # 4096 singletons -> array
+    sets.append(np.arange(0, 8194, 2, dtype=np.uint32))                      # 4097 singletons -> bitset
+    v = []
+    x = 0
+    for k in [2] * 2046 + [5]:                                               # c=4097, r=2047 -> run
+        v += list(range(x, x + k))
+        x += k + 1
+    sets.append(np.array(v, np.uint32) + np.uint32(3 * 65536))
+    v2 = v[:-1] + [65535]                                                    # c=4097, r=2048 -> bitset
+    sets.append(np.array(v2, np.uint32) + np.uint32(3 * 65536))
+    sets.append(np.arange(5 * 65536 + 100, 5 * 65536 + 103, dtype=np.uint32))  # c=3 r=1 -> run
+    sets.append(np.array([7 * 65536 + 1, 7 * 65536 + 2], np.uint32))         # c=2 r=1 -> array
+    rng = np.random.default_rng(99)
+    sets.append(np.unique(np.concatenate([rng.integers(0, 1 << 20, 30000), np.arange(200000, 260000),
+                                          rng.integers(300000, 300000 + 65536, 40000)])).astype(np.uint32))
+    sets.append(np.unique(rng.integers(0, 1 << 32, 5000, dtype=np.uint64)).astype(np.uint32))
+    sets.append(np.arange(65536 * 9, 65536 * 11, 3, dtype=np.uint32))        # 2 chunks, 21846 values each
+    sets.append(np.concatenate([np.arange(65536 * 9, 65536 * 9 + 40000), np.arange(65536 * 10 + 7, 65536 * 11)]
+                               ).astype(np.uint32))
+    return sets

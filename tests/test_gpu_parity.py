@@ -1,0 +1,256 @@
+"""GPU parity: every operation, through the C ABI, against the CPU oracle,
+element by element (values, container keys/types/cards/sizes, counts,
+Jaccard bit-for-bit, fingerprints)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import rgtest
+
+pytestmark = pytest.mark.gpu
+
+OPS = ("and", "or", "xor", "andnot")
+# Materialised OR/XOR/ANDNOT are switched off in the library (RG_ENOTSUP): their
+# first GPU run ended in a memory fault whose cause is not yet shown. Their
+# count-only forms and Jaccard are tested for every op.
+MAT_OPS = ("and",)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rg():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1709_07821_amd as rg
+
+    return rg
+
+
+@pytest.fixture(scope="module")
+def ctx(rg):
+    c = rg.Context(0)
+    yield c
+    c.close()
+
+
+def _t(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).cuda()
+
+
+def check_batch(rg, ctx, bs, ia, ib, ops=OPS, bs_b=None, label=""):
+    """Run each op on pairs (ia[p] of bs, ib[p] of bs_b) and compare everything with the oracle."""
+    import torch
+
+    bs_b = bs if bs_b is None else bs_b
+    A = rg.Pool.from_sets(bs.values, bs.offsets)
+    B = A if bs_b is bs else rg.Pool.from_sets(bs_b.values, bs_b.offsets)
+    assert rg.rg_pool_validate(ctx, A) == 0
+    assert rg.rg_pool_validate(ctx, B) == 0
+    tia, tib = _t(ia), _t(ib)
+    n = len(ia)
+    for op in ops:
+        mat = op in MAT_OPS
+        _say(f"[{label}] op={op} pairs={n} materialise={mat}")
+        _, cards2, jacc2 = rg.batch(ctx, op, A, B, tia, tib, materialize=False, card=True, jaccard=True)
+        if mat:
+            out, cards, jacc = rg.batch(ctx, op, A, B, tia, tib, materialize=True, card=True, jaccard=True)
+        torch.cuda.synchronize()
+        cards2 = cards2.cpu().numpy().view(np.uint64)
+        jacc2 = jacc2.cpu().numpy()
+        if mat:
+            res = out.as_pool()
+            assert rg.rg_pool_validate(ctx, res) == 0, "result violates the container rules"
+            dig = rg.rg_pool_digest(ctx, res).cpu().numpy().view(np.uint64)
+            h = res.to_host()
+            cards = cards.cpu().numpy().view(np.uint64)
+            jacc = jacc.cpu().numpy()
+        for p in range(n):
+            a, b = bs[int(ia[p])], bs_b[int(ib[p])]
+            exp = oracle.op(op, a, b)
+            j = oracle.jaccard(a, b)
+            assert int(cards2[p]) == len(exp), (label, op, p)
+            assert jacc2[p] == j, (label, op, p, jacc2[p], j)
+            if not mat:
+                continue
+            got, meta = rgtest.decode_bitmap(h, p)
+            assert np.array_equal(got, exp), (label, op, p)
+            assert meta == rgtest.oracle_meta(oracle, exp), (label, op, p)
+            assert int(h["bm_card"][p]) == len(exp)
+            assert int(cards[p]) == len(exp), (label, op, p)
+            assert jacc[p] == j, (label, op, p, jacc[p], j)
+            assert int(dig[p]) == oracle.digest(exp), (label, op, p)
+
+
+def test_edge_sets_all_pairs(rg, ctx):
+    sets = rgtest.edge_sets()
+    bs = synth.BitmapSet.from_list(sets)
+    k = len(sets)
+    ia = np.repeat(np.arange(k), k).astype(np.uint32)
+    ib = np.tile(np.arange(k), k).astype(np.uint32)
+    check_batch(rg, ctx, bs, ia, ib, label="edges")
+
+
+def test_mixed_small_consecutive(rg, ctx):
+    bs = synth.mixed_small()
+    ia, ib = synth.consecutive_pairs(len(bs))
+    check_batch(rg, ctx, bs, ia, ib, label="mixed")
+
+
+@pytest.mark.parametrize("variant", ["generic", "merge", "gallop", "probe", "runmerge"])
+def test_forced_variants_same_result(rg, ctx, variant):
+    bs = synth.mixed_small(n_bitmaps=30)
+    ia, ib = synth.consecutive_pairs(len(bs))
+    ctx.set_dispatch(rg.RG_DISPATCH_FIXED, rg.VARIANTS[variant])
+    try:
+        check_batch(rg, ctx, bs, ia, ib, label=f"forced-{variant}")
+        sets = rgtest.edge_sets()
+        eb = synth.BitmapSet.from_list(sets)
+        k = len(sets)
+        check_batch(rg, ctx, eb, np.repeat(np.arange(k), k).astype(np.uint32),
+                    np.tile(np.arange(k), k).astype(np.uint32), label=f"forced-edges-{variant}")
+    finally:
+        ctx.set_dispatch(rg.RG_DISPATCH_HEURISTIC)
+
+
+def test_array_stress_sample(rg, ctx):
+    bs, ia, ib = synth.array_stress(n_pairs=3000)
+    check_batch(rg, ctx, bs, ia, ib, label="array-stress")
+
+
+def test_two_pools_and_repeats(rg, ctx):
+    a = synth.mixed_small(n_bitmaps=8, seed=5)
+    b = synth.mixed_small(n_bitmaps=6, seed=6)
+    ia = np.array([0, 1, 2, 7, 7, 3, 0], np.uint32)
+    ib = np.array([5, 0, 2, 1, 1, 3, 0], np.uint32)
+    check_batch(rg, ctx, a, ia, ib, bs_b=b, label="two-pools")
+
+
+def test_single_pair_entry_points(rg, ctx):
+    import torch
+
+    bs = synth.mixed_small(n_bitmaps=4, seed=11)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    d = torch.zeros(1, dtype=torch.int64, device="cuda")
+    dj = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for op in OPS:
+        for (x, y) in [(0, 1), (2, 3), (1, 1)]:
+            exp = oracle.op(op, bs[x], bs[y])
+            ctx.check(getattr(rg, f"roaring_{op}_cardinality")(ctx, P, x, P, y, d))
+            torch.cuda.synchronize()
+            assert int(d.item()) == len(exp)
+            if op not in MAT_OPS:
+                out = rg.OutArena(1, 1 << 16, 1 << 24)
+                assert getattr(rg, f"roaring_{op}")(ctx, P, x, P, y, out) == rg.RG_ENOTSUP
+                continue
+            probe = rg.OutArena(1, 0, 0)
+            probe.c.cap_containers = 0
+            probe.c.cap_payload_bytes = 0
+            st = getattr(rg, f"roaring_{op}")(ctx, P, x, P, y, probe)
+            assert st in (rg.RG_ECAPACITY, rg.RG_OK)
+            out = rg.OutArena(1, probe.c.needed_containers, probe.c.needed_payload_bytes)
+            ctx.check(getattr(rg, f"roaring_{op}")(ctx, P, x, P, y, out))
+            torch.cuda.synchronize()
+            got, meta = rgtest.decode_bitmap(out.as_pool().to_host(), 0)
+            assert np.array_equal(got, exp) and meta == rgtest.oracle_meta(oracle, exp)
+        ctx.check(rg.roaring_jaccard(ctx, P, 0, P, 1, dj))
+        torch.cuda.synchronize()
+        assert dj.item() == oracle.jaccard(bs[0], bs[1])
+
+
+def test_errors(rg, ctx):
+    import torch
+
+    bs = synth.mixed_small(n_bitmaps=3, seed=12)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    d = torch.zeros(1, dtype=torch.int64, device="cuda")
+    assert rg.roaring_and_cardinality(ctx, P, 3, P, 0, d) == rg.RG_EINVAL
+    ia = _t(np.array([0, 5], np.uint32))
+    ib = _t(np.array([1, 1], np.uint32))
+    cards = torch.zeros(2, dtype=torch.int64, device="cuda")
+    assert rg.roaring_batch(ctx, "and", P, P, ia, ib, rg.RG_FLAG_CARD, None, cards) == rg.RG_EINVAL
+    out = rg.OutArena(1, 1, 16)
+    assert rg.roaring_and(ctx, P, 0, P, 1, out) == rg.RG_ECAPACITY
+    assert out.c.needed_containers > 1 and out.c.needed_payload_bytes > 16
+    assert rg.roaring_batch(ctx, 7, P, P, ia, ib, rg.RG_FLAG_CARD, None, cards) == rg.RG_EINVAL
+
+
+def test_empty_batch(rg, ctx):
+    bs = synth.mixed_small(n_bitmaps=3, seed=13)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    e = _t(np.zeros(0, np.uint32))
+    out, cards, jacc = rg.batch(ctx, "and", P, P, e, e, materialize=True, card=True, jaccard=True)
+    assert out.c.n_containers == 0
+
+
+def test_dense_generator_device_matches_host(rg, ctx):
+    import torch
+
+    w = torch.empty(3 * 4 * 1024, dtype=torch.int64, device="cuda")
+    synth.dense_bitsets_device(w.data_ptr(), 17, 3, 4, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    host = w.cpu().numpy().view(np.uint64).reshape(3, 4, 1024)
+    for b in range(3):
+        for k in range(4):
+            assert np.array_equal(host[b, k], synth.dense_container(17 + b, k))
+
+
+def test_dense_bitsets_reduced(rg, ctx):
+    """Bitset-bandwidth workload at reduced scale: 24 bitmaps x 256 bitsets."""
+    import torch
+
+    nb, nk = 24, 256
+    w = torch.empty(nb * nk * 1024, dtype=torch.int64, device="cuda")
+    synth.dense_bitsets_device(w.data_ptr(), 0, nb, nk, torch.cuda.current_stream().cuda_stream)
+    P = rg.Pool.from_dense_words(ctx, w, nb, nk)
+    assert rg.rg_pool_validate(ctx, P) == 0
+    ia, ib = synth.random_pairs(nb, 12, seed=synth.DENSE_SEED)
+    vals = {b: synth.dense_bitmap_values(int(b), nk) for b in set(ia.tolist()) | set(ib.tolist())}
+    for op in OPS:
+        mat = op in MAT_OPS
+        _say(f"[dense-reduced] op={op} materialise={mat}")
+        _, cards2, jacc = rg.batch(ctx, op, P, P, _t(ia), _t(ib), materialize=False, card=True, jaccard=True)
+        if mat:
+            out, cards, _ = rg.batch(ctx, op, P, P, _t(ia), _t(ib), materialize=True, card=True)
+        torch.cuda.synchronize()
+        cards2 = cards2.cpu().numpy().view(np.uint64)
+        jacc = jacc.cpu().numpy()
+        if mat:
+            res = out.as_pool()
+            assert rg.rg_pool_validate(ctx, res) == 0
+            dig = rg.rg_pool_digest(ctx, res).cpu().numpy().view(np.uint64)
+            h = res.to_host()
+            cards = cards.cpu().numpy().view(np.uint64)
+        for p in range(len(ia)):
+            a, b = vals[int(ia[p])], vals[int(ib[p])]
+            n_exp = oracle.count(op, a, b)
+            assert int(cards2[p]) == n_exp
+            assert jacc[p] == oracle.jaccard(a, b)
+            if mat:
+                assert int(cards[p]) == n_exp
+            if mat and p < 3:
+                exp = oracle.op(op, a, b)
+                got, meta = rgtest.decode_bitmap(h, p)
+                assert np.array_equal(got, exp)
+                assert meta == rgtest.oracle_meta(oracle, exp)
+                assert int(dig[p]) == oracle.digest(exp)
+
+
+def test_materialised_or_xor_andnot_switched_off(rg, ctx):
+    """Materialised OR/XOR/ANDNOT return RG_ENOTSUP (the path is switched off, not faked)."""
+    bs = synth.mixed_small(n_bitmaps=3, seed=14)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    ia = _t(np.array([0, 1], np.uint32))
+    ib = _t(np.array([1, 2], np.uint32))
+    for op in ("or", "xor", "andnot"):
+        out = rg.OutArena(2, 1 << 16, 1 << 24)
+        assert rg.roaring_batch(ctx, op, P, P, ia, ib, rg.RG_FLAG_MATERIALIZE, out) == rg.RG_ENOTSUP
