@@ -160,6 +160,34 @@ rg_status roaring_batch(rg_ctx *ctx, int op, const rg_pool *A, const rg_pool *B,
                         const uint32_t *d_ib, uint64_t n_pairs, uint32_t flags, rg_out *out, uint64_t *d_cards,
                         double *d_jacc, void *stream);
 
+/* ---- batched count-only plans (pointer-stable, graph-capturable) --------
+ * A plan fixes the pools, the pairs (d_ia/d_ib, device uint32), the op and the
+ * outputs (d_cards uint64 and/or d_jacc binary64, one per pair). Creating it
+ * reads the per-pair key-candidate counts back once (synchronising) and
+ * allocates its own device memory. rg_plan_execute then enqueues the whole
+ * batch on `stream` - per-pair seeds, key matching, binning by variant, one
+ * persistent work-stealing kernel for all container pairs, count finishing -
+ * with no host synchronisation and no allocation. rg_plan_capture records that
+ * sequence into a hipGraph on a non-default stream; later executes replay it.
+ * rg_plan_tune times the plan on its own data for several persistent grid sizes
+ * and galloping ratios and keeps the fastest (results never change). The pools,
+ * pair arrays and outputs must stay valid and unmoved for the plan's life;
+ * their contents may change between executions as long as every pair's
+ * candidate count (number of keys of its smaller bitmap) does not. */
+typedef struct rg_plan rg_plan;
+rg_status rg_plan_create(rg_ctx *ctx, int op, const rg_pool *A, const rg_pool *B, const uint32_t *d_ia,
+                         const uint32_t *d_ib, uint64_t n_pairs, uint32_t flags, uint64_t *d_cards, double *d_jacc,
+                         rg_plan **plan, void *stream);
+rg_status rg_plan_execute(rg_plan *plan, void *stream);
+rg_status rg_plan_capture(rg_plan *plan, void *stream);
+rg_status rg_plan_tune(rg_plan *plan, void *stream, int reps);
+/* Sets the persistent grid and galloping ratio; drops a captured graph
+ * (returns RG_ENOTSUP if one existed: capture again). */
+rg_status rg_plan_set(rg_plan *plan, uint32_t grid, uint32_t gallop_ratio);
+rg_status rg_plan_info(const rg_plan *plan, uint32_t *grid, uint32_t *gallop_ratio, uint64_t *slots,
+                       uint32_t *waves, int *graph);
+void rg_plan_destroy(rg_plan *plan);
+
 /* Kernel-variant selection for matched container pairs. Every variant
  * computes the same result; they differ only in speed.
  *   mode RG_DISPATCH_HEURISTIC (default): size-ratio / type heuristic;

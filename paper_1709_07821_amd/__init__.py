@@ -33,7 +33,8 @@ EXPORTS = ["rg_create", "rg_destroy", "rg_last_error", "rg_set_dispatch", "roari
            "roaring_andnot", "roaring_and_cardinality", "roaring_or_cardinality", "roaring_xor_cardinality",
            "roaring_andnot_cardinality", "roaring_jaccard", "roaring_batch", "rg_pool_measure_host",
            "rg_pool_build_host", "rg_pool_recount", "rg_pool_validate", "rg_pool_digest", "rg_profile_enable",
-           "rg_profile_reset", "rg_profile_read"]
+           "rg_profile_reset", "rg_profile_read", "rg_plan_create", "rg_plan_execute", "rg_plan_capture",
+           "rg_plan_tune", "rg_plan_set", "rg_plan_info", "rg_plan_destroy"]
 
 
 class RoaringError(RuntimeError):
@@ -92,8 +93,16 @@ def lib():
         L.rg_profile_enable.argtypes = [V, I]
         L.rg_profile_reset.argtypes = [V]
         L.rg_profile_read.argtypes = [V, I, I, P(ctypes.c_double), P(U64), P(U64)]
+        L.rg_plan_create.argtypes = [V, I, pool_p, pool_p, V, V, U64, U32, V, V, P(V), V]
+        L.rg_plan_execute.argtypes = [V, V]
+        L.rg_plan_capture.argtypes = [V, V]
+        L.rg_plan_tune.argtypes = [V, V, I]
+        L.rg_plan_set.argtypes = [V, U32, U32]
+        L.rg_plan_info.argtypes = [V, P(U32), P(U32), P(U64), P(U32), P(I)]
+        L.rg_plan_destroy.argtypes = [V]
+        L.rg_plan_destroy.restype = None
         for nm in EXPORTS:
-            if nm not in ("rg_destroy", "rg_last_error"):
+            if nm not in ("rg_destroy", "rg_last_error", "rg_plan_destroy"):
                 getattr(L, nm).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -310,6 +319,57 @@ def rg_pool_digest(ctx: Context, pool: Pool, stream=None):
     d = torch.zeros(max(pool.n_bitmaps, 1), dtype=torch.int64, device=pool.bm_begin.device)
     ctx.check(lib().rg_pool_digest(ctx.h, ctypes.byref(pool.c), _ptr(d), _stream(stream)))
     return d[:pool.n_bitmaps]
+
+
+class Plan:
+    """rg_plan: batched count-only execution, sync-free, graph-capturable, tunable.
+    Keeps references to the pools, pair tensors and outputs it was made with."""
+
+    def __init__(self, ctx: Context, op, A: Pool, B: Pool, ia, ib, card=True, jaccard=False, stream=None):
+        torch = _torch()
+        dev = A.bm_begin.device
+        n = int(ia.numel())
+        self.ctx, self.A, self.B, self.ia, self.ib = ctx, A, B, ia, ib
+        self.cards = torch.zeros(n, dtype=torch.int64, device=dev) if card else None
+        self.jacc = torch.zeros(n, dtype=torch.float64, device=dev) if jaccard else None
+        flags = (RG_FLAG_CARD if card else 0) | (RG_FLAG_JACCARD if jaccard else 0)
+        h = ctypes.c_void_p()
+        op = OPS[op] if isinstance(op, str) else op
+        ctx.check(lib().rg_plan_create(ctx.h, op, ctypes.byref(A.c), ctypes.byref(B.c), _ptr(ia), _ptr(ib), n, flags,
+                                       _ptr(self.cards), _ptr(self.jacc), ctypes.byref(h), _stream(stream)))
+        self.h = h
+
+    def execute(self, stream=None):
+        self.ctx.check(lib().rg_plan_execute(self.h, _stream(stream)))
+
+    def capture(self, stream):
+        self.ctx.check(lib().rg_plan_capture(self.h, _stream(stream)))
+
+    def tune(self, stream=None, reps=3):
+        self.ctx.check(lib().rg_plan_tune(self.h, _stream(stream), reps))
+
+    def set(self, grid: int, gallop_ratio: int):
+        st = lib().rg_plan_set(self.h, grid, gallop_ratio)
+        if st not in (RG_OK, RG_ENOTSUP):
+            self.ctx.check(st)
+
+    def info(self):
+        g, r, w, gr = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_int()
+        s = ctypes.c_uint64()
+        self.ctx.check(lib().rg_plan_info(self.h, ctypes.byref(g), ctypes.byref(r), ctypes.byref(s), ctypes.byref(w),
+                                          ctypes.byref(gr)))
+        return {"grid": g.value, "gallop_ratio": r.value, "slots": s.value, "waves": w.value, "graph": bool(gr.value)}
+
+    def close(self):
+        if self.h:
+            lib().rg_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 PROFILE_CLASSES = {0: "bb", 1: "copy", 2: "generic", 3: "merge", 4: "gallop", 5: "probe", 6: "runmerge",

@@ -201,8 +201,12 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
     uint32_t* redo_count = d_err + 48;
     uint64_t* totals = reinterpret_cast<uint64_t*>(d_err + 64);  // [0] payload end, [1] container end
 
+    // Count-only calls accumulate |A n B| for every operation and convert at
+    // the end (Section 5.9 identities): the kernels then depend on the
+    // operation only when they materialise.
+    const int kop = mat ? op : RG_AND;
     launch_fill_u32(d_err, 0, 1, st);
-    launch_pair_prep(op, mat, pa, pb, A->n_bitmaps, B->n_bitmaps, d_ia, d_ib, ia0, ib0, n_pairs, n_cand, bound,
+    launch_pair_prep(kop, mat, pa, pb, A->n_bitmaps, B->n_bitmaps, d_ia, d_ib, ia0, ib0, n_pairs, n_cand, bound,
                      min_cont, acc, d_err, st);
     const size_t host_pairs = align256(4 * n_pairs) + align256(8 * n_pairs) + align256(4 * n_pairs);
     if (rg_status s = grow_host(c, host_pairs + 4096 + align256(8 * (n_pairs + 1)) + 512)) return s;
@@ -292,7 +296,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
         }
         launch_fill_u32(bin_count, 0, NBINS, st);
         MatchArgs m;
-        m.op = op;
+        m.op = kop;
         m.materialize = mat;
         m.A = pa;
         m.B = pb;
@@ -330,7 +334,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
         launch_fill_u32(redo_count, 0, 1, st);
 
         ComputeArgs ca;
-        ca.op = op;
+        ca.op = kop;
         ca.materialize = mat;
         ca.A = pa;
         ca.B = pb;
@@ -399,7 +403,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
                               (flags & RG_FLAG_CARD) ? d_cards : nullptr, (flags & RG_FLAG_JACCARD) ? d_jacc : nullptr,
                               st);
     } else {
-        launch_finish_counts(op, acc, pa, pb, d_ia, d_ib, ia0, ib0, 0, (uint32_t)n_pairs,
+        launch_finish_counts(kop, op, acc, pa, pb, d_ia, d_ib, ia0, ib0, 0, (uint32_t)n_pairs,
                              (flags & RG_FLAG_CARD) ? d_cards : nullptr, (flags & RG_FLAG_JACCARD) ? d_jacc : nullptr,
                              st);
     }
@@ -573,6 +577,331 @@ rg_status rg_pool_digest(rg_ctx* c, const rg_pool* p, uint64_t* d_digest, void* 
     launch_pool_digest(*p, d_digest, (hipStream_t)stream);
     HIPCHK(c, hipGetLastError());
     return RG_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched count-only plans: fixed pairs, pools and outputs; sync-free execution
+// (graph-capturable); persistent work-stealing kernel; autotuned grid and
+// galloping ratio.
+// ===========================================================================
+
+struct rg_plan {
+    rg_ctx* ctx = nullptr;
+    int op = RG_AND;
+    uint32_t flags = 0;
+    rg_pool A{}, B{};
+    const uint32_t* d_ia = nullptr;
+    const uint32_t* d_ib = nullptr;
+    uint64_t n_pairs = 0;
+    uint64_t* d_cards = nullptr;
+    double* d_jacc = nullptr;
+    struct Wave {
+        uint64_t p0;
+        uint32_t np;
+        uint64_t C;
+        uint64_t* cand_off;
+    };
+    std::vector<Wave> waves;
+    void* mem = nullptr;
+    uint32_t* n_cand = nullptr;
+    uint64_t* bound = nullptr;
+    uint32_t* min_cont = nullptr;
+    long long* acc = nullptr;
+    uint32_t* err = nullptr;
+    Task* tasks = nullptr;
+    uint32_t* res_card = nullptr;
+    uint32_t* lists = nullptr;
+    uint32_t* bin_count = nullptr;
+    uint32_t* bin_info = nullptr;
+    uint32_t* cursor = nullptr;
+    uint32_t* next = nullptr;
+    uint64_t S_max = 0;
+    uint32_t grid = 0;
+    int dispatch_mode = RG_DISPATCH_HEURISTIC;
+    int fixed_bin = BIN_GEN;
+    uint32_t gallop_ratio = 64;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void plan_enqueue(rg_plan* p, hipStream_t st) {
+    const PoolView pa = view(p->A), pb = view(p->B);
+    launch_fill_u32(p->err, 0, 1, st);
+    // the plan accumulates |A n B| for every operation; the requested count
+    // follows from the Section 5.9 identities in the last step
+    launch_pair_prep(RG_AND, false, pa, pb, p->A.n_bitmaps, p->B.n_bitmaps, p->d_ia, p->d_ib, 0, 0, p->n_pairs,
+                     p->n_cand, p->bound, p->min_cont, p->acc, p->err, st);
+    for (const auto& w : p->waves) {
+        if (!w.C) continue;
+        launch_fill_u32(p->bin_count, 0, NBINS, st);
+        MatchArgs m;
+        m.op = RG_AND;
+        m.materialize = false;
+        m.A = pa;
+        m.B = pb;
+        m.ia = p->d_ia;
+        m.ib = p->d_ib;
+        m.ia0 = 0;
+        m.ib0 = 0;
+        m.pair0 = w.p0;
+        m.n_pairs = w.np;
+        m.cand_off = w.cand_off;
+        m.n_cand = w.C;
+        m.tasks = p->tasks;
+        m.ub = nullptr;
+        m.res_card = p->res_card;
+        m.bin_count = p->bin_count;
+        m.dispatch_mode = p->dispatch_mode;
+        m.fixed_bin = p->fixed_bin;
+        m.gallop_ratio = p->gallop_ratio;
+        launch_match(m, st);
+        launch_bin_info(p->bin_count, p->bin_info, p->cursor, p->next, st);
+        launch_bin_scatter(p->tasks, w.C, p->cursor, p->lists, st);
+        PersistArgs a{pa, pb, p->tasks, p->lists, p->bin_info, p->next, p->acc};
+        launch_persist(a, p->grid, st);
+    }
+    launch_finish_counts(RG_AND, p->op, p->acc, pa, pb, p->d_ia, p->d_ib, 0, 0, 0, (uint32_t)p->n_pairs,
+                         (p->flags & RG_FLAG_CARD) ? p->d_cards : nullptr,
+                         (p->flags & RG_FLAG_JACCARD) ? p->d_jacc : nullptr, st);
+}
+
+void plan_drop_graph(rg_plan* p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+rg_status rg_plan_create(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const uint32_t* d_ia,
+                         const uint32_t* d_ib, uint64_t n_pairs, uint32_t flags, uint64_t* d_cards, double* d_jacc,
+                         rg_plan** out_plan, void* stream) {
+    if (!c) return RG_EINVAL;
+    if (!out_plan) return fail(c, RG_EINVAL, "null plan pointer");
+    *out_plan = nullptr;
+    if (op < RG_AND || op > RG_ANDNOT) return fail(c, RG_EINVAL, "op must be RG_AND..RG_ANDNOT");
+    if (!pool_ok(A) || !pool_ok(B)) return fail(c, RG_EINVAL, "incomplete pool (null pointer)");
+    if (flags & RG_FLAG_MATERIALIZE) return fail(c, RG_ENOTSUP, "plans are count-only (RG_FLAG_CARD/JACCARD)");
+    if (!(flags & (RG_FLAG_CARD | RG_FLAG_JACCARD))) return fail(c, RG_EINVAL, "flags select no output");
+    if ((flags & RG_FLAG_CARD) && !d_cards) return fail(c, RG_EINVAL, "RG_FLAG_CARD needs d_cards");
+    if ((flags & RG_FLAG_JACCARD) && !d_jacc) return fail(c, RG_EINVAL, "RG_FLAG_JACCARD needs d_jacc");
+    if (n_pairs == 0 || n_pairs > 0xFFFFFFFFull || !d_ia || !d_ib)
+        return fail(c, RG_EINVAL, "a plan needs 1..2^32-1 pairs and device pair arrays");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    rg_plan* p = new rg_plan();
+    p->ctx = c;
+    p->op = op;
+    p->flags = flags;
+    p->A = *A;
+    p->B = *B;
+    p->d_ia = d_ia;
+    p->d_ib = d_ib;
+    p->n_pairs = n_pairs;
+    p->d_cards = d_cards;
+    p->d_jacc = d_jacc;
+    p->dispatch_mode = c->dispatch_mode;
+    p->fixed_bin = c->fixed_bin;
+    p->gallop_ratio = c->gallop_ratio;
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    p->grid = (uint32_t)cus * 8;
+
+    // candidate counts: one preparation pass, read back once
+    auto cleanup = [&](rg_status s) {
+        if (p->mem) (void)hipFree(p->mem);
+        delete p;
+        return s;
+    };
+    const size_t pair_bytes = align256(4 * n_pairs) + align256(8 * n_pairs) + align256(4 * n_pairs) +
+                              align256(8 * n_pairs) + 256;
+    std::vector<uint32_t> h_cand(n_pairs);
+    {
+        void* tmp = nullptr;
+        if (hipMalloc(&tmp, pair_bytes) != hipSuccess) return cleanup(fail(c, RG_EDEVICE, "hipMalloc failed"));
+        Bump b{(uint8_t*)tmp};
+        uint32_t* nc = b.take<uint32_t>(n_pairs);
+        uint64_t* bd = b.take<uint64_t>(n_pairs);
+        uint32_t* mc = b.take<uint32_t>(n_pairs);
+        long long* ac = b.take<long long>(n_pairs);
+        uint32_t* er = b.take<uint32_t>(1);
+        launch_fill_u32(er, 0, 1, st);
+        launch_pair_prep(RG_AND, false, view(*A), view(*B), A->n_bitmaps, B->n_bitmaps, d_ia, d_ib, 0, 0, n_pairs,
+                         nc, bd, mc, ac, er, st);
+        uint32_t h_err = 0;
+        hipError_t e1 = hipMemcpyAsync(h_cand.data(), nc, 4 * n_pairs, hipMemcpyDeviceToHost, st);
+        hipError_t e2 = hipMemcpyAsync(&h_err, er, 4, hipMemcpyDeviceToHost, st);
+        hipError_t e3 = hipStreamSynchronize(st);
+        (void)hipFree(tmp);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+            return cleanup(fail(c, RG_EDEVICE, "plan preparation failed"));
+        if (h_err) return cleanup(fail(c, RG_EINVAL, "pair index out of range of its pool"));
+    }
+    // waves
+    std::vector<uint64_t> starts{0};
+    uint64_t accs = 0;
+    for (uint64_t q = 0; q < n_pairs; ++q) {
+        if (accs + h_cand[q] > c->max_wave_slots && accs > 0) {
+            p->S_max = std::max(p->S_max, accs);
+            starts.push_back(q);
+            accs = 0;
+        }
+        accs += h_cand[q];
+    }
+    p->S_max = std::max(p->S_max, accs);
+    starts.push_back(n_pairs);
+    size_t offs_bytes = 0;
+    for (size_t w = 0; w + 1 < starts.size(); ++w) offs_bytes += align256(8 * (starts[w + 1] - starts[w] + 1));
+    const uint64_t S = std::max<uint64_t>(p->S_max, 1);
+    const size_t total = pair_bytes + offs_bytes + align256(sizeof(Task) * S) + 2 * align256(4 * S) + 4 * 256;
+    if (hipMalloc(&p->mem, total) != hipSuccess) return cleanup(fail(c, RG_EDEVICE, "hipMalloc failed"));
+    Bump b{(uint8_t*)p->mem};
+    p->n_cand = b.take<uint32_t>(n_pairs);
+    p->bound = b.take<uint64_t>(n_pairs);
+    p->min_cont = b.take<uint32_t>(n_pairs);
+    p->acc = b.take<long long>(n_pairs);
+    p->err = b.take<uint32_t>(1);
+    p->tasks = b.take<Task>(S);
+    p->res_card = b.take<uint32_t>(S);
+    p->lists = b.take<uint32_t>(S);
+    p->bin_count = b.take<uint32_t>(NBINS);
+    p->bin_info = b.take<uint32_t>(2 * NBINS);
+    p->cursor = b.take<uint32_t>(NBINS);
+    p->next = b.take<uint32_t>(NBINS);
+    std::vector<uint64_t> h_off;
+    for (size_t w = 0; w + 1 < starts.size(); ++w) {
+        rg_plan::Wave wv;
+        wv.p0 = starts[w];
+        wv.np = (uint32_t)(starts[w + 1] - starts[w]);
+        h_off.assign(wv.np + 1, 0);
+        for (uint32_t q = 0; q < wv.np; ++q) h_off[q + 1] = h_off[q] + h_cand[wv.p0 + q];
+        wv.C = h_off[wv.np];
+        wv.cand_off = b.take<uint64_t>(wv.np + 1);
+        if (hipMemcpy(wv.cand_off, h_off.data(), 8 * (wv.np + 1), hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(c, RG_EDEVICE, "plan upload failed"));
+        p->waves.push_back(wv);
+    }
+    *out_plan = p;
+    return RG_OK;
+}
+
+rg_status rg_plan_execute(rg_plan* p, void* stream) {
+    if (!p) return RG_EINVAL;
+    rg_ctx* c = p->ctx;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (p->exec) {
+        HIPCHK(c, hipGraphLaunch(p->exec, st));
+    } else {
+        plan_enqueue(p, st);
+        HIPCHK(c, hipGetLastError());
+    }
+    return RG_OK;
+}
+
+rg_status rg_plan_capture(rg_plan* p, void* stream) {
+    if (!p) return RG_EINVAL;
+    rg_ctx* c = p->ctx;
+    if (!stream) return fail(c, RG_EINVAL, "graph capture needs a non-default stream");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    plan_drop_graph(p);
+    HIPCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    plan_enqueue(p, st);
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamEndCapture(st, &g));
+    p->graph = g;
+    HIPCHK(c, hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0));
+    return RG_OK;
+}
+
+rg_status rg_plan_tune(rg_plan* p, void* stream, int reps) {
+    if (!p) return RG_EINVAL;
+    rg_ctx* c = p->ctx;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const bool had_graph = p->exec != nullptr;
+    plan_drop_graph(p);
+    if (reps < 1) reps = 3;
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    const uint32_t grids[] = {(uint32_t)cus * 2, (uint32_t)cus * 4, (uint32_t)cus * 8, (uint32_t)cus * 12,
+                              (uint32_t)cus * 16};
+    const uint32_t ratios[] = {8, 32, 128, 512};
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    float best = 1e30f;
+    uint32_t bg = p->grid, br = p->gallop_ratio;
+    for (uint32_t g : grids) {
+        for (uint32_t r : ratios) {
+            if (p->dispatch_mode != RG_DISPATCH_HEURISTIC && r != ratios[0]) continue;
+            p->grid = g;
+            p->gallop_ratio = r;
+            plan_enqueue(p, st);  // warm-up
+            float tot = 0;
+            for (int i = 0; i < reps; ++i) {
+                (void)hipEventRecord(e0, st);
+                plan_enqueue(p, st);
+                (void)hipEventRecord(e1, st);
+                HIPCHK(c, hipEventSynchronize(e1));
+                float ms = 0;
+                HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+                tot += ms;
+            }
+            if (tot < best) {
+                best = tot;
+                bg = g;
+                br = r;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->grid = bg;
+    p->gallop_ratio = br;
+    if (had_graph) return rg_plan_capture(p, stream);
+    return RG_OK;
+}
+
+rg_status rg_plan_info(const rg_plan* p, uint32_t* grid, uint32_t* gallop_ratio, uint64_t* slots, uint32_t* waves,
+                       int* graph) {
+    if (!p) return RG_EINVAL;
+    if (grid) *grid = p->grid;
+    if (gallop_ratio) *gallop_ratio = p->gallop_ratio;
+    if (slots) {
+        uint64_t s = 0;
+        for (const auto& w : p->waves) s += w.C;
+        *slots = s;
+    }
+    if (waves) *waves = (uint32_t)p->waves.size();
+    if (graph) *graph = p->exec != nullptr;
+    return RG_OK;
+}
+
+rg_status rg_plan_set(rg_plan* p, uint32_t grid, uint32_t gallop_ratio) {
+    if (!p || grid == 0 || gallop_ratio == 0) return RG_EINVAL;
+    const bool had_graph = p->exec != nullptr;
+    plan_drop_graph(p);
+    p->grid = grid;
+    p->gallop_ratio = gallop_ratio;
+    return had_graph ? RG_ENOTSUP : RG_OK;  // caller re-captures explicitly
+}
+
+void rg_plan_destroy(rg_plan* p) {
+    if (!p) return;
+    (void)hipSetDevice(p->ctx->device);
+    (void)hipDeviceSynchronize();
+    plan_drop_graph(p);
+    if (p->mem) (void)hipFree(p->mem);
+    delete p;
 }
 
 }  // extern "C"

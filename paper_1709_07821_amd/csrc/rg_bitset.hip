@@ -13,17 +13,22 @@
 // Word order in registers: lane l, step k holds words 128k + 2l and
 // 128k + 2l + 1 (lo, hi), so the word preceding (k, l, lo) is (k, l-1, hi),
 // or (k-1, 63, hi) for lane 0.
-#include "rg_internal.h"
+#include "rg_count_dev.h"
 
 namespace rg {
 
 template <int OP, bool MAT>
 __global__ void __launch_bounds__(256) k_bb(ComputeArgs a) {
     const uint32_t lane = lane_id();
-    const uint32_t w = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (w >= a.n) return;  // wave-uniform
-    const uint32_t slot = a.list[w];
-    const Task t = a.tasks[slot];
+    const uint32_t w = wave_index();
+    if (w >= a.n) return;
+    const uint32_t slot = uniform(a.list[w]);
+    const Task t = uniform_task(a.tasks, slot);
+    if (!MAT) {
+        const uint32_t c = bb_count_wave<OP>(a.A, a.B, t, lane);
+        if (lane == 0) acc_add(a.acc, t.pair, (long long)c);
+        return;
+    }
     const u32x4* pa = reinterpret_cast<const u32x4*>(a.A.payload + a.A.off[t.ia]);
     const u32x4* pb = reinterpret_cast<const u32x4*>(a.B.payload + a.B.off[t.ib]);
     u32x4 x[8], y[8];
@@ -43,16 +48,6 @@ __global__ void __launch_bounds__(256) k_bb(ComputeArgs a) {
         lo[k] = apply_op<OP>(xa, ya);
         hi[k] = apply_op<OP>(xb, yb);
         c += __popcll(lo[k]) + __popcll(hi[k]);
-    }
-    if (!MAT) {
-        c = wave_sum_u32(c);
-        if (lane == 0) {
-            long long d = (long long)c;
-            if (OP == RG_OR || OP == RG_XOR) d -= (long long)a.A.card[t.ia] + (long long)a.B.card[t.ib];
-            else if (OP == RG_ANDNOT) d -= (long long)a.A.card[t.ia];
-            atomicAdd(reinterpret_cast<unsigned long long*>(&a.acc[t.pair]), (unsigned long long)d);
-        }
-        return;
     }
     // run starts: bit set and the bit below it (previous word's MSB for bit 0) clear
     uint32_t r = 0;
@@ -92,20 +87,19 @@ __global__ void __launch_bounds__(256) k_bb(ComputeArgs a) {
     }
 }
 
-template <int OP>
-static void launch_bb_op(const ComputeArgs& a, hipStream_t st) {
-    dim3 grid((a.n + 3) / 4);
-    if (a.materialize) hipLaunchKernelGGL((k_bb<OP, true>), grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_bb<OP, false>), grid, dim3(256), 0, st, a);
-}
-
 void launch_bb(const ComputeArgs& a, hipStream_t st) {
     if (!a.n) return;
+    const dim3 grid((a.n + 3) / 4);
+    // count-only calls accumulate the intersection for every operation
+    if (!a.materialize) {
+        hipLaunchKernelGGL((k_bb<RG_AND, false>), grid, dim3(256), 0, st, a);
+        return;
+    }
     switch (a.op) {
-    case RG_AND: launch_bb_op<RG_AND>(a, st); break;
-    case RG_OR: launch_bb_op<RG_OR>(a, st); break;
-    case RG_XOR: launch_bb_op<RG_XOR>(a, st); break;
-    default: launch_bb_op<RG_ANDNOT>(a, st); break;
+    case RG_AND: hipLaunchKernelGGL((k_bb<RG_AND, true>), grid, dim3(256), 0, st, a); break;
+    case RG_OR: hipLaunchKernelGGL((k_bb<RG_OR, true>), grid, dim3(256), 0, st, a); break;
+    case RG_XOR: hipLaunchKernelGGL((k_bb<RG_XOR, true>), grid, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_bb<RG_ANDNOT, true>), grid, dim3(256), 0, st, a); break;
     }
 }
 
@@ -114,24 +108,29 @@ void launch_bb(const ComputeArgs& a, hipStream_t st) {
 // present in A only): copied through unchanged, already in P1 form.
 __global__ void __launch_bounds__(256) k_copy(ComputeArgs a) {
     const uint32_t lane = lane_id();
-    const uint32_t w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t w = wave_index();
     if (w >= a.n) return;
-    const uint32_t slot = a.list[w];
-    const Task t = a.tasks[slot];
+    const uint32_t slot = uniform(a.list[w]);
+    const Task t = uniform_task(a.tasks, slot);
     const bool fromA = t.kind == KIND_COPY_A;
-    const PoolView& P = fromA ? a.A : a.B;
     const uint32_t idx = fromA ? t.ia : t.ib;
-    const uint8_t type = P.types[idx];
-    const uint32_t size = P.size[idx];
+    const uint8_t* types = fromA ? a.A.types : a.B.types;
+    const uint32_t* sizes = fromA ? a.A.size : a.B.size;
+    const uint32_t* cards = fromA ? a.A.card : a.B.card;
+    const uint64_t* offs = fromA ? a.A.off : a.B.off;
+    const uint8_t* payload = fromA ? a.A.payload : a.B.payload;
+    const uint8_t type = (uint8_t)uniform(types[idx]);
+    const uint32_t size = uniform(sizes[idx]);
+    const uint32_t card = uniform(cards[idx]);
     // the slot holds wbytes_of(card) bytes; a canonical container always fits
     uint32_t n16 = round16(payload_bytes_of(type, size)) >> 4;
-    const uint32_t cap16 = wbytes_of(P.card[idx]) >> 4;
+    const uint32_t cap16 = wbytes_of(card) >> 4;
     if (n16 > cap16) n16 = cap16;
-    const u32x4* src = reinterpret_cast<const u32x4*>(P.payload + P.off[idx]);
+    const u32x4* src = reinterpret_cast<const u32x4*>(payload + uniform64(offs[idx]));
     u32x4* dst = reinterpret_cast<u32x4*>(a.so.payload + a.so.slot_off[slot]);
     for (uint32_t i = lane; i < n16; i += 64) dst[i] = src[i];
     if (lane == 0) {
-        a.so.res_card[slot] = P.card[idx];
+        a.so.res_card[slot] = card;
         a.so.res_type[slot] = type;
         a.so.res_size[slot] = size;
     }

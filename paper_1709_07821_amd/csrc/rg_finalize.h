@@ -23,9 +23,13 @@ struct WgShared {
 // Bitset: copied. Ends with a barrier. idx == NONE gives the empty set.
 __device__ inline void expand_container(uint64_t* s, const PoolView& P, uint32_t idx, WgShared& sh) {
     const uint32_t tid = threadIdx.x;
-    const uint8_t type = idx == NONE ? 0 : P.types[idx];
+    // type, size and offset are the same for the whole workgroup; as scalars
+    // they keep every branch below (each holds barriers) uniform control flow
+    const uint8_t type = idx == NONE ? 0 : (uint8_t)uniform(P.types[idx]);
+    const uint32_t size = idx == NONE ? 0 : uniform(P.size[idx]);
+    const uint8_t* pl = idx == NONE ? nullptr : P.payload + uniform64(P.off[idx]);
     if (type == RG_BITSET) {
-        const u32x4* src = reinterpret_cast<const u32x4*>(P.payload + P.off[idx]);
+        const u32x4* src = reinterpret_cast<const u32x4*>(pl);
         for (uint32_t i = tid; i < 512; i += 256) {
             u32x4 v = src[i];
             s[2 * i] = (uint64_t)v.x | ((uint64_t)v.y << 32);
@@ -37,16 +41,16 @@ __device__ inline void expand_container(uint64_t* s, const PoolView& P, uint32_t
     for (uint32_t i = tid; i < 1024; i += 256) s[i] = 0;
     __syncthreads();
     if (type == RG_ARRAY) {
-        const uint16_t* v = reinterpret_cast<const uint16_t*>(P.payload + P.off[idx]);
-        const uint32_t c = P.size[idx];
+        const uint16_t* v = reinterpret_cast<const uint16_t*>(pl);
+        const uint32_t c = size;
         for (uint32_t i = tid; i < c; i += 256) {
             uint32_t x = v[i];
             atomicOr(reinterpret_cast<unsigned long long*>(&s[x >> 6]), 1ull << (x & 63));
         }
         __syncthreads();
     } else if (type == RG_RUN) {
-        const uint32_t* rp = reinterpret_cast<const uint32_t*>(P.payload + P.off[idx]);
-        const uint32_t r = P.size[idx];
+        const uint32_t* rp = reinterpret_cast<const uint32_t*>(pl);
+        const uint32_t r = size;
         for (uint32_t i = tid; i < r; i += 256) {
             uint32_t pr = rp[i];
             uint32_t st = pr & 0xFFFFu, e = st + (pr >> 16) + 1;
@@ -191,13 +195,6 @@ __device__ inline uint32_t count_words(const uint64_t (&w)[4], WgShared& sh) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) ct += __popcll(w[j]);
     return (uint32_t)block_sum_u64(ct, sh.tmp64);
-}
-
-__device__ inline void add_count_delta(int op, const ComputeArgs& a, const Task& t, uint32_t c) {
-    long long d = (long long)c;
-    if (op == RG_OR || op == RG_XOR) d -= (long long)a.A.card[t.ia] + (long long)a.B.card[t.ib];
-    else if (op == RG_ANDNOT) d -= (long long)a.A.card[t.ia];
-    atomicAdd(reinterpret_cast<unsigned long long*>(&a.acc[t.pair]), (unsigned long long)d);
 }
 
 }  // namespace rg

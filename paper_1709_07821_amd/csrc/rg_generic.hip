@@ -7,17 +7,17 @@
 //
 // One 256-thread workgroup per container pair, grid-stride over the list so
 // that a device-side count (the bitset redo list) can drive it.
-#include "rg_finalize.h"
+#include "rg_count_dev.h"
 
 namespace rg {
 
 template <int OP, bool MAT>
 __global__ void __launch_bounds__(256) k_generic(ComputeArgs a) {
     __shared__ WgShared sh;
-    const uint32_t n = a.n_dev ? *a.n_dev : a.n;
+    const uint32_t n = a.n_dev ? uniform(*a.n_dev) : a.n;
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const uint32_t slot = a.list[i];
-        const Task t = a.tasks[slot];
+        const uint32_t slot = uniform(a.list[i]);
+        const Task t = uniform_task(a.tasks, slot);
         expand_container(sh.sa, a.A, t.ia, sh);
         expand_container(sh.sb, a.B, t.ib, sh);
         uint64_t w[4];
@@ -26,17 +26,16 @@ __global__ void __launch_bounds__(256) k_generic(ComputeArgs a) {
         if (MAT) {
             finalize_words(w, slot, a.so, sh.sa, sh.sb, sh);
         } else {
-            uint32_t c = count_words(w, sh);
-            if (threadIdx.x == 0) add_count_delta(OP, a, t, c);
+            const uint32_t c = count_words(w, sh);
+            if (threadIdx.x == 0) acc_add(a.acc, t.pair, (long long)c);
         }
         __syncthreads();
     }
 }
 
 template <int OP>
-static void launch_gen_op(const ComputeArgs& a, uint32_t grid, hipStream_t st) {
-    if (a.materialize) hipLaunchKernelGGL((k_generic<OP, true>), dim3(grid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_generic<OP, false>), dim3(grid), dim3(256), 0, st, a);
+static void launch_gen_mat(const ComputeArgs& a, uint32_t grid, hipStream_t st) {
+    hipLaunchKernelGGL((k_generic<OP, true>), dim3(grid), dim3(256), 0, st, a);
 }
 
 void launch_generic(const ComputeArgs& a, hipStream_t st) {
@@ -44,11 +43,16 @@ void launch_generic(const ComputeArgs& a, hipStream_t st) {
     if (a.n_dev) grid = a.n;  // caller passes the maximum possible count as n
     if (!grid) return;
     if (grid > 65536u) grid = 65536u;
+    // count-only calls accumulate the intersection for every operation
+    if (!a.materialize) {
+        hipLaunchKernelGGL((k_generic<RG_AND, false>), dim3(grid), dim3(256), 0, st, a);
+        return;
+    }
     switch (a.op) {
-    case RG_AND: launch_gen_op<RG_AND>(a, grid, st); break;
-    case RG_OR: launch_gen_op<RG_OR>(a, grid, st); break;
-    case RG_XOR: launch_gen_op<RG_XOR>(a, grid, st); break;
-    default: launch_gen_op<RG_ANDNOT>(a, grid, st); break;
+    case RG_AND: launch_gen_mat<RG_AND>(a, grid, st); break;
+    case RG_OR: launch_gen_mat<RG_OR>(a, grid, st); break;
+    case RG_XOR: launch_gen_mat<RG_XOR>(a, grid, st); break;
+    default: launch_gen_mat<RG_ANDNOT>(a, grid, st); break;
     }
 }
 

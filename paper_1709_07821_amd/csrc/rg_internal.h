@@ -68,6 +68,35 @@ struct SlotOut {
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// Values that are the same in every lane of a wave (task indices, container
+// types and sizes, counts summed over the wave or workgroup) are passed through
+// readfirstlane so the compiler holds them in scalar registers and every
+// branch, loop exit and early return that depends on them is scalar control
+// flow. Barriers and cross-lane operations must only sit under such branches.
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// index of the calling wave in a grid of 256-thread workgroups, as a scalar
+__device__ __forceinline__ uint32_t wave_index() { return uniform(blockIdx.x * 4 + (threadIdx.x >> 6)); }
+
+// a task record read by every lane of a wave, with all fields made uniform
+__device__ __forceinline__ Task uniform_task(const Task* tasks, uint32_t slot) {
+    const Task t = tasks[slot];
+    Task u;
+    u.pair = uniform(t.pair);
+    u.ia = uniform(t.ia);
+    u.ib = uniform(t.ib);
+    const uint32_t w = uniform((uint32_t)t.key | ((uint32_t)t.kind << 16) | ((uint32_t)t.bin << 24));
+    u.key = (uint16_t)w;
+    u.kind = (uint8_t)(w >> 16);
+    u.bin = (uint8_t)(w >> 24);
+    return u;
+}
+
 __device__ __forceinline__ uint32_t round16(uint32_t b) { return (b + 15u) & ~15u; }
 
 // P1: least-memory container type allowed by the size rules
@@ -98,13 +127,13 @@ __device__ __forceinline__ uint64_t apply_op(uint64_t a, uint64_t b) {
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    return uniform(v);
 }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    return uniform64(v);
 }
 
 // inclusive prefix sum over the 64 lanes of a wave
@@ -133,7 +162,7 @@ __device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t* tm
         tot += t;
     }
     __syncthreads();
-    *total = tot;
+    *total = uniform(tot);
     return base + inc - v;
 }
 
@@ -142,7 +171,7 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* tmp) {
     v = wave_sum_u64(v);
     if (lane == 0) tmp[wid] = v;
     __syncthreads();
-    uint64_t s = tmp[0] + tmp[1] + tmp[2] + tmp[3];
+    uint64_t s = uniform64(tmp[0] + tmp[1] + tmp[2] + tmp[3]);
     __syncthreads();
     return s;
 }
@@ -225,12 +254,28 @@ void launch_flags(const uint32_t* res_card, uint32_t* flags, uint64_t n, hipStre
 void launch_compact(const CompactArgs& c, hipStream_t st);
 void launch_bm_begin(const uint64_t* cand_off, const uint64_t* out_idx, uint64_t n_slots, const uint64_t* out_total,
                      uint32_t n_pairs, uint64_t pair0, uint64_t* bm_begin, bool last_wave, hipStream_t st);
-void launch_finish_counts(int op, const long long* acc, PoolView A, PoolView B, const uint32_t* ia,
+// acc_op: the operation whose cardinality the accumulator holds; out_op: the
+// operation whose cardinality goes to d_cards (converted with the Section 5.9
+// identities when they differ)
+void launch_finish_counts(int acc_op, int out_op, const long long* acc, PoolView A, PoolView B, const uint32_t* ia,
                           const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t pair0, uint32_t n_pairs,
                           uint64_t* d_cards, double* d_jacc, hipStream_t st);
 void launch_mat_counts(int op, const uint64_t* bm_card, PoolView A, PoolView B, const uint32_t* ia,
                        const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs, uint64_t* d_cards,
                        double* d_jacc, hipStream_t st);
+
+// persistent work-stealing count kernel (batched plans)
+struct PersistArgs {
+    PoolView A, B;
+    const Task* tasks;
+    const uint32_t* lists;     // bin lists
+    const uint32_t* bin_info;  // [NBINS] counts, then [NBINS] offsets (device)
+    uint32_t* next;            // [NBINS] work counters, reset by k_bin_info
+    long long* acc;
+};
+void launch_bin_info(const uint32_t* bin_count, uint32_t* bin_info, uint32_t* cursor, uint32_t* next,
+                     hipStream_t st);
+void launch_persist(const PersistArgs& a, uint32_t grid, hipStream_t st);
 
 // pool utilities
 void launch_pool_recount(const rg_pool& p, hipStream_t st);

@@ -119,23 +119,37 @@ __device__ __forceinline__ uint32_t find_pair(const uint64_t* off, uint32_t n_pa
 
 // Variant selection (plain heuristic). It never changes results: every bin
 // computes the same set; the bins differ only in how.
-__device__ __forceinline__ uint8_t classify(int op, uint8_t kind, uint8_t ta, uint8_t tb, uint32_t ca, uint32_t cb,
-                                            uint32_t sa, uint32_t sb, int mode, int fixed_bin,
+__device__ __forceinline__ bool variant_applies(int bin, uint8_t ta, uint8_t tb) {
+    const bool aa = ta == RG_ARRAY && tb == RG_ARRAY;
+    const bool ab = (ta == RG_ARRAY && tb == RG_BITSET) || (ta == RG_BITSET && tb == RG_ARRAY);
+    const bool run = ta == RG_RUN || tb == RG_RUN;
+    switch (bin) {
+    case BIN_GEN: return true;
+    case BIN_AA: return aa;
+    case BIN_GALLOP: return aa;
+    case BIN_AB: return ab;
+    case BIN_RR: return run;
+    default: return false;
+    }
+}
+
+__device__ __forceinline__ uint8_t classify(int op, bool materialize, uint8_t kind, uint8_t ta, uint8_t tb,
+                                            uint32_t ca, uint32_t cb, int mode, int fixed_bin,
                                             uint32_t gallop_ratio) {
     if (kind == KIND_COPY_A || kind == KIND_COPY_B) return BIN_COPY;
     if (ta == RG_BITSET && tb == RG_BITSET) return BIN_BB;
-    if (mode == 2) {
-        // forced variant where it applies, otherwise the generic kernel
-        if (fixed_bin == BIN_GEN) return BIN_GEN;
-        if (fixed_bin == BIN_AA && ta == RG_ARRAY && tb == RG_ARRAY) return BIN_AA;
-        if (fixed_bin == BIN_GALLOP && ta == RG_ARRAY && tb == RG_ARRAY) return BIN_GALLOP;
-        if (fixed_bin == BIN_AB && ((ta == RG_ARRAY && tb == RG_BITSET) || (ta == RG_BITSET && tb == RG_ARRAY)))
-            return BIN_AB;
-        if (fixed_bin == BIN_RR && (ta == RG_RUN || tb == RG_RUN) && ta != RG_BITSET && tb != RG_BITSET)
-            return BIN_RR;
-        return BIN_GEN;
+    if (materialize) return BIN_GEN;  // specialised variants are count-only
+    if (mode == 2) return variant_applies(fixed_bin, ta, tb) ? (uint8_t)fixed_bin : (uint8_t)BIN_GEN;
+    // heuristic: galloping when one array is much smaller (Section 2.2)
+    if (ta == RG_ARRAY && tb == RG_ARRAY) {
+        uint32_t mx = ca > cb ? ca : cb, mn = ca < cb ? ca : cb;
+        return (uint64_t)mx >= (uint64_t)gallop_ratio * mn ? BIN_GALLOP : BIN_AA;
     }
-    return BIN_GEN;
+    if (ta == RG_ARRAY || tb == RG_ARRAY) {
+        if (ta == RG_BITSET || tb == RG_BITSET) return BIN_AB;
+        return BIN_RR;  // array-run
+    }
+    return BIN_RR;      // run-run, run-bitset
 }
 
 __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
@@ -214,9 +228,7 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
                 uint8_t tb = task.ib != NONE ? m.B.types[task.ib] : 0;
                 uint32_t ca = task.ia != NONE ? m.A.card[task.ia] : 0;
                 uint32_t cb = task.ib != NONE ? m.B.card[task.ib] : 0;
-                uint32_t sa = task.ia != NONE ? m.A.size[task.ia] : 0;
-                uint32_t sb = task.ib != NONE ? m.B.size[task.ib] : 0;
-                task.bin = classify(m.op, task.kind, ta, tb, ca, cb, sa, sb, m.dispatch_mode, m.fixed_bin,
+                task.bin = classify(m.op, m.materialize, task.kind, ta, tb, ca, cb, m.dispatch_mode, m.fixed_bin,
                                     m.gallop_ratio);
                 atomicAdd(&cnt[task.bin], 1u);
                 if (m.materialize) {

@@ -19,11 +19,11 @@ __device__ __forceinline__ uint32_t bitmap_of(const uint64_t* bm_begin, uint32_t
 // ------------------------------------------------------------------ recount
 __global__ void __launch_bounds__(256) k_recount(rg_pool p) {
     const uint32_t lane = lane_id();
-    const uint64_t i = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint64_t i = wave_index();
     if (i >= p.n_containers) return;
-    const uint8_t type = p.types[i];
-    const uint32_t size = p.size[i];
-    const uint8_t* pl = p.payload + p.off[i];
+    const uint8_t type = (uint8_t)uniform(p.types[i]);
+    const uint32_t size = uniform(p.size[i]);
+    const uint8_t* pl = p.payload + uniform64(p.off[i]);
     uint32_t c = 0;
     if (type == RG_ARRAY) {
         c = size;
@@ -58,11 +58,11 @@ void launch_pool_recount(const rg_pool& p, hipStream_t st) {
 // ------------------------------------------------------------------ validate
 __global__ void __launch_bounds__(256) k_validate(rg_pool p, unsigned long long* bad) {
     const uint32_t lane = lane_id();
-    const uint64_t i = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint64_t i = wave_index();
     if (i >= p.n_containers) return;
-    const uint8_t type = p.types[i];
-    const uint32_t size = p.size[i], card = p.card[i];
-    const uint64_t off = p.off[i];
+    const uint8_t type = (uint8_t)uniform(p.types[i]);
+    const uint32_t size = uniform(p.size[i]), card = uniform(p.card[i]);
+    const uint64_t off = uniform64(p.off[i]);
     bool ok = type >= RG_ARRAY && type <= RG_RUN && (off & 15) == 0 && card >= 1 && card <= 65536;
     if (ok) {
         uint64_t bytes = payload_bytes_of(type, size);
@@ -154,12 +154,12 @@ __device__ __forceinline__ uint64_t dmix64(uint64_t z) {
 
 __global__ void __launch_bounds__(256) k_digest(rg_pool p, uint64_t* digest) {
     const uint32_t lane = lane_id();
-    const uint64_t i = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint64_t i = wave_index();
     if (i >= p.n_containers) return;
-    const uint8_t type = p.types[i];
-    const uint32_t size = p.size[i], card = p.card[i];
-    const uint32_t key = p.keys[i];
-    const uint8_t* pl = p.payload + p.off[i];
+    const uint8_t type = (uint8_t)uniform(p.types[i]);
+    const uint32_t size = uniform(p.size[i]), card = uniform(p.card[i]);
+    const uint32_t key = uniform(p.keys[i]);
+    const uint8_t* pl = p.payload + uniform64(p.off[i]);
     uint32_t npl = type == RG_ARRAY ? (size + 3) / 4 : type == RG_BITSET ? 1024 : (size + 1) / 2;
     uint64_t sum = 0;
     for (uint32_t k = lane; k < npl + 2; k += 64) {

@@ -1,0 +1,150 @@
+"""Batched plans on the GPU: persistent work-stealing execution, hipGraph
+capture and replay, autotuning - all against the oracle and the eager path."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import rgtest
+
+pytestmark = pytest.mark.gpu
+
+OPS = ("and", "or", "xor", "andnot")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rg():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1709_07821_amd as rg
+
+    return rg
+
+
+@pytest.fixture(scope="module")
+def ctx(rg):
+    c = rg.Context(0)
+    yield c
+    c.close()
+
+
+def _t(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).cuda()
+
+
+def _expect(bs, ia, ib, op):
+    card = np.array([oracle.count(op, bs[int(x)], bs[int(y)]) for x, y in zip(ia, ib)], np.uint64)
+    jac = np.array([oracle.jaccard(bs[int(x)], bs[int(y)]) for x, y in zip(ia, ib)])
+    return card, jac
+
+
+def _workloads():
+    sets = rgtest.edge_sets()
+    k = len(sets)
+    yield "edges", synth.BitmapSet.from_list(sets), np.repeat(np.arange(k), k), np.tile(np.arange(k), k)
+    bs = synth.mixed_small()
+    ia, ib = synth.consecutive_pairs(len(bs))
+    yield "mixed", bs, ia, ib
+    bs, ia, ib = synth.array_stress(n_pairs=4000)
+    yield "array-stress", bs, ia, ib
+
+
+@pytest.mark.parametrize("which", ["edges", "mixed", "array-stress"])
+def test_plan_matches_oracle(rg, ctx, which):
+    import torch
+
+    name, bs, ia, ib = next(w for w in _workloads() if w[0] == which)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    tia, tib = _t(ia), _t(ib)
+    for op in OPS:
+        _say(f"[plan {name}] op={op} pairs={len(ia)}")
+        card, jac = _expect(bs, ia, ib, op)
+        pl = rg.Plan(ctx, op, P, P, tia, tib, card=True, jaccard=True)
+        for rep in range(2):
+            pl.cards.zero_()
+            pl.jacc.zero_()
+            pl.execute()
+            torch.cuda.synchronize()
+            assert np.array_equal(pl.cards.cpu().numpy().view(np.uint64), card), (name, op, rep)
+            assert np.array_equal(pl.jacc.cpu().numpy(), jac), (name, op, rep)
+        pl.close()
+
+
+def test_plan_graph_replays_match_eager(rg, ctx):
+    """Capture once on a side stream; replay several times with eager work and
+    synchronisations in between; every replay equals the eager result."""
+    import torch
+
+    bs = synth.mixed_small(n_bitmaps=40, seed=21)
+    ia, ib = synth.random_pairs(len(bs), 300, seed=21)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    tia, tib = _t(ia), _t(ib)
+    for op in ("and", "xor"):
+        _, eager_cards, eager_jacc = rg.batch(ctx, op, P, P, tia, tib, materialize=False, card=True, jaccard=True)
+        torch.cuda.synchronize()
+        eager_cards = eager_cards.cpu().numpy().copy()
+        eager_jacc = eager_jacc.cpu().numpy().copy()
+        card, jac = _expect(bs, ia, ib, op)
+        assert np.array_equal(eager_cards.view(np.uint64), card)
+        side = torch.cuda.Stream()
+        pl = rg.Plan(ctx, op, P, P, tia, tib, card=True, jaccard=True, stream=side)
+        torch.cuda.synchronize()
+        pl.capture(side)
+        assert pl.info()["graph"]
+        for rep in range(4):
+            pl.cards.zero_()
+            pl.jacc.zero_()
+            torch.cuda.synchronize()
+            with torch.cuda.stream(side):
+                pl.execute(side)
+            side.synchronize()
+            assert np.array_equal(pl.cards.cpu().numpy(), eager_cards), (op, rep)
+            assert np.array_equal(pl.jacc.cpu().numpy(), eager_jacc), (op, rep)
+            # eager work between replays
+            rg.batch(ctx, "or", P, P, tia, tib, materialize=False, card=True)
+            torch.cuda.synchronize()
+        pl.close()
+
+
+def test_plan_tune_keeps_results(rg, ctx):
+    import torch
+
+    bs, ia, ib = synth.array_stress(n_pairs=2000)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    tia, tib = _t(ia), _t(ib)
+    card, jac = _expect(bs, ia, ib, "and")
+    pl = rg.Plan(ctx, "and", P, P, tia, tib, card=True, jaccard=True)
+    pl.tune(reps=1)
+    info = pl.info()
+    _say(f"[tune] chose {info}")
+    pl.cards.zero_()
+    pl.execute()
+    torch.cuda.synchronize()
+    assert np.array_equal(pl.cards.cpu().numpy().view(np.uint64), card)
+    assert np.array_equal(pl.jacc.cpu().numpy(), jac)
+    for g, r in [(256, 8), (4096, 1000)]:
+        pl.set(g, r)
+        pl.cards.zero_()
+        pl.execute()
+        torch.cuda.synchronize()
+        assert np.array_equal(pl.cards.cpu().numpy().view(np.uint64), card), (g, r)
+    pl.close()
+
+
+def test_plan_errors(rg, ctx):
+    import torch
+
+    bs = synth.mixed_small(n_bitmaps=3, seed=22)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    with pytest.raises(rg.RoaringError):
+        rg.Plan(ctx, "and", P, P, _t(np.array([0, 9], np.uint32)), _t(np.array([1, 1], np.uint32)))
