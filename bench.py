@@ -43,6 +43,13 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=24, help="pairs in the oracle timing sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", type=int, default=2, help="pairs checked against the oracle before timing")
+    ap.add_argument("--workload", choices=("dense", "batched"), default="dense",
+                    help="dense: the bitset-bandwidth headline; batched: many uneven pairs, plan vs per-pair")
+    ap.add_argument("--pool", type=int, default=1024, help="batched: bitmaps in the pool")
+    ap.add_argument("--batched-pairs", type=int, default=100000, help="batched: random pairs per step")
+    ap.add_argument("--per-pair-sample", type=int, default=500, help="batched: pairs timed one call each")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run one plain device-to-device copy of BYTES bytes (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -57,6 +64,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe // 8, dtype=torch.int64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copied {src.numel() * 8} bytes device to device", file=sys.stderr, flush=True)
+        return None
+    if args.workload == "batched":
+        return bench_batched(args)
     dev = torch.device("cuda:0")
     ctx = rg.Context(0)
     stream = torch.cuda.current_stream()
@@ -134,6 +151,8 @@ def main():
                 "kernel": "k_bb<op, count-only>", "mean_launch_ms": round(mean_s * 1e3, 4),
                 "launches": int(k["launches"]), "bytes_per_launch": int(alg_bytes)}
 
+    if roof is not None:
+        roof["traffic"] = measured_traffic()
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(ia, ib, nk, args.cpu_pairs)
@@ -152,6 +171,137 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def bench_batched(args):
+    """Many uneven pairs: |A n B| and Jaccard for every pair of a random pair list
+    over a pool of mixed bitmaps (lognormal cardinality, median 1e4, sigma 2,
+    clipped to [10, 1e7], over [0, 2^32), 40/30/30 sparse/dense/run with a
+    256-key hot set). Three executions of the same step, same results:
+    one library call per pair; one batched call (host-synchronised waves);
+    a plan (persistent work-stealing kernel, autotuned, replayed as a hipGraph)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1709_07821_amd as rg
+    import synth
+
+    dev = torch.device("cuda:0")
+    ctx = rg.Context(0)
+    seed = synth.SEED_BASE + 3
+    t0 = time.time()
+    hot = synth.hot_keys(seed, 256, 1 << 16)
+    cards = [synth.lognormal_card(i, 1e4, 2.0, 10, 10 ** 7, seed) for i in range(args.pool)]
+    bs = synth.BitmapSet.from_list([synth.mixed_bitmap(seed, i, cards[i], 32, hot) for i in range(args.pool)])
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    ia, ib = synth.random_pairs(args.pool, args.batched_pairs, seed)
+    n = len(ia)
+    tia = torch.from_numpy(ia.view(np.int32)).to(dev)
+    tib = torch.from_numpy(ib.view(np.int32)).to(dev)
+    torch.cuda.synchronize()
+    print(f"# pool of {args.pool} bitmaps, {len(bs.values)} values, {P.c.n_containers} containers, "
+          f"{n} pairs, built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    # eager batched call; also gives the matched container pairs (profile items)
+    rg.profile_enable(ctx, True)
+    rg.profile_reset(ctx)
+    _, c_e, j_e = rg.batch(ctx, "and", P, P, tia, tib, materialize=False, card=True, jaccard=True)
+    torch.cuda.synchronize()
+    matched = sum(v["items"] for v in rg.profile_read(ctx).values())
+    rg.profile_enable(ctx, False)
+    c_e, j_e = c_e.cpu().numpy().view(np.uint64), j_e.cpu().numpy()
+    for p in range(0, n, max(1, n // 16)):
+        a, b = bs[int(ia[p])], bs[int(ib[p])]
+        assert int(c_e[p]) == oracle.count("and", a, b) and j_e[p] == oracle.jaccard(a, b), p
+    print(f"# 16 sampled pairs match the oracle; {matched} matched container pairs per step",
+          file=sys.stderr, flush=True)
+
+    def timed(fn, steps, warm):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps
+
+    eager_s = timed(lambda: rg.batch(ctx, "and", P, P, tia, tib, materialize=False, card=True, jaccard=True),
+                    args.steps, 1)
+    print(f"# eager batched: {eager_s * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+
+    # plan: tuned, captured, replayed on a side stream
+    st = torch.cuda.Stream()
+    pl = rg.Plan(ctx, "and", P, P, tia, tib, card=True, jaccard=True, stream=st)
+    pl.tune(stream=st, reps=1)
+    pl.capture(st)
+    torch.cuda.synchronize()
+
+    def run_plan():
+        pl.execute(stream=st)
+
+    plan_s = timed(run_plan, args.steps, args.warmup)
+    assert np.array_equal(pl.cards.cpu().numpy().view(np.uint64), c_e)
+    assert np.array_equal(pl.jacc.cpu().numpy(), j_e)
+    info = pl.info()
+    print(f"# plan (graph, {info}): {plan_s * 1e3:.2f} ms/step, results equal to the eager call",
+          file=sys.stderr, flush=True)
+
+    # one call per pair, on a sample
+    k = min(args.per_pair_sample, n)
+    one_c = torch.zeros(1, dtype=torch.int64, device=dev)
+    one_j = torch.zeros(1, dtype=torch.float64, device=dev)
+    flags = rg.RG_FLAG_CARD | rg.RG_FLAG_JACCARD
+
+    def per_pair():
+        for p in range(k):
+            ctx.check(rg.roaring_batch(ctx, "and", P, P, tia[p:p + 1], tib[p:p + 1], flags, None, one_c, one_j))
+
+    pp_s = timed(per_pair, 1, 0) / k * n
+    print(f"# one call per pair: {pp_s / n * 1e6:.1f} us/pair on {k} pairs -> {pp_s * 1e3:.1f} ms/step",
+          file=sys.stderr, flush=True)
+    pl.close()
+
+    line = {
+        "metric": "container-pairs/sec, batched count + Jaccard over uneven pairs",
+        "value": round(matched / plan_s, 1), "unit": "container-pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(plan_s * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"batched uneven pairs: pool of {args.pool} mixed bitmaps (lognormal card, median "
+                               f"1e4, sigma 2, [10, 1e7], universe 2^32), {n} random pairs, |A n B| + Jaccard",
+                   "pool": args.pool, "pairs": n, "parallelism": "single GPU"},
+        "pairs_per_s": round(n / plan_s, 1),
+        "matched_container_pairs": int(matched),
+        "plan": info,
+        "eager_batched_ms": round(eager_s * 1e3, 3),
+        "per_pair_ms_extrapolated": round(pp_s * 1e3, 3),
+        "speedup_plan_vs_per_pair": round(pp_s / plan_s, 2),
+        "speedup_plan_vs_eager": round(eager_s / plan_s, 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def measured_traffic():
+    """HBM bytes per k_bb count launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel sources have changed since it was taken."""
+    import hashlib
+
+    prof = os.path.join(ROOT, "profiles", "k_bb_count_dense_bitsets.md")
+    if not os.path.exists(prof):
+        return None
+    text = open(prof).read()
+    tb = [l.split(":", 1)[1].strip() for l in text.splitlines() if l.startswith("traffic_bytes_per_launch:")]
+    hv = [l.split(":", 1)[1].strip() for l in text.splitlines() if l.startswith("k_bb_source_hash:")]
+    if not tb or not hv:
+        return None
+    h = hashlib.sha256()
+    digests = []
+    for f in ("rg_bitset.hip", "rg_count_dev.h"):
+        digests.append(hashlib.sha256(open(os.path.join(ROOT, "paper_1709_07821_amd", "csrc", f), "rb").read())
+                       .hexdigest())
+    h.update("".join(digests).encode())
+    return int(tb[0]) if h.hexdigest()[:16] == hv[0] else None
 
 
 def cpu_baseline(ia, ib, nk, n_pairs):
