@@ -169,8 +169,9 @@ rg_status roaring_batch(rg_ctx *ctx, int op, const rg_pool *A, const rg_pool *B,
  * persistent work-stealing kernel for all container pairs, count finishing -
  * with no host synchronisation and no allocation. rg_plan_capture records that
  * sequence into a hipGraph on a non-default stream; later executes replay it.
- * rg_plan_tune times the plan on its own data for several persistent grid sizes
- * and galloping ratios and keeps the fastest (results never change). The pools,
+ * rg_plan_tune times the plan on its own data and keeps the fastest setting of
+ * the thread-size threshold, the persistent grid size and the galloping ratio,
+ * one after the other (results never change). The pools,
  * pair arrays and outputs must stay valid and unmoved for the plan's life;
  * their contents may change between executions as long as every pair's
  * candidate count (number of keys of its smaller bitmap) does not. */
@@ -181,11 +182,13 @@ rg_status rg_plan_create(rg_ctx *ctx, int op, const rg_pool *A, const rg_pool *B
 rg_status rg_plan_execute(rg_plan *plan, void *stream);
 rg_status rg_plan_capture(rg_plan *plan, void *stream);
 rg_status rg_plan_tune(rg_plan *plan, void *stream, int reps);
-/* Sets the persistent grid and galloping ratio; drops a captured graph
- * (returns RG_ENOTSUP if one existed: capture again). */
-rg_status rg_plan_set(rg_plan *plan, uint32_t grid, uint32_t gallop_ratio);
-rg_status rg_plan_info(const rg_plan *plan, uint32_t *grid, uint32_t *gallop_ratio, uint64_t *slots,
-                       uint32_t *waves, int *graph);
+/* Sets the persistent grid, galloping ratio and thread-size threshold (see
+ * rg_set_thresholds); drops a captured graph (returns RG_ENOTSUP if one
+ * existed: capture again). RG_EINVAL for grid 0, ratio 0, threshold > 4096. */
+rg_status rg_plan_set(rg_plan *plan, uint32_t grid, uint32_t gallop_ratio, uint32_t thread_max);
+/* Any output pointer may be NULL. */
+rg_status rg_plan_info(const rg_plan *plan, uint32_t *grid, uint32_t *gallop_ratio, uint32_t *thread_max,
+                       uint64_t *slots, uint32_t *waves, int *graph);
 void rg_plan_destroy(rg_plan *plan);
 
 /* Kernel-variant selection for matched container pairs. Every variant
@@ -201,13 +204,21 @@ void rg_plan_destroy(rg_plan *plan);
 #define RG_V_GALLOP 4    /* array-array galloping search (Section 2.2) */
 #define RG_V_PROBE 5     /* array-bitset probe / set / clear / flip (Section 3.2) */
 #define RG_V_RUNMERGE 6  /* run-run and run-array interval merge */
+#define RG_V_THREAD 7    /* one thread per pair: array-side values looked up in the other container */
 rg_status rg_set_dispatch(rg_ctx *ctx, int mode, int variant);
+
+/* Heuristic thresholds of a context (inherited by plans made from it):
+ * galloping when max(c_A, c_B) >= gallop_ratio * min(c_A, c_B) for two arrays
+ * (the paper gives no value, Section 2.2; default 64), and one thread per pair
+ * when an array side holds at most thread_max values (default 8; 0 disables).
+ * RG_EINVAL for gallop_ratio 0 or thread_max > 4096. Results never change. */
+rg_status rg_set_thresholds(rg_ctx *ctx, uint32_t gallop_ratio, uint32_t thread_max);
 
 /* Kernel timing. When enabled, every compute-kernel launch of a call is
  * bracketed by two HIP events recorded on the call's stream; rg_profile_read
  * waits for them and returns the accumulated time, launch count and number of
  * container pairs processed for one variant (RG_V_* or 0 for the
- * bitset-bitset kernel, 1 for one-sided copies, 7 for the bitset pairs redone
+ * bitset-bitset kernel, 1 for one-sided copies, 8 for the bitset pairs redone
  * by the generic kernel) in count-only (materialize = 0) or materialising
  * form. Synchronises on the recorded events; costs two events per launch. */
 rg_status rg_profile_enable(rg_ctx *ctx, int on);

@@ -26,10 +26,10 @@ RG_AND, RG_OR, RG_XOR, RG_ANDNOT = 0, 1, 2, 3
 OPS = {"and": RG_AND, "or": RG_OR, "xor": RG_XOR, "andnot": RG_ANDNOT}
 RG_FLAG_MATERIALIZE, RG_FLAG_CARD, RG_FLAG_JACCARD = 1, 2, 4
 RG_DISPATCH_HEURISTIC, RG_DISPATCH_FIXED = 0, 2
-VARIANTS = {"generic": 2, "merge": 3, "gallop": 4, "probe": 5, "runmerge": 6}
+VARIANTS = {"generic": 2, "merge": 3, "gallop": 4, "probe": 5, "runmerge": 6, "thread": 7}
 
 # every symbol the C header declares
-EXPORTS = ["rg_create", "rg_destroy", "rg_last_error", "rg_set_dispatch", "roaring_and", "roaring_or", "roaring_xor",
+EXPORTS = ["rg_create", "rg_destroy", "rg_last_error", "rg_set_dispatch", "rg_set_thresholds", "roaring_and", "roaring_or", "roaring_xor",
            "roaring_andnot", "roaring_and_cardinality", "roaring_or_cardinality", "roaring_xor_cardinality",
            "roaring_andnot_cardinality", "roaring_jaccard", "roaring_batch", "rg_pool_measure_host",
            "rg_pool_build_host", "rg_pool_recount", "rg_pool_validate", "rg_pool_digest", "rg_profile_enable",
@@ -79,6 +79,7 @@ def lib():
         L.rg_last_error.argtypes = [V]
         L.rg_last_error.restype = ctypes.c_char_p
         L.rg_set_dispatch.argtypes = [V, I, I]
+        L.rg_set_thresholds.argtypes = [V, U32, U32]
         for nm in ("roaring_and", "roaring_or", "roaring_xor", "roaring_andnot"):
             getattr(L, nm).argtypes = [V, pool_p, U32, pool_p, U32, out_p, V]
         for nm in ("roaring_and_cardinality", "roaring_or_cardinality", "roaring_xor_cardinality",
@@ -97,8 +98,8 @@ def lib():
         L.rg_plan_execute.argtypes = [V, V]
         L.rg_plan_capture.argtypes = [V, V]
         L.rg_plan_tune.argtypes = [V, V, I]
-        L.rg_plan_set.argtypes = [V, U32, U32]
-        L.rg_plan_info.argtypes = [V, P(U32), P(U32), P(U64), P(U32), P(I)]
+        L.rg_plan_set.argtypes = [V, U32, U32, U32]
+        L.rg_plan_info.argtypes = [V, P(U32), P(U32), P(U32), P(U64), P(U32), P(I)]
         L.rg_plan_destroy.argtypes = [V]
         L.rg_plan_destroy.restype = None
         for nm in EXPORTS:
@@ -153,6 +154,9 @@ class Context:
 
     def set_dispatch(self, mode: int = RG_DISPATCH_HEURISTIC, variant: int = 2):
         self.check(lib().rg_set_dispatch(self.h, mode, variant))
+
+    def set_thresholds(self, gallop_ratio: int = 64, thread_max: int = 8):
+        self.check(lib().rg_set_thresholds(self.h, gallop_ratio, thread_max))
 
 
 class Pool:
@@ -348,17 +352,18 @@ class Plan:
     def tune(self, stream=None, reps=3):
         self.ctx.check(lib().rg_plan_tune(self.h, _stream(stream), reps))
 
-    def set(self, grid: int, gallop_ratio: int):
-        st = lib().rg_plan_set(self.h, grid, gallop_ratio)
+    def set(self, grid: int, gallop_ratio: int, thread_max: int = 8):
+        st = lib().rg_plan_set(self.h, grid, gallop_ratio, thread_max)
         if st not in (RG_OK, RG_ENOTSUP):
             self.ctx.check(st)
 
     def info(self):
-        g, r, w, gr = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_int()
+        g, r, tm, w, gr = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_int()
         s = ctypes.c_uint64()
-        self.ctx.check(lib().rg_plan_info(self.h, ctypes.byref(g), ctypes.byref(r), ctypes.byref(s), ctypes.byref(w),
-                                          ctypes.byref(gr)))
-        return {"grid": g.value, "gallop_ratio": r.value, "slots": s.value, "waves": w.value, "graph": bool(gr.value)}
+        self.ctx.check(lib().rg_plan_info(self.h, ctypes.byref(g), ctypes.byref(r), ctypes.byref(tm), ctypes.byref(s),
+                                          ctypes.byref(w), ctypes.byref(gr)))
+        return {"grid": g.value, "gallop_ratio": r.value, "thread_max": tm.value, "slots": s.value, "waves": w.value,
+                "graph": bool(gr.value)}
 
     def close(self):
         if self.h:
@@ -373,7 +378,7 @@ class Plan:
 
 
 PROFILE_CLASSES = {0: "bb", 1: "copy", 2: "generic", 3: "merge", 4: "gallop", 5: "probe", 6: "runmerge",
-                   7: "bb-redo"}
+                   7: "thread", 8: "bb-redo"}
 
 
 def profile_enable(ctx: Context, on: bool = True):

@@ -37,6 +37,7 @@ struct rg_ctx {
     int dispatch_mode = RG_DISPATCH_HEURISTIC;
     int fixed_bin = BIN_GEN;
     uint32_t gallop_ratio = 64;
+    uint32_t thread_max = 8;
     uint64_t max_wave_slots = 1ull << 24;
 };
 
@@ -315,6 +316,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
         m.dispatch_mode = c->dispatch_mode;
         m.fixed_bin = c->fixed_bin;
         m.gallop_ratio = c->gallop_ratio;
+        m.thread_max = c->thread_max;
         launch_match(m, st);
         if (mat) launch_scan_u32_u64(ub, slot_off, C, pay_base, partials, totals, st);
         HIPCHK(c, hipMemcpyAsync(h_small, bin_count, 4 * NBINS, hipMemcpyDeviceToHost, st));
@@ -355,6 +357,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
                 case BIN_GALLOP: launch_gallop(ca, st); break;
                 case BIN_AB: launch_ab(ca, st); break;
                 case BIN_RR: launch_rr(ca, st); break;
+                case BIN_THREAD: launch_thread(ca, st); break;
                 default: launch_generic(ca, st); break;
                 }
             });
@@ -494,12 +497,20 @@ rg_status rg_set_dispatch(rg_ctx* c, int mode, int variant) {
         c->dispatch_mode = mode;
         return RG_OK;
     }
-    if (mode == RG_DISPATCH_FIXED && variant >= RG_V_GENERIC && variant <= RG_V_RUNMERGE) {
+    if (mode == RG_DISPATCH_FIXED && variant >= RG_V_GENERIC && variant <= RG_V_THREAD) {
         c->dispatch_mode = mode;
         c->fixed_bin = variant;
         return RG_OK;
     }
     return fail(c, RG_EINVAL, "unknown dispatch mode or variant");
+}
+
+rg_status rg_set_thresholds(rg_ctx* c, uint32_t gallop_ratio, uint32_t thread_max) {
+    if (!c) return RG_EINVAL;
+    if (gallop_ratio == 0 || thread_max > 4096) return fail(c, RG_EINVAL, "gallop_ratio >= 1, thread_max <= 4096");
+    c->gallop_ratio = gallop_ratio;
+    c->thread_max = thread_max;
+    return RG_OK;
 }
 
 rg_status roaring_and(rg_ctx* c, const rg_pool* A, uint32_t ia, const rg_pool* B, uint32_t ib, rg_out* out,
@@ -622,6 +633,7 @@ struct rg_plan {
     int dispatch_mode = RG_DISPATCH_HEURISTIC;
     int fixed_bin = BIN_GEN;
     uint32_t gallop_ratio = 64;
+    uint32_t thread_max = 8;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -658,6 +670,7 @@ void plan_enqueue(rg_plan* p, hipStream_t st) {
         m.dispatch_mode = p->dispatch_mode;
         m.fixed_bin = p->fixed_bin;
         m.gallop_ratio = p->gallop_ratio;
+        m.thread_max = p->thread_max;
         launch_match(m, st);
         launch_bin_info(p->bin_count, p->bin_info, p->cursor, p->next, st);
         launch_bin_scatter(p->tasks, w.C, p->cursor, p->lists, st);
@@ -710,6 +723,7 @@ rg_status rg_plan_create(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, 
     p->dispatch_mode = c->dispatch_mode;
     p->fixed_bin = c->fixed_bin;
     p->gallop_ratio = c->gallop_ratio;
+    p->thread_max = c->thread_max;
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
     p->grid = (uint32_t)cus * 8;
@@ -832,50 +846,60 @@ rg_status rg_plan_tune(rg_plan* p, void* stream, int reps) {
     if (reps < 1) reps = 3;
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
-    const uint32_t grids[] = {(uint32_t)cus * 2, (uint32_t)cus * 4, (uint32_t)cus * 8, (uint32_t)cus * 12,
-                              (uint32_t)cus * 16};
-    const uint32_t ratios[] = {8, 32, 128, 512};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    float best = 1e30f;
-    uint32_t bg = p->grid, br = p->gallop_ratio;
-    for (uint32_t g : grids) {
-        for (uint32_t r : ratios) {
-            if (p->dispatch_mode != RG_DISPATCH_HEURISTIC && r != ratios[0]) continue;
-            p->grid = g;
-            p->gallop_ratio = r;
-            plan_enqueue(p, st);  // warm-up
-            float tot = 0;
-            for (int i = 0; i < reps; ++i) {
-                (void)hipEventRecord(e0, st);
-                plan_enqueue(p, st);
-                (void)hipEventRecord(e1, st);
-                HIPCHK(c, hipEventSynchronize(e1));
-                float ms = 0;
-                HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-                tot += ms;
-            }
-            if (tot < best) {
-                best = tot;
-                bg = g;
-                br = r;
+    auto measure = [&](float* ms_out) -> rg_status {
+        plan_enqueue(p, st);  // warm-up
+        float tot = 0;
+        for (int i = 0; i < reps; ++i) {
+            (void)hipEventRecord(e0, st);
+            plan_enqueue(p, st);
+            (void)hipEventRecord(e1, st);
+            HIPCHK(c, hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+            tot += ms;
+        }
+        *ms_out = tot;
+        return RG_OK;
+    };
+    // coordinate descent: thread-size threshold, then grid, then galloping ratio
+    const bool heur = p->dispatch_mode == RG_DISPATCH_HEURISTIC;
+    std::vector<uint32_t> tvals = heur ? std::vector<uint32_t>{0, 4, 16, 64} : std::vector<uint32_t>{};
+    std::vector<uint32_t> gvals;
+    for (uint32_t f : {2u, 4u, 8u, 12u, 16u}) gvals.push_back((uint32_t)cus * f);
+    std::vector<uint32_t> rvals = heur ? std::vector<uint32_t>{8, 32, 128, 512} : std::vector<uint32_t>{};
+    uint32_t* knobs[3] = {&p->thread_max, &p->grid, &p->gallop_ratio};
+    const std::vector<uint32_t>* vals[3] = {&tvals, &gvals, &rvals};
+    rg_status s = RG_OK;
+    for (int k = 0; k < 3 && s == RG_OK; ++k) {
+        float best = 1e30f;
+        uint32_t bv = *knobs[k];
+        for (uint32_t v : *vals[k]) {
+            *knobs[k] = v;
+            float ms = 0;
+            if ((s = measure(&ms)) != RG_OK) break;
+            if (ms < best) {
+                best = ms;
+                bv = v;
             }
         }
+        *knobs[k] = bv;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    p->grid = bg;
-    p->gallop_ratio = br;
+    if (s != RG_OK) return s;
     if (had_graph) return rg_plan_capture(p, stream);
     return RG_OK;
 }
 
-rg_status rg_plan_info(const rg_plan* p, uint32_t* grid, uint32_t* gallop_ratio, uint64_t* slots, uint32_t* waves,
-                       int* graph) {
+rg_status rg_plan_info(const rg_plan* p, uint32_t* grid, uint32_t* gallop_ratio, uint32_t* thread_max, uint64_t* slots,
+                       uint32_t* waves, int* graph) {
     if (!p) return RG_EINVAL;
     if (grid) *grid = p->grid;
     if (gallop_ratio) *gallop_ratio = p->gallop_ratio;
+    if (thread_max) *thread_max = p->thread_max;
     if (slots) {
         uint64_t s = 0;
         for (const auto& w : p->waves) s += w.C;
@@ -886,12 +910,13 @@ rg_status rg_plan_info(const rg_plan* p, uint32_t* grid, uint32_t* gallop_ratio,
     return RG_OK;
 }
 
-rg_status rg_plan_set(rg_plan* p, uint32_t grid, uint32_t gallop_ratio) {
-    if (!p || grid == 0 || gallop_ratio == 0) return RG_EINVAL;
+rg_status rg_plan_set(rg_plan* p, uint32_t grid, uint32_t gallop_ratio, uint32_t thread_max) {
+    if (!p || grid == 0 || gallop_ratio == 0 || thread_max > 4096) return RG_EINVAL;
     const bool had_graph = p->exec != nullptr;
     plan_drop_graph(p);
     p->grid = grid;
     p->gallop_ratio = gallop_ratio;
+    p->thread_max = thread_max;
     return had_graph ? RG_ENOTSUP : RG_OK;  // caller re-captures explicitly
 }
 

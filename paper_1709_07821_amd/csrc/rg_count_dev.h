@@ -155,6 +155,65 @@ __device__ __forceinline__ uint32_t wave_inter(const PoolView& PA, const PoolVie
     return wave_sum_u32(inter);
 }
 
+// |A n B| of one pair by one thread: every value of the smaller array side is
+// looked up in the other container (bit test, binary search in an array or
+// in the run starts). For small array sides only. Per-lane values throughout.
+__device__ __forceinline__ uint32_t thread_inter(const PoolView& PA, const PoolView& PB, const Task& t) {
+    uint8_t ta = PA.types[t.ia], tb = PB.types[t.ib];
+    uint32_t sa = PA.size[t.ia], sb = PB.size[t.ib];
+    const uint8_t* pa = PA.payload + PA.off[t.ia];
+    const uint8_t* pb = PB.payload + PB.off[t.ib];
+    // s: the array side (the smaller one when both are arrays); l: the other
+    const bool a_is_s = ta == RG_ARRAY && (tb != RG_ARRAY || sa <= sb);
+    const uint16_t* sv = reinterpret_cast<const uint16_t*>(a_is_s ? pa : pb);
+    const uint32_t n = a_is_s ? sa : sb;
+    const uint8_t lt = a_is_s ? tb : ta;
+    const uint32_t ln = a_is_s ? sb : sa;
+    const uint8_t* lp = a_is_s ? pb : pa;
+    uint32_t hits = 0;
+    if (lt == RG_BITSET) {
+        const uint64_t* w = reinterpret_cast<const uint64_t*>(lp);
+        for (uint32_t i = 0; i < n; ++i) {
+            const uint32_t x = sv[i];
+            hits += (uint32_t)(w[x >> 6] >> (x & 63)) & 1u;
+        }
+    } else if (lt == RG_ARRAY) {
+        const uint16_t* lv = reinterpret_cast<const uint16_t*>(lp);
+        uint32_t lo = 0;  // values of s are increasing: each search starts where the last ended
+        for (uint32_t i = 0; i < n; ++i) {
+            const uint32_t x = sv[i];
+            uint32_t hi = ln;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (lv[mid] < x) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < ln && lv[lo] == x) ++hits;
+        }
+    } else {
+        const uint32_t* lr = reinterpret_cast<const uint32_t*>(lp);
+        for (uint32_t i = 0; i < n; ++i) hits += in_runs(lr, ln, sv[i]) ? 1u : 0u;
+    }
+    return hits;
+}
+
+// Adds each lane's value v to acc[pair] (lanes with pair == NONE add nothing)
+// with one atomic per distinct pair in the wave: neighbouring items mostly
+// belong to the same pair. Call with the whole wave active.
+__device__ __forceinline__ void wave_aggregate_add(long long* acc, uint32_t pair, uint32_t v) {
+    const uint32_t lane = lane_id();
+    uint64_t pending = __ballot(pair != NONE);
+    while (pending) {
+        const uint32_t leader = (uint32_t)__builtin_ctzll(pending);
+        const uint32_t p = __builtin_amdgcn_readlane(pair, leader);
+        const bool mine = pair == p;
+        const uint64_t m = __ballot(mine);
+        const uint32_t s = wave_sum_u32(mine ? v : 0u);
+        if (lane == leader && s) atomicAdd(reinterpret_cast<unsigned long long*>(&acc[p]), (unsigned long long)s);
+        pending &= ~m;
+    }
+}
+
 // |A n B| of two array containers by a 256-thread workgroup: both arrays staged
 // in LDS, merge path split of the merged sequence over the threads; a B value
 // equal to the A value merged just before it is a match. Contains barriers.

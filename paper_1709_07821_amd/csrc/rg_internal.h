@@ -28,7 +28,8 @@ enum : uint8_t {
     BIN_GALLOP = 4, // array op array, very unequal sizes: galloping search
     BIN_AB = 5,     // array op bitset (either order): probe / set / clear / flip
     BIN_RR = 6,     // run op run / run op array: interval merge
-    NBINS = 8
+    BIN_THREAD = 7, // small array side: one thread per pair probes the other container
+    NBINS = 9       // bin NBINS - 1 only names the profile class of redone bitset pairs
 };
 
 struct Task {
@@ -197,6 +198,7 @@ struct MatchArgs {
     int dispatch_mode;        // 0 heuristic, 2 fixed
     int fixed_bin;
     uint32_t gallop_ratio;
+    uint32_t thread_max;  // largest array side handled one thread per pair
 };
 
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st);
@@ -232,6 +234,7 @@ void launch_aa(const ComputeArgs& a, hipStream_t st);
 void launch_gallop(const ComputeArgs& a, hipStream_t st);
 void launch_ab(const ComputeArgs& a, hipStream_t st);
 void launch_rr(const ComputeArgs& a, hipStream_t st);
+void launch_thread(const ComputeArgs& a, hipStream_t st);
 
 struct CompactArgs {
     const Task* tasks;

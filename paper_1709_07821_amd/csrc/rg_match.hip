@@ -129,18 +129,22 @@ __device__ __forceinline__ bool variant_applies(int bin, uint8_t ta, uint8_t tb)
     case BIN_GALLOP: return aa;
     case BIN_AB: return ab;
     case BIN_RR: return run;
+    case BIN_THREAD: return ta == RG_ARRAY || tb == RG_ARRAY;
     default: return false;
     }
 }
 
 __device__ __forceinline__ uint8_t classify(int op, bool materialize, uint8_t kind, uint8_t ta, uint8_t tb,
                                             uint32_t ca, uint32_t cb, int mode, int fixed_bin,
-                                            uint32_t gallop_ratio) {
+                                            uint32_t gallop_ratio, uint32_t thread_max) {
     if (kind == KIND_COPY_A || kind == KIND_COPY_B) return BIN_COPY;
     if (ta == RG_BITSET && tb == RG_BITSET) return BIN_BB;
     if (materialize) return BIN_GEN;  // specialised variants are count-only
     if (mode == 2) return variant_applies(fixed_bin, ta, tb) ? (uint8_t)fixed_bin : (uint8_t)BIN_GEN;
-    // heuristic: galloping when one array is much smaller (Section 2.2)
+    // heuristic: a small array side is probed by one thread (each value
+    // looked up in the other container); galloping when one array is much
+    // smaller than the other (Section 2.2)
+    if ((ta == RG_ARRAY && ca <= thread_max) || (tb == RG_ARRAY && cb <= thread_max)) return BIN_THREAD;
     if (ta == RG_ARRAY && tb == RG_ARRAY) {
         uint32_t mx = ca > cb ? ca : cb, mn = ca < cb ? ca : cb;
         return (uint64_t)mx >= (uint64_t)gallop_ratio * mn ? BIN_GALLOP : BIN_AA;
@@ -229,7 +233,7 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
                 uint32_t ca = task.ia != NONE ? m.A.card[task.ia] : 0;
                 uint32_t cb = task.ib != NONE ? m.B.card[task.ib] : 0;
                 task.bin = classify(m.op, m.materialize, task.kind, ta, tb, ca, cb, m.dispatch_mode, m.fixed_bin,
-                                    m.gallop_ratio);
+                                    m.gallop_ratio, m.thread_max);
                 atomicAdd(&cnt[task.bin], 1u);
                 if (m.materialize) {
                     uint64_t bc;

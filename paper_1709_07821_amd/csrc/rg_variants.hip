@@ -12,6 +12,10 @@
 //                 per pair: O(min log max), the galloping regime of Section 2.2.
 //   RG_V_PROBE    array-bitset (either order): one bit test per array value
 //                 (Section 3.2 bit addressing), one wave per pair.
+//   RG_V_THREAD   any pair with an array side: one thread per pair looks every
+//                 value of the (smaller) array up in the other container;
+//                 chosen for small array sides, where a wave or a workgroup
+//                 per pair would idle. Wave-aggregated atomics per pair.
 //   RG_V_RUNMERGE run-run: interval intersection, each run of the side with
 //                 fewer runs searches the other run list; run-array: each array
 //                 value searches the run list; run-bitset: population count of
@@ -44,6 +48,18 @@ __global__ void __launch_bounds__(256) k_merge_count(ComputeArgs a) {
     }
 }
 
+// One thread per pair.
+__global__ void __launch_bounds__(256) k_thread_count(ComputeArgs a) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    uint32_t pair = NONE, inter = 0;
+    if (i < a.n) {
+        const Task t = a.tasks[a.list[i]];
+        inter = thread_inter(a.A, a.B, t);
+        pair = t.pair;
+    }
+    wave_aggregate_add(a.acc, pair, inter);
+}
+
 static void launch_wave_count(const ComputeArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_wave_count, dim3((a.n + 3) / 4), dim3(256), 0, st, a);
 }
@@ -69,6 +85,11 @@ void launch_ab(const ComputeArgs& a, hipStream_t st) {
     if (!a.n) return;
     if (a.materialize) launch_generic(a, st);
     else launch_wave_count(a, st);
+}
+void launch_thread(const ComputeArgs& a, hipStream_t st) {
+    if (!a.n) return;
+    if (a.materialize) launch_generic(a, st);
+    else hipLaunchKernelGGL(k_thread_count, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
 }
 void launch_rr(const ComputeArgs& a, hipStream_t st) {
     if (!a.n) return;

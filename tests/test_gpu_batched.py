@@ -132,12 +132,12 @@ def test_plan_tune_keeps_results(rg, ctx):
     torch.cuda.synchronize()
     assert np.array_equal(pl.cards.cpu().numpy().view(np.uint64), card)
     assert np.array_equal(pl.jacc.cpu().numpy(), jac)
-    for g, r in [(256, 8), (4096, 1000)]:
-        pl.set(g, r)
+    for g, r, tm in [(256, 8, 0), (4096, 1000, 64), (512, 32, 4096)]:
+        pl.set(g, r, tm)
         pl.cards.zero_()
         pl.execute()
         torch.cuda.synchronize()
-        assert np.array_equal(pl.cards.cpu().numpy().view(np.uint64), card), (g, r)
+        assert np.array_equal(pl.cards.cpu().numpy().view(np.uint64), card), (g, r, tm)
     pl.close()
 
 

@@ -106,7 +106,7 @@ def test_mixed_small_consecutive(rg, ctx):
     check_batch(rg, ctx, bs, ia, ib, label="mixed")
 
 
-@pytest.mark.parametrize("variant", ["generic", "merge", "gallop", "probe", "runmerge"])
+@pytest.mark.parametrize("variant", ["generic", "merge", "gallop", "probe", "runmerge", "thread"])
 def test_forced_variants_same_result(rg, ctx, variant):
     bs = synth.mixed_small(n_bitmaps=30)
     ia, ib = synth.consecutive_pairs(len(bs))
