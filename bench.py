@@ -43,8 +43,12 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=24, help="pairs in the oracle timing sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", type=int, default=2, help="pairs checked against the oracle before timing")
-    ap.add_argument("--workload", choices=("dense", "batched"), default="dense",
-                    help="dense: the bitset-bandwidth headline; batched: many uneven pairs, plan vs per-pair")
+    ap.add_argument("--workload", choices=("dense", "batched", "serve"), default="dense",
+                    help="dense: the bitset-bandwidth headline; batched: many uneven pairs, plan vs per-pair; "
+                         "serve: k-way queries under Poisson arrivals, batched server vs one query at a time")
+    ap.add_argument("--index", type=int, default=4000, help="serve: bitmaps in the index")
+    ap.add_argument("--rates", default="2000,5000,10000,20000,50000", help="serve: arrival rates (queries/s)")
+    ap.add_argument("--duration", type=float, default=2.0, help="serve: seconds of arrivals per rate")
     ap.add_argument("--pool", type=int, default=1024, help="batched: bitmaps in the pool")
     ap.add_argument("--batched-pairs", type=int, default=100000, help="batched: random pairs per step")
     ap.add_argument("--per-pair-sample", type=int, default=500, help="batched: pairs timed one call each")
@@ -74,6 +78,8 @@ def main():
         return None
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     dev = torch.device("cuda:0")
     ctx = rg.Context(0)
     stream = torch.cuda.current_stream()
@@ -278,6 +284,94 @@ def bench_batched(args):
         "per_pair_ms_extrapolated": round(pp_s * 1e3, 3),
         "speedup_plan_vs_per_pair": round(pp_s / plan_s, 2),
         "speedup_plan_vs_eager": round(eager_s / plan_s, 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_serve(args):
+    """k-way AND/OR queries over a device-resident index under open-loop Poisson
+    arrivals. Index: mixed bitmaps over [0, 2^26) (40/30/30 sparse/dense/run,
+    32-key hot set), cardinality lognormal (median 5e4, sigma 1, clipped to
+    [1e3, 1e6]). Mix: 40 % k-AND, 40 % k-OR (both materialised), 20 %
+    count-only (half AND, half OR); k uniform in 2..32; ids uniform without
+    replacement. Each rate runs twice: the continuous-batching server (up to 64
+    queries per step, two steps in flight) and one query at a time."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1709_07821_amd as rg
+    import synth
+
+    ctx = rg.Context(0)
+    seed = synth.SEED_BASE + 4
+    t0 = time.time()
+    hot = synth.hot_keys(seed, 32, 1 << 10)
+    cards = [synth.lognormal_card(i, 5e4, 1.0, 1000, 10 ** 6, seed) for i in range(args.index)]
+    bs = synth.BitmapSet.from_list([synth.mixed_bitmap(seed, i, cards[i], 26, hot) for i in range(args.index)])
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    torch.cuda.synchronize()
+    print(f"# index of {args.index} bitmaps, {len(bs.values)} values, {P.c.n_containers} containers, "
+          f"built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    rng = np.random.default_rng(seed)
+
+    def make_queries(n):
+        qs = []
+        for _ in range(n):
+            u = rng.random()
+            k = int(rng.integers(2, 33))
+            ids = rng.choice(args.index, size=k, replace=False).astype(np.uint32)
+            if u < 0.4:
+                qs.append(("and", ids, True))
+            elif u < 0.8:
+                qs.append(("or", ids, True))
+            else:
+                qs.append(("and" if u < 0.9 else "or", ids, False))
+        return qs
+
+    # correctness gate: a sample against the oracle
+    sample = make_queries(12)
+    srv = rg.Server(ctx, P, arena_bytes=4 << 30, max_batch=64, max_inflight=2)
+    _, c_s, d_s = srv.replay(sample, np.zeros(len(sample), np.uint64))
+    srv.stop()
+    for i, (op, ids, mat) in enumerate(sample):
+        e = oracle.kway(op, [bs[int(j)] for j in ids])
+        assert c_s[i] == len(e) and d_s[i] == (oracle.digest(e) if mat else 0), i
+    print("# 12 sampled queries match the oracle", file=sys.stderr, flush=True)
+
+    rows = []
+    for lam in [float(x) for x in args.rates.split(",")]:
+        n = max(1, int(lam * args.duration))
+        qs = make_queries(n)
+        gaps = rng.exponential(1.0 / lam, n)
+        arrival = (np.cumsum(gaps) * 1e9).astype(np.uint64)
+        row = {"rate_qps": lam, "queries": n}
+        for mode, mb, mi in (("batched", 64, 2), ("one_at_a_time", 1, 1)):
+            srv = rg.Server(ctx, P, arena_bytes=4 << 30, max_batch=mb, max_inflight=mi)
+            t = time.perf_counter()
+            lat, c, d = srv.replay(qs, arrival)
+            wall = time.perf_counter() - t
+            st = srv.stop()
+            if mode == "batched":
+                ref = (c, d)
+            else:
+                assert np.array_equal(c, ref[0]) and np.array_equal(d, ref[1]), "results differ between modes"
+            row[mode] = {"achieved_qps": round(n / wall, 1), "p50_us": round(float(np.percentile(lat, 50)) / 1e3, 1),
+                         "p99_us": round(float(np.percentile(lat, 99)) / 1e3, 1),
+                         "mean_batch": round(st["mean_batch"], 2), "steps": st["steps"]}
+            print(f"# rate {lam:.0f}/s {mode}: {row[mode]}", file=sys.stderr, flush=True)
+        rows.append(row)
+    best = max(r["batched"]["achieved_qps"] for r in rows)
+    line = {
+        "metric": "queries/sec and p50/p99 latency, k-way AND/OR serving (continuous batching)",
+        "value": best, "unit": "queries/s", "n_gpus": 1, "steps": len(rows), "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"serving: index of {args.index} mixed bitmaps over [0, 2^26) (lognormal card, median "
+                               f"5e4, sigma 1), Poisson arrivals, 40% k-AND / 40% k-OR materialised, 20% "
+                               f"count-only, k in 2..32", "index": args.index, "duration_s": args.duration,
+                   "parallelism": "single GPU"},
+        "rates": rows,
     }
     print(json.dumps(line), flush=True)
 

@@ -78,7 +78,9 @@ typedef struct rg_pool {
     uint32_t n_bitmaps;
     uint64_t n_containers;     /* < 2^32 */
     uint64_t payload_bytes;    /* multiple of 16 */
-    const uint64_t *bm_begin;  /* [n_bitmaps + 1], bm_begin[n_bitmaps] == n_containers */
+    const uint64_t *bm_begin;  /* [n_bitmaps + 1], bm_begin[n_bitmaps] == n_containers; bm_begin[0] is 0
+                                  except for a window into larger arrays (rg_result.view), where the
+                                  containers before it belong to no bitmap of the view */
     const uint16_t *keys;      /* [n_containers], ascending within a bitmap */
     const uint8_t *types;      /* [n_containers], rg_ctype */
     const uint32_t *card;      /* [n_containers], 1..65536 */
@@ -225,6 +227,79 @@ rg_status rg_profile_enable(rg_ctx *ctx, int on);
 rg_status rg_profile_reset(rg_ctx *ctx);
 rg_status rg_profile_read(rg_ctx *ctx, int variant, int materialize, double *total_ms, uint64_t *launches,
                           uint64_t *items);
+
+/* ---- k-way queries and the serving loop ---------------------------------
+ * roaring_multi: the intersection (op RG_AND) or union (RG_OR) of k bitmaps
+ * of one pool, d_ids[0..k) (device uint32, 1 <= k <= 256, ids may repeat).
+ * The paper builds wide unions and intersections by folding pairwise or by
+ * lazy aggregation (Section 2.2, Section 5.9); here each result container is
+ * built directly from the k input containers of its key. flags:
+ * RG_FLAG_MATERIALIZE (result bitmap 0 of `out`, which needs bm_wbytes) and/or
+ * RG_FLAG_CARD (cardinality into d_card[0], device uint64). Output sizing as
+ * for the pairwise calls (RG_ECAPACITY with needed_*): at most min_i K_i (AND)
+ * or min(65536, sum_i K_i) (OR) containers and min_i / sum_i bm_wbytes bytes.
+ * Synchronises on `stream` (one small readback of the ids' key counts). */
+rg_status roaring_multi(rg_ctx *ctx, int op, const rg_pool *pool, const uint32_t *d_ids, uint32_t k, uint32_t flags,
+                        rg_out *out, uint64_t *d_card, void *stream);
+
+/* A query of the serving loop: op RG_AND / RG_OR over k bitmap ids (host
+ * array, copied at submission) of the server's pool; flags RG_FLAG_CARD
+ * (count only) or RG_FLAG_MATERIALIZE (the result containers are built and
+ * stay readable through rg_result.view until the query is released). */
+typedef struct rg_query {
+    int op;
+    uint32_t k;
+    const uint32_t *ids;
+    uint32_t flags;
+} rg_query;
+
+typedef struct rg_result {
+    int done;              /* 0: not finished yet (the other fields are unset) */
+    int status;            /* RG_OK, or the failure of the step that ran it */
+    uint64_t card;         /* |result| */
+    uint64_t digest;       /* fingerprint of the result's container form (0 for count-only) */
+    uint64_t n_containers;
+    uint64_t latency_ns;   /* arrival (or submission) to result-ready */
+    rg_pool view;          /* materialised result as a one-bitmap window into the
+                              server's arena (bm_begin[0..1] are absolute container
+                              indices); valid until rg_serve_release */
+} rg_result;
+
+typedef struct rg_serve_stats {
+    uint64_t queries;      /* finished */
+    uint64_t steps;        /* device steps run */
+    double mean_batch;     /* queries per step */
+    uint64_t arena_peak_bytes;
+    uint64_t deferred;     /* times the queue head waited for arena memory */
+} rg_serve_stats;
+
+typedef struct rg_server rg_server;
+
+/* Starts a server thread over a device-resident pool. Queries are admitted in
+ * arrival order into device steps of at most max_batch queries (1..4096) whose
+ * result bound fits the arena (arena_bytes of device memory, allocated here):
+ * queries arriving while steps run join the next step, and up to max_inflight
+ * (1 or 2) steps are on the GPU at once, on two streams. max_batch = 1 and
+ * max_inflight = 1 serve one query at a time. The pool must stay valid and
+ * unchanged while the server runs. */
+rg_status rg_serve_start(rg_ctx *ctx, const rg_pool *pool, uint64_t arena_bytes, uint32_t max_batch,
+                         uint32_t max_inflight, rg_server **server);
+/* Non-blocking. arrival_ns: the query's arrival time on the steady clock in
+ * ns (latency is measured from it), or 0 for "now". RG_EINVAL for a bad query,
+ * RG_ECAPACITY if its result bound alone exceeds the arena. Thread-safe. */
+rg_status rg_serve_submit(rg_server *server, const rg_query *query, uint64_t arrival_ns, uint64_t *ticket);
+/* wait = 0: returns at once (result->done says whether it finished);
+ * wait = 1: blocks until it has. Thread-safe. */
+rg_status rg_serve_poll(rg_server *server, uint64_t ticket, int wait, rg_result *result);
+/* Frees a finished query's result memory and its ticket. */
+rg_status rg_serve_release(rg_server *server, uint64_t ticket);
+/* Open-loop replay: submits qs[i] at arrival_ns[i] (ns after the call starts,
+ * non-decreasing), waits for all, and returns each query's latency, card and
+ * digest (any output array may be NULL). Results are released as they finish. */
+rg_status rg_serve_replay(rg_server *server, uint64_t n, const rg_query *qs, const uint64_t *arrival_ns,
+                          uint64_t *latency_ns, uint64_t *cards, uint64_t *digests);
+/* Drains, stops the thread, frees everything; stats may be NULL. */
+rg_status rg_serve_stop(rg_server *server, rg_serve_stats *stats);
 
 /* ---- pools -------------------------------------------------------------- */
 

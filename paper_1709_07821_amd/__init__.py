@@ -13,6 +13,7 @@ binding's entry points raises.
 from __future__ import annotations
 
 import ctypes
+import weakref
 import os
 
 import numpy as np
@@ -34,7 +35,8 @@ EXPORTS = ["rg_create", "rg_destroy", "rg_last_error", "rg_set_dispatch", "rg_se
            "roaring_andnot_cardinality", "roaring_jaccard", "roaring_batch", "rg_pool_measure_host",
            "rg_pool_build_host", "rg_pool_recount", "rg_pool_validate", "rg_pool_digest", "rg_profile_enable",
            "rg_profile_reset", "rg_profile_read", "rg_plan_create", "rg_plan_execute", "rg_plan_capture",
-           "rg_plan_tune", "rg_plan_set", "rg_plan_info", "rg_plan_destroy"]
+           "rg_plan_tune", "rg_plan_set", "rg_plan_info", "rg_plan_destroy", "roaring_multi", "rg_serve_start",
+           "rg_serve_submit", "rg_serve_poll", "rg_serve_release", "rg_serve_replay", "rg_serve_stop"]
 
 
 class RoaringError(RuntimeError):
@@ -58,6 +60,22 @@ class rg_out(ctypes.Structure):
                 ("payload", ctypes.c_void_p), ("bm_card", ctypes.c_void_p), ("bm_wbytes", ctypes.c_void_p),
                 ("needed_containers", ctypes.c_uint64), ("needed_payload_bytes", ctypes.c_uint64),
                 ("n_containers", ctypes.c_uint64), ("payload_used", ctypes.c_uint64)]
+
+
+class rg_query(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int), ("k", ctypes.c_uint32), ("ids", ctypes.POINTER(ctypes.c_uint32)),
+                ("flags", ctypes.c_uint32)]
+
+
+class rg_result(ctypes.Structure):
+    _fields_ = [("done", ctypes.c_int), ("status", ctypes.c_int), ("card", ctypes.c_uint64),
+                ("digest", ctypes.c_uint64), ("n_containers", ctypes.c_uint64), ("latency_ns", ctypes.c_uint64),
+                ("view", rg_pool)]
+
+
+class rg_serve_stats(ctypes.Structure):
+    _fields_ = [("queries", ctypes.c_uint64), ("steps", ctypes.c_uint64), ("mean_batch", ctypes.c_double),
+                ("arena_peak_bytes", ctypes.c_uint64), ("deferred", ctypes.c_uint64)]
 
 
 _lib = None
@@ -102,6 +120,13 @@ def lib():
         L.rg_plan_info.argtypes = [V, P(U32), P(U32), P(U32), P(U64), P(U32), P(I)]
         L.rg_plan_destroy.argtypes = [V]
         L.rg_plan_destroy.restype = None
+        L.roaring_multi.argtypes = [V, I, pool_p, V, U32, U32, out_p, V, V]
+        L.rg_serve_start.argtypes = [V, pool_p, U64, U32, U32, P(V)]
+        L.rg_serve_submit.argtypes = [V, P(rg_query), U64, P(U64)]
+        L.rg_serve_poll.argtypes = [V, U64, I, P(rg_result)]
+        L.rg_serve_release.argtypes = [V, U64]
+        L.rg_serve_replay.argtypes = [V, U64, P(rg_query), V, V, V, V]
+        L.rg_serve_stop.argtypes = [V, P(rg_serve_stats)]
         for nm in EXPORTS:
             if nm not in ("rg_destroy", "rg_last_error", "rg_plan_destroy"):
                 getattr(L, nm).restype = ctypes.c_int
@@ -135,8 +160,14 @@ class Context:
             raise RoaringError(st, f"rg_create failed on device {device}")
         self.h = h
         self.device = device
+        self.servers = weakref.WeakSet()  # stopped before the context goes away
 
     def close(self):
+        for srv in list(getattr(self, "servers", ())):
+            try:
+                srv.stop()
+            except Exception:
+                pass
         if self.h:
             lib().rg_destroy(self.h)
             self.h = None
@@ -176,6 +207,15 @@ class Pool:
     @property
     def c(self):
         return self._c
+
+    @staticmethod
+    def from_view(view: "rg_pool") -> "Pool":
+        """A Pool over device memory someone else owns (e.g. a server result view)."""
+        p = Pool.__new__(Pool)
+        p.n_bitmaps, p.n_containers, p.payload_bytes = view.n_bitmaps, view.n_containers, view.payload_bytes
+        p.bm_begin = p.keys = p.types = p.card = p.size = p.off = p.payload = p.bm_card = p.bm_wbytes = None
+        p._c = view
+        return p
 
     @staticmethod
     def host_arrays(values, offsets):
@@ -320,7 +360,8 @@ def rg_pool_validate(ctx: Context, pool: Pool, stream=None) -> int:
 
 def rg_pool_digest(ctx: Context, pool: Pool, stream=None):
     torch = _torch()
-    d = torch.zeros(max(pool.n_bitmaps, 1), dtype=torch.int64, device=pool.bm_begin.device)
+    dev = pool.bm_begin.device if pool.bm_begin is not None else torch.device("cuda", ctx.device)
+    d = torch.zeros(max(pool.n_bitmaps, 1), dtype=torch.int64, device=dev)
     ctx.check(lib().rg_pool_digest(ctx.h, ctypes.byref(pool.c), _ptr(d), _stream(stream)))
     return d[:pool.n_bitmaps]
 
@@ -428,3 +469,107 @@ def batch(ctx: Context, op, A: Pool, B: Pool, ia, ib, materialize=True, card=Fal
     if not done:
         ctx.check(roaring_batch(ctx, op, A, B, ia, ib, flags, out, cards, jacc, stream))
     return out, (cards[:n] if card else None), (jacc[:n] if jaccard else None)
+
+
+# ---------------------------------------------------------------- k-way and serving
+
+def roaring_multi(ctx: Context, op, pool: Pool, d_ids, flags: int, out: OutArena | None = None, d_card=None,
+                  stream=None) -> int:
+    op = OPS[op] if isinstance(op, str) else op
+    return lib().roaring_multi(ctx.h, op, ctypes.byref(pool.c), _ptr(d_ids), int(d_ids.numel()), flags,
+                               ctypes.byref(out.c) if out is not None else None, _ptr(d_card), _stream(stream))
+
+
+def multi(ctx: Context, op, pool: Pool, d_ids, materialize=True, card=True, stream=None):
+    """roaring_multi with arena sizing: returns (out_arena or None, card tensor or None)."""
+    torch = _torch()
+    dev = pool.bm_begin.device
+    flags = (RG_FLAG_MATERIALIZE if materialize else 0) | (RG_FLAG_CARD if card else 0)
+    d_card = torch.zeros(1, dtype=torch.int64, device=dev) if card else None
+    out = None
+    if materialize:
+        out = OutArena(1, 0, 0, dev)
+        out.c.cap_containers = 0
+        out.c.cap_payload_bytes = 0
+        st = roaring_multi(ctx, op, pool, d_ids, flags, out, d_card, stream)
+        if st == RG_ECAPACITY:
+            out = OutArena(1, out.c.needed_containers, out.c.needed_payload_bytes, dev)
+            ctx.check(roaring_multi(ctx, op, pool, d_ids, flags, out, d_card, stream))
+        else:
+            ctx.check(st)
+    else:
+        ctx.check(roaring_multi(ctx, op, pool, d_ids, flags, None, d_card, stream))
+    return out, d_card
+
+
+class Server:
+    """rg_serve_*: continuous-batching k-way query server over a device pool."""
+
+    def __init__(self, ctx: Context, pool: Pool, arena_bytes: int = 1 << 30, max_batch: int = 64,
+                 max_inflight: int = 2):
+        self.ctx, self.pool = ctx, pool
+        h = ctypes.c_void_p()
+        ctx.check(lib().rg_serve_start(ctx.h, ctypes.byref(pool.c), arena_bytes, max_batch, max_inflight,
+                                       ctypes.byref(h)))
+        self.h = h
+        ctx.servers.add(self)
+
+    @staticmethod
+    def _query(op, ids, materialize):
+        import numpy as np
+
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        q = rg_query(OPS[op] if isinstance(op, str) else op, len(ids),
+                     ids.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                     RG_FLAG_MATERIALIZE if materialize else RG_FLAG_CARD)
+        return q, ids
+
+    def submit(self, op, ids, materialize=False) -> int:
+        q, keep = self._query(op, ids, materialize)
+        t = ctypes.c_uint64()
+        self.ctx.check(lib().rg_serve_submit(self.h, ctypes.byref(q), 0, ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = True) -> rg_result:
+        r = rg_result()
+        self.ctx.check(lib().rg_serve_poll(self.h, ticket, 1 if wait else 0, ctypes.byref(r)))
+        return r
+
+    def release(self, ticket: int):
+        self.ctx.check(lib().rg_serve_release(self.h, ticket))
+
+    def replay(self, queries, arrival_ns):
+        """queries: list of (op, ids, materialize); arrival_ns: offsets from the start.
+        Returns (latency_ns, cards, digests) as numpy uint64 arrays."""
+        import numpy as np
+
+        n = len(queries)
+        arr = (rg_query * max(n, 1))()
+        keep = []
+        for i, (op, ids, mat) in enumerate(queries):
+            q, k = self._query(op, ids, mat)
+            arr[i] = q
+            keep.append(k)
+        at = np.ascontiguousarray(arrival_ns, dtype=np.uint64)
+        lat = np.zeros(n, np.uint64)
+        cards = np.zeros(n, np.uint64)
+        dig = np.zeros(n, np.uint64)
+        self.ctx.check(lib().rg_serve_replay(self.h, n, arr, at.ctypes.data, lat.ctypes.data, cards.ctypes.data,
+                                             dig.ctypes.data))
+        return lat, cards, dig
+
+    def stop(self) -> dict:
+        if not self.h:
+            return {}
+        st = rg_serve_stats()
+        rc = lib().rg_serve_stop(self.h, ctypes.byref(st))
+        self.h = None
+        self.ctx.check(rc)
+        return {"queries": st.queries, "steps": st.steps, "mean_batch": st.mean_batch,
+                "arena_peak_bytes": st.arena_peak_bytes, "deferred": st.deferred}
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

@@ -1,0 +1,108 @@
+// rg_host.h - host-side internals shared by the C ABI sources: the context,
+// error reporting, workspace growth and small helpers.
+#pragma once
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "rg_internal.h"
+
+using namespace rg;
+
+struct rg_ctx {
+    int device = 0;
+    std::string err;
+    void* ws_pairs = nullptr;  // per-pair arrays
+    size_t ws_pairs_bytes = 0;
+    void* ws_wave = nullptr;   // per-slot arrays of one wave
+    size_t ws_wave_bytes = 0;
+    void* small = nullptr;     // 4 KiB of counters
+    void* host = nullptr;      // pinned staging
+    size_t host_bytes = 0;
+    // kernel timing (rg_profile_*): events around each compute-kernel launch
+    struct Pending {
+        hipEvent_t a, b;
+        int cls;
+        int mat;
+        uint64_t items;
+    };
+    bool prof = false;
+    std::vector<Pending> pend;
+    std::vector<hipEvent_t> evpool;
+    double prof_ms[NBINS][2] = {};
+    uint64_t prof_launches[NBINS][2] = {};
+    uint64_t prof_items[NBINS][2] = {};
+    int dispatch_mode = RG_DISPATCH_HEURISTIC;
+    int fixed_bin = BIN_GEN;
+    uint32_t gallop_ratio = 64;
+    uint32_t thread_max = 8;
+    uint64_t max_wave_slots = 1ull << 24;
+};
+
+
+inline rg_status fail(rg_ctx* c, rg_status s, const std::string& m) {
+    if (c) c->err = m;
+    return s;
+}
+
+#define HIPCHK(ctx, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) return fail(ctx, RG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+inline rg_status grow_device(rg_ctx* c, void** buf, size_t* cap, size_t need) {
+    if (need <= *cap) return RG_OK;
+    const size_t old = *cap;
+    if (*buf) {
+        HIPCHK(c, hipDeviceSynchronize());
+        HIPCHK(c, hipFree(*buf));
+        *buf = nullptr;
+        *cap = 0;
+    }
+    size_t nb = std::max(need, old + old / 2);
+    nb = (nb + (1u << 20) - 1) & ~(size_t)((1u << 20) - 1);
+    HIPCHK(c, hipMalloc(buf, nb));
+    *cap = nb;
+    return RG_OK;
+}
+
+inline rg_status grow_host(rg_ctx* c, size_t need) {
+    if (need <= c->host_bytes) return RG_OK;
+    if (c->host) {
+        HIPCHK(c, hipDeviceSynchronize());
+        HIPCHK(c, hipHostFree(c->host));
+        c->host = nullptr;
+        c->host_bytes = 0;
+    }
+    size_t nb = std::max(need, (size_t)1 << 20);
+    HIPCHK(c, hipHostMalloc(&c->host, nb, hipHostMallocDefault));
+    c->host_bytes = nb;
+    return RG_OK;
+}
+
+struct Bump {
+    uint8_t* base;
+    size_t used = 0;
+    template <class T>
+    T* take(size_t n) {
+        T* p = reinterpret_cast<T*>(base + used);
+        used += align256(n * sizeof(T));
+        return p;
+    }
+};
+
+inline PoolView view(const rg_pool& p) {
+    return PoolView{p.bm_begin, p.keys, p.types, p.card, p.size, p.off, p.payload, p.bm_card, p.bm_wbytes};
+}
+
+inline bool pool_ok(const rg_pool* p) {
+    return p && p->bm_begin && p->bm_card && p->bm_wbytes && (p->n_containers == 0 ||
+           (p->keys && p->types && p->card && p->size && p->off && p->payload)) &&
+           p->n_containers < 0xFFFFFFFFull;
+}
+

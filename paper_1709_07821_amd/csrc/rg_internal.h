@@ -280,9 +280,45 @@ void launch_bin_info(const uint32_t* bin_count, uint32_t* bin_info, uint32_t* cu
                      hipStream_t st);
 void launch_persist(const PersistArgs& a, uint32_t grid, hipStream_t st);
 
+// k-way queries over one pool (rg_kway.hip)
+constexpr uint32_t KW_MATERIALIZE = 1u;  // KwQuery.flags: build the result containers
+constexpr uint32_t KW_MAX_K = 256;       // bitmaps per query (one lookup thread each)
+struct KwQuery {
+    uint32_t op;       // RG_AND or RG_OR
+    uint32_t k;        // number of bitmaps, 1..KW_MAX_K
+    uint32_t ids_off;  // first of the query's bitmap ids in KwArgs.ids
+    uint32_t flags;    // KW_MATERIALIZE or 0 (count only)
+    uint64_t slot0;    // first slot of the query's range
+    uint32_t kbound;   // slots in the range (bound on result containers)
+    uint32_t pad;
+};
+static_assert(sizeof(KwQuery) == 32, "query record is 32 bytes");
+struct KwArgs {
+    PoolView P;
+    const KwQuery* queries;
+    uint32_t n_queries;
+    const uint32_t* ids;
+    Task* tasks;        // one per slot; pair = query index
+    uint64_t n_slots;
+    uint32_t* ub;       // payload bound per slot
+    uint32_t* res_card; // per slot, 0 = empty
+    SlotOut so;
+    long long* acc;     // per query, count-only results
+    uint32_t* err;      // set when a query's key set exceeds its slot range
+};
+void launch_kw_keys(const KwArgs& a, hipStream_t st);
+void launch_kw_bounds(const KwArgs& a, hipStream_t st);
+void launch_kw_eval(const KwArgs& a, hipStream_t st);
+void launch_kw_cards(const KwArgs& a, const uint64_t* bm_card, uint64_t* cards, hipStream_t st);
+// out[3j..3j+2] = key count, payload bound, 1 (0, 0, 0 for an id outside the pool)
+void launch_kw_gather_meta(const uint64_t* bm_begin, const uint64_t* bm_wbytes, uint32_t n_bitmaps,
+                           const uint32_t* ids, uint32_t k, uint64_t* out, hipStream_t st);
+
 // pool utilities
 void launch_pool_recount(const rg_pool& p, hipStream_t st);
 void launch_pool_validate(const rg_pool& p, uint64_t* d_bad, hipStream_t st);
 void launch_pool_digest(const rg_pool& p, uint64_t* d_digest, hipStream_t st);
+// containers i >= *d_n (device count) are skipped
+void launch_pool_digest_n(const rg_pool& p, const uint64_t* d_n, uint64_t* d_digest, hipStream_t st);
 
 }  // namespace rg

@@ -1,0 +1,243 @@
+// rg_kway.hip - k-way intersection and union of bitmaps of one pool, for many
+// queries at once (the building block of the serving loop).
+//
+// The paper folds many bitmaps pairwise or aggregates lazily (Section 5.9,
+// wide unions; lazy aggregation, Section 2.2). Here a query's result is built
+// key by key, each key by one workgroup, so no intermediate bitmap is ever
+// written:
+//   1. k_kw_keys: one workgroup per query builds the query's result key set as
+//      a 65536-bit LDS mask (AND of the bitmaps' key masks, or OR), writes the
+//      keys in ascending order as one task per result key, and marks the rest
+//      of the query's slot range empty.
+//   2. k_kw_bounds: one thread per slot looks the key up in each of the k
+//      bitmaps and bounds the result payload (AND: the smallest container,
+//      OR: the sum, both capped at a bitset) - the slot sizes of step 3.
+//   3. k_kw_eval: one workgroup per result key: every present container is
+//      expanded into an LDS bitset and combined word by word (AND stops when
+//      the running result is empty); then the common output step (P1 type,
+//      payload into the slot) or, count-only, the population count.
+// Compaction of non-empty results into per-query bitmaps uses the pairwise
+// path's kernels (flags, scan, compact, bitmap starts).
+#include "rg_count_dev.h"
+
+namespace rg {
+
+__device__ __forceinline__ uint32_t kw_find_key(const PoolView& P, uint32_t b, uint16_t key) {
+    const uint64_t s = P.bm_begin[b], e = P.bm_begin[b + 1];
+    uint64_t lo = s, hi = e;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (P.keys[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < e && P.keys[lo] == key) ? (uint32_t)lo : NONE;
+}
+
+// ---------------------------------------------------------------- 1. keys
+__global__ void __launch_bounds__(256) k_kw_keys(KwArgs a) {
+    __shared__ uint64_t acc[1024];
+    __shared__ uint64_t cur[1024];
+    __shared__ uint32_t tmp[8];
+    const uint32_t q = blockIdx.x;
+    const KwQuery Q = a.queries[q];
+    const uint32_t op = uniform(Q.op), k = uniform(Q.k), ids0 = uniform(Q.ids_off);
+    const uint64_t slot0 = uniform64(Q.slot0);
+    const uint32_t kbound = uniform(Q.kbound);
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t i = tid; i < 1024; i += 256) acc[i] = 0;
+    __syncthreads();
+    for (uint32_t j = 0; j < k; ++j) {
+        const uint32_t b = uniform(a.ids[ids0 + j]);
+        const uint64_t s = uniform64(a.P.bm_begin[b]);
+        const uint32_t n = (uint32_t)(uniform64(a.P.bm_begin[b + 1]) - s);
+        if (op == RG_OR || j == 0) {
+            for (uint32_t i = tid; i < n; i += 256) {
+                const uint32_t key = a.P.keys[s + i];
+                atomicOr(reinterpret_cast<unsigned long long*>(&acc[key >> 6]), 1ull << (key & 63));
+            }
+            __syncthreads();
+        } else {
+            for (uint32_t i = tid; i < 1024; i += 256) cur[i] = 0;
+            __syncthreads();
+            for (uint32_t i = tid; i < n; i += 256) {
+                const uint32_t key = a.P.keys[s + i];
+                atomicOr(reinterpret_cast<unsigned long long*>(&cur[key >> 6]), 1ull << (key & 63));
+            }
+            __syncthreads();
+            for (uint32_t i = tid; i < 1024; i += 256) acc[i] &= cur[i];
+            __syncthreads();
+        }
+    }
+    // ascending keys: thread t owns words 4t..4t+3
+    uint64_t w[4];
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        w[j] = acc[4 * tid + j];
+        c += __popcll(w[j]);
+    }
+    uint32_t total;
+    uint32_t pos = block_excl_scan_u32(c, tmp, &total);
+    // total <= kbound holds by construction of the host bound; guard anyway
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        uint64_t x = w[j];
+        while (x) {
+            const uint32_t key = (4 * tid + j) * 64 + (uint32_t)__builtin_ctzll(x);
+            x &= x - 1;
+            if (pos < kbound) {
+                Task t;
+                t.pair = q;
+                t.ia = NONE;
+                t.ib = NONE;
+                t.key = (uint16_t)key;
+                t.kind = KIND_MATCH;
+                t.bin = 0;
+                a.tasks[slot0 + pos] = t;
+            }
+            ++pos;
+        }
+    }
+    const uint32_t used = total < kbound ? total : kbound;
+    for (uint32_t i = used + tid; i < kbound; i += 256) {
+        Task t;
+        t.pair = q;
+        t.ia = NONE;
+        t.ib = NONE;
+        t.key = 0;
+        t.kind = KIND_NOOP;
+        t.bin = 0;
+        a.tasks[slot0 + i] = t;
+    }
+    if (tid == 0 && total > kbound) atomicOr(a.err, 1u);
+}
+
+// ---------------------------------------------------------------- 2. bounds
+__global__ void __launch_bounds__(256) k_kw_bounds(KwArgs a) {
+    const uint64_t s = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= a.n_slots) return;
+    const Task t = a.tasks[s];
+    uint32_t ub = 0;
+    if (t.kind == KIND_MATCH) {
+        const KwQuery Q = a.queries[t.pair];
+        if (Q.flags & KW_MATERIALIZE) {
+            uint64_t sum = 0;
+            uint32_t mn = 0xFFFFFFFFu;
+            for (uint32_t j = 0; j < Q.k; ++j) {
+                const uint32_t ci = kw_find_key(a.P, a.ids[Q.ids_off + j], t.key);
+                const uint32_t cj = ci == NONE ? 0u : a.P.card[ci];
+                sum += cj;
+                if (cj < mn) mn = cj;
+            }
+            const uint64_t bc = Q.op == RG_AND ? (uint64_t)mn : sum;
+            ub = wbytes_of(bc);
+        }
+    }
+    a.ub[s] = ub;
+    a.res_card[s] = 0;
+}
+
+// ---------------------------------------------------------------- 3. evaluate
+__global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
+    __shared__ WgShared sh;
+    __shared__ uint32_t cidx[KW_MAX_K];
+    const uint32_t tid = threadIdx.x;
+    for (uint64_t s = blockIdx.x; s < a.n_slots; s += gridDim.x) {
+        const Task t = uniform_task(a.tasks, (uint32_t)s);
+        if (t.kind != KIND_MATCH) continue;
+        const uint32_t q = t.pair;
+        const KwQuery Q = a.queries[q];
+        const uint32_t op = uniform(Q.op), k = uniform(Q.k), flags = uniform(Q.flags);
+        const uint32_t ids0 = uniform(Q.ids_off);
+        if (tid < k) cidx[tid] = kw_find_key(a.P, a.ids[ids0 + tid], t.key);
+        __syncthreads();
+        // running result in sh.sa; each container is expanded into sh.sb
+        bool empty = false;
+        bool first = true;
+        for (uint32_t j = 0; j < k && !empty; ++j) {
+            const uint32_t ci = uniform(cidx[j]);
+            if (ci == NONE) {
+                if (op == RG_AND) empty = true;  // cannot happen: the key is in every bitmap
+                continue;
+            }
+            expand_container(first ? sh.sa : sh.sb, a.P, ci, sh);
+            if (!first) {
+                uint32_t any = 0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint32_t wi = 4 * tid + i;
+                    const uint64_t v = op == RG_AND ? (sh.sa[wi] & sh.sb[wi]) : (sh.sa[wi] | sh.sb[wi]);
+                    sh.sa[wi] = v;
+                    any |= v != 0 ? 1u : 0u;
+                }
+                if (op == RG_AND) empty = block_sum_u64(any, sh.tmp64) == 0;
+                else __syncthreads();
+            }
+            first = false;
+        }
+        uint64_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i] = (empty || first) ? 0ull : sh.sa[4 * tid + i];
+        __syncthreads();
+        if (flags & KW_MATERIALIZE) {
+            finalize_words(w, (uint32_t)s, a.so, sh.sa, sh.sb, sh);
+        } else {
+            const uint32_t c = count_words(w, sh);
+            if (tid == 0 && c) atomicAdd(reinterpret_cast<unsigned long long*>(&a.acc[q]), (unsigned long long)c);
+        }
+        __syncthreads();
+    }
+}
+
+// per-query cardinality of count-only and materialised queries alike
+__global__ void k_kw_cards(KwArgs a, const uint64_t* bm_card, uint64_t* cards) {
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.n_queries) return;
+    cards[q] = (a.queries[q].flags & KW_MATERIALIZE) ? bm_card[q] : (uint64_t)a.acc[q];
+}
+
+void launch_kw_keys(const KwArgs& a, hipStream_t st) {
+    if (a.n_queries) hipLaunchKernelGGL(k_kw_keys, dim3(a.n_queries), dim3(256), 0, st, a);
+}
+void launch_kw_bounds(const KwArgs& a, hipStream_t st) {
+    if (a.n_slots)
+        hipLaunchKernelGGL(k_kw_bounds, dim3((uint32_t)((a.n_slots + 255) / 256)), dim3(256), 0, st, a);
+}
+void launch_kw_eval(const KwArgs& a, hipStream_t st) {
+    if (!a.n_slots) return;
+    const uint32_t g = a.n_slots < 65536 ? (uint32_t)a.n_slots : 65536u;
+    hipLaunchKernelGGL(k_kw_eval, dim3(g), dim3(256), 0, st, a);
+}
+void launch_kw_cards(const KwArgs& a, const uint64_t* bm_card, uint64_t* cards, hipStream_t st) {
+    if (a.n_queries)
+        hipLaunchKernelGGL(k_kw_cards, dim3((a.n_queries + 255) / 256), dim3(256), 0, st, a, bm_card, cards);
+}
+
+}  // namespace rg
+
+namespace rg {
+
+// per id: key count, payload bound (bm_wbytes), and validity, for host-side bounds
+__global__ void k_kw_gather_meta(const uint64_t* bm_begin, const uint64_t* bm_wbytes, uint32_t n_bitmaps,
+                                 const uint32_t* ids, uint32_t k, uint64_t* out) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= k) return;
+    const uint32_t b = ids[j];
+    if (b >= n_bitmaps) {
+        out[3 * j] = 0;
+        out[3 * j + 1] = 0;
+        out[3 * j + 2] = 0;
+        return;
+    }
+    out[3 * j] = bm_begin[b + 1] - bm_begin[b];
+    out[3 * j + 1] = bm_wbytes[b];
+    out[3 * j + 2] = 1;
+}
+
+void launch_kw_gather_meta(const uint64_t* bm_begin, const uint64_t* bm_wbytes, uint32_t n_bitmaps,
+                           const uint32_t* ids, uint32_t k, uint64_t* out, hipStream_t st) {
+    if (k) hipLaunchKernelGGL(k_kw_gather_meta, dim3((k + 255) / 256), dim3(256), 0, st, bm_begin, bm_wbytes,
+                              n_bitmaps, ids, k, out);
+}
+
+}  // namespace rg

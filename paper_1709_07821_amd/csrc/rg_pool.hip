@@ -20,7 +20,7 @@ __device__ __forceinline__ uint32_t bitmap_of(const uint64_t* bm_begin, uint32_t
 __global__ void __launch_bounds__(256) k_recount(rg_pool p) {
     const uint32_t lane = lane_id();
     const uint64_t i = wave_index();
-    if (i >= p.n_containers) return;
+    if (i >= p.n_containers || i < uniform64(p.bm_begin[0])) return;  // a window may start past 0
     const uint8_t type = (uint8_t)uniform(p.types[i]);
     const uint32_t size = uniform(p.size[i]);
     const uint8_t* pl = p.payload + uniform64(p.off[i]);
@@ -59,7 +59,7 @@ void launch_pool_recount(const rg_pool& p, hipStream_t st) {
 __global__ void __launch_bounds__(256) k_validate(rg_pool p, unsigned long long* bad) {
     const uint32_t lane = lane_id();
     const uint64_t i = wave_index();
-    if (i >= p.n_containers) return;
+    if (i >= p.n_containers || i < uniform64(p.bm_begin[0])) return;  // a window may start past 0
     const uint8_t type = (uint8_t)uniform(p.types[i]);
     const uint32_t size = uniform(p.size[i]), card = uniform(p.card[i]);
     const uint64_t off = uniform64(p.off[i]);
@@ -152,10 +152,11 @@ __device__ __forceinline__ uint64_t dmix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-__global__ void __launch_bounds__(256) k_digest(rg_pool p, uint64_t* digest) {
+__global__ void __launch_bounds__(256) k_digest(rg_pool p, const uint64_t* d_n, uint64_t* digest) {
     const uint32_t lane = lane_id();
     const uint64_t i = wave_index();
-    if (i >= p.n_containers) return;
+    const uint64_t n = d_n ? uniform64(*d_n) : p.n_containers;  // d_n: live count (<= p.n_containers)
+    if (i >= n || i >= p.n_containers || i < uniform64(p.bm_begin[0])) return;
     const uint8_t type = (uint8_t)uniform(p.types[i]);
     const uint32_t size = uniform(p.size[i]), card = uniform(p.card[i]);
     const uint32_t key = uniform(p.keys[i]);
@@ -193,9 +194,13 @@ __global__ void __launch_bounds__(256) k_digest(rg_pool p, uint64_t* digest) {
 }
 
 void launch_pool_digest(const rg_pool& p, uint64_t* d_digest, hipStream_t st) {
+    launch_pool_digest_n(p, nullptr, d_digest, st);
+}
+
+void launch_pool_digest_n(const rg_pool& p, const uint64_t* d_n, uint64_t* d_digest, hipStream_t st) {
     launch_fill_u64(d_digest, 0, p.n_bitmaps, st);
     if (!p.n_containers) return;
-    hipLaunchKernelGGL(k_digest, dim3((uint32_t)((p.n_containers + 3) / 4)), dim3(256), 0, st, p, d_digest);
+    hipLaunchKernelGGL(k_digest, dim3((uint32_t)((p.n_containers + 3) / 4)), dim3(256), 0, st, p, d_n, d_digest);
 }
 
 }  // namespace rg

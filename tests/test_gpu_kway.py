@@ -1,0 +1,198 @@
+"""k-way intersection / union (roaring_multi) and the serving loop on the GPU,
+against the oracle's left fold (k-way semantics as defined for the serving
+workload: AND / OR of k bitmaps of one pool)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import rgtest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rg():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1709_07821_amd as rg
+
+    return rg
+
+
+@pytest.fixture(scope="module")
+def ctx(rg):
+    c = rg.Context(0)
+    yield c
+    c.close()
+
+
+def overlapping_sets(n=24, seed=7):
+    """Bitmaps that share most of their content, so that k-way intersections
+    are non-empty and cross every container type: each is one of two mixed base
+    bitmaps (two thirds use the first), whole for every fourth bitmap (runs
+    intact) and otherwise thinned to a seeded 85 %, plus a few private values."""
+    hot = synth.hot_keys(seed, 16, 1 << 10)
+    bases = [synth.mixed_bitmap(seed, i, 40000, 26, hot) for i in range(2)]
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        b = bases[1 if i % 3 == 0 else 0]
+        keep = b if i % 4 == 0 else b[rng.random(len(b)) < 0.85]
+        extra = rng.integers(0, 1 << 26, 500).astype(np.uint32)
+        out.append(np.unique(np.concatenate([keep, extra])).astype(np.uint32))
+    return synth.BitmapSet.from_list(out)
+
+
+def _queries(n_bitmaps, n, seed, kmax=8):
+    rng = np.random.default_rng(seed)
+    qs = []
+    for i in range(n):
+        k = int(rng.integers(1, kmax + 1))
+        ids = rng.choice(n_bitmaps, size=k, replace=(i % 4 == 0)).astype(np.uint32)
+        qs.append(("and" if i % 2 == 0 else "or", ids))
+    return qs
+
+
+def _workload(which):
+    if which == "overlapping":
+        return overlapping_sets()
+    if which == "edges":
+        return synth.BitmapSet.from_list(rgtest.edge_sets())
+    return synth.mixed_small(n_bitmaps=30)
+
+
+@pytest.mark.parametrize("which", ["overlapping", "edges", "mixed"])
+def test_multi_matches_oracle(rg, ctx, which):
+    import torch
+
+    bs = _workload(which)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    qs = _queries(len(bs), 16, seed=11)
+    # k at the limit: 256 ids (repeats allowed)
+    qs.append(("and", np.resize(np.arange(min(3, len(bs)), dtype=np.uint32), 256)))
+    qs.append(("or", np.resize(np.arange(len(bs), dtype=np.uint32), 256)))
+    n_nonempty_and = 0
+    for op, ids in qs:
+        _say(f"[multi {which}] op={op} k={len(ids)}")
+        exp = oracle.kway(op, [bs[int(i)] for i in ids])
+        n_nonempty_and += op == "and" and len(exp) > 0
+        tids = torch.from_numpy(ids.view(np.int32)).cuda()
+        out, card = rg.multi(ctx, op, P, tids, materialize=True, card=True)
+        torch.cuda.synchronize()
+        assert int(card[0].item()) == len(exp), (which, op, ids)
+        res = out.as_pool()
+        assert rg.rg_pool_validate(ctx, res) == 0
+        assert int(rg.rg_pool_digest(ctx, res).cpu().numpy().view(np.uint64)[0]) == oracle.digest(exp)
+        h = res.to_host()
+        got, meta = rgtest.decode_bitmap(h, 0)
+        assert np.array_equal(got, exp), (which, op, ids)
+        assert meta == rgtest.oracle_meta(oracle, exp), (which, op, ids)
+        _, card2 = rg.multi(ctx, op, P, tids, materialize=False, card=True)
+        assert int(card2[0].item()) == len(exp)
+    if which == "overlapping":
+        assert n_nonempty_and >= 3  # the workload does exercise non-empty intersections
+
+
+def test_multi_errors(rg, ctx):
+    import torch
+
+    bs = synth.mixed_small(n_bitmaps=4, seed=5)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    card = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+    def call(op, ids, flags=rg.RG_FLAG_CARD):
+        t = torch.tensor(np.asarray(ids, np.uint32).view(np.int32), device="cuda")
+        return rg.roaring_multi(ctx, op, P, t, flags, None, card)
+
+    assert call(rg.RG_XOR, [0, 1]) == rg.RG_EINVAL
+    assert call("and", [0, 9]) == rg.RG_EINVAL
+    assert call("and", [0] * 257) == rg.RG_EINVAL
+    assert call("or", [0, 1], flags=0) == rg.RG_EINVAL
+    out = rg.OutArena(1, 0, 0, "cuda")
+    out.c.cap_containers = 0
+    out.c.cap_payload_bytes = 0
+    t = torch.tensor([0, 1], dtype=torch.int32, device="cuda")
+    assert rg.roaring_multi(ctx, "or", P, t, rg.RG_FLAG_MATERIALIZE, out, None) == rg.RG_ECAPACITY
+    assert out.c.needed_containers > 0 and out.c.needed_payload_bytes > 0
+
+
+def _expect(bs, qs):
+    res = []
+    for op, ids, mat in qs:
+        e = oracle.kway(op, [bs[int(i)] for i in ids])
+        res.append((len(e), oracle.digest(e) if mat else 0))
+    return res
+
+
+def test_server_results_alone_and_in_mix(rg, ctx):
+    """Each query's result (cardinality, container-form fingerprint) is the
+    oracle's, whether it runs alone (one query per step) or in the mix."""
+    bs = overlapping_sets()
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    base = _queries(len(bs), 48, seed=23, kmax=12)
+    qs = [(op, ids, i % 5 != 4) for i, (op, ids) in enumerate(base)]
+    exp = _expect(bs, qs)
+    # alone: one query per step, one step in flight
+    alone = rg.Server(ctx, P, arena_bytes=256 << 20, max_batch=1, max_inflight=1)
+    lat, cards, dig = alone.replay(qs, np.zeros(len(qs), np.uint64))
+    st = alone.stop()
+    _say(f"[serve alone] {st}")
+    assert st["steps"] == len(qs)
+    for i, (c, d) in enumerate(exp):
+        assert cards[i] == c and dig[i] == d, ("alone", i)
+    # in the mix: all arrive at once, batched, two steps in flight
+    mix = rg.Server(ctx, P, arena_bytes=256 << 20, max_batch=16, max_inflight=2)
+    lat2, cards2, dig2 = mix.replay(qs, np.zeros(len(qs), np.uint64))
+    st2 = mix.stop()
+    _say(f"[serve mix] {st2}")
+    assert st2["mean_batch"] > 1.0
+    assert np.array_equal(cards2, cards) and np.array_equal(dig2, dig)
+    # spread arrivals (continuous batching while steps run)
+    mix = rg.Server(ctx, P, arena_bytes=256 << 20, max_batch=8, max_inflight=2)
+    lat3, cards3, dig3 = mix.replay(qs, np.arange(len(qs), dtype=np.uint64) * 20000)
+    st3 = mix.stop()
+    _say(f"[serve spread] {st3} p50={np.percentile(lat3, 50) / 1e3:.1f}us p99={np.percentile(lat3, 99) / 1e3:.1f}us")
+    assert np.array_equal(cards3, cards) and np.array_equal(dig3, dig)
+
+
+def test_server_views_and_small_arena(rg, ctx):
+    """Materialised results are readable through the view until released; an
+    arena that holds only a few queries at a time still serves every query."""
+    import torch
+
+    bs = overlapping_sets(n=12, seed=3)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    qs = [(op, ids, True) for op, ids in _queries(len(bs), 20, seed=31, kmax=6)]
+    exp = _expect(bs, qs)
+    srv = rg.Server(ctx, P, arena_bytes=8 << 20, max_batch=4, max_inflight=2)
+    try:
+        tickets = [srv.submit(op, ids, materialize=m) for op, ids, m in qs]
+        for i, t in enumerate(tickets):
+            r = srv.poll(t, wait=True)
+            assert r.done and r.status == 0 and r.card == exp[i][0] and r.digest == exp[i][1], i
+            if i < 6 and r.n_containers:
+                # the view is a window into the step's arrays: its containers need
+                # not start at 0 (query i of a step)
+                view = rg.Pool.from_view(r.view)
+                assert int(rg.rg_pool_digest(ctx, view).cpu().numpy().view(np.uint64)[0]) == exp[i][1]
+                torch.cuda.synchronize()
+            srv.release(t)
+    finally:
+        st = srv.stop()
+    _say(f"[serve small arena] {st}")
+    assert st["queries"] == len(qs)
+    with pytest.raises(rg.RoaringError):
+        srv2 = rg.Server(ctx, P, arena_bytes=1 << 20, max_batch=4, max_inflight=2)
+        try:
+            srv2.submit("or", np.resize(np.arange(12, dtype=np.uint32), 256), materialize=True)
+        finally:
+            srv2.stop()
