@@ -52,6 +52,8 @@ def main():
     ap.add_argument("--pool", type=int, default=1024, help="batched: bitmaps in the pool")
     ap.add_argument("--batched-pairs", type=int, default=100000, help="batched: random pairs per step")
     ap.add_argument("--per-pair-sample", type=int, default=500, help="batched: pairs timed one call each")
+    ap.add_argument("--dispatch-pairs", type=int, default=300, help="batched: pairs whose costs train the dispatcher")
+    ap.add_argument("--dispatch-epochs", type=int, default=10, help="batched: dispatcher training epochs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES bytes (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -254,6 +256,29 @@ def bench_batched(args):
     print(f"# plan (graph, {info}): {plan_s * 1e3:.2f} ms/step, results equal to the eager call",
           file=sys.stderr, flush=True)
 
+    # learned dispatch: cost samples measured by the kernels on a subset of the
+    # pairs, the network trained on the GPU, installed, and a new plan timed
+    t_s = time.perf_counter()
+    sub_n = min(args.dispatch_pairs, n)
+    X, T, M = rg.dispatch_samples(ctx, P, P, tia[:sub_n], tib[:sub_n])
+    params, losses = rg.dispatch_train(ctx, X, T, M, epochs=args.dispatch_epochs, batch=4096, lr=2e-3, seed=11)
+    rg.dispatch_set_mlp(ctx, params)
+    losses = losses.cpu().numpy()
+    print(f"# dispatcher: {int(M.any(1).sum())} sampled container pairs, loss {losses[0]:.3f} -> {losses[-1]:.3f}, "
+          f"{time.perf_counter() - t_s:.1f} s", file=sys.stderr, flush=True)
+    pl2 = rg.Plan(ctx, "and", P, P, tia, tib, card=True, jaccard=True, stream=st)
+    pl2.tune(stream=st, reps=1)
+    pl2.capture(st)
+    torch.cuda.synchronize()
+    learned_s = timed(lambda: pl2.execute(stream=st), args.steps, args.warmup)
+    assert np.array_equal(pl2.cards.cpu().numpy().view(np.uint64), c_e)
+    assert np.array_equal(pl2.jacc.cpu().numpy(), j_e)
+    info2 = pl2.info()
+    pl2.close()
+    ctx.set_dispatch(rg.RG_DISPATCH_HEURISTIC)
+    print(f"# plan with learned dispatch ({info2}): {learned_s * 1e3:.2f} ms/step, results equal",
+          file=sys.stderr, flush=True)
+
     # one call per pair, on a sample
     k = min(args.per_pair_sample, n)
     one_c = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -284,6 +309,10 @@ def bench_batched(args):
         "per_pair_ms_extrapolated": round(pp_s * 1e3, 3),
         "speedup_plan_vs_per_pair": round(pp_s / plan_s, 2),
         "speedup_plan_vs_eager": round(eager_s / plan_s, 3),
+        "plan_learned_dispatch_ms": round(learned_s * 1e3, 3),
+        "plan_learned": info2,
+        "speedup_learned_vs_heuristic": round(plan_s / learned_s, 3),
+        "dispatcher_loss": [round(float(losses[0]), 4), round(float(losses[-1]), 4)],
     }
     print(json.dumps(line), flush=True)
 

@@ -126,7 +126,10 @@ const char *rg_last_error(const rg_ctx *ctx);
  * left unchanged and the result is built as a new bitmap) ----------------- */
 
 /* Result of A[ia] op B[ib] into `out` (one result bitmap). Returns
- * RG_ECAPACITY with out->needed_* filled if the arena is too small. */
+ * RG_ECAPACITY with out->needed_* filled if the arena is too small.
+ * Intersections are built per matched key pair by the binned kernels; union,
+ * symmetric difference and difference per result key by the k-way kernels
+ * (two bitmaps per query; see roaring_multi). */
 rg_status roaring_and(rg_ctx *ctx, const rg_pool *A, uint32_t ia, const rg_pool *B, uint32_t ib, rg_out *out,
                       void *stream);
 rg_status roaring_or(rg_ctx *ctx, const rg_pool *A, uint32_t ia, const rg_pool *B, uint32_t ib, rg_out *out,
@@ -196,10 +199,13 @@ void rg_plan_destroy(rg_plan *plan);
 /* Kernel-variant selection for matched container pairs. Every variant
  * computes the same result; they differ only in speed.
  *   mode RG_DISPATCH_HEURISTIC (default): size-ratio / type heuristic;
+ *   mode RG_DISPATCH_MLP: the learned dispatcher (count-only pairs; needs a
+ *   network installed with rg_dispatch_set_mlp, else RG_EINVAL);
  *   mode RG_DISPATCH_FIXED: use `variant` wherever it applies to the pair's
  *   container types, the generic variant elsewhere (bitset-bitset pairs
  *   always use their own kernel). */
 #define RG_DISPATCH_HEURISTIC 0
+#define RG_DISPATCH_MLP 1 /* learned: the table installed by rg_dispatch_set_mlp */
 #define RG_DISPATCH_FIXED 2
 #define RG_V_GENERIC 2   /* both sides expanded to LDS bitsets, any types */
 #define RG_V_MERGE 3     /* array-array merge */
@@ -216,11 +222,62 @@ rg_status rg_set_dispatch(rg_ctx *ctx, int mode, int variant);
  * RG_EINVAL for gallop_ratio 0 or thread_max > 4096. Results never change. */
 rg_status rg_set_thresholds(rg_ctx *ctx, uint32_t gallop_ratio, uint32_t thread_max);
 
+/* ---- learned dispatcher --------------------------------------------------
+ * Not from the paper (its variant rule is fixed, Section 2.2): a 12 -> 64 ->
+ * 64 -> 6 ReLU network, fp32, that predicts the log2 cost of each count
+ * variant (outputs v = 0..5 are RG_V_GENERIC + v) of one matched container
+ * pair from 12 features: one-hot type of each side (3 + 3), log2(1 + c)/16 of
+ * each side, log2(1 + r)/16 of each side (r = run count of a run container,
+ * else 0), log2(max c / max(1, min c))/16, op/3 (0: count-only pairs always
+ * compute the intersection). Parameters: flat fp32 [RG_MLP_PARAMS], W1[12][64],
+ * b1[64], W2[64][64], b2[64], W3[64][6], b3[6], row-major, device memory. */
+#define RG_MLP_PARAMS 5382
+#define RG_MLP_TABLE 374544
+/* y[n][6] = network(x[n][12]) (device arrays). */
+rg_status rg_mlp_forward(rg_ctx *ctx, const float *d_params, const float *d_x, uint64_t n, float *d_y, void *stream);
+/* Gradient of the masked mean squared error sum(m (y - t)^2) / sum(m) over
+ * the n samples (t, m: [n][6]; m bytes 0/1) into d_grad[RG_MLP_PARAMS], the
+ * loss into d_loss[0] (may be NULL). Sums in a fixed order of 256-sample
+ * blocks; within a block the order of fp32 additions is not fixed. */
+rg_status rg_mlp_grad(rg_ctx *ctx, const float *d_params, const float *d_x, const float *d_t, const uint8_t *d_m,
+                      uint64_t n, float *d_grad, float *d_loss, void *stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected for step >= 1) on
+ * d_params with moment buffers d_m, d_v [RG_MLP_PARAMS]. */
+rg_status rg_mlp_adam(rg_ctx *ctx, float *d_params, const float *d_grad, float *d_m, float *d_v, uint32_t step,
+                      float lr, void *stream);
+/* Training samples measured by the count kernels themselves: runs the
+ * count-only intersection of the pairs with `variant` (RG_V_GENERIC ..
+ * RG_V_THREAD) forced where it applies and records each slot's cost in
+ * wave-cycles (s_memtime; a workgroup task counts four waves, a thread task
+ * its wave's time shared by the active lanes). Writes, per slot s < *n_slots,
+ * the features d_x[s][12] (zeros for an unmatched slot), and column
+ * variant - RG_V_GENERIC of d_t[s][6] (log2 cost) and d_m[s][6] (1 when the
+ * slot is a matched pair that ran with `variant`). Calling it once per variant
+ * fills all columns. All pairs must fit one wave of slots; RG_ECAPACITY (with
+ * *n_slots set) when *n_slots > cap_slots. Synchronises. */
+rg_status rg_dispatch_sample(rg_ctx *ctx, const rg_pool *A, const rg_pool *B, const uint32_t *d_ia,
+                             const uint32_t *d_ib, uint64_t n_pairs, int variant, float *d_x, float *d_t,
+                             uint8_t *d_m, uint64_t cap_slots, uint64_t *n_slots, void *stream);
+/* Adam training on (x[n][12], t[n][6], m[n][6]) for `epochs` passes in
+ * shuffled batches of `batch`; seed != 0 initialises d_params first (He
+ * normal weights, zero biases, counter-based generator). d_epoch_loss[epochs]
+ * receives the mean batch loss of each epoch. Synchronises. */
+rg_status rg_dispatch_train(rg_ctx *ctx, const float *d_x, const float *d_t, const uint8_t *d_m, uint64_t n,
+                            uint32_t epochs, uint32_t batch, float lr, uint64_t seed, float *d_params,
+                            float *d_epoch_loss, void *stream);
+/* Installs a trained network: evaluates it on the quantised feature grid
+ * (type x type x 17 log2-cardinality buckets x 17 x 12 log2-run buckets x 12,
+ * bucket centres), keeps the cheapest applicable variant of each cell, and
+ * switches the context to RG_DISPATCH_MLP. Results never change. */
+rg_status rg_dispatch_set_mlp(rg_ctx *ctx, const float *d_params, void *stream);
+/* Copies the installed table (RG_MLP_TABLE bytes of variant numbers) to host memory. */
+rg_status rg_dispatch_table(rg_ctx *ctx, uint8_t *h_table, uint64_t cap);
+
 /* Kernel timing. When enabled, every compute-kernel launch of a call is
  * bracketed by two HIP events recorded on the call's stream; rg_profile_read
  * waits for them and returns the accumulated time, launch count and number of
  * container pairs processed for one variant (RG_V_* or 0 for the
- * bitset-bitset kernel, 1 for one-sided copies, 8 for the bitset pairs redone
+ * bitset-bitset kernel, 8 for the bitset pairs redone
  * by the generic kernel) in count-only (materialize = 0) or materialising
  * form. Synchronises on the recorded events; costs two events per launch. */
 rg_status rg_profile_enable(rg_ctx *ctx, int on);

@@ -26,7 +26,8 @@ RG_ARRAY, RG_BITSET, RG_RUN = 1, 2, 3
 RG_AND, RG_OR, RG_XOR, RG_ANDNOT = 0, 1, 2, 3
 OPS = {"and": RG_AND, "or": RG_OR, "xor": RG_XOR, "andnot": RG_ANDNOT}
 RG_FLAG_MATERIALIZE, RG_FLAG_CARD, RG_FLAG_JACCARD = 1, 2, 4
-RG_DISPATCH_HEURISTIC, RG_DISPATCH_FIXED = 0, 2
+RG_DISPATCH_HEURISTIC, RG_DISPATCH_MLP, RG_DISPATCH_FIXED = 0, 1, 2
+RG_MLP_PARAMS, RG_MLP_TABLE = 5382, 374544
 VARIANTS = {"generic": 2, "merge": 3, "gallop": 4, "probe": 5, "runmerge": 6, "thread": 7}
 
 # every symbol the C header declares
@@ -36,7 +37,9 @@ EXPORTS = ["rg_create", "rg_destroy", "rg_last_error", "rg_set_dispatch", "rg_se
            "rg_pool_build_host", "rg_pool_recount", "rg_pool_validate", "rg_pool_digest", "rg_profile_enable",
            "rg_profile_reset", "rg_profile_read", "rg_plan_create", "rg_plan_execute", "rg_plan_capture",
            "rg_plan_tune", "rg_plan_set", "rg_plan_info", "rg_plan_destroy", "roaring_multi", "rg_serve_start",
-           "rg_serve_submit", "rg_serve_poll", "rg_serve_release", "rg_serve_replay", "rg_serve_stop"]
+           "rg_serve_submit", "rg_serve_poll", "rg_serve_release", "rg_serve_replay", "rg_serve_stop",
+           "rg_mlp_forward", "rg_mlp_grad", "rg_mlp_adam", "rg_dispatch_sample", "rg_dispatch_train",
+           "rg_dispatch_set_mlp", "rg_dispatch_table"]
 
 
 class RoaringError(RuntimeError):
@@ -127,6 +130,13 @@ def lib():
         L.rg_serve_release.argtypes = [V, U64]
         L.rg_serve_replay.argtypes = [V, U64, P(rg_query), V, V, V, V]
         L.rg_serve_stop.argtypes = [V, P(rg_serve_stats)]
+        L.rg_mlp_forward.argtypes = [V, V, V, U64, V, V]
+        L.rg_mlp_grad.argtypes = [V, V, V, V, V, U64, V, V, V]
+        L.rg_mlp_adam.argtypes = [V, V, V, V, V, U32, ctypes.c_float, V]
+        L.rg_dispatch_sample.argtypes = [V, pool_p, pool_p, V, V, U64, I, V, V, V, U64, P(U64), V]
+        L.rg_dispatch_train.argtypes = [V, V, V, V, U64, U32, U32, ctypes.c_float, U64, V, V, V]
+        L.rg_dispatch_set_mlp.argtypes = [V, V, V]
+        L.rg_dispatch_table.argtypes = [V, V, U64]
         for nm in EXPORTS:
             if nm not in ("rg_destroy", "rg_last_error", "rg_plan_destroy"):
                 getattr(L, nm).restype = ctypes.c_int
@@ -418,7 +428,7 @@ class Plan:
             pass
 
 
-PROFILE_CLASSES = {0: "bb", 1: "copy", 2: "generic", 3: "merge", 4: "gallop", 5: "probe", 6: "runmerge",
+PROFILE_CLASSES = {0: "bb", 1: "unused", 2: "generic", 3: "merge", 4: "gallop", 5: "probe", 6: "runmerge",
                    7: "thread", 8: "bb-redo"}
 
 
@@ -573,3 +583,66 @@ class Server:
             self.stop()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- learned dispatcher
+
+def mlp_forward(ctx: Context, params, x, stream=None):
+    torch = _torch()
+    y = torch.empty((x.shape[0], 6), dtype=torch.float32, device=x.device)
+    ctx.check(lib().rg_mlp_forward(ctx.h, _ptr(params), _ptr(x), x.shape[0], _ptr(y), _stream(stream)))
+    return y
+
+
+def mlp_grad(ctx: Context, params, x, t, m, stream=None):
+    torch = _torch()
+    g = torch.empty(RG_MLP_PARAMS, dtype=torch.float32, device=x.device)
+    loss = torch.zeros(1, dtype=torch.float32, device=x.device)
+    ctx.check(lib().rg_mlp_grad(ctx.h, _ptr(params), _ptr(x), _ptr(t), _ptr(m), x.shape[0], _ptr(g), _ptr(loss),
+                                _stream(stream)))
+    return g, loss
+
+
+def mlp_adam(ctx: Context, params, grad, m, v, step: int, lr: float, stream=None):
+    ctx.check(lib().rg_mlp_adam(ctx.h, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, _stream(stream)))
+
+
+def dispatch_samples(ctx: Context, A: Pool, B: Pool, ia, ib, stream=None):
+    """Cost samples of every count variant on the pairs: (x [n, 12], t [n, 6], m [n, 6])."""
+    torch = _torch()
+    dev = A.bm_begin.device
+    n_slots = ctypes.c_uint64()
+    st = lib().rg_dispatch_sample(ctx.h, ctypes.byref(A.c), ctypes.byref(B.c), _ptr(ia), _ptr(ib), int(ia.numel()),
+                                  VARIANTS["generic"], None, None, None, 0, ctypes.byref(n_slots), _stream(stream))
+    if st != RG_ECAPACITY:
+        ctx.check(st)
+    n = max(int(n_slots.value), 1)
+    x = torch.zeros((n, 12), dtype=torch.float32, device=dev)
+    t = torch.zeros((n, 6), dtype=torch.float32, device=dev)
+    m = torch.zeros((n, 6), dtype=torch.uint8, device=dev)
+    for name in ("generic", "merge", "gallop", "probe", "runmerge", "thread"):
+        ctx.check(lib().rg_dispatch_sample(ctx.h, ctypes.byref(A.c), ctypes.byref(B.c), _ptr(ia), _ptr(ib),
+                                           int(ia.numel()), VARIANTS[name], _ptr(x), _ptr(t), _ptr(m), n,
+                                           ctypes.byref(n_slots), _stream(stream)))
+    return x, t, m
+
+
+def dispatch_train(ctx: Context, x, t, m, epochs=20, batch=4096, lr=1e-3, seed=1, params=None, stream=None):
+    """Trains (initialises when seed != 0); returns (params, per-epoch loss)."""
+    torch = _torch()
+    if params is None:
+        params = torch.zeros(RG_MLP_PARAMS, dtype=torch.float32, device=x.device)
+    losses = torch.zeros(max(epochs, 1), dtype=torch.float32, device=x.device)
+    ctx.check(lib().rg_dispatch_train(ctx.h, _ptr(x), _ptr(t), _ptr(m), x.shape[0], epochs, batch, lr, seed,
+                                      _ptr(params), _ptr(losses), _stream(stream)))
+    return params, losses[:epochs]
+
+
+def dispatch_set_mlp(ctx: Context, params, stream=None):
+    ctx.check(lib().rg_dispatch_set_mlp(ctx.h, _ptr(params), _stream(stream)))
+
+
+def dispatch_table(ctx: Context):
+    table = np.zeros(RG_MLP_TABLE, dtype=np.uint8)
+    ctx.check(lib().rg_dispatch_table(ctx.h, table.ctypes.data, table.size))
+    return table

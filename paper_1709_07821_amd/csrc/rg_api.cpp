@@ -59,6 +59,9 @@ rg_status drain_profile(rg_ctx* c) {
 constexpr size_t SLOT_BYTES = sizeof(Task) + 4 /*ub*/ + 8 /*slot_off*/ + 4 /*res_card*/ + 1 /*res_type*/ +
                               4 /*res_size*/ + 4 /*flags*/ + 8 /*out_idx*/ + 4 /*bin list*/ + 4 /*redo*/;
 
+}  // namespace
+
+// one batched call (also used by the dispatcher's cost sampling)
 rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const uint32_t* d_ia,
                     const uint32_t* d_ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs, uint32_t flags, rg_out* out,
                     uint64_t* d_cards, double* d_jacc, hipStream_t st) {
@@ -73,10 +76,6 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
     if (mat && (!out || !out->bm_begin || !out->keys || !out->types || !out->card || !out->size || !out->off ||
                 !out->payload || !out->bm_card))
         return fail(c, RG_EINVAL, "materialisation needs a complete rg_out");
-    if (mat && op != RG_AND)
-        return fail(c, RG_ENOTSUP,
-                    "materialised OR/XOR/ANDNOT are switched off: their first GPU run ended in a memory fault "
-                    "whose cause is not yet shown; the count-only forms of every operation are available");
     if (n_pairs > 0xFFFFFFFFull) return fail(c, RG_EINVAL, "at most 2^32-1 pairs per call");
     if ((d_ia == nullptr) != (d_ib == nullptr)) return fail(c, RG_EINVAL, "d_ia and d_ib go together");
     HIPCHK(c, hipSetDevice(c->device));
@@ -161,8 +160,12 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
     P_max = std::max(P_max, n_pairs - wstart.back());
     wstart.push_back(n_pairs);
 
+    // materialised OR / XOR / ANDNOT run through the k-way path (two bitmaps
+    // per query): key set per pair, then one workgroup per result key
+    const bool kw = mat && op != RG_AND;
     size_t wneed = S_max * SLOT_BYTES + 16 * 256 + align256(8 * (P_max + 1)) +
-                   align256(8 * scan_partials_needed(S_max));
+                   align256(8 * scan_partials_needed(S_max)) +
+                   (kw ? align256(sizeof(KwQuery) * P_max) + align256(8 * P_max) + 512 : 0);
     if (rg_status s = grow_device(c, &c->ws_wave, &c->ws_wave_bytes, wneed)) return s;
     Bump wb{(uint8_t*)c->ws_wave};
     Task* tasks = wb.take<Task>(S_max);
@@ -177,6 +180,8 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
     uint32_t* redo_list = wb.take<uint32_t>(S_max);
     uint64_t* cand_off = wb.take<uint64_t>(P_max + 1);
     uint64_t* partials = wb.take<uint64_t>(scan_partials_needed(S_max));
+    KwQuery* kw_queries = kw ? wb.take<KwQuery>(P_max) : nullptr;
+    uint32_t* kw_ids = kw ? wb.take<uint32_t>(2 * P_max) : nullptr;
 
     uint64_t out_base = 0, pay_base = 0;
     const size_t nw = wstart.size() - 1;
@@ -195,85 +200,113 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
             }
             continue;
         }
-        if (mat && (op == RG_OR || op == RG_XOR)) {
-            launch_fill_u32(reinterpret_cast<uint32_t*>(tasks), 0, 4 * C, st);
-            launch_fill_u32(res_card, 0, C, st);
-            launch_fill_u32(ub, 0, C, st);
-        }
-        launch_fill_u32(bin_count, 0, NBINS, st);
-        MatchArgs m;
-        m.op = kop;
-        m.materialize = mat;
-        m.A = pa;
-        m.B = pb;
-        m.ia = d_ia;
-        m.ib = d_ib;
-        m.ia0 = ia0;
-        m.ib0 = ib0;
-        m.pair0 = p0;
-        m.n_pairs = np;
-        m.cand_off = cand_off;
-        m.n_cand = C;
-        m.tasks = tasks;
-        m.ub = ub;
-        m.res_card = res_card;
-        m.bin_count = bin_count;
-        m.dispatch_mode = c->dispatch_mode;
-        m.fixed_bin = c->fixed_bin;
-        m.gallop_ratio = c->gallop_ratio;
-        m.thread_max = c->thread_max;
-        launch_match(m, st);
-        if (mat) launch_scan_u32_u64(ub, slot_off, C, pay_base, partials, totals, st);
-        HIPCHK(c, hipMemcpyAsync(h_small, bin_count, 4 * NBINS, hipMemcpyDeviceToHost, st));
-        if (mat) HIPCHK(c, hipMemcpyAsync(h_small + 64, totals, 8, hipMemcpyDeviceToHost, st));
-        HIPCHK(c, hipStreamSynchronize(st));
-        uint32_t cnt[NBINS], boff[NBINS];
-        uint32_t run = 0;
-        for (int b = 0; b < NBINS; ++b) {
-            cnt[b] = h_small[b];
-            boff[b] = run;
-            run += cnt[b];
-        }
-        const uint64_t pay_end = mat ? *reinterpret_cast<uint64_t*>(h_small + 64) : 0;
-        memcpy(h_small + 128, boff, sizeof(boff));
-        HIPCHK(c, hipMemcpyAsync(bin_cursor, h_small + 128, sizeof(boff), hipMemcpyHostToDevice, st));
-        launch_bin_scatter(tasks, C, bin_cursor, bin_lists, st);
-        launch_fill_u32(redo_count, 0, 1, st);
+        uint64_t pay_end = 0;
+        if (kw) {
+            launch_kw_pair_queries(op, d_ia, d_ib, ia0, ib0, p0, np, cand_off, kw_queries, kw_ids, st);
+            KwArgs ka;
+            ka.P0 = pa;
+            ka.P1 = pb;
+            ka.pair_base = (uint32_t)p0;
+            ka.queries = kw_queries;
+            ka.n_queries = np;
+            ka.ids = kw_ids;
+            ka.tasks = tasks;
+            ka.n_slots = C;
+            ka.ub = ub;
+            ka.res_card = res_card;
+            ka.so = SlotOut{slot_off, out->payload, res_card, res_type, res_size, nullptr, nullptr};
+            ka.acc = nullptr;
+            ka.err = d_err;
+            launch_kw_keys(ka, st);
+            launch_kw_bounds(ka, st);
+            launch_scan_u32_u64(ub, slot_off, C, pay_base, partials, totals, st);
+            timed(c, BIN_GEN, true, C, st, [&] { launch_kw_eval(ka, st); });
+        } else {
+            launch_fill_u32(bin_count, 0, NBINS, st);
+            MatchArgs m;
+            m.op = kop;
+            m.materialize = mat;
+            m.A = pa;
+            m.B = pb;
+            m.ia = d_ia;
+            m.ib = d_ib;
+            m.ia0 = ia0;
+            m.ib0 = ib0;
+            m.pair0 = p0;
+            m.n_pairs = np;
+            m.cand_off = cand_off;
+            m.n_cand = C;
+            m.tasks = tasks;
+            m.ub = ub;
+            m.res_card = res_card;
+            m.bin_count = bin_count;
+            m.dispatch_mode = c->dispatch_mode;
+            m.fixed_bin = c->fixed_bin;
+            m.gallop_ratio = c->gallop_ratio;
+            m.thread_max = c->thread_max;
+            m.mlp_table = c->mlp_table;
+            launch_match(m, st);
+            if (mat) launch_scan_u32_u64(ub, slot_off, C, pay_base, partials, totals, st);
+            HIPCHK(c, hipMemcpyAsync(h_small, bin_count, 4 * NBINS, hipMemcpyDeviceToHost, st));
+            if (mat) HIPCHK(c, hipMemcpyAsync(h_small + 64, totals, 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            uint32_t cnt[NBINS], boff[NBINS];
+            uint32_t run = 0;
+            for (int b = 0; b < NBINS; ++b) {
+                cnt[b] = h_small[b];
+                boff[b] = run;
+                run += cnt[b];
+            }
+            pay_end = mat ? *reinterpret_cast<uint64_t*>(h_small + 64) : 0;
+            memcpy(h_small + 128, boff, sizeof(boff));
+            HIPCHK(c, hipMemcpyAsync(bin_cursor, h_small + 128, sizeof(boff), hipMemcpyHostToDevice, st));
+            launch_bin_scatter(tasks, C, bin_cursor, bin_lists, st);
+            launch_fill_u32(redo_count, 0, 1, st);
 
-        ComputeArgs ca;
-        ca.op = kop;
-        ca.materialize = mat;
-        ca.A = pa;
-        ca.B = pb;
-        ca.tasks = tasks;
-        ca.n_dev = nullptr;
-        ca.acc = acc;
-        ca.pair0 = p0;
-        ca.so = SlotOut{slot_off, mat ? out->payload : nullptr, res_card, res_type, res_size, redo_list, redo_count};
-        for (int b = 0; b < NBINS; ++b) {
-            if (!cnt[b]) continue;
-            ca.list = bin_lists + boff[b];
-            ca.n = cnt[b];
-            timed(c, b, mat, cnt[b], st, [&] {
-                switch (b) {
-                case BIN_BB: launch_bb(ca, st); break;
-                case BIN_COPY: launch_copy(ca, st); break;
-                case BIN_AA: launch_aa(ca, st); break;
-                case BIN_GALLOP: launch_gallop(ca, st); break;
-                case BIN_AB: launch_ab(ca, st); break;
-                case BIN_RR: launch_rr(ca, st); break;
-                case BIN_THREAD: launch_thread(ca, st); break;
-                default: launch_generic(ca, st); break;
+            ComputeArgs ca;
+            ca.cost = nullptr;
+            if (c->cost_out) {  // dispatcher training: per-slot costs of a single wave
+                if (nw != 1) return fail(c, RG_EINVAL, "cost sampling needs all pairs in one wave");
+                c->cost_slots = C;
+                c->cost_tasks = tasks;
+                if (C <= c->cost_cap) {
+                    launch_fill_u32(reinterpret_cast<uint32_t*>(c->cost_out), 0, C, st);
+                    ca.cost = c->cost_out;
                 }
-            });
-        }
-        if (mat && cnt[BIN_BB]) {
-            // bitset pairs whose result is an array or run container
-            ComputeArgs rd = ca;
-            rd.list = redo_list;
-            rd.n = std::min<uint32_t>(cnt[BIN_BB], 4096u);
-            rd.n_dev = redo_count;
-            timed(c, NBINS - 1, mat, 0, st, [&] { launch_generic(rd, st); });
+            }
+            ca.op = kop;
+            ca.materialize = mat;
+            ca.A = pa;
+            ca.B = pb;
+            ca.tasks = tasks;
+            ca.n_dev = nullptr;
+            ca.acc = acc;
+            ca.pair0 = p0;
+            ca.so = SlotOut{slot_off, mat ? out->payload : nullptr, res_card, res_type, res_size, redo_list, redo_count};
+            for (int b = 0; b < NBINS; ++b) {
+                if (!cnt[b]) continue;
+                ca.list = bin_lists + boff[b];
+                ca.n = cnt[b];
+                timed(c, b, mat, cnt[b], st, [&] {
+                    switch (b) {
+                    case BIN_BB: launch_bb(ca, st); break;
+                    case BIN_AA: launch_aa(ca, st); break;
+                    case BIN_GALLOP: launch_gallop(ca, st); break;
+                    case BIN_AB: launch_ab(ca, st); break;
+                    case BIN_RR: launch_rr(ca, st); break;
+                    case BIN_THREAD: launch_thread(ca, st); break;
+                    default: launch_generic(ca, st); break;
+                    }
+                });
+            }
+            if (mat && cnt[BIN_BB]) {
+                // bitset pairs whose result is an array or run container
+                ComputeArgs rd = ca;
+                rd.list = redo_list;
+                rd.n = std::min<uint32_t>(cnt[BIN_BB], 4096u);
+                rd.n_dev = redo_count;
+                timed(c, NBINS - 1, mat, 0, st, [&] { launch_generic(rd, st); });
+            }
         }
         HIPCHK(c, hipGetLastError());
         if (mat) {
@@ -298,9 +331,14 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
             launch_compact(cp, st);
             launch_bm_begin(cand_off, out_idx, C, totals + 1, np, p0, out->bm_begin, last, st);
             HIPCHK(c, hipMemcpyAsync(h_small + 66, totals + 1, 8, hipMemcpyDeviceToHost, st));
+            if (kw) {
+                HIPCHK(c, hipMemcpyAsync(h_small + 64, totals, 8, hipMemcpyDeviceToHost, st));
+                HIPCHK(c, hipMemcpyAsync(h_small + 68, d_err, 4, hipMemcpyDeviceToHost, st));
+            }
             HIPCHK(c, hipStreamSynchronize(st));
             out_base = *reinterpret_cast<uint64_t*>(h_small + 66);
-            pay_base = pay_end;
+            pay_base = kw ? *reinterpret_cast<uint64_t*>(h_small + 64) : pay_end;
+            if (kw && h_small[68]) return fail(c, RG_EDEVICE, "result key set exceeded its bound (internal error)");
         }
     }
     if (mat) {
@@ -327,7 +365,6 @@ rg_status single(rg_ctx* c, int op, const rg_pool* A, uint32_t ia, const rg_pool
     return run_batch(c, op, A, B, nullptr, nullptr, ia, ib, 1, flags, out, d_card, d_j, (hipStream_t)stream);
 }
 
-}  // namespace
 
 extern "C" {
 
@@ -355,6 +392,7 @@ void rg_destroy(rg_ctx* c) {
     if (c->ws_wave) (void)hipFree(c->ws_wave);
     if (c->small) (void)hipFree(c->small);
     if (c->host) (void)hipHostFree(c->host);
+    if (c->mlp_table) (void)hipFree(c->mlp_table);
     for (auto& p : c->pend) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
@@ -399,6 +437,11 @@ rg_status rg_profile_read(rg_ctx* c, int variant, int materialize, double* total
 rg_status rg_set_dispatch(rg_ctx* c, int mode, int variant) {
     if (!c) return RG_EINVAL;
     if (mode == RG_DISPATCH_HEURISTIC) {
+        c->dispatch_mode = mode;
+        return RG_OK;
+    }
+    if (mode == RG_DISPATCH_MLP) {
+        if (!c->mlp_table) return fail(c, RG_EINVAL, "no network installed (rg_dispatch_set_mlp)");
         c->dispatch_mode = mode;
         return RG_OK;
     }
@@ -576,6 +619,7 @@ void plan_enqueue(rg_plan* p, hipStream_t st) {
         m.fixed_bin = p->fixed_bin;
         m.gallop_ratio = p->gallop_ratio;
         m.thread_max = p->thread_max;
+        m.mlp_table = p->ctx->mlp_table;
         launch_match(m, st);
         launch_bin_info(p->bin_count, p->bin_info, p->cursor, p->next, st);
         launch_bin_scatter(p->tasks, w.C, p->cursor, p->lists, st);

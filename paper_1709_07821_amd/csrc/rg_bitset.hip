@@ -90,55 +90,11 @@ __global__ void __launch_bounds__(256) k_bb(ComputeArgs a) {
 void launch_bb(const ComputeArgs& a, hipStream_t st) {
     if (!a.n) return;
     const dim3 grid((a.n + 3) / 4);
-    // count-only calls accumulate the intersection for every operation
-    if (!a.materialize) {
-        hipLaunchKernelGGL((k_bb<RG_AND, false>), grid, dim3(256), 0, st, a);
-        return;
-    }
-    switch (a.op) {
-    case RG_AND: hipLaunchKernelGGL((k_bb<RG_AND, true>), grid, dim3(256), 0, st, a); break;
-    case RG_OR: hipLaunchKernelGGL((k_bb<RG_OR, true>), grid, dim3(256), 0, st, a); break;
-    case RG_XOR: hipLaunchKernelGGL((k_bb<RG_XOR, true>), grid, dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_bb<RG_ANDNOT, true>), grid, dim3(256), 0, st, a); break;
-    }
-}
-
-// ------------------------------------------------------------------ copy
-// One-sided container (union/xor: present in one input only; difference:
-// present in A only): copied through unchanged, already in P1 form.
-__global__ void __launch_bounds__(256) k_copy(ComputeArgs a) {
-    const uint32_t lane = lane_id();
-    const uint32_t w = wave_index();
-    if (w >= a.n) return;
-    const uint32_t slot = uniform(a.list[w]);
-    const Task t = uniform_task(a.tasks, slot);
-    const bool fromA = t.kind == KIND_COPY_A;
-    const uint32_t idx = fromA ? t.ia : t.ib;
-    const uint8_t* types = fromA ? a.A.types : a.B.types;
-    const uint32_t* sizes = fromA ? a.A.size : a.B.size;
-    const uint32_t* cards = fromA ? a.A.card : a.B.card;
-    const uint64_t* offs = fromA ? a.A.off : a.B.off;
-    const uint8_t* payload = fromA ? a.A.payload : a.B.payload;
-    const uint8_t type = (uint8_t)uniform(types[idx]);
-    const uint32_t size = uniform(sizes[idx]);
-    const uint32_t card = uniform(cards[idx]);
-    // the slot holds wbytes_of(card) bytes; a canonical container always fits
-    uint32_t n16 = round16(payload_bytes_of(type, size)) >> 4;
-    const uint32_t cap16 = wbytes_of(card) >> 4;
-    if (n16 > cap16) n16 = cap16;
-    const u32x4* src = reinterpret_cast<const u32x4*>(payload + uniform64(offs[idx]));
-    u32x4* dst = reinterpret_cast<u32x4*>(a.so.payload + a.so.slot_off[slot]);
-    for (uint32_t i = lane; i < n16; i += 64) dst[i] = src[i];
-    if (lane == 0) {
-        a.so.res_card[slot] = card;
-        a.so.res_type[slot] = type;
-        a.so.res_size[slot] = size;
-    }
-}
-
-void launch_copy(const ComputeArgs& a, hipStream_t st) {
-    if (!a.n) return;
-    hipLaunchKernelGGL(k_copy, dim3((a.n + 3) / 4), dim3(256), 0, st, a);
+    // count-only calls accumulate the intersection for every operation; the
+    // binned path materialises intersections only (the other operations go
+    // through the k-way path)
+    if (!a.materialize) hipLaunchKernelGGL((k_bb<RG_AND, false>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_bb<RG_AND, true>), grid, dim3(256), 0, st, a);
 }
 
 }  // namespace rg

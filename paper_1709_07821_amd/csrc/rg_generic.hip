@@ -18,6 +18,7 @@ __global__ void __launch_bounds__(256) k_generic(ComputeArgs a) {
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
         const uint32_t slot = uniform(a.list[i]);
         const Task t = uniform_task(a.tasks, slot);
+        const uint64_t t0 = (!MAT && a.cost) ? __builtin_amdgcn_s_memtime() : 0;
         expand_container(sh.sa, a.A, t.ia, sh);
         expand_container(sh.sb, a.B, t.ib, sh);
         uint64_t w[4];
@@ -28,14 +29,10 @@ __global__ void __launch_bounds__(256) k_generic(ComputeArgs a) {
         } else {
             const uint32_t c = count_words(w, sh);
             if (threadIdx.x == 0) acc_add(a.acc, t.pair, (long long)c);
+            if (a.cost && threadIdx.x == 0) a.cost[slot] = 4.f * (float)(__builtin_amdgcn_s_memtime() - t0);
         }
         __syncthreads();
     }
-}
-
-template <int OP>
-static void launch_gen_mat(const ComputeArgs& a, uint32_t grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_generic<OP, true>), dim3(grid), dim3(256), 0, st, a);
 }
 
 void launch_generic(const ComputeArgs& a, hipStream_t st) {
@@ -43,17 +40,10 @@ void launch_generic(const ComputeArgs& a, hipStream_t st) {
     if (a.n_dev) grid = a.n;  // caller passes the maximum possible count as n
     if (!grid) return;
     if (grid > 65536u) grid = 65536u;
-    // count-only calls accumulate the intersection for every operation
-    if (!a.materialize) {
-        hipLaunchKernelGGL((k_generic<RG_AND, false>), dim3(grid), dim3(256), 0, st, a);
-        return;
-    }
-    switch (a.op) {
-    case RG_AND: launch_gen_mat<RG_AND>(a, grid, st); break;
-    case RG_OR: launch_gen_mat<RG_OR>(a, grid, st); break;
-    case RG_XOR: launch_gen_mat<RG_XOR>(a, grid, st); break;
-    default: launch_gen_mat<RG_ANDNOT>(a, grid, st); break;
-    }
+    // count-only calls accumulate the intersection for every operation; the
+    // binned path materialises intersections only
+    if (!a.materialize) hipLaunchKernelGGL((k_generic<RG_AND, false>), dim3(grid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_generic<RG_AND, true>), dim3(grid), dim3(256), 0, st, a);
 }
 
 }  // namespace rg

@@ -39,6 +39,12 @@ struct rg_ctx {
     uint32_t gallop_ratio = 64;
     uint32_t thread_max = 8;
     uint64_t max_wave_slots = 1ull << 24;
+    uint8_t* mlp_table = nullptr;      // learned dispatch table (device, MLP_TABLE bytes)
+    // dispatcher training: when cost_out is set, the count kernels record per-slot costs
+    float* cost_out = nullptr;
+    uint64_t cost_cap = 0;
+    uint64_t cost_slots = 0;
+    const Task* cost_tasks = nullptr;
 };
 
 

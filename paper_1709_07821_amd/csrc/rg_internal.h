@@ -17,12 +17,12 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // What one slot of the work space does. Slots are laid out per pair in key
 // order of the result, so compaction of non-empty slots yields the result
 // containers in ascending key order.
-enum : uint8_t { KIND_NOOP = 0, KIND_MATCH = 1, KIND_COPY_A = 2, KIND_COPY_B = 3 };
+enum : uint8_t { KIND_NOOP = 0, KIND_MATCH = 1 };
 
 // Kernel classes (bins). Variant selection decides the bin of every slot.
 enum : uint8_t {
     BIN_BB = 0,     // bitset op bitset: one wave per pair, words in registers
-    BIN_COPY = 1,   // one-sided container copied through unchanged
+    BIN_UNUSED = 1, // (no kernel class; keeps the variant numbers of the C ABI)
     BIN_GEN = 2,    // any pair: expand both sides into LDS bitsets, op, finalize
     BIN_AA = 3,     // array op array: LDS merge
     BIN_GALLOP = 4, // array op array, very unequal sizes: galloping search
@@ -195,10 +195,11 @@ struct MatchArgs {
     uint32_t* ub;             // [n_cand] slot payload bound in bytes (materialize)
     uint32_t* res_card;       // [n_cand]
     uint32_t* bin_count;      // [NBINS]
-    int dispatch_mode;        // 0 heuristic, 2 fixed
+    int dispatch_mode;        // 0 heuristic, 1 learned (mlp_table), 2 fixed
     int fixed_bin;
     uint32_t gallop_ratio;
     uint32_t thread_max;  // largest array side handled one thread per pair
+    const uint8_t* mlp_table;  // learned dispatch: bin per quantised feature cell (mode 1)
 };
 
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st);
@@ -225,11 +226,11 @@ struct ComputeArgs {
     long long* acc;           // count mode: per-pair (wave-local) accumulators
     uint64_t pair0;
     SlotOut so;
+    float* cost;              // if non-null: per-slot cost in wave-cycles (training samples)
 };
 
 void launch_bb(const ComputeArgs& a, hipStream_t st);
 void launch_generic(const ComputeArgs& a, hipStream_t st);
-void launch_copy(const ComputeArgs& a, hipStream_t st);
 void launch_aa(const ComputeArgs& a, hipStream_t st);
 void launch_gallop(const ComputeArgs& a, hipStream_t st);
 void launch_ab(const ComputeArgs& a, hipStream_t st);
@@ -280,11 +281,39 @@ void launch_bin_info(const uint32_t* bin_count, uint32_t* bin_info, uint32_t* cu
                      hipStream_t st);
 void launch_persist(const PersistArgs& a, uint32_t grid, hipStream_t st);
 
+// learned dispatcher (rg_mlp.hip)
+constexpr int MLP_IN = 12, MLP_H = 64, MLP_OUT = 6;
+constexpr int MLP_PARAMS = MLP_IN * MLP_H + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H * MLP_OUT + MLP_OUT;
+constexpr uint32_t MLP_TABLE = 3 * 3 * 17 * 17 * 12 * 12;  // type_a, type_b, log2 c_a, c_b, log2 r_a, r_b
+__host__ __device__ __forceinline__ uint32_t mlp_cell(uint8_t ta, uint8_t tb, uint32_t ca, uint32_t cb, uint32_t ra,
+                                                      uint32_t rb) {
+    auto q = [](uint32_t c, uint32_t hi) {
+        const uint32_t l = 31u - (uint32_t)__builtin_clz(c + 1u);  // floor(log2(1 + c))
+        return l < hi ? l : hi;
+    };
+    const uint32_t qra = ta == RG_RUN ? q(ra, 11) : 0u, qrb = tb == RG_RUN ? q(rb, 11) : 0u;
+    return ((((uint32_t)(ta - 1) * 3 + (uint32_t)(tb - 1)) * 17 + q(ca, 16)) * 17 + q(cb, 16)) * 144 + qra * 12 + qrb;
+}
+void launch_mlp_forward(const float* P, const float* X, uint64_t n, float* Y, hipStream_t st);
+uint32_t mlp_grad_blocks(uint64_t n);
+// d_inv: device scratch float (1 / unmasked count, computed here)
+void launch_mlp_grad(const float* P, const float* X, const float* T, const uint8_t* M, uint64_t n, float* d_inv,
+                     float* partial, float* partial_loss, float* grad, float* loss, hipStream_t st);
+void launch_mlp_adam(float* P, const float* G, float* m, float* v, float lr, float b1, float b2, float eps, float c1,
+                     float c2, hipStream_t st);
+// training rows: features, and target column `col` from the measured costs
+void launch_slot_features(const Task* tasks, uint64_t n, PoolView A, PoolView B, int want_bin, const float* cost,
+                          int col, float* F, float* T, uint8_t* M, hipStream_t st);
+void launch_gather_rows(const float* X, const float* T, const uint8_t* M, const uint32_t* idx, uint64_t b0,
+                        uint32_t nb, float* Xb, float* Tb, uint8_t* Mb, hipStream_t st);
+void launch_accum_scaled(const float* x, float* acc, float scale, hipStream_t st);
+void launch_mlp_table(const float* P, uint8_t* table, hipStream_t st);
+
 // k-way queries over one pool (rg_kway.hip)
 constexpr uint32_t KW_MATERIALIZE = 1u;  // KwQuery.flags: build the result containers
 constexpr uint32_t KW_MAX_K = 256;       // bitmaps per query (one lookup thread each)
 struct KwQuery {
-    uint32_t op;       // RG_AND or RG_OR
+    uint32_t op;       // RG_AND, RG_OR, RG_XOR (fold of k) or RG_ANDNOT (first minus the others)
     uint32_t k;        // number of bitmaps, 1..KW_MAX_K
     uint32_t ids_off;  // first of the query's bitmap ids in KwArgs.ids
     uint32_t flags;    // KW_MATERIALIZE or 0 (count only)
@@ -294,7 +323,9 @@ struct KwQuery {
 };
 static_assert(sizeof(KwQuery) == 32, "query record is 32 bytes");
 struct KwArgs {
-    PoolView P;
+    PoolView P0;        // pool of each query's first bitmap
+    PoolView P1;        // pool of its other bitmaps (the same pool for k-way queries)
+    uint32_t pair_base; // Task.pair = pair_base + query index (output bitmap index)
     const KwQuery* queries;
     uint32_t n_queries;
     const uint32_t* ids;
@@ -310,6 +341,10 @@ void launch_kw_keys(const KwArgs& a, hipStream_t st);
 void launch_kw_bounds(const KwArgs& a, hipStream_t st);
 void launch_kw_eval(const KwArgs& a, hipStream_t st);
 void launch_kw_cards(const KwArgs& a, const uint64_t* bm_card, uint64_t* cards, hipStream_t st);
+// queries q < n_pairs for pairs pair0 + q (k = 2: A side, B side), slot ranges from cand_off
+void launch_kw_pair_queries(int op, const uint32_t* ia, const uint32_t* ib, uint32_t ia0, uint32_t ib0,
+                            uint64_t pair0, uint32_t n_pairs, const uint64_t* cand_off, KwQuery* queries,
+                            uint32_t* ids, hipStream_t st);
 // out[3j..3j+2] = key count, payload bound, 1 (0, 0, 0 for an id outside the pool)
 void launch_kw_gather_meta(const uint64_t* bm_begin, const uint64_t* bm_wbytes, uint32_t n_bitmaps,
                            const uint32_t* ids, uint32_t k, uint64_t* out, hipStream_t st);

@@ -22,15 +22,32 @@
 
 namespace rg {
 
-__device__ __forceinline__ uint32_t kw_find_key(const PoolView& P, uint32_t b, uint16_t key) {
-    const uint64_t s = P.bm_begin[b], e = P.bm_begin[b + 1];
+__device__ __forceinline__ uint32_t kw_find_key(const uint64_t* bm_begin, const uint16_t* keys, uint32_t b,
+                                                uint16_t key) {
+    const uint64_t s = bm_begin[b], e = bm_begin[b + 1];
     uint64_t lo = s, hi = e;
     while (lo < hi) {
         const uint64_t mid = (lo + hi) >> 1;
-        if (P.keys[mid] < key) lo = mid + 1;
+        if (keys[mid] < key) lo = mid + 1;
         else hi = mid;
     }
-    return (lo < e && P.keys[lo] == key) ? (uint32_t)lo : NONE;
+    return (lo < e && keys[lo] == key) ? (uint32_t)lo : NONE;
+}
+
+// The pool of a query's j-th bitmap, selected field by field (plain pointer
+// selects; no address arithmetic on the kernel-argument block).
+__device__ __forceinline__ PoolView kw_side(const KwArgs& a, bool second) {
+    PoolView v;
+    v.bm_begin = second ? a.P1.bm_begin : a.P0.bm_begin;
+    v.keys = second ? a.P1.keys : a.P0.keys;
+    v.types = second ? a.P1.types : a.P0.types;
+    v.card = second ? a.P1.card : a.P0.card;
+    v.size = second ? a.P1.size : a.P0.size;
+    v.off = second ? a.P1.off : a.P0.off;
+    v.payload = second ? a.P1.payload : a.P0.payload;
+    v.bm_card = second ? a.P1.bm_card : a.P0.bm_card;
+    v.bm_wbytes = second ? a.P1.bm_wbytes : a.P0.bm_wbytes;
+    return v;
 }
 
 // ---------------------------------------------------------------- 1. keys
@@ -46,13 +63,17 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a) {
     const uint32_t tid = threadIdx.x;
     for (uint32_t i = tid; i < 1024; i += 256) acc[i] = 0;
     __syncthreads();
-    for (uint32_t j = 0; j < k; ++j) {
+    // result keys: AND - in every bitmap; OR, XOR - in any; ANDNOT - the first bitmap's
+    const uint32_t kk = op == RG_ANDNOT ? 1u : k;
+    for (uint32_t j = 0; j < kk; ++j) {
+        const uint64_t* bmb = j ? a.P1.bm_begin : a.P0.bm_begin;
+        const uint16_t* pkeys = j ? a.P1.keys : a.P0.keys;
         const uint32_t b = uniform(a.ids[ids0 + j]);
-        const uint64_t s = uniform64(a.P.bm_begin[b]);
-        const uint32_t n = (uint32_t)(uniform64(a.P.bm_begin[b + 1]) - s);
-        if (op == RG_OR || j == 0) {
+        const uint64_t s = uniform64(bmb[b]);
+        const uint32_t n = (uint32_t)(uniform64(bmb[b + 1]) - s);
+        if (op != RG_AND || j == 0) {
             for (uint32_t i = tid; i < n; i += 256) {
-                const uint32_t key = a.P.keys[s + i];
+                const uint32_t key = pkeys[s + i];
                 atomicOr(reinterpret_cast<unsigned long long*>(&acc[key >> 6]), 1ull << (key & 63));
             }
             __syncthreads();
@@ -60,7 +81,7 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a) {
             for (uint32_t i = tid; i < 1024; i += 256) cur[i] = 0;
             __syncthreads();
             for (uint32_t i = tid; i < n; i += 256) {
-                const uint32_t key = a.P.keys[s + i];
+                const uint32_t key = pkeys[s + i];
                 atomicOr(reinterpret_cast<unsigned long long*>(&cur[key >> 6]), 1ull << (key & 63));
             }
             __syncthreads();
@@ -87,7 +108,7 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a) {
             x &= x - 1;
             if (pos < kbound) {
                 Task t;
-                t.pair = q;
+                t.pair = a.pair_base + q;
                 t.ia = NONE;
                 t.ib = NONE;
                 t.key = (uint16_t)key;
@@ -101,7 +122,7 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a) {
     const uint32_t used = total < kbound ? total : kbound;
     for (uint32_t i = used + tid; i < kbound; i += 256) {
         Task t;
-        t.pair = q;
+        t.pair = a.pair_base + q;
         t.ia = NONE;
         t.ib = NONE;
         t.key = 0;
@@ -119,17 +140,20 @@ __global__ void __launch_bounds__(256) k_kw_bounds(KwArgs a) {
     const Task t = a.tasks[s];
     uint32_t ub = 0;
     if (t.kind == KIND_MATCH) {
-        const KwQuery Q = a.queries[t.pair];
+        const KwQuery Q = a.queries[t.pair - a.pair_base];
         if (Q.flags & KW_MATERIALIZE) {
+            // AND: the smallest container; OR, XOR: the sum; ANDNOT: the first
             uint64_t sum = 0;
-            uint32_t mn = 0xFFFFFFFFu;
+            uint32_t mn = 0xFFFFFFFFu, first = 0;
             for (uint32_t j = 0; j < Q.k; ++j) {
-                const uint32_t ci = kw_find_key(a.P, a.ids[Q.ids_off + j], t.key);
-                const uint32_t cj = ci == NONE ? 0u : a.P.card[ci];
+                const PoolView pv = kw_side(a, j != 0);
+                const uint32_t ci = kw_find_key(pv.bm_begin, pv.keys, a.ids[Q.ids_off + j], t.key);
+                const uint32_t cj = ci == NONE ? 0u : pv.card[ci];
+                if (j == 0) first = cj;
                 sum += cj;
                 if (cj < mn) mn = cj;
             }
-            const uint64_t bc = Q.op == RG_AND ? (uint64_t)mn : sum;
+            const uint64_t bc = Q.op == RG_AND ? (uint64_t)mn : Q.op == RG_ANDNOT ? (uint64_t)first : sum;
             ub = wbytes_of(bc);
         }
     }
@@ -145,11 +169,15 @@ __global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
     for (uint64_t s = blockIdx.x; s < a.n_slots; s += gridDim.x) {
         const Task t = uniform_task(a.tasks, (uint32_t)s);
         if (t.kind != KIND_MATCH) continue;
-        const uint32_t q = t.pair;
+        const uint32_t q = t.pair - a.pair_base;
         const KwQuery Q = a.queries[q];
         const uint32_t op = uniform(Q.op), k = uniform(Q.k), flags = uniform(Q.flags);
         const uint32_t ids0 = uniform(Q.ids_off);
-        if (tid < k) cidx[tid] = kw_find_key(a.P, a.ids[ids0 + tid], t.key);
+        if (tid < k) {
+            const uint64_t* bmb = tid ? a.P1.bm_begin : a.P0.bm_begin;
+            const uint16_t* pkeys = tid ? a.P1.keys : a.P0.keys;
+            cidx[tid] = kw_find_key(bmb, pkeys, a.ids[ids0 + tid], t.key);
+        }
         __syncthreads();
         // running result in sh.sa; each container is expanded into sh.sb
         bool empty = false;
@@ -157,20 +185,25 @@ __global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
         for (uint32_t j = 0; j < k && !empty; ++j) {
             const uint32_t ci = uniform(cidx[j]);
             if (ci == NONE) {
-                if (op == RG_AND) empty = true;  // cannot happen: the key is in every bitmap
+                // AND: cannot happen (the key is in every bitmap); ANDNOT: the
+                // first bitmap holds the key, a missing later one removes nothing
+                if (op == RG_AND) empty = true;
                 continue;
             }
-            expand_container(first ? sh.sa : sh.sb, a.P, ci, sh);
+            const PoolView pv = kw_side(a, j != 0);
+            expand_container(first ? sh.sa : sh.sb, pv, ci, sh);
             if (!first) {
                 uint32_t any = 0;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const uint32_t wi = 4 * tid + i;
-                    const uint64_t v = op == RG_AND ? (sh.sa[wi] & sh.sb[wi]) : (sh.sa[wi] | sh.sb[wi]);
+                    const uint64_t x = sh.sa[wi], y = sh.sb[wi];
+                    const uint64_t v = op == RG_AND ? (x & y) : op == RG_OR ? (x | y) : op == RG_XOR ? (x ^ y) : (x & ~y);
                     sh.sa[wi] = v;
                     any |= v != 0 ? 1u : 0u;
                 }
-                if (op == RG_AND) empty = block_sum_u64(any, sh.tmp64) == 0;
+                // AND and ANDNOT stay empty once empty
+                if (op == RG_AND || op == RG_ANDNOT) empty = block_sum_u64(any, sh.tmp64) == 0;
                 else __syncthreads();
             }
             first = false;
@@ -216,6 +249,34 @@ void launch_kw_cards(const KwArgs& a, const uint64_t* bm_card, uint64_t* cards, 
 }  // namespace rg
 
 namespace rg {
+
+// pairwise materialisation through the k-way path: query q is pair pair0 + q
+__global__ void k_kw_pair_queries(int op, const uint32_t* ia, const uint32_t* ib, uint32_t ia0, uint32_t ib0,
+                                  uint64_t pair0, uint32_t n_pairs, const uint64_t* cand_off, KwQuery* queries,
+                                  uint32_t* ids) {
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_pairs) return;
+    const uint64_t p = pair0 + q;
+    ids[2 * q] = ia ? ia[p] : ia0;
+    ids[2 * q + 1] = ib ? ib[p] : ib0;
+    KwQuery Q;
+    Q.op = (uint32_t)op;
+    Q.k = 2;
+    Q.ids_off = 2 * q;
+    Q.flags = KW_MATERIALIZE;
+    Q.slot0 = cand_off[q];
+    Q.kbound = (uint32_t)(cand_off[q + 1] - cand_off[q]);
+    Q.pad = 0;
+    queries[q] = Q;
+}
+
+void launch_kw_pair_queries(int op, const uint32_t* ia, const uint32_t* ib, uint32_t ia0, uint32_t ib0,
+                            uint64_t pair0, uint32_t n_pairs, const uint64_t* cand_off, KwQuery* queries,
+                            uint32_t* ids, hipStream_t st) {
+    if (n_pairs)
+        hipLaunchKernelGGL(k_kw_pair_queries, dim3((n_pairs + 255) / 256), dim3(256), 0, st, op, ia, ib, ia0, ib0,
+                           pair0, n_pairs, cand_off, queries, ids);
+}
 
 // per id: key count, payload bound (bm_wbytes), and validity, for host-side bounds
 __global__ void k_kw_gather_meta(const uint64_t* bm_begin, const uint64_t* bm_wbytes, uint32_t n_bitmaps,

@@ -135,12 +135,13 @@ __device__ __forceinline__ bool variant_applies(int bin, uint8_t ta, uint8_t tb)
 }
 
 __device__ __forceinline__ uint8_t classify(int op, bool materialize, uint8_t kind, uint8_t ta, uint8_t tb,
-                                            uint32_t ca, uint32_t cb, int mode, int fixed_bin,
-                                            uint32_t gallop_ratio, uint32_t thread_max) {
-    if (kind == KIND_COPY_A || kind == KIND_COPY_B) return BIN_COPY;
+                                            uint32_t ca, uint32_t cb, uint32_t ra, uint32_t rb, int mode,
+                                            int fixed_bin, uint32_t gallop_ratio, uint32_t thread_max,
+                                            const uint8_t* mlp_table) {
     if (ta == RG_BITSET && tb == RG_BITSET) return BIN_BB;
     if (materialize) return BIN_GEN;  // specialised variants are count-only
     if (mode == 2) return variant_applies(fixed_bin, ta, tb) ? (uint8_t)fixed_bin : (uint8_t)BIN_GEN;
+    if (mode == 1 && mlp_table) return mlp_table[mlp_cell(ta, tb, ca, cb, ra, rb)];  // learned
     // heuristic: a small array side is probed by one thread (each value
     // looked up in the other container); galloping when one array is much
     // smaller than the other (Section 2.2)
@@ -199,7 +200,9 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
                 }
             }
             slot = t;
-        } else if (u < KA) {
+        } else {
+            // materialised intersection: one slot per key of A, in A's key
+            // order (the other operations materialise through the k-way path)
             uint16_t key = m.A.keys[a0 + u];
             uint32_t j = lower_bound_u16(m.B.keys + b0, KB, key);
             bool hit = j < KB && m.B.keys[b0 + j] == key;
@@ -208,22 +211,8 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
             if (hit) {
                 task.kind = KIND_MATCH;
                 task.ib = (uint32_t)(b0 + j);
-            } else if (m.op != RG_AND) {
-                task.kind = KIND_COPY_A;
             }
-            uint64_t local = (m.op == RG_OR || m.op == RG_XOR) ? u + j : u;
-            slot = m.cand_off[pl] + local;
-        } else {
-            uint32_t v = (uint32_t)(u - KA);
-            uint16_t key = m.B.keys[b0 + v];
-            uint32_t i = lower_bound_u16(m.A.keys + a0, KA, key);
-            bool hit = i < KA && m.A.keys[a0 + i] == key;
-            if (!hit) {
-                task.key = key;
-                task.ib = (uint32_t)(b0 + v);
-                task.kind = KIND_COPY_B;
-                slot = m.cand_off[pl] + v + i;
-            }
+            slot = m.cand_off[pl] + u;
         }
         if (slot != NONE) {
             uint32_t ub = 0;
@@ -232,18 +221,13 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
                 uint8_t tb = task.ib != NONE ? m.B.types[task.ib] : 0;
                 uint32_t ca = task.ia != NONE ? m.A.card[task.ia] : 0;
                 uint32_t cb = task.ib != NONE ? m.B.card[task.ib] : 0;
-                task.bin = classify(m.op, m.materialize, task.kind, ta, tb, ca, cb, m.dispatch_mode, m.fixed_bin,
-                                    m.gallop_ratio, m.thread_max);
+                const bool need_r = m.dispatch_mode == 1;
+                uint32_t ra = need_r && ta == RG_RUN ? m.A.size[task.ia] : 0;
+                uint32_t rb = need_r && tb == RG_RUN ? m.B.size[task.ib] : 0;
+                task.bin = classify(m.op, m.materialize, task.kind, ta, tb, ca, cb, ra, rb, m.dispatch_mode,
+                                    m.fixed_bin, m.gallop_ratio, m.thread_max, m.mlp_table);
                 atomicAdd(&cnt[task.bin], 1u);
-                if (m.materialize) {
-                    uint64_t bc;
-                    if (task.kind == KIND_COPY_A) bc = ca;
-                    else if (task.kind == KIND_COPY_B) bc = cb;
-                    else if (m.op == RG_AND) bc = ca < cb ? ca : cb;
-                    else if (m.op == RG_ANDNOT) bc = ca;
-                    else bc = (uint64_t)ca + cb;
-                    ub = wbytes_of(bc);
-                }
+                if (m.materialize) ub = wbytes_of(ca < cb ? ca : cb);
             }
             m.tasks[slot] = task;
             m.res_card[slot] = 0;

@@ -4,8 +4,9 @@
 // on a stream without host synchronisation (rg_kway.hip kernels, then the
 // pairwise path's compaction and the per-bitmap fingerprint). The host sizes a
 // step from per-bitmap key counts and payload bounds alone:
-//   AND: at most min_i K_i result containers and min_i W_i payload bytes,
-//   OR:  at most min(65536, sum_i K_i) containers and sum_i W_i bytes,
+//   AND:     at most min_i K_i result containers and min_i W_i payload bytes,
+//   OR, XOR: at most min(65536, sum_i K_i) containers and sum_i W_i bytes,
+//   ANDNOT:  at most K_0 containers and W_0 bytes,
 // (W_i = sum over bitmap i's containers of min(8192, 2c), rounded to 16 B,
 // which bounds every container's P1 form), so a step never needs a readback
 // before its results.
@@ -54,6 +55,9 @@ Bounds query_bounds(int op, uint32_t k, const uint64_t* meta, bool mat) {
     if (op == RG_AND) {
         b.kbound = kmin;
         b.pbound = wmin;
+    } else if (op == RG_ANDNOT) {
+        b.kbound = meta[0];
+        b.pbound = meta[1];
     } else {
         b.kbound = std::min<uint64_t>(ksum, 65536);
         b.pbound = std::min<uint64_t>(wsum, 65536ull * 8192);
@@ -176,7 +180,9 @@ rg_status step_enqueue(rg_ctx* c, const rg_pool& pool, const StepLayout& L, uint
     launch_fill_u64(o.bm_card, 0, L.nq, st);
     launch_fill_u64(o.bm_wbytes, 0, L.nq, st);
     KwArgs a;
-    a.P = view(pool);
+    a.P0 = view(pool);
+    a.P1 = a.P0;
+    a.pair_base = 0;
     a.queries = queries;
     a.n_queries = L.nq;
     a.ids = ids;
@@ -241,7 +247,7 @@ void stage_upload(const StepLayout& L, uint8_t* h_stage, const std::vector<KwQue
 extern "C" rg_status roaring_multi(rg_ctx* c, int op, const rg_pool* pool, const uint32_t* d_ids, uint32_t k,
                                    uint32_t flags, rg_out* out, uint64_t* d_card, void* stream) {
     if (!c) return RG_EINVAL;
-    if (op != RG_AND && op != RG_OR) return fail(c, RG_EINVAL, "roaring_multi: op must be RG_AND or RG_OR");
+    if (op < RG_AND || op > RG_ANDNOT) return fail(c, RG_EINVAL, "roaring_multi: op must be RG_AND..RG_ANDNOT");
     if (k < 1 || k > KW_MAX_K || !d_ids) return fail(c, RG_EINVAL, "roaring_multi: 1 <= k <= 256 device ids");
     if (!pool_ok(pool)) return fail(c, RG_EINVAL, "incomplete pool (null pointer)");
     const bool mat = flags & RG_FLAG_MATERIALIZE;
@@ -415,7 +421,7 @@ struct rg_server {
 namespace {
 
 bool query_host_ok(const rg_server* s, const rg_query* q) {
-    if (!q || (q->op != RG_AND && q->op != RG_OR) || q->k < 1 || q->k > KW_MAX_K || !q->ids) return false;
+    if (!q || q->op < RG_AND || q->op > RG_ANDNOT || q->k < 1 || q->k > KW_MAX_K || !q->ids) return false;
     for (uint32_t j = 0; j < q->k; ++j)
         if (q->ids[j] >= s->pool.n_bitmaps) return false;
     return (q->flags & (RG_FLAG_MATERIALIZE | RG_FLAG_CARD)) != 0;

@@ -30,9 +30,12 @@ __global__ void __launch_bounds__(256) k_wave_count(ComputeArgs a) {
     const uint32_t lane = lane_id();
     const uint32_t w = wave_index();
     if (w >= a.n) return;
-    const Task t = uniform_task(a.tasks, uniform(a.list[w]));
+    const uint32_t slot = uniform(a.list[w]);
+    const Task t = uniform_task(a.tasks, slot);
+    const uint64_t t0 = a.cost ? __builtin_amdgcn_s_memtime() : 0;
     const uint32_t inter = wave_inter(a.A, a.B, t, lane);
     if (lane == 0) acc_add(a.acc, t.pair, (long long)inter);
+    if (a.cost && lane == 0) a.cost[slot] = (float)(__builtin_amdgcn_s_memtime() - t0);
 }
 
 // Array-array merge path: one 256-thread workgroup per pair, both arrays in LDS.
@@ -41,9 +44,13 @@ __global__ void __launch_bounds__(256) k_merge_count(ComputeArgs a) {
     __shared__ uint16_t sB[4096];
     __shared__ uint64_t tmp64[4];
     for (uint32_t it = blockIdx.x; it < a.n; it += gridDim.x) {
-        const Task t = uniform_task(a.tasks, uniform(a.list[it]));
+        const uint32_t slot = uniform(a.list[it]);
+        const Task t = uniform_task(a.tasks, slot);
+        const uint64_t t0 = a.cost ? __builtin_amdgcn_s_memtime() : 0;
         const uint32_t inter = merge_inter_wg(a.A, a.B, t, sA, sB, tmp64);
         if (threadIdx.x == 0) acc_add(a.acc, t.pair, (long long)inter);
+        // cost in wave-cycles: four waves for the task's duration
+        if (a.cost && threadIdx.x == 0) a.cost[slot] = 4.f * (float)(__builtin_amdgcn_s_memtime() - t0);
         __syncthreads();
     }
 }
@@ -51,13 +58,21 @@ __global__ void __launch_bounds__(256) k_merge_count(ComputeArgs a) {
 // One thread per pair.
 __global__ void __launch_bounds__(256) k_thread_count(ComputeArgs a) {
     const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    uint32_t pair = NONE, inter = 0;
+    uint32_t pair = NONE, inter = 0, slot = NONE;
+    const uint64_t t0 = a.cost ? __builtin_amdgcn_s_memtime() : 0;
     if (i < a.n) {
-        const Task t = a.tasks[a.list[i]];
+        slot = a.list[i];
+        const Task t = a.tasks[slot];
         inter = thread_inter(a.A, a.B, t);
         pair = t.pair;
     }
     wave_aggregate_add(a.acc, pair, inter);
+    if (a.cost) {
+        // the wave's time, shared by its active lanes
+        const uint64_t dt = __builtin_amdgcn_s_memtime() - t0;
+        const uint32_t act = (uint32_t)__popcll(__ballot(slot != NONE));
+        if (slot != NONE) a.cost[slot] = (float)dt / (float)act;
+    }
 }
 
 static void launch_wave_count(const ComputeArgs& a, hipStream_t st) {

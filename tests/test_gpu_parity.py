@@ -13,10 +13,8 @@ from tests import rgtest
 pytestmark = pytest.mark.gpu
 
 OPS = ("and", "or", "xor", "andnot")
-# Materialised OR/XOR/ANDNOT are switched off in the library (RG_ENOTSUP): their
-# first GPU run ended in a memory fault whose cause is not yet shown. Their
-# count-only forms and Jaccard are tested for every op.
-MAT_OPS = ("and",)
+# every operation is materialised (OR/XOR/ANDNOT through the k-way path)
+MAT_OPS = ("and", "or", "xor", "andnot")
 
 
 def _say(*a):
@@ -148,10 +146,6 @@ def test_single_pair_entry_points(rg, ctx):
             ctx.check(getattr(rg, f"roaring_{op}_cardinality")(ctx, P, x, P, y, d))
             torch.cuda.synchronize()
             assert int(d.item()) == len(exp)
-            if op not in MAT_OPS:
-                out = rg.OutArena(1, 1 << 16, 1 << 24)
-                assert getattr(rg, f"roaring_{op}")(ctx, P, x, P, y, out) == rg.RG_ENOTSUP
-                continue
             probe = rg.OutArena(1, 0, 0)
             probe.c.cap_containers = 0
             probe.c.cap_payload_bytes = 0
@@ -245,12 +239,29 @@ def test_dense_bitsets_reduced(rg, ctx):
                 assert int(dig[p]) == oracle.digest(exp)
 
 
-def test_materialised_or_xor_andnot_switched_off(rg, ctx):
-    """Materialised OR/XOR/ANDNOT return RG_ENOTSUP (the path is switched off, not faked)."""
-    bs = synth.mixed_small(n_bitmaps=3, seed=14)
-    P = rg.Pool.from_sets(bs.values, bs.offsets)
-    ia = _t(np.array([0, 1], np.uint32))
-    ib = _t(np.array([1, 2], np.uint32))
+def test_materialised_two_pools_different_layouts(rg, ctx):
+    """Materialised OR/XOR/ANDNOT between two different pools (the A side and
+    the B side of each pair come from different pools)."""
+    import torch
+
+    a_bs = synth.mixed_small(n_bitmaps=6, seed=14)
+    b_bs = synth.BitmapSet.from_list(rgtest.edge_sets())
+    A = rg.Pool.from_sets(a_bs.values, a_bs.offsets)
+    B = rg.Pool.from_sets(b_bs.values, b_bs.offsets)
+    ia = np.repeat(np.arange(len(a_bs)), len(b_bs)).astype(np.uint32)
+    ib = np.tile(np.arange(len(b_bs)), len(a_bs)).astype(np.uint32)
     for op in ("or", "xor", "andnot"):
-        out = rg.OutArena(2, 1 << 16, 1 << 24)
-        assert rg.roaring_batch(ctx, op, P, P, ia, ib, rg.RG_FLAG_MATERIALIZE, out) == rg.RG_ENOTSUP
+        _say(f"[two-pools-mat] op={op} pairs={len(ia)}")
+        out, cards, jacc = rg.batch(ctx, op, A, B, _t(ia), _t(ib), materialize=True, card=True, jaccard=True)
+        torch.cuda.synchronize()
+        res = out.as_pool()
+        assert rg.rg_pool_validate(ctx, res) == 0
+        dig = rg.rg_pool_digest(ctx, res).cpu().numpy().view(np.uint64)
+        cards = cards.cpu().numpy().view(np.uint64)
+        jacc = jacc.cpu().numpy()
+        for p in range(len(ia)):
+            a, b = a_bs[int(ia[p])], b_bs[int(ib[p])]
+            exp = oracle.op(op, a, b)
+            assert int(cards[p]) == len(exp) and int(dig[p]) == oracle.digest(exp), (op, p)
+            assert jacc[p] == oracle.jaccard(a, b)
+
