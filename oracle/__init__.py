@@ -109,7 +109,9 @@ def kway(name: str, lists) -> np.ndarray:
     k = len(arrs)
     if k == 0:
         return np.zeros(0, np.uint32)
-    cap = sum(len(a) for a in arrs) if name == "or" else len(arrs[0])
+    # a union or symmetric difference can hold every input value; an
+    # intersection or difference at most the first input's
+    cap = sum(len(a) for a in arrs) if name in ("or", "xor") else len(arrs[0])
     ptrs = (_u32p * k)(*[a.ctypes.data_as(_u32p) for a in arrs])
     lens = np.array([len(a) for a in arrs], dtype=np.uint64)
     out = np.zeros(max(cap, 1), np.uint32)

@@ -52,13 +52,13 @@ def overlapping_sets(n=24, seed=7):
     return synth.BitmapSet.from_list(out)
 
 
-def _queries(n_bitmaps, n, seed, kmax=8):
+def _queries(n_bitmaps, n, seed, kmax=8, ops=("and", "or")):
     rng = np.random.default_rng(seed)
     qs = []
     for i in range(n):
         k = int(rng.integers(1, kmax + 1))
         ids = rng.choice(n_bitmaps, size=k, replace=(i % 4 == 0)).astype(np.uint32)
-        qs.append(("and" if i % 2 == 0 else "or", ids))
+        qs.append((ops[i % len(ops)], ids))
     return qs
 
 
@@ -77,6 +77,8 @@ def test_multi_matches_oracle(rg, ctx, which):
     bs = _workload(which)
     P = rg.Pool.from_sets(bs.values, bs.offsets)
     qs = _queries(len(bs), 16, seed=11)
+    # symmetric difference (parity of k) and difference (first minus the others)
+    qs += _queries(len(bs), 8, seed=12, kmax=5, ops=("xor", "andnot"))
     # k at the limit: 256 ids (repeats allowed)
     qs.append(("and", np.resize(np.arange(min(3, len(bs)), dtype=np.uint32), 256)))
     qs.append(("or", np.resize(np.arange(len(bs), dtype=np.uint32), 256)))
@@ -113,7 +115,7 @@ def test_multi_errors(rg, ctx):
         t = torch.tensor(np.asarray(ids, np.uint32).view(np.int32), device="cuda")
         return rg.roaring_multi(ctx, op, P, t, flags, None, card)
 
-    assert call(rg.RG_XOR, [0, 1]) == rg.RG_EINVAL
+    assert call(7, [0, 1]) == rg.RG_EINVAL
     assert call("and", [0, 9]) == rg.RG_EINVAL
     assert call("and", [0] * 257) == rg.RG_EINVAL
     assert call("or", [0, 1], flags=0) == rg.RG_EINVAL

@@ -125,6 +125,19 @@ def test_kway_fold():
     assert np.array_equal(oracle.kway("or", lists[::-1]), oracle.kway("or", lists))
     assert np.array_equal(oracle.kway("and", lists[3:] + lists[:3]), oracle.kway("and", lists))
     assert np.array_equal(oracle.kway("and", lists[:1]), lists[0])
+    # symmetric difference of k sets: the values in an odd number of them
+    counts = {}
+    for st in sets:
+        for v in st:
+            counts[v] = counts.get(v, 0) + 1
+    odd = sorted(v for v, c in counts.items() if c % 2 == 1)
+    assert np.array_equal(oracle.kway("xor", lists), np.array(odd, np.uint32))
+    # disjoint inputs: the symmetric difference is the whole union (largest possible result)
+    disjoint = [np.arange(i * 3000, i * 3000 + 2500, dtype=np.uint32) for i in range(6)]
+    assert len(oracle.kway("xor", disjoint)) == 6 * 2500
+    # difference of k sets: the first minus all the others
+    assert np.array_equal(oracle.kway("andnot", lists),
+                          np.array(sorted(sets[0].difference(*sets[1:])), np.uint32))
 
 
 # ----------------------------------------------------------------- containers
