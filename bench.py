@@ -261,6 +261,12 @@ def bench_batched(args):
     t_s = time.perf_counter()
     sub_n = min(args.dispatch_pairs, n)
     X, T, M = rg.dispatch_samples(ctx, P, P, tia[:sub_n], tib[:sub_n])
+    # plus array pairs of every size (Zipf), so that larger arrays are covered too
+    zs, za, zb = synth.array_stress(n_pairs=4000)
+    ZP = rg.Pool.from_sets(zs.values, zs.offsets)
+    X2, T2, M2 = rg.dispatch_samples(ctx, ZP, ZP, torch.from_numpy(za.view(np.int32)).to(dev),
+                                     torch.from_numpy(zb.view(np.int32)).to(dev))
+    X, T, M = torch.cat([X, X2]), torch.cat([T, T2]), torch.cat([M, M2])
     params, losses = rg.dispatch_train(ctx, X, T, M, epochs=args.dispatch_epochs, batch=4096, lr=2e-3, seed=11)
     rg.dispatch_set_mlp(ctx, params)
     losses = losses.cpu().numpy()

@@ -281,6 +281,26 @@ void launch_bin_info(const uint32_t* bin_count, uint32_t* bin_info, uint32_t* cu
                      hipStream_t st);
 void launch_persist(const PersistArgs& a, uint32_t grid, hipStream_t st);
 
+// Which count variants may take a matched pair (forced and learned dispatch;
+// the generic variant takes any pair). A forced or learned thread-per-pair
+// choice needs an array side of at most THREAD_FORCE_MAX values: a thread
+// probing a long array would hold its whole wave.
+constexpr uint32_t THREAD_FORCE_MAX = 62;  // floor(log2(1 + c)) <= 5
+__host__ __device__ __forceinline__ bool variant_applies(int bin, uint8_t ta, uint8_t tb, uint32_t ca, uint32_t cb) {
+    const bool aa = ta == RG_ARRAY && tb == RG_ARRAY;
+    const bool ab = (ta == RG_ARRAY && tb == RG_BITSET) || (ta == RG_BITSET && tb == RG_ARRAY);
+    const bool run = ta == RG_RUN || tb == RG_RUN;
+    switch (bin) {
+    case BIN_GEN: return true;
+    case BIN_AA: return aa;
+    case BIN_GALLOP: return aa;
+    case BIN_AB: return ab;
+    case BIN_RR: return run;
+    case BIN_THREAD: return (ta == RG_ARRAY && ca <= THREAD_FORCE_MAX) || (tb == RG_ARRAY && cb <= THREAD_FORCE_MAX);
+    default: return false;
+    }
+}
+
 // learned dispatcher (rg_mlp.hip)
 constexpr int MLP_IN = 12, MLP_H = 64, MLP_OUT = 6;
 constexpr int MLP_PARAMS = MLP_IN * MLP_H + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H * MLP_OUT + MLP_OUT;

@@ -119,20 +119,6 @@ __device__ __forceinline__ uint32_t find_pair(const uint64_t* off, uint32_t n_pa
 
 // Variant selection (plain heuristic). It never changes results: every bin
 // computes the same set; the bins differ only in how.
-__device__ __forceinline__ bool variant_applies(int bin, uint8_t ta, uint8_t tb) {
-    const bool aa = ta == RG_ARRAY && tb == RG_ARRAY;
-    const bool ab = (ta == RG_ARRAY && tb == RG_BITSET) || (ta == RG_BITSET && tb == RG_ARRAY);
-    const bool run = ta == RG_RUN || tb == RG_RUN;
-    switch (bin) {
-    case BIN_GEN: return true;
-    case BIN_AA: return aa;
-    case BIN_GALLOP: return aa;
-    case BIN_AB: return ab;
-    case BIN_RR: return run;
-    case BIN_THREAD: return ta == RG_ARRAY || tb == RG_ARRAY;
-    default: return false;
-    }
-}
 
 __device__ __forceinline__ uint8_t classify(int op, bool materialize, uint8_t kind, uint8_t ta, uint8_t tb,
                                             uint32_t ca, uint32_t cb, uint32_t ra, uint32_t rb, int mode,
@@ -140,7 +126,7 @@ __device__ __forceinline__ uint8_t classify(int op, bool materialize, uint8_t ki
                                             const uint8_t* mlp_table) {
     if (ta == RG_BITSET && tb == RG_BITSET) return BIN_BB;
     if (materialize) return BIN_GEN;  // specialised variants are count-only
-    if (mode == 2) return variant_applies(fixed_bin, ta, tb) ? (uint8_t)fixed_bin : (uint8_t)BIN_GEN;
+    if (mode == 2) return variant_applies(fixed_bin, ta, tb, ca, cb) ? (uint8_t)fixed_bin : (uint8_t)BIN_GEN;
     if (mode == 1 && mlp_table) return mlp_table[mlp_cell(ta, tb, ca, cb, ra, rb)];  // learned
     // heuristic: a small array side is probed by one thread (each value
     // looked up in the other container); galloping when one array is much

@@ -192,21 +192,6 @@ __global__ void k_slot_features(const Task* tasks, uint64_t n, PoolView A, PoolV
 // run counts r_a, r_b (0..11, only for run containers; 0 otherwise). Each cell
 // is evaluated at its bucket centre and stores the argmin over the applicable
 // variants (ties to the lower index) as a bin number.
-__device__ __forceinline__ bool mlp_variant_applies(int bin, uint8_t ta, uint8_t tb) {
-    const bool aa = ta == RG_ARRAY && tb == RG_ARRAY;
-    const bool ab = (ta == RG_ARRAY && tb == RG_BITSET) || (ta == RG_BITSET && tb == RG_ARRAY);
-    const bool run = ta == RG_RUN || tb == RG_RUN;
-    switch (bin) {
-    case BIN_GEN: return true;
-    case BIN_AA: return aa;
-    case BIN_GALLOP: return aa;
-    case BIN_AB: return ab;
-    case BIN_RR: return run;
-    case BIN_THREAD: return ta == RG_ARRAY || tb == RG_ARRAY;
-    default: return false;
-    }
-}
-
 __global__ void __launch_bounds__(256) k_mlp_table(const float* P, uint8_t* table) {
     __shared__ float sP[MLP_PARAMS];
     load_params(sP, P);
@@ -238,7 +223,8 @@ __global__ void __launch_bounds__(256) k_mlp_table(const float* P, uint8_t* tabl
     float bv = 3.4e38f;
     for (int v = 0; v < MLP_OUT; ++v) {
         const int bin = BIN_GEN + v;
-        if (!mlp_variant_applies(bin, ta, tb)) continue;
+        // a representative cardinality of the cell (its largest: 2^(q+1) - 2)
+        if (!variant_applies(bin, ta, tb, (2u << qa) - 2u, (2u << qb) - 2u)) continue;
         if (y[v] < bv) {
             bv = y[v];
             best = bin;

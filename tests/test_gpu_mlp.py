@@ -116,7 +116,9 @@ def test_trained_dispatch_keeps_every_result(rg, ctx):
         bad = ((tab == 3) | (tab == 4)) & ~(arr_a & arr_b)
         bad |= (tab == 5) & ~((arr_a & (tb == 2)) | ((ta == 2) & arr_b))
         bad |= (tab == 6) & ~((ta == 3) | (tb == 3))
-        bad |= (tab == 7) & ~(arr_a | arr_b)
+        qa = (cells // (17 * 144)) % 17
+        qb = (cells // 144) % 17
+        bad |= (tab == 7) & ~((arr_a & (qa <= 5)) | (arr_b & (qb <= 5)))
         bad |= (tab < 2) | (tab > 7)
         assert not bad.any()
         _say(f"[dispatch] table bins {np.bincount(tab, minlength=9).tolist()}")
