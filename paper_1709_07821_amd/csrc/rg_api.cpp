@@ -101,9 +101,9 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
     uint32_t* min_cont = bp.take<uint32_t>(n_pairs);
     long long* acc = bp.take<long long>(n_pairs);
     uint32_t* d_err = reinterpret_cast<uint32_t*>(c->small);
-    uint32_t* bin_count = d_err + 16;
-    uint32_t* bin_cursor = d_err + 32;
     uint32_t* redo_count = d_err + 48;
+    uint32_t* bin_info = d_err + 128;                              // [2 NBINS] counts, offsets
+    uint64_t* bin_total = reinterpret_cast<uint64_t*>(d_err + 160);
     uint64_t* totals = reinterpret_cast<uint64_t*>(d_err + 64);  // [0] payload end, [1] container end
 
     // Count-only calls accumulate |A n B| for every operation and convert at
@@ -165,7 +165,9 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
     const bool kw = mat && op != RG_AND;
     size_t wneed = S_max * SLOT_BYTES + 16 * 256 + align256(8 * (P_max + 1)) +
                    align256(8 * scan_partials_needed(S_max)) +
-                   (kw ? align256(sizeof(KwQuery) * P_max) + align256(8 * P_max) + 512 : 0);
+                   (kw ? align256(sizeof(KwQuery) * P_max) + align256(8 * P_max) + 512 : 0) +
+                   align256(4ull * NBINS * match_blocks(S_max)) + align256(8ull * NBINS * match_blocks(S_max)) +
+                   align256(8 * scan_partials_needed((uint64_t)NBINS * match_blocks(S_max))) + 768;
     if (rg_status s = grow_device(c, &c->ws_wave, &c->ws_wave_bytes, wneed)) return s;
     Bump wb{(uint8_t*)c->ws_wave};
     Task* tasks = wb.take<Task>(S_max);
@@ -180,6 +182,9 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
     uint32_t* redo_list = wb.take<uint32_t>(S_max);
     uint64_t* cand_off = wb.take<uint64_t>(P_max + 1);
     uint64_t* partials = wb.take<uint64_t>(scan_partials_needed(S_max));
+    uint32_t* blk_cnt = wb.take<uint32_t>((size_t)NBINS * match_blocks(S_max));
+    uint64_t* blk_off = wb.take<uint64_t>((size_t)NBINS * match_blocks(S_max));
+    uint64_t* bpart = wb.take<uint64_t>(scan_partials_needed((uint64_t)NBINS * match_blocks(S_max)));
     KwQuery* kw_queries = kw ? wb.take<KwQuery>(P_max) : nullptr;
     uint32_t* kw_ids = kw ? wb.take<uint32_t>(2 * P_max) : nullptr;
 
@@ -222,7 +227,6 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
             launch_scan_u32_u64(ub, slot_off, C, pay_base, partials, totals, st);
             timed(c, BIN_GEN, true, C, st, [&] { launch_kw_eval(ka, st); });
         } else {
-            launch_fill_u32(bin_count, 0, NBINS, st);
             MatchArgs m;
             m.op = kop;
             m.materialize = mat;
@@ -239,7 +243,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
             m.tasks = tasks;
             m.ub = ub;
             m.res_card = res_card;
-            m.bin_count = bin_count;
+            m.blk_cnt = blk_cnt;
             m.dispatch_mode = c->dispatch_mode;
             m.fixed_bin = c->fixed_bin;
             m.gallop_ratio = c->gallop_ratio;
@@ -247,20 +251,17 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
             m.mlp_table = c->mlp_table;
             launch_match(m, st);
             if (mat) launch_scan_u32_u64(ub, slot_off, C, pay_base, partials, totals, st);
-            HIPCHK(c, hipMemcpyAsync(h_small, bin_count, 4 * NBINS, hipMemcpyDeviceToHost, st));
+            launch_bin_layout(blk_cnt, match_blocks(C), blk_off, bpart, bin_total, bin_info, nullptr, st);
+            launch_bin_scatter(tasks, C, blk_off, bin_lists, st);
+            HIPCHK(c, hipMemcpyAsync(h_small, bin_info, 8 * NBINS, hipMemcpyDeviceToHost, st));
             if (mat) HIPCHK(c, hipMemcpyAsync(h_small + 64, totals, 8, hipMemcpyDeviceToHost, st));
             HIPCHK(c, hipStreamSynchronize(st));
             uint32_t cnt[NBINS], boff[NBINS];
-            uint32_t run = 0;
             for (int b = 0; b < NBINS; ++b) {
                 cnt[b] = h_small[b];
-                boff[b] = run;
-                run += cnt[b];
+                boff[b] = h_small[NBINS + b];
             }
             pay_end = mat ? *reinterpret_cast<uint64_t*>(h_small + 64) : 0;
-            memcpy(h_small + 128, boff, sizeof(boff));
-            HIPCHK(c, hipMemcpyAsync(bin_cursor, h_small + 128, sizeof(boff), hipMemcpyHostToDevice, st));
-            launch_bin_scatter(tasks, C, bin_cursor, bin_lists, st);
             launch_fill_u32(redo_count, 0, 1, st);
 
             ComputeArgs ca;
@@ -572,9 +573,11 @@ struct rg_plan {
     Task* tasks = nullptr;
     uint32_t* res_card = nullptr;
     uint32_t* lists = nullptr;
-    uint32_t* bin_count = nullptr;
+    uint32_t* blk_cnt = nullptr;
+    uint64_t* blk_off = nullptr;
+    uint64_t* bpart = nullptr;
+    uint64_t* bin_total = nullptr;
     uint32_t* bin_info = nullptr;
-    uint32_t* cursor = nullptr;
     uint32_t* next = nullptr;
     uint64_t S_max = 0;
     uint32_t grid = 0;
@@ -597,7 +600,6 @@ void plan_enqueue(rg_plan* p, hipStream_t st) {
                      p->n_cand, p->bound, p->min_cont, p->acc, p->err, st);
     for (const auto& w : p->waves) {
         if (!w.C) continue;
-        launch_fill_u32(p->bin_count, 0, NBINS, st);
         MatchArgs m;
         m.op = RG_AND;
         m.materialize = false;
@@ -614,15 +616,16 @@ void plan_enqueue(rg_plan* p, hipStream_t st) {
         m.tasks = p->tasks;
         m.ub = nullptr;
         m.res_card = p->res_card;
-        m.bin_count = p->bin_count;
+        m.blk_cnt = p->blk_cnt;
         m.dispatch_mode = p->dispatch_mode;
         m.fixed_bin = p->fixed_bin;
         m.gallop_ratio = p->gallop_ratio;
         m.thread_max = p->thread_max;
         m.mlp_table = p->ctx->mlp_table;
         launch_match(m, st);
-        launch_bin_info(p->bin_count, p->bin_info, p->cursor, p->next, st);
-        launch_bin_scatter(p->tasks, w.C, p->cursor, p->lists, st);
+        launch_bin_layout(p->blk_cnt, match_blocks(w.C), p->blk_off, p->bpart, p->bin_total, p->bin_info, p->next,
+                          st);
+        launch_bin_scatter(p->tasks, w.C, p->blk_off, p->lists, st);
         PersistArgs a{pa, pb, p->tasks, p->lists, p->bin_info, p->next, p->acc};
         launch_persist(a, p->grid, st);
     }
@@ -723,7 +726,9 @@ rg_status rg_plan_create(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, 
     size_t offs_bytes = 0;
     for (size_t w = 0; w + 1 < starts.size(); ++w) offs_bytes += align256(8 * (starts[w + 1] - starts[w] + 1));
     const uint64_t S = std::max<uint64_t>(p->S_max, 1);
-    const size_t total = pair_bytes + offs_bytes + align256(sizeof(Task) * S) + 2 * align256(4 * S) + 4 * 256;
+    const uint64_t NB = (uint64_t)NBINS * match_blocks(S);
+    const size_t total = pair_bytes + offs_bytes + align256(sizeof(Task) * S) + 2 * align256(4 * S) + 6 * 256 +
+                         align256(4 * NB) + align256(8 * NB) + align256(8 * scan_partials_needed(NB));
     if (hipMalloc(&p->mem, total) != hipSuccess) return cleanup(fail(c, RG_EDEVICE, "hipMalloc failed"));
     Bump b{(uint8_t*)p->mem};
     p->n_cand = b.take<uint32_t>(n_pairs);
@@ -734,9 +739,11 @@ rg_status rg_plan_create(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, 
     p->tasks = b.take<Task>(S);
     p->res_card = b.take<uint32_t>(S);
     p->lists = b.take<uint32_t>(S);
-    p->bin_count = b.take<uint32_t>(NBINS);
+    p->blk_cnt = b.take<uint32_t>(NB);
+    p->blk_off = b.take<uint64_t>(NB);
+    p->bpart = b.take<uint64_t>(scan_partials_needed(NB));
+    p->bin_total = b.take<uint64_t>(1);
     p->bin_info = b.take<uint32_t>(2 * NBINS);
-    p->cursor = b.take<uint32_t>(NBINS);
     p->next = b.take<uint32_t>(NBINS);
     std::vector<uint64_t> h_off;
     for (size_t w = 0; w + 1 < starts.size(); ++w) {

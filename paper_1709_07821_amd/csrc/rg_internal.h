@@ -194,7 +194,7 @@ struct MatchArgs {
     Task* tasks;              // [n_cand]
     uint32_t* ub;             // [n_cand] slot payload bound in bytes (materialize)
     uint32_t* res_card;       // [n_cand]
-    uint32_t* bin_count;      // [NBINS]
+    uint32_t* blk_cnt;        // [NBINS][ceil(n_cand / 256)]: per-block bin counts, bin-major
     int dispatch_mode;        // 0 heuristic, 1 learned (mlp_table), 2 fixed
     int fixed_bin;
     uint32_t gallop_ratio;
@@ -209,7 +209,14 @@ void launch_pair_prep(int op, bool materialize, PoolView A, PoolView B, uint32_t
                       uint32_t* n_cand, uint64_t* bound, uint32_t* min_cont, long long* acc, uint32_t* err,
                       hipStream_t st);
 void launch_match(const MatchArgs& m, hipStream_t st);
-void launch_bin_scatter(const Task* tasks, uint64_t n, uint32_t* bin_cursor, uint32_t* bin_lists, hipStream_t st);
+// Binning without contended atomics: k_match leaves per-block bin counts; an
+// exclusive scan of them (bin-major) gives each block's place in each bin's
+// list, and the bins' counts and offsets (bin_info[0..NBINS) counts,
+// bin_info[NBINS..2 NBINS) offsets; next[] work counters reset when given).
+inline uint32_t match_blocks(uint64_t n_cand) { return (uint32_t)((n_cand + 255) / 256); }
+void launch_bin_layout(const uint32_t* blk_cnt, uint32_t nblk, uint64_t* blk_off, uint64_t* partials, uint64_t* total,
+                       uint32_t* bin_info, uint32_t* next, hipStream_t st);
+void launch_bin_scatter(const Task* tasks, uint64_t n, const uint64_t* blk_off, uint32_t* bin_lists, hipStream_t st);
 // exclusive scan of u32 into u64 with an added base; writes total to *total_out (device)
 void launch_scan_u32_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t base, uint64_t* partials,
                          uint64_t* total_out, hipStream_t st);
@@ -274,11 +281,9 @@ struct PersistArgs {
     const Task* tasks;
     const uint32_t* lists;     // bin lists
     const uint32_t* bin_info;  // [NBINS] counts, then [NBINS] offsets (device)
-    uint32_t* next;            // [NBINS] work counters, reset by k_bin_info
+    uint32_t* next;            // [NBINS] work counters, reset with the bin layout
     long long* acc;
 };
-void launch_bin_info(const uint32_t* bin_count, uint32_t* bin_info, uint32_t* cursor, uint32_t* next,
-                     hipStream_t st);
 void launch_persist(const PersistArgs& a, uint32_t grid, hipStream_t st);
 
 // Which count variants may take a matched pair (forced and learned dispatch;

@@ -143,13 +143,81 @@ __device__ __forceinline__ uint8_t classify(int op, bool materialize, uint8_t ki
     return BIN_RR;      // run-run, run-bitset
 }
 
+constexpr uint32_t MATCH_LDS_KEYS = 2048;
+
 __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
     __shared__ uint32_t cnt[NBINS];
+    __shared__ uint32_t pl_range[2];
+    __shared__ uint16_t lkeys[MATCH_LDS_KEYS];
+    __shared__ uint32_t lwin[2];  // [0] first index of the staged window in the searched list, [1] its length
     if (threadIdx.x < NBINS) cnt[threadIdx.x] = 0;
+    // the pairs of this block's first and last candidate bound every thread's search
+    const uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x;
+    if (threadIdx.x == 0) pl_range[0] = find_pair(m.cand_off, m.n_pairs, t0);
+    if (threadIdx.x == 1) {
+        const uint64_t tl = t0 + blockDim.x - 1 < m.n_cand ? t0 + blockDim.x - 1 : m.n_cand - 1;
+        pl_range[1] = find_pair(m.cand_off, m.n_pairs, tl);
+    }
     __syncthreads();
-    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // Count-only block whose candidates all belong to one pair: its candidate
+    // keys are consecutive keys of the pair's smaller side, so the matching keys
+    // of the other side lie in one window; stage that window in LDS and search
+    // there instead of in global memory.
+    const bool one_pair = !m.materialize && uniform(pl_range[0]) == uniform(pl_range[1]);
+    if (one_pair) {
+        if (threadIdx.x == 0) {
+            const uint32_t pl = pl_range[0];
+            const uint64_t p = m.pair0 + pl;
+            const uint32_t a = m.ia ? m.ia[p] : m.ia0, b = m.ib ? m.ib[p] : m.ib0;
+            const uint64_t a0 = m.A.bm_begin[a], b0 = m.B.bm_begin[b];
+            const uint32_t KA = (uint32_t)(m.A.bm_begin[a + 1] - a0), KB = (uint32_t)(m.B.bm_begin[b + 1] - b0);
+            const bool a_small = KA <= KB;
+            const uint16_t* sk = a_small ? m.A.keys + a0 : m.B.keys + b0;
+            const uint16_t* lk = a_small ? m.B.keys + b0 : m.A.keys + a0;
+            const uint32_t nl = a_small ? KB : KA;
+            const uint64_t u0 = t0 - m.cand_off[pl];
+            const uint64_t tl = t0 + blockDim.x - 1 < m.n_cand ? t0 + blockDim.x - 1 : m.n_cand - 1;
+            const uint64_t u1 = tl - m.cand_off[pl];
+            const uint32_t lo = lower_bound_u16(lk, nl, sk[u0]);
+            uint32_t hi = lo;
+            {
+                uint32_t l2 = lo, h2 = nl;  // first index with key > last candidate key
+                const uint16_t kl = sk[u1];
+                while (l2 < h2) {
+                    const uint32_t mid = (l2 + h2) >> 1;
+                    if (lk[mid] <= kl) l2 = mid + 1;
+                    else h2 = mid;
+                }
+                hi = l2;
+            }
+            lwin[0] = lo;
+            lwin[1] = hi - lo <= MATCH_LDS_KEYS ? hi - lo : 0xFFFFFFFFu;
+        }
+        __syncthreads();
+        const uint32_t wn = uniform(lwin[1]);
+        if (wn != 0xFFFFFFFFu) {
+            const uint32_t pl = pl_range[0];
+            const uint64_t p = m.pair0 + pl;
+            const uint32_t a = m.ia ? m.ia[p] : m.ia0, b = m.ib ? m.ib[p] : m.ib0;
+            const uint64_t a0 = m.A.bm_begin[a], b0 = m.B.bm_begin[b];
+            const uint32_t KA = (uint32_t)(m.A.bm_begin[a + 1] - a0), KB = (uint32_t)(m.B.bm_begin[b + 1] - b0);
+            const uint16_t* lk = KA <= KB ? m.B.keys + b0 : m.A.keys + a0;
+            for (uint32_t i = threadIdx.x; i < wn; i += blockDim.x) lkeys[i] = lk[lwin[0] + i];
+        }
+        __syncthreads();
+    }
+    const uint32_t win_n = one_pair ? uniform(lwin[1]) : 0xFFFFFFFFu;
+    const uint32_t win_lo = one_pair ? lwin[0] : 0u;
+    uint64_t t = t0 + threadIdx.x;
     if (t < m.n_cand) {
-        uint32_t pl = find_pair(m.cand_off, m.n_pairs, t);
+        // largest pl in [lo, hi] with cand_off[pl] <= t
+        uint32_t lo = pl_range[0], hi = pl_range[1];
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (m.cand_off[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        uint32_t pl = lo;
         uint64_t p = m.pair0 + pl;
         uint64_t u = t - m.cand_off[pl];
         uint32_t a = m.ia ? m.ia[p] : m.ia0;
@@ -168,7 +236,8 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
             // count only: candidates from the side with fewer keys
             if (KA <= KB) {
                 uint16_t key = m.A.keys[a0 + u];
-                uint32_t j = lower_bound_u16(m.B.keys + b0, KB, key);
+                uint32_t j = win_n != 0xFFFFFFFFu ? win_lo + lower_bound_u16(lkeys, win_n, key)
+                                                  : lower_bound_u16(m.B.keys + b0, KB, key);
                 task.key = key;
                 if (j < KB && m.B.keys[b0 + j] == key) {
                     task.kind = KIND_MATCH;
@@ -177,7 +246,8 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
                 }
             } else {
                 uint16_t key = m.B.keys[b0 + u];
-                uint32_t i = lower_bound_u16(m.A.keys + a0, KA, key);
+                uint32_t i = win_n != 0xFFFFFFFFu ? win_lo + lower_bound_u16(lkeys, win_n, key)
+                                                  : lower_bound_u16(m.A.keys + a0, KA, key);
                 task.key = key;
                 if (i < KA && m.A.keys[a0 + i] == key) {
                     task.kind = KIND_MATCH;
@@ -221,7 +291,7 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
         }
     }
     __syncthreads();
-    if (threadIdx.x < NBINS && cnt[threadIdx.x]) atomicAdd(&m.bin_count[threadIdx.x], cnt[threadIdx.x]);
+    if (threadIdx.x < NBINS) m.blk_cnt[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = cnt[threadIdx.x];
 }
 
 void launch_match(const MatchArgs& m, hipStream_t st) {
@@ -230,34 +300,45 @@ void launch_match(const MatchArgs& m, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ binning
-// Scatter slot ids into per-bin lists. bin_cursor[b] starts at the bin's
-// offset; one global atomic per bin per block.
-__global__ void __launch_bounds__(256) k_bin_scatter(const Task* tasks, uint64_t n, uint32_t* cursor,
+// bin counts and offsets from the scanned per-block counts
+__global__ void k_bin_totals(const uint64_t* blk_off, uint32_t nblk, const uint64_t* total, uint32_t* bin_info,
+                             uint32_t* next) {
+    const uint32_t b = threadIdx.x;
+    if (b >= NBINS) return;
+    const uint64_t o = blk_off[(uint64_t)b * nblk];
+    const uint64_t e = b + 1 < NBINS ? blk_off[(uint64_t)(b + 1) * nblk] : *total;
+    bin_info[b] = (uint32_t)(e - o);
+    bin_info[NBINS + b] = (uint32_t)o;
+    if (next) next[b] = 0;
+}
+
+void launch_bin_layout(const uint32_t* blk_cnt, uint32_t nblk, uint64_t* blk_off, uint64_t* partials, uint64_t* total,
+                       uint32_t* bin_info, uint32_t* next, hipStream_t st) {
+    launch_scan_u32_u64(blk_cnt, blk_off, (uint64_t)NBINS * nblk, 0, partials, total, st);
+    hipLaunchKernelGGL(k_bin_totals, dim3(1), dim3(64), 0, st, (const uint64_t*)blk_off, nblk, (const uint64_t*)total,
+                       bin_info, next);
+}
+
+// Slot ids into per-bin lists: the same 256-slot blocks as k_match, each
+// block's slots of bin b go to blk_off[b][block] + rank (rank from LDS atomics).
+__global__ void __launch_bounds__(256) k_bin_scatter(const Task* tasks, uint64_t n, const uint64_t* blk_off,
                                                      uint32_t* lists) {
     __shared__ uint32_t cnt[NBINS];
-    __shared__ uint32_t base[NBINS];
     if (threadIdx.x < NBINS) cnt[threadIdx.x] = 0;
     __syncthreads();
     uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint8_t bin = 0xFF;
-    uint32_t rank = 0;
     if (s < n) {
         Task t = tasks[s];
         if (t.kind != KIND_NOOP) {
-            bin = t.bin;
-            rank = atomicAdd(&cnt[bin], 1u);
+            const uint32_t rank = atomicAdd(&cnt[t.bin], 1u);
+            lists[blk_off[(uint64_t)t.bin * gridDim.x + blockIdx.x] + rank] = (uint32_t)s;
         }
     }
-    __syncthreads();
-    if (threadIdx.x < NBINS && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
-    __syncthreads();
-    if (bin != 0xFF) lists[base[bin] + rank] = (uint32_t)s;
 }
 
-void launch_bin_scatter(const Task* tasks, uint64_t n, uint32_t* bin_cursor, uint32_t* bin_lists, hipStream_t st) {
+void launch_bin_scatter(const Task* tasks, uint64_t n, const uint64_t* blk_off, uint32_t* bin_lists, hipStream_t st) {
     if (!n) return;
-    hipLaunchKernelGGL(k_bin_scatter, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, tasks, n, bin_cursor,
-                       bin_lists);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(match_blocks(n)), dim3(256), 0, st, tasks, n, blk_off, bin_lists);
 }
 
 // ------------------------------------------------------------------ scan

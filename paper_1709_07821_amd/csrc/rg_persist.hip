@@ -13,26 +13,6 @@
 
 namespace rg {
 
-// counts -> exclusive offsets; scatter cursors; work counters reset
-__global__ void k_bin_info(const uint32_t* bin_count, uint32_t* bin_info, uint32_t* cursor, uint32_t* next) {
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int b = 0; b < NBINS; ++b) {
-            uint32_t c = bin_count[b];
-            bin_info[b] = c;
-            bin_info[NBINS + b] = run;
-            cursor[b] = run;
-            next[b] = 0;
-            run += c;
-        }
-    }
-}
-
-void launch_bin_info(const uint32_t* bin_count, uint32_t* bin_info, uint32_t* cursor, uint32_t* next,
-                     hipStream_t st) {
-    hipLaunchKernelGGL(k_bin_info, dim3(1), dim3(64), 0, st, bin_count, bin_info, cursor, next);
-}
-
 __global__ void __launch_bounds__(256) k_persist(PersistArgs a) {
     __shared__ WgShared sh;
     __shared__ uint32_t grab;
