@@ -156,7 +156,7 @@ def main():
         ach = alg_bytes / mean_s / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_bb<op, count-only>", "mean_launch_ms": round(mean_s * 1e3, 4),
+                "kernel": "k_bb_count", "mean_launch_ms": round(mean_s * 1e3, 4),
                 "launches": int(k["launches"]), "bytes_per_launch": int(alg_bytes)}
 
     if roof is not None:

@@ -415,11 +415,47 @@ __global__ void __launch_bounds__(256) k_scan_down(const uint32_t* in, uint64_t 
     }
 }
 
+// one tile: the whole scan in one workgroup (small inputs: one launch, not three)
+__global__ void __launch_bounds__(256) k_scan_single(const uint32_t* in, uint64_t n, uint64_t base, uint64_t* out,
+                                                     uint64_t* total_out) {
+    __shared__ uint64_t tmp[4];
+    const uint64_t start = (uint64_t)threadIdx.x * SCAN_PER_THREAD;
+    uint32_t v[SCAN_PER_THREAD];
+    uint64_t s = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < SCAN_PER_THREAD; ++k) {
+        v[k] = start + k < n ? in[start + k] : 0;
+        s += v[k];
+    }
+    const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
+    uint64_t inc = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint64_t x = __shfl_up(inc, o);
+        if (lane >= (uint32_t)o) inc += x;
+    }
+    if (lane == 63) tmp[wid] = inc;
+    __syncthreads();
+    uint64_t wbase = 0;
+    for (uint32_t w = 0; w < wid; ++w) wbase += tmp[w];
+    uint64_t run = base + wbase + inc - s;
+#pragma unroll
+    for (uint32_t k = 0; k < SCAN_PER_THREAD; ++k) {
+        if (start + k < n) out[start + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 255 && total_out) *total_out = base + wbase + inc;
+}
+
 void launch_scan_u32_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t base, uint64_t* partials,
                          uint64_t* total_out, hipStream_t st) {
     uint64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb == 0) {
-        hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, st, total_out, base, (uint64_t)1);
+        if (total_out) hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, st, total_out, base, (uint64_t)1);
+        return;
+    }
+    if (nb == 1) {
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(256), 0, st, in, n, base, out, total_out);
         return;
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)nb), dim3(256), 0, st, in, n, partials);
