@@ -265,3 +265,76 @@ def test_materialised_two_pools_different_layouts(rg, ctx):
             assert int(cards[p]) == len(exp) and int(dig[p]) == oracle.digest(exp), (op, p)
             assert jacc[p] == oracle.jaccard(a, b)
 
+
+
+def test_dense_bitsets_full_size_sampled(rg, ctx):
+    """The bitset-bandwidth workload at full size, in the launch configuration the
+    bench times (2e4 bitmaps x 256 bitsets, 1e4 random pairs, count-only batched
+    calls): every pair's four counts satisfy the identities, and sampled pairs
+    equal the oracle; a materialised batch of sampled pairs is decoded."""
+    import torch
+
+    nb, nk, npairs = 20000, 256, 10000
+    w = torch.empty(nb * nk * 1024, dtype=torch.int64, device="cuda")
+    for b0 in range(0, nb, 1000):
+        synth.dense_bitsets_device(w.data_ptr() + b0 * nk * 8192, b0, min(1000, nb - b0), nk,
+                                   torch.cuda.current_stream().cuda_stream)
+    P = rg.Pool.from_dense_words(ctx, w, nb, nk)
+    ia, ib = synth.random_pairs(nb, npairs, seed=synth.DENSE_SEED)
+    tia, tib = _t(ia), _t(ib)
+    cards = {}
+    for op in OPS:
+        _, c, j = rg.batch(ctx, op, P, P, tia, tib, materialize=False, card=True, jaccard=True)
+        torch.cuda.synchronize()
+        cards[op] = c.cpu().numpy().view(np.uint64).astype(np.int64)
+        jac = j.cpu().numpy()
+    tot = P.bm_card.cpu().numpy()
+    na, nb_ = tot[ia], tot[ib]
+    # identities on every pair (Section 5.9)
+    assert np.array_equal(cards["or"] + cards["and"], na + nb_)
+    assert np.array_equal(cards["xor"], na + nb_ - 2 * cards["and"])
+    assert np.array_equal(cards["andnot"], na - cards["and"])
+    sample = [0, 1, npairs // 2, npairs - 1]
+    for p in sample:
+        a = synth.dense_bitmap_values(int(ia[p]), nk)
+        b = synth.dense_bitmap_values(int(ib[p]), nk)
+        _say(f"[dense-full] pair {p}")
+        for op in OPS:
+            assert int(cards[op][p]) == oracle.count(op, a, b), (op, p)
+        assert jac[p] == oracle.jaccard(a, b)
+    sia, sib = _t(ia[sample]), _t(ib[sample])
+    for op in OPS:
+        out, mc, _ = rg.batch(ctx, op, P, P, sia, sib, materialize=True, card=True)
+        torch.cuda.synchronize()
+        res = out.as_pool()
+        assert rg.rg_pool_validate(ctx, res) == 0
+        dig = rg.rg_pool_digest(ctx, res).cpu().numpy().view(np.uint64)
+        for q, p in enumerate(sample[:2]):
+            a = synth.dense_bitmap_values(int(ia[p]), nk)
+            b = synth.dense_bitmap_values(int(ib[p]), nk)
+            exp = oracle.op(op, a, b)
+            assert int(dig[q]) == oracle.digest(exp), (op, p)
+    del w, P
+    torch.cuda.empty_cache()
+
+
+def test_array_stress_full_size_sampled(rg, ctx):
+    """Array-array stress at full size (1e5 pairs): counts of every pair satisfy
+    the identities; 200 sampled pairs equal the oracle for all four operations."""
+    import torch
+
+    bs, ia, ib = synth.array_stress()
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    tia, tib = _t(ia), _t(ib)
+    cards = {}
+    for op in OPS:
+        _, c, _ = rg.batch(ctx, op, P, P, tia, tib, materialize=False, card=True)
+        torch.cuda.synchronize()
+        cards[op] = c.cpu().numpy().view(np.uint64).astype(np.int64)
+    tot = P.bm_card.cpu().numpy()
+    assert np.array_equal(cards["or"] + cards["and"], tot[ia] + tot[ib])
+    rng = np.random.default_rng(9)
+    for p in rng.choice(len(ia), 200, replace=False):
+        a, b = bs[int(ia[p])], bs[int(ib[p])]
+        for op in OPS:
+            assert int(cards[op][p]) == oracle.count(op, a, b), (op, p)
