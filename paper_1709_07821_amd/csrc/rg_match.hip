@@ -106,15 +106,31 @@ __device__ __forceinline__ uint32_t lower_bound_u16(const uint16_t* k, uint32_t 
     return lo;
 }
 
-__device__ __forceinline__ uint32_t find_pair(const uint64_t* off, uint32_t n_pairs, uint64_t t) {
-    // largest p with off[p] <= t (off has n_pairs + 1 entries, off[0] = 0)
-    uint32_t lo = 0, hi = n_pairs;
-    while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (off[mid] <= t) lo = mid;
-        else hi = mid;
+// First index i in [0, n) for which pred(i) is false, pred being true on a
+// prefix; n if it holds everywhere. The 64 lanes of a wave probe 64 evenly
+// spaced positions per round, so a list of n entries takes about log64(n)
+// dependent loads instead of log2(n). All lanes must call it together; the
+// result is uniform.
+template <class Pred>
+__device__ __forceinline__ uint32_t wave_partition_point(uint32_t n, uint32_t lane, Pred pred) {
+    uint32_t lo = 0, len = n;  // the answer lies in [lo, lo + len]
+    while (len > 0) {
+        const uint32_t step = (len + 63) >> 6;
+        const uint32_t pos = lo + lane * step;
+        const bool t = pos < lo + len && pred(pos);
+        const uint32_t c = (uint32_t)__popcll(__ballot(t));  // lanes 0..c-1 hold
+        if (c == 0) break;
+        const uint32_t nlo = lo + (c - 1) * step + 1;
+        const uint32_t nhi = lo + c * step < lo + len ? lo + c * step : lo + len;
+        lo = uniform(nlo);
+        len = uniform(nhi - nlo);
     }
     return lo;
+}
+
+// largest pl with off[pl] <= t (off has n_pairs + 1 entries, off[0] = 0 <= t < off[n_pairs])
+__device__ __forceinline__ uint32_t wave_find_pair(const uint64_t* off, uint32_t n_pairs, uint64_t t, uint32_t lane) {
+    return wave_partition_point(n_pairs + 1, lane, [&](uint32_t i) { return off[i] <= t; }) - 1;
 }
 
 // Variant selection (plain heuristic). It never changes results: every bin
@@ -151,63 +167,49 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
     __shared__ uint16_t lkeys[MATCH_LDS_KEYS];
     __shared__ uint32_t lwin[2];  // [0] first index of the staged window in the searched list, [1] its length
     if (threadIdx.x < NBINS) cnt[threadIdx.x] = 0;
-    // the pairs of this block's first and last candidate bound every thread's search
+    const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
+    // the pairs of this block's first and last candidate bound every thread's
+    // search: wave 0 finds the first, wave 1 the last
     const uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x;
-    if (threadIdx.x == 0) pl_range[0] = find_pair(m.cand_off, m.n_pairs, t0);
-    if (threadIdx.x == 1) {
-        const uint64_t tl = t0 + blockDim.x - 1 < m.n_cand ? t0 + blockDim.x - 1 : m.n_cand - 1;
-        pl_range[1] = find_pair(m.cand_off, m.n_pairs, tl);
+    const uint64_t tl = t0 + blockDim.x - 1 < m.n_cand ? t0 + blockDim.x - 1 : m.n_cand - 1;
+    if (wid < 2) {
+        const uint32_t pl = wave_find_pair(m.cand_off, m.n_pairs, wid == 0 ? t0 : tl, lane);
+        if (lane == 0) pl_range[wid] = pl;
     }
     __syncthreads();
     // Count-only block whose candidates all belong to one pair: its candidate
     // keys are consecutive keys of the pair's smaller side, so the matching keys
     // of the other side lie in one window; stage that window in LDS and search
-    // there instead of in global memory.
+    // there instead of in global memory. Wave 0 finds the window's first index
+    // (first key >= the first candidate), wave 1 its end (first key > the last).
     const bool one_pair = !m.materialize && uniform(pl_range[0]) == uniform(pl_range[1]);
+    uint32_t win_n = 0xFFFFFFFFu, win_lo = 0;  // staged window: none
     if (one_pair) {
-        if (threadIdx.x == 0) {
-            const uint32_t pl = pl_range[0];
-            const uint64_t p = m.pair0 + pl;
-            const uint32_t a = m.ia ? m.ia[p] : m.ia0, b = m.ib ? m.ib[p] : m.ib0;
-            const uint64_t a0 = m.A.bm_begin[a], b0 = m.B.bm_begin[b];
-            const uint32_t KA = (uint32_t)(m.A.bm_begin[a + 1] - a0), KB = (uint32_t)(m.B.bm_begin[b + 1] - b0);
-            const bool a_small = KA <= KB;
-            const uint16_t* sk = a_small ? m.A.keys + a0 : m.B.keys + b0;
-            const uint16_t* lk = a_small ? m.B.keys + b0 : m.A.keys + a0;
-            const uint32_t nl = a_small ? KB : KA;
-            const uint64_t u0 = t0 - m.cand_off[pl];
-            const uint64_t tl = t0 + blockDim.x - 1 < m.n_cand ? t0 + blockDim.x - 1 : m.n_cand - 1;
-            const uint64_t u1 = tl - m.cand_off[pl];
-            const uint32_t lo = lower_bound_u16(lk, nl, sk[u0]);
-            uint32_t hi = lo;
-            {
-                uint32_t l2 = lo, h2 = nl;  // first index with key > last candidate key
-                const uint16_t kl = sk[u1];
-                while (l2 < h2) {
-                    const uint32_t mid = (l2 + h2) >> 1;
-                    if (lk[mid] <= kl) l2 = mid + 1;
-                    else h2 = mid;
-                }
-                hi = l2;
-            }
-            lwin[0] = lo;
-            lwin[1] = hi - lo <= MATCH_LDS_KEYS ? hi - lo : 0xFFFFFFFFu;
+        const uint32_t pl = uniform(pl_range[0]);
+        const uint64_t p = m.pair0 + pl;
+        const uint32_t a = uniform(m.ia ? m.ia[p] : m.ia0), b = uniform(m.ib ? m.ib[p] : m.ib0);
+        const uint64_t a0 = uniform64(m.A.bm_begin[a]), b0 = uniform64(m.B.bm_begin[b]);
+        const uint32_t KA = uniform((uint32_t)(m.A.bm_begin[a + 1] - a0));
+        const uint32_t KB = uniform((uint32_t)(m.B.bm_begin[b + 1] - b0));
+        const bool a_small = KA <= KB;
+        const uint16_t* sk = a_small ? m.A.keys + a0 : m.B.keys + b0;
+        const uint16_t* lk = a_small ? m.B.keys + b0 : m.A.keys + a0;
+        const uint32_t nl = a_small ? KB : KA;
+        if (wid < 2) {
+            const uint64_t u = (wid == 0 ? t0 : tl) - m.cand_off[pl];
+            const uint16_t key = (uint16_t)uniform(sk[u]);
+            const uint32_t j = wid == 0 ? wave_partition_point(nl, lane, [&](uint32_t i) { return lk[i] < key; })
+                                        : wave_partition_point(nl, lane, [&](uint32_t i) { return lk[i] <= key; });
+            if (lane == 0) lwin[wid] = j;
         }
         __syncthreads();
-        const uint32_t wn = uniform(lwin[1]);
-        if (wn != 0xFFFFFFFFu) {
-            const uint32_t pl = pl_range[0];
-            const uint64_t p = m.pair0 + pl;
-            const uint32_t a = m.ia ? m.ia[p] : m.ia0, b = m.ib ? m.ib[p] : m.ib0;
-            const uint64_t a0 = m.A.bm_begin[a], b0 = m.B.bm_begin[b];
-            const uint32_t KA = (uint32_t)(m.A.bm_begin[a + 1] - a0), KB = (uint32_t)(m.B.bm_begin[b + 1] - b0);
-            const uint16_t* lk = KA <= KB ? m.B.keys + b0 : m.A.keys + a0;
-            for (uint32_t i = threadIdx.x; i < wn; i += blockDim.x) lkeys[i] = lk[lwin[0] + i];
-        }
+        const uint32_t lo = uniform(lwin[0]), hi = uniform(lwin[1]);
+        win_lo = lo;
+        win_n = hi - lo <= MATCH_LDS_KEYS ? hi - lo : 0xFFFFFFFFu;
+        if (win_n != 0xFFFFFFFFu)
+            for (uint32_t i = threadIdx.x; i < win_n; i += blockDim.x) lkeys[i] = lk[lo + i];
         __syncthreads();
     }
-    const uint32_t win_n = one_pair ? uniform(lwin[1]) : 0xFFFFFFFFu;
-    const uint32_t win_lo = one_pair ? lwin[0] : 0u;
     uint64_t t = t0 + threadIdx.x;
     if (t < m.n_cand) {
         // largest pl in [lo, hi] with cand_off[pl] <= t

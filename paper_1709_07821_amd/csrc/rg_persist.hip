@@ -1,10 +1,11 @@
-// rg_persist.hip - one persistent, work-stealing kernel for all container
-// pairs of a batched count-only call. A fixed grid (a few workgroups per CU)
-// drains per-bin work counters with atomics, largest items first:
-// workgroup-sized tasks (generic LDS expansion, merge path), then wave-sized
-// tasks (bitset pairs, galloping search, bitset probes, run merges), each wave
-// grabbing its own, then thread-sized tasks (small array sides), 256 per grab.
-// Every wave exits when all counters are drained, so the grid always finishes.
+// rg_persist.hip - one persistent kernel for all container pairs of a batched
+// count-only call. A fixed grid (a few workgroups per CU) first takes its
+// static share of the thread-sized tasks (small array sides), then drains
+// per-bin work counters with atomics, largest items first: workgroup-sized
+// tasks (generic LDS expansion, merge path), then wave-sized tasks (bitset
+// pairs, galloping search, bitset probes, run merges), each wave grabbing its
+// own. Every wave exits when its share is done and all counters are drained,
+// so the grid always finishes.
 //
 // The kernel accumulates |A n B| per pair, whatever operation was asked for:
 // union, symmetric difference and difference counts follow from it and the
@@ -17,7 +18,24 @@ __global__ void __launch_bounds__(256) k_persist(PersistArgs a) {
     __shared__ WgShared sh;
     __shared__ uint32_t grab;
     const uint32_t lane = lane_id();
-    // workgroup-sized tasks
+    // thread-sized tasks (small array sides) first, split statically: chunk c
+    // of 256 consecutive items goes to workgroup c mod grid. They are many and
+    // of similar cost, so no counter is needed (a shared counter would be hit
+    // once per chunk by every workgroup).
+    {
+        const uint32_t cnt = uniform(a.bin_info[BIN_THREAD]), off = uniform(a.bin_info[NBINS + BIN_THREAD]);
+        for (uint32_t base = blockIdx.x * 256u; base < cnt; base += gridDim.x * 256u) {
+            const uint32_t i = base + threadIdx.x;
+            uint32_t pair = NONE, inter = 0;
+            if (i < cnt) {
+                const Task t = a.tasks[a.lists[off + i]];
+                inter = thread_inter(a.A, a.B, t);
+                pair = t.pair;
+            }
+            wave_aggregate_add(a.acc, pair, inter);
+        }
+    }
+    // workgroup-sized tasks, largest first, taken from a counter
 #pragma unroll 1
     for (int q = 0; q < 2; ++q) {
         const int b = q == 0 ? BIN_GEN : BIN_AA;
@@ -60,25 +78,6 @@ __global__ void __launch_bounds__(256) k_persist(PersistArgs a) {
                 const uint32_t inter = wave_inter(a.A, a.B, t, lane);
                 if (lane == 0) acc_add(a.acc, t.pair, (long long)inter);
             }
-        }
-    }
-    // thread-sized tasks: a workgroup takes 256 consecutive items per grab
-    {
-        const uint32_t cnt = uniform(a.bin_info[BIN_THREAD]), off = uniform(a.bin_info[NBINS + BIN_THREAD]);
-        for (;;) {
-            if (threadIdx.x == 0) grab = atomicAdd(&a.next[BIN_THREAD], 256u);
-            __syncthreads();
-            const uint32_t base = uniform(grab);
-            __syncthreads();
-            if (base >= cnt) break;
-            const uint32_t i = base + threadIdx.x;
-            uint32_t pair = NONE, inter = 0;
-            if (i < cnt) {
-                const Task t = a.tasks[a.lists[off + i]];
-                inter = thread_inter(a.A, a.B, t);
-                pair = t.pair;
-            }
-            wave_aggregate_add(a.acc, pair, inter);
         }
     }
 }
