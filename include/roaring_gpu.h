@@ -278,8 +278,10 @@ rg_status rg_dispatch_table(rg_ctx *ctx, uint8_t *h_table, uint64_t cap);
  * waits for them and returns the accumulated time, launch count and number of
  * container pairs processed for one variant (RG_V_* or 0 for the
  * bitset-bitset kernel, 8 for the bitset pairs redone
- * by the generic kernel) in count-only (materialize = 0) or materialising
- * form. Synchronises on the recorded events; costs two events per launch. */
+ * by the generic kernel, 9 for the small-array pairs of count-only calls that
+ * key matching counts itself: items only, their time is part of key matching)
+ * in count-only (materialize = 0) or materialising form. Synchronises on the
+ * recorded events; costs two events per launch. */
 rg_status rg_profile_enable(rg_ctx *ctx, int on);
 rg_status rg_profile_reset(rg_ctx *ctx);
 rg_status rg_profile_read(rg_ctx *ctx, int variant, int materialize, double *total_ms, uint64_t *launches,

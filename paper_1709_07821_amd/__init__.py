@@ -429,7 +429,7 @@ class Plan:
 
 
 PROFILE_CLASSES = {0: "bb", 1: "unused", 2: "generic", 3: "merge", 4: "gallop", 5: "probe", 6: "runmerge",
-                   7: "thread", 8: "bb-redo"}
+                   7: "thread", 8: "bb-redo", 9: "thread-fused"}
 
 
 def profile_enable(ctx: Context, on: bool = True):
@@ -447,7 +447,7 @@ def profile_read(ctx: Context):
         for m in (0, 1):
             ms, n, it = ctypes.c_double(), ctypes.c_uint64(), ctypes.c_uint64()
             ctx.check(lib().rg_profile_read(ctx.h, v, m, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(it)))
-            if n.value:
+            if n.value or it.value:  # the fused class has items but no launches
                 out[(name, bool(m))] = {"ms": ms.value, "launches": n.value, "items": it.value}
     return out
 

@@ -249,6 +249,9 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
             m.gallop_ratio = c->gallop_ratio;
             m.thread_max = c->thread_max;
             m.mlp_table = c->mlp_table;
+            // cost sampling times the thread kernel itself, so nothing is fused then
+            m.fuse_thread = !mat && !c->cost_out;
+            m.acc = acc;
             launch_match(m, st);
             if (mat) launch_scan_u32_u64(ub, slot_off, C, pay_base, partials, totals, st);
             launch_bin_layout(blk_cnt, match_blocks(C), blk_off, bpart, bin_total, bin_info, nullptr, st);
@@ -286,6 +289,10 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
             ca.so = SlotOut{slot_off, mat ? out->payload : nullptr, res_card, res_type, res_size, redo_list, redo_count};
             for (int b = 0; b < NBINS; ++b) {
                 if (!cnt[b]) continue;
+                if (b == BIN_FUSED) {  // already counted by key matching
+                    if (c->prof) c->prof_items[BIN_FUSED][mat ? 1 : 0] += cnt[b];
+                    continue;
+                }
                 ca.list = bin_lists + boff[b];
                 ca.n = cnt[b];
                 timed(c, b, mat, cnt[b], st, [&] {
@@ -306,7 +313,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
                 rd.list = redo_list;
                 rd.n = std::min<uint32_t>(cnt[BIN_BB], 4096u);
                 rd.n_dev = redo_count;
-                timed(c, NBINS - 1, mat, 0, st, [&] { launch_generic(rd, st); });
+                timed(c, PROF_REDO, mat, 0, st, [&] { launch_generic(rd, st); });
             }
         }
         HIPCHK(c, hipGetLastError());
@@ -622,6 +629,8 @@ void plan_enqueue(rg_plan* p, hipStream_t st) {
         m.gallop_ratio = p->gallop_ratio;
         m.thread_max = p->thread_max;
         m.mlp_table = p->ctx->mlp_table;
+        m.fuse_thread = true;
+        m.acc = p->acc;
         launch_match(m, st);
         launch_bin_layout(p->blk_cnt, match_blocks(w.C), p->blk_off, p->bpart, p->bin_total, p->bin_info, p->next,
                           st);

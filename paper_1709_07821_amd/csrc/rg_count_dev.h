@@ -158,11 +158,12 @@ __device__ __forceinline__ uint32_t wave_inter(const PoolView& PA, const PoolVie
 // |A n B| of one pair by one thread: every value of the smaller array side is
 // looked up in the other container (bit test, binary search in an array or
 // in the run starts). For small array sides only. Per-lane values throughout.
-__device__ __forceinline__ uint32_t thread_inter(const PoolView& PA, const PoolView& PB, const Task& t) {
-    uint8_t ta = PA.types[t.ia], tb = PB.types[t.ib];
-    uint32_t sa = PA.size[t.ia], sb = PB.size[t.ib];
-    const uint8_t* pa = PA.payload + PA.off[t.ia];
-    const uint8_t* pb = PB.payload + PB.off[t.ib];
+// The container types are passed in when the caller has read them already.
+__device__ __forceinline__ uint32_t thread_inter_typed(const PoolView& PA, const PoolView& PB, uint32_t ia,
+                                                       uint32_t ib, uint8_t ta, uint8_t tb) {
+    uint32_t sa = PA.size[ia], sb = PB.size[ib];
+    const uint8_t* pa = PA.payload + PA.off[ia];
+    const uint8_t* pb = PB.payload + PB.off[ib];
     // s: the array side (the smaller one when both are arrays); l: the other
     const bool a_is_s = ta == RG_ARRAY && (tb != RG_ARRAY || sa <= sb);
     const uint16_t* sv = reinterpret_cast<const uint16_t*>(a_is_s ? pa : pb);
@@ -195,6 +196,10 @@ __device__ __forceinline__ uint32_t thread_inter(const PoolView& PA, const PoolV
         for (uint32_t i = 0; i < n; ++i) hits += in_runs(lr, ln, sv[i]) ? 1u : 0u;
     }
     return hits;
+}
+
+__device__ __forceinline__ uint32_t thread_inter(const PoolView& PA, const PoolView& PB, const Task& t) {
+    return thread_inter_typed(PA, PB, t.ia, t.ib, PA.types[t.ia], PB.types[t.ib]);
 }
 
 // Adds each lane's value v to acc[pair] (lanes with pair == NONE add nothing)

@@ -29,7 +29,9 @@ enum : uint8_t {
     BIN_AB = 5,     // array op bitset (either order): probe / set / clear / flip
     BIN_RR = 6,     // run op run / run op array: interval merge
     BIN_THREAD = 7, // small array side: one thread per pair probes the other container
-    NBINS = 9       // bin NBINS - 1 only names the profile class of redone bitset pairs
+    PROF_REDO = 8,  // no bin: profile class of the bitset pairs redone by the generic kernel
+    BIN_FUSED = 9,  // small array sides counted inside key matching (count-only); never listed
+    NBINS = 10
 };
 
 struct Task {
@@ -200,6 +202,11 @@ struct MatchArgs {
     uint32_t gallop_ratio;
     uint32_t thread_max;  // largest array side handled one thread per pair
     const uint8_t* mlp_table;  // learned dispatch: bin per quantised feature cell (mode 1)
+    // count-only: pairs that land in BIN_THREAD are counted by the matching
+    // thread itself into acc[pair] (wave-aggregated atomics) and emitted as
+    // no-op tasks; their number goes to bin BIN_FUSED of blk_cnt
+    bool fuse_thread;
+    long long* acc;
 };
 
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st);

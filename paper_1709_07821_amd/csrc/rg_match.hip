@@ -1,7 +1,7 @@
 // rg_match.hip - per-pair preparation, key matching (the "high-level" merge of
 // two sorted key lists, Section 1 / Appendix A), variant selection (bins),
 // binning and the device prefix scan.
-#include "rg_internal.h"
+#include "rg_count_dev.h"
 
 namespace rg {
 
@@ -211,6 +211,7 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
         __syncthreads();
     }
     uint64_t t = t0 + threadIdx.x;
+    uint32_t fused_pair = NONE, fused_inter = 0;  // a small-array pair counted here
     if (t < m.n_cand) {
         // largest pl in [lo, hi] with cand_off[pl] <= t
         uint32_t lo = pl_range[0], hi = pl_range[1];
@@ -284,6 +285,13 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
                 uint32_t rb = need_r && tb == RG_RUN ? m.B.size[task.ib] : 0;
                 task.bin = classify(m.op, m.materialize, task.kind, ta, tb, ca, cb, ra, rb, m.dispatch_mode,
                                     m.fixed_bin, m.gallop_ratio, m.thread_max, m.mlp_table);
+                if (m.fuse_thread && task.bin == BIN_THREAD) {
+                    // the types are at hand: probe now instead of listing the pair
+                    fused_inter = thread_inter_typed(m.A, m.B, task.ia, task.ib, ta, tb);
+                    fused_pair = task.pair;
+                    task.kind = KIND_NOOP;
+                    task.bin = BIN_FUSED;
+                }
                 atomicAdd(&cnt[task.bin], 1u);
                 if (m.materialize) ub = wbytes_of(ca < cb ? ca : cb);
             }
@@ -292,6 +300,7 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
             if (m.materialize) m.ub[slot] = ub;
         }
     }
+    if (m.fuse_thread) wave_aggregate_add(m.acc, fused_pair, fused_inter);
     __syncthreads();
     if (threadIdx.x < NBINS) m.blk_cnt[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = cnt[threadIdx.x];
 }

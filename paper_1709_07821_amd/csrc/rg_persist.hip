@@ -14,6 +14,16 @@
 
 namespace rg {
 
+// Next item index from a bin's work counter. Read-modify-writes of one
+// address are serialised in its L2 channel, so thousands of waves asking an
+// exhausted counter would queue behind each other: a coherent plain read
+// first, and the atomic only while items remain. A stale read only costs the
+// atomic; the atomic's result decides.
+__device__ __forceinline__ uint32_t take_next(uint32_t* next, uint32_t cnt) {
+    const uint32_t seen = __hip_atomic_load(next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return seen >= cnt ? seen : atomicAdd(next, 1u);
+}
+
 __global__ void __launch_bounds__(256) k_persist(PersistArgs a) {
     __shared__ WgShared sh;
     __shared__ uint32_t grab;
@@ -40,8 +50,9 @@ __global__ void __launch_bounds__(256) k_persist(PersistArgs a) {
     for (int q = 0; q < 2; ++q) {
         const int b = q == 0 ? BIN_GEN : BIN_AA;
         const uint32_t cnt = uniform(a.bin_info[b]), off = uniform(a.bin_info[NBINS + b]);
+        if (cnt == 0) continue;
         for (;;) {
-            if (threadIdx.x == 0) grab = atomicAdd(&a.next[b], 1u);
+            if (threadIdx.x == 0) grab = take_next(&a.next[b], cnt);
             __syncthreads();
             const uint32_t i = uniform(grab);
             __syncthreads();
@@ -63,11 +74,12 @@ __global__ void __launch_bounds__(256) k_persist(PersistArgs a) {
     for (int q = 0; q < 4; ++q) {
         const int b = q == 0 ? BIN_BB : q == 1 ? BIN_GALLOP : q == 2 ? BIN_AB : BIN_RR;
         const uint32_t cnt = uniform(a.bin_info[b]), off = uniform(a.bin_info[NBINS + b]);
+        if (cnt == 0) continue;
         for (;;) {
             // lane 0 takes the next item; readlane makes the index a scalar, so
             // the loop exit below is one branch for the whole wave
             uint32_t v = 0;
-            if (lane == 0) v = atomicAdd(&a.next[b], 1u);
+            if (lane == 0) v = take_next(&a.next[b], cnt);
             const uint32_t i = __builtin_amdgcn_readlane(v, 0);
             if (i >= cnt) break;
             const Task t = uniform_task(a.tasks, uniform(a.lists[off + i]));
