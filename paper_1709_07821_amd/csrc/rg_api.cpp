@@ -831,7 +831,9 @@ rg_status rg_plan_tune(rg_plan* p, void* stream, int reps) {
     };
     // coordinate descent: thread-size threshold, then grid, then galloping ratio
     const bool heur = p->dispatch_mode == RG_DISPATCH_HEURISTIC;
-    std::vector<uint32_t> tvals = heur ? std::vector<uint32_t>{0, 4, 16, 64} : std::vector<uint32_t>{};
+    // (no threshold 0: without a thread variant the many one-value arrays of a
+    // typical pool become workgroup merges, hundreds of times slower)
+    std::vector<uint32_t> tvals = heur ? std::vector<uint32_t>{4, 16, 64} : std::vector<uint32_t>{};
     std::vector<uint32_t> gvals;
     for (uint32_t f : {2u, 4u, 8u, 12u, 16u}) gvals.push_back((uint32_t)cus * f);
     std::vector<uint32_t> rvals = heur ? std::vector<uint32_t>{8, 32, 128, 512} : std::vector<uint32_t>{};
