@@ -255,7 +255,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
             launch_match(m, st);
             if (mat) launch_scan_u32_u64(ub, slot_off, C, pay_base, partials, totals, st);
             launch_bin_layout(blk_cnt, match_blocks(C), blk_off, bpart, bin_total, bin_info, nullptr, st);
-            launch_bin_scatter(tasks, C, blk_off, bin_lists, st);
+            launch_bin_scatter(tasks, C, blk_cnt, blk_off, bin_lists, st);
             HIPCHK(c, hipMemcpyAsync(h_small, bin_info, 8 * NBINS, hipMemcpyDeviceToHost, st));
             if (mat) HIPCHK(c, hipMemcpyAsync(h_small + 64, totals, 8, hipMemcpyDeviceToHost, st));
             HIPCHK(c, hipStreamSynchronize(st));
@@ -634,7 +634,7 @@ void plan_enqueue(rg_plan* p, hipStream_t st) {
         launch_match(m, st);
         launch_bin_layout(p->blk_cnt, match_blocks(w.C), p->blk_off, p->bpart, p->bin_total, p->bin_info, p->next,
                           st);
-        launch_bin_scatter(p->tasks, w.C, p->blk_off, p->lists, st);
+        launch_bin_scatter(p->tasks, w.C, p->blk_cnt, p->blk_off, p->lists, st);
         PersistArgs a{pa, pb, p->tasks, p->lists, p->bin_info, p->next, p->acc};
         launch_persist(a, p->grid, st);
     }

@@ -223,7 +223,8 @@ void launch_match(const MatchArgs& m, hipStream_t st);
 inline uint32_t match_blocks(uint64_t n_cand) { return (uint32_t)((n_cand + 255) / 256); }
 void launch_bin_layout(const uint32_t* blk_cnt, uint32_t nblk, uint64_t* blk_off, uint64_t* partials, uint64_t* total,
                        uint32_t* bin_info, uint32_t* next, hipStream_t st);
-void launch_bin_scatter(const Task* tasks, uint64_t n, const uint64_t* blk_off, uint32_t* bin_lists, hipStream_t st);
+void launch_bin_scatter(const Task* tasks, uint64_t n, const uint32_t* blk_cnt, const uint64_t* blk_off,
+                        uint32_t* bin_lists, hipStream_t st);
 // exclusive scan of u32 into u64 with an added base; writes total to *total_out (device)
 void launch_scan_u32_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t base, uint64_t* partials,
                          uint64_t* total_out, hipStream_t st);

@@ -184,13 +184,21 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
     // (first key >= the first candidate), wave 1 its end (first key > the last).
     const bool one_pair = !m.materialize && uniform(pl_range[0]) == uniform(pl_range[1]);
     uint32_t win_n = 0xFFFFFFFFu, win_lo = 0;  // staged window: none
+    // the block's pair, when it has one: container ranges of both sides
+    uint64_t o_a0 = 0, o_b0 = 0;
+    uint32_t o_KA = 0, o_KB = 0, o_pl = 0;
     if (one_pair) {
         const uint32_t pl = uniform(pl_range[0]);
+        o_pl = pl;
         const uint64_t p = m.pair0 + pl;
         const uint32_t a = uniform(m.ia ? m.ia[p] : m.ia0), b = uniform(m.ib ? m.ib[p] : m.ib0);
         const uint64_t a0 = uniform64(m.A.bm_begin[a]), b0 = uniform64(m.B.bm_begin[b]);
         const uint32_t KA = uniform((uint32_t)(m.A.bm_begin[a + 1] - a0));
         const uint32_t KB = uniform((uint32_t)(m.B.bm_begin[b + 1] - b0));
+        o_a0 = a0;
+        o_b0 = b0;
+        o_KA = KA;
+        o_KB = KB;
         const bool a_small = KA <= KB;
         const uint16_t* sk = a_small ? m.A.keys + a0 : m.B.keys + b0;
         const uint16_t* lk = a_small ? m.B.keys + b0 : m.A.keys + a0;
@@ -212,51 +220,67 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
     }
     uint64_t t = t0 + threadIdx.x;
     uint32_t fused_pair = NONE, fused_inter = 0;  // a small-array pair counted here
+    Task task{};
+    uint64_t slot = NONE;
     if (t < m.n_cand) {
-        // largest pl in [lo, hi] with cand_off[pl] <= t
-        uint32_t lo = pl_range[0], hi = pl_range[1];
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (m.cand_off[mid] <= t) lo = mid;
-            else hi = mid - 1;
+        uint32_t pl;
+        uint64_t a0, b0;
+        uint32_t KA, KB;
+        if (one_pair) {
+            pl = o_pl;
+            a0 = o_a0;
+            b0 = o_b0;
+            KA = o_KA;
+            KB = o_KB;
+        } else {
+            // largest pl in [lo, hi] with cand_off[pl] <= t
+            uint32_t lo = pl_range[0], hi = pl_range[1];
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) >> 1;
+                if (m.cand_off[mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            pl = lo;
+            const uint64_t pp = m.pair0 + pl;
+            const uint32_t a = m.ia ? m.ia[pp] : m.ia0;
+            const uint32_t b = m.ib ? m.ib[pp] : m.ib0;
+            a0 = m.A.bm_begin[a];
+            b0 = m.B.bm_begin[b];
+            KA = (uint32_t)(m.A.bm_begin[a + 1] - a0);
+            KB = (uint32_t)(m.B.bm_begin[b + 1] - b0);
         }
-        uint32_t pl = lo;
-        uint64_t p = m.pair0 + pl;
-        uint64_t u = t - m.cand_off[pl];
-        uint32_t a = m.ia ? m.ia[p] : m.ia0;
-        uint32_t b = m.ib ? m.ib[p] : m.ib0;
-        uint64_t a0 = m.A.bm_begin[a], b0 = m.B.bm_begin[b];
-        uint32_t KA = (uint32_t)(m.A.bm_begin[a + 1] - a0);
-        uint32_t KB = (uint32_t)(m.B.bm_begin[b + 1] - b0);
-        Task task;
+        const uint64_t p = m.pair0 + pl;
+        const uint64_t u = t - m.cand_off[pl];
         task.pair = (uint32_t)p;
         task.ia = NONE;
         task.ib = NONE;
         task.kind = KIND_NOOP;
         task.bin = 0xFF;
-        uint64_t slot = NONE;
         if (!m.materialize) {
-            // count only: candidates from the side with fewer keys
-            if (KA <= KB) {
-                uint16_t key = m.A.keys[a0 + u];
-                uint32_t j = win_n != 0xFFFFFFFFu ? win_lo + lower_bound_u16(lkeys, win_n, key)
-                                                  : lower_bound_u16(m.B.keys + b0, KB, key);
-                task.key = key;
-                if (j < KB && m.B.keys[b0 + j] == key) {
-                    task.kind = KIND_MATCH;
-                    task.ia = (uint32_t)(a0 + u);
-                    task.ib = (uint32_t)(b0 + j);
-                }
+            // count only: candidates from the side with fewer keys; the other
+            // side is searched in the staged window when there is one (a key
+            // past the window's end cannot match: the window ends at the first
+            // key above the block's last candidate)
+            const bool a_small = KA <= KB;
+            const uint16_t* sk = a_small ? m.A.keys + a0 : m.B.keys + b0;
+            const uint16_t* lk = a_small ? m.B.keys + b0 : m.A.keys + a0;
+            const uint32_t nl = a_small ? KB : KA;
+            const uint16_t key = sk[u];
+            uint32_t j;
+            bool hit;
+            if (win_n != 0xFFFFFFFFu) {
+                const uint32_t jl = lower_bound_u16(lkeys, win_n, key);
+                hit = jl < win_n && lkeys[jl] == key;
+                j = win_lo + jl;
             } else {
-                uint16_t key = m.B.keys[b0 + u];
-                uint32_t i = win_n != 0xFFFFFFFFu ? win_lo + lower_bound_u16(lkeys, win_n, key)
-                                                  : lower_bound_u16(m.A.keys + a0, KA, key);
-                task.key = key;
-                if (i < KA && m.A.keys[a0 + i] == key) {
-                    task.kind = KIND_MATCH;
-                    task.ia = (uint32_t)(a0 + i);
-                    task.ib = (uint32_t)(b0 + u);
-                }
+                j = lower_bound_u16(lk, nl, key);
+                hit = j < nl && lk[j] == key;
+            }
+            task.key = key;
+            if (hit) {
+                task.kind = KIND_MATCH;
+                task.ia = (uint32_t)(a_small ? a0 + u : a0 + j);
+                task.ib = (uint32_t)(a_small ? b0 + j : b0 + u);
             }
             slot = t;
         } else {
@@ -295,14 +319,20 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
                 atomicAdd(&cnt[task.bin], 1u);
                 if (m.materialize) ub = wbytes_of(ca < cb ? ca : cb);
             }
-            m.tasks[slot] = task;
-            m.res_card[slot] = 0;
-            if (m.materialize) m.ub[slot] = ub;
+            if (m.materialize) {
+                m.res_card[slot] = 0;
+                m.ub[slot] = ub;
+            }
         }
     }
     if (m.fuse_thread) wave_aggregate_add(m.acc, fused_pair, fused_inter);
     __syncthreads();
     if (threadIdx.x < NBINS) m.blk_cnt[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = cnt[threadIdx.x];
+    // With fusion, the tasks of a block that lists nothing are never read
+    // (binning skips such blocks), so they are not written.
+    uint32_t listed = 0;
+    for (int b = 0; b < NBINS; ++b) listed += b == BIN_FUSED ? 0u : cnt[b];
+    if (slot != NONE && (listed || !m.fuse_thread)) m.tasks[slot] = task;
 }
 
 void launch_match(const MatchArgs& m, hipStream_t st) {
@@ -332,11 +362,20 @@ void launch_bin_layout(const uint32_t* blk_cnt, uint32_t nblk, uint64_t* blk_off
 
 // Slot ids into per-bin lists: the same 256-slot blocks as k_match, each
 // block's slots of bin b go to blk_off[b][block] + rank (rank from LDS atomics).
-__global__ void __launch_bounds__(256) k_bin_scatter(const Task* tasks, uint64_t n, const uint64_t* blk_off,
-                                                     uint32_t* lists) {
+// A block whose counts list nothing returns at once (its tasks may be unwritten).
+__global__ void __launch_bounds__(256) k_bin_scatter(const Task* tasks, uint64_t n, const uint32_t* blk_cnt,
+                                                     const uint64_t* blk_off, uint32_t* lists) {
     __shared__ uint32_t cnt[NBINS];
+    __shared__ uint32_t listed;
     if (threadIdx.x < NBINS) cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        uint32_t l = 0;
+        for (int b = 0; b < NBINS; ++b)
+            if (b != BIN_FUSED) l += blk_cnt[(uint64_t)b * gridDim.x + blockIdx.x];
+        listed = l;
+    }
     __syncthreads();
+    if (uniform(listed) == 0) return;
     uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s < n) {
         Task t = tasks[s];
@@ -347,9 +386,10 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const Task* tasks, uint64_t
     }
 }
 
-void launch_bin_scatter(const Task* tasks, uint64_t n, const uint64_t* blk_off, uint32_t* bin_lists, hipStream_t st) {
+void launch_bin_scatter(const Task* tasks, uint64_t n, const uint32_t* blk_cnt, const uint64_t* blk_off,
+                        uint32_t* bin_lists, hipStream_t st) {
     if (!n) return;
-    hipLaunchKernelGGL(k_bin_scatter, dim3(match_blocks(n)), dim3(256), 0, st, tasks, n, blk_off, bin_lists);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(match_blocks(n)), dim3(256), 0, st, tasks, n, blk_cnt, blk_off, bin_lists);
 }
 
 // ------------------------------------------------------------------ scan
