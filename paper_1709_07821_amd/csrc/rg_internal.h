@@ -196,7 +196,7 @@ struct MatchArgs {
     Task* tasks;              // [n_cand]
     uint32_t* ub;             // [n_cand] slot payload bound in bytes (materialize)
     uint32_t* res_card;       // [n_cand]
-    uint32_t* blk_cnt;        // [NBINS][ceil(n_cand / 256)]: per-block bin counts, bin-major
+    uint32_t* blk_cnt;        // [NBINS][match_blocks(n_cand)]: per-block bin counts, bin-major
     int dispatch_mode;        // 0 heuristic, 1 learned (mlp_table), 2 fixed
     int fixed_bin;
     uint32_t gallop_ratio;
@@ -220,7 +220,11 @@ void launch_match(const MatchArgs& m, hipStream_t st);
 // exclusive scan of them (bin-major) gives each block's place in each bin's
 // list, and the bins' counts and offsets (bin_info[0..NBINS) counts,
 // bin_info[NBINS..2 NBINS) offsets; next[] work counters reset when given).
-inline uint32_t match_blocks(uint64_t n_cand) { return (uint32_t)((n_cand + 255) / 256); }
+// A key-matching block takes MATCH_SLOTS consecutive candidate slots, each of
+// its 256 threads MATCH_PER_THREAD of them.
+constexpr uint32_t MATCH_PER_THREAD = 4;
+constexpr uint32_t MATCH_SLOTS = 256 * MATCH_PER_THREAD;
+inline uint32_t match_blocks(uint64_t n_cand) { return (uint32_t)((n_cand + MATCH_SLOTS - 1) / MATCH_SLOTS); }
 void launch_bin_layout(const uint32_t* blk_cnt, uint32_t nblk, uint64_t* blk_off, uint64_t* partials, uint64_t* total,
                        uint32_t* bin_info, uint32_t* next, hipStream_t st);
 void launch_bin_scatter(const Task* tasks, uint64_t n, const uint32_t* blk_cnt, const uint64_t* blk_off,

@@ -159,185 +159,238 @@ __device__ __forceinline__ uint8_t classify(int op, bool materialize, uint8_t ki
     return BIN_RR;      // run-run, run-bitset
 }
 
-constexpr uint32_t MATCH_LDS_KEYS = 2048;
+constexpr uint32_t MATCH_LDS_KEYS = 4096;
 
+// What matching decided for one candidate slot.
+struct SlotOutcome {
+    Task task;
+    uint64_t slot;        // NONE: no slot
+    uint32_t fused_pair;  // NONE: nothing counted in place
+    uint32_t fused_inter;
+};
+
+// Variant choice (and, when fusing, the in-place count) of a candidate whose
+// match is known; task.ia / task.ib / task.kind are set.
+__device__ __forceinline__ void finish_slot(const MatchArgs& m, uint32_t* cnt, SlotOutcome& o) {
+    Task& task = o.task;
+    uint32_t ub = 0;
+    if (task.kind != KIND_NOOP) {
+        const uint8_t ta = task.ia != NONE ? m.A.types[task.ia] : 0;
+        const uint8_t tb = task.ib != NONE ? m.B.types[task.ib] : 0;
+        const uint32_t ca = task.ia != NONE ? m.A.card[task.ia] : 0;
+        const uint32_t cb = task.ib != NONE ? m.B.card[task.ib] : 0;
+        const bool need_r = m.dispatch_mode == 1;
+        const uint32_t ra = need_r && ta == RG_RUN ? m.A.size[task.ia] : 0;
+        const uint32_t rb = need_r && tb == RG_RUN ? m.B.size[task.ib] : 0;
+        task.bin = classify(m.op, m.materialize, task.kind, ta, tb, ca, cb, ra, rb, m.dispatch_mode, m.fixed_bin,
+                            m.gallop_ratio, m.thread_max, m.mlp_table);
+        if (m.fuse_thread && task.bin == BIN_THREAD) {
+            // the types are at hand: probe now instead of listing the pair
+            o.fused_inter = thread_inter_typed(m.A, m.B, task.ia, task.ib, ta, tb);
+            o.fused_pair = task.pair;
+            task.kind = KIND_NOOP;
+            task.bin = BIN_FUSED;
+        }
+        atomicAdd(&cnt[task.bin], 1u);
+        if (m.materialize) ub = wbytes_of(ca < cb ? ca : cb);
+    }
+    if (m.materialize) {
+        m.res_card[o.slot] = 0;
+        m.ub[o.slot] = ub;
+    }
+}
+
+// One candidate slot t of a block without a staged window: its pair is
+// searched among the block's pairs [pl_lo, pl_hi], the other side's keys in
+// global memory.
+__device__ __forceinline__ void match_slot_global(const MatchArgs& m, uint64_t t, uint32_t pl_lo, uint32_t pl_hi,
+                                                  uint32_t* cnt, SlotOutcome& o) {
+    uint32_t lo = pl_lo, hi = pl_hi;  // largest pl in [lo, hi] with cand_off[pl] <= t
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (m.cand_off[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const uint32_t pl = lo;
+    const uint64_t p = m.pair0 + pl;
+    const uint32_t a = m.ia ? m.ia[p] : m.ia0;
+    const uint32_t b = m.ib ? m.ib[p] : m.ib0;
+    const uint64_t a0 = m.A.bm_begin[a], b0 = m.B.bm_begin[b];
+    const uint32_t KA = (uint32_t)(m.A.bm_begin[a + 1] - a0);
+    const uint32_t KB = (uint32_t)(m.B.bm_begin[b + 1] - b0);
+    const uint64_t u = t - m.cand_off[pl];
+    Task& task = o.task;
+    task.pair = (uint32_t)p;
+    if (!m.materialize) {
+        // count only: candidates from the side with fewer keys
+        const bool a_small = KA <= KB;
+        const uint16_t* sk = a_small ? m.A.keys + a0 : m.B.keys + b0;
+        const uint16_t* lk = a_small ? m.B.keys + b0 : m.A.keys + a0;
+        const uint32_t nl = a_small ? KB : KA;
+        const uint16_t key = sk[u];
+        const uint32_t j = lower_bound_u16(lk, nl, key);
+        task.key = key;
+        if (j < nl && lk[j] == key) {
+            task.kind = KIND_MATCH;
+            task.ia = (uint32_t)(a_small ? a0 + u : a0 + j);
+            task.ib = (uint32_t)(a_small ? b0 + j : b0 + u);
+        }
+    } else {
+        // materialised intersection: one slot per key of A, in A's key order
+        // (the other operations materialise through the k-way path)
+        const uint16_t key = m.A.keys[a0 + u];
+        const uint32_t j = lower_bound_u16(m.B.keys + b0, KB, key);
+        task.key = key;
+        task.ia = (uint32_t)(a0 + u);
+        if (j < KB && m.B.keys[b0 + j] == key) {
+            task.kind = KIND_MATCH;
+            task.ib = (uint32_t)(b0 + j);
+        }
+    }
+    o.slot = t;
+    finish_slot(m, cnt, o);
+}
+
+// Key matching. A block takes MATCH_SLOTS consecutive candidate slots; each
+// thread carries MATCH_PER_THREAD of them (slots t0 + k * 256 + thread) through
+// the same steps, so that their loads overlap.
 __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
     __shared__ uint32_t cnt[NBINS];
     __shared__ uint32_t pl_range[2];
     __shared__ uint16_t lkeys[MATCH_LDS_KEYS];
-    __shared__ uint32_t lwin[2];  // [0] first index of the staged window in the searched list, [1] its length
+    __shared__ uint32_t lwin[2];  // first index of the staged window in the searched list, and its end
     if (threadIdx.x < NBINS) cnt[threadIdx.x] = 0;
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
     // the pairs of this block's first and last candidate bound every thread's
     // search: wave 0 finds the first, wave 1 the last
-    const uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x;
-    const uint64_t tl = t0 + blockDim.x - 1 < m.n_cand ? t0 + blockDim.x - 1 : m.n_cand - 1;
+    const uint64_t t0 = (uint64_t)blockIdx.x * MATCH_SLOTS;
+    const uint64_t tl = t0 + MATCH_SLOTS - 1 < m.n_cand ? t0 + MATCH_SLOTS - 1 : m.n_cand - 1;
     if (wid < 2) {
         const uint32_t pl = wave_find_pair(m.cand_off, m.n_pairs, wid == 0 ? t0 : tl, lane);
         if (lane == 0) pl_range[wid] = pl;
     }
     __syncthreads();
+    const uint32_t pl_lo = uniform(pl_range[0]), pl_hi = uniform(pl_range[1]);
     // Count-only block whose candidates all belong to one pair: its candidate
     // keys are consecutive keys of the pair's smaller side, so the matching keys
     // of the other side lie in one window; stage that window in LDS and search
     // there instead of in global memory. Wave 0 finds the window's first index
     // (first key >= the first candidate), wave 1 its end (first key > the last).
-    const bool one_pair = !m.materialize && uniform(pl_range[0]) == uniform(pl_range[1]);
-    uint32_t win_n = 0xFFFFFFFFu, win_lo = 0;  // staged window: none
-    // the block's pair, when it has one: container ranges of both sides
-    uint64_t o_a0 = 0, o_b0 = 0;
-    uint32_t o_KA = 0, o_KB = 0, o_pl = 0;
-    if (one_pair) {
-        const uint32_t pl = uniform(pl_range[0]);
-        o_pl = pl;
-        const uint64_t p = m.pair0 + pl;
+    bool staged = false;
+    uint64_t o_a0 = 0, o_b0 = 0, o_base = 0;
+    uint32_t o_p = 0, win_lo = 0, win_n = 0;
+    bool o_a_small = true;
+    const uint16_t* o_sk = nullptr;
+    if (!m.materialize && pl_lo == pl_hi) {
+        const uint64_t p = m.pair0 + pl_lo;
         const uint32_t a = uniform(m.ia ? m.ia[p] : m.ia0), b = uniform(m.ib ? m.ib[p] : m.ib0);
         const uint64_t a0 = uniform64(m.A.bm_begin[a]), b0 = uniform64(m.B.bm_begin[b]);
         const uint32_t KA = uniform((uint32_t)(m.A.bm_begin[a + 1] - a0));
         const uint32_t KB = uniform((uint32_t)(m.B.bm_begin[b + 1] - b0));
-        o_a0 = a0;
-        o_b0 = b0;
-        o_KA = KA;
-        o_KB = KB;
         const bool a_small = KA <= KB;
         const uint16_t* sk = a_small ? m.A.keys + a0 : m.B.keys + b0;
         const uint16_t* lk = a_small ? m.B.keys + b0 : m.A.keys + a0;
         const uint32_t nl = a_small ? KB : KA;
+        const uint64_t base = uniform64(m.cand_off[pl_lo]);
         if (wid < 2) {
-            const uint64_t u = (wid == 0 ? t0 : tl) - m.cand_off[pl];
-            const uint16_t key = (uint16_t)uniform(sk[u]);
+            const uint16_t key = (uint16_t)uniform(sk[(wid == 0 ? t0 : tl) - base]);
             const uint32_t j = wid == 0 ? wave_partition_point(nl, lane, [&](uint32_t i) { return lk[i] < key; })
                                         : wave_partition_point(nl, lane, [&](uint32_t i) { return lk[i] <= key; });
             if (lane == 0) lwin[wid] = j;
         }
         __syncthreads();
         const uint32_t lo = uniform(lwin[0]), hi = uniform(lwin[1]);
-        win_lo = lo;
-        win_n = hi - lo <= MATCH_LDS_KEYS ? hi - lo : 0xFFFFFFFFu;
-        if (win_n != 0xFFFFFFFFu)
-            for (uint32_t i = threadIdx.x; i < win_n; i += blockDim.x) lkeys[i] = lk[lo + i];
+        if (hi - lo <= MATCH_LDS_KEYS) {
+            staged = true;
+            for (uint32_t i = threadIdx.x; i < hi - lo; i += blockDim.x) lkeys[i] = lk[lo + i];
+        }
         __syncthreads();
+        o_a0 = a0;
+        o_b0 = b0;
+        o_base = base;
+        o_p = (uint32_t)p;
+        win_lo = lo;
+        win_n = hi - lo;
+        o_a_small = a_small;
+        o_sk = sk;
     }
-    uint64_t t = t0 + threadIdx.x;
-    uint32_t fused_pair = NONE, fused_inter = 0;  // a small-array pair counted here
-    Task task{};
-    uint64_t slot = NONE;
-    if (t < m.n_cand) {
-        uint32_t pl;
-        uint64_t a0, b0;
-        uint32_t KA, KB;
-        if (one_pair) {
-            pl = o_pl;
-            a0 = o_a0;
-            b0 = o_b0;
-            KA = o_KA;
-            KB = o_KB;
-        } else {
-            // largest pl in [lo, hi] with cand_off[pl] <= t
-            uint32_t lo = pl_range[0], hi = pl_range[1];
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi + 1) >> 1;
-                if (m.cand_off[mid] <= t) lo = mid;
-                else hi = mid - 1;
-            }
-            pl = lo;
-            const uint64_t pp = m.pair0 + pl;
-            const uint32_t a = m.ia ? m.ia[pp] : m.ia0;
-            const uint32_t b = m.ib ? m.ib[pp] : m.ib0;
-            a0 = m.A.bm_begin[a];
-            b0 = m.B.bm_begin[b];
-            KA = (uint32_t)(m.A.bm_begin[a + 1] - a0);
-            KB = (uint32_t)(m.B.bm_begin[b + 1] - b0);
+    SlotOutcome o[MATCH_PER_THREAD];
+#pragma unroll
+    for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
+        o[k].task = Task{};
+        o[k].task.ia = NONE;
+        o[k].task.ib = NONE;
+        o[k].task.kind = KIND_NOOP;
+        o[k].task.bin = 0xFF;
+        o[k].slot = NONE;
+        o[k].fused_pair = NONE;
+        o[k].fused_inter = 0;
+    }
+    if (staged) {
+        // every step for all of the thread's candidates before the next step
+        uint32_t top = 0;
+        if (win_n) top = 1u << (31 - __builtin_clz(win_n));
+        uint16_t key[MATCH_PER_THREAD];
+        uint32_t jl[MATCH_PER_THREAD];
+#pragma unroll
+        for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
+            const uint64_t t = t0 + (uint64_t)k * 256 + threadIdx.x;
+            key[k] = t < m.n_cand ? o_sk[t - o_base] : (uint16_t)0;
+            jl[k] = 0;
         }
-        const uint64_t p = m.pair0 + pl;
-        const uint64_t u = t - m.cand_off[pl];
-        task.pair = (uint32_t)p;
-        task.ia = NONE;
-        task.ib = NONE;
-        task.kind = KIND_NOOP;
-        task.bin = 0xFF;
-        if (!m.materialize) {
-            // count only: candidates from the side with fewer keys; the other
-            // side is searched in the staged window when there is one (a key
-            // past the window's end cannot match: the window ends at the first
-            // key above the block's last candidate)
-            const bool a_small = KA <= KB;
-            const uint16_t* sk = a_small ? m.A.keys + a0 : m.B.keys + b0;
-            const uint16_t* lk = a_small ? m.B.keys + b0 : m.A.keys + a0;
-            const uint32_t nl = a_small ? KB : KA;
-            const uint16_t key = sk[u];
-            uint32_t j;
-            bool hit;
-            if (win_n != 0xFFFFFFFFu) {
-                const uint32_t jl = lower_bound_u16(lkeys, win_n, key);
-                hit = jl < win_n && lkeys[jl] == key;
-                j = win_lo + jl;
-            } else {
-                j = lower_bound_u16(lk, nl, key);
-                hit = j < nl && lk[j] == key;
-            }
-            task.key = key;
-            if (hit) {
-                task.kind = KIND_MATCH;
-                task.ia = (uint32_t)(a_small ? a0 + u : a0 + j);
-                task.ib = (uint32_t)(a_small ? b0 + j : b0 + u);
-            }
-            slot = t;
-        } else {
-            // materialised intersection: one slot per key of A, in A's key
-            // order (the other operations materialise through the k-way path)
-            uint16_t key = m.A.keys[a0 + u];
-            uint32_t j = lower_bound_u16(m.B.keys + b0, KB, key);
-            bool hit = j < KB && m.B.keys[b0 + j] == key;
-            task.key = key;
-            task.ia = (uint32_t)(a0 + u);
-            if (hit) {
-                task.kind = KIND_MATCH;
-                task.ib = (uint32_t)(b0 + j);
-            }
-            slot = m.cand_off[pl] + u;
+        for (uint32_t step = top; step; step >>= 1) {
+#pragma unroll
+            for (int k = 0; k < (int)MATCH_PER_THREAD; ++k)
+                if (jl[k] + step <= win_n && lkeys[jl[k] + step - 1] < key[k]) jl[k] += step;
         }
-        if (slot != NONE) {
-            uint32_t ub = 0;
-            if (task.kind != KIND_NOOP) {
-                uint8_t ta = task.ia != NONE ? m.A.types[task.ia] : 0;
-                uint8_t tb = task.ib != NONE ? m.B.types[task.ib] : 0;
-                uint32_t ca = task.ia != NONE ? m.A.card[task.ia] : 0;
-                uint32_t cb = task.ib != NONE ? m.B.card[task.ib] : 0;
-                const bool need_r = m.dispatch_mode == 1;
-                uint32_t ra = need_r && ta == RG_RUN ? m.A.size[task.ia] : 0;
-                uint32_t rb = need_r && tb == RG_RUN ? m.B.size[task.ib] : 0;
-                task.bin = classify(m.op, m.materialize, task.kind, ta, tb, ca, cb, ra, rb, m.dispatch_mode,
-                                    m.fixed_bin, m.gallop_ratio, m.thread_max, m.mlp_table);
-                if (m.fuse_thread && task.bin == BIN_THREAD) {
-                    // the types are at hand: probe now instead of listing the pair
-                    fused_inter = thread_inter_typed(m.A, m.B, task.ia, task.ib, ta, tb);
-                    fused_pair = task.pair;
-                    task.kind = KIND_NOOP;
-                    task.bin = BIN_FUSED;
-                }
-                atomicAdd(&cnt[task.bin], 1u);
-                if (m.materialize) ub = wbytes_of(ca < cb ? ca : cb);
+#pragma unroll
+        for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
+            const uint64_t t = t0 + (uint64_t)k * 256 + threadIdx.x;
+            if (t >= m.n_cand) continue;
+            // a key past the window's end cannot match: the window ends at the
+            // first key above the block's last candidate
+            const uint64_t u = t - o_base;
+            const uint32_t j = win_lo + jl[k];
+            Task& task = o[k].task;
+            task.pair = o_p;
+            task.key = key[k];
+            if (jl[k] < win_n && lkeys[jl[k]] == key[k]) {
+                task.kind = KIND_MATCH;
+                task.ia = (uint32_t)(o_a_small ? o_a0 + u : o_a0 + j);
+                task.ib = (uint32_t)(o_a_small ? o_b0 + j : o_b0 + u);
             }
-            if (m.materialize) {
-                m.res_card[slot] = 0;
-                m.ub[slot] = ub;
-            }
+            o[k].slot = t;
+        }
+#pragma unroll
+        for (int k = 0; k < (int)MATCH_PER_THREAD; ++k)
+            if (o[k].slot != NONE) finish_slot(m, cnt, o[k]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
+            const uint64_t t = t0 + (uint64_t)k * 256 + threadIdx.x;
+            if (t < m.n_cand) match_slot_global(m, t, pl_lo, pl_hi, cnt, o[k]);
         }
     }
-    if (m.fuse_thread) wave_aggregate_add(m.acc, fused_pair, fused_inter);
+    if (m.fuse_thread) {
+#pragma unroll
+        for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) wave_aggregate_add(m.acc, o[k].fused_pair, o[k].fused_inter);
+    }
     __syncthreads();
     if (threadIdx.x < NBINS) m.blk_cnt[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = cnt[threadIdx.x];
     // With fusion, the tasks of a block that lists nothing are never read
     // (binning skips such blocks), so they are not written.
     uint32_t listed = 0;
     for (int b = 0; b < NBINS; ++b) listed += b == BIN_FUSED ? 0u : cnt[b];
-    if (slot != NONE && (listed || !m.fuse_thread)) m.tasks[slot] = task;
+    if (listed || !m.fuse_thread) {
+#pragma unroll
+        for (int k = 0; k < (int)MATCH_PER_THREAD; ++k)
+            if (o[k].slot != NONE) m.tasks[o[k].slot] = o[k].task;
+    }
 }
 
 void launch_match(const MatchArgs& m, hipStream_t st) {
     if (!m.n_cand) return;
-    hipLaunchKernelGGL(k_match, dim3((uint32_t)((m.n_cand + 255) / 256)), dim3(256), 0, st, m);
+    hipLaunchKernelGGL(k_match, dim3(match_blocks(m.n_cand)), dim3(256), 0, st, m);
 }
 
 // ------------------------------------------------------------------ binning
@@ -360,7 +413,7 @@ void launch_bin_layout(const uint32_t* blk_cnt, uint32_t nblk, uint64_t* blk_off
                        bin_info, next);
 }
 
-// Slot ids into per-bin lists: the same 256-slot blocks as k_match, each
+// Slot ids into per-bin lists: the same MATCH_SLOTS-slot blocks as k_match, each
 // block's slots of bin b go to blk_off[b][block] + rank (rank from LDS atomics).
 // A block whose counts list nothing returns at once (its tasks may be unwritten).
 __global__ void __launch_bounds__(256) k_bin_scatter(const Task* tasks, uint64_t n, const uint32_t* blk_cnt,
@@ -376,12 +429,15 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const Task* tasks, uint64_t
     }
     __syncthreads();
     if (uniform(listed) == 0) return;
-    uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < n) {
-        Task t = tasks[s];
-        if (t.kind != KIND_NOOP) {
-            const uint32_t rank = atomicAdd(&cnt[t.bin], 1u);
-            lists[blk_off[(uint64_t)t.bin * gridDim.x + blockIdx.x] + rank] = (uint32_t)s;
+#pragma unroll
+    for (uint32_t k = 0; k < MATCH_PER_THREAD; ++k) {
+        const uint64_t s = (uint64_t)blockIdx.x * MATCH_SLOTS + k * 256 + threadIdx.x;
+        if (s < n) {
+            const Task t = tasks[s];
+            if (t.kind != KIND_NOOP) {
+                const uint32_t rank = atomicAdd(&cnt[t.bin], 1u);
+                lists[blk_off[(uint64_t)t.bin * gridDim.x + blockIdx.x] + rank] = (uint32_t)s;
+            }
         }
     }
 }
