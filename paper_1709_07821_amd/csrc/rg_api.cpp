@@ -835,7 +835,7 @@ rg_status rg_plan_tune(rg_plan* p, void* stream, int reps) {
     // typical pool become workgroup merges, hundreds of times slower)
     std::vector<uint32_t> tvals = heur ? std::vector<uint32_t>{4, 16, 64} : std::vector<uint32_t>{};
     std::vector<uint32_t> gvals;
-    for (uint32_t f : {2u, 4u, 8u, 12u, 16u}) gvals.push_back((uint32_t)cus * f);
+    for (uint32_t f : {1u, 2u, 4u, 8u, 16u}) gvals.push_back((uint32_t)cus * f);
     std::vector<uint32_t> rvals = heur ? std::vector<uint32_t>{8, 32, 128, 512} : std::vector<uint32_t>{};
     uint32_t* knobs[3] = {&p->thread_max, &p->grid, &p->gallop_ratio};
     const std::vector<uint32_t>* vals[3] = {&tvals, &gvals, &rvals};
