@@ -338,3 +338,66 @@ def test_array_stress_full_size_sampled(rg, ctx):
         a, b = bs[int(ia[p])], bs[int(ib[p])]
         for op in OPS:
             assert int(cards[op][p]) == oracle.count(op, a, b), (op, p)
+
+
+def _key_matching_layouts():
+    """Bitmaps that stress key matching: eight with every one of the 65536 keys
+    (one value per key, so each pair of them matches 65536 containers and the
+    staged key window overflows), every third key with two values, a single
+    value, an empty bitmap, and scattered values over the whole universe."""
+    sets = []
+    k = np.arange(65536, dtype=np.uint64)
+    for i in range(8):
+        sets.append((k * 65536 + (((k * 2654435761) >> (i + 7)) & 3)).astype(np.uint32))
+    k3 = np.arange(0, 65536, 3, dtype=np.uint64)
+    sets.append(np.sort(np.concatenate([k3 * 65536 + 5, k3 * 65536 + (k3 & 0xFFFF)])).astype(np.uint32))
+    sets.append(np.array([7 * 65536 + 7], np.uint32))
+    sets.append(np.zeros(0, np.uint32))
+    rng = np.random.default_rng(5)
+    sets.append(np.unique(rng.integers(0, 1 << 32, 5000, dtype=np.uint64)).astype(np.uint32))
+    return synth.BitmapSet.from_list([np.unique(s) for s in sets])
+
+
+def test_key_matching_block_layouts(rg, ctx):
+    """Pairs of 65536-key bitmaps (more than 2^24 candidate slots: two waves,
+    blocks inside one pair with no staged window) interleaved with empty,
+    one-key and small pairs (blocks spanning many pairs, pairs without
+    candidates); every count and Jaccard index, eager and as a plan, equals
+    the oracle, and materialised intersections of a sample decode to it."""
+    import torch
+
+    bs = _key_matching_layouts()
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    rng = np.random.default_rng(17)
+    big = [(int(a), int(b)) for a, b in rng.integers(0, 8, (260, 2))]
+    small = [(int(a), int(b)) for a, b in rng.integers(0, len(bs), (120, 2))]
+    pairs = big + small
+    order = rng.permutation(len(pairs))
+    ia = np.array([pairs[i][0] for i in order], np.uint32)
+    ib = np.array([pairs[i][1] for i in order], np.uint32)
+    tia, tib = _t(ia), _t(ib)
+    for op in OPS:
+        _say(f"[key-matching] op={op} pairs={len(ia)}")
+        exp, _, jexp = oracle.pairs(op, bs.values, bs.offsets, bs.values, bs.offsets, ia, ib, want_jaccard=True)
+        _, c, j = rg.batch(ctx, op, P, P, tia, tib, materialize=False, card=True, jaccard=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(c.cpu().numpy().view(np.uint64), exp), op
+        assert np.array_equal(j.cpu().numpy(), jexp), op
+        pl = rg.Plan(ctx, op, P, P, tia, tib, card=True, jaccard=True)
+        assert pl.info()["waves"] >= 2
+        pl.execute()
+        torch.cuda.synchronize()
+        assert np.array_equal(pl.cards.cpu().numpy().view(np.uint64), exp), op
+        assert np.array_equal(pl.jacc.cpu().numpy(), jexp), op
+        pl.close()
+    sample = np.array([0, 1, len(ia) - 1] + [p for p in range(len(ia)) if ia[p] >= 8][:3])
+    out, mc, _ = rg.batch(ctx, "and", P, P, _t(ia[sample]), _t(ib[sample]), materialize=True, card=True)
+    torch.cuda.synchronize()
+    res = out.as_pool()
+    assert rg.rg_pool_validate(ctx, res) == 0
+    h = res.to_host()
+    for q, p in enumerate(sample):
+        e = oracle.op("and", bs[int(ia[p])], bs[int(ib[p])])
+        got, meta = rgtest.decode_bitmap(h, q)
+        assert np.array_equal(got, e), p
+        assert meta == rgtest.oracle_meta(oracle, e), p
