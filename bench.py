@@ -49,8 +49,8 @@ def main():
     ap.add_argument("--index", type=int, default=4000, help="serve: bitmaps in the index")
     ap.add_argument("--rates", default="2000,5000,10000,20000,50000", help="serve: arrival rates (queries/s)")
     ap.add_argument("--duration", type=float, default=2.0, help="serve: seconds of arrivals per rate")
-    ap.add_argument("--pool", type=int, default=1024, help="batched: bitmaps in the pool")
-    ap.add_argument("--batched-pairs", type=int, default=100000, help="batched: random pairs per step")
+    ap.add_argument("--pool", type=int, default=16384, help="batched: bitmaps in the pool")
+    ap.add_argument("--batched-pairs", type=int, default=1000000, help="batched: random pairs per step")
     ap.add_argument("--per-pair-sample", type=int, default=500, help="batched: pairs timed one call each")
     ap.add_argument("--dispatch-pairs", type=int, default=300, help="batched: pairs whose costs train the dispatcher")
     ap.add_argument("--dispatch-epochs", type=int, default=10, help="batched: dispatcher training epochs")
@@ -201,7 +201,13 @@ def bench_batched(args):
     t0 = time.time()
     hot = synth.hot_keys(seed, 256, 1 << 16)
     cards = [synth.lognormal_card(i, 1e4, 2.0, 10, 10 ** 7, seed) for i in range(args.pool)]
-    bs = synth.BitmapSet.from_list([synth.mixed_bitmap(seed, i, cards[i], 32, hot) for i in range(args.pool)])
+    sets = []
+    for i in range(args.pool):
+        sets.append(synth.mixed_bitmap(seed, i, cards[i], 32, hot))
+        if (i + 1) % 4096 == 0:
+            print(f"# generated {i + 1} of {args.pool} bitmaps, {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    bs = synth.BitmapSet.from_list(sets)
+    del sets
     P = rg.Pool.from_sets(bs.values, bs.offsets)
     ia, ib = synth.random_pairs(args.pool, args.batched_pairs, seed)
     n = len(ia)
