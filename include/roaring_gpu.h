@@ -340,7 +340,10 @@ typedef struct rg_server rg_server;
  * queries arriving while steps run join the next step, and up to max_inflight
  * (1 or 2) steps are on the GPU at once, on two streams. max_batch = 1 and
  * max_inflight = 1 serve one query at a time. The pool must stay valid and
- * unchanged while the server runs. */
+ * unchanged while the server runs. The server thread uses its own buffers,
+ * streams and error record, never the context's, so the caller may go on
+ * using ctx for other calls meanwhile (a failed step is reported by
+ * rg_serve_poll and rg_serve_stop). */
 rg_status rg_serve_start(rg_ctx *ctx, const rg_pool *pool, uint64_t arena_bytes, uint32_t max_batch,
                          uint32_t max_inflight, rg_server **server);
 /* Non-blocking. arrival_ns: the query's arrival time on the steady clock in

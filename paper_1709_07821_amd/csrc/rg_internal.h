@@ -374,6 +374,8 @@ struct KwArgs {
     long long* acc;     // per query, count-only results
     uint32_t* err;      // set when a query's key set exceeds its slot range
 };
+void launch_kw_step_init(uint64_t* totals, uint32_t* err, long long* acc, uint64_t* bm_card, uint64_t* bm_wbytes,
+                         uint32_t nq, hipStream_t st);
 void launch_kw_keys(const KwArgs& a, hipStream_t st);
 void launch_kw_bounds(const KwArgs& a, hipStream_t st);
 void launch_kw_eval(const KwArgs& a, hipStream_t st);

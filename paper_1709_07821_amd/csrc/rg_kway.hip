@@ -229,6 +229,27 @@ __global__ void k_kw_cards(KwArgs a, const uint64_t* bm_card, uint64_t* cards) {
     cards[q] = (a.queries[q].flags & KW_MATERIALIZE) ? bm_card[q] : (uint64_t)a.acc[q];
 }
 
+// Zeroes what a step accumulates into, in one launch: two scan totals, the
+// error flag, and per query its count accumulator, cardinality and payload bound.
+__global__ void k_kw_step_init(uint64_t* totals, uint32_t* err, long long* acc, uint64_t* bm_card,
+                               uint64_t* bm_wbytes, uint32_t nq) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 2) totals[i] = 0;
+    if (i == 0) *err = 0;
+    if (i < nq) {
+        acc[i] = 0;
+        bm_card[i] = 0;
+        bm_wbytes[i] = 0;
+    }
+}
+
+void launch_kw_step_init(uint64_t* totals, uint32_t* err, long long* acc, uint64_t* bm_card, uint64_t* bm_wbytes,
+                         uint32_t nq, hipStream_t st) {
+    const uint32_t n = nq > 2 ? nq : 2;
+    hipLaunchKernelGGL(k_kw_step_init, dim3((n + 255) / 256), dim3(256), 0, st, totals, err, acc, bm_card, bm_wbytes,
+                       nq);
+}
+
 void launch_kw_keys(const KwArgs& a, hipStream_t st) {
     if (a.n_queries) hipLaunchKernelGGL(k_kw_keys, dim3(a.n_queries), dim3(256), 0, st, a);
 }

@@ -149,10 +149,22 @@ StepOut own_out(const StepLayout& L, uint8_t* d) {
                    reinterpret_cast<uint64_t*>(d + L.o_bm_wbytes)};
 }
 
+// A failed HIP call in step_enqueue: the message goes to *err (the caller's
+// context, or the server's own record: the server thread never writes the
+// context, which its owner may be using meanwhile).
+#define STEPCHK(call)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            *err_out = std::string(#call) + ": " + hipGetErrorString(e_);              \
+            return RG_EDEVICE;                                                         \
+        }                                                                              \
+    } while (0)
+
 // Enqueues one step. h_stage: pinned host memory of L.down_off + L.down_bytes
 // bytes whose upload section is filled; the download section receives the
 // results once the stream reaches the end of the step.
-rg_status step_enqueue(rg_ctx* c, const rg_pool& pool, const StepLayout& L, uint8_t* d, const StepOut& o,
+rg_status step_enqueue(std::string* err_out, const rg_pool& pool, const StepLayout& L, uint8_t* d, const StepOut& o,
                        uint8_t* h_stage, hipStream_t st) {
     auto* queries = reinterpret_cast<KwQuery*>(d + L.o_queries);
     auto* ids = reinterpret_cast<uint32_t*>(d + L.o_ids);
@@ -173,12 +185,8 @@ rg_status step_enqueue(rg_ctx* c, const rg_pool& pool, const StepLayout& L, uint
     auto* acc = reinterpret_cast<long long*>(d + L.o_acc);
     auto* step_bm_begin = reinterpret_cast<uint64_t*>(d + L.o_bm_begin);
 
-    HIPCHK(c, hipMemcpyAsync(d, h_stage, L.up_bytes, hipMemcpyHostToDevice, st));
-    launch_fill_u64(totals, 0, 2, st);
-    launch_fill_u32(err, 0, 1, st);
-    launch_fill_u64(reinterpret_cast<uint64_t*>(acc), 0, L.nq, st);
-    launch_fill_u64(o.bm_card, 0, L.nq, st);
-    launch_fill_u64(o.bm_wbytes, 0, L.nq, st);
+    STEPCHK(hipMemcpyAsync(d, h_stage, L.up_bytes, hipMemcpyHostToDevice, st));
+    launch_kw_step_init(totals, err, acc, o.bm_card, o.bm_wbytes, L.nq, st);
     KwArgs a;
     a.P0 = view(pool);
     a.P1 = a.P0;
@@ -220,13 +228,13 @@ rg_status step_enqueue(rg_ctx* c, const rg_pool& pool, const StepLayout& L, uint
     }
     launch_bm_begin(cand, out_idx, L.S, totals + 1, L.nq, 0, step_bm_begin, true, st);
     if (o.bm_begin != step_bm_begin)
-        HIPCHK(c, hipMemcpyAsync(o.bm_begin, step_bm_begin, 8 * (L.nq + 1), hipMemcpyDeviceToDevice, st));
+        STEPCHK(hipMemcpyAsync(o.bm_begin, step_bm_begin, 8 * (L.nq + 1), hipMemcpyDeviceToDevice, st));
     launch_kw_cards(a, o.bm_card, cards, st);
     rg_pool outp{L.nq, L.S, L.P, step_bm_begin, o.keys, o.types, o.card, o.size, o.off, o.payload, o.bm_card,
                  o.bm_wbytes};
     launch_pool_digest_n(outp, totals + 1, digest, st);
-    HIPCHK(c, hipMemcpyAsync(h_stage + L.down_off, d + L.down_off, L.down_bytes, hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipGetLastError());
+    STEPCHK(hipMemcpyAsync(h_stage + L.down_off, d + L.down_off, L.down_bytes, hipMemcpyDeviceToHost, st));
+    STEPCHK(hipGetLastError());
     return RG_OK;
 }
 
@@ -294,7 +302,7 @@ extern "C" rg_status roaring_multi(rg_ctx* c, int op, const rg_pool* pool, const
     StepOut o = mat ? StepOut{out->bm_begin, out->keys, out->types, out->card, out->size, out->off, out->payload,
                               out->bm_card, out->bm_wbytes}
                     : own_out(L, d);
-    if (rg_status s = step_enqueue(c, *pool, L, d, o, h, st)) return s;
+    if (rg_status s = step_enqueue(&c->err, *pool, L, d, o, h, st)) return s;
     HIPCHK(c, hipStreamSynchronize(st));
     const uint64_t* totals = reinterpret_cast<const uint64_t*>(h + L.o_totals);
     const uint32_t err = *reinterpret_cast<const uint32_t*>(h + L.o_err);
@@ -541,12 +549,13 @@ void rg_server::run() {
                     ++n_steps;
                     sum_batch += take.size();
                     lk.unlock();
-                    rg_status st = step_enqueue(c, pool, s->L, s->d, own_out(s->L, s->d), s->h, s->st);
+                    std::string step_err;
+                    rg_status st = step_enqueue(&step_err, pool, s->L, s->d, own_out(s->L, s->d), s->h, s->st);
                     if (st == RG_OK && hipEventCreateWithFlags(&s->done, hipEventDisableTiming) != hipSuccess)
                         st = RG_EDEVICE;
                     if (st == RG_OK && hipEventRecord(s->done, s->st) != hipSuccess) st = RG_EDEVICE;
                     lk.lock();
-                    if (st != RG_OK) fatal = c->err.empty() ? "step enqueue failed" : c->err;
+                    if (st != RG_OK) fatal = step_err.empty() ? "step enqueue failed" : step_err;
                     inflight.push_back(s);
                     progressed = true;
                 }
