@@ -9,9 +9,10 @@
 //      a 65536-bit LDS mask (AND of the bitmaps' key masks, or OR), writes the
 //      keys in ascending order as one task per result key, and marks the rest
 //      of the query's slot range empty.
-//   2. k_kw_bounds: one thread per slot looks the key up in each of the k
-//      bitmaps and bounds the result payload (AND: the smallest container,
-//      OR: the sum, both capped at a bitset) - the slot sizes of step 3.
+//   2. k_kw_bounds: one wave per slot looks the key up in the k bitmaps (one
+//      lane per bitmap) and bounds the result payload (AND: the smallest
+//      container, OR: the sum, both capped at a bitset) - the slot sizes of
+//      step 3.
 //   3. k_kw_eval: one workgroup per result key: every present container is
 //      expanded into an LDS bitset and combined word by word (AND stops when
 //      the running result is empty); then the common output step (P1 type,
@@ -55,6 +56,9 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a) {
     __shared__ uint64_t acc[1024];
     __shared__ uint64_t cur[1024];
     __shared__ uint32_t tmp[8];
+    __shared__ uint64_t rs[KW_MAX_K];  // key-list start of each of the query's bitmaps
+    __shared__ uint32_t rn[KW_MAX_K];  // and its length
+    __shared__ uint32_t roff[KW_MAX_K + 1];  // exclusive prefix of the lengths (union pass)
     const uint32_t q = blockIdx.x;
     const KwQuery Q = a.queries[q];
     const uint32_t op = uniform(Q.op), k = uniform(Q.k), ids0 = uniform(Q.ids_off);
@@ -62,31 +66,57 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a) {
     const uint32_t kbound = uniform(Q.kbound);
     const uint32_t tid = threadIdx.x;
     for (uint32_t i = tid; i < 1024; i += 256) acc[i] = 0;
+    // all key ranges at once (one load level instead of one per bitmap)
+    const uint32_t kk = op == RG_ANDNOT ? 1u : k;  // bitmaps that decide the result keys
+    for (uint32_t j = tid; j < kk; j += 256) {
+        const uint64_t* bmb = j ? a.P1.bm_begin : a.P0.bm_begin;
+        const uint32_t b = a.ids[ids0 + j];
+        const uint64_t s0 = bmb[b];
+        rs[j] = s0;
+        rn[j] = (uint32_t)(bmb[b + 1] - s0);
+    }
     __syncthreads();
     // result keys: AND - in every bitmap; OR, XOR - in any; ANDNOT - the first bitmap's
-    const uint32_t kk = op == RG_ANDNOT ? 1u : k;
-    for (uint32_t j = 0; j < kk; ++j) {
-        const uint64_t* bmb = j ? a.P1.bm_begin : a.P0.bm_begin;
-        const uint16_t* pkeys = j ? a.P1.keys : a.P0.keys;
-        const uint32_t b = uniform(a.ids[ids0 + j]);
-        const uint64_t s = uniform64(bmb[b]);
-        const uint32_t n = (uint32_t)(uniform64(bmb[b + 1]) - s);
-        if (op != RG_AND || j == 0) {
+    if (op != RG_AND) {
+        // a union of key sets: every key of every deciding bitmap sets its bit,
+        // in one pass over the concatenated lists
+        if (tid == 0) {
+            uint32_t o = 0;
+            for (uint32_t j = 0; j < kk; ++j) {
+                roff[j] = o;
+                o += rn[j];
+            }
+            roff[kk] = o;
+        }
+        __syncthreads();
+        const uint32_t total_keys = uniform(roff[kk]);
+        uint32_t j = 0;
+        for (uint32_t i = tid; i < total_keys; i += 256) {
+            while (roff[j + 1] <= i) ++j;  // i only grows, so j only moves forward
+            const uint16_t* pkeys = j ? a.P1.keys : a.P0.keys;
+            const uint32_t key = pkeys[rs[j] + (i - roff[j])];
+            atomicOr(reinterpret_cast<unsigned long long*>(&acc[key >> 6]), 1ull << (key & 63));
+        }
+        __syncthreads();
+    } else {
+        for (uint32_t j = 0; j < k; ++j) {
+            const uint16_t* pkeys = j ? a.P1.keys : a.P0.keys;
+            const uint64_t s0 = rs[j];
+            const uint32_t n = uniform(rn[j]);
+            uint64_t* dst = j == 0 ? acc : cur;
+            if (j) {
+                for (uint32_t i = tid; i < 1024; i += 256) cur[i] = 0;
+                __syncthreads();
+            }
             for (uint32_t i = tid; i < n; i += 256) {
-                const uint32_t key = pkeys[s + i];
-                atomicOr(reinterpret_cast<unsigned long long*>(&acc[key >> 6]), 1ull << (key & 63));
+                const uint32_t key = pkeys[s0 + i];
+                atomicOr(reinterpret_cast<unsigned long long*>(&dst[key >> 6]), 1ull << (key & 63));
             }
             __syncthreads();
-        } else {
-            for (uint32_t i = tid; i < 1024; i += 256) cur[i] = 0;
-            __syncthreads();
-            for (uint32_t i = tid; i < n; i += 256) {
-                const uint32_t key = pkeys[s + i];
-                atomicOr(reinterpret_cast<unsigned long long*>(&cur[key >> 6]), 1ull << (key & 63));
+            if (j) {
+                for (uint32_t i = tid; i < 1024; i += 256) acc[i] &= cur[i];
+                __syncthreads();
             }
-            __syncthreads();
-            for (uint32_t i = tid; i < 1024; i += 256) acc[i] &= cur[i];
-            __syncthreads();
         }
     }
     // ascending keys: thread t owns words 4t..4t+3
@@ -134,31 +164,52 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a) {
 }
 
 // ---------------------------------------------------------------- 2. bounds
+// One wave per slot: lane j looks the key up in the query's j-th bitmap (64
+// bitmaps per round), so the k searches run side by side.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t x = __shfl_xor(v, o);
+        v = x < v ? x : v;
+    }
+    return v;
+}
+
 __global__ void __launch_bounds__(256) k_kw_bounds(KwArgs a) {
-    const uint64_t s = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (s >= a.n_slots) return;
-    const Task t = a.tasks[s];
+    const uint32_t lane = lane_id();
+    const uint64_t s = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (s >= a.n_slots) return;  // wave-uniform
+    const Task t = uniform_task(a.tasks, (uint32_t)s);
     uint32_t ub = 0;
     if (t.kind == KIND_MATCH) {
-        const KwQuery Q = a.queries[t.pair - a.pair_base];
-        if (Q.flags & KW_MATERIALIZE) {
+        const KwQuery* Qp = a.queries + (t.pair - a.pair_base);
+        const uint32_t flags = uniform(Qp->flags);
+        if (flags & KW_MATERIALIZE) {
+            const uint32_t op = uniform(Qp->op), k = uniform(Qp->k), ids0 = uniform(Qp->ids_off);
             // AND: the smallest container; OR, XOR: the sum; ANDNOT: the first
             uint64_t sum = 0;
             uint32_t mn = 0xFFFFFFFFu, first = 0;
-            for (uint32_t j = 0; j < Q.k; ++j) {
-                const PoolView pv = kw_side(a, j != 0);
-                const uint32_t ci = kw_find_key(pv.bm_begin, pv.keys, a.ids[Q.ids_off + j], t.key);
-                const uint32_t cj = ci == NONE ? 0u : pv.card[ci];
-                if (j == 0) first = cj;
-                sum += cj;
-                if (cj < mn) mn = cj;
+            for (uint32_t j0 = 0; j0 < k; j0 += 64) {
+                const uint32_t j = j0 + lane;
+                uint32_t cj = 0;
+                if (j < k) {
+                    const PoolView pv = kw_side(a, j != 0);
+                    const uint32_t ci = kw_find_key(pv.bm_begin, pv.keys, a.ids[ids0 + j], t.key);
+                    cj = ci == NONE ? 0u : pv.card[ci];
+                }
+                if (j0 == 0) first = __builtin_amdgcn_readlane(cj, 0);
+                sum += wave_sum_u64(cj);
+                const uint32_t m = wave_min_u32(j < k ? cj : 0xFFFFFFFFu);
+                mn = m < mn ? m : mn;
             }
-            const uint64_t bc = Q.op == RG_AND ? (uint64_t)mn : Q.op == RG_ANDNOT ? (uint64_t)first : sum;
+            const uint64_t bc = op == RG_AND ? (uint64_t)mn : op == RG_ANDNOT ? (uint64_t)first : sum;
             ub = wbytes_of(bc);
         }
     }
-    a.ub[s] = ub;
-    a.res_card[s] = 0;
+    if (lane == 0) {
+        a.ub[s] = ub;
+        a.res_card[s] = 0;
+    }
 }
 
 // ---------------------------------------------------------------- 3. evaluate
@@ -255,7 +306,7 @@ void launch_kw_keys(const KwArgs& a, hipStream_t st) {
 }
 void launch_kw_bounds(const KwArgs& a, hipStream_t st) {
     if (a.n_slots)
-        hipLaunchKernelGGL(k_kw_bounds, dim3((uint32_t)((a.n_slots + 255) / 256)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_kw_bounds, dim3((uint32_t)((a.n_slots + 3) / 4)), dim3(256), 0, st, a);
 }
 void launch_kw_eval(const KwArgs& a, hipStream_t st) {
     if (!a.n_slots) return;
