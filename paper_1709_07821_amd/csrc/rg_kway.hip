@@ -13,9 +13,11 @@
 //      lane per bitmap) and bounds the result payload (AND: the smallest
 //      container, OR: the sum, both capped at a bitset) - the slot sizes of
 //      step 3.
-//   3. k_kw_eval: one workgroup per result key: every present container is
-//      expanded into an LDS bitset and combined word by word (AND stops when
-//      the running result is empty); then the common output step (P1 type,
+//   3. k_kw_eval: one workgroup per result key. Intersection: every container
+//      is expanded into an LDS bitset and combined word by word, stopping once
+//      the running result is empty. Union, symmetric difference, difference:
+//      all containers fold into one LDS bitset at once (LDS atomics per array
+//      value, bitset word or run). Then the common output step (P1 type,
 //      payload into the slot) or, count-only, the population count.
 // Compaction of non-empty results into per-query bitmaps uses the pairwise
 // path's kernels (flags, scan, compact, bitmap starts).
@@ -213,9 +215,56 @@ __global__ void __launch_bounds__(256) k_kw_bounds(KwArgs a) {
 }
 
 // ---------------------------------------------------------------- 3. evaluate
+// Folds a set of containers into the LDS bitset r with one read-modify-write
+// per unit: OP 0 sets bits (union), 1 flips them (symmetric difference: each
+// container flips its own values, so a bit ends up set when an odd number of
+// containers hold it), 2 clears them (difference). Units: array value, bitset
+// word, run.
+template <int OP>
+__device__ __forceinline__ void kw_fold_units(uint64_t* r, const uint32_t* cunits, const uint8_t* ctype,
+                                              const uint64_t* cpl, uint32_t total) {
+    uint32_t j = 0;
+    for (uint32_t u = threadIdx.x; u < total; u += 256) {
+        while (cunits[j + 1] <= u) ++j;  // u only grows, so j only moves forward
+        const uint32_t loc = u - cunits[j];
+        const uint8_t* pl = reinterpret_cast<const uint8_t*>(cpl[j]);
+        const uint8_t type = ctype[j];
+        uint32_t first, last;  // bit range [first, last] (array, run) or one word (bitset)
+        uint64_t word = 0;
+        if (type == RG_ARRAY) {
+            first = last = reinterpret_cast<const uint16_t*>(pl)[loc];
+        } else if (type == RG_BITSET) {
+            word = reinterpret_cast<const uint64_t*>(pl)[loc];
+            if (word) {
+                unsigned long long* dst = reinterpret_cast<unsigned long long*>(&r[loc]);
+                if (OP == 0) atomicOr(dst, word);
+                else if (OP == 1) atomicXor(dst, word);
+                else atomicAnd(dst, ~word);
+            }
+            continue;
+        } else {
+            const uint32_t pr = reinterpret_cast<const uint32_t*>(pl)[loc];
+            first = pr & 0xFFFFu;
+            last = first + (pr >> 16);
+        }
+        for (uint32_t wi = first >> 6; wi <= last >> 6; ++wi) {
+            const uint32_t lo = wi == first >> 6 ? first & 63 : 0;
+            const uint32_t hi = wi == last >> 6 ? last & 63 : 63;
+            const uint64_t m = (~0ull << lo) & (~0ull >> (63 - hi));
+            unsigned long long* dst = reinterpret_cast<unsigned long long*>(&r[wi]);
+            if (OP == 0) atomicOr(dst, m);
+            else if (OP == 1) atomicXor(dst, m);
+            else atomicAnd(dst, ~m);
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
     __shared__ WgShared sh;
     __shared__ uint32_t cidx[KW_MAX_K];
+    __shared__ uint32_t cunits[KW_MAX_K + 1];  // exclusive prefix of the containers' unit counts
+    __shared__ uint8_t ctype[KW_MAX_K];
+    __shared__ uint64_t cpl[KW_MAX_K];         // payload address of each container
     const uint32_t tid = threadIdx.x;
     for (uint64_t s = blockIdx.x; s < a.n_slots; s += gridDim.x) {
         const Task t = uniform_task(a.tasks, (uint32_t)s);
@@ -230,15 +279,47 @@ __global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
             cidx[tid] = kw_find_key(bmb, pkeys, a.ids[ids0 + tid], t.key);
         }
         __syncthreads();
-        // running result in sh.sa; each container is expanded into sh.sb
         bool empty = false;
         bool first = true;
-        for (uint32_t j = 0; j < k && !empty; ++j) {
+        if (op != RG_AND) {
+            // Union and symmetric difference: all present containers fold into a
+            // zeroed bitset at once. Difference: the first container is expanded,
+            // then all others clear their bits at once. No container waits for
+            // another.
+            const uint32_t j0 = op == RG_ANDNOT ? 1u : 0u;
+            if (op == RG_ANDNOT) {
+                expand_container(sh.sa, a.P0, uniform(cidx[0]), sh);
+            } else {
+                for (uint32_t i = tid; i < 1024; i += 256) sh.sa[i] = 0;
+            }
+            uint32_t units = 0;
+            if (tid < k && tid >= j0) {
+                const uint32_t ci = cidx[tid];
+                if (ci != NONE) {
+                    const PoolView pv = kw_side(a, tid != 0);
+                    const uint8_t ty = pv.types[ci];
+                    units = ty == RG_BITSET ? 1024u : pv.size[ci];
+                    ctype[tid] = ty;
+                    cpl[tid] = reinterpret_cast<uint64_t>(pv.payload + pv.off[ci]);
+                }
+            }
+            uint32_t total;
+            const uint32_t pos = block_excl_scan_u32(units, sh.tmp, &total);
+            if (tid < k) cunits[tid] = pos;
+            if (tid == 0) cunits[k] = total;
+            __syncthreads();
+            if (op == RG_ANDNOT) kw_fold_units<2>(sh.sa, cunits, ctype, cpl, uniform(total));
+            else if (op == RG_XOR) kw_fold_units<1>(sh.sa, cunits, ctype, cpl, uniform(total));
+            else kw_fold_units<0>(sh.sa, cunits, ctype, cpl, uniform(total));
+            __syncthreads();
+            first = false;
+        }
+        // intersection: running result in sh.sa; each container is expanded
+        // into sh.sb and combined, stopping once the result is empty
+        for (uint32_t j = 0; op == RG_AND && j < k && !empty; ++j) {
             const uint32_t ci = uniform(cidx[j]);
-            if (ci == NONE) {
-                // AND: cannot happen (the key is in every bitmap); ANDNOT: the
-                // first bitmap holds the key, a missing later one removes nothing
-                if (op == RG_AND) empty = true;
+            if (ci == NONE) {  // cannot happen: the key is in every bitmap
+                empty = true;
                 continue;
             }
             const PoolView pv = kw_side(a, j != 0);
@@ -248,14 +329,11 @@ __global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const uint32_t wi = 4 * tid + i;
-                    const uint64_t x = sh.sa[wi], y = sh.sb[wi];
-                    const uint64_t v = op == RG_AND ? (x & y) : op == RG_OR ? (x | y) : op == RG_XOR ? (x ^ y) : (x & ~y);
+                    const uint64_t v = sh.sa[wi] & sh.sb[wi];
                     sh.sa[wi] = v;
                     any |= v != 0 ? 1u : 0u;
                 }
-                // AND and ANDNOT stay empty once empty
-                if (op == RG_AND || op == RG_ANDNOT) empty = block_sum_u64(any, sh.tmp64) == 0;
-                else __syncthreads();
+                empty = block_sum_u64(any, sh.tmp64) == 0;
             }
             first = false;
         }
