@@ -170,6 +170,7 @@ class Context:
             raise RoaringError(st, f"rg_create failed on device {device}")
         self.h = h
         self.device = device
+        self.dispatch_mode = RG_DISPATCH_HEURISTIC  # mirrors the context's variant selection
         self.servers = weakref.WeakSet()  # stopped before the context goes away
 
     def close(self):
@@ -195,6 +196,7 @@ class Context:
 
     def set_dispatch(self, mode: int = RG_DISPATCH_HEURISTIC, variant: int = 2):
         self.check(lib().rg_set_dispatch(self.h, mode, variant))
+        self.dispatch_mode = mode
 
     def set_thresholds(self, gallop_ratio: int = 64, thread_max: int = 8):
         self.check(lib().rg_set_thresholds(self.h, gallop_ratio, thread_max))
@@ -384,6 +386,7 @@ class Plan:
         torch = _torch()
         dev = A.bm_begin.device
         n = int(ia.numel())
+        self.n_pairs = n
         self.ctx, self.A, self.B, self.ia, self.ib = ctx, A, B, ia, ib
         self.cards = torch.zeros(n, dtype=torch.int64, device=dev) if card else None
         self.jacc = torch.zeros(n, dtype=torch.float64, device=dev) if jaccard else None
@@ -400,8 +403,32 @@ class Plan:
     def capture(self, stream):
         self.ctx.check(lib().rg_plan_capture(self.h, _stream(stream)))
 
-    def tune(self, stream=None, reps=3):
+    def tune(self, stream=None, reps=3, cache=None, key=None):
+        """rg_plan_tune. With cache (a JSON file path), a setting stored under key
+        (default: the plan's pair, slot and wave counts and its dispatch mode) is
+        applied with rg_plan_set instead of tuning again; a new one is stored."""
+        if cache is None:
+            self.ctx.check(lib().rg_plan_tune(self.h, _stream(stream), reps))
+            return
+        import json
+
+        info = self.info()
+        key = key or f"pairs={self.n_pairs},slots={info['slots']},waves={info['waves']},mode={self.ctx.dispatch_mode}"
+        table = {}
+        if os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        hit = table.get(key)
+        if hit:
+            self.set(hit["grid"], hit["gallop_ratio"], hit["thread_max"])
+            return
         self.ctx.check(lib().rg_plan_tune(self.h, _stream(stream), reps))
+        info = self.info()
+        table[key] = {k: info[k] for k in ("grid", "gallop_ratio", "thread_max")}
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
 
     def set(self, grid: int, gallop_ratio: int, thread_max: int = 8):
         st = lib().rg_plan_set(self.h, grid, gallop_ratio, thread_max)
@@ -640,6 +667,7 @@ def dispatch_train(ctx: Context, x, t, m, epochs=20, batch=4096, lr=1e-3, seed=1
 
 def dispatch_set_mlp(ctx: Context, params, stream=None):
     ctx.check(lib().rg_dispatch_set_mlp(ctx.h, _ptr(params), _stream(stream)))
+    ctx.dispatch_mode = RG_DISPATCH_MLP
 
 
 def dispatch_table(ctx: Context):

@@ -314,9 +314,27 @@ __global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
             __syncthreads();
             first = false;
         }
-        // intersection: running result in sh.sa; each container is expanded
-        // into sh.sb and combined, stopping once the result is empty
-        for (uint32_t j = 0; op == RG_AND && j < k && !empty; ++j) {
+        // intersection: running result in sh.sa, starting from the container
+        // with the fewest values (ties: the lowest index); each other one is
+        // expanded into sh.sb and combined, stopping once the result is empty
+        uint32_t jmin = 0;
+        if (op == RG_AND) {
+            uint32_t key = 0xFFFFFFFFu;  // cardinality << 8 | index; a missing container counts as empty
+            if (tid < k) {
+                const uint32_t ci = cidx[tid];
+                const PoolView pv = kw_side(a, tid != 0);
+                key = ((ci == NONE ? 0u : pv.card[ci]) << 8) | tid;
+            }
+            key = wave_min_u32(key);
+            if ((tid & 63) == 0) sh.xchg[tid >> 6] = key;
+            __syncthreads();
+            uint32_t m = sh.xchg[0];
+            for (int w = 1; w < 4; ++w) m = sh.xchg[w] < m ? sh.xchg[w] : m;
+            jmin = uniform(m & 0xFFu);
+            __syncthreads();
+        }
+        for (uint32_t step = 0; op == RG_AND && step < k && !empty; ++step) {
+            const uint32_t j = step == 0 ? jmin : (step - 1 < jmin ? step - 1 : step);
             const uint32_t ci = uniform(cidx[j]);
             if (ci == NONE) {  // cannot happen: the key is in every bitmap
                 empty = true;

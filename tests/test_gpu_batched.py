@@ -141,6 +141,41 @@ def test_plan_tune_keeps_results(rg, ctx):
     pl.close()
 
 
+def test_plan_tune_cache(rg, ctx, tmp_path):
+    """A tuned setting is stored in the JSON cache under the plan's key and
+    applied to the next plan of the same shape without tuning; results equal."""
+    import json
+
+    import torch
+
+    bs, ia, ib = synth.array_stress(n_pairs=1500)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    tia, tib = _t(ia), _t(ib)
+    card, jac = _expect(bs, ia, ib, "xor")
+    cache = str(tmp_path / "tune.json")
+    pl = rg.Plan(ctx, "xor", P, P, tia, tib, card=True, jaccard=True)
+    pl.tune(reps=1, cache=cache)
+    chosen = pl.info()
+    pl.close()
+    table = json.load(open(cache))
+    assert len(table) == 1
+    stored = next(iter(table.values()))
+    assert stored == {k: chosen[k] for k in ("grid", "gallop_ratio", "thread_max")}
+    # a different setting is stored by hand: the next plan must take it from the cache
+    key = next(iter(table))
+    table[key] = {"grid": 256, "gallop_ratio": 8, "thread_max": 16}
+    json.dump(table, open(cache, "w"))
+    pl2 = rg.Plan(ctx, "xor", P, P, tia, tib, card=True, jaccard=True)
+    pl2.tune(reps=1, cache=cache)
+    info = pl2.info()
+    assert (info["grid"], info["gallop_ratio"], info["thread_max"]) == (256, 8, 16)
+    pl2.execute()
+    torch.cuda.synchronize()
+    assert np.array_equal(pl2.cards.cpu().numpy().view(np.uint64), card)
+    assert np.array_equal(pl2.jacc.cpu().numpy(), jac)
+    pl2.close()
+
+
 def test_plan_errors(rg, ctx):
     import torch
 
