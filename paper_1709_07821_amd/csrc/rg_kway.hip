@@ -25,6 +25,8 @@
 
 namespace rg {
 
+constexpr int KW_UNROLL = 4;  // independent loads in flight per thread in the key and fold passes
+
 __device__ __forceinline__ uint32_t kw_find_key(const uint64_t* bm_begin, const uint16_t* keys, uint32_t b,
                                                 uint16_t key) {
     const uint64_t s = bm_begin[b], e = bm_begin[b + 1];
@@ -93,11 +95,23 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a) {
         __syncthreads();
         const uint32_t total_keys = uniform(roff[kk]);
         uint32_t j = 0;
-        for (uint32_t i = tid; i < total_keys; i += 256) {
-            while (roff[j + 1] <= i) ++j;  // i only grows, so j only moves forward
-            const uint16_t* pkeys = j ? a.P1.keys : a.P0.keys;
-            const uint32_t key = pkeys[rs[j] + (i - roff[j])];
-            atomicOr(reinterpret_cast<unsigned long long*>(&acc[key >> 6]), 1ull << (key & 63));
+        // KW_UNROLL keys per thread per round: their loads are issued together
+        for (uint32_t base = 0; base < total_keys; base += 256 * KW_UNROLL) {
+            uint32_t key[KW_UNROLL];
+#pragma unroll
+            for (int r = 0; r < KW_UNROLL; ++r) {
+                const uint32_t i = base + r * 256 + tid;
+                key[r] = 0xFFFFFFFFu;
+                if (i < total_keys) {
+                    while (roff[j + 1] <= i) ++j;  // i only grows, so j only moves forward
+                    const uint16_t* pkeys = j ? a.P1.keys : a.P0.keys;
+                    key[r] = pkeys[rs[j] + (i - roff[j])];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < KW_UNROLL; ++r)
+                if (key[r] != 0xFFFFFFFFu)
+                    atomicOr(reinterpret_cast<unsigned long long*>(&acc[key[r] >> 6]), 1ull << (key[r] & 63));
         }
         __syncthreads();
     } else {
@@ -110,9 +124,17 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a) {
                 for (uint32_t i = tid; i < 1024; i += 256) cur[i] = 0;
                 __syncthreads();
             }
-            for (uint32_t i = tid; i < n; i += 256) {
-                const uint32_t key = pkeys[s0 + i];
-                atomicOr(reinterpret_cast<unsigned long long*>(&dst[key >> 6]), 1ull << (key & 63));
+            for (uint32_t base = 0; base < n; base += 256 * KW_UNROLL) {
+                uint32_t key[KW_UNROLL];
+#pragma unroll
+                for (int r = 0; r < KW_UNROLL; ++r) {
+                    const uint32_t i = base + r * 256 + tid;
+                    key[r] = i < n ? pkeys[s0 + i] : 0xFFFFFFFFu;
+                }
+#pragma unroll
+                for (int r = 0; r < KW_UNROLL; ++r)
+                    if (key[r] != 0xFFFFFFFFu)
+                        atomicOr(reinterpret_cast<unsigned long long*>(&dst[key[r] >> 6]), 1ull << (key[r] & 63));
             }
             __syncthreads();
             if (j) {
@@ -221,40 +243,52 @@ __global__ void __launch_bounds__(256) k_kw_bounds(KwArgs a) {
 // containers hold it), 2 clears them (difference). Units: array value, bitset
 // word, run.
 template <int OP>
+__device__ __forceinline__ void kw_apply(uint64_t* r, uint32_t wi, uint64_t m) {
+    unsigned long long* dst = reinterpret_cast<unsigned long long*>(&r[wi]);
+    if (OP == 0) atomicOr(dst, m);
+    else if (OP == 1) atomicXor(dst, m);
+    else atomicAnd(dst, ~m);
+}
+
+template <int OP>
 __device__ __forceinline__ void kw_fold_units(uint64_t* r, const uint32_t* cunits, const uint8_t* ctype,
                                               const uint64_t* cpl, uint32_t total) {
     uint32_t j = 0;
-    for (uint32_t u = threadIdx.x; u < total; u += 256) {
-        while (cunits[j + 1] <= u) ++j;  // u only grows, so j only moves forward
-        const uint32_t loc = u - cunits[j];
-        const uint8_t* pl = reinterpret_cast<const uint8_t*>(cpl[j]);
-        const uint8_t type = ctype[j];
-        uint32_t first, last;  // bit range [first, last] (array, run) or one word (bitset)
-        uint64_t word = 0;
-        if (type == RG_ARRAY) {
-            first = last = reinterpret_cast<const uint16_t*>(pl)[loc];
-        } else if (type == RG_BITSET) {
-            word = reinterpret_cast<const uint64_t*>(pl)[loc];
-            if (word) {
-                unsigned long long* dst = reinterpret_cast<unsigned long long*>(&r[loc]);
-                if (OP == 0) atomicOr(dst, word);
-                else if (OP == 1) atomicXor(dst, word);
-                else atomicAnd(dst, ~word);
+    for (uint32_t base = 0; base < total; base += 256 * KW_UNROLL) {
+        // the round's units are read first, so that their loads overlap
+        uint64_t raw[KW_UNROLL];
+        uint32_t loc[KW_UNROLL];
+        uint8_t type[KW_UNROLL];
+#pragma unroll
+        for (int q = 0; q < KW_UNROLL; ++q) {
+            const uint32_t u = base + q * 256 + threadIdx.x;
+            type[q] = 0;
+            loc[q] = 0;
+            raw[q] = 0;
+            if (u < total) {
+                while (cunits[j + 1] <= u) ++j;  // u only grows, so j only moves forward
+                loc[q] = u - cunits[j];
+                type[q] = ctype[j];
+                const uint8_t* pl = reinterpret_cast<const uint8_t*>(cpl[j]);
+                if (type[q] == RG_ARRAY) raw[q] = reinterpret_cast<const uint16_t*>(pl)[loc[q]];
+                else if (type[q] == RG_BITSET) raw[q] = reinterpret_cast<const uint64_t*>(pl)[loc[q]];
+                else raw[q] = reinterpret_cast<const uint32_t*>(pl)[loc[q]];
             }
-            continue;
-        } else {
-            const uint32_t pr = reinterpret_cast<const uint32_t*>(pl)[loc];
-            first = pr & 0xFFFFu;
-            last = first + (pr >> 16);
         }
-        for (uint32_t wi = first >> 6; wi <= last >> 6; ++wi) {
-            const uint32_t lo = wi == first >> 6 ? first & 63 : 0;
-            const uint32_t hi = wi == last >> 6 ? last & 63 : 63;
-            const uint64_t m = (~0ull << lo) & (~0ull >> (63 - hi));
-            unsigned long long* dst = reinterpret_cast<unsigned long long*>(&r[wi]);
-            if (OP == 0) atomicOr(dst, m);
-            else if (OP == 1) atomicXor(dst, m);
-            else atomicAnd(dst, ~m);
+#pragma unroll
+        for (int q = 0; q < KW_UNROLL; ++q) {
+            if (type[q] == RG_ARRAY) {
+                kw_apply<OP>(r, (uint32_t)raw[q] >> 6, 1ull << (raw[q] & 63));
+            } else if (type[q] == RG_BITSET) {
+                if (raw[q]) kw_apply<OP>(r, loc[q], raw[q]);
+            } else if (type[q] == RG_RUN) {
+                const uint32_t first = (uint32_t)raw[q] & 0xFFFFu, last = first + ((uint32_t)raw[q] >> 16);
+                for (uint32_t wi = first >> 6; wi <= last >> 6; ++wi) {
+                    const uint32_t lo = wi == first >> 6 ? first & 63 : 0;
+                    const uint32_t hi = wi == last >> 6 ? last & 63 : 63;
+                    kw_apply<OP>(r, wi, (~0ull << lo) & (~0ull >> (63 - hi)));
+                }
+            }
         }
     }
 }
