@@ -49,6 +49,7 @@ def main():
     ap.add_argument("--index", type=int, default=4000, help="serve: bitmaps in the index")
     ap.add_argument("--rates", default="2000,5000,10000,20000,50000", help="serve: arrival rates (queries/s)")
     ap.add_argument("--duration", type=float, default=2.0, help="serve: seconds of arrivals per rate")
+    ap.add_argument("--max-batch", type=int, default=256, help="serve: most queries per step (batched mode)")
     ap.add_argument("--pool", type=int, default=16384, help="batched: bitmaps in the pool")
     ap.add_argument("--batched-pairs", type=int, default=1000000, help="batched: random pairs per step")
     ap.add_argument("--per-pair-sample", type=int, default=500, help="batched: pairs timed one call each")
@@ -335,8 +336,8 @@ def bench_serve(args):
     32-key hot set), cardinality lognormal (median 5e4, sigma 1, clipped to
     [1e3, 1e6]). Mix: 40 % k-AND, 40 % k-OR (both materialised), 20 %
     count-only (half AND, half OR); k uniform in 2..32; ids uniform without
-    replacement. Each rate runs twice: the continuous-batching server (up to 64
-    queries per step, two steps in flight) and one query at a time."""
+    replacement. Each rate runs twice: the continuous-batching server (up to
+    --max-batch queries per step, two steps in flight) and one query at a time."""
     import numpy as np
     import torch
 
@@ -372,7 +373,7 @@ def bench_serve(args):
 
     # correctness gate: a sample against the oracle
     sample = make_queries(12)
-    srv = rg.Server(ctx, P, arena_bytes=4 << 30, max_batch=64, max_inflight=2)
+    srv = rg.Server(ctx, P, arena_bytes=4 << 30, max_batch=args.max_batch, max_inflight=2)
     _, c_s, d_s = srv.replay(sample, np.zeros(len(sample), np.uint64))
     srv.stop()
     for i, (op, ids, mat) in enumerate(sample):
@@ -387,7 +388,7 @@ def bench_serve(args):
         gaps = rng.exponential(1.0 / lam, n)
         arrival = (np.cumsum(gaps) * 1e9).astype(np.uint64)
         row = {"rate_qps": lam, "queries": n}
-        for mode, mb, mi in (("batched", 64, 2), ("one_at_a_time", 1, 1)):
+        for mode, mb, mi in (("batched", args.max_batch, 2), ("one_at_a_time", 1, 1)):
             srv = rg.Server(ctx, P, arena_bytes=4 << 30, max_batch=mb, max_inflight=mi)
             t = time.perf_counter()
             lat, c, d = srv.replay(qs, arrival)
