@@ -1,11 +1,11 @@
-// rg_persist.hip - one persistent kernel for all container pairs of a batched
-// count-only call. A fixed grid (a few workgroups per CU) first takes its
-// static share of the thread-sized tasks (small array sides), then drains
+// rg_persist.hip - one persistent kernel for the listed container pairs of a
+// batched count-only call (a plan). Small-array pairs never get here: key
+// matching counts them itself. A fixed grid (a few workgroups per CU) drains
 // per-bin work counters with atomics, largest items first: workgroup-sized
 // tasks (generic LDS expansion, merge path), then wave-sized tasks (bitset
 // pairs, galloping search, bitset probes, run merges), each wave grabbing its
-// own. Every wave exits when its share is done and all counters are drained,
-// so the grid always finishes.
+// own. Every wave exits when all counters are drained, so the grid always
+// finishes.
 //
 // The kernel accumulates |A n B| per pair, whatever operation was asked for:
 // union, symmetric difference and difference counts follow from it and the
@@ -28,23 +28,6 @@ __global__ void __launch_bounds__(256) k_persist(PersistArgs a) {
     __shared__ WgShared sh;
     __shared__ uint32_t grab;
     const uint32_t lane = lane_id();
-    // thread-sized tasks (small array sides) first, split statically: chunk c
-    // of 256 consecutive items goes to workgroup c mod grid. They are many and
-    // of similar cost, so no counter is needed (a shared counter would be hit
-    // once per chunk by every workgroup).
-    {
-        const uint32_t cnt = uniform(a.bin_info[BIN_THREAD]), off = uniform(a.bin_info[NBINS + BIN_THREAD]);
-        for (uint32_t base = blockIdx.x * 256u; base < cnt; base += gridDim.x * 256u) {
-            const uint32_t i = base + threadIdx.x;
-            uint32_t pair = NONE, inter = 0;
-            if (i < cnt) {
-                const Task t = a.tasks[a.lists[off + i]];
-                inter = thread_inter(a.A, a.B, t);
-                pair = t.pair;
-            }
-            wave_aggregate_add(a.acc, pair, inter);
-        }
-    }
     // workgroup-sized tasks, largest first, taken from a counter
 #pragma unroll 1
     for (int q = 0; q < 2; ++q) {
