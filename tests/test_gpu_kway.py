@@ -198,3 +198,36 @@ def test_server_views_and_small_arena(rg, ctx):
             srv2.submit("or", np.resize(np.arange(12, dtype=np.uint32), 256), materialize=True)
         finally:
             srv2.stop()
+
+
+def test_server_all_ops_while_context_busy(rg, ctx):
+    """Queries of all four operations, served while the owner of the context
+    keeps making pairwise calls on it: both sides give the oracle's results."""
+    import torch
+
+    bs = overlapping_sets(n=16, seed=8)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    qs = [(op, ids, i % 3 != 2) for i, (op, ids) in
+          enumerate(_queries(len(bs), 40, seed=41, kmax=7, ops=("and", "or", "xor", "andnot")))]
+    exp = _expect(bs, qs)
+    ia = np.arange(0, 15, dtype=np.uint32)
+    ib = np.arange(1, 16, dtype=np.uint32)
+    tia = torch.from_numpy(ia.view(np.int32)).cuda()
+    tib = torch.from_numpy(ib.view(np.int32)).cuda()
+    srv = rg.Server(ctx, P, arena_bytes=64 << 20, max_batch=8, max_inflight=2)
+    try:
+        tickets = [srv.submit(op, ids, materialize=m) for op, ids, m in qs]
+        for rep in range(3):
+            for op in ("and", "or", "xor", "andnot"):
+                _, c, _ = rg.batch(ctx, op, P, P, tia, tib, materialize=False, card=True)
+                torch.cuda.synchronize()
+                c = c.cpu().numpy().view(np.uint64)
+                for p in range(len(ia)):
+                    assert int(c[p]) == oracle.count(op, bs[int(ia[p])], bs[int(ib[p])]), (rep, op, p)
+        for i, t in enumerate(tickets):
+            r = srv.poll(t, wait=True)
+            assert r.done and r.status == 0 and r.card == exp[i][0] and r.digest == exp[i][1], (i, qs[i][0])
+            srv.release(t)
+    finally:
+        st = srv.stop()
+    _say(f"[serve all ops, busy context] {st}")
