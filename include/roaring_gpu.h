@@ -176,10 +176,13 @@ rg_status roaring_batch(rg_ctx *ctx, int op, const rg_pool *A, const rg_pool *B,
  * sequence into a hipGraph on a non-default stream; later executes replay it.
  * rg_plan_tune times the plan on its own data and keeps the fastest setting of
  * the thread-size threshold, the persistent grid size and the galloping ratio,
- * one after the other (results never change). The pools,
- * pair arrays and outputs must stay valid and unmoved for the plan's life;
- * their contents may change between executions as long as every pair's
- * candidate count (number of keys of its smaller bitmap) does not. */
+ * one after the other (results never change). The pools, pair arrays and
+ * outputs must stay valid and unmoved for the plan's life. The pools' contents
+ * must not change either: the plan keeps a packed copy of their container
+ * metadata (16 bytes per container, made at creation; without the memory for
+ * it the plan reads the pool arrays). The pair arrays' contents may change
+ * between executions as long as every pair's candidate count (number of keys
+ * of its smaller bitmap) does not. */
 typedef struct rg_plan rg_plan;
 rg_status rg_plan_create(rg_ctx *ctx, int op, const rg_pool *A, const rg_pool *B, const uint32_t *d_ia,
                          const uint32_t *d_ib, uint64_t n_pairs, uint32_t flags, uint64_t *d_cards, double *d_jacc,

@@ -594,12 +594,18 @@ struct rg_plan {
     uint32_t thread_max = 8;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // packed container metadata of both pools (null: not packed)
+    void* meta_mem = nullptr;
+    const u32x4* metaA = nullptr;
+    const u32x4* metaB = nullptr;
 };
 
 namespace {
 
 void plan_enqueue(rg_plan* p, hipStream_t st) {
-    const PoolView pa = view(p->A), pb = view(p->B);
+    PoolView pa = view(p->A), pb = view(p->B);
+    pa.meta = p->metaA;
+    pb.meta = p->metaB;
     launch_fill_u32(p->err, 0, 1, st);
     // the plan accumulates |A n B| for every operation; the requested count
     // follows from the Section 5.9 identities in the last step
@@ -692,6 +698,7 @@ rg_status rg_plan_create(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, 
     // candidate counts: one preparation pass, read back once
     auto cleanup = [&](rg_status s) {
         if (p->mem) (void)hipFree(p->mem);
+        if (p->meta_mem) (void)hipFree(p->meta_mem);
         delete p;
         return s;
     };
@@ -766,6 +773,30 @@ rg_status rg_plan_create(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, 
         if (hipMemcpy(wv.cand_off, h_off.data(), 8 * (wv.np + 1), hipMemcpyHostToDevice) != hipSuccess)
             return cleanup(fail(c, RG_EDEVICE, "plan upload failed"));
         p->waves.push_back(wv);
+    }
+    // Key matching reads every matched container's type, cardinality, size and
+    // offset; the plan packs them into one 16-byte record per container once
+    // (both pools, or one when A and B are the same pool). Without the memory
+    // the plan runs from the separate arrays.
+    {
+        const bool same = A->keys == B->keys && A->off == B->off && A->n_containers == B->n_containers;
+        const uint64_t nA = A->n_containers, nB = same ? 0 : B->n_containers;
+        if (nA + nB) {
+            if (hipMalloc(&p->meta_mem, 16 * (nA + nB)) == hipSuccess) {
+                u32x4* ma = reinterpret_cast<u32x4*>(p->meta_mem);
+                u32x4* mb = same ? ma : ma + nA;
+                launch_pack_meta(view(*A), nA, ma, st);
+                if (!same) launch_pack_meta(view(*B), nB, mb, st);
+                // complete before the plan runs on any stream
+                if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+                    return cleanup(fail(c, RG_EDEVICE, "plan metadata packing failed"));
+                p->metaA = ma;
+                p->metaB = mb;
+            } else {
+                p->meta_mem = nullptr;
+                (void)hipGetLastError();  // the failed allocation is not an error of the plan
+            }
+        }
     }
     *out_plan = p;
     return RG_OK;
@@ -893,6 +924,7 @@ void rg_plan_destroy(rg_plan* p) {
     (void)hipDeviceSynchronize();
     plan_drop_graph(p);
     if (p->mem) (void)hipFree(p->mem);
+    if (p->meta_mem) (void)hipFree(p->meta_mem);
     delete p;
 }
 

@@ -158,12 +158,10 @@ __device__ __forceinline__ uint32_t wave_inter(const PoolView& PA, const PoolVie
 // |A n B| of one pair by one thread: every value of the smaller array side is
 // looked up in the other container (bit test, binary search in an array or
 // in the run starts). For small array sides only. Per-lane values throughout.
-// The container types are passed in when the caller has read them already.
-__device__ __forceinline__ uint32_t thread_inter_typed(const PoolView& PA, const PoolView& PB, uint32_t ia,
-                                                       uint32_t ib, uint8_t ta, uint8_t tb) {
-    uint32_t sa = PA.size[ia], sb = PB.size[ib];
-    const uint8_t* pa = PA.payload + PA.off[ia];
-    const uint8_t* pb = PB.payload + PB.off[ib];
+// The form taking what the caller has read already: types, sizes (array:
+// cardinality, run: run count; unused for a bitset) and payload addresses.
+__device__ __forceinline__ uint32_t thread_inter_at(uint8_t ta, uint8_t tb, uint32_t sa, uint32_t sb,
+                                                    const uint8_t* pa, const uint8_t* pb) {
     // s: the array side (the smaller one when both are arrays); l: the other
     const bool a_is_s = ta == RG_ARRAY && (tb != RG_ARRAY || sa <= sb);
     const uint16_t* sv = reinterpret_cast<const uint16_t*>(a_is_s ? pa : pb);
@@ -196,6 +194,12 @@ __device__ __forceinline__ uint32_t thread_inter_typed(const PoolView& PA, const
         for (uint32_t i = 0; i < n; ++i) hits += in_runs(lr, ln, sv[i]) ? 1u : 0u;
     }
     return hits;
+}
+
+// The container types are passed in when the caller has read them already.
+__device__ __forceinline__ uint32_t thread_inter_typed(const PoolView& PA, const PoolView& PB, uint32_t ia,
+                                                       uint32_t ib, uint8_t ta, uint8_t tb) {
+    return thread_inter_at(ta, tb, PA.size[ia], PB.size[ib], PA.payload + PA.off[ia], PB.payload + PB.off[ib]);
 }
 
 __device__ __forceinline__ uint32_t thread_inter(const PoolView& PA, const PoolView& PB, const Task& t) {

@@ -103,7 +103,7 @@ struct Bump {
 };
 
 inline PoolView view(const rg_pool& p) {
-    return PoolView{p.bm_begin, p.keys, p.types, p.card, p.size, p.off, p.payload, p.bm_card, p.bm_wbytes};
+    return PoolView{p.bm_begin, p.keys, p.types, p.card, p.size, p.off, p.payload, p.bm_card, p.bm_wbytes, nullptr};
 }
 
 inline bool pool_ok(const rg_pool* p) {

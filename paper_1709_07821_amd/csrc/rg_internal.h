@@ -54,7 +54,14 @@ struct PoolView {
     const uint8_t* payload;
     const uint64_t* bm_card;
     const uint64_t* bm_wbytes;
+    // Optional (plans): every container's metadata packed in one 16-byte record,
+    // {offset low word, offset high word, card, size | type << 24}, so that key
+    // matching reads one record per side instead of four arrays. Null: use the arrays.
+    const u32x4* meta;
 };
+
+// Packs the metadata records of a pool's n containers (PoolView::meta).
+void launch_pack_meta(const PoolView& P, uint64_t n, u32x4* out, hipStream_t st);
 
 // Per-wave result slots written by the compute kernels.
 struct SlotOut {

@@ -52,6 +52,7 @@ __device__ __forceinline__ PoolView kw_side(const KwArgs& a, bool second) {
     v.payload = second ? a.P1.payload : a.P0.payload;
     v.bm_card = second ? a.P1.bm_card : a.P0.bm_card;
     v.bm_wbytes = second ? a.P1.bm_wbytes : a.P0.bm_wbytes;
+    v.meta = second ? a.P1.meta : a.P0.meta;
     return v;
 }
 

@@ -175,18 +175,38 @@ __device__ __forceinline__ void finish_slot(const MatchArgs& m, uint32_t* cnt, S
     Task& task = o.task;
     uint32_t ub = 0;
     if (task.kind != KIND_NOOP) {
-        const uint8_t ta = task.ia != NONE ? m.A.types[task.ia] : 0;
-        const uint8_t tb = task.ib != NONE ? m.B.types[task.ib] : 0;
-        const uint32_t ca = task.ia != NONE ? m.A.card[task.ia] : 0;
-        const uint32_t cb = task.ib != NONE ? m.B.card[task.ib] : 0;
-        const bool need_r = m.dispatch_mode == 1;
-        const uint32_t ra = need_r && ta == RG_RUN ? m.A.size[task.ia] : 0;
-        const uint32_t rb = need_r && tb == RG_RUN ? m.B.size[task.ib] : 0;
+        uint8_t ta, tb;
+        uint32_t ca, cb, sa = 0, sb = 0, ra = 0, rb = 0;
+        uint64_t oa = 0, ob = 0;
+        const bool packed = m.A.meta && m.B.meta;
+        if (packed) {
+            // one record per side: type, card, size and payload offset together
+            const u32x4 xa = m.A.meta[task.ia], xb = m.B.meta[task.ib];
+            ta = (uint8_t)(xa.w >> 24);
+            tb = (uint8_t)(xb.w >> 24);
+            ca = xa.z;
+            cb = xb.z;
+            sa = xa.w & 0xFFFFFFu;
+            sb = xb.w & 0xFFFFFFu;
+            oa = (uint64_t)xa.x | ((uint64_t)xa.y << 32);
+            ob = (uint64_t)xb.x | ((uint64_t)xb.y << 32);
+            ra = ta == RG_RUN ? sa : 0;
+            rb = tb == RG_RUN ? sb : 0;
+        } else {
+            ta = m.A.types[task.ia];
+            tb = m.B.types[task.ib];
+            ca = m.A.card[task.ia];
+            cb = m.B.card[task.ib];
+            const bool need_r = m.dispatch_mode == 1;
+            ra = need_r && ta == RG_RUN ? m.A.size[task.ia] : 0;
+            rb = need_r && tb == RG_RUN ? m.B.size[task.ib] : 0;
+        }
         task.bin = classify(m.op, m.materialize, task.kind, ta, tb, ca, cb, ra, rb, m.dispatch_mode, m.fixed_bin,
                             m.gallop_ratio, m.thread_max, m.mlp_table);
         if (m.fuse_thread && task.bin == BIN_THREAD) {
             // the types are at hand: probe now instead of listing the pair
-            o.fused_inter = thread_inter_typed(m.A, m.B, task.ia, task.ib, ta, tb);
+            o.fused_inter = packed ? thread_inter_at(ta, tb, sa, sb, m.A.payload + oa, m.B.payload + ob)
+                                   : thread_inter_typed(m.A, m.B, task.ia, task.ib, ta, tb);
             o.fused_pair = task.pair;
             task.kind = KIND_NOOP;
             task.bin = BIN_FUSED;

@@ -203,4 +203,21 @@ void launch_pool_digest_n(const rg_pool& p, const uint64_t* d_n, uint64_t* d_dig
     hipLaunchKernelGGL(k_digest, dim3((uint32_t)((p.n_containers + 3) / 4)), dim3(256), 0, st, p, d_n, d_digest);
 }
 
+// ------------------------------------------------------------------ packed metadata
+__global__ void k_pack_meta(PoolView P, uint64_t n, u32x4* out) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t off = P.off[i];
+    u32x4 r;
+    r.x = (uint32_t)off;
+    r.y = (uint32_t)(off >> 32);
+    r.z = P.card[i];
+    r.w = (P.size[i] & 0xFFFFFFu) | ((uint32_t)P.types[i] << 24);
+    out[i] = r;
+}
+
+void launch_pack_meta(const PoolView& P, uint64_t n, u32x4* out, hipStream_t st) {
+    if (n) hipLaunchKernelGGL(k_pack_meta, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, P, n, out);
+}
+
 }  // namespace rg

@@ -176,6 +176,28 @@ def test_plan_tune_cache(rg, ctx, tmp_path):
     pl2.close()
 
 
+def test_plan_two_pools(rg, ctx):
+    """A plan whose pairs take A from one pool and B from another (each pool's
+    container metadata packed separately) gives the oracle's counts."""
+    import torch
+
+    a_bs = synth.mixed_small(n_bitmaps=10, seed=31)
+    b_bs = synth.BitmapSet.from_list(rgtest.edge_sets())
+    A = rg.Pool.from_sets(a_bs.values, a_bs.offsets)
+    B = rg.Pool.from_sets(b_bs.values, b_bs.offsets)
+    ia = np.repeat(np.arange(len(a_bs)), len(b_bs)).astype(np.uint32)
+    ib = np.tile(np.arange(len(b_bs)), len(a_bs)).astype(np.uint32)
+    for op in OPS:
+        exp, _, jexp = oracle.pairs(op, a_bs.values, a_bs.offsets, b_bs.values, b_bs.offsets, ia, ib,
+                                    want_jaccard=True)
+        pl = rg.Plan(ctx, op, A, B, _t(ia), _t(ib), card=True, jaccard=True)
+        pl.execute()
+        torch.cuda.synchronize()
+        assert np.array_equal(pl.cards.cpu().numpy().view(np.uint64), exp), op
+        assert np.array_equal(pl.jacc.cpu().numpy(), jexp), op
+        pl.close()
+
+
 def test_plan_errors(rg, ctx):
     import torch
 
