@@ -196,6 +196,41 @@ __device__ __forceinline__ uint32_t thread_inter_at(uint8_t ta, uint8_t tb, uint
     return hits;
 }
 
+// The form taking two packed metadata records' contents (PoolView::meta):
+// data is a payload offset, or the values of an array of at most
+// META_INLINE_MAX values when its inline flag is set.
+__device__ __forceinline__ uint32_t thread_inter_rec(uint8_t ta, uint8_t tb, uint32_t sa, uint32_t sb, bool ina,
+                                                     bool inb, uint64_t da, uint64_t db, const uint8_t* payA,
+                                                     const uint8_t* payB) {
+    if (!ina && !inb) return thread_inter_at(ta, tb, sa, sb, payA + da, payB + db);
+    const bool a_is_s = ta == RG_ARRAY && (tb != RG_ARRAY || sa <= sb);
+    const uint32_t n = a_is_s ? sa : sb;
+    const bool s_in = a_is_s ? ina : inb;
+    const uint64_t s_data = a_is_s ? da : db;
+    const uint16_t* sv = s_in ? nullptr : reinterpret_cast<const uint16_t*>((a_is_s ? payA : payB) + s_data);
+    const uint8_t lt = a_is_s ? tb : ta;
+    const uint32_t ln = a_is_s ? sb : sa;
+    const bool l_in = a_is_s ? inb : ina;
+    const uint64_t l_data = a_is_s ? db : da;
+    const uint8_t* lp = l_in ? nullptr : (a_is_s ? payB : payA) + l_data;
+    uint32_t hits = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint32_t x = s_in ? (uint32_t)(s_data >> (16 * i)) & 0xFFFFu : sv[i];
+        if (lt == RG_BITSET) {
+            hits += (uint32_t)(reinterpret_cast<const uint64_t*>(lp)[x >> 6] >> (x & 63)) & 1u;
+        } else if (lt == RG_ARRAY) {
+            if (l_in) {
+                for (uint32_t t = 0; t < ln; ++t) hits += ((uint32_t)(l_data >> (16 * t)) & 0xFFFFu) == x ? 1u : 0u;
+            } else {
+                hits += search_u16(reinterpret_cast<const uint16_t*>(lp), ln, x) ? 1u : 0u;
+            }
+        } else {
+            hits += in_runs(reinterpret_cast<const uint32_t*>(lp), ln, x) ? 1u : 0u;
+        }
+    }
+    return hits;
+}
+
 // The container types are passed in when the caller has read them already.
 __device__ __forceinline__ uint32_t thread_inter_typed(const PoolView& PA, const PoolView& PB, uint32_t ia,
                                                        uint32_t ib, uint8_t ta, uint8_t tb) {

@@ -55,11 +55,15 @@ struct PoolView {
     const uint64_t* bm_card;
     const uint64_t* bm_wbytes;
     // Optional (plans): every container's metadata packed in one 16-byte record,
-    // {offset low word, offset high word, card, size | type << 24}, so that key
-    // matching reads one record per side instead of four arrays. Null: use the arrays.
+    // {data low word, data high word, card, size | inline << 21 | type << 24},
+    // where data is the payload offset or, for an array of at most 4 values
+    // (inline = 1), the values themselves (value i in bits 16i..16i+15). Key
+    // matching reads one record per side instead of four arrays, and no payload
+    // for the smallest arrays. Null: use the arrays.
     const u32x4* meta;
 };
 
+constexpr uint32_t META_INLINE_MAX = 4;  // array values held in a packed record
 // Packs the metadata records of a pool's n containers (PoolView::meta).
 void launch_pack_meta(const PoolView& P, uint64_t n, u32x4* out, hipStream_t st);
 

@@ -177,19 +177,23 @@ __device__ __forceinline__ void finish_slot(const MatchArgs& m, uint32_t* cnt, S
     if (task.kind != KIND_NOOP) {
         uint8_t ta, tb;
         uint32_t ca, cb, sa = 0, sb = 0, ra = 0, rb = 0;
-        uint64_t oa = 0, ob = 0;
+        uint64_t da = 0, db = 0;
+        bool ina = false, inb = false;
         const bool packed = m.A.meta && m.B.meta;
         if (packed) {
-            // one record per side: type, card, size and payload offset together
+            // one record per side: type, card, size and the payload offset, or
+            // the values themselves for the smallest arrays
             const u32x4 xa = m.A.meta[task.ia], xb = m.B.meta[task.ib];
             ta = (uint8_t)(xa.w >> 24);
             tb = (uint8_t)(xb.w >> 24);
             ca = xa.z;
             cb = xb.z;
-            sa = xa.w & 0xFFFFFFu;
-            sb = xb.w & 0xFFFFFFu;
-            oa = (uint64_t)xa.x | ((uint64_t)xa.y << 32);
-            ob = (uint64_t)xb.x | ((uint64_t)xb.y << 32);
+            sa = xa.w & 0x1FFFFFu;
+            sb = xb.w & 0x1FFFFFu;
+            ina = (xa.w >> 21) & 1u;
+            inb = (xb.w >> 21) & 1u;
+            da = (uint64_t)xa.x | ((uint64_t)xa.y << 32);
+            db = (uint64_t)xb.x | ((uint64_t)xb.y << 32);
             ra = ta == RG_RUN ? sa : 0;
             rb = tb == RG_RUN ? sb : 0;
         } else {
@@ -205,7 +209,7 @@ __device__ __forceinline__ void finish_slot(const MatchArgs& m, uint32_t* cnt, S
                             m.gallop_ratio, m.thread_max, m.mlp_table);
         if (m.fuse_thread && task.bin == BIN_THREAD) {
             // the types are at hand: probe now instead of listing the pair
-            o.fused_inter = packed ? thread_inter_at(ta, tb, sa, sb, m.A.payload + oa, m.B.payload + ob)
+            o.fused_inter = packed ? thread_inter_rec(ta, tb, sa, sb, ina, inb, da, db, m.A.payload, m.B.payload)
                                    : thread_inter_typed(m.A, m.B, task.ia, task.ib, ta, tb);
             o.fused_pair = task.pair;
             task.kind = KIND_NOOP;

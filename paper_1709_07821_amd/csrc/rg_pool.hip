@@ -208,11 +208,21 @@ __global__ void k_pack_meta(PoolView P, uint64_t n, u32x4* out) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint64_t off = P.off[i];
+    const uint8_t type = P.types[i];
+    const uint32_t card = P.card[i], size = P.size[i];
+    uint64_t data = off;
+    uint32_t inl = 0;
+    if (type == RG_ARRAY && card <= META_INLINE_MAX) {
+        const uint16_t* v = reinterpret_cast<const uint16_t*>(P.payload + off);
+        data = 0;
+        for (uint32_t k = 0; k < card; ++k) data |= (uint64_t)v[k] << (16 * k);
+        inl = 1;
+    }
     u32x4 r;
-    r.x = (uint32_t)off;
-    r.y = (uint32_t)(off >> 32);
-    r.z = P.card[i];
-    r.w = (P.size[i] & 0xFFFFFFu) | ((uint32_t)P.types[i] << 24);
+    r.x = (uint32_t)data;
+    r.y = (uint32_t)(data >> 32);
+    r.z = card;
+    r.w = (size & 0x1FFFFFu) | (inl << 21) | ((uint32_t)type << 24);
     out[i] = r;
 }
 
