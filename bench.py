@@ -245,6 +245,19 @@ def bench_batched(args):
     eager_s = timed(lambda: rg.batch(ctx, "and", P, P, tia, tib, materialize=False, card=True, jaccard=True),
                     args.steps, 1)
     print(f"# eager batched: {eager_s * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+    # the same eager call on a pool that carries packed metadata records
+    # (rg_pool_pack_meta); the plans below reuse them
+    t_p = time.perf_counter()
+    P.pack_meta(ctx)
+    torch.cuda.synchronize()
+    pack_s = time.perf_counter() - t_p
+    eager_packed_s = timed(lambda: rg.batch(ctx, "and", P, P, tia, tib, materialize=False, card=True, jaccard=True),
+                           args.steps, 1)
+    _, c_p, j_p = rg.batch(ctx, "and", P, P, tia, tib, materialize=False, card=True, jaccard=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(c_p.cpu().numpy().view(np.uint64), c_e) and np.array_equal(j_p.cpu().numpy(), j_e)
+    print(f"# eager batched, packed metadata: {eager_packed_s * 1e3:.2f} ms/step (packing once: "
+          f"{pack_s * 1e3:.1f} ms), results equal", file=sys.stderr, flush=True)
 
     # plan: tuned, captured, replayed on a side stream
     st = torch.cuda.Stream()
@@ -319,6 +332,7 @@ def bench_batched(args):
         "matched_container_pairs": int(matched),
         "plan": info,
         "eager_batched_ms": round(eager_s * 1e3, 3),
+        "eager_batched_packed_ms": round(eager_packed_s * 1e3, 3),
         "per_pair_ms_extrapolated": round(pp_s * 1e3, 3),
         "speedup_plan_vs_per_pair": round(pp_s / plan_s, 2),
         "speedup_plan_vs_eager": round(eager_s / plan_s, 3),

@@ -90,6 +90,10 @@ typedef struct rg_pool {
     const uint64_t *bm_card;   /* [n_bitmaps], total cardinality of each bitmap */
     const uint64_t *bm_wbytes; /* [n_bitmaps], sum over its containers of
                                   roundup16(min(8192, 2 * card)): bounds result payloads */
+    const uint32_t *meta;      /* optional, may be NULL: [4 * n_containers], the packed
+                                  records rg_pool_pack_meta writes. When set, key matching
+                                  reads one record per matched container instead of the
+                                  separate arrays; it must match the arrays. */
 } rg_pool;
 
 /* Caller-provided output arena (device pointers) for materialised results:
@@ -383,6 +387,17 @@ rg_status rg_pool_build_host(const uint32_t *values, const uint64_t *offsets, ui
  * bm_begin/keys/types/size/off/payload are set. The card/bm_card/bm_wbytes
  * pointers of `pool` are written through (they must be writable). */
 rg_status rg_pool_recount(rg_ctx *ctx, const rg_pool *pool, void *stream);
+
+/* Packs every container's type, cardinality, size and payload offset into one
+ * 16-byte record: d_meta (device, caller-owned, 16 * n_containers bytes, 16-byte
+ * aligned) receives {data low, data high, card, size | inline << 21 | type << 24}
+ * per container, data being the payload offset or, for an array of at most 4
+ * values (inline = 1), the values (value i in bits 16i..16i+15). Setting
+ * pool.meta = d_meta afterwards lets key matching read one record per side of
+ * each matched container pair (and no payload for the smallest arrays); the
+ * pool must then not change while meta is set. Not from the paper: a layout
+ * choice for gathers on this GPU. Enqueued on `stream`, no synchronisation. */
+rg_status rg_pool_pack_meta(rg_ctx *ctx, const rg_pool *pool, uint32_t *d_meta, void *stream);
 
 /* Check every container of a device pool against the format rules above;
  * *n_bad (host) receives the number of offending containers. Synchronises. */

@@ -34,7 +34,8 @@ VARIANTS = {"generic": 2, "merge": 3, "gallop": 4, "probe": 5, "runmerge": 6, "t
 EXPORTS = ["rg_create", "rg_destroy", "rg_last_error", "rg_set_dispatch", "rg_set_thresholds", "roaring_and", "roaring_or", "roaring_xor",
            "roaring_andnot", "roaring_and_cardinality", "roaring_or_cardinality", "roaring_xor_cardinality",
            "roaring_andnot_cardinality", "roaring_jaccard", "roaring_batch", "rg_pool_measure_host",
-           "rg_pool_build_host", "rg_pool_recount", "rg_pool_validate", "rg_pool_digest", "rg_profile_enable",
+           "rg_pool_build_host", "rg_pool_recount", "rg_pool_pack_meta", "rg_pool_validate", "rg_pool_digest",
+           "rg_profile_enable",
            "rg_profile_reset", "rg_profile_read", "rg_plan_create", "rg_plan_execute", "rg_plan_capture",
            "rg_plan_tune", "rg_plan_set", "rg_plan_info", "rg_plan_destroy", "roaring_multi", "rg_serve_start",
            "rg_serve_submit", "rg_serve_poll", "rg_serve_release", "rg_serve_replay", "rg_serve_stop",
@@ -53,7 +54,7 @@ class rg_pool(ctypes.Structure):
                 ("payload_bytes", ctypes.c_uint64), ("bm_begin", ctypes.c_void_p), ("keys", ctypes.c_void_p),
                 ("types", ctypes.c_void_p), ("card", ctypes.c_void_p), ("size", ctypes.c_void_p),
                 ("off", ctypes.c_void_p), ("payload", ctypes.c_void_p), ("bm_card", ctypes.c_void_p),
-                ("bm_wbytes", ctypes.c_void_p)]
+                ("bm_wbytes", ctypes.c_void_p), ("meta", ctypes.c_void_p)]
 
 
 class rg_out(ctypes.Structure):
@@ -110,6 +111,7 @@ def lib():
         L.rg_pool_measure_host.argtypes = [V, V, U32, P(U64), P(U64)]
         L.rg_pool_build_host.argtypes = [V, V, U32] + [V] * 9
         L.rg_pool_recount.argtypes = [V, pool_p, V]
+        L.rg_pool_pack_meta.argtypes = [V, pool_p, V, V]
         L.rg_pool_validate.argtypes = [V, pool_p, P(U64), V]
         L.rg_pool_digest.argtypes = [V, pool_p, V, V]
         L.rg_profile_enable.argtypes = [V, I]
@@ -219,6 +221,16 @@ class Pool:
     @property
     def c(self):
         return self._c
+
+    def pack_meta(self, ctx: "Context", stream=None):
+        """rg_pool_pack_meta into a tensor this pool keeps; sets the pool's meta.
+        The pool must not change afterwards (the records mirror its arrays)."""
+        torch = _torch()
+        dev = self.bm_begin.device if self.bm_begin is not None else torch.device("cuda")
+        self.meta = torch.empty(max(self.n_containers, 1) * 4, dtype=torch.int32, device=dev)
+        ctx.check(lib().rg_pool_pack_meta(ctx.h, ctypes.byref(self._c), _ptr(self.meta), _stream(stream)))
+        self._c.meta = _ptr(self.meta).value
+        return self
 
     @staticmethod
     def from_view(view: "rg_pool") -> "Pool":

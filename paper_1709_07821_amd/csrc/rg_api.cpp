@@ -523,6 +523,16 @@ rg_status rg_pool_recount(rg_ctx* c, const rg_pool* p, void* stream) {
     return RG_OK;
 }
 
+rg_status rg_pool_pack_meta(rg_ctx* c, const rg_pool* p, uint32_t* d_meta, void* stream) {
+    if (!c) return RG_EINVAL;
+    if (!pool_ok(p) || (!d_meta && p->n_containers)) return fail(c, RG_EINVAL, "incomplete pool or no d_meta");
+    if (reinterpret_cast<uintptr_t>(d_meta) & 15) return fail(c, RG_EINVAL, "d_meta must be 16-byte aligned");
+    HIPCHK(c, hipSetDevice(c->device));
+    launch_pack_meta(view(*p), p->n_containers, reinterpret_cast<u32x4*>(d_meta), (hipStream_t)stream);
+    HIPCHK(c, hipGetLastError());
+    return RG_OK;
+}
+
 rg_status rg_pool_validate(rg_ctx* c, const rg_pool* p, uint64_t* n_bad, void* stream) {
     if (!c) return RG_EINVAL;
     if (!pool_ok(p) || !n_bad) return fail(c, RG_EINVAL, "incomplete pool");
@@ -604,7 +614,7 @@ namespace {
 
 void plan_enqueue(rg_plan* p, hipStream_t st) {
     PoolView pa = view(p->A), pb = view(p->B);
-    pa.meta = p->metaA;
+    pa.meta = p->metaA;  // the plan's records (its own, or the pools' when they carry them)
     pb.meta = p->metaB;
     launch_fill_u32(p->err, 0, 1, st);
     // the plan accumulates |A n B| for every operation; the requested count
@@ -778,7 +788,11 @@ rg_status rg_plan_create(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, 
     // offset; the plan packs them into one 16-byte record per container once
     // (both pools, or one when A and B are the same pool). Without the memory
     // the plan runs from the separate arrays.
-    {
+    if (A->meta && B->meta) {
+        // the caller packed them (rg_pool_pack_meta): use those
+        p->metaA = reinterpret_cast<const u32x4*>(A->meta);
+        p->metaB = reinterpret_cast<const u32x4*>(B->meta);
+    } else {
         const bool same = A->keys == B->keys && A->off == B->off && A->n_containers == B->n_containers;
         const uint64_t nA = A->n_containers, nB = same ? 0 : B->n_containers;
         if (nA + nB) {

@@ -103,7 +103,8 @@ struct Bump {
 };
 
 inline PoolView view(const rg_pool& p) {
-    return PoolView{p.bm_begin, p.keys, p.types, p.card, p.size, p.off, p.payload, p.bm_card, p.bm_wbytes, nullptr};
+    return PoolView{p.bm_begin, p.keys,    p.types,     p.card,      p.size,
+                    p.off,      p.payload, p.bm_card,   p.bm_wbytes, reinterpret_cast<const u32x4*>(p.meta)};
 }
 
 inline bool pool_ok(const rg_pool* p) {

@@ -401,3 +401,40 @@ def test_key_matching_block_layouts(rg, ctx):
         got, meta = rgtest.decode_bitmap(h, q)
         assert np.array_equal(got, e), p
         assert meta == rgtest.oracle_meta(oracle, e), p
+
+
+@pytest.mark.parametrize("which", ["edges", "array-stress"])
+def test_packed_metadata_same_results(rg, ctx, which):
+    """A pool carrying packed metadata records (rg_pool_pack_meta) gives the
+    oracle's counts, Jaccard indices and materialised intersections, eagerly and
+    through a plan that reuses the records."""
+    import torch
+
+    if which == "edges":
+        bs = synth.BitmapSet.from_list(rgtest.edge_sets())
+        k = len(bs)
+        ia, ib = np.repeat(np.arange(k), k).astype(np.uint32), np.tile(np.arange(k), k).astype(np.uint32)
+    else:
+        bs, ia, ib = synth.array_stress(n_pairs=3000)
+    P = rg.Pool.from_sets(bs.values, bs.offsets).pack_meta(ctx)
+    torch.cuda.synchronize()
+    tia, tib = _t(ia), _t(ib)
+    for op in OPS:
+        _say(f"[packed {which}] op={op}")
+        exp, _, jexp = oracle.pairs(op, bs.values, bs.offsets, bs.values, bs.offsets, ia, ib, want_jaccard=True)
+        _, c, j = rg.batch(ctx, op, P, P, tia, tib, materialize=False, card=True, jaccard=True)
+        pl = rg.Plan(ctx, op, P, P, tia, tib, card=True, jaccard=True)
+        pl.execute()
+        torch.cuda.synchronize()
+        assert np.array_equal(c.cpu().numpy().view(np.uint64), exp), op
+        assert np.array_equal(j.cpu().numpy(), jexp), op
+        assert np.array_equal(pl.cards.cpu().numpy().view(np.uint64), exp), op
+        pl.close()
+    n = min(len(ia), 40)
+    out, mc, _ = rg.batch(ctx, "and", P, P, _t(ia[:n]), _t(ib[:n]), materialize=True, card=True)
+    torch.cuda.synchronize()
+    h = out.as_pool().to_host()
+    for p in range(n):
+        e = oracle.op("and", bs[int(ia[p])], bs[int(ib[p])])
+        got, meta = rgtest.decode_bitmap(h, p)
+        assert np.array_equal(got, e) and meta == rgtest.oracle_meta(oracle, e), p
