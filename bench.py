@@ -60,7 +60,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is a design in DESIGN.md, not built", file=sys.stderr)
+              "sharding over several GPUs is designed (keys partition the universe), not built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -271,7 +271,7 @@ uint64_t ora_digest(const uint32_t *v, uint64_t n) {
     return d;
 }
 
-/* Per-pair driver over a collection: for each pair p, op(A[ia[p]], B[ib[p]]).
+/* Per-pair loop over a collection: for each pair p, op(A[ia[p]], B[ib[p]]).
  * Writes the result size to card[p] (if card != NULL), the digest of the
  * result to digest[p] (if digest != NULL) and the Jaccard index to jac[p] (if
  * jac != NULL). Scratch `tmp` must hold the largest possible result. */

@@ -283,7 +283,7 @@ def test_digest_properties():
     assert oracle.digest(np.zeros(0, np.uint32)) == 0
 
 
-def test_pairs_driver():
+def test_pairs_loop():
     rng = np.random.default_rng(9)
     lists = [_rand_set(rng, int(rng.integers(0, 3000)), 1 << 18) for _ in range(10)]
     offs = np.zeros(11, np.uint64)
