@@ -40,7 +40,7 @@ def main():
     ap.add_argument("--bitmaps", type=int, default=20000)
     ap.add_argument("--keys", type=int, default=256)
     ap.add_argument("--pairs", type=int, default=10000)
-    ap.add_argument("--cpu-pairs", type=int, default=24, help="pairs in the oracle timing sample")
+    ap.add_argument("--cpu-pairs", type=int, default=48, help="pairs in the oracle timing sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", type=int, default=2, help="pairs checked against the oracle before timing")
     ap.add_argument("--workload", choices=("dense", "batched", "serve"), default="dense",
