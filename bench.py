@@ -43,7 +43,7 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=48, help="pairs in the oracle timing sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", type=int, default=2, help="pairs checked against the oracle before timing")
-    ap.add_argument("--workload", choices=("dense", "batched", "serve"), default="dense",
+    ap.add_argument("--workload", choices=("dense", "dense-mat", "batched", "serve"), default="dense",
                     help="dense: the bitset-bandwidth headline; batched: many uneven pairs, plan vs per-pair; "
                          "serve: k-way queries under Poisson arrivals, batched server vs one query at a time")
     ap.add_argument("--index", type=int, default=4000, help="serve: bitmaps in the index")
@@ -81,6 +81,8 @@ def main():
         return None
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "dense-mat":
+        return bench_dense_mat(args)
     if args.workload == "serve":
         return bench_serve(args)
     dev = torch.device("cuda:0")
@@ -178,6 +180,72 @@ def main():
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "roofline": roof,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_dense_mat(args):
+    """Materialised AND/OR/XOR/ANDNOT of dense bitset pairs: the dense-bitset
+    recipe at a tenth of its pairs (--bitmaps 2000 --pairs 1000 by default for
+    this workload), every result written into a preallocated arena (each op's
+    first call sizes it). GB/s = (input bytes + result payload bytes) / time."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1709_07821_amd as rg
+    import synth
+
+    dev = torch.device("cuda:0")
+    ctx = rg.Context(0)
+    stream = torch.cuda.current_stream()
+    nb = args.bitmaps if args.bitmaps != 20000 else 2000
+    npairs = args.pairs if args.pairs != 10000 else 1000
+    nk = args.keys
+    words = torch.empty(nb * nk * 1024, dtype=torch.int64, device=dev)
+    for b0 in range(0, nb, 1000):
+        synth.dense_bitsets_device(words.data_ptr() + b0 * nk * 8192, b0, min(1000, nb - b0), nk, stream.cuda_stream)
+    P = rg.Pool.from_dense_words(ctx, words, nb, nk)
+    ia, ib = synth.random_pairs(nb, npairs, seed=synth.DENSE_SEED)
+    tia = torch.from_numpy(ia.view(np.int32)).to(dev)
+    tib = torch.from_numpy(ib.view(np.int32)).to(dev)
+    arenas = {}
+    for op in rg.OPS:
+        arenas[op], _, _ = rg.batch(ctx, op, P, P, tia, tib, materialize=True, card=True)
+    torch.cuda.synchronize()
+    # correctness gate: two pairs of every op against the oracle (fingerprints)
+    for op in rg.OPS:
+        dig = rg.rg_pool_digest(ctx, arenas[op].as_pool()).cpu().numpy().view(np.uint64)
+        for p in range(2):
+            exp = oracle.op(op, synth.dense_bitmap_values(int(ia[p]), nk), synth.dense_bitmap_values(int(ib[p]), nk))
+            assert int(dig[p]) == oracle.digest(exp), (op, p)
+    print(f"# {nb} x {nk} bitsets, {npairs} pairs; 2 pairs x 4 ops match the oracle", file=sys.stderr, flush=True)
+    out_bytes = {op: int(arenas[op].c.payload_used) for op in rg.OPS}
+
+    def step():
+        for op in rg.OPS:
+            rg.batch(ctx, op, P, P, tia, tib, materialize=True, card=True, out=arenas[op])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    in_bytes = 4 * npairs * nk * 2 * 8192
+    total = in_bytes + sum(out_bytes.values())
+    line = {
+        "metric": "materialised AND/OR/XOR/ANDNOT of dense bitset pairs, input + result GB/s",
+        "value": round(total / dt / 1e9, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"dense-bitset pairs, materialised: {nb} bitmaps x {nk} bitset containers, "
+                               f"{npairs} random pairs, four operations", "bitmaps": nb, "pairs": npairs,
+                   "parallelism": "single GPU"},
+        "result_payload_bytes": out_bytes,
+        "pct_hbm_peak": round(100 * total / dt / 1e9 / HBM_PEAK_GBS, 2),
     }
     print(json.dumps(line), flush=True)
 

@@ -16,9 +16,11 @@
 //   3. k_kw_eval: one workgroup per result key. Intersection: every container
 //      is expanded into an LDS bitset and combined word by word, stopping once
 //      the running result is empty. Union, symmetric difference, difference:
-//      all containers fold into one LDS bitset at once (LDS atomics per array
-//      value, bitset word or run). Then the common output step (P1 type,
-//      payload into the slot) or, count-only, the population count.
+//      bitset containers are combined in registers (each thread owns four
+//      result words), then all array and run containers fold into the LDS
+//      bitset at once (an LDS atomic per value or run). Then the common output
+//      step (P1 type, payload into the slot) or, count-only, the population
+//      count.
 // Compaction of non-empty results into per-query bitmaps uses the pairwise
 // path's kernels (flags, scan, compact, bitmap starts).
 #include "rg_count_dev.h"
@@ -316,24 +318,24 @@ __global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
         __syncthreads();
         bool empty = false;
         bool first = true;
+        bool direct = false;  // the result words are already in w (registers)
+        uint64_t w[4] = {0, 0, 0, 0};
         if (op != RG_AND) {
-            // Union and symmetric difference: all present containers fold into a
-            // zeroed bitset at once. Difference: the first container is expanded,
-            // then all others clear their bits at once. No container waits for
-            // another.
+            // Union, symmetric difference, difference. Every thread owns words
+            // 4t..4t+3 of the result: it combines the matching words of each
+            // bitset container in registers (no atomics), starting from zero or,
+            // for a difference, from the expanded first container. Array and
+            // run containers then fold into the LDS bitset all at once with one
+            // LDS atomic per value or run. No container waits for another.
             const uint32_t j0 = op == RG_ANDNOT ? 1u : 0u;
-            if (op == RG_ANDNOT) {
-                expand_container(sh.sa, a.P0, uniform(cidx[0]), sh);
-            } else {
-                for (uint32_t i = tid; i < 1024; i += 256) sh.sa[i] = 0;
-            }
             uint32_t units = 0;
-            if (tid < k && tid >= j0) {
+            if (tid < k) {
+                ctype[tid] = 0;  // absent (or the first container of a difference)
                 const uint32_t ci = cidx[tid];
-                if (ci != NONE) {
+                if (ci != NONE && tid >= j0) {
                     const PoolView pv = kw_side(a, tid != 0);
                     const uint8_t ty = pv.types[ci];
-                    units = ty == RG_BITSET ? 1024u : pv.size[ci];
+                    units = ty == RG_BITSET ? 0u : pv.size[ci];
                     ctype[tid] = ty;
                     cpl[tid] = reinterpret_cast<uint64_t>(pv.payload + pv.off[ci]);
                 }
@@ -342,11 +344,35 @@ __global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
             const uint32_t pos = block_excl_scan_u32(units, sh.tmp, &total);
             if (tid < k) cunits[tid] = pos;
             if (tid == 0) cunits[k] = total;
-            __syncthreads();
-            if (op == RG_ANDNOT) kw_fold_units<2>(sh.sa, cunits, ctype, cpl, uniform(total));
-            else if (op == RG_XOR) kw_fold_units<1>(sh.sa, cunits, ctype, cpl, uniform(total));
-            else kw_fold_units<0>(sh.sa, cunits, ctype, cpl, uniform(total));
-            __syncthreads();
+            if (op == RG_ANDNOT) expand_container(sh.sa, a.P0, uniform(cidx[0]), sh);  // ends with a barrier
+            else __syncthreads();
+            uint64_t r[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) r[q] = op == RG_ANDNOT ? sh.sa[4 * tid + q] : 0ull;
+            for (uint32_t jj = j0; jj < k; ++jj) {
+                if (uniform(ctype[jj]) != RG_BITSET) continue;
+                const u32x4* src = reinterpret_cast<const u32x4*>(cpl[jj]) + 2 * tid;
+                const u32x4 v0 = src[0], v1 = src[1];
+                const uint64_t x[4] = {(uint64_t)v0.x | ((uint64_t)v0.y << 32), (uint64_t)v0.z | ((uint64_t)v0.w << 32),
+                                       (uint64_t)v1.x | ((uint64_t)v1.y << 32), (uint64_t)v1.z | ((uint64_t)v1.w << 32)};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) r[q] = op == RG_OR ? (r[q] | x[q]) : op == RG_XOR ? (r[q] ^ x[q]) : (r[q] & ~x[q]);
+            }
+            const uint32_t tu = uniform(total);
+            if (tu == 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) w[q] = r[q];
+                direct = true;
+            } else {
+                __syncthreads();  // every thread has read its start words from sh.sa
+#pragma unroll
+                for (int q = 0; q < 4; ++q) sh.sa[4 * tid + q] = r[q];
+                __syncthreads();
+                if (op == RG_ANDNOT) kw_fold_units<2>(sh.sa, cunits, ctype, cpl, tu);
+                else if (op == RG_XOR) kw_fold_units<1>(sh.sa, cunits, ctype, cpl, tu);
+                else kw_fold_units<0>(sh.sa, cunits, ctype, cpl, tu);
+                __syncthreads();
+            }
             first = false;
         }
         // intersection: running result in sh.sa, starting from the container
@@ -390,9 +416,10 @@ __global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
             }
             first = false;
         }
-        uint64_t w[4];
+        if (!direct) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) w[i] = (empty || first) ? 0ull : sh.sa[4 * tid + i];
+            for (int i = 0; i < 4; ++i) w[i] = (empty || first) ? 0ull : sh.sa[4 * tid + i];
+        }
         __syncthreads();
         if (flags & KW_MATERIALIZE) {
             finalize_words(w, (uint32_t)s, a.so, sh.sa, sh.sb, sh);
