@@ -438,3 +438,30 @@ def test_packed_metadata_same_results(rg, ctx, which):
         e = oracle.op("and", bs[int(ia[p])], bs[int(ib[p])])
         got, meta = rgtest.decode_bitmap(h, p)
         assert np.array_equal(got, e) and meta == rgtest.oracle_meta(oracle, e), p
+
+
+def test_array_stress_full_size_materialised(rg, ctx):
+    """Array-array stress at full size (1e5 pairs) materialised for all four
+    operations: every pair's cardinality and container-form fingerprint equal
+    the oracle's (union and symmetric difference results above 4096 values
+    become bitsets or runs by P1); a sample of results is decoded in full."""
+    import torch
+
+    bs, ia, ib = synth.array_stress()
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    tia, tib = _t(ia), _t(ib)
+    for op in OPS:
+        _say(f"[array-stress full mat] op={op}")
+        card, dig, _ = oracle.pairs(op, bs.values, bs.offsets, bs.values, bs.offsets, ia, ib, want_digest=True)
+        out, c, _ = rg.batch(ctx, op, P, P, tia, tib, materialize=True, card=True)
+        torch.cuda.synchronize()
+        res = out.as_pool()
+        assert rg.rg_pool_validate(ctx, res) == 0
+        assert np.array_equal(c.cpu().numpy().view(np.uint64), card), op
+        assert np.array_equal(rg.rg_pool_digest(ctx, res).cpu().numpy().view(np.uint64), dig), op
+        h = res.to_host()
+        for p in np.random.default_rng(3).choice(len(ia), 20, replace=False):
+            e = oracle.op(op, bs[int(ia[p])], bs[int(ib[p])])
+            got, meta = rgtest.decode_bitmap(h, int(p))
+            assert np.array_equal(got, e) and meta == rgtest.oracle_meta(oracle, e), (op, p)
+        del out, res, h
