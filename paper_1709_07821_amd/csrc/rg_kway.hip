@@ -28,6 +28,9 @@
 namespace rg {
 
 constexpr int KW_UNROLL = 4;  // independent loads in flight per thread in the key and fold passes
+// Task.bin of a k-way result key whose containers are recorded in Task.ia
+// (first bitmap) and Task.ib (second), NONE where absent: queries of k <= 2.
+constexpr uint8_t KW_TASK_INDEXED = 1;
 
 __device__ __forceinline__ uint32_t kw_find_key(const uint64_t* bm_begin, const uint16_t* keys, uint32_t b,
                                                 uint16_t key) {
@@ -75,7 +78,10 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a) {
     for (uint32_t i = tid; i < 1024; i += 256) acc[i] = 0;
     // all key ranges at once (one load level instead of one per bitmap)
     const uint32_t kk = op == RG_ANDNOT ? 1u : k;  // bitmaps that decide the result keys
-    for (uint32_t j = tid; j < kk; j += 256) {
+    // With at most two bitmaps each result key's containers are recorded in its
+    // task (positions from the two key masks), so the later kernels need no search.
+    const bool indexed = k <= 2;
+    for (uint32_t j = tid; j < (indexed ? k : kk); j += 256) {
         const uint64_t* bmb = j ? a.P1.bm_begin : a.P0.bm_begin;
         const uint32_t b = a.ids[ids0 + j];
         const uint64_t s0 = bmb[b];
@@ -84,7 +90,30 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a) {
     }
     __syncthreads();
     // result keys: AND - in every bitmap; OR, XOR - in any; ANDNOT - the first bitmap's
-    if (op != RG_AND) {
+    if (indexed) {
+        // the key masks of both bitmaps, side by side: acc = bitmap 0, cur = bitmap 1
+        for (uint32_t i = tid; i < 1024; i += 256) cur[i] = 0;
+        __syncthreads();
+        for (uint32_t j = 0; j < k; ++j) {
+            const uint16_t* pkeys = j ? a.P1.keys : a.P0.keys;
+            const uint64_t s0 = rs[j];
+            const uint32_t n = uniform(rn[j]);
+            uint64_t* dst = j == 0 ? acc : cur;
+            for (uint32_t base = 0; base < n; base += 256 * KW_UNROLL) {
+                uint32_t key[KW_UNROLL];
+#pragma unroll
+                for (int r = 0; r < KW_UNROLL; ++r) {
+                    const uint32_t i = base + r * 256 + tid;
+                    key[r] = i < n ? pkeys[s0 + i] : 0xFFFFFFFFu;
+                }
+#pragma unroll
+                for (int r = 0; r < KW_UNROLL; ++r)
+                    if (key[r] != 0xFFFFFFFFu)
+                        atomicOr(reinterpret_cast<unsigned long long*>(&dst[key[r] >> 6]), 1ull << (key[r] & 63));
+            }
+        }
+        __syncthreads();
+    } else if (op != RG_AND) {
         // a union of key sets: every key of every deciding bitmap sets its bit,
         // in one pass over the concatenated lists
         if (tid == 0) {
@@ -147,21 +176,34 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a) {
         }
     }
     // ascending keys: thread t owns words 4t..4t+3
-    uint64_t w[4];
-    uint32_t c = 0;
+    uint64_t w[4], m0[4], m1[4];
+    uint32_t c = 0, c0 = 0, c1 = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        w[j] = acc[4 * tid + j];
+        m0[j] = acc[4 * tid + j];
+        m1[j] = indexed && k == 2 ? cur[4 * tid + j] : 0ull;
+        w[j] = !indexed ? m0[j]
+               : k == 1 ? m0[j]
+               : op == RG_AND ? (m0[j] & m1[j]) : op == RG_ANDNOT ? m0[j] : (m0[j] | m1[j]);
         c += __popcll(w[j]);
+        c0 += __popcll(m0[j]);
+        c1 += __popcll(m1[j]);
     }
     uint32_t total;
     uint32_t pos = block_excl_scan_u32(c, tmp, &total);
+    // with recorded positions: ranks of this thread's first word in each key mask
+    uint32_t r0 = 0, r1 = 0, unused;
+    if (indexed) {
+        r0 = block_excl_scan_u32(c0, tmp, &unused);
+        r1 = block_excl_scan_u32(c1, tmp, &unused);
+    }
     // total <= kbound holds by construction of the host bound; guard anyway
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         uint64_t x = w[j];
         while (x) {
-            const uint32_t key = (4 * tid + j) * 64 + (uint32_t)__builtin_ctzll(x);
+            const uint32_t b = (uint32_t)__builtin_ctzll(x);
+            const uint32_t key = (4 * tid + j) * 64 + b;
             x &= x - 1;
             if (pos < kbound) {
                 Task t;
@@ -171,10 +213,19 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a) {
                 t.key = (uint16_t)key;
                 t.kind = KIND_MATCH;
                 t.bin = 0;
+                if (indexed) {
+                    // container index = list start + number of the bitmap's keys below this one
+                    const uint64_t below = (1ull << b) - 1ull;
+                    if ((m0[j] >> b) & 1ull) t.ia = (uint32_t)(rs[0] + r0 + __popcll(m0[j] & below));
+                    if ((m1[j] >> b) & 1ull) t.ib = (uint32_t)(rs[1] + r1 + __popcll(m1[j] & below));
+                    t.bin = KW_TASK_INDEXED;
+                }
                 a.tasks[slot0 + pos] = t;
             }
             ++pos;
         }
+        r0 += __popcll(m0[j]);
+        r1 += __popcll(m1[j]);
     }
     const uint32_t used = total < kbound ? total : kbound;
     for (uint32_t i = used + tid; i < kbound; i += 256) {
@@ -221,7 +272,8 @@ __global__ void __launch_bounds__(256) k_kw_bounds(KwArgs a) {
                 uint32_t cj = 0;
                 if (j < k) {
                     const PoolView pv = kw_side(a, j != 0);
-                    const uint32_t ci = kw_find_key(pv.bm_begin, pv.keys, a.ids[ids0 + j], t.key);
+                    const uint32_t ci = t.bin == KW_TASK_INDEXED ? (j == 0 ? t.ia : t.ib)
+                                                                 : kw_find_key(pv.bm_begin, pv.keys, a.ids[ids0 + j], t.key);
                     cj = ci == NONE ? 0u : pv.card[ci];
                 }
                 if (j0 == 0) first = __builtin_amdgcn_readlane(cj, 0);
@@ -311,9 +363,13 @@ __global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
         const uint32_t op = uniform(Q.op), k = uniform(Q.k), flags = uniform(Q.flags);
         const uint32_t ids0 = uniform(Q.ids_off);
         if (tid < k) {
-            const uint64_t* bmb = tid ? a.P1.bm_begin : a.P0.bm_begin;
-            const uint16_t* pkeys = tid ? a.P1.keys : a.P0.keys;
-            cidx[tid] = kw_find_key(bmb, pkeys, a.ids[ids0 + tid], t.key);
+            if (t.bin == KW_TASK_INDEXED) {
+                cidx[tid] = tid == 0 ? t.ia : t.ib;
+            } else {
+                const uint64_t* bmb = tid ? a.P1.bm_begin : a.P0.bm_begin;
+                const uint16_t* pkeys = tid ? a.P1.keys : a.P0.keys;
+                cidx[tid] = kw_find_key(bmb, pkeys, a.ids[ids0 + tid], t.key);
+            }
         }
         __syncthreads();
         bool empty = false;
