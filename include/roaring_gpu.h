@@ -121,7 +121,9 @@ typedef struct rg_out {
 /* ---- context ---------------------------------------------------------- */
 
 /* Create a context on HIP device `device`. The context owns a growable device
- * workspace and pinned host staging; it is not thread-safe (one per thread). */
+ * workspace and pinned host staging; it is not thread-safe (one per thread).
+ * Calls that use the workspace may be issued on different streams: each waits,
+ * on the device, for the previous one to finish with it. */
 rg_status rg_create(rg_ctx **ctx, int device);
 void rg_destroy(rg_ctx *ctx);
 const char *rg_last_error(const rg_ctx *ctx);

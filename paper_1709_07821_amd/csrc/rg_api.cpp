@@ -79,6 +79,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
     if (n_pairs > 0xFFFFFFFFull) return fail(c, RG_EINVAL, "at most 2^32-1 pairs per call");
     if ((d_ia == nullptr) != (d_ib == nullptr)) return fail(c, RG_EINVAL, "d_ia and d_ib go together");
     HIPCHK(c, hipSetDevice(c->device));
+    WorkspaceOrder order(c, st);
     if (mat) {
         out->n_containers = 0;
         out->payload_used = 0;
@@ -89,7 +90,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
         if (mat) launch_fill_u64(out->bm_begin, 0, 1, st);
         return RG_OK;
     }
-    const PoolView pa = view(*A), pb = view(*B);
+    PoolView pa = view(*A), pb = view(*B);
 
     // ---- per-pair preparation
     Bump bp{nullptr};
@@ -159,6 +160,40 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
     S_max = std::max(S_max, accs);
     P_max = std::max(P_max, n_pairs - wstart.back());
     wstart.push_back(n_pairs);
+
+    // A count-only call that visits many more candidate keys than its pools
+    // hold containers packs their metadata first (one pass, 16 B per container,
+    // as a plan does), unless the pools carry records already. Without the
+    // memory for it the call reads the arrays.
+    if (!mat && !c->cost_out && !(pa.meta && pb.meta)) {
+        const bool same = A->keys == B->keys && A->off == B->off && A->n_containers == B->n_containers;
+        const uint64_t nA = A->n_containers, nB = same ? 0 : B->n_containers;
+        uint64_t ctot = 0;
+        for (uint64_t p = 0; p < n_pairs; ++p) ctot += h_cand[p];
+        if (nA + nB > 0 && ctot >= META_PACK_FACTOR * (nA + nB)) {
+            const size_t need = 16 * (nA + nB);
+            bool ok = need <= c->ws_meta_bytes;
+            if (!ok) {
+                if (c->ws_meta) {
+                    HIPCHK(c, hipDeviceSynchronize());
+                    HIPCHK(c, hipFree(c->ws_meta));
+                }
+                ok = hipMalloc(&c->ws_meta, need) == hipSuccess;
+                c->ws_meta_bytes = ok ? need : 0;
+                if (!ok) {
+                    c->ws_meta = nullptr;
+                    (void)hipGetLastError();  // not an error of the call: it runs unpacked
+                }
+            }
+            if (ok) {
+                u32x4* ma = reinterpret_cast<u32x4*>(c->ws_meta);
+                launch_pack_meta(view(*A), nA, ma, st);
+                if (!same) launch_pack_meta(view(*B), nB, ma + nA, st);
+                pa.meta = ma;
+                pb.meta = same ? ma : ma + nA;
+            }
+        }
+    }
 
     // materialised OR / XOR / ANDNOT run through the k-way path (two bitmaps
     // per query): key set per pair, then one workgroup per result key
@@ -398,6 +433,8 @@ void rg_destroy(rg_ctx* c) {
     (void)hipDeviceSynchronize();
     if (c->ws_pairs) (void)hipFree(c->ws_pairs);
     if (c->ws_wave) (void)hipFree(c->ws_wave);
+    if (c->ws_meta) (void)hipFree(c->ws_meta);
+    if (c->ws_event) (void)hipEventDestroy(c->ws_event);
     if (c->small) (void)hipFree(c->small);
     if (c->host) (void)hipHostFree(c->host);
     if (c->mlp_table) (void)hipFree(c->mlp_table);

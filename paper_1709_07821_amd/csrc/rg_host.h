@@ -21,6 +21,12 @@ struct rg_ctx {
     void* small = nullptr;     // 4 KiB of counters
     void* host = nullptr;      // pinned staging
     size_t host_bytes = 0;
+    void* ws_meta = nullptr;   // packed container metadata of a large count-only call
+    size_t ws_meta_bytes = 0;
+    // completion of the last call that used the workspaces, on its stream: the
+    // next call waits for it on its own stream (no host synchronisation)
+    hipEvent_t ws_event = nullptr;
+    bool ws_event_live = false;
     // kernel timing (rg_profile_*): events around each compute-kernel launch
     struct Pending {
         hipEvent_t a, b;
@@ -76,6 +82,24 @@ inline rg_status grow_device(rg_ctx* c, void** buf, size_t* cap, size_t need) {
     *cap = nb;
     return RG_OK;
 }
+
+// Orders a call that uses the context's workspaces after the previous such
+// call, whatever streams they are on: waits (on the device) for the previous
+// call's completion event, and records its own when it goes out of scope.
+struct WorkspaceOrder {
+    rg_ctx* c;
+    hipStream_t st;
+    WorkspaceOrder(rg_ctx* c_, hipStream_t st_) : c(c_), st(st_) {
+        if (c->ws_event_live) (void)hipStreamWaitEvent(st, c->ws_event, 0);
+    }
+    ~WorkspaceOrder() {
+        if (!c->ws_event && hipEventCreateWithFlags(&c->ws_event, hipEventDisableTiming) != hipSuccess) {
+            c->ws_event = nullptr;
+            return;
+        }
+        c->ws_event_live = hipEventRecord(c->ws_event, st) == hipSuccess;
+    }
+};
 
 inline rg_status grow_host(rg_ctx* c, size_t need) {
     if (need <= c->host_bytes) return RG_OK;

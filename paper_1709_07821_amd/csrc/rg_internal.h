@@ -64,6 +64,9 @@ struct PoolView {
 };
 
 constexpr uint32_t META_INLINE_MAX = 4;  // array values held in a packed record
+// A count-only call packs its pools' metadata when it visits at least this many
+// candidate keys per container of the pools (packing costs one pass over them).
+constexpr uint64_t META_PACK_FACTOR = 4;
 // Packs the metadata records of a pool's n containers (PoolView::meta).
 void launch_pack_meta(const PoolView& P, uint64_t n, u32x4* out, hipStream_t st);
 

@@ -265,6 +265,7 @@ extern "C" rg_status roaring_multi(rg_ctx* c, int op, const rg_pool* pool, const
                 !out->payload || !out->bm_card || !out->bm_wbytes))
         return fail(c, RG_EINVAL, "materialisation needs a complete rg_out (with bm_wbytes)");
     HIPCHK(c, hipSetDevice(c->device));
+    WorkspaceOrder order(c, (hipStream_t)stream);
     hipStream_t st = (hipStream_t)stream;
     // per-id metadata -> host bounds (one small readback)
     if (rg_status s = grow_device(c, &c->ws_pairs, &c->ws_pairs_bytes, align256(24 * k) + 256)) return s;
