@@ -57,7 +57,7 @@ rg_status drain_profile(rg_ctx* c) {
 
 // per-slot bytes of the wave workspace
 constexpr size_t SLOT_BYTES = sizeof(Task) + 4 /*ub*/ + 8 /*slot_off*/ + 4 /*res_card*/ + 1 /*res_type*/ +
-                              4 /*res_size*/ + 4 /*flags*/ + 8 /*out_idx*/ + 4 /*bin list*/ + 4 /*redo*/;
+                              4 /*res_size*/ + 8 /*out_idx*/ + 4 /*bin list*/ + 4 /*redo*/;
 
 }  // namespace
 
@@ -211,7 +211,6 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
     uint32_t* res_card = wb.take<uint32_t>(S_max);
     uint8_t* res_type = wb.take<uint8_t>(S_max);
     uint32_t* res_size = wb.take<uint32_t>(S_max);
-    uint32_t* sflags = wb.take<uint32_t>(S_max);
     uint64_t* out_idx = wb.take<uint64_t>(S_max);
     uint32_t* bin_lists = wb.take<uint32_t>(S_max);
     uint32_t* redo_list = wb.take<uint32_t>(S_max);
@@ -353,8 +352,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
         }
         HIPCHK(c, hipGetLastError());
         if (mat) {
-            launch_flags(res_card, sflags, C, st);
-            launch_scan_u32_u64(sflags, out_idx, C, out_base, partials, totals + 1, st);
+            launch_scan_nonzero_u64(res_card, out_idx, C, out_base, partials, totals + 1, st);
             CompactArgs cp;
             cp.tasks = tasks;
             cp.n_slots = C;

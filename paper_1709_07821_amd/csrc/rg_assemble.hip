@@ -15,18 +15,6 @@
 
 namespace rg {
 
-__global__ void k_flags(const uint32_t* res_card, uint32_t* flags, uint64_t n) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        flags[i] = res_card[i] ? 1u : 0u;
-}
-
-void launch_flags(const uint32_t* res_card, uint32_t* flags, uint64_t n, hipStream_t st) {
-    if (!n) return;
-    uint64_t g = (n + 255) / 256;
-    if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_flags, dim3((uint32_t)g), dim3(256), 0, st, res_card, flags, n);
-}
-
 __global__ void k_compact(CompactArgs c) {
     for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < c.n_slots;
          s += (uint64_t)gridDim.x * blockDim.x) {

@@ -246,6 +246,9 @@ void launch_bin_scatter(const Task* tasks, uint64_t n, const uint32_t* blk_cnt, 
 // exclusive scan of u32 into u64 with an added base; writes total to *total_out (device)
 void launch_scan_u32_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t base, uint64_t* partials,
                          uint64_t* total_out, hipStream_t st);
+// The same exclusive scan over (in[i] != 0): output positions of the non-empty results.
+void launch_scan_nonzero_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t base, uint64_t* partials,
+                             uint64_t* total_out, hipStream_t st);
 size_t scan_partials_needed(uint64_t n);
 
 struct ComputeArgs {
@@ -287,7 +290,6 @@ struct CompactArgs {
     uint64_t* bm_wbytes;      // may be null
     uint64_t pair0;
 };
-void launch_flags(const uint32_t* res_card, uint32_t* flags, uint64_t n, hipStream_t st);
 void launch_compact(const CompactArgs& c, hipStream_t st);
 void launch_bm_begin(const uint64_t* cand_off, const uint64_t* out_idx, uint64_t n_slots, const uint64_t* out_total,
                      uint32_t n_pairs, uint64_t pair0, uint64_t* bm_begin, bool last_wave, hipStream_t st);

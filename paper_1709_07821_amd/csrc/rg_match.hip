@@ -480,13 +480,15 @@ constexpr uint32_t SCAN_TILE = 256 * SCAN_PER_THREAD;
 
 size_t scan_partials_needed(uint64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE) + 1; }
 
+// NZ: the scanned value of element i is (in[i] != 0) rather than in[i]
+template <bool NZ>
 __global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t* in, uint64_t n, uint64_t* partials) {
     __shared__ uint64_t tmp[4];
     uint64_t start = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_PER_THREAD;
     uint64_t s = 0;
 #pragma unroll
     for (uint32_t k = 0; k < SCAN_PER_THREAD; ++k)
-        if (start + k < n) s += in[start + k];
+        if (start + k < n) s += NZ ? (in[start + k] != 0u ? 1u : 0u) : in[start + k];
     s = block_sum_u64(s, tmp);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
@@ -515,6 +517,7 @@ __global__ void __launch_bounds__(256) k_scan_partials(uint64_t* partials, uint6
     if (threadIdx.x == 0 && total_out) *total_out = carry;
 }
 
+template <bool NZ>
 __global__ void __launch_bounds__(256) k_scan_down(const uint32_t* in, uint64_t n, const uint64_t* partials,
                                                    uint64_t* out) {
     __shared__ uint64_t tmp[4];
@@ -523,7 +526,7 @@ __global__ void __launch_bounds__(256) k_scan_down(const uint32_t* in, uint64_t 
     uint64_t s = 0;
 #pragma unroll
     for (uint32_t k = 0; k < SCAN_PER_THREAD; ++k) {
-        v[k] = start + k < n ? in[start + k] : 0;
+        v[k] = start + k < n ? (NZ ? (in[start + k] != 0u ? 1u : 0u) : in[start + k]) : 0;
         s += v[k];
     }
     // block exclusive scan of per-thread sums (64-bit)
@@ -547,6 +550,7 @@ __global__ void __launch_bounds__(256) k_scan_down(const uint32_t* in, uint64_t 
 }
 
 // one tile: the whole scan in one workgroup (small inputs: one launch, not three)
+template <bool NZ>
 __global__ void __launch_bounds__(256) k_scan_single(const uint32_t* in, uint64_t n, uint64_t base, uint64_t* out,
                                                      uint64_t* total_out) {
     __shared__ uint64_t tmp[4];
@@ -555,7 +559,7 @@ __global__ void __launch_bounds__(256) k_scan_single(const uint32_t* in, uint64_
     uint64_t s = 0;
 #pragma unroll
     for (uint32_t k = 0; k < SCAN_PER_THREAD; ++k) {
-        v[k] = start + k < n ? in[start + k] : 0;
+        v[k] = start + k < n ? (NZ ? (in[start + k] != 0u ? 1u : 0u) : in[start + k]) : 0;
         s += v[k];
     }
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
@@ -578,20 +582,31 @@ __global__ void __launch_bounds__(256) k_scan_single(const uint32_t* in, uint64_
     if (threadIdx.x == 255 && total_out) *total_out = base + wbase + inc;
 }
 
-void launch_scan_u32_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t base, uint64_t* partials,
-                         uint64_t* total_out, hipStream_t st) {
+template <bool NZ>
+static void launch_scan(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t base, uint64_t* partials,
+                        uint64_t* total_out, hipStream_t st) {
     uint64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb == 0) {
         if (total_out) hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, st, total_out, base, (uint64_t)1);
         return;
     }
     if (nb == 1) {
-        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(256), 0, st, in, n, base, out, total_out);
+        hipLaunchKernelGGL(k_scan_single<NZ>, dim3(1), dim3(256), 0, st, in, n, base, out, total_out);
         return;
     }
-    hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)nb), dim3(256), 0, st, in, n, partials);
+    hipLaunchKernelGGL(k_scan_reduce<NZ>, dim3((uint32_t)nb), dim3(256), 0, st, in, n, partials);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(256), 0, st, partials, nb, base, total_out);
-    hipLaunchKernelGGL(k_scan_down, dim3((uint32_t)nb), dim3(256), 0, st, in, n, partials, out);
+    hipLaunchKernelGGL(k_scan_down<NZ>, dim3((uint32_t)nb), dim3(256), 0, st, in, n, partials, out);
+}
+
+void launch_scan_u32_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t base, uint64_t* partials,
+                         uint64_t* total_out, hipStream_t st) {
+    launch_scan<false>(in, out, n, base, partials, total_out, st);
+}
+
+void launch_scan_nonzero_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t base, uint64_t* partials,
+                             uint64_t* total_out, hipStream_t st) {
+    launch_scan<true>(in, out, n, base, partials, total_out, st);
 }
 
 }  // namespace rg

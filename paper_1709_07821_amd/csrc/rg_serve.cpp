@@ -69,7 +69,7 @@ Bounds query_bounds(int op, uint32_t k, const uint64_t* meta, bool mat) {
 // Device layout of one step (each piece 256-byte aligned):
 //   upload   : queries, ids, cand_off            (mirrored in pinned host memory)
 //   download : cards, digest, bm_begin, totals, err
-//   work     : tasks, ub, slot_off, res_card, res_type, res_size, sflags, out_idx, partials, acc
+//   work     : tasks, ub, slot_off, res_card, res_type, res_size, out_idx, partials, acc
 //   out      : keys, types, card, size, off, payload, bm_card, bm_wbytes (unless the caller's)
 struct StepLayout {
     uint32_t nq = 0;
@@ -78,7 +78,7 @@ struct StepLayout {
     size_t up_bytes = 0, down_off = 0, down_bytes = 0, total = 0;
     // offsets
     size_t o_queries, o_ids, o_cand, o_cards, o_digest, o_bm_begin, o_totals, o_err, o_tasks, o_ub, o_slot_off,
-        o_res_card, o_res_type, o_res_size, o_sflags, o_out_idx, o_partials, o_acc, o_keys, o_types, o_card,
+        o_res_card, o_res_type, o_res_size, o_out_idx, o_partials, o_acc, o_keys, o_types, o_card,
         o_size, o_off, o_payload, o_bm_card, o_bm_wbytes;
 
     void plan(uint32_t nq_, uint64_t nids_, uint64_t S_, uint64_t P_, bool own) {
@@ -110,7 +110,6 @@ struct StepLayout {
         o_res_card = take(4 * S);
         o_res_type = take(S);
         o_res_size = take(4 * S);
-        o_sflags = take(4 * S);
         o_out_idx = take(8 * S);
         o_partials = take(8 * scan_partials_needed(S));
         o_acc = take(8 * nq);
@@ -179,7 +178,6 @@ rg_status step_enqueue(std::string* err_out, const rg_pool& pool, const StepLayo
     auto* res_card = reinterpret_cast<uint32_t*>(d + L.o_res_card);
     auto* res_type = d + L.o_res_type;
     auto* res_size = reinterpret_cast<uint32_t*>(d + L.o_res_size);
-    auto* sflags = reinterpret_cast<uint32_t*>(d + L.o_sflags);
     auto* out_idx = reinterpret_cast<uint64_t*>(d + L.o_out_idx);
     auto* partials = reinterpret_cast<uint64_t*>(d + L.o_partials);
     auto* acc = reinterpret_cast<long long*>(d + L.o_acc);
@@ -206,8 +204,7 @@ rg_status step_enqueue(std::string* err_out, const rg_pool& pool, const StepLayo
     if (L.S) launch_scan_u32_u64(ub, slot_off, L.S, 0, partials, totals, st);
     launch_kw_eval(a, st);
     if (L.S) {
-        launch_flags(res_card, sflags, L.S, st);
-        launch_scan_u32_u64(sflags, out_idx, L.S, 0, partials, totals + 1, st);
+        launch_scan_nonzero_u64(res_card, out_idx, L.S, 0, partials, totals + 1, st);
         CompactArgs cp;
         cp.tasks = tasks;
         cp.n_slots = L.S;
