@@ -297,20 +297,24 @@ rg_status rg_profile_read(rg_ctx *ctx, int variant, int materialize, double *tot
                           uint64_t *items);
 
 /* ---- k-way queries and the serving loop ---------------------------------
- * roaring_multi: the intersection (op RG_AND) or union (RG_OR) of k bitmaps
+ * roaring_multi: the intersection (op RG_AND), union (RG_OR), symmetric
+ * difference (RG_XOR: the values held by an odd number of the k bitmaps) or
+ * difference (RG_ANDNOT: the first bitmap minus all the others) of k bitmaps
  * of one pool, d_ids[0..k) (device uint32, 1 <= k <= 256, ids may repeat).
  * The paper builds wide unions and intersections by folding pairwise or by
  * lazy aggregation (Section 2.2, Section 5.9); here each result container is
  * built directly from the k input containers of its key. flags:
  * RG_FLAG_MATERIALIZE (result bitmap 0 of `out`, which needs bm_wbytes) and/or
  * RG_FLAG_CARD (cardinality into d_card[0], device uint64). Output sizing as
- * for the pairwise calls (RG_ECAPACITY with needed_*): at most min_i K_i (AND)
- * or min(65536, sum_i K_i) (OR) containers and min_i / sum_i bm_wbytes bytes.
+ * for the pairwise calls (RG_ECAPACITY with needed_*): at most min_i K_i (AND),
+ * min(65536, sum_i K_i) (OR, XOR) or K_1 (ANDNOT) containers, and the matching
+ * min / sum / first of the bm_wbytes bytes.
  * Synchronises on `stream` (one small readback of the ids' key counts). */
 rg_status roaring_multi(rg_ctx *ctx, int op, const rg_pool *pool, const uint32_t *d_ids, uint32_t k, uint32_t flags,
                         rg_out *out, uint64_t *d_card, void *stream);
 
-/* A query of the serving loop: op RG_AND / RG_OR over k bitmap ids (host
+/* A query of the serving loop: op RG_AND, RG_OR, RG_XOR or RG_ANDNOT (as for
+ * roaring_multi) over k bitmap ids (host
  * array, copied at submission) of the server's pool; flags RG_FLAG_CARD
  * (count only) or RG_FLAG_MATERIALIZE (the result containers are built and
  * stay readable through rg_result.view until the query is released). */
