@@ -74,4 +74,29 @@ def edge_sets():
     sets.append(np.arange(65536 * 9, 65536 * 11, 3, dtype=np.uint32))        # 2 chunks, 21846 values each
     sets.append(np.concatenate([np.arange(65536 * 9, 65536 * 9 + 40000), np.arange(65536 * 10 + 7, 65536 * 11)]
                                ).astype(np.uint32))
+    # Section 1 size-rule boundaries at and below 4096 values, one chunk each:
+    # key 11: c=4096, r=2048 -> array (2r < c fails);  key 12: c=4096, r=2047 -> run;
+    # key 13: c=5, r=2 -> run;  key 14: c=4, r=2 -> array;
+    # key 15: c=4095, r=2047 (odd c, r=(c-1)/2) -> run;  key 16: c=4095, r=2048 -> array
+    sets.append(np.concatenate([_chunk_runs(11, [2] * 2048), _chunk_runs(12, [2] * 2046 + [4]),
+                                _chunk_runs(13, [3, 2]), _chunk_runs(14, [2, 2]),
+                                _chunk_runs(15, [2] * 2046 + [3]), _chunk_runs(16, [2] * 2047 + [1])]))
+    # its partner: the same keys on the other side of each boundary (key 11:
+    # c=4096, r=2047; 12: c=4096, r=2048; 13: c=4, r=2; 14: c=5, r=2; 15: c=4095,
+    # r=2048; 16: c=4095, r=2047); their union gives c=4097 with r=2047 (run)
+    # and c=4096 with r=2047 (run), their intersection c=4095 with r=2048 (array)
+    sets.append(np.concatenate([_chunk_runs(11, [2] * 2046 + [4]), _chunk_runs(12, [2] * 2048),
+                                _chunk_runs(13, [2, 2]), _chunk_runs(14, [3, 2]),
+                                _chunk_runs(15, [2] * 2047 + [1]), _chunk_runs(16, [2] * 2046 + [3])]))
     return sets
+
+
+def _chunk_runs(key, lengths, gap=1):
+    """Values of chunk `key`: runs of the given lengths starting at 0, separated
+    by `gap` absent values (so the runs are maximal and their count is exact)."""
+    v, x = [], 0
+    for n in lengths:
+        v.extend(range(x, x + n))
+        x += n + gap
+    assert x - gap <= 65536
+    return (np.array(v, np.uint32) + np.uint32(key * 65536)).astype(np.uint32)

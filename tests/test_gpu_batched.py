@@ -205,3 +205,46 @@ def test_plan_errors(rg, ctx):
     P = rg.Pool.from_sets(bs.values, bs.offsets)
     with pytest.raises(rg.RoaringError):
         rg.Plan(ctx, "and", P, P, _t(np.array([0, 9], np.uint32)), _t(np.array([1, 1], np.uint32)))
+
+
+def _uneven_pool(n_bitmaps=256, n_pairs=3000):
+    """The shape of the batched uneven workload at a size the oracle checks in
+    seconds: cardinalities lognormal (median 1e4, sigma 2, clipped to
+    [10, 1e7]) over [0, 2^32), the mixed recipe with a 256-key hot set, random
+    pairs."""
+    seed = synth.SEED_BASE + 3
+    hot = synth.hot_keys(seed, 256, 1 << 16)
+    sets = [synth.mixed_bitmap(seed, i, synth.lognormal_card(i, 1e4, 2.0, 10, 10 ** 7, seed), 32, hot)
+            for i in range(n_bitmaps)]
+    bs = synth.BitmapSet.from_list(sets)
+    ia, ib = synth.random_pairs(n_bitmaps, n_pairs, seed)
+    return bs, ia, ib
+
+
+def test_uneven_shape_eager_and_plan_match_oracle(rg, ctx):
+    """Every pair's count and Jaccard index, from the eager batched call and
+    from a plan (executed and replayed as a graph), equal the oracle's."""
+    import torch
+
+    bs, ia, ib = _uneven_pool()
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    tia, tib = _t(ia), _t(ib)
+    stream = torch.cuda.Stream()
+    for op in OPS:
+        _say(f"[uneven] op={op} pairs={len(ia)} values={len(bs.values)}")
+        card, _, jac = oracle.pairs(op, bs.values, bs.offsets, bs.values, bs.offsets, ia, ib, want_jaccard=True)
+        _, c, j = rg.batch(ctx, op, P, P, tia, tib, materialize=False, card=True, jaccard=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(c.cpu().numpy().view(np.uint64), card), op
+        assert np.array_equal(j.cpu().numpy(), jac), op
+        pl = rg.Plan(ctx, op, P, P, tia, tib, card=True, jaccard=True)
+        with torch.cuda.stream(stream):
+            pl.capture(stream)
+            for rep in range(2):
+                pl.cards.zero_()
+                pl.jacc.zero_()
+                pl.execute(stream)
+                stream.synchronize()
+                assert np.array_equal(pl.cards.cpu().numpy().view(np.uint64), card), (op, rep)
+                assert np.array_equal(pl.jacc.cpu().numpy(), jac), (op, rep)
+        pl.close()

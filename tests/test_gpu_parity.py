@@ -1,6 +1,7 @@
 """GPU parity: every operation, through the C ABI, against the CPU oracle,
 element by element (values, container keys/types/cards/sizes, counts,
 Jaccard bit-for-bit, fingerprints)."""
+import os
 import sys
 
 import numpy as np
@@ -267,11 +268,28 @@ def test_materialised_two_pools_different_layouts(rg, ctx):
 
 
 
+def _popcount_table():
+    import torch
+
+    t = torch.zeros(256, dtype=torch.int32)
+    for v in range(256):
+        t[v] = bin(v).count("1")
+    return t
+
+
 def test_dense_bitsets_full_size_sampled(rg, ctx):
     """The bitset-bandwidth workload at full size, in the launch configuration the
     bench times (2e4 bitmaps x 256 bitsets, 1e4 random pairs, count-only batched
-    calls): every pair's four counts satisfy the identities, and sampled pairs
-    equal the oracle; a materialised batch of sampled pairs is decoded."""
+    calls). Three checks: (1) 64 pairs spread over the list (first, last, every
+    157th) against the oracle for all four counts and the Jaccard index; (2)
+    every pair's intersection count against a popcount of the AND of the two
+    bitmaps' words computed by torch (byte table lookups; no library code);
+    (3) every pair's four counts are consistent with the Section 5.9 identities
+    (a self-consistency check of the count conversion only: the library derives
+    the other counts from the intersection). A materialised batch of sampled
+    pairs is decoded and fingerprinted against the oracle."""
+    import concurrent.futures as cf
+
     import torch
 
     nb, nk, npairs = 20000, 256, 10000
@@ -288,28 +306,46 @@ def test_dense_bitsets_full_size_sampled(rg, ctx):
         torch.cuda.synchronize()
         cards[op] = c.cpu().numpy().view(np.uint64).astype(np.int64)
         jac = j.cpu().numpy()
+    # (1) oracle on 64 spread pairs (ctypes calls release the GIL: a thread pool)
+    sample = sorted(set([0, npairs - 1] + list(range(157, npairs - 1, 157))))
+    assert len(sample) >= 64
+
+    def oracle_pair(p):
+        a = synth.dense_bitmap_values(int(ia[p]), nk)
+        b = synth.dense_bitmap_values(int(ib[p]), nk)
+        return p, {op: oracle.count(op, a, b) for op in OPS}, oracle.jaccard(a, b)
+
+    _say(f"[dense-full] oracle on {len(sample)} pairs")
+    with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        for p, exp, jexp in ex.map(oracle_pair, sample):
+            for op in OPS:
+                assert int(cards[op][p]) == exp[op], (op, p)
+            assert jac[p] == jexp, p
+    # (2) every pair's |A n B| by torch: AND of the words, byte popcount table, sum
+    _say("[dense-full] torch popcount of every pair")
+    tab = _popcount_table().cuda()
+    wv = w.view(nb, nk * 1024)
+    got = np.zeros(npairs, np.int64)
+    for p0 in range(0, npairs, 50):
+        p1 = min(npairs, p0 + 50)
+        x = wv[tia[p0:p1].long()] & wv[tib[p0:p1].long()]
+        got[p0:p1] = tab[x.view(torch.uint8).long()].sum(dim=1).cpu().numpy()
+    assert np.array_equal(cards["and"], got)
+    # (3) self-consistency of the derived counts with the stored totals
     tot = P.bm_card.cpu().numpy()
     na, nb_ = tot[ia], tot[ib]
-    # identities on every pair (Section 5.9)
     assert np.array_equal(cards["or"] + cards["and"], na + nb_)
     assert np.array_equal(cards["xor"], na + nb_ - 2 * cards["and"])
     assert np.array_equal(cards["andnot"], na - cards["and"])
-    sample = [0, 1, npairs // 2, npairs - 1]
-    for p in sample:
-        a = synth.dense_bitmap_values(int(ia[p]), nk)
-        b = synth.dense_bitmap_values(int(ib[p]), nk)
-        _say(f"[dense-full] pair {p}")
-        for op in OPS:
-            assert int(cards[op][p]) == oracle.count(op, a, b), (op, p)
-        assert jac[p] == oracle.jaccard(a, b)
-    sia, sib = _t(ia[sample]), _t(ib[sample])
+    mat_sample = [0, 1, npairs // 2, npairs - 1]
+    sia, sib = _t(ia[mat_sample]), _t(ib[mat_sample])
     for op in OPS:
         out, mc, _ = rg.batch(ctx, op, P, P, sia, sib, materialize=True, card=True)
         torch.cuda.synchronize()
         res = out.as_pool()
         assert rg.rg_pool_validate(ctx, res) == 0
         dig = rg.rg_pool_digest(ctx, res).cpu().numpy().view(np.uint64)
-        for q, p in enumerate(sample[:2]):
+        for q, p in enumerate(mat_sample[:2]):
             a = synth.dense_bitmap_values(int(ia[p]), nk)
             b = synth.dense_bitmap_values(int(ib[p]), nk)
             exp = oracle.op(op, a, b)

@@ -72,6 +72,41 @@ def test_adam_first_step_moves_by_lr_times_sign():
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
 
 
+def test_adam_constant_gradient_closed_form():
+    # With the same gradient g at every step, m_t = (1 - b1^t) g and
+    # v_t = (1 - b2^t) g^2, so the bias-corrected moments are exactly g and g^2
+    # at every step and each step moves by -lr g / (|g| + eps). A correction
+    # that used the wrong step, the wrong beta, or none at all breaks this from
+    # step 2 on.
+    g = np.array([3.0, -0.5, 1e-3, 2.0e-2])
+    lr, eps = 0.01, 1e-8
+    p, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    for t in range(1, 11):
+        p, m, v = mlp.adam(p, g, m, v, step=t, lr=lr, eps=eps)
+        assert np.allclose(p, -t * lr * g / (np.abs(g) + eps), rtol=1e-12, atol=0)
+        assert np.allclose(m, (1 - 0.9 ** t) * g, rtol=1e-12)
+        assert np.allclose(v, (1 - 0.999 ** t) * g * g, rtol=1e-12)
+
+
+def test_adam_alternating_gradient_closed_form():
+    # g_t = (-1)^(t+1) g: the squares stay constant (v_hat = g^2) while the
+    # first moment is a geometric sum,
+    #   m_t = (1 - b1) g (-1)^(t+1) (1 - (-b1)^t) / (1 + b1),
+    # so the step t update is -lr (m_t / (1 - b1^t)) / (|g| + eps).
+    b1 = 0.9
+    g = np.array([1.5, -0.25])
+    lr, eps = 1e-3, 1e-8
+    p, m, v = np.zeros(2), np.zeros(2), np.zeros(2)
+    exp_p = np.zeros(2)
+    for t in range(1, 9):
+        gt = g if t % 2 == 1 else -g
+        p, m, v = mlp.adam(p, gt, m, v, step=t, lr=lr, eps=eps)
+        mt = (1 - b1) * g * (-1) ** (t + 1) * (1 - (-b1) ** t) / (1 + b1)
+        assert np.allclose(m, mt, rtol=1e-12)
+        exp_p = exp_p - lr * (mt / (1 - b1 ** t)) / (np.abs(g) + eps)
+        assert np.allclose(p, exp_p, rtol=1e-12)
+
+
 def test_features_hand_example():
     # an array of 1000 values against a bitset of 32768 (Fig. 1's first and third containers)
     f = mlp.features(1, 2, 1000, 32768, 0, 0, 0)
