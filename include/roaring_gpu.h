@@ -34,13 +34,23 @@
  * writes the rg_out buffers and its own workspace (held by the context).
  *
  * Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
- * Calls enqueue work on it. Calls that must size their launches or report
- * capacity read small counters back from the device, so they synchronise the
- * stream at those points; on return from a successful call every result has
- * been computed or is enqueued on `stream` (synchronise before reading).
+ * Calls enqueue work on it. Count-only calls (cardinalities, Jaccard) are
+ * asynchronous: they never wait for the device. Materialising calls must size
+ * their launches and report arena capacity, so they read small counters back
+ * and synchronise the stream at those points. On return from a successful call
+ * every result has been computed or is enqueued on `stream` (synchronise
+ * before reading).
+ *
+ * Workspace: calls need device scratch. By default the context owns it and
+ * grows it on demand (hipMalloc). A caller that must not see allocations gives
+ * the context a workspace of its own (rg_set_workspace, sized with
+ * rg_workspace_size); calls then carve their scratch from it, never allocate
+ * device memory, and fail with RG_ECAPACITY when it is too small.
  *
  * Errors: every call returns an rg_status; on failure rg_last_error(ctx)
- * describes it. Outputs are unspecified after a failed call.
+ * describes it. Outputs are unspecified after a failed call. Errors that only
+ * the device can see in an asynchronous call (a pair index outside its pool)
+ * give that pair count 0 / Jaccard 0 and raise a flag that rg_sync reports.
  */
 #ifndef ROARING_GPU_H
 #define ROARING_GPU_H
@@ -128,6 +138,29 @@ rg_status rg_create(rg_ctx **ctx, int device);
 void rg_destroy(rg_ctx *ctx);
 const char *rg_last_error(const rg_ctx *ctx);
 
+/* Waits for `stream` and reports what asynchronous calls of the context found
+ * on the device since the last rg_sync: RG_EINVAL if a pair index was outside
+ * its pool (the flag is then cleared), else RG_OK. */
+rg_status rg_sync(rg_ctx *ctx, void *stream);
+
+/* Caller-owned workspace. d_ws: device memory, 256-byte aligned, owned by the
+ * caller, which must keep it valid while calls that use it may run; NULL
+ * returns to the context's own growable workspace. Waits for the last call
+ * that used the previous workspace. With a workspace set, calls allocate no
+ * device memory and never call hipDeviceSynchronize: pair calls, batches,
+ * roaring_multi and rg_mlp_grad take their scratch from it (plans, servers
+ * and the dispatcher's sampling and training keep their own memory, made at
+ * creation). Calls on different streams that share it are ordered on the
+ * device, as with the context's own workspace. */
+rg_status rg_set_workspace(rg_ctx *ctx, void *d_ws, uint64_t bytes);
+/* Bytes of workspace that a roaring_batch (or pair call: n_pairs = 1) with
+ * this op, flags and pools needs. Count-only: exact (per-pair arrays, plus the
+ * pools' packed metadata records when the call would pack them). Materialising:
+ * the least that runs the call (per-pair arrays and one wave of the largest
+ * pair's candidate slots); more lets it run in fewer waves. No device work. */
+rg_status rg_workspace_size(rg_ctx *ctx, int op, uint32_t flags, const rg_pool *A, const rg_pool *B,
+                            uint64_t n_pairs, uint64_t *bytes);
+
 /* ---- two-bitmap operations (Section 1 operations; Section 5.7: inputs are
  * left unchanged and the result is built as a new bitmap) ----------------- */
 
@@ -161,12 +194,20 @@ rg_status roaring_andnot_cardinality(rg_ctx *ctx, const rg_pool *A, uint32_t ia,
  * two empty sets give 1.0. */
 rg_status roaring_jaccard(rg_ctx *ctx, const rg_pool *A, uint32_t ia, const rg_pool *B, uint32_t ib, double *d_j,
                           void *stream);
+/* The same index into host double *h_j; synchronises `stream`. */
+rg_status roaring_jaccard_host(rg_ctx *ctx, const rg_pool *A, uint32_t ia, const rg_pool *B, uint32_t ib, double *h_j,
+                               void *stream);
 
 /* Batched: for p < n_pairs, A[d_ia[p]] op B[d_ib[p]] (d_ia, d_ib device
  * uint32 arrays). flags: RG_FLAG_MATERIALIZE (results into out, result
  * bitmap p = pair p), RG_FLAG_CARD (|result| into d_cards[p]),
  * RG_FLAG_JACCARD (Jaccard of the two inputs into d_jacc[p]; derived from
- * the same count through the Section 5.9 identities). */
+ * the same count through the Section 5.9 identities). Without
+ * RG_FLAG_MATERIALIZE the call is asynchronous: one kernel matches the keys of
+ * all pairs and counts every matched container pair, and the number of
+ * candidate keys never goes to the host; an index outside its pool is
+ * reported by rg_sync. With it, the call synchronises (arena sizing) and
+ * reports a bad index as RG_EINVAL. */
 rg_status roaring_batch(rg_ctx *ctx, int op, const rg_pool *A, const rg_pool *B, const uint32_t *d_ia,
                         const uint32_t *d_ib, uint64_t n_pairs, uint32_t flags, rg_out *out, uint64_t *d_cards,
                         double *d_jacc, void *stream);
@@ -393,6 +434,16 @@ rg_status rg_pool_build_host(const uint32_t *values, const uint64_t *offsets, ui
  * bm_begin/keys/types/size/off/payload are set. The card/bm_card/bm_wbytes
  * pointers of `pool` are written through (they must be writable). */
 rg_status rg_pool_recount(rg_ctx *ctx, const rg_pool *pool, void *stream);
+
+/* Fills the metadata of a pool of dense bitsets: `pool` points at writable
+ * device arrays for n_bitmaps bitmaps of n_keys containers each
+ * (n_containers = n_bitmaps * n_keys) and at a payload of n_containers x 1024
+ * uint64 words laid out [bitmap][key][word] (Section 3.2 bit addressing).
+ * Writes bm_begin, keys (0..n_keys-1 in every bitmap), types (bitset), size,
+ * off, then card, bm_card and bm_wbytes as rg_pool_recount does. The bitsets
+ * must be in P1 form (more than 4096 values, more than 2047 runs) for the pool
+ * to validate. Enqueued on `stream`, no synchronisation. */
+rg_status rg_pool_init_dense(rg_ctx *ctx, const rg_pool *pool, uint32_t n_keys, void *stream);
 
 /* Packs every container's type, cardinality, size and payload offset into one
  * 16-byte record: d_meta (device, caller-owned, 16 * n_containers bytes, 16-byte

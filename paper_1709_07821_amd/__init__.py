@@ -40,7 +40,8 @@ EXPORTS = ["rg_create", "rg_destroy", "rg_last_error", "rg_set_dispatch", "rg_se
            "rg_plan_tune", "rg_plan_set", "rg_plan_info", "rg_plan_destroy", "roaring_multi", "rg_serve_start",
            "rg_serve_submit", "rg_serve_poll", "rg_serve_release", "rg_serve_replay", "rg_serve_stop",
            "rg_mlp_forward", "rg_mlp_grad", "rg_mlp_adam", "rg_dispatch_sample", "rg_dispatch_train",
-           "rg_dispatch_set_mlp", "rg_dispatch_table"]
+           "rg_dispatch_set_mlp", "rg_dispatch_table", "rg_sync", "rg_set_workspace", "rg_workspace_size",
+           "roaring_jaccard_host", "rg_pool_init_dense"]
 
 
 class RoaringError(RuntimeError):
@@ -139,6 +140,11 @@ def lib():
         L.rg_dispatch_train.argtypes = [V, V, V, V, U64, U32, U32, ctypes.c_float, U64, V, V, V]
         L.rg_dispatch_set_mlp.argtypes = [V, V, V]
         L.rg_dispatch_table.argtypes = [V, V, U64]
+        L.rg_sync.argtypes = [V, V]
+        L.rg_set_workspace.argtypes = [V, V, U64]
+        L.rg_workspace_size.argtypes = [V, I, U32, pool_p, pool_p, U64, P(U64)]
+        L.roaring_jaccard_host.argtypes = [V, pool_p, U32, pool_p, U32, P(ctypes.c_double), V]
+        L.rg_pool_init_dense.argtypes = [V, pool_p, U32, V]
         for nm in EXPORTS:
             if nm not in ("rg_destroy", "rg_last_error", "rg_plan_destroy"):
                 getattr(L, nm).restype = ctypes.c_int
@@ -202,6 +208,26 @@ class Context:
 
     def set_thresholds(self, gallop_ratio: int = 64, thread_max: int = 8):
         self.check(lib().rg_set_thresholds(self.h, gallop_ratio, thread_max))
+
+    def sync(self, stream=None):
+        """rg_sync: waits for the stream; raises what asynchronous calls found on the device."""
+        self.check(lib().rg_sync(self.h, _stream(stream)))
+
+    def set_workspace(self, buf=None):
+        """rg_set_workspace over a device tensor (256-byte aligned; None: the context's own).
+        The context keeps a reference so the memory outlives the calls using it."""
+        if buf is None:
+            self.check(lib().rg_set_workspace(self.h, None, 0))
+        else:
+            self.check(lib().rg_set_workspace(self.h, _ptr(buf), buf.numel() * buf.element_size()))
+        self.workspace = buf
+
+    def workspace_size(self, op, flags: int, A: "Pool", B: "Pool", n_pairs: int) -> int:
+        op = OPS[op] if isinstance(op, str) else op
+        b = ctypes.c_uint64()
+        self.check(lib().rg_workspace_size(self.h, op, flags, ctypes.byref(A.c), ctypes.byref(B.c), n_pairs,
+                                           ctypes.byref(b)))
+        return int(b.value)
 
 
 class Pool:
@@ -284,17 +310,12 @@ class Pool:
         torch = _torch()
         dev = words.device
         nc = n_bitmaps * n_keys
-        bm_begin = torch.arange(0, nc + 1, n_keys, dtype=torch.int64, device=dev)
-        keys = torch.arange(n_keys, dtype=torch.int16, device=dev).repeat(n_bitmaps)
-        types = torch.full((nc,), RG_BITSET, dtype=torch.uint8, device=dev)
-        card = torch.zeros(nc, dtype=torch.int32, device=dev)
-        size = torch.full((nc,), 1024, dtype=torch.int32, device=dev)
-        off = torch.arange(nc, dtype=torch.int64, device=dev) * 8192
-        bm_card = torch.zeros(n_bitmaps, dtype=torch.int64, device=dev)
-        bm_wbytes = torch.zeros(n_bitmaps, dtype=torch.int64, device=dev)
+        e = lambda n, dt: torch.empty(n, dtype=dt, device=dev)
         payload = words.view(torch.uint8).reshape(-1)
-        p = Pool(n_bitmaps, nc, nc * 8192, bm_begin, keys, types, card, size, off, payload, bm_card, bm_wbytes)
-        rg_pool_recount(ctx, p, stream)
+        p = Pool(n_bitmaps, nc, nc * 8192, e(n_bitmaps + 1, torch.int64), e(nc, torch.int16), e(nc, torch.uint8),
+                 e(nc, torch.int32), e(nc, torch.int32), e(nc, torch.int64), payload, e(n_bitmaps, torch.int64),
+                 e(n_bitmaps, torch.int64))
+        ctx.check(lib().rg_pool_init_dense(ctx.h, ctypes.byref(p.c), n_keys, _stream(stream)))
         return p
 
     def to_host(self):
@@ -370,6 +391,14 @@ roaring_or_cardinality = _single_card("roaring_or_cardinality")
 roaring_xor_cardinality = _single_card("roaring_xor_cardinality")
 roaring_andnot_cardinality = _single_card("roaring_andnot_cardinality")
 roaring_jaccard = _single_card("roaring_jaccard")
+
+
+def roaring_jaccard_host(ctx: Context, A: Pool, ia: int, B: Pool, ib: int, stream=None) -> float:
+    """roaring_jaccard_host: the Jaccard index as a Python float (synchronises)."""
+    j = ctypes.c_double()
+    ctx.check(lib().roaring_jaccard_host(ctx.h, ctypes.byref(A.c), ia, ctypes.byref(B.c), ib, ctypes.byref(j),
+                                         _stream(stream)))
+    return j.value
 
 
 def rg_pool_recount(ctx: Context, pool: Pool, stream=None):
@@ -468,7 +497,7 @@ class Plan:
 
 
 PROFILE_CLASSES = {0: "bb", 1: "unused", 2: "generic", 3: "merge", 4: "gallop", 5: "probe", 6: "runmerge",
-                   7: "thread", 8: "bb-redo", 9: "thread-fused"}
+                   7: "thread", 8: "bb-redo", 9: "thread-fused", 10: "count-fused"}
 
 
 def profile_enable(ctx: Context, on: bool = True):

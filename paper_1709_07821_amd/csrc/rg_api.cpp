@@ -55,11 +55,136 @@ rg_status drain_profile(rg_ctx* c) {
     return RG_OK;
 }
 
-// per-slot bytes of the wave workspace
-constexpr size_t SLOT_BYTES = sizeof(Task) + 4 /*ub*/ + 8 /*slot_off*/ + 4 /*res_card*/ + 1 /*res_type*/ +
-                              4 /*res_size*/ + 8 /*out_idx*/ + 4 /*bin list*/ + 4 /*redo*/;
-
 }  // namespace
+
+// ---- workspace sizing (shared by the calls and rg_workspace_size)
+
+// per-pair scratch of an asynchronous count-only call
+size_t count_pair_bytes(uint64_t n_pairs) {
+    return align256(4 * n_pairs) + align256(8 * n_pairs) + align256(8 * (n_pairs + 1)) +
+           align256(8 * scan_partials_needed(n_pairs)) + align256(4);
+}
+
+// Whether packing the pools' metadata pays for a count-only call: when it is
+// expected to visit at least META_PACK_FACTOR candidate keys per container
+// (estimate: pairs x the smaller mean key count per bitmap).
+bool count_pack_pays(const rg_pool* A, const rg_pool* B, uint64_t n_pairs, uint64_t* n_records, bool* same_pool) {
+    const bool same = A->keys == B->keys && A->off == B->off && A->n_containers == B->n_containers;
+    *same_pool = same;
+    const uint64_t nA = A->n_containers, nB = same ? 0 : B->n_containers;
+    *n_records = nA + nB;
+    if (!*n_records || (A->meta && B->meta)) return false;
+    const double kA = A->n_bitmaps ? (double)A->n_containers / A->n_bitmaps : 0.0;
+    const double kB = B->n_bitmaps ? (double)B->n_containers / B->n_bitmaps : 0.0;
+    const double est = (double)n_pairs * std::min(kA, kB);
+    return est >= (double)META_PACK_FACTOR * (double)(nA + nB);
+}
+
+// per-pair scratch of the materialising (binned) path
+size_t mat_pair_bytes(uint64_t n_pairs) {
+    return align256(4 * n_pairs) + align256(8 * n_pairs) + align256(4 * n_pairs) + align256(8 * n_pairs);
+}
+
+// scratch of one wave of S candidate slots over at most P pairs
+size_t wave_bytes(uint64_t S, uint64_t P, bool kw) {
+    const uint64_t nb = (uint64_t)NBINS * match_blocks(S);
+    size_t b = 0;
+    for (size_t x : {sizeof(Task) * S, 4 * S, 8 * S, 4 * S, 1 * S, 4 * S, 8 * S, 4 * S, 4 * S})
+        b += align256(x);  // tasks, ub, slot_off, res_card, res_type, res_size, out_idx, lists, redo
+    b += align256(8 * (P + 1)) + align256(8 * scan_partials_needed(S)) + align256(4 * nb) + align256(8 * nb) +
+         align256(8 * scan_partials_needed(nb));
+    if (kw) b += align256(sizeof(KwQuery) * P) + align256(8 * P);
+    return b;
+}
+
+// most candidate slots one pair can need (a wave holds whole pairs)
+uint64_t max_pair_slots(int op, bool mat) {
+    if (!mat) return 65536;
+    return (op == RG_OR || op == RG_XOR) ? 131072 : 65536;
+}
+
+// Persistent grid of the fused count kernel: workgroups per CU that fit its
+// LDS, never more blocks than there can be candidate blocks (65536 keys per
+// pair at most).
+uint32_t fused_grid(rg_ctx* c, uint64_t n_pairs) {
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    const uint64_t cap = (uint64_t)cus * 4;
+    const uint64_t most = n_pairs * (65536 / MATCH_SLOTS);
+    return (uint32_t)std::max<uint64_t>(1, std::min(cap, most));
+}
+
+// Count-only batched call with no host round trip: per-pair preparation,
+// device scan of the candidate counts, the fused match-and-count kernel, and
+// the conversion to the requested count (Section 5.9 identities). Pair indices
+// outside their pool give count 0 and set the context's asynchronous error
+// flag (rg_sync reports it).
+rg_status run_count_async(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const uint32_t* d_ia,
+                          const uint32_t* d_ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs, uint32_t flags,
+                          uint64_t* d_cards, double* d_jacc, hipStream_t st) {
+    Scratch sc(c);
+    void* base = nullptr;
+    if (rg_status s = sc.take(WS_PAIRS, count_pair_bytes(n_pairs), &base)) return s;
+    Bump bp{(uint8_t*)base};
+    uint32_t* n_cand = bp.take<uint32_t>(n_pairs);
+    long long* acc = bp.take<long long>(n_pairs);
+    uint64_t* cand_off = bp.take<uint64_t>(n_pairs + 1);
+    uint64_t* partials = bp.take<uint64_t>(scan_partials_needed(n_pairs));
+    uint32_t* next_blk = bp.take<uint32_t>(1);
+    PoolView pa = view(*A), pb = view(*B);
+    // Packed metadata records: the pools' own, or packed here when the call is
+    // expected to visit many candidate keys per container (one pass, 16 B per
+    // container). Without the memory for it the call reads the arrays.
+    uint64_t nrec = 0;
+    bool same = false;
+    if (count_pack_pays(A, B, n_pairs, &nrec, &same)) {
+        void* mm = nullptr;
+        bool ok = false;
+        if (sc.caller()) {
+            ok = align256(16 * nrec) <= sc.left() && sc.take(WS_META, 16 * nrec, &mm) == RG_OK;
+        } else {
+            ok = grow_device(c, &c->ws_meta, &c->ws_meta_bytes, 16 * nrec) == RG_OK;
+            mm = c->ws_meta;
+            if (!ok) (void)hipGetLastError();  // not an error of the call: it runs unpacked
+        }
+        if (ok) {
+            u32x4* ma = reinterpret_cast<u32x4*>(mm);
+            launch_pack_meta(view(*A), A->n_containers, ma, st);
+            if (!same) launch_pack_meta(view(*B), B->n_containers, ma + A->n_containers, st);
+            pa.meta = ma;
+            pb.meta = same ? ma : ma + A->n_containers;
+        }
+    }
+    launch_pair_prep(RG_AND, false, pa, pb, A->n_bitmaps, B->n_bitmaps, d_ia, d_ib, ia0, ib0, n_pairs, n_cand,
+                     nullptr, nullptr, acc, async_err_word(c), st, next_blk);
+    launch_scan_u32_u64(n_cand, cand_off, n_pairs, 0, partials, cand_off + n_pairs, st);
+    MatchArgs m{};
+    m.op = RG_AND;
+    m.materialize = false;
+    m.A = pa;
+    m.B = pb;
+    m.ia = d_ia;
+    m.ib = d_ib;
+    m.ia0 = ia0;
+    m.ib0 = ib0;
+    m.pair0 = 0;
+    m.n_pairs = (uint32_t)n_pairs;
+    m.cand_off = cand_off;
+    m.n_cand = 0;  // read on the device
+    m.dispatch_mode = c->dispatch_mode;
+    m.fixed_bin = c->fixed_bin;
+    m.gallop_ratio = c->gallop_ratio;
+    m.thread_max = c->thread_max;
+    m.mlp_table = c->mlp_table;
+    m.fuse_thread = true;
+    m.acc = acc;
+    timed(c, PROF_FUSED, false, n_pairs, st, [&] { launch_count_fused(m, next_blk, fused_grid(c, n_pairs), st); });
+    launch_finish_counts(RG_AND, op, acc, pa, pb, A->n_bitmaps, B->n_bitmaps, d_ia, d_ib, ia0, ib0, 0,
+                         (uint32_t)n_pairs, (flags & RG_FLAG_CARD) ? d_cards : nullptr,
+                         (flags & RG_FLAG_JACCARD) ? d_jacc : nullptr, st);
+    HIPCHK(c, hipGetLastError());
+    return RG_OK;
+}
 
 // one batched call (also used by the dispatcher's cost sampling)
 rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const uint32_t* d_ia,
@@ -90,13 +215,18 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
         if (mat) launch_fill_u64(out->bm_begin, 0, 1, st);
         return RG_OK;
     }
+    // count-only calls (other than the dispatcher's cost sampling) run without
+    // a host round trip
+    if (!mat && !c->cost_out)
+        return run_count_async(c, op, A, B, d_ia, d_ib, ia0, ib0, n_pairs, flags, d_cards, d_jacc, st);
     PoolView pa = view(*A), pb = view(*B);
+    Scratch sc(c);
 
     // ---- per-pair preparation
     Bump bp{nullptr};
-    size_t need = align256(4 * n_pairs) + align256(8 * n_pairs) + align256(4 * n_pairs) + align256(8 * n_pairs);
-    if (rg_status s = grow_device(c, &c->ws_pairs, &c->ws_pairs_bytes, need)) return s;
-    bp.base = (uint8_t*)c->ws_pairs;
+    void* pbase = nullptr;
+    if (rg_status s = sc.take(WS_PAIRS, mat_pair_bytes(n_pairs), &pbase)) return s;
+    bp.base = (uint8_t*)pbase;
     uint32_t* n_cand = bp.take<uint32_t>(n_pairs);
     uint64_t* bound = bp.take<uint64_t>(n_pairs);
     uint32_t* min_cont = bp.take<uint32_t>(n_pairs);
@@ -115,8 +245,9 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
     launch_pair_prep(kop, mat, pa, pb, A->n_bitmaps, B->n_bitmaps, d_ia, d_ib, ia0, ib0, n_pairs, n_cand, bound,
                      min_cont, acc, d_err, st);
     const size_t host_pairs = align256(4 * n_pairs) + align256(8 * n_pairs) + align256(4 * n_pairs);
-    if (rg_status s = grow_host(c, host_pairs + 4096 + align256(8 * (n_pairs + 1)) + 512)) return s;
-    Bump hb{(uint8_t*)c->host};
+    uint8_t* hbase = nullptr;
+    if (rg_status s = host_buffer(c, host_pairs + 4096 + align256(8 * (n_pairs + 1)) + 512, &hbase)) return s;
+    Bump hb{hbase};
     uint32_t* h_cand = hb.take<uint32_t>(n_pairs);
     uint64_t* h_bound = hb.take<uint64_t>(n_pairs);
     uint32_t* h_minc = hb.take<uint32_t>(n_pairs);
@@ -145,11 +276,28 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
         if (out->bm_wbytes) launch_fill_u64(out->bm_wbytes, 0, n_pairs, st);
     }
 
-    // ---- plan waves of at most max_wave_slots candidate slots
+    // ---- plan waves of at most S_cap candidate slots (a caller workspace
+    // bounds S_cap by what is left of it; a wave holds whole pairs)
+    const bool kw = mat && op != RG_AND;
+    uint64_t S_cap = c->max_wave_slots;
+    if (sc.caller()) {
+        uint64_t lo = 0, hi = S_cap;
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi + 1) / 2;
+            if (wave_bytes(mid, n_pairs, kw) <= sc.left()) lo = mid;
+            else hi = mid - 1;
+        }
+        S_cap = lo;
+        uint64_t most = 0;
+        for (uint64_t p = 0; p < n_pairs; ++p) most = std::max<uint64_t>(most, h_cand[p]);
+        if (most > S_cap)
+            return fail(c, RG_ECAPACITY,
+                        "workspace too small for one pair's candidate slots (rg_workspace_size gives enough)");
+    }
     std::vector<uint64_t> wstart{0};
     uint64_t accs = 0, S_max = 0, P_max = 0;
     for (uint64_t p = 0; p < n_pairs; ++p) {
-        if (accs + h_cand[p] > c->max_wave_slots && accs > 0) {
+        if (accs + h_cand[p] > S_cap && accs > 0) {
             S_max = std::max(S_max, accs);
             P_max = std::max(P_max, p - wstart.back());
             wstart.push_back(p);
@@ -161,50 +309,11 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
     P_max = std::max(P_max, n_pairs - wstart.back());
     wstart.push_back(n_pairs);
 
-    // A count-only call that visits many more candidate keys than its pools
-    // hold containers packs their metadata first (one pass, 16 B per container,
-    // as a plan does), unless the pools carry records already. Without the
-    // memory for it the call reads the arrays.
-    if (!mat && !c->cost_out && !(pa.meta && pb.meta)) {
-        const bool same = A->keys == B->keys && A->off == B->off && A->n_containers == B->n_containers;
-        const uint64_t nA = A->n_containers, nB = same ? 0 : B->n_containers;
-        uint64_t ctot = 0;
-        for (uint64_t p = 0; p < n_pairs; ++p) ctot += h_cand[p];
-        if (nA + nB > 0 && ctot >= META_PACK_FACTOR * (nA + nB)) {
-            const size_t need = 16 * (nA + nB);
-            bool ok = need <= c->ws_meta_bytes;
-            if (!ok) {
-                if (c->ws_meta) {
-                    HIPCHK(c, hipDeviceSynchronize());
-                    HIPCHK(c, hipFree(c->ws_meta));
-                }
-                ok = hipMalloc(&c->ws_meta, need) == hipSuccess;
-                c->ws_meta_bytes = ok ? need : 0;
-                if (!ok) {
-                    c->ws_meta = nullptr;
-                    (void)hipGetLastError();  // not an error of the call: it runs unpacked
-                }
-            }
-            if (ok) {
-                u32x4* ma = reinterpret_cast<u32x4*>(c->ws_meta);
-                launch_pack_meta(view(*A), nA, ma, st);
-                if (!same) launch_pack_meta(view(*B), nB, ma + nA, st);
-                pa.meta = ma;
-                pb.meta = same ? ma : ma + nA;
-            }
-        }
-    }
-
     // materialised OR / XOR / ANDNOT run through the k-way path (two bitmaps
     // per query): key set per pair, then one workgroup per result key
-    const bool kw = mat && op != RG_AND;
-    size_t wneed = S_max * SLOT_BYTES + 16 * 256 + align256(8 * (P_max + 1)) +
-                   align256(8 * scan_partials_needed(S_max)) +
-                   (kw ? align256(sizeof(KwQuery) * P_max) + align256(8 * P_max) + 512 : 0) +
-                   align256(4ull * NBINS * match_blocks(S_max)) + align256(8ull * NBINS * match_blocks(S_max)) +
-                   align256(8 * scan_partials_needed((uint64_t)NBINS * match_blocks(S_max))) + 768;
-    if (rg_status s = grow_device(c, &c->ws_wave, &c->ws_wave_bytes, wneed)) return s;
-    Bump wb{(uint8_t*)c->ws_wave};
+    void* wbase = nullptr;
+    if (rg_status s = sc.take(WS_WAVE, wave_bytes(S_max, P_max, kw), &wbase)) return s;
+    Bump wb{(uint8_t*)wbase};
     Task* tasks = wb.take<Task>(S_max);
     uint32_t* ub = wb.take<uint32_t>(S_max);
     uint64_t* slot_off = wb.take<uint64_t>(S_max);
@@ -299,6 +408,11 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
                 boff[b] = h_small[NBINS + b];
             }
             pay_end = mat ? *reinterpret_cast<uint64_t*>(h_small + 64) : 0;
+            // the slots' payload bounds come from the containers' cardinalities,
+            // the arena check above from bm_wbytes: a pool whose two disagree
+            // fails here, before any kernel writes past the arena
+            if (mat && pay_end > out->cap_payload_bytes)
+                return fail(c, RG_ECAPACITY, "result payload exceeds the arena (pool bm_wbytes inconsistent with card)");
             launch_fill_u32(redo_count, 0, 1, st);
 
             ComputeArgs ca;
@@ -390,7 +504,8 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
                               (flags & RG_FLAG_CARD) ? d_cards : nullptr, (flags & RG_FLAG_JACCARD) ? d_jacc : nullptr,
                               st);
     } else {
-        launch_finish_counts(kop, op, acc, pa, pb, d_ia, d_ib, ia0, ib0, 0, (uint32_t)n_pairs,
+        launch_finish_counts(kop, op, acc, pa, pb, A->n_bitmaps, B->n_bitmaps, d_ia, d_ib, ia0, ib0, 0,
+                             (uint32_t)n_pairs,
                              (flags & RG_FLAG_CARD) ? d_cards : nullptr, (flags & RG_FLAG_JACCARD) ? d_jacc : nullptr,
                              st);
     }
@@ -421,7 +536,66 @@ rg_status rg_create(rg_ctx** ctx, int device) {
         delete c;
         return RG_EDEVICE;
     }
+    if (hipMemset(c->small, 0, 4096) != hipSuccess ||
+        hipHostMalloc(&c->host, HOST_STAGING_BYTES, hipHostMallocDefault) != hipSuccess) {
+        (void)hipFree(c->small);
+        delete c;
+        return RG_EDEVICE;
+    }
+    c->host_bytes = HOST_STAGING_BYTES;
     *ctx = c;
+    return RG_OK;
+}
+
+rg_status rg_set_workspace(rg_ctx* c, void* d_ws, uint64_t bytes) {
+    if (!c) return RG_EINVAL;
+    if (d_ws && (reinterpret_cast<uintptr_t>(d_ws) & 255))
+        return fail(c, RG_EINVAL, "rg_set_workspace: the workspace must be 256-byte aligned");
+    if (d_ws && bytes == 0) return fail(c, RG_EINVAL, "rg_set_workspace: empty workspace");
+    HIPCHK(c, hipSetDevice(c->device));
+    // calls still running on the previous workspace must finish before the
+    // caller reuses or frees it: wait for the last one
+    if (c->ws_event_live) HIPCHK(c, hipEventSynchronize(c->ws_event));
+    c->user_ws = d_ws;
+    c->user_ws_bytes = d_ws ? (size_t)bytes : 0;
+    return RG_OK;
+}
+
+rg_status rg_workspace_size(rg_ctx* c, int op, uint32_t flags, const rg_pool* A, const rg_pool* B,
+                            uint64_t n_pairs, uint64_t* bytes) {
+    if (!c) return RG_EINVAL;
+    if (!bytes || !A || !B) return fail(c, RG_EINVAL, "rg_workspace_size: null argument");
+    if (op < RG_AND || op > RG_ANDNOT) return fail(c, RG_EINVAL, "op must be RG_AND..RG_ANDNOT");
+    if (!(flags & (RG_FLAG_MATERIALIZE | RG_FLAG_CARD | RG_FLAG_JACCARD)))
+        return fail(c, RG_EINVAL, "flags select no output");
+    const bool mat = flags & RG_FLAG_MATERIALIZE;
+    if (!mat) {
+        size_t b = count_pair_bytes(n_pairs);
+        uint64_t nrec = 0;
+        bool same = false;
+        if (count_pack_pays(A, B, n_pairs, &nrec, &same)) b += align256(16 * nrec);
+        *bytes = b;
+        return RG_OK;
+    }
+    // the per-pair arrays and one wave that holds the largest possible pair;
+    // more lets a call run in fewer waves
+    const bool kw = op != RG_AND;
+    *bytes = mat_pair_bytes(n_pairs) + wave_bytes(max_pair_slots(op, true), n_pairs, kw);
+    return RG_OK;
+}
+
+rg_status rg_sync(rg_ctx* c, void* stream) {
+    if (!c) return RG_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t* h = reinterpret_cast<uint32_t*>(c->host);
+    HIPCHK(c, hipMemcpyAsync(h, async_err_word(c), 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (*h) {
+        launch_fill_u32(async_err_word(c), 0, 1, st);
+        HIPCHK(c, hipStreamSynchronize(st));
+        return fail(c, RG_EINVAL, "an asynchronous call had a pair index out of range of its pool");
+    }
     return RG_OK;
 }
 
@@ -467,7 +641,7 @@ rg_status rg_profile_reset(rg_ctx* c) {
 rg_status rg_profile_read(rg_ctx* c, int variant, int materialize, double* total_ms, uint64_t* launches,
                           uint64_t* items) {
     if (!c) return RG_EINVAL;
-    if (variant < 0 || variant >= NBINS || !total_ms || !launches || !items)
+    if (variant < 0 || variant >= NPROF || !total_ms || !launches || !items)
         return fail(c, RG_EINVAL, "bad profile query");
     if (rg_status s = drain_profile(c)) return s;
     const int m = materialize ? 1 : 0;
@@ -540,6 +714,19 @@ rg_status roaring_jaccard(rg_ctx* c, const rg_pool* A, uint32_t ia, const rg_poo
                           void* stream) {
     return single(c, RG_AND, A, ia, B, ib, RG_FLAG_JACCARD, nullptr, nullptr, d_j, stream);
 }
+rg_status roaring_jaccard_host(rg_ctx* c, const rg_pool* A, uint32_t ia, const rg_pool* B, uint32_t ib, double* h_j,
+                               void* stream) {
+    if (!c) return RG_EINVAL;
+    if (!h_j) return fail(c, RG_EINVAL, "roaring_jaccard_host: null result pointer");
+    // the device result goes to the context's 4 KiB block (a word no call uses)
+    double* d_j = reinterpret_cast<double*>(reinterpret_cast<uint8_t*>(c->small) + 3840);
+    if (rg_status s = single(c, RG_AND, A, ia, B, ib, RG_FLAG_JACCARD, nullptr, nullptr, d_j, stream)) return s;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(c, hipMemcpyAsync(c->host, d_j, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    memcpy(h_j, c->host, 8);
+    return RG_OK;
+}
 
 rg_status roaring_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const uint32_t* d_ia,
                         const uint32_t* d_ib, uint64_t n_pairs, uint32_t flags, rg_out* out, uint64_t* d_cards,
@@ -554,6 +741,18 @@ rg_status rg_pool_recount(rg_ctx* c, const rg_pool* p, void* stream) {
     if (!p || !p->bm_begin || !p->bm_card || !p->bm_wbytes) return fail(c, RG_EINVAL, "incomplete pool");
     HIPCHK(c, hipSetDevice(c->device));
     launch_pool_recount(*p, (hipStream_t)stream);
+    HIPCHK(c, hipGetLastError());
+    return RG_OK;
+}
+
+rg_status rg_pool_init_dense(rg_ctx* c, const rg_pool* p, uint32_t n_keys, void* stream) {
+    if (!c) return RG_EINVAL;
+    if (!p || n_keys < 1 || n_keys > 65536) return fail(c, RG_EINVAL, "rg_pool_init_dense: 1 <= n_keys <= 65536");
+    if (!pool_ok(p) || p->n_containers != (uint64_t)p->n_bitmaps * n_keys ||
+        p->payload_bytes < p->n_containers * 8192ull)
+        return fail(c, RG_EINVAL, "rg_pool_init_dense: pool arrays, n_containers or payload do not match");
+    HIPCHK(c, hipSetDevice(c->device));
+    launch_pool_dense_init(*p, n_keys, (hipStream_t)stream);
     HIPCHK(c, hipGetLastError());
     return RG_OK;
 }
@@ -573,9 +772,9 @@ rg_status rg_pool_validate(rg_ctx* c, const rg_pool* p, uint64_t* n_bad, void* s
     if (!pool_ok(p) || !n_bad) return fail(c, RG_EINVAL, "incomplete pool");
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
+    WorkspaceOrder order(c, st);  // the context's device block and staging are shared with other calls
     uint64_t* d_bad = reinterpret_cast<uint64_t*>((uint8_t*)c->small + 2048);
     launch_pool_validate(*p, d_bad, st);
-    if (rg_status s = grow_host(c, 4096)) return s;
     HIPCHK(c, hipMemcpyAsync(c->host, d_bad, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     *n_bad = *reinterpret_cast<uint64_t*>(c->host);
@@ -689,7 +888,8 @@ void plan_enqueue(rg_plan* p, hipStream_t st) {
         PersistArgs a{pa, pb, p->tasks, p->lists, p->bin_info, p->next, p->acc};
         launch_persist(a, p->grid, st);
     }
-    launch_finish_counts(RG_AND, p->op, p->acc, pa, pb, p->d_ia, p->d_ib, 0, 0, 0, (uint32_t)p->n_pairs,
+    launch_finish_counts(RG_AND, p->op, p->acc, pa, pb, p->A.n_bitmaps, p->B.n_bitmaps, p->d_ia, p->d_ib, 0, 0, 0,
+                         (uint32_t)p->n_pairs,
                          (p->flags & RG_FLAG_CARD) ? p->d_cards : nullptr,
                          (p->flags & RG_FLAG_JACCARD) ? p->d_jacc : nullptr, st);
 }

@@ -81,26 +81,31 @@ __device__ __forceinline__ uint64_t card_from(int op, uint64_t inter, uint64_t n
     return na - inter;
 }
 
-__global__ void k_finish_counts(int acc_op, int out_op, const long long* acc, PoolView A, PoolView B,
-                                const uint32_t* ia, const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t pair0,
-                                uint32_t n_pairs, uint64_t* d_cards, double* d_jacc) {
+__global__ void k_finish_counts(int acc_op, int out_op, const long long* acc, PoolView A, PoolView B, uint32_t nA,
+                                uint32_t nB, const uint32_t* ia, const uint32_t* ib, uint32_t ia0, uint32_t ib0,
+                                uint64_t pair0, uint32_t n_pairs, uint64_t* d_cards, double* d_jacc) {
     uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n_pairs) return;
     uint64_t p = pair0 + q;
     const uint64_t v = (uint64_t)acc[p];
     uint32_t a = ia ? ia[p] : ia0, b = ib ? ib[p] : ib0;
+    if (a >= nA || b >= nB) {  // reported through the call's error flag
+        if (d_cards) d_cards[p] = 0;
+        if (d_jacc) d_jacc[p] = 0.0;
+        return;
+    }
     uint64_t na = A.bm_card[a], nb = B.bm_card[b];
     const uint64_t inter = inter_from(acc_op, v, na, nb);
     if (d_cards) d_cards[p] = acc_op == out_op ? v : card_from(out_op, inter, na, nb);
     if (d_jacc) d_jacc[p] = jaccard_of(inter, na, nb);
 }
 
-void launch_finish_counts(int acc_op, int out_op, const long long* acc, PoolView A, PoolView B, const uint32_t* ia,
-                          const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t pair0, uint32_t n_pairs,
-                          uint64_t* d_cards, double* d_jacc, hipStream_t st) {
+void launch_finish_counts(int acc_op, int out_op, const long long* acc, PoolView A, PoolView B, uint32_t nA,
+                          uint32_t nB, const uint32_t* ia, const uint32_t* ib, uint32_t ia0, uint32_t ib0,
+                          uint64_t pair0, uint32_t n_pairs, uint64_t* d_cards, double* d_jacc, hipStream_t st) {
     if (!n_pairs) return;
     hipLaunchKernelGGL(k_finish_counts, dim3((n_pairs + 255) / 256), dim3(256), 0, st, acc_op, out_op, acc, A, B,
-                       ia, ib, ia0, ib0, pair0, n_pairs, d_cards, d_jacc);
+                       nA, nB, ia, ib, ia0, ib0, pair0, n_pairs, d_cards, d_jacc);
 }
 
 __global__ void k_mat_counts(int op, const uint64_t* bm_card, PoolView A, PoolView B, const uint32_t* ia,

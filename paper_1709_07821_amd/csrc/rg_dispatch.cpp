@@ -61,10 +61,14 @@ rg_status rg_mlp_grad(rg_ctx* c, const float* d_params, const float* d_x, const 
     if (!c) return RG_EINVAL;
     if (!d_params || !d_grad || (n && (!d_x || !d_t || !d_m))) return fail(c, RG_EINVAL, "rg_mlp_grad: null pointer");
     HIPCHK(c, hipSetDevice(c->device));
+    // the partial sums live in the workspace other calls use: order after them
+    WorkspaceOrder order(c, (hipStream_t)stream);
     const size_t need = align256((size_t)mlp_grad_blocks(n) * MLP_PARAMS * 4 + 4) +
                         align256((size_t)mlp_grad_blocks(n) * 4 + 4) + 256;
-    if (rg_status s = grow_device(c, &c->ws_pairs, &c->ws_pairs_bytes, need)) return s;
-    Bump b{(uint8_t*)c->ws_pairs};
+    Scratch sc(c);
+    void* base = nullptr;
+    if (rg_status s = sc.take(WS_PAIRS, need, &base)) return s;
+    Bump b{(uint8_t*)base};
     float* partial = b.take<float>((size_t)mlp_grad_blocks(n) * MLP_PARAMS + 1);
     float* partial_loss = b.take<float>(mlp_grad_blocks(n) + 1);
     float* inv = b.take<float>(1);

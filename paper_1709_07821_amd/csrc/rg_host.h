@@ -23,6 +23,13 @@ struct rg_ctx {
     size_t host_bytes = 0;
     void* ws_meta = nullptr;   // packed container metadata of a large count-only call
     size_t ws_meta_bytes = 0;
+    // caller-owned device workspace (rg_set_workspace): when set, calls carve
+    // their scratch out of it and never allocate device memory
+    void* user_ws = nullptr;
+    size_t user_ws_bytes = 0;
+    // host buffer for readbacks larger than the pinned staging when calls may
+    // not allocate pinned memory (caller workspace set)
+    std::vector<uint8_t> host_pageable;
     // completion of the last call that used the workspaces, on its stream: the
     // next call waits for it on its own stream (no host synchronisation)
     hipEvent_t ws_event = nullptr;
@@ -37,9 +44,9 @@ struct rg_ctx {
     bool prof = false;
     std::vector<Pending> pend;
     std::vector<hipEvent_t> evpool;
-    double prof_ms[NBINS][2] = {};
-    uint64_t prof_launches[NBINS][2] = {};
-    uint64_t prof_items[NBINS][2] = {};
+    double prof_ms[NPROF][2] = {};
+    uint64_t prof_launches[NPROF][2] = {};
+    uint64_t prof_items[NPROF][2] = {};
     int dispatch_mode = RG_DISPATCH_HEURISTIC;
     int fixed_bin = BIN_GEN;
     uint32_t gallop_ratio = 64;
@@ -101,6 +108,30 @@ struct WorkspaceOrder {
     }
 };
 
+// Words of the context's 4 KiB device block (c->small).
+constexpr size_t SMALL_ASYNC_ERR = 1020;  // u32: sticky flag of asynchronous calls, cleared by rg_sync
+
+inline uint32_t* async_err_word(rg_ctx* c) { return reinterpret_cast<uint32_t*>(c->small) + SMALL_ASYNC_ERR; }
+
+// Pinned host staging allocated with the context; larger readbacks grow it
+// (or, with a caller workspace, use pageable memory instead).
+constexpr size_t HOST_STAGING_BYTES = 1u << 20;
+
+// Device scratch of one call, in regions taken one after another. With a
+// caller workspace the regions are carved from it in order and a region that
+// does not fit fails with RG_ECAPACITY (nothing is allocated); otherwise each
+// region is one of the context's own buffers, grown on demand.
+enum WsRegion { WS_PAIRS = 0, WS_WAVE = 1, WS_META = 2 };
+struct Scratch {
+    rg_ctx* c;
+    size_t used = 0;
+    explicit Scratch(rg_ctx* c_) : c(c_) {}
+    bool caller() const { return c->user_ws != nullptr; }
+    // bytes still free in a caller workspace (unbounded for the context's own)
+    size_t left() const { return caller() ? c->user_ws_bytes - used : ~(size_t)0; }
+    rg_status take(WsRegion r, size_t need, void** out);
+};
+
 inline rg_status grow_host(rg_ctx* c, size_t need) {
     if (need <= c->host_bytes) return RG_OK;
     if (c->host) {
@@ -112,6 +143,42 @@ inline rg_status grow_host(rg_ctx* c, size_t need) {
     size_t nb = std::max(need, (size_t)1 << 20);
     HIPCHK(c, hipHostMalloc(&c->host, nb, hipHostMallocDefault));
     c->host_bytes = nb;
+    return RG_OK;
+}
+
+inline rg_status Scratch::take(WsRegion r, size_t need, void** out) {
+    need = align256(need ? need : 1);
+    if (caller()) {
+        if (need > left())
+            return fail(c, RG_ECAPACITY,
+                        "workspace too small: the call needs at least " + std::to_string(used + need) +
+                            " bytes (rg_workspace_size)");
+        *out = static_cast<uint8_t*>(c->user_ws) + used;
+        used += need;
+        return RG_OK;
+    }
+    void** buf = r == WS_PAIRS ? &c->ws_pairs : r == WS_WAVE ? &c->ws_wave : &c->ws_meta;
+    size_t* cap = r == WS_PAIRS ? &c->ws_pairs_bytes : r == WS_WAVE ? &c->ws_wave_bytes : &c->ws_meta_bytes;
+    if (rg_status s = grow_device(c, buf, cap, need)) return s;
+    *out = *buf;
+    return RG_OK;
+}
+
+// Host memory for a readback of `need` bytes: the pinned staging when it is
+// large enough; beyond it, grown pinned memory, or pageable memory when the
+// call may not allocate through HIP (caller workspace).
+inline rg_status host_buffer(rg_ctx* c, size_t need, uint8_t** out) {
+    if (need <= c->host_bytes) {
+        *out = static_cast<uint8_t*>(c->host);
+        return RG_OK;
+    }
+    if (c->user_ws) {
+        if (c->host_pageable.size() < need) c->host_pageable.resize(need);
+        *out = c->host_pageable.data();
+        return RG_OK;
+    }
+    if (rg_status s = grow_host(c, need)) return s;
+    *out = static_cast<uint8_t*>(c->host);
     return RG_OK;
 }
 

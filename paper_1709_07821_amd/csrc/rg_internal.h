@@ -33,6 +33,9 @@ enum : uint8_t {
     BIN_FUSED = 9,  // small array sides counted inside key matching (count-only); never listed
     NBINS = 10
 };
+// profile classes beyond the bins
+constexpr int PROF_FUSED = 10;  // the fused match-and-count kernel of asynchronous count-only calls
+constexpr int NPROF = 11;
 
 struct Task {
     uint32_t pair;
@@ -228,8 +231,13 @@ void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t st);
 void launch_pair_prep(int op, bool materialize, PoolView A, PoolView B, uint32_t nA, uint32_t nB,
                       const uint32_t* ia, const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs,
                       uint32_t* n_cand, uint64_t* bound, uint32_t* min_cont, long long* acc, uint32_t* err,
-                      hipStream_t st);
+                      hipStream_t st, uint32_t* zero_word = nullptr);
 void launch_match(const MatchArgs& m, hipStream_t st);
+// Asynchronous count-only path: key matching and counting of every pair in one
+// persistent kernel (m.materialize false, m.fuse_thread true, m.pair0 0, m.cand_off
+// the exclusive scan over all pairs with the total at cand_off[n_pairs]).
+// *next_blk must be 0 at launch (k_pair_prep's zero_word).
+void launch_count_fused(const MatchArgs& m, uint32_t* next_blk, uint32_t grid, hipStream_t st);
 // Binning without contended atomics: k_match leaves per-block bin counts; an
 // exclusive scan of them (bin-major) gives each block's place in each bin's
 // list, and the bins' counts and offsets (bin_info[0..NBINS) counts,
@@ -296,9 +304,10 @@ void launch_bm_begin(const uint64_t* cand_off, const uint64_t* out_idx, uint64_t
 // acc_op: the operation whose cardinality the accumulator holds; out_op: the
 // operation whose cardinality goes to d_cards (converted with the Section 5.9
 // identities when they differ)
-void launch_finish_counts(int acc_op, int out_op, const long long* acc, PoolView A, PoolView B, const uint32_t* ia,
-                          const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t pair0, uint32_t n_pairs,
-                          uint64_t* d_cards, double* d_jacc, hipStream_t st);
+// Pairs with an index outside its pool (nA / nB bitmaps) get count 0 and Jaccard 0.
+void launch_finish_counts(int acc_op, int out_op, const long long* acc, PoolView A, PoolView B, uint32_t nA,
+                          uint32_t nB, const uint32_t* ia, const uint32_t* ib, uint32_t ia0, uint32_t ib0,
+                          uint64_t pair0, uint32_t n_pairs, uint64_t* d_cards, double* d_jacc, hipStream_t st);
 void launch_mat_counts(int op, const uint64_t* bm_card, PoolView A, PoolView B, const uint32_t* ia,
                        const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs, uint64_t* d_cards,
                        double* d_jacc, hipStream_t st);
@@ -406,6 +415,7 @@ void launch_kw_gather_meta(const uint64_t* bm_begin, const uint64_t* bm_wbytes, 
 
 // pool utilities
 void launch_pool_recount(const rg_pool& p, hipStream_t st);
+void launch_pool_dense_init(const rg_pool& p, uint32_t n_keys, hipStream_t st);
 void launch_pool_validate(const rg_pool& p, uint64_t* d_bad, hipStream_t st);
 void launch_pool_digest(const rg_pool& p, uint64_t* d_digest, hipStream_t st);
 // containers i >= *d_n (device count) are skipped

@@ -38,16 +38,18 @@ void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t st) {
 // their stored cardinality).
 __global__ void k_pair_prep(int op, int materialize, PoolView A, PoolView B, uint32_t nA, uint32_t nB,
                             const uint32_t* ia, const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs,
-                            uint32_t* n_cand, uint64_t* bound, uint32_t* min_cont, long long* acc, uint32_t* err) {
+                            uint32_t* n_cand, uint64_t* bound, uint32_t* min_cont, long long* acc, uint32_t* err,
+                            uint32_t* zero_word) {
     uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0 && zero_word) *zero_word = 0;
     if (p >= n_pairs) return;
     uint32_t a = ia ? ia[p] : ia0;
     uint32_t b = ib ? ib[p] : ib0;
     if (a >= nA || b >= nB) {  // bad index: report, and give the pair no work
         atomicOr(err, 1u);
         n_cand[p] = 0;
-        bound[p] = 0;
-        min_cont[p] = 0;
+        if (bound) bound[p] = 0;
+        if (min_cont) min_cont[p] = 0;
         acc[p] = 0;
         return;
     }
@@ -76,8 +78,8 @@ __global__ void k_pair_prep(int op, int materialize, PoolView A, PoolView B, uin
         min_cont[p] = mc;
     } else {
         n_cand[p] = KA < KB ? KA : KB;
-        bound[p] = 0;
-        min_cont[p] = 0;
+        if (bound) bound[p] = 0;
+        if (min_cont) min_cont[p] = 0;
         long long base = 0;
         if (op == RG_OR || op == RG_XOR) base = (long long)(A.bm_card[a] + B.bm_card[b]);
         else if (op == RG_ANDNOT) base = (long long)A.bm_card[a];
@@ -88,10 +90,10 @@ __global__ void k_pair_prep(int op, int materialize, PoolView A, PoolView B, uin
 void launch_pair_prep(int op, bool materialize, PoolView A, PoolView B, uint32_t nA, uint32_t nB,
                       const uint32_t* ia, const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs,
                       uint32_t* n_cand, uint64_t* bound, uint32_t* min_cont, long long* acc, uint32_t* err,
-                      hipStream_t st) {
+                      hipStream_t st, uint32_t* zero_word) {
     if (!n_pairs) return;
     hipLaunchKernelGGL(k_pair_prep, dim3((uint32_t)((n_pairs + 255) / 256)), dim3(256), 0, st, op, (int)materialize,
-                       A, B, nA, nB, ia, ib, ia0, ib0, n_pairs, n_cand, bound, min_cont, acc, err);
+                       A, B, nA, nB, ia, ib, ia0, ib0, n_pairs, n_cand, bound, min_cont, acc, err, zero_word);
 }
 
 // ------------------------------------------------------------------ match
@@ -275,20 +277,21 @@ __device__ __forceinline__ void match_slot_global(const MatchArgs& m, uint64_t t
     finish_slot(m, cnt, o);
 }
 
-// Key matching. A block takes MATCH_SLOTS consecutive candidate slots; each
-// thread carries MATCH_PER_THREAD of them (slots t0 + k * 256 + thread) through
-// the same steps, so that their loads overlap.
-__global__ void __launch_bounds__(256) k_match(MatchArgs m) {
-    __shared__ uint32_t cnt[NBINS];
-    __shared__ uint32_t pl_range[2];
-    __shared__ uint16_t lkeys[MATCH_LDS_KEYS];
-    __shared__ uint32_t lwin[2];  // first index of the staged window in the searched list, and its end
+// Key matching of one block of MATCH_SLOTS consecutive candidate slots from
+// t0 (n_cand candidates in all): each thread carries MATCH_PER_THREAD of them
+// (slots t0 + k * 256 + thread) through the same steps, so that their loads
+// overlap. o[k] receives what was decided for slot t0 + k * 256 + thread; bin
+// counts go to the LDS counters cnt[NBINS] (zeroed here). The LDS arrays are
+// the caller's: pl_range[2], lwin[2], lkeys[MATCH_LDS_KEYS]. Contains barriers;
+// the whole workgroup calls it.
+__device__ __forceinline__ void match_block(const MatchArgs& m, uint64_t n_cand, uint64_t t0, uint32_t* cnt,
+                                            uint32_t* pl_range, uint32_t* lwin, uint16_t* lkeys,
+                                            SlotOutcome (&o)[MATCH_PER_THREAD]) {
     if (threadIdx.x < NBINS) cnt[threadIdx.x] = 0;
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
     // the pairs of this block's first and last candidate bound every thread's
     // search: wave 0 finds the first, wave 1 the last
-    const uint64_t t0 = (uint64_t)blockIdx.x * MATCH_SLOTS;
-    const uint64_t tl = t0 + MATCH_SLOTS - 1 < m.n_cand ? t0 + MATCH_SLOTS - 1 : m.n_cand - 1;
+    const uint64_t tl = t0 + MATCH_SLOTS - 1 < n_cand ? t0 + MATCH_SLOTS - 1 : n_cand - 1;
     if (wid < 2) {
         const uint32_t pl = wave_find_pair(m.cand_off, m.n_pairs, wid == 0 ? t0 : tl, lane);
         if (lane == 0) pl_range[wid] = pl;
@@ -338,7 +341,6 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
         o_a_small = a_small;
         o_sk = sk;
     }
-    SlotOutcome o[MATCH_PER_THREAD];
 #pragma unroll
     for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
         o[k].task = Task{};
@@ -359,7 +361,7 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
 #pragma unroll
         for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
             const uint64_t t = t0 + (uint64_t)k * 256 + threadIdx.x;
-            key[k] = t < m.n_cand ? o_sk[t - o_base] : (uint16_t)0;
+            key[k] = t < n_cand ? o_sk[t - o_base] : (uint16_t)0;
             jl[k] = 0;
         }
         for (uint32_t step = top; step; step >>= 1) {
@@ -370,7 +372,7 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
 #pragma unroll
         for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
             const uint64_t t = t0 + (uint64_t)k * 256 + threadIdx.x;
-            if (t >= m.n_cand) continue;
+            if (t >= n_cand) continue;
             // a key past the window's end cannot match: the window ends at the
             // first key above the block's last candidate
             const uint64_t u = t - o_base;
@@ -392,9 +394,20 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
 #pragma unroll
         for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
             const uint64_t t = t0 + (uint64_t)k * 256 + threadIdx.x;
-            if (t < m.n_cand) match_slot_global(m, t, pl_lo, pl_hi, cnt, o[k]);
+            if (t < n_cand) match_slot_global(m, t, pl_lo, pl_hi, cnt, o[k]);
         }
     }
+}
+
+// Key matching of a wave of candidate slots into task records and per-block
+// bin counts (the binned path).
+__global__ void __launch_bounds__(256) k_match(MatchArgs m) {
+    __shared__ uint32_t cnt[NBINS];
+    __shared__ uint32_t pl_range[2];
+    __shared__ uint16_t lkeys[MATCH_LDS_KEYS];
+    __shared__ uint32_t lwin[2];  // first index of the staged window in the searched list, and its end
+    SlotOutcome o[MATCH_PER_THREAD];
+    match_block(m, m.n_cand, (uint64_t)blockIdx.x * MATCH_SLOTS, cnt, pl_range, lwin, lkeys, o);
     if (m.fuse_thread) {
 #pragma unroll
         for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) wave_aggregate_add(m.acc, o[k].fused_pair, o[k].fused_inter);
@@ -415,6 +428,91 @@ __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
 void launch_match(const MatchArgs& m, hipStream_t st) {
     if (!m.n_cand) return;
     hipLaunchKernelGGL(k_match, dim3(match_blocks(m.n_cand)), dim3(256), 0, st, m);
+}
+
+// ------------------------------------------------------------------ fused count
+// Count-only calls without a host round trip. One kernel matches the keys of
+// every pair and counts every matched container pair, block by block, so no
+// task list, binning or per-bin launch is needed and the number of candidate
+// keys (device value cand_off[n_pairs]) never goes to the host. Each workgroup
+// takes blocks of MATCH_SLOTS candidate slots from a work counter until none
+// is left. In a block, key matching counts the small-array pairs in place (as
+// in the binned path) and lists every other matched pair in LDS: workgroup
+// items (generic LDS expansion, merge path) run one after the other on the
+// whole workgroup; wave items (bitset pairs, galloping search, bitset probes,
+// run merges) are taken by the four waves from an LDS counter. The kernel
+// accumulates |A n B| per pair whatever operation was asked for (the other
+// counts follow from the Section 5.9 identities).
+struct FusedShared {
+    Task items[MATCH_SLOTS];  // workgroup items from the front, wave items from the back
+    union {
+        WgShared sh;                   // processing
+        uint16_t lkeys[MATCH_LDS_KEYS];  // key matching's staged window
+    } u;
+    uint32_t cnt[NBINS];
+    uint32_t pl_range[2];
+    uint32_t lwin[2];
+    uint32_t blk, n_wg, n_wv, next_wv;
+};
+
+__global__ void __launch_bounds__(256) k_count_fused(MatchArgs m, uint32_t* next_blk) {
+    __shared__ FusedShared f;
+    const uint32_t lane = lane_id();
+    const uint64_t n_cand = uniform64(m.cand_off[m.n_pairs]);
+    const uint64_t nblk = (n_cand + MATCH_SLOTS - 1) / MATCH_SLOTS;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            f.blk = atomicAdd(next_blk, 1u);
+            f.n_wg = 0;
+            f.n_wv = 0;
+            f.next_wv = 0;
+        }
+        __syncthreads();
+        const uint32_t blk = uniform(f.blk);
+        if (blk >= nblk) break;  // the same value in every thread: the whole workgroup leaves
+        SlotOutcome o[MATCH_PER_THREAD];
+        match_block(m, n_cand, (uint64_t)blk * MATCH_SLOTS, f.cnt, f.pl_range, f.lwin, f.u.lkeys, o);
+#pragma unroll
+        for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) wave_aggregate_add(m.acc, o[k].fused_pair, o[k].fused_inter);
+#pragma unroll
+        for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
+            if (o[k].task.kind != KIND_MATCH) continue;
+            const uint8_t b = o[k].task.bin;
+            if (b == BIN_GEN || b == BIN_AA) f.items[atomicAdd(&f.n_wg, 1u)] = o[k].task;
+            else f.items[MATCH_SLOTS - 1 - atomicAdd(&f.n_wv, 1u)] = o[k].task;
+        }
+        __syncthreads();  // the lists are complete; the staged key window is no longer needed
+        const uint32_t n_wg = uniform(f.n_wg), n_wv = uniform(f.n_wv);
+        for (uint32_t i = 0; i < n_wg; ++i) {
+            const Task t = uniform_task(f.items, i);
+            uint32_t c;
+            if (t.bin == BIN_GEN) {
+                c = generic_count_wg<RG_AND>(m.A, m.B, t, f.u.sh);
+            } else {
+                c = merge_inter_wg(m.A, m.B, t, reinterpret_cast<uint16_t*>(f.u.sh.sa),
+                                   reinterpret_cast<uint16_t*>(f.u.sh.sb), f.u.sh.tmp64);
+            }
+            if (threadIdx.x == 0) acc_add(m.acc, t.pair, (long long)c);
+            __syncthreads();
+        }
+        for (;;) {
+            // lane 0 takes the next item; readlane makes the index a scalar, so
+            // the loop exit is one branch for the whole wave
+            uint32_t v = 0;
+            if (lane == 0) v = atomicAdd(&f.next_wv, 1u);
+            const uint32_t i = __builtin_amdgcn_readlane(v, 0);
+            if (i >= n_wv) break;
+            const Task t = uniform_task(f.items, MATCH_SLOTS - 1 - i);
+            const uint32_t c = t.bin == BIN_BB ? bb_count_wave<RG_AND>(m.A, m.B, t, lane) : wave_inter(m.A, m.B, t, lane);
+            if (lane == 0) acc_add(m.acc, t.pair, (long long)c);
+        }
+        __syncthreads();  // every wave is done with this block's lists
+    }
+}
+
+void launch_count_fused(const MatchArgs& m, uint32_t* next_blk, uint32_t grid, hipStream_t st) {
+    if (!m.n_pairs || !grid) return;
+    hipLaunchKernelGGL(k_count_fused, dim3(grid), dim3(256), 0, st, m, next_blk);
 }
 
 // ------------------------------------------------------------------ binning

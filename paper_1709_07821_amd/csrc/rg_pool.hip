@@ -55,6 +55,29 @@ void launch_pool_recount(const rg_pool& p, hipStream_t st) {
     hipLaunchKernelGGL(k_recount, dim3((uint32_t)((p.n_containers + 3) / 4)), dim3(256), 0, st, p);
 }
 
+// ------------------------------------------------------------------ dense pools
+// Metadata of a pool whose payload is n_bitmaps x n_keys bitset containers laid
+// out [bitmap][key][1024 words]: bitmap b holds keys 0..n_keys-1, container
+// i = b * n_keys + k at byte offset 8192 i. Cardinalities come from the recount.
+__global__ void k_dense_init(rg_pool p, uint32_t n_keys) {
+    const uint64_t n = p.n_containers;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (uint64_t)gridDim.x * blockDim.x) {
+        if (i % n_keys == 0) const_cast<uint64_t*>(p.bm_begin)[i / n_keys] = i;
+        if (i == n) break;
+        const_cast<uint16_t*>(p.keys)[i] = (uint16_t)(i % n_keys);
+        const_cast<uint8_t*>(p.types)[i] = RG_BITSET;
+        const_cast<uint32_t*>(p.size)[i] = 1024;
+        const_cast<uint64_t*>(p.off)[i] = i * 8192ull;
+    }
+}
+
+void launch_pool_dense_init(const rg_pool& p, uint32_t n_keys, hipStream_t st) {
+    uint64_t g = (p.n_containers + 1 + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_dense_init, dim3((uint32_t)g), dim3(256), 0, st, p, n_keys);
+    launch_pool_recount(p, st);
+}
+
 // ------------------------------------------------------------------ validate
 __global__ void __launch_bounds__(256) k_validate(rg_pool p, unsigned long long* bad) {
     const uint32_t lane = lane_id();

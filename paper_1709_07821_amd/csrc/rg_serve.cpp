@@ -265,10 +265,11 @@ extern "C" rg_status roaring_multi(rg_ctx* c, int op, const rg_pool* pool, const
     WorkspaceOrder order(c, (hipStream_t)stream);
     hipStream_t st = (hipStream_t)stream;
     // per-id metadata -> host bounds (one small readback)
-    if (rg_status s = grow_device(c, &c->ws_pairs, &c->ws_pairs_bytes, align256(24 * k) + 256)) return s;
-    if (rg_status s = grow_host(c, align256(24 * k) + (1u << 16))) return s;
-    auto* d_meta = reinterpret_cast<uint64_t*>(c->ws_pairs);
-    auto* h_meta = reinterpret_cast<uint64_t*>(c->host);
+    Scratch sc(c);
+    void* mbase = nullptr;
+    if (rg_status s = sc.take(WS_PAIRS, align256(24 * k) + 256, &mbase)) return s;
+    auto* d_meta = reinterpret_cast<uint64_t*>(mbase);
+    auto* h_meta = reinterpret_cast<uint64_t*>(c->host);  // 24 k <= 6 KiB: the pinned staging
     launch_kw_gather_meta(pool->bm_begin, pool->bm_wbytes, pool->n_bitmaps, d_ids, k, d_meta, st);
     HIPCHK(c, hipMemcpyAsync(h_meta, d_meta, 24 * k, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
@@ -287,10 +288,11 @@ extern "C" rg_status roaring_multi(rg_ctx* c, int op, const rg_pool* pool, const
     qs[0] = KwQuery{(uint32_t)op, k, 0, mat ? KW_MATERIALIZE : 0u, 0, (uint32_t)b.kbound, 0};
     StepLayout L;
     L.plan(1, k, b.kbound, mat ? b.pbound : 0, !mat);
-    if (rg_status s = grow_device(c, &c->ws_wave, &c->ws_wave_bytes, L.total)) return s;
-    if (rg_status s = grow_host(c, L.down_off + L.down_bytes + 256)) return s;
-    auto* d = reinterpret_cast<uint8_t*>(c->ws_wave);
-    auto* h = reinterpret_cast<uint8_t*>(c->host);
+    void* wbase = nullptr;
+    if (rg_status s = sc.take(WS_WAVE, L.total, &wbase)) return s;
+    uint8_t* h = nullptr;
+    if (rg_status s = host_buffer(c, L.down_off + L.down_bytes + 256, &h)) return s;
+    auto* d = reinterpret_cast<uint8_t*>(wbase);
     // the ids into the staging copy (the step uploads the whole section)
     HIPCHK(c, hipMemcpyAsync(h + L.o_ids, d_ids, 4ull * k, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
