@@ -212,6 +212,28 @@ rg_status roaring_batch(rg_ctx *ctx, int op, const rg_pool *A, const rg_pool *B,
                         const uint32_t *d_ib, uint64_t n_pairs, uint32_t flags, rg_out *out, uint64_t *d_cards,
                         double *d_jacc, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * roaring_batch's count-only form (flags RG_FLAG_CARD and/or RG_FLAG_JACCARD;
+ * RG_FLAG_MATERIALIZE is RG_ENOTSUP) with every byte of its scratch taken
+ * from a fixed device array of RG_STATIC_SCRATCH_BYTES that the library holds
+ * on each GPU it runs on until the process ends (its address is looked up by
+ * rg_create). The call allocates nothing (no hipMalloc / hipFree, no events,
+ * no pinned memory), never waits for the device, and gives the same counts
+ * and Jaccard values as roaring_batch. At most RG_STATIC_MAX_PAIRS pairs per
+ * call (more: RG_ECAPACITY before any device work). The pools' packed
+ * metadata records are built in the same array when they fit beside the
+ * per-pair scratch, else the call reads the pool arrays. Every call on a GPU
+ * shares that GPU's array and overwrites what the last call left there: calls
+ * of one context are ordered on the device (as calls sharing a workspace
+ * are), but calls from two contexts that overlap on one GPU race and give
+ * wrong results. Kernel timing (rg_profile_*) does not cover these calls. */
+#define RG_STATIC_SCRATCH_BYTES (32ull << 20)
+#define RG_STATIC_MAX_PAIRS (1ull << 20)
+rg_status roaring_batch_static(rg_ctx *ctx, int op, const rg_pool *A, const rg_pool *B, const uint32_t *d_ia,
+                               const uint32_t *d_ib, uint64_t n_pairs, uint32_t flags, uint64_t *d_cards,
+                               double *d_jacc, void *stream);
+
 /* ---- batched count-only plans (pointer-stable, graph-capturable) --------
  * A plan fixes the pools, the pairs (d_ia/d_ib, device uint32), the op and the
  * outputs (d_cards uint64 and/or d_jacc binary64, one per pair). Creating it

@@ -41,7 +41,7 @@ EXPORTS = ["rg_create", "rg_destroy", "rg_last_error", "rg_set_dispatch", "rg_se
            "rg_serve_submit", "rg_serve_poll", "rg_serve_release", "rg_serve_replay", "rg_serve_stop",
            "rg_mlp_forward", "rg_mlp_grad", "rg_mlp_adam", "rg_dispatch_sample", "rg_dispatch_train",
            "rg_dispatch_set_mlp", "rg_dispatch_table", "rg_sync", "rg_set_workspace", "rg_workspace_size",
-           "roaring_jaccard_host", "rg_pool_init_dense"]
+           "roaring_jaccard_host", "rg_pool_init_dense", "roaring_batch_static"]
 
 
 class RoaringError(RuntimeError):
@@ -145,6 +145,7 @@ def lib():
         L.rg_workspace_size.argtypes = [V, I, U32, pool_p, pool_p, U64, P(U64)]
         L.roaring_jaccard_host.argtypes = [V, pool_p, U32, pool_p, U32, P(ctypes.c_double), V]
         L.rg_pool_init_dense.argtypes = [V, pool_p, U32, V]
+        L.roaring_batch_static.argtypes = [V, I, pool_p, pool_p, V, V, U64, U32, V, V, V]
         for nm in EXPORTS:
             if nm not in ("rg_destroy", "rg_last_error", "rg_plan_destroy"):
                 getattr(L, nm).restype = ctypes.c_int
@@ -364,6 +365,19 @@ def roaring_batch(ctx: Context, op, A: Pool, B: Pool, ia, ib, flags: int, out: O
     return lib().roaring_batch(ctx.h, op, ctypes.byref(A.c), ctypes.byref(B.c), _ptr(ia), _ptr(ib), n, flags,
                                ctypes.byref(out.c) if out is not None else None, _ptr(cards), _ptr(jacc),
                                _stream(stream))
+
+
+RG_STATIC_SCRATCH_BYTES, RG_STATIC_MAX_PAIRS = 32 << 20, 1 << 20
+
+
+def roaring_batch_static(ctx: Context, op, A: Pool, B: Pool, ia, ib, flags: int, cards=None, jacc=None,
+                         stream=None, n_pairs=None) -> int:
+    """Thin wrapper of roaring_batch_static() (count-only, no allocation):
+    ia, ib are device uint32 (torch int32) tensors; n_pairs defaults to their length."""
+    op = OPS[op] if isinstance(op, str) else op
+    n = int(ia.numel()) if n_pairs is None else int(n_pairs)
+    return lib().roaring_batch_static(ctx.h, op, ctypes.byref(A.c), ctypes.byref(B.c), _ptr(ia), _ptr(ib), n,
+                                      flags, _ptr(cards), _ptr(jacc), _stream(stream))
 
 
 def _single_mat(name):

@@ -7,9 +7,35 @@
 #include <string>
 #include <vector>
 
+#include <mutex>
+
 #include "rg_host.h"
 
+// Scratch of roaring_batch_static, for callers that cannot allocate: a fixed
+// array in the library's device code. Each GPU the library runs on holds its
+// own copy, at its own address, until the process ends. Host code never uses
+// this name as an address: rg_create looks the address up once per device
+// (hipGetSymbolAddress) and keeps it in static_scratch_ptr.
+static __device__ __align__(256) uint8_t scratch[RG_STATIC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex static_scratch_mu;
+void* static_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on `device`, which must be the current device.
+rg_status static_scratch_init(int device, void** out) {
+    if (device < 0 || device >= MAX_DEVICES) return RG_ENOTSUP;
+    std::lock_guard<std::mutex> lk(static_scratch_mu);
+    if (!static_scratch_ptr[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return RG_EDEVICE;
+        static_scratch_ptr[device] = p;
+    }
+    *out = static_scratch_ptr[device];
+    return RG_OK;
+}
 
 hipEvent_t take_event(rg_ctx* c) {
     if (!c->evpool.empty()) {
@@ -119,10 +145,14 @@ uint32_t fused_grid(rg_ctx* c, uint64_t n_pairs) {
 // the conversion to the requested count (Section 5.9 identities). Pair indices
 // outside their pool give count 0 and set the context's asynchronous error
 // flag (rg_sync reports it).
+// `fixed`, when given, is the device region all scratch comes from (the
+// static scratch of roaring_batch_static); kernel timing is then skipped, so
+// the call creates no events either.
 rg_status run_count_async(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const uint32_t* d_ia,
                           const uint32_t* d_ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs, uint32_t flags,
-                          uint64_t* d_cards, double* d_jacc, hipStream_t st) {
-    Scratch sc(c);
+                          uint64_t* d_cards, double* d_jacc, hipStream_t st, void* fixed = nullptr,
+                          size_t fixed_bytes = 0) {
+    Scratch sc = fixed ? Scratch(c, fixed, fixed_bytes) : Scratch(c);
     void* base = nullptr;
     if (rg_status s = sc.take(WS_PAIRS, count_pair_bytes(n_pairs), &base)) return s;
     Bump bp{(uint8_t*)base};
@@ -178,7 +208,9 @@ rg_status run_count_async(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B,
     m.mlp_table = c->mlp_table;
     m.fuse_thread = true;
     m.acc = acc;
-    timed(c, PROF_FUSED, false, n_pairs, st, [&] { launch_count_fused(m, next_blk, fused_grid(c, n_pairs), st); });
+    const uint32_t grid = fused_grid(c, n_pairs);
+    if (fixed) launch_count_fused(m, next_blk, grid, st);
+    else timed(c, PROF_FUSED, false, n_pairs, st, [&] { launch_count_fused(m, next_blk, grid, st); });
     launch_finish_counts(RG_AND, op, acc, pa, pb, A->n_bitmaps, B->n_bitmaps, d_ia, d_ib, ia0, ib0, 0,
                          (uint32_t)n_pairs, (flags & RG_FLAG_CARD) ? d_cards : nullptr,
                          (flags & RG_FLAG_JACCARD) ? d_jacc : nullptr, st);
@@ -543,6 +575,16 @@ rg_status rg_create(rg_ctx** ctx, int device) {
         return RG_EDEVICE;
     }
     c->host_bytes = HOST_STAGING_BYTES;
+    // made here so that no call has to create it (roaring_batch_static creates
+    // nothing), and the static scratch's address on this device
+    if (hipEventCreateWithFlags(&c->ws_event, hipEventDisableTiming) != hipSuccess ||
+        static_scratch_init(device, &c->static_ws) != RG_OK) {
+        if (c->ws_event) (void)hipEventDestroy(c->ws_event);
+        (void)hipHostFree(c->host);
+        (void)hipFree(c->small);
+        delete c;
+        return RG_EDEVICE;
+    }
     *ctx = c;
     return RG_OK;
 }
@@ -734,6 +776,33 @@ rg_status roaring_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, c
     if (!c) return RG_EINVAL;
     if (n_pairs && (!d_ia || !d_ib)) return fail(c, RG_EINVAL, "null pair arrays");
     return run_batch(c, op, A, B, d_ia, d_ib, 0, 0, n_pairs, flags, out, d_cards, d_jacc, (hipStream_t)stream);
+}
+
+rg_status roaring_batch_static(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const uint32_t* d_ia,
+                               const uint32_t* d_ib, uint64_t n_pairs, uint32_t flags, uint64_t* d_cards,
+                               double* d_jacc, void* stream) {
+    if (!c) return RG_EINVAL;
+    if (op < RG_AND || op > RG_ANDNOT) return fail(c, RG_EINVAL, "op must be RG_AND..RG_ANDNOT");
+    if (flags & RG_FLAG_MATERIALIZE)
+        return fail(c, RG_ENOTSUP, "roaring_batch_static is count-only (RG_FLAG_CARD / RG_FLAG_JACCARD)");
+    if (!(flags & (RG_FLAG_CARD | RG_FLAG_JACCARD))) return fail(c, RG_EINVAL, "flags select no output");
+    if ((flags & RG_FLAG_CARD) && !d_cards) return fail(c, RG_EINVAL, "RG_FLAG_CARD needs d_cards");
+    if ((flags & RG_FLAG_JACCARD) && !d_jacc) return fail(c, RG_EINVAL, "RG_FLAG_JACCARD needs d_jacc");
+    if (!pool_ok(A) || !pool_ok(B)) return fail(c, RG_EINVAL, "incomplete pool (null pointer)");
+    if (n_pairs > RG_STATIC_MAX_PAIRS)
+        return fail(c, RG_ECAPACITY,
+                    "roaring_batch_static takes at most RG_STATIC_MAX_PAIRS (" + std::to_string(RG_STATIC_MAX_PAIRS) +
+                        ") pairs per call");
+    if (n_pairs && (!d_ia || !d_ib)) return fail(c, RG_EINVAL, "null pair arrays");
+    if (!c->static_ws) return fail(c, RG_EDEVICE, "static scratch unavailable on this device");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    // ordered after the context's previous call (the asynchronous error word
+    // is shared); calls from other contexts on this GPU are not ordered
+    WorkspaceOrder order(c, st);
+    if (n_pairs == 0) return RG_OK;
+    return run_count_async(c, op, A, B, d_ia, d_ib, 0, 0, n_pairs, flags, d_cards, d_jacc, st, c->static_ws,
+                           RG_STATIC_SCRATCH_BYTES);
 }
 
 rg_status rg_pool_recount(rg_ctx* c, const rg_pool* p, void* stream) {

@@ -27,6 +27,9 @@ struct rg_ctx {
     // their scratch out of it and never allocate device memory
     void* user_ws = nullptr;
     size_t user_ws_bytes = 0;
+    // device address of the library's static scratch on this context's device
+    // (roaring_batch_static), found at rg_create
+    void* static_ws = nullptr;
     // host buffer for readbacks larger than the pinned staging when calls may
     // not allocate pinned memory (caller workspace set)
     std::vector<uint8_t> host_pageable;
@@ -118,17 +121,26 @@ inline uint32_t* async_err_word(rg_ctx* c) { return reinterpret_cast<uint32_t*>(
 constexpr size_t HOST_STAGING_BYTES = 1u << 20;
 
 // Device scratch of one call, in regions taken one after another. With a
-// caller workspace the regions are carved from it in order and a region that
-// does not fit fails with RG_ECAPACITY (nothing is allocated); otherwise each
-// region is one of the context's own buffers, grown on demand.
+// fixed region (the caller's workspace, or the library's static scratch for
+// roaring_batch_static) the regions are carved from it in order and a region
+// that does not fit fails with RG_ECAPACITY (nothing is allocated); otherwise
+// each region is one of the context's own buffers, grown on demand.
 enum WsRegion { WS_PAIRS = 0, WS_WAVE = 1, WS_META = 2 };
 struct Scratch {
     rg_ctx* c;
+    uint8_t* fixed = nullptr;
+    size_t fixed_bytes = 0;
     size_t used = 0;
-    explicit Scratch(rg_ctx* c_) : c(c_) {}
-    bool caller() const { return c->user_ws != nullptr; }
-    // bytes still free in a caller workspace (unbounded for the context's own)
-    size_t left() const { return caller() ? c->user_ws_bytes - used : ~(size_t)0; }
+    explicit Scratch(rg_ctx* c_) : c(c_) {
+        if (c->user_ws) {
+            fixed = static_cast<uint8_t*>(c->user_ws);
+            fixed_bytes = c->user_ws_bytes;
+        }
+    }
+    Scratch(rg_ctx* c_, void* base, size_t bytes) : c(c_), fixed(static_cast<uint8_t*>(base)), fixed_bytes(bytes) {}
+    bool caller() const { return fixed != nullptr; }
+    // bytes still free in a fixed region (unbounded for the context's own)
+    size_t left() const { return caller() ? fixed_bytes - used : ~(size_t)0; }
     rg_status take(WsRegion r, size_t need, void** out);
 };
 
@@ -151,9 +163,9 @@ inline rg_status Scratch::take(WsRegion r, size_t need, void** out) {
     if (caller()) {
         if (need > left())
             return fail(c, RG_ECAPACITY,
-                        "workspace too small: the call needs at least " + std::to_string(used + need) +
-                            " bytes (rg_workspace_size)");
-        *out = static_cast<uint8_t*>(c->user_ws) + used;
+                        "workspace too small: the call needs at least " + std::to_string(used + need) + " bytes of " +
+                            std::to_string(fixed_bytes));
+        *out = fixed + used;
         used += need;
         return RG_OK;
     }
