@@ -439,6 +439,30 @@ rg_status rg_serve_replay(rg_server *server, uint64_t n, const rg_query *qs, con
 /* Drains, stops the thread, frees everything; stats may be NULL. */
 rg_status rg_serve_stop(rg_server *server, rg_serve_stats *stats);
 
+/* ---- access to values ----------------------------------------------------
+ * Membership (Section 1: the value's 16 high bits are found among the sorted
+ * keys by binary search, then the container is searched - binary search in an
+ * array, bit test in a bitset (Section 3.2), search of the run starts in a run
+ * container; Section 5.6 times such queries): for i < n, d_out[i] (device
+ * uint8) = 1 if d_values[i] is in bitmap d_ids[i] of P, else 0 (d_ids,
+ * d_values device uint32). Asynchronous, no allocation; an id outside the pool
+ * gives 0 and is reported by rg_sync. */
+rg_status roaring_contains(rg_ctx *ctx, const rg_pool *P, const uint32_t *d_ids, const uint32_t *d_values, uint64_t n,
+                           uint8_t *d_out, void *stream);
+
+/* Export to sorted uint32 values (Section 3.1: a bitset's set bits are turned
+ * into values by counting each word's bits and extracting their positions;
+ * Section 5.5 iterates over every value): the values of bitmaps b0 .. b0+n-1
+ * of P, each ascending, concatenated in bitmap order into d_values (device
+ * uint32, room for cap_values); d_offsets[j] (device uint64, n + 1 entries)
+ * receives the index of bitmap b0 + j's first value and d_offsets[n] the total.
+ * *needed_values (host, may be NULL) receives the total (the sum of the
+ * bitmaps' bm_card); RG_ECAPACITY when it exceeds cap_values (nothing
+ * written). RG_EINVAL when b0 + n > n_bitmaps. Synchronises once (the
+ * total). */
+rg_status roaring_to_uint32(rg_ctx *ctx, const rg_pool *P, uint32_t b0, uint32_t n, uint64_t *d_offsets,
+                            uint32_t *d_values, uint64_t cap_values, uint64_t *needed_values, void *stream);
+
 /* ---- pools -------------------------------------------------------------- */
 
 /* Host-side pool construction from sorted values. Bitmap b holds

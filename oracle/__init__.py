@@ -16,6 +16,11 @@ Functions (all take strictly increasing uint32 numpy arrays):
 * ``type_of(c, r)``       - P1 type rule (Section 1 size rules, least memory)
 * ``serialise(v, i)``     - words of container i in the fingerprint layout
 * ``digest(v)``           - canonical fingerprint of the container form
+* ``contains(v, x)``      - membership of one value (Section 1 random access)
+* ``contains_many(values, offsets, ids, xs)`` - batched membership over a collection
+
+Export to uint32 (Section 3.1, Section 5.5) has no function here: the oracle
+holds every set as its sorted uint32 list, which is the expected export.
 """
 from __future__ import annotations
 
@@ -72,6 +77,10 @@ def _load():
         L.ora_pairs.restype = None
         L.ora_pairs.argtypes = [ctypes.c_int, _u32p, _u64p, _u32p, _u64p, _u32p, _u32p, ctypes.c_uint64,
                                 _u64p, _u64p, _f64p, _u32p]
+        L.ora_contains.restype = ctypes.c_int
+        L.ora_contains.argtypes = [_u32p, ctypes.c_uint64, ctypes.c_uint32]
+        L.ora_contains_many.restype = None
+        L.ora_contains_many.argtypes = [_u32p, _u64p, _u32p, _u32p, ctypes.c_uint64, _u8p]
         L.ora_serialise.restype = ctypes.c_uint64
         L.ora_serialise.argtypes = [_u32p, ctypes.c_uint64, ctypes.c_uint64, _u64p]
         _lib = L
@@ -173,3 +182,19 @@ def pairs(name: str, va, oa, vb, ob, ia, ib, want_card=True, want_digest=False, 
                       dig.ctypes.data_as(_u64p) if dig is not None else None,
                       jac.ctypes.data_as(_f64p) if jac is not None else None, tmp.ctypes.data_as(_u32p))
     return card, dig, jac
+
+
+def contains(v, x: int) -> bool:
+    v, pv = _c32(v)
+    return bool(_load().ora_contains(pv, len(v), int(x)))
+
+
+def contains_many(values, offsets, ids, xs) -> np.ndarray:
+    """out[i] = xs[i] in set ids[i] of the collection (values, offsets); uint8."""
+    values, pv = _c32(values)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    ids, pi = _c32(ids)
+    xs, px = _c32(xs)
+    out = np.zeros(max(len(ids), 1), np.uint8)
+    _load().ora_contains_many(pv, offsets.ctypes.data_as(_u64p), pi, px, len(ids), out.ctypes.data_as(_u8p))
+    return out[:len(ids)]

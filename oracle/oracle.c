@@ -292,6 +292,30 @@ void ora_pairs(int op, const uint32_t *va, const uint64_t *oa, const uint32_t *v
     }
 }
 
+/* Membership (Section 1: random access to one value of a set): 1 if x is in
+ * the strictly increasing list v of n values, else 0. A plain binary search
+ * over the whole list; the two-level search the library does (key, then
+ * container) reaches the same answer. */
+int ora_contains(const uint32_t *v, uint64_t n, uint32_t x) {
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (v[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < n && v[lo] == x;
+}
+
+/* Batched membership over a collection (values va, offsets oa):
+ * out[i] = contains(set ids[i], xs[i]). */
+void ora_contains_many(const uint32_t *va, const uint64_t *oa, const uint32_t *ids, const uint32_t *xs, uint64_t n,
+                       uint8_t *out) {
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t s = oa[ids[i]], e = oa[ids[i] + 1];
+        out[i] = (uint8_t)ora_contains(va + s, e - s, xs[i]);
+    }
+}
+
 /* Serialised words (the digest's layout above) of container number `idx` of
  * the set v; returns the number of words (at most 1026), 0 if idx is out of
  * range. */

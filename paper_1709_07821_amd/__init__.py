@@ -41,7 +41,8 @@ EXPORTS = ["rg_create", "rg_destroy", "rg_last_error", "rg_set_dispatch", "rg_se
            "rg_serve_submit", "rg_serve_poll", "rg_serve_release", "rg_serve_replay", "rg_serve_stop",
            "rg_mlp_forward", "rg_mlp_grad", "rg_mlp_adam", "rg_dispatch_sample", "rg_dispatch_train",
            "rg_dispatch_set_mlp", "rg_dispatch_table", "rg_sync", "rg_set_workspace", "rg_workspace_size",
-           "roaring_jaccard_host", "rg_pool_init_dense", "roaring_batch_static"]
+           "roaring_jaccard_host", "rg_pool_init_dense", "roaring_batch_static",
+           "roaring_contains", "roaring_to_uint32"]
 
 
 class RoaringError(RuntimeError):
@@ -146,6 +147,8 @@ def lib():
         L.roaring_jaccard_host.argtypes = [V, pool_p, U32, pool_p, U32, P(ctypes.c_double), V]
         L.rg_pool_init_dense.argtypes = [V, pool_p, U32, V]
         L.roaring_batch_static.argtypes = [V, I, pool_p, pool_p, V, V, U64, U32, V, V, V]
+        L.roaring_contains.argtypes = [V, pool_p, V, V, U64, V, V]
+        L.roaring_to_uint32.argtypes = [V, pool_p, U32, U32, V, V, U64, P(U64), V]
         for nm in EXPORTS:
             if nm not in ("rg_destroy", "rg_last_error", "rg_plan_destroy"):
                 getattr(L, nm).restype = ctypes.c_int
@@ -413,6 +416,46 @@ def roaring_jaccard_host(ctx: Context, A: Pool, ia: int, B: Pool, ib: int, strea
     ctx.check(lib().roaring_jaccard_host(ctx.h, ctypes.byref(A.c), ia, ctypes.byref(B.c), ib, ctypes.byref(j),
                                          _stream(stream)))
     return j.value
+
+
+def roaring_contains(ctx: Context, P: Pool, ids, values, out, stream=None) -> int:
+    """Thin wrapper of roaring_contains(): ids, values device uint32 (torch int32),
+    out device uint8, all of one length."""
+    n = int(ids.numel())
+    return lib().roaring_contains(ctx.h, ctypes.byref(P.c), _ptr(ids), _ptr(values), n, _ptr(out), _stream(stream))
+
+
+def contains(ctx: Context, P: Pool, ids, values, stream=None):
+    """Membership of values[i] in bitmap ids[i]: a device bool tensor."""
+    torch = _torch()
+    out = torch.empty(max(int(ids.numel()), 1), dtype=torch.uint8, device=ids.device)
+    ctx.check(roaring_contains(ctx, P, ids, values, out, stream))
+    return out[:int(ids.numel())].bool()
+
+
+def roaring_to_uint32(ctx: Context, P: Pool, b0: int, n: int, offsets, values, cap: int, stream=None):
+    """Thin wrapper of roaring_to_uint32(): (status, needed values)."""
+    need = ctypes.c_uint64()
+    st = lib().roaring_to_uint32(ctx.h, ctypes.byref(P.c), b0, n, _ptr(offsets), _ptr(values), cap,
+                                 ctypes.byref(need), _stream(stream))
+    return st, int(need.value)
+
+
+def to_uint32(ctx: Context, P: Pool, b0: int = 0, n: int | None = None, stream=None):
+    """Sorted uint32 values of bitmaps b0 .. b0+n-1: (offsets int64[n+1], values
+    int32 tensor viewed as uint32), sized from the library's report."""
+    torch = _torch()
+    n = P.n_bitmaps - b0 if n is None else n
+    dev = P.bm_begin.device if P.bm_begin is not None else torch.device("cuda", ctx.device)
+    offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    # first call without room: it succeeds only when there are no values
+    values = torch.empty(1, dtype=torch.int32, device=dev)
+    st, need = roaring_to_uint32(ctx, P, b0, n, offsets, None, 0, stream)
+    if st == RG_ECAPACITY:
+        values = torch.empty(need, dtype=torch.int32, device=dev)
+        st, need = roaring_to_uint32(ctx, P, b0, n, offsets, values, need, stream)
+    ctx.check(st)
+    return offsets, values[:need]
 
 
 def rg_pool_recount(ctx: Context, pool: Pool, stream=None):

@@ -111,8 +111,12 @@ struct WorkspaceOrder {
     }
 };
 
-// Words of the context's 4 KiB device block (c->small).
+// The context's 4 KiB device block (c->small): bytes 0..767 the counters of
+// one materialising call (error word, bin counts and offsets, totals), 2048
+// rg_pool_validate's count, 3584 roaring_to_uint32's range (3 x u64), 3840
+// roaring_jaccard_host's result, u32 word 1020 the asynchronous error flag.
 constexpr size_t SMALL_ASYNC_ERR = 1020;  // u32: sticky flag of asynchronous calls, cleared by rg_sync
+constexpr size_t SMALL_EXPORT_RANGE = 3584;  // bytes
 
 inline uint32_t* async_err_word(rg_ctx* c) { return reinterpret_cast<uint32_t*>(c->small) + SMALL_ASYNC_ERR; }
 

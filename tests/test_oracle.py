@@ -298,3 +298,30 @@ def test_pairs_loop():
             assert int(card[p]) == len(r)
             assert int(dig[p]) == oracle.digest(r)
             assert jac[p] == oracle.jaccard(lists[p], lists[p + 1])
+
+
+def test_contains_bruteforce_subsets():
+    """Membership against the subset's defining mask: every subset of 8
+    boundary values, every boundary value and its neighbours as the query."""
+    vals = [0, 63, 64, 65535, 65536, 131071, 2**31, 2**32 - 1]
+    queries = sorted({q for v in vals for q in (v - 1, v, v + 1) if 0 <= q < 2**32})
+    for m in range(256):
+        A = _from_mask(m, vals)
+        for q in queries:
+            exp = q in vals and (m >> vals.index(q)) & 1 == 1
+            assert oracle.contains(A, q) == exp, (m, q)
+
+
+def test_contains_many_matches_python_sets():
+    rng = np.random.default_rng(41)
+    sets = [_rand_set(rng, n, hi) for n, hi in ((0, 10), (1, 2**32), (300, 70000), (5000, 2**20), (2000, 2**32))]
+    offs = np.cumsum([0] + [len(s) for s in sets]).astype(np.uint64)
+    vals = np.concatenate(sets).astype(np.uint32)
+    ids = rng.integers(0, len(sets), 20000).astype(np.uint32)
+    xs = np.where(rng.random(20000) < 0.5, rng.integers(0, 2**32, 20000, dtype=np.uint64),
+                  np.concatenate([vals, vals, vals, vals, vals])[rng.integers(0, len(vals), 20000)]).astype(np.uint32)
+    got = oracle.contains_many(vals, offs, ids, xs)
+    py = [set(s.tolist()) for s in sets]
+    exp = np.array([int(x) in py[i] for i, x in zip(ids.tolist(), xs.tolist())], np.uint8)
+    assert np.array_equal(got, exp)
+    assert got.sum() > 1000  # the sample holds members and non-members
