@@ -503,8 +503,30 @@ rg_status rg_pool_init_dense(rg_ctx *ctx, const rg_pool *pool, uint32_t n_keys, 
 rg_status rg_pool_pack_meta(rg_ctx *ctx, const rg_pool *pool, uint32_t *d_meta, void *stream);
 
 /* Check every container of a device pool against the format rules above;
- * *n_bad (host) receives the number of offending containers. Synchronises. */
+ * *n_bad (host) receives the number of offending containers. Synchronises.
+ * rg_pool_validate checks everything, including the P1 form (Section 1 size
+ * rules) and maximal runs: the form every call but rg_pool_canonicalize
+ * requires. rg_pool_check with rules 0 checks only that the pool is
+ * well-formed Roaring data: keys ascending; arrays of 1..65536 strictly
+ * increasing values; bitsets with at least one bit; runs sorted and disjoint
+ * (they may touch), at most 65536; card, bm_card and bm_wbytes consistent
+ * with the payload - what rg_pool_canonicalize accepts. RG_RULES_P1 adds the
+ * P1 rules (rg_pool_validate). */
+#define RG_RULES_P1 1u
 rg_status rg_pool_validate(rg_ctx *ctx, const rg_pool *pool, uint64_t *n_bad, void *stream);
+rg_status rg_pool_check(rg_ctx *ctx, const rg_pool *pool, uint32_t rules, uint64_t *n_bad, void *stream);
+
+/* Canonicalisation (the paper's inputs are run-optimised before any timing,
+ * Section 5.1; the Section 1 size rules pick each container's type for least
+ * memory): rebuilds every bitmap of a well-formed pool `in` (rg_pool_check
+ * with rules 0; card, bm_card and bm_wbytes must be right, which
+ * rg_pool_recount ensures) into `out` in P1 form - arrays longer than 4096
+ * values become bitsets or runs, sparse bitsets arrays or runs, touching runs
+ * merge, and every container takes the least-memory type. Result bitmap b =
+ * input bitmap b. Output sizing as for roaring_batch (RG_ECAPACITY with
+ * needed_*: at most n_containers containers and the sum of bm_wbytes payload
+ * bytes). Synchronises (arena sizing). */
+rg_status rg_pool_canonicalize(rg_ctx *ctx, const rg_pool *in, rg_out *out, void *stream);
 
 /* Per-bitmap fingerprint of the container form into device uint64
  * d_digest[n_bitmaps]: the sum, over containers and their serialised 64-bit

@@ -26,6 +26,7 @@ RG_ARRAY, RG_BITSET, RG_RUN = 1, 2, 3
 RG_AND, RG_OR, RG_XOR, RG_ANDNOT = 0, 1, 2, 3
 OPS = {"and": RG_AND, "or": RG_OR, "xor": RG_XOR, "andnot": RG_ANDNOT}
 RG_FLAG_MATERIALIZE, RG_FLAG_CARD, RG_FLAG_JACCARD = 1, 2, 4
+RG_RULES_P1 = 1
 RG_DISPATCH_HEURISTIC, RG_DISPATCH_MLP, RG_DISPATCH_FIXED = 0, 1, 2
 RG_MLP_PARAMS, RG_MLP_TABLE = 5382, 374544
 VARIANTS = {"generic": 2, "merge": 3, "gallop": 4, "probe": 5, "runmerge": 6, "thread": 7}
@@ -42,7 +43,7 @@ EXPORTS = ["rg_create", "rg_destroy", "rg_last_error", "rg_set_dispatch", "rg_se
            "rg_mlp_forward", "rg_mlp_grad", "rg_mlp_adam", "rg_dispatch_sample", "rg_dispatch_train",
            "rg_dispatch_set_mlp", "rg_dispatch_table", "rg_sync", "rg_set_workspace", "rg_workspace_size",
            "roaring_jaccard_host", "rg_pool_init_dense", "roaring_batch_static",
-           "roaring_contains", "roaring_to_uint32"]
+           "roaring_contains", "roaring_to_uint32", "rg_pool_check", "rg_pool_canonicalize"]
 
 
 class RoaringError(RuntimeError):
@@ -148,6 +149,8 @@ def lib():
         L.rg_pool_init_dense.argtypes = [V, pool_p, U32, V]
         L.roaring_batch_static.argtypes = [V, I, pool_p, pool_p, V, V, U64, U32, V, V, V]
         L.roaring_contains.argtypes = [V, pool_p, V, V, U64, V, V]
+        L.rg_pool_check.argtypes = [V, pool_p, U32, P(U64), V]
+        L.rg_pool_canonicalize.argtypes = [V, pool_p, out_p, V]
         L.roaring_to_uint32.argtypes = [V, pool_p, U32, U32, V, V, U64, P(U64), V]
         for nm in EXPORTS:
             if nm not in ("rg_destroy", "rg_last_error", "rg_plan_destroy"):
@@ -296,13 +299,21 @@ class Pool:
 
     @staticmethod
     def from_sets(values, offsets, device="cuda"):
-        torch = _torch()
         n, nc, pb, a = Pool.host_arrays(values, offsets)
+        return Pool.from_host_arrays(a, device)
+
+    @staticmethod
+    def from_host_arrays(a, device="cuda"):
+        """A device pool from host arrays in the pool format (the keys of
+        host_arrays' result; payload a multiple of 16 bytes)."""
+        torch = _torch()
 
         def dev(x, dt):
-            return torch.from_numpy(x.view(dt)).to(device)
+            return torch.from_numpy(np.ascontiguousarray(x).view(dt)).to(device)
 
-        return Pool(n, nc, max(pb, 16), dev(a["bm_begin"], np.int64), dev(a["keys"], np.int16),
+        n = len(a["bm_begin"]) - 1
+        nc = len(a["keys"])
+        return Pool(n, nc, max(len(a["payload"]), 16), dev(a["bm_begin"], np.int64), dev(a["keys"], np.int16),
                     dev(a["types"], np.uint8), dev(a["card"], np.int32), dev(a["size"], np.int32),
                     dev(a["off"], np.int64), dev(a["payload"], np.uint8), dev(a["bm_card"], np.int64),
                     dev(a["bm_wbytes"], np.int64))
@@ -466,6 +477,27 @@ def rg_pool_validate(ctx: Context, pool: Pool, stream=None) -> int:
     bad = ctypes.c_uint64()
     ctx.check(lib().rg_pool_validate(ctx.h, ctypes.byref(pool.c), ctypes.byref(bad), _stream(stream)))
     return int(bad.value)
+
+
+def rg_pool_check(ctx: Context, pool: Pool, rules: int = 0, stream=None) -> int:
+    """rg_pool_check: number of containers that break the rules (0: well-formed; RG_RULES_P1: also P1)."""
+    n = ctypes.c_uint64()
+    ctx.check(lib().rg_pool_check(ctx.h, ctypes.byref(pool.c), rules, ctypes.byref(n), _stream(stream)))
+    return int(n.value)
+
+
+def canonicalize(ctx: Context, pool: Pool, stream=None) -> "OutArena":
+    """rg_pool_canonicalize with arena sizing: the pool's bitmaps in P1 form (an OutArena)."""
+    dev = pool.bm_begin.device
+    out = OutArena(pool.n_bitmaps, 0, 0, dev)
+    out.c.cap_containers = 0
+    out.c.cap_payload_bytes = 0
+    st = lib().rg_pool_canonicalize(ctx.h, ctypes.byref(pool.c), ctypes.byref(out.c), _stream(stream))
+    if st == RG_ECAPACITY:
+        out = OutArena(pool.n_bitmaps, out.c.needed_containers, out.c.needed_payload_bytes, dev)
+        st = lib().rg_pool_canonicalize(ctx.h, ctypes.byref(pool.c), ctypes.byref(out.c), _stream(stream))
+    ctx.check(st)
+    return out
 
 
 def rg_pool_digest(ctx: Context, pool: Pool, stream=None):

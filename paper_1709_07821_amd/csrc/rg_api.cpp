@@ -219,9 +219,11 @@ rg_status run_count_async(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B,
 }
 
 // one batched call (also used by the dispatcher's cost sampling)
+// single (materialising, op RG_ANDNOT): every pair is the union of its A
+// bitmap alone, i.e. that bitmap rebuilt in P1 form (rg_pool_canonicalize)
 rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const uint32_t* d_ia,
                     const uint32_t* d_ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs, uint32_t flags, rg_out* out,
-                    uint64_t* d_cards, double* d_jacc, hipStream_t st) {
+                    uint64_t* d_cards, double* d_jacc, hipStream_t st, bool single) {
     if (!c) return RG_EINVAL;
     if (op < RG_AND || op > RG_ANDNOT) return fail(c, RG_EINVAL, "op must be RG_AND..RG_ANDNOT");
     if (!pool_ok(A) || !pool_ok(B)) return fail(c, RG_EINVAL, "incomplete pool (null pointer)");
@@ -382,7 +384,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
         }
         uint64_t pay_end = 0;
         if (kw) {
-            launch_kw_pair_queries(op, d_ia, d_ib, ia0, ib0, p0, np, cand_off, kw_queries, kw_ids, st);
+            launch_kw_pair_queries(op, d_ia, d_ib, ia0, ib0, p0, np, cand_off, kw_queries, kw_ids, st, single);
             KwArgs ka;
             ka.P0 = pa;
             ka.P1 = pb;
@@ -837,13 +839,26 @@ rg_status rg_pool_pack_meta(rg_ctx* c, const rg_pool* p, uint32_t* d_meta, void*
 }
 
 rg_status rg_pool_validate(rg_ctx* c, const rg_pool* p, uint64_t* n_bad, void* stream) {
+    return rg_pool_check(c, p, RG_RULES_P1, n_bad, stream);
+}
+
+rg_status rg_pool_canonicalize(rg_ctx* c, const rg_pool* in, rg_out* out, void* stream) {
+    if (!c) return RG_EINVAL;
+    if (!pool_ok(in)) return fail(c, RG_EINVAL, "incomplete pool (null pointer)");
+    // pair p = (bitmap p, bitmap p); each result is the union of bitmap p alone
+    return run_batch(c, RG_ANDNOT, in, in, nullptr, nullptr, NONE, NONE, in->n_bitmaps, RG_FLAG_MATERIALIZE, out,
+                     nullptr, nullptr, (hipStream_t)stream, /*single=*/true);
+}
+
+rg_status rg_pool_check(rg_ctx* c, const rg_pool* p, uint32_t rules, uint64_t* n_bad, void* stream) {
     if (!c) return RG_EINVAL;
     if (!pool_ok(p) || !n_bad) return fail(c, RG_EINVAL, "incomplete pool");
+    if (rules & ~(uint32_t)RG_RULES_P1) return fail(c, RG_EINVAL, "rg_pool_check: unknown rules");
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
     WorkspaceOrder order(c, st);  // the context's device block and staging are shared with other calls
     uint64_t* d_bad = reinterpret_cast<uint64_t*>((uint8_t*)c->small + 2048);
-    launch_pool_validate(*p, d_bad, st);
+    launch_pool_validate(*p, d_bad, (rules & RG_RULES_P1) != 0, st);
     HIPCHK(c, hipMemcpyAsync(c->host, d_bad, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     *n_bad = *reinterpret_cast<uint64_t*>(c->host);

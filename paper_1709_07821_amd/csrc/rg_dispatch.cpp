@@ -41,10 +41,6 @@ std::vector<float> he_init(uint64_t seed) {
 
 }  // namespace
 
-rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const uint32_t* d_ia, const uint32_t* d_ib,
-                    uint32_t ia0, uint32_t ib0, uint64_t n_pairs, uint32_t flags, rg_out* out, uint64_t* d_cards,
-                    double* d_jacc, hipStream_t st);
-
 extern "C" {
 
 rg_status rg_mlp_forward(rg_ctx* c, const float* d_params, const float* d_x, uint64_t n, float* d_y, void* stream) {

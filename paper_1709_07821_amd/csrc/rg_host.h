@@ -220,3 +220,9 @@ inline bool pool_ok(const rg_pool* p) {
            p->n_containers < 0xFFFFFFFFull;
 }
 
+// One batched call (rg_api.cpp): pair preparation, key matching in waves,
+// binned kernels, output assembly or count finishing. single: see
+// rg_pool_canonicalize.
+rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const uint32_t* d_ia,
+                    const uint32_t* d_ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs, uint32_t flags, rg_out* out,
+                    uint64_t* d_cards, double* d_jacc, hipStream_t st, bool single = false);

@@ -405,10 +405,11 @@ void launch_kw_keys(const KwArgs& a, hipStream_t st);
 void launch_kw_bounds(const KwArgs& a, hipStream_t st);
 void launch_kw_eval(const KwArgs& a, hipStream_t st);
 void launch_kw_cards(const KwArgs& a, const uint64_t* bm_card, uint64_t* cards, hipStream_t st);
-// queries q < n_pairs for pairs pair0 + q (k = 2: A side, B side), slot ranges from cand_off
+// queries q < n_pairs for pairs pair0 + q (k = 2: A side, B side), slot ranges
+// from cand_off; single: k = 1 union queries of the A side (its P1 form)
 void launch_kw_pair_queries(int op, const uint32_t* ia, const uint32_t* ib, uint32_t ia0, uint32_t ib0,
                             uint64_t pair0, uint32_t n_pairs, const uint64_t* cand_off, KwQuery* queries,
-                            uint32_t* ids, hipStream_t st);
+                            uint32_t* ids, hipStream_t st, bool single = false);
 // out[3j..3j+2] = key count, payload bound, 1 (0, 0, 0 for an id outside the pool)
 void launch_kw_gather_meta(const uint64_t* bm_begin, const uint64_t* bm_wbytes, uint32_t n_bitmaps,
                            const uint32_t* ids, uint32_t k, uint64_t* out, hipStream_t st);
@@ -416,7 +417,8 @@ void launch_kw_gather_meta(const uint64_t* bm_begin, const uint64_t* bm_wbytes, 
 // pool utilities
 void launch_pool_recount(const rg_pool& p, hipStream_t st);
 void launch_pool_dense_init(const rg_pool& p, uint32_t n_keys, hipStream_t st);
-void launch_pool_validate(const rg_pool& p, uint64_t* d_bad, hipStream_t st);
+// p1: also require the least-memory (P1) container types and maximal runs
+void launch_pool_validate(const rg_pool& p, uint64_t* d_bad, bool p1, hipStream_t st);
 void launch_pool_digest(const rg_pool& p, uint64_t* d_digest, hipStream_t st);
 // containers i >= *d_n (device count) are skipped
 void launch_pool_digest_n(const rg_pool& p, const uint64_t* d_n, uint64_t* d_digest, hipStream_t st);

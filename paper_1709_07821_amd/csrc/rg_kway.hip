@@ -536,18 +536,21 @@ void launch_kw_cards(const KwArgs& a, const uint64_t* bm_card, uint64_t* cards, 
 
 namespace rg {
 
-// pairwise materialisation through the k-way path: query q is pair pair0 + q
+// pairwise materialisation through the k-way path: query q is pair pair0 + q.
+// single: the query is the union of the pair's first bitmap alone (k = 1),
+// which rebuilds that bitmap's containers in P1 form (canonicalisation).
+// Without pair arrays, ia0 / ib0 == NONE make pair p bitmap p.
 __global__ void k_kw_pair_queries(int op, const uint32_t* ia, const uint32_t* ib, uint32_t ia0, uint32_t ib0,
                                   uint64_t pair0, uint32_t n_pairs, const uint64_t* cand_off, KwQuery* queries,
-                                  uint32_t* ids) {
+                                  uint32_t* ids, int single) {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n_pairs) return;
     const uint64_t p = pair0 + q;
-    ids[2 * q] = ia ? ia[p] : ia0;
-    ids[2 * q + 1] = ib ? ib[p] : ib0;
+    ids[2 * q] = ia ? ia[p] : ia0 == NONE ? (uint32_t)p : ia0;
+    ids[2 * q + 1] = ib ? ib[p] : ib0 == NONE ? (uint32_t)p : ib0;
     KwQuery Q;
-    Q.op = (uint32_t)op;
-    Q.k = 2;
+    Q.op = single ? (uint32_t)RG_OR : (uint32_t)op;
+    Q.k = single ? 1u : 2u;
     Q.ids_off = 2 * q;
     Q.flags = KW_MATERIALIZE;
     Q.slot0 = cand_off[q];
@@ -558,10 +561,10 @@ __global__ void k_kw_pair_queries(int op, const uint32_t* ia, const uint32_t* ib
 
 void launch_kw_pair_queries(int op, const uint32_t* ia, const uint32_t* ib, uint32_t ia0, uint32_t ib0,
                             uint64_t pair0, uint32_t n_pairs, const uint64_t* cand_off, KwQuery* queries,
-                            uint32_t* ids, hipStream_t st) {
+                            uint32_t* ids, hipStream_t st, bool single) {
     if (n_pairs)
         hipLaunchKernelGGL(k_kw_pair_queries, dim3((n_pairs + 255) / 256), dim3(256), 0, st, op, ia, ib, ia0, ib0,
-                           pair0, n_pairs, cand_off, queries, ids);
+                           pair0, n_pairs, cand_off, queries, ids, (int)single);
 }
 
 // per id: key count, payload bound (bm_wbytes), and validity, for host-side bounds

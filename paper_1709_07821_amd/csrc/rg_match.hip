@@ -43,8 +43,10 @@ __global__ void k_pair_prep(int op, int materialize, PoolView A, PoolView B, uin
     uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p == 0 && zero_word) *zero_word = 0;
     if (p >= n_pairs) return;
-    uint32_t a = ia ? ia[p] : ia0;
-    uint32_t b = ib ? ib[p] : ib0;
+    // without pair arrays, ia0 / ib0 name the bitmap of every pair, or (NONE)
+    // pair p is bitmap p itself
+    uint32_t a = ia ? ia[p] : ia0 == NONE ? (uint32_t)p : ia0;
+    uint32_t b = ib ? ib[p] : ib0 == NONE ? (uint32_t)p : ib0;
     if (a >= nA || b >= nB) {  // bad index: report, and give the pair no work
         atomicOr(err, 1u);
         n_cand[p] = 0;

@@ -79,7 +79,10 @@ void launch_pool_dense_init(const rg_pool& p, uint32_t n_keys, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ validate
-__global__ void __launch_bounds__(256) k_validate(rg_pool p, unsigned long long* bad) {
+// p1 = 0 checks only that every container is a well-formed set (arrays of
+// any length strictly increasing, runs sorted and disjoint but possibly
+// touching, cardinalities right); p1 = 1 also requires the P1 form.
+__global__ void __launch_bounds__(256) k_validate(rg_pool p, unsigned long long* bad, int p1) {
     const uint32_t lane = lane_id();
     const uint64_t i = wave_index();
     if (i >= p.n_containers || i < uniform64(p.bm_begin[0])) return;  // a window may start past 0
@@ -89,9 +92,9 @@ __global__ void __launch_bounds__(256) k_validate(rg_pool p, unsigned long long*
     bool ok = type >= RG_ARRAY && type <= RG_RUN && (off & 15) == 0 && card >= 1 && card <= 65536;
     if (ok) {
         uint64_t bytes = payload_bytes_of(type, size);
-        if (type == RG_ARRAY) ok = size >= 1 && size <= 4096 && size == card;
+        if (type == RG_ARRAY) ok = size >= 1 && size <= (p1 ? 4096u : 65536u) && size == card;
         if (type == RG_BITSET) ok = size == 1024;
-        if (type == RG_RUN) ok = size >= 1 && size <= 32768;
+        if (type == RG_RUN) ok = size >= 1 && size <= (p1 ? 32768u : 65536u);
         ok = ok && off + ((bytes + 15) & ~15ull) <= p.payload_bytes;
     }
     const uint32_t b = bitmap_of(p.bm_begin, p.n_bitmaps, i);
@@ -122,7 +125,8 @@ __global__ void __launch_bounds__(256) k_validate(rg_pool p, unsigned long long*
                 if (s + l > 65535u) lok = false;
                 if (k > 0) {
                     uint32_t ps = rp[k - 1] & 0xFFFFu, pl2 = rp[k - 1] >> 16;
-                    if (!(s > ps + pl2 + 1)) lok = false;  // sorted, disjoint, not touching
+                    // sorted and disjoint; P1 also forbids touching runs
+                    if (!(s > ps + pl2 + (p1 ? 1u : 0u))) lok = false;
                 }
                 c += l + 1;
             }
@@ -134,7 +138,7 @@ __global__ void __launch_bounds__(256) k_validate(rg_pool p, unsigned long long*
     bool all_ok = __ballot(!lok) == 0;
     if (lane == 0) {
         if (type == RG_RUN) rr = size;
-        bool good = ok && all_ok && c == card && p1_type(c, rr) == type;
+        bool good = ok && all_ok && c == card && (!p1 || p1_type(c, rr) == type);
         if (!good) atomicAdd(bad, 1ull);
     }
 }
@@ -159,13 +163,13 @@ __global__ void k_validate_bitmaps(rg_pool p, unsigned long long* bad) {
     if (tc != p.bm_card[b] || tw != p.bm_wbytes[b]) atomicAdd(bad, 1ull);
 }
 
-void launch_pool_validate(const rg_pool& p, uint64_t* d_bad, hipStream_t st) {
+void launch_pool_validate(const rg_pool& p, uint64_t* d_bad, bool p1, hipStream_t st) {
     launch_fill_u64(d_bad, 0, 1, st);
     hipLaunchKernelGGL(k_validate_bitmaps, dim3((p.n_bitmaps + 1 + 255) / 256), dim3(256), 0, st, p,
                        reinterpret_cast<unsigned long long*>(d_bad));
     if (p.n_containers)
         hipLaunchKernelGGL(k_validate, dim3((uint32_t)((p.n_containers + 3) / 4)), dim3(256), 0, st, p,
-                           reinterpret_cast<unsigned long long*>(d_bad));
+                           reinterpret_cast<unsigned long long*>(d_bad), (int)p1);
 }
 
 // ------------------------------------------------------------------ digest

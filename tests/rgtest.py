@@ -100,3 +100,59 @@ def _chunk_runs(key, lengths, gap=1):
         x += n + gap
     assert x - gap <= 65536
     return (np.array(v, np.uint32) + np.uint32(key * 65536)).astype(np.uint32)
+
+
+def noncanonical_arrays(sets, rng, p_array=0.34, p_bitset=0.33):
+    """Host pool arrays (the pool format) holding the given sorted sets in
+    well-formed but not necessarily least-memory containers: each chunk is
+    stored, at random, as an array (any length), a bitset (any cardinality) or
+    a run list whose maximal runs are cut at random points into touching runs.
+    card, bm_card and bm_wbytes are consistent with the contents."""
+    keys, types, card, size, offs, chunks = [], [], [], [], [], []
+    bm_begin, bm_card, bm_wbytes = [0], [], []
+    pos = 0
+    for v in sets:
+        v = np.asarray(v, dtype=np.uint32)
+        hi = v >> np.uint32(16)
+        tw = 0
+        for key in np.unique(hi):
+            low = (v[hi == key] & np.uint32(0xFFFF)).astype(np.int64)
+            c = len(low)
+            u = rng.random()
+            if u < p_array:
+                t, pl = ARRAY, low.astype(np.uint16).tobytes()
+                sz = c
+            elif u < p_array + p_bitset:
+                w = np.zeros(1024, np.uint64)
+                np.bitwise_or.at(w, low >> 6, np.left_shift(np.uint64(1), (low & 63).astype(np.uint64)))
+                t, pl, sz = BITSET, w.tobytes(), 1024
+            else:
+                starts = np.concatenate([[0], np.nonzero(np.diff(low) != 1)[0] + 1])
+                ends = np.concatenate([starts[1:], [c]])  # exclusive indices
+                runs = []
+                for s0, e0 in zip(starts, ends):
+                    a, b = int(low[s0]), int(low[e0 - 1])
+                    cuts = sorted(set(int(x) for x in rng.integers(a + 1, b + 1, size=rng.integers(0, 3)))) if b > a \
+                        else []
+                    pts = [a] + cuts + [b + 1]
+                    for x, y in zip(pts[:-1], pts[1:]):
+                        runs.append((x, y - x - 1))
+                pr = np.array(runs, np.uint16).reshape(-1, 2)
+                t, pl, sz = RUN, pr.tobytes(), len(runs)
+            keys.append(int(key))
+            types.append(t)
+            card.append(c)
+            size.append(sz)
+            offs.append(pos)
+            padded = pl + b"\0" * ((-len(pl)) % 16)
+            chunks.append(padded)
+            pos += len(padded)
+            tw += (min(8192, 2 * c) + 15) & ~15
+        bm_begin.append(len(keys))
+        bm_card.append(len(v))
+        bm_wbytes.append(tw)
+    payload = np.frombuffer(b"".join(chunks) or b"\0" * 16, np.uint8).copy()
+    return {"bm_begin": np.array(bm_begin, np.uint64), "keys": np.array(keys, np.uint16),
+            "types": np.array(types, np.uint8), "card": np.array(card, np.uint32),
+            "size": np.array(size, np.uint32), "off": np.array(offs, np.uint64), "payload": payload,
+            "bm_card": np.array(bm_card, np.uint64), "bm_wbytes": np.array(bm_wbytes, np.uint64)}
