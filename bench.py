@@ -1,21 +1,30 @@
-"""Benchmark: Roaring set operations on the dense-bitset workload.
+"""Benchmark: Roaring set operations on one MI355X.
 
-Workload (bitset-bandwidth): 2e4 bitmaps, each with 256 bitset containers
-(keys 0..255, 8 KiB each, bit density U(0.2, 0.8)), about 42 GB resident in
-HBM, generated on the device; 1e4 random pairs (ia != ib). One step runs, for
-each of AND, OR, XOR, ANDNOT, the count-only form (fused op + popcount,
-|A op B| per pair) over all pairs, plus the Jaccard index per pair.
+Default workload (bitset-bandwidth): 2e4 bitmaps, each with 256 bitset
+containers (keys 0..255, 8 KiB each, bit density U(0.2, 0.8)), about 42 GB
+resident in HBM, generated on the device; 1e4 random pairs (ia != ib). One
+step runs, for each of AND, OR, XOR, ANDNOT, the count-only form (fused op +
+popcount, |A op B| per pair) over all pairs, plus the Jaccard index per pair.
 
 value = algorithmic input bytes of the step / step time (GB/s), the metric's
 "input GB/s"; container-pairs/s is reported beside it. Inputs are resident in
 HBM before timing starts.
 
 The dominant kernel's roofline entry is measured live: the library brackets
-each launch of its bitset-bitset kernel with HIP events on the launch stream
+each launch of its kernels with HIP events on the launch stream
 (rg_profile_*), and achieved = algorithmic bytes per launch / mean launch time.
 
 cpu_baseline: the CPU oracle (plain two-pointer merges over sorted uint32
-lists) timed on a bounded sample of the same pairs, rank 0 only.
+lists) timed on a bounded sample of the same work, rank 0 only, on one core
+and on every host core (a thread pool over pairs: the oracle's C calls release
+Python's lock); value is the all-core rate.
+
+Other workloads (--workload): mixed (100 mixed bitmaps, 99 successive pairs,
+four operations materialised with counts and Jaccard), array (1e5 array-array
+pairs, Zipf sizes, materialised), dense-mat (materialised dense pairs),
+batched (1e6 uneven pairs: plan, eager call, one call per pair, learned
+dispatch), serve (k-way queries over a 1e5-bitmap index under Poisson
+arrivals).
 """
 from __future__ import annotations
 
@@ -24,12 +33,14 @@ import json
 import os
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 META_BYTES = 19  # key u16 + type u8 + card u32 + size u32 + off u64 per container
+OPS4 = ("and", "or", "xor", "andnot")
 
 
 def main():
@@ -40,13 +51,17 @@ def main():
     ap.add_argument("--bitmaps", type=int, default=20000)
     ap.add_argument("--keys", type=int, default=256)
     ap.add_argument("--pairs", type=int, default=10000)
-    ap.add_argument("--cpu-pairs", type=int, default=48, help="pairs in the oracle timing sample")
+    ap.add_argument("--cpu-pairs", type=int, default=48, help="dense: pairs in the oracle timing sample")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target single-core oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", type=int, default=2, help="pairs checked against the oracle before timing")
-    ap.add_argument("--workload", choices=("dense", "dense-mat", "batched", "serve"), default="dense",
-                    help="dense: the bitset-bandwidth headline; batched: many uneven pairs, plan vs per-pair; "
-                         "serve: k-way queries under Poisson arrivals, batched server vs one query at a time")
-    ap.add_argument("--index", type=int, default=4000, help="serve: bitmaps in the index")
+    ap.add_argument("--workload", choices=("dense", "mixed", "array", "dense-mat", "batched", "serve"),
+                    default="dense",
+                    help="dense: the bitset-bandwidth headline; mixed / array: the small mixed and array-stress "
+                         "pairs, materialised; batched: many uneven pairs, plan vs per-pair; serve: k-way "
+                         "queries under Poisson arrivals, batched server vs one query at a time")
+    ap.add_argument("--array-pairs", type=int, default=100000, help="array: pairs")
+    ap.add_argument("--index", type=int, default=100000, help="serve: bitmaps in the index")
     ap.add_argument("--rates", default="2000,5000,10000,20000,50000", help="serve: arrival rates (queries/s)")
     ap.add_argument("--duration", type=float, default=2.0, help="serve: seconds of arrivals per rate")
     ap.add_argument("--max-batch", type=int, default=256, help="serve: most queries per step (batched mode)")
@@ -63,11 +78,7 @@ def main():
               "sharding over several GPUs is designed (keys partition the universe), not built", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-
-    import paper_1709_07821_amd as rg
-    import synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -79,12 +90,147 @@ def main():
         torch.cuda.synchronize()
         print(f"# copied {src.numel() * 8} bytes device to device", file=sys.stderr, flush=True)
         return None
-    if args.workload == "batched":
-        return bench_batched(args)
-    if args.workload == "dense-mat":
-        return bench_dense_mat(args)
-    if args.workload == "serve":
-        return bench_serve(args)
+    fn = {"dense": bench_dense, "mixed": bench_mixed, "array": bench_array, "dense-mat": bench_dense_mat,
+          "batched": bench_batched, "serve": bench_serve}[args.workload]
+    return fn(args)
+
+
+# ---------------------------------------------------------------- shared helpers
+
+def say(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)), "model": model}
+
+
+def cpu_threads():
+    # one GPU's share of the host: at most 16 workers, whatever the machine shows
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def cpu_baseline_tasks(tasks, work_units, unit, sample, target_s):
+    """Times the oracle on `tasks` (zero-argument callables, each one oracle
+    call over a slice of the sample): once to size the run, then repeated to
+    about target_s on one thread, then the same repeated tasks on every usable
+    core. work_units: the metric's units (bytes or container pairs) of one pass."""
+    t0 = time.perf_counter()
+    for f in tasks:
+        f()
+    t1 = time.perf_counter() - t0
+    if t1 >= 0.5 * target_s:
+        reps, t_single = 1, t1  # one pass is long enough to be the single-core measurement
+    else:
+        reps = max(1, min(100, int(round(target_s / max(t1, 1e-4)))))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for f in tasks:
+                f()
+        t_single = time.perf_counter() - t0
+    nt = cpu_threads()
+    work = tasks * reps
+    with ThreadPoolExecutor(nt) as ex:
+        t0 = time.perf_counter()
+        list(ex.map(lambda f: f(), work))
+        t_multi = time.perf_counter() - t0
+    scale = 1e9 if unit == "GB/s" else 1.0
+    return {"value": round(work_units * reps / t_multi / scale, 4), "unit": unit, "cores": nt, "kind": "oracle",
+            "sample": f"{sample}; {reps} pass(es): {t_single:.1f} s on 1 core, {t_multi:.1f} s on {nt} threads",
+            "single_core_value": round(work_units * reps / t_single / scale, 4), "host": host_info()}
+
+
+def container_payload_bytes(h):
+    """Payload bytes of every container of host pool arrays (array 2c, bitset 8192, run 4r)."""
+    import numpy as np
+
+    t = h["types"]
+    sz = h["size"].astype(np.int64)
+    return np.where(t == 1, 2 * sz, np.where(t == 2, 8192, 4 * sz))
+
+
+def pair_stats(h, ia, ib):
+    """Per pair: key counts of both bitmaps, matched containers, payload bytes
+    of all containers of each side and of the matched containers of each side
+    (host pool arrays h; pairs ia, ib)."""
+    import numpy as np
+
+    bb = h["bm_begin"].astype(np.int64)
+    pay = container_payload_bytes(h)
+    keys = h["keys"].astype(np.int64)
+    n = len(ia)
+
+    def side(ids):
+        s = bb[ids.astype(np.int64)]
+        cnt = bb[ids.astype(np.int64) + 1] - s
+        pidx = np.repeat(np.arange(n, dtype=np.int64), cnt)
+        start = np.repeat(np.cumsum(cnt) - cnt, cnt)
+        cidx = np.repeat(s, cnt) + (np.arange(int(cnt.sum()), dtype=np.int64) - start)
+        return pidx, cidx, cnt
+
+    pa, ca, na = side(ia)
+    pb, cb, nb = side(ib)
+    _, xa, xb = np.intersect1d((pa << 16) | keys[ca], (pb << 16) | keys[cb], assume_unique=True,
+                               return_indices=True)
+    f = lambda idx, w: np.bincount(idx, weights=w, minlength=n)
+    return {"KA": na, "KB": nb, "matched": np.bincount(pa[xa], minlength=n), "payA": f(pa, pay[ca]),
+            "payB": f(pb, pay[cb]), "payAm": f(pa[xa], pay[ca[xa]]), "payBm": f(pa[xa], pay[cb[xb]])}
+
+
+def op_input_bytes(st, op):
+    """Algorithmic input bytes per pair of one operation: the payloads it must
+    read (matched containers; for union and symmetric difference also every
+    one-sided container, for difference A's) plus 19 B of metadata per
+    container of both bitmaps."""
+    meta = META_BYTES * (st["KA"] + st["KB"])
+    if op == "and":
+        return st["payAm"] + st["payBm"] + meta
+    if op in ("or", "xor"):
+        return st["payA"] + st["payB"] + meta
+    return st["payA"] + st["payBm"] + meta
+
+
+def result_payload_bytes(out):
+    """Payload bytes and container count of the results in an output arena."""
+    import numpy as np
+
+    n = int(out.c.n_containers)
+    t = out.types[:n].cpu().numpy()
+    sz = out.size[:n].cpu().numpy().astype(np.int64)
+    return int(np.where(t == 1, 2 * sz, np.where(t == 2, 8192, 4 * sz)).sum()), n
+
+
+def time_steps(step, steps, warmup):
+    import torch
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+# ---------------------------------------------------------------- dense (headline)
+
+def bench_dense(args):
+    import numpy as np
+    import torch
+
+    import paper_1709_07821_amd as rg
+    import synth
+
     dev = torch.device("cuda:0")
     ctx = rg.Context(0)
     stream = torch.cuda.current_stream()
@@ -98,8 +244,7 @@ def main():
         synth.dense_bitsets_device(words.data_ptr() + b0 * nk * 8192, b0, n, nk, stream.cuda_stream)
     P = rg.Pool.from_dense_words(ctx, words, nb, nk)
     torch.cuda.synchronize()
-    print(f"# generated {nb} x {nk} bitsets ({words.numel() * 8 / 1e9:.1f} GB) in {time.time() - t0:.1f} s",
-          file=sys.stderr, flush=True)
+    say(f"generated {nb} x {nk} bitsets ({words.numel() * 8 / 1e9:.1f} GB) in {time.time() - t0:.1f} s")
     ia, ib = synth.random_pairs(nb, npairs, seed=synth.DENSE_SEED)
     tia = torch.from_numpy(ia.view(np.int32)).to(dev)
     tib = torch.from_numpy(ib.view(np.int32)).to(dev)
@@ -107,7 +252,7 @@ def main():
     jacc = torch.zeros(npairs, dtype=torch.float64, device=dev)
 
     def step():
-        for op in ("and", "or", "xor", "andnot"):
+        for op in OPS4:
             flags = rg.RG_FLAG_CARD | (rg.RG_FLAG_JACCARD if op == "and" else 0)
             ctx.check(rg.roaring_batch(ctx, op, P, P, tia, tib, flags, None, cards[op],
                                        jacc if op == "and" else None, stream))
@@ -126,7 +271,7 @@ def main():
                 exp = oracle.count(op, a, b)
                 assert got == exp, f"pair {p} {op}: gpu {got} oracle {exp}"
             assert float(jacc[p].item()) == oracle.jaccard(a, b)
-        print(f"# {args.check} pairs x 4 ops match the oracle", file=sys.stderr, flush=True)
+        say(f"{args.check} pairs x 4 ops match the oracle")
 
     for _ in range(args.warmup):
         step()
@@ -140,6 +285,7 @@ def main():
     dt = time.perf_counter() - t0
     prof = rg.profile_read(ctx)
     rg.profile_enable(ctx, False)
+    ctx.sync()
 
     cont_pairs = npairs * nk                      # matched container pairs per op
     in_bytes_op = cont_pairs * 2 * (8192 + META_BYTES)
@@ -159,15 +305,12 @@ def main():
         mean_s = k["ms"] / k["launches"] / 1e3
         ach = alg_bytes / mean_s / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                 "kernel": "k_count_fused", "mean_launch_ms": round(mean_s * 1e3, 4),
                 "launches": int(k["launches"]), "bytes_per_launch": int(alg_bytes)}
-
-    if roof is not None:
-        roof["traffic"] = measured_traffic()
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(ia, ib, nk, args.cpu_pairs)
+        cpu = dense_cpu_baseline(ia, ib, nk, args.cpu_pairs, args.cpu_seconds)
 
     line = {
         "metric": "input GB/s and container-pairs/sec for AND/OR/XOR/ANDNOT+card (% HBM peak)",
@@ -183,6 +326,161 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def dense_cpu_baseline(ia, ib, nk, n_pairs, target_s):
+    """The oracle, as it stands, on the first n_pairs pairs: 4 counts + Jaccard per pair."""
+    import oracle
+    import synth
+
+    n_pairs = min(n_pairs, len(ia))
+    sets = {}
+    for p in range(n_pairs):
+        for b in (int(ia[p]), int(ib[p])):
+            if b not in sets:
+                sets[b] = synth.dense_bitmap_values(b, nk)
+
+    def task(p):
+        def f():
+            a, b = sets[int(ia[p])], sets[int(ib[p])]
+            for op in OPS4:
+                oracle.count(op, a, b)
+            oracle.jaccard(a, b)
+        return f
+
+    tasks = [task(p) for p in range(n_pairs)]
+    in_bytes = n_pairs * nk * 2 * (8192 + META_BYTES) * 4
+    return cpu_baseline_tasks(tasks, in_bytes, "GB/s",
+                              f"{n_pairs} of the pairs, 4 count-only ops + Jaccard each (two-pointer merges over "
+                              f"sorted uint32)", target_s)
+
+
+# ---------------------------------------------------------------- materialised pair workloads
+
+def bench_pairs_materialised(args, bs, ia, ib, workload, metric_config):
+    """Four operations materialised over the given pairs (result bitmaps in
+    preallocated arenas; each op's first call sizes its arena), with the result
+    cardinalities and the Jaccard index of every pair in the same calls. Every
+    pair's result cardinality, fingerprint and Jaccard are checked against the
+    oracle before timing. value = algorithmic input bytes of the step / step
+    time; the roofline entry is the k-way evaluation kernel (union, symmetric
+    difference, difference): result payload read and written per launch over
+    its launch time."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1709_07821_amd as rg
+
+    dev = torch.device("cuda:0")
+    ctx = rg.Context(0)
+    n = len(ia)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    h = rg.Pool.host_arrays(bs.values, bs.offsets)[3]
+    tia = torch.from_numpy(ia.view(np.int32)).to(dev)
+    tib = torch.from_numpy(ib.view(np.int32)).to(dev)
+    arenas, cards, jaccs = {}, {}, {}
+    for op in OPS4:
+        arenas[op], cards[op], jaccs[op] = rg.batch(ctx, op, P, P, tia, tib, materialize=True, card=True,
+                                                    jaccard=True)
+    torch.cuda.synchronize()
+    # correctness gate: every pair's count, fingerprint and Jaccard against the oracle
+    for op in OPS4:
+        c_exp, d_exp, j_exp = oracle.pairs(op, bs.values, bs.offsets, bs.values, bs.offsets, ia, ib,
+                                           want_digest=True, want_jaccard=True)
+        dig = rg.rg_pool_digest(ctx, arenas[op].as_pool()).cpu().numpy().view(np.uint64)[:n]
+        assert np.array_equal(cards[op].cpu().numpy().view(np.uint64), c_exp), op
+        assert np.array_equal(dig, d_exp), op
+        assert np.array_equal(jaccs[op].cpu().numpy(), j_exp), op
+    say(f"{n} pairs x 4 ops materialised: counts, fingerprints and Jaccard match the oracle")
+
+    def step():
+        for op in OPS4:
+            rg.batch(ctx, op, P, P, tia, tib, materialize=True, card=True, jaccard=True, out=arenas[op])
+
+    dt = time_steps(step, args.steps, args.warmup)
+    rg.profile_enable(ctx, True)
+    rg.profile_reset(ctx)
+    dt_prof = time_steps(step, args.steps, 0)
+    prof = rg.profile_read(ctx)
+    rg.profile_enable(ctx, False)
+
+    st = pair_stats(h, ia, ib)
+    in_bytes = {op: float(op_input_bytes(st, op).sum()) for op in OPS4}
+    out_pay = {op: result_payload_bytes(arenas[op]) for op in OPS4}
+    out_bytes = {op: out_pay[op][0] + META_BYTES * out_pay[op][1] for op in OPS4}
+    step_in = sum(in_bytes.values())
+    matched = int(st["matched"].sum())
+    # roofline: k_kw_eval reads the containers of every result key and writes the result
+    kw = prof.get(("kway-eval", True))
+    roof = None
+    if kw and kw["launches"]:
+        kw_bytes = sum(float((st["payA"] + st["payB"]).sum()) for op in ("or", "xor")) + \
+            float((st["payA"] + st["payBm"]).sum()) + sum(out_pay[op][0] for op in ("or", "xor", "andnot"))
+        kw_bytes *= args.steps
+        ach = kw_bytes / (kw["ms"] / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_kw_eval",
+                "mean_launch_ms": round(kw["ms"] / kw["launches"], 4), "launches": int(kw["launches"]),
+                "bytes_per_launch": int(kw_bytes / kw["launches"]),
+                "share_of_step": round(kw["ms"] / (dt_prof * 1e3 * args.steps), 3)}
+    kernels = {f"{k[0]}{'-mat' if k[1] else ''}": round(v["ms"] / args.steps, 4) for k, v in prof.items() if v["ms"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        nt = cpu_threads()
+        chunk = max(1, n // (4 * nt))
+
+        def task(op, s0):
+            s1 = min(n, s0 + chunk)
+            return lambda: oracle.pairs(op, bs.values, bs.offsets, bs.values, bs.offsets, ia[s0:s1], ib[s0:s1],
+                                        want_digest=True, want_jaccard=True)
+
+        tasks = [task(op, s0) for op in OPS4 for s0 in range(0, n, chunk)]
+        cpu = cpu_baseline_tasks(tasks, step_in, "GB/s",
+                                 f"all {n} pairs, 4 ops each materialised (sorted result list and its container-"
+                                 f"view fingerprint) with the count and Jaccard", args.cpu_seconds)
+
+    line = {
+        "metric": "input GB/s and container-pairs/sec for AND/OR/XOR/ANDNOT+card (% HBM peak)",
+        "value": round(step_in / dt / 1e9, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": dict(metric_config, workload=workload, parallelism="single GPU"),
+        "container_pairs_per_s": round(4 * matched / dt, 1),
+        "pairs_per_s": round(4 * n / dt, 1),
+        "input_bytes_per_op": {op: int(v) for op, v in in_bytes.items()},
+        "output_bytes_per_op": out_bytes,
+        "pct_hbm_peak": round(100 * (step_in + sum(out_bytes.values())) / dt / 1e9 / HBM_PEAK_GBS, 3),
+        "cache_resident": True,
+        "kernel_ms_per_step": kernels,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_mixed(args):
+    import synth
+
+    bs = synth.mixed_small()
+    ia, ib = synth.consecutive_pairs(len(bs))
+    say(f"mixed small: {len(bs)} bitmaps, {len(bs.values)} values, {len(ia)} successive pairs")
+    bench_pairs_materialised(args, bs, ia, ib,
+                             "mixed small: 100 bitmaps over [0, 2^26), 1e3..5e4 values, 40/30/30 sparse/dense/"
+                             "run, 99 successive pairs; AND/OR/XOR/ANDNOT materialised + counts + Jaccard",
+                             {"bitmaps": len(bs), "pairs": len(ia)})
+
+
+def bench_array(args):
+    import synth
+
+    bs, ia, ib = synth.array_stress(n_pairs=args.array_pairs)
+    say(f"array stress: {len(ia)} pairs, {len(bs.values)} values")
+    bench_pairs_materialised(args, bs, ia, ib,
+                             f"array stress: {len(ia)} pairs of sorted uint16 arrays, sizes Zipf(1.2) on "
+                             f"[1, 4096], ratio <= 1000; AND/OR/XOR/ANDNOT materialised + counts + Jaccard",
+                             {"pairs": len(ia)})
 
 
 def bench_dense_mat(args):
@@ -220,21 +518,14 @@ def bench_dense_mat(args):
         for p in range(2):
             exp = oracle.op(op, synth.dense_bitmap_values(int(ia[p]), nk), synth.dense_bitmap_values(int(ib[p]), nk))
             assert int(dig[p]) == oracle.digest(exp), (op, p)
-    print(f"# {nb} x {nk} bitsets, {npairs} pairs; 2 pairs x 4 ops match the oracle", file=sys.stderr, flush=True)
+    say(f"{nb} x {nk} bitsets, {npairs} pairs; 2 pairs x 4 ops match the oracle")
     out_bytes = {op: int(arenas[op].c.payload_used) for op in rg.OPS}
 
     def step():
         for op in rg.OPS:
             rg.batch(ctx, op, P, P, tia, tib, materialize=True, card=True, out=arenas[op])
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    dt = time_steps(step, args.steps, args.warmup)
     in_bytes = 4 * npairs * nk * 2 * 8192
     total = in_bytes + sum(out_bytes.values())
     line = {
@@ -251,13 +542,16 @@ def bench_dense_mat(args):
     print(json.dumps(line), flush=True)
 
 
+# ---------------------------------------------------------------- batched uneven pairs
+
 def bench_batched(args):
     """Many uneven pairs: |A n B| and Jaccard for every pair of a random pair list
     over a pool of mixed bitmaps (lognormal cardinality, median 1e4, sigma 2,
     clipped to [10, 1e7], over [0, 2^32), 40/30/30 sparse/dense/run with a
-    256-key hot set). Three executions of the same step, same results:
-    one library call per pair; one batched call (host-synchronised waves);
-    a plan (persistent work-stealing kernel, autotuned, replayed as a hipGraph)."""
+    256-key hot set). Executions of the same step, same results: one library
+    call per pair; one batched call (asynchronous, fused match-and-count
+    kernel); a plan (persistent work-stealing kernel, autotuned, replayed as a
+    hipGraph), with heuristic and with learned dispatch."""
     import numpy as np
     import torch
 
@@ -271,62 +565,53 @@ def bench_batched(args):
     t0 = time.time()
     hot = synth.hot_keys(seed, 256, 1 << 16)
     cards = [synth.lognormal_card(i, 1e4, 2.0, 10, 10 ** 7, seed) for i in range(args.pool)]
-    sets = []
-    for i in range(args.pool):
-        sets.append(synth.mixed_bitmap(seed, i, cards[i], 32, hot))
-        if (i + 1) % 4096 == 0:
-            print(f"# generated {i + 1} of {args.pool} bitmaps, {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
-    bs = synth.BitmapSet.from_list(sets)
-    del sets
-    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    bs = build_sets_threaded(lambda i: synth.mixed_bitmap(seed, i, cards[i], 32, hot), args.pool)
+    h = rg.Pool.host_arrays(bs.values, bs.offsets)[3]
+    P = rg.Pool.from_host_arrays(h)
     ia, ib = synth.random_pairs(args.pool, args.batched_pairs, seed)
     n = len(ia)
     tia = torch.from_numpy(ia.view(np.int32)).to(dev)
     tib = torch.from_numpy(ib.view(np.int32)).to(dev)
     torch.cuda.synchronize()
-    print(f"# pool of {args.pool} bitmaps, {len(bs.values)} values, {P.c.n_containers} containers, "
-          f"{n} pairs, built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    say(f"pool of {args.pool} bitmaps, {len(bs.values)} values, {P.c.n_containers} containers, "
+        f"{n} pairs, built in {time.time() - t0:.1f} s")
 
-    # eager batched call; also gives the matched container pairs (profile items)
-    rg.profile_enable(ctx, True)
-    rg.profile_reset(ctx)
+    # eager batched call (asynchronous: one fused match-and-count kernel)
     _, c_e, j_e = rg.batch(ctx, "and", P, P, tia, tib, materialize=False, card=True, jaccard=True)
     torch.cuda.synchronize()
-    matched = sum(v["items"] for v in rg.profile_read(ctx).values())
-    rg.profile_enable(ctx, False)
+    ctx.sync()
     c_e, j_e = c_e.cpu().numpy().view(np.uint64), j_e.cpu().numpy()
     for p in range(0, n, max(1, n // 16)):
         a, b = bs[int(ia[p])], bs[int(ib[p])]
         assert int(c_e[p]) == oracle.count("and", a, b) and j_e[p] == oracle.jaccard(a, b), p
-    print(f"# 16 sampled pairs match the oracle; {matched} matched container pairs per step",
-          file=sys.stderr, flush=True)
+    say("16 sampled pairs match the oracle")
 
-    def timed(fn, steps, warm):
-        for _ in range(warm):
-            fn()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(steps):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t) / steps
-
-    eager_s = timed(lambda: rg.batch(ctx, "and", P, P, tia, tib, materialize=False, card=True, jaccard=True),
-                    args.steps, 1)
-    print(f"# eager batched: {eager_s * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+    eager_s = time_steps(lambda: rg.batch(ctx, "and", P, P, tia, tib, materialize=False, card=True, jaccard=True),
+                         args.steps, 1)
+    # the same calls timed per kernel: the fused kernel's launch time, and the
+    # matched container pairs it counts while timed (its profile items)
+    rg.profile_enable(ctx, True)
+    rg.profile_reset(ctx)
+    time_steps(lambda: rg.batch(ctx, "and", P, P, tia, tib, materialize=False, card=True, jaccard=True),
+               args.steps, 0)
+    prof = rg.profile_read(ctx)
+    rg.profile_enable(ctx, False)
+    kf = prof.get(("count-fused", False), {"ms": 0, "launches": 0, "items": 0})
+    matched = int(kf["items"]) // max(1, int(kf["launches"]))
+    say(f"eager batched: {eager_s * 1e3:.2f} ms/step; {matched} matched container pairs per step")
     # the same eager call on a pool that carries packed metadata records
     # (rg_pool_pack_meta); the plans below reuse them
     t_p = time.perf_counter()
     P.pack_meta(ctx)
     torch.cuda.synchronize()
     pack_s = time.perf_counter() - t_p
-    eager_packed_s = timed(lambda: rg.batch(ctx, "and", P, P, tia, tib, materialize=False, card=True, jaccard=True),
-                           args.steps, 1)
+    eager_packed_s = time_steps(lambda: rg.batch(ctx, "and", P, P, tia, tib, materialize=False, card=True,
+                                                 jaccard=True), args.steps, 1)
     _, c_p, j_p = rg.batch(ctx, "and", P, P, tia, tib, materialize=False, card=True, jaccard=True)
     torch.cuda.synchronize()
     assert np.array_equal(c_p.cpu().numpy().view(np.uint64), c_e) and np.array_equal(j_p.cpu().numpy(), j_e)
-    print(f"# eager batched, packed metadata: {eager_packed_s * 1e3:.2f} ms/step (packing once: "
-          f"{pack_s * 1e3:.1f} ms), results equal", file=sys.stderr, flush=True)
+    say(f"eager batched, packed metadata: {eager_packed_s * 1e3:.2f} ms/step (packing once: {pack_s * 1e3:.1f} ms), "
+        f"results equal")
 
     # plan: tuned, captured, replayed on a side stream
     st = torch.cuda.Stream()
@@ -334,16 +619,11 @@ def bench_batched(args):
     pl.tune(stream=st, reps=1)
     pl.capture(st)
     torch.cuda.synchronize()
-
-    def run_plan():
-        pl.execute(stream=st)
-
-    plan_s = timed(run_plan, args.steps, args.warmup)
+    plan_s = time_steps(lambda: pl.execute(stream=st), args.steps, args.warmup)
     assert np.array_equal(pl.cards.cpu().numpy().view(np.uint64), c_e)
     assert np.array_equal(pl.jacc.cpu().numpy(), j_e)
     info = pl.info()
-    print(f"# plan (graph, {info}): {plan_s * 1e3:.2f} ms/step, results equal to the eager call",
-          file=sys.stderr, flush=True)
+    say(f"plan (graph, {info}): {plan_s * 1e3:.2f} ms/step, results equal to the eager call")
 
     # learned dispatch: cost samples measured by the kernels on a subset of the
     # pairs, the network trained on the GPU, installed, and a new plan timed
@@ -359,20 +639,19 @@ def bench_batched(args):
     params, losses = rg.dispatch_train(ctx, X, T, M, epochs=args.dispatch_epochs, batch=4096, lr=2e-3, seed=11)
     rg.dispatch_set_mlp(ctx, params)
     losses = losses.cpu().numpy()
-    print(f"# dispatcher: {int(M.any(1).sum())} sampled container pairs, loss {losses[0]:.3f} -> {losses[-1]:.3f}, "
-          f"{time.perf_counter() - t_s:.1f} s", file=sys.stderr, flush=True)
+    say(f"dispatcher: {int(M.any(1).sum())} sampled container pairs, loss {losses[0]:.3f} -> {losses[-1]:.3f}, "
+        f"{time.perf_counter() - t_s:.1f} s")
     pl2 = rg.Plan(ctx, "and", P, P, tia, tib, card=True, jaccard=True, stream=st)
     pl2.tune(stream=st, reps=1)
     pl2.capture(st)
     torch.cuda.synchronize()
-    learned_s = timed(lambda: pl2.execute(stream=st), args.steps, args.warmup)
+    learned_s = time_steps(lambda: pl2.execute(stream=st), args.steps, args.warmup)
     assert np.array_equal(pl2.cards.cpu().numpy().view(np.uint64), c_e)
     assert np.array_equal(pl2.jacc.cpu().numpy(), j_e)
     info2 = pl2.info()
     pl2.close()
     ctx.set_dispatch(rg.RG_DISPATCH_HEURISTIC)
-    print(f"# plan with learned dispatch ({info2}): {learned_s * 1e3:.2f} ms/step, results equal",
-          file=sys.stderr, flush=True)
+    say(f"plan with learned dispatch ({info2}): {learned_s * 1e3:.2f} ms/step, results equal")
 
     # one call per pair, on a sample
     k = min(args.per_pair_sample, n)
@@ -384,10 +663,37 @@ def bench_batched(args):
         for p in range(k):
             ctx.check(rg.roaring_batch(ctx, "and", P, P, tia[p:p + 1], tib[p:p + 1], flags, None, one_c, one_j))
 
-    pp_s = timed(per_pair, 1, 0) / k * n
-    print(f"# one call per pair: {pp_s / n * 1e6:.1f} us/pair on {k} pairs -> {pp_s * 1e3:.1f} ms/step",
-          file=sys.stderr, flush=True)
+    pp_s = time_steps(per_pair, 1, 0) / k * n
+    say(f"one call per pair: {pp_s / n * 1e6:.1f} us/pair on {k} pairs -> {pp_s * 1e3:.1f} ms/step")
     pl.close()
+
+    # roofline: the eager call's fused match-and-count kernel; algorithmic bytes
+    # per launch = bytes per matched container pair (payloads of both containers,
+    # 19 B metadata per container of both bitmaps, averaged over a sample of the
+    # pairs) x the matched container pairs of the launch
+    samp = np.random.default_rng(7).choice(n, size=min(4000, n), replace=False)
+    stt = pair_stats(h, ia[samp], ib[samp])
+    per_matched = float(op_input_bytes(stt, "and").sum()) / max(1, int(stt["matched"].sum()))
+    roof = None
+    if kf["launches"]:
+        alg = per_matched * matched
+        mean_s = kf["ms"] / kf["launches"] / 1e3
+        roof = {"bound": "hbm", "achieved": round(alg / mean_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(alg / mean_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_count_fused (eager batched call)", "mean_launch_ms": round(mean_s * 1e3, 3),
+                "launches": int(kf["launches"]), "bytes_per_launch": int(alg),
+                "bytes_per_matched_pair": round(per_matched, 1),
+                "bytes_per_matched_pair_sample": f"{len(samp)} random pairs"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        m = min(len(samp), 4000)
+        sa, sb = ia[samp[:m]], ib[samp[:m]]
+        nt = cpu_threads()
+        chunk = max(1, m // (4 * nt))
+        tasks = [(lambda s0=s0: oracle.pairs("and", bs.values, bs.offsets, bs.values, bs.offsets, sa[s0:s0 + chunk],
+                                             sb[s0:s0 + chunk], want_jaccard=True)) for s0 in range(0, m, chunk)]
+        cpu = cpu_baseline_tasks(tasks, float(stt["matched"][:m].sum()), "container-pairs/s",
+                                 f"{m} random pairs of the step, |A n B| + Jaccard each", args.cpu_seconds)
 
     line = {
         "metric": "container-pairs/sec, batched count + Jaccard over uneven pairs",
@@ -409,9 +715,54 @@ def bench_batched(args):
         "plan_learned": info2,
         "speedup_learned_vs_heuristic": round(plan_s / learned_s, 3),
         "dispatcher_loss": [round(float(losses[0]), 4), round(float(losses[-1]), 4)],
+        "roofline": roof,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
+
+def build_sets_threaded(gen, n):
+    """BitmapSet of gen(0) .. gen(n - 1), generated by a thread pool (the
+    generator's C calls release Python's lock)."""
+    import synth
+
+    t0 = time.time()
+    with ThreadPoolExecutor(cpu_threads()) as ex:
+        lists = list(ex.map(gen, range(n), chunksize=64))
+    say(f"generated {n} bitmaps in {time.time() - t0:.1f} s")
+    return synth.BitmapSet.from_list(lists)
+
+
+def build_pool_threaded(gen, n, chunk=2000):
+    """Host pool arrays of bitmaps gen(0) .. gen(n - 1), built chunk by chunk
+    in a thread pool and joined (offsets shifted), so the values of all
+    bitmaps never have to be held at once."""
+    import numpy as np
+
+    import paper_1709_07821_amd as rg
+    import synth
+
+    def part(c0):
+        bs = synth.BitmapSet.from_list([gen(i) for i in range(c0, min(n, c0 + chunk))])
+        return rg.Pool.host_arrays(bs.values, bs.offsets)[3]
+
+    t0 = time.time()
+    with ThreadPoolExecutor(cpu_threads()) as ex:
+        parts = list(ex.map(part, range(0, n, chunk)))
+    say(f"generated and built {n} bitmaps in {len(parts)} chunks, {time.time() - t0:.1f} s")
+    c_base = np.cumsum([0] + [len(p["keys"]) for p in parts])
+    p_base = np.cumsum([0] + [len(p["payload"]) for p in parts])
+    out = {"bm_begin": np.concatenate([p["bm_begin"][:-1] + np.uint64(c_base[i]) for i, p in enumerate(parts)] +
+                                      [np.array([c_base[-1]], np.uint64)]),
+           "off": np.concatenate([p["off"] + np.uint64(p_base[i]) for i, p in enumerate(parts)])}
+    for k in ("keys", "types", "card", "size", "payload", "bm_card", "bm_wbytes"):
+        out[k] = np.concatenate([p[k] for p in parts])
+        for p in parts:
+            p[k] = None
+    return out
+
+
+# ---------------------------------------------------------------- serving
 
 def bench_serve(args):
     """k-way AND/OR queries over a device-resident index under open-loop Poisson
@@ -433,11 +784,16 @@ def bench_serve(args):
     t0 = time.time()
     hot = synth.hot_keys(seed, 32, 1 << 10)
     cards = [synth.lognormal_card(i, 5e4, 1.0, 1000, 10 ** 6, seed) for i in range(args.index)]
-    bs = synth.BitmapSet.from_list([synth.mixed_bitmap(seed, i, cards[i], 26, hot) for i in range(args.index)])
-    P = rg.Pool.from_sets(bs.values, bs.offsets)
+
+    def gen(i):
+        return synth.mixed_bitmap(seed, i, cards[i], 26, hot)
+
+    h = build_pool_threaded(gen, args.index)
+    P = rg.Pool.from_host_arrays(h)
     torch.cuda.synchronize()
-    print(f"# index of {args.index} bitmaps, {len(bs.values)} values, {P.c.n_containers} containers, "
-          f"built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    n_values = int(h["bm_card"].sum())
+    say(f"index of {args.index} bitmaps, {n_values} values, {P.c.n_containers} containers, "
+        f"{len(h['payload']) / 1e9:.1f} GB payload, built in {time.time() - t0:.1f} s")
     rng = np.random.default_rng(seed)
 
     def make_queries(n):
@@ -454,15 +810,15 @@ def bench_serve(args):
                 qs.append(("and" if u < 0.9 else "or", ids, False))
         return qs
 
-    # correctness gate: a sample against the oracle
+    # correctness gate: a sample against the oracle (bitmaps regenerated on the host)
     sample = make_queries(12)
     srv = rg.Server(ctx, P, arena_bytes=4 << 30, max_batch=args.max_batch, max_inflight=2)
     _, c_s, d_s = srv.replay(sample, np.zeros(len(sample), np.uint64))
     srv.stop()
     for i, (op, ids, mat) in enumerate(sample):
-        e = oracle.kway(op, [bs[int(j)] for j in ids])
+        e = oracle.kway(op, [gen(int(j)) for j in ids])
         assert c_s[i] == len(e) and d_s[i] == (oracle.digest(e) if mat else 0), i
-    print("# 12 sampled queries match the oracle", file=sys.stderr, flush=True)
+    say("12 sampled queries match the oracle")
 
     rows = []
     for lam in [float(x) for x in args.rates.split(",")]:
@@ -484,9 +840,14 @@ def bench_serve(args):
             row[mode] = {"achieved_qps": round(n / wall, 1), "p50_us": round(float(np.percentile(lat, 50)) / 1e3, 1),
                          "p99_us": round(float(np.percentile(lat, 99)) / 1e3, 1),
                          "mean_batch": round(st["mean_batch"], 2), "steps": st["steps"]}
-            print(f"# rate {lam:.0f}/s {mode}: {row[mode]}", file=sys.stderr, flush=True)
+            say(f"rate {lam:.0f}/s {mode}: {row[mode]}")
         rows.append(row)
     best = max(r["batched"]["achieved_qps"] for r in rows)
+
+    # roofline of the evaluation kernel on queries of the same mix, one
+    # roaring_multi call each (k_kw_eval reads every container of each result
+    # key and writes the result): bytes from the host pool arrays
+    roof, cpu = serve_roofline_and_cpu(args, ctx, P, h, make_queries(64), gen)
     line = {
         "metric": "queries/sec and p50/p99 latency, k-way AND/OR serving (continuous batching)",
         "value": best, "unit": "queries/s", "n_gpus": 1, "steps": len(rows), "warmup": 0,
@@ -496,10 +857,63 @@ def bench_serve(args):
                                f"5e4, sigma 1), Poisson arrivals, 40% k-AND / 40% k-OR materialised, 20% "
                                f"count-only, k in 2..32", "index": args.index, "duration_s": args.duration,
                    "parallelism": "single GPU"},
+        "index_values": n_values, "index_containers": int(P.c.n_containers),
         "rates": rows,
+        "roofline": roof,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
+
+def serve_roofline_and_cpu(args, ctx, P, h, qs, gen):
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1709_07821_amd as rg
+
+    bb = h["bm_begin"].astype(np.int64)
+    keys = h["keys"]
+    pay = container_payload_bytes(h)
+    in_bytes = 0.0
+    out_bytes = 0
+    rg.profile_enable(ctx, True)
+    rg.profile_reset(ctx)
+    for op, ids, mat in qs:
+        lists = [keys[bb[b]:bb[b + 1]] for b in ids]
+        ks = lists[0]
+        for l in lists[1:]:
+            ks = np.intersect1d(ks, l) if op == "and" else np.union1d(ks, l)
+        for b, l in zip(ids, lists):
+            sel = np.isin(l, ks)
+            in_bytes += float(pay[bb[b]:bb[b + 1]][sel].sum())
+        d_ids = torch.from_numpy(np.ascontiguousarray(ids).view(np.int32)).cuda()
+        out, _ = rg.multi(ctx, op, P, d_ids, materialize=True, card=True)
+        out_bytes += result_payload_bytes(out)[0]
+    torch.cuda.synchronize()
+    kw = rg.profile_read(ctx).get(("kway-eval", True))
+    rg.profile_enable(ctx, False)
+    roof = None
+    if kw and kw["launches"]:
+        tot = in_bytes + out_bytes
+        ach = tot / (kw["ms"] / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_kw_eval (one roaring_multi call per query, materialised)",
+                "mean_launch_ms": round(kw["ms"] / kw["launches"], 4), "launches": int(kw["launches"]),
+                "bytes_per_launch": int(tot / kw["launches"]),
+                "sample": f"{len(qs)} queries of the mix, all materialised"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        sets = {int(b): gen(int(b)) for _, ids, _ in qs for b in ids}
+        tasks = [(lambda op=op, ids=ids: oracle.kway(op, [sets[int(b)] for b in ids])) for op, ids, _ in qs]
+        cpu = cpu_baseline_tasks(tasks, float(len(tasks)), "queries/s",
+                                 f"{len(tasks)} queries of the mix, k-way left fold of two-pointer merges",
+                                 args.cpu_seconds)
+    return roof, cpu
+
+
+# ---------------------------------------------------------------- HBM byte counters
 
 TRAFFIC_SOURCES = ("rg_match.hip", "rg_count_dev.h", "rg_finalize.h", "rg_internal.h")
 
@@ -529,30 +943,6 @@ def measured_traffic():
     if not tb or not hv:
         return None
     return int(tb[0]) if source_hash() == hv[0] else None
-
-
-def cpu_baseline(ia, ib, nk, n_pairs):
-    """The oracle, as it stands, on the first n_pairs pairs: 4 counts + Jaccard per pair."""
-    import oracle
-    import synth
-
-    n_pairs = min(n_pairs, len(ia))
-    sets = {}
-    for p in range(n_pairs):
-        for b in (int(ia[p]), int(ib[p])):
-            if b not in sets:
-                sets[b] = synth.dense_bitmap_values(b, nk)
-    t0 = time.perf_counter()
-    for p in range(n_pairs):
-        a, b = sets[int(ia[p])], sets[int(ib[p])]
-        for op in ("and", "or", "xor", "andnot"):
-            oracle.count(op, a, b)
-        oracle.jaccard(a, b)
-    dt = time.perf_counter() - t0
-    in_bytes = n_pairs * nk * 2 * (8192 + META_BYTES) * 4
-    return {"value": round(in_bytes / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_pairs} of the pairs, 4 count-only ops + Jaccard each (two-pointer merges over "
-                      f"sorted uint32), {dt:.1f} s"}
 
 
 if __name__ == "__main__":

@@ -351,8 +351,12 @@ rg_status rg_dispatch_table(rg_ctx *ctx, uint8_t *h_table, uint64_t cap);
  * container pairs processed for one variant (RG_V_* or 0 for the
  * bitset-bitset kernel, 8 for the bitset pairs redone
  * by the generic kernel, 9 for the small-array pairs of count-only calls that
- * key matching counts itself: items only, their time is part of key matching)
- * in count-only (materialize = 0) or materialising form. Synchronises on the
+ * key matching counts itself: items only, their time is part of key matching,
+ * 10 for the fused match-and-count kernel of count-only calls (items: matched
+ * container pairs, counted by the kernel while timing is on),
+ * 11 for the k-way evaluation of materialised unions, symmetric differences
+ * and differences (items: result slots)) in count-only (materialize = 0) or
+ * materialising form. Synchronises on the
  * recorded events; costs two events per launch. */
 rg_status rg_profile_enable(rg_ctx *ctx, int on);
 rg_status rg_profile_reset(rg_ctx *ctx);

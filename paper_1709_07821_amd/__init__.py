@@ -586,7 +586,7 @@ class Plan:
 
 
 PROFILE_CLASSES = {0: "bb", 1: "unused", 2: "generic", 3: "merge", 4: "gallop", 5: "probe", 6: "runmerge",
-                   7: "thread", 8: "bb-redo", 9: "thread-fused", 10: "count-fused"}
+                   7: "thread", 8: "bb-redo", 9: "thread-fused", 10: "count-fused", 11: "kway-eval"}
 
 
 def profile_enable(ctx: Context, on: bool = True):

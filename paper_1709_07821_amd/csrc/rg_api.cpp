@@ -37,36 +37,17 @@ rg_status static_scratch_init(int device, void** out) {
     return RG_OK;
 }
 
-hipEvent_t take_event(rg_ctx* c) {
-    if (!c->evpool.empty()) {
-        hipEvent_t e = c->evpool.back();
-        c->evpool.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-}
-
-// Launches `fn` on st; when profiling, brackets it with events on the same stream.
-template <class F>
-void timed(rg_ctx* c, int cls, bool mat, uint64_t items, hipStream_t st, F&& fn) {
-    if (!c->prof) {
-        fn();
-        return;
-    }
-    hipEvent_t a = take_event(c), b = take_event(c);
-    if (!a || !b) {
-        fn();
-        return;
-    }
-    (void)hipEventRecord(a, st);
-    fn();
-    (void)hipEventRecord(b, st);
-    c->pend.push_back({a, b, cls, mat ? 1 : 0, items});
-}
-
 rg_status drain_profile(rg_ctx* c) {
+    if (c->prof_fused_pending) {
+        // matched container pairs counted by timed fused launches (the context's
+        // device block; ordered after them on the device by the wait below)
+        uint64_t* h = static_cast<uint64_t*>(c->host);
+        HIPCHK(c, hipDeviceSynchronize());
+        HIPCHK(c, hipMemcpy(h, fused_matched_word(c), 8, hipMemcpyDeviceToHost));
+        c->prof_items[PROF_FUSED][0] += *h;
+        HIPCHK(c, hipMemset(fused_matched_word(c), 0, 8));
+        c->prof_fused_pending = false;
+    }
     for (auto& p : c->pend) {
         float ms = 0;
         HIPCHK(c, hipEventSynchronize(p.b));
@@ -209,8 +190,15 @@ rg_status run_count_async(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B,
     m.fuse_thread = true;
     m.acc = acc;
     const uint32_t grid = fused_grid(c, n_pairs);
-    if (fixed) launch_count_fused(m, next_blk, grid, st);
-    else timed(c, PROF_FUSED, false, n_pairs, st, [&] { launch_count_fused(m, next_blk, grid, st); });
+    if (fixed || !c->prof) {
+        launch_count_fused(m, next_blk, grid, st);
+    } else {
+        // timed: the kernel also counts the matched container pairs (the
+        // class's items, read when the timings are drained)
+        m.matched = fused_matched_word(c);
+        timed(c, PROF_FUSED, false, 0, st, [&] { launch_count_fused(m, next_blk, grid, st); });
+        c->prof_fused_pending = true;
+    }
     launch_finish_counts(RG_AND, op, acc, pa, pb, A->n_bitmaps, B->n_bitmaps, d_ia, d_ib, ia0, ib0, 0,
                          (uint32_t)n_pairs, (flags & RG_FLAG_CARD) ? d_cards : nullptr,
                          (flags & RG_FLAG_JACCARD) ? d_jacc : nullptr, st);
@@ -402,7 +390,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
             launch_kw_keys(ka, st);
             launch_kw_bounds(ka, st);
             launch_scan_u32_u64(ub, slot_off, C, pay_base, partials, totals, st);
-            timed(c, BIN_GEN, true, C, st, [&] { launch_kw_eval(ka, st); });
+            timed(c, PROF_KWEVAL, true, C, st, [&] { launch_kw_eval(ka, st); });
         } else {
             MatchArgs m;
             m.op = kop;

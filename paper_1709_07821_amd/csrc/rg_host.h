@@ -45,6 +45,7 @@ struct rg_ctx {
         uint64_t items;
     };
     bool prof = false;
+    bool prof_fused_pending = false;  // timed fused launches have counted into the device block
     std::vector<Pending> pend;
     std::vector<hipEvent_t> evpool;
     double prof_ms[NPROF][2] = {};
@@ -63,6 +64,36 @@ struct rg_ctx {
     const Task* cost_tasks = nullptr;
 };
 
+
+// Kernel timing (rg_profile_*): an event from the context's pool, or a new one.
+inline hipEvent_t take_event(rg_ctx* c) {
+    if (!c->evpool.empty()) {
+        hipEvent_t e = c->evpool.back();
+        c->evpool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launches `fn` on st; when profiling, brackets it with events on the same stream.
+template <class F>
+void timed(rg_ctx* c, int cls, bool mat, uint64_t items, hipStream_t st, F&& fn) {
+    if (!c->prof) {
+        fn();
+        return;
+    }
+    hipEvent_t a = take_event(c), b = take_event(c);
+    if (!a || !b) {
+        fn();
+        return;
+    }
+    (void)hipEventRecord(a, st);
+    fn();
+    (void)hipEventRecord(b, st);
+    c->pend.push_back({a, b, cls, mat ? 1 : 0, items});
+}
 
 inline rg_status fail(rg_ctx* c, rg_status s, const std::string& m) {
     if (c) c->err = m;
@@ -114,9 +145,15 @@ struct WorkspaceOrder {
 // The context's 4 KiB device block (c->small): bytes 0..767 the counters of
 // one materialising call (error word, bin counts and offsets, totals), 2048
 // rg_pool_validate's count, 3584 roaring_to_uint32's range (3 x u64), 3840
-// roaring_jaccard_host's result, u32 word 1020 the asynchronous error flag.
+// roaring_jaccard_host's result, 3616 the fused count kernel's matched
+// container pairs while timing is on, u32 word 1020 the asynchronous error flag.
 constexpr size_t SMALL_ASYNC_ERR = 1020;  // u32: sticky flag of asynchronous calls, cleared by rg_sync
 constexpr size_t SMALL_EXPORT_RANGE = 3584;  // bytes
+constexpr size_t SMALL_FUSED_MATCHED = 3616;  // bytes
+
+inline unsigned long long* fused_matched_word(rg_ctx* c) {
+    return reinterpret_cast<unsigned long long*>(static_cast<uint8_t*>(c->small) + SMALL_FUSED_MATCHED);
+}
 
 inline uint32_t* async_err_word(rg_ctx* c) { return reinterpret_cast<uint32_t*>(c->small) + SMALL_ASYNC_ERR; }
 

@@ -35,7 +35,8 @@ enum : uint8_t {
 };
 // profile classes beyond the bins
 constexpr int PROF_FUSED = 10;  // the fused match-and-count kernel of asynchronous count-only calls
-constexpr int NPROF = 11;
+constexpr int PROF_KWEVAL = 11; // k-way evaluation of materialised unions, differences, symmetric differences
+constexpr int NPROF = 12;
 
 struct Task {
     uint32_t pair;
@@ -224,6 +225,9 @@ struct MatchArgs {
     // no-op tasks; their number goes to bin BIN_FUSED of blk_cnt
     bool fuse_thread;
     long long* acc;
+    // k_count_fused with kernel timing on: matched container pairs are added
+    // here (one atomic per block); null otherwise
+    unsigned long long* matched = nullptr;
 };
 
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st);

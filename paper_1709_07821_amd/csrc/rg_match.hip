@@ -476,6 +476,15 @@ __global__ void __launch_bounds__(256) k_count_fused(MatchArgs m, uint32_t* next
         match_block(m, n_cand, (uint64_t)blk * MATCH_SLOTS, f.cnt, f.pl_range, f.lwin, f.u.lkeys, o);
 #pragma unroll
         for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) wave_aggregate_add(m.acc, o[k].fused_pair, o[k].fused_inter);
+        if (m.matched) {
+            // matched container pairs of the block: counted in place or listed below
+            uint32_t mk = 0;
+#pragma unroll
+            for (int k = 0; k < (int)MATCH_PER_THREAD; ++k)
+                mk += (o[k].task.kind == KIND_MATCH || o[k].fused_pair != NONE) ? 1u : 0u;
+            mk = wave_sum_u32(mk);
+            if (lane == 0 && mk) atomicAdd(m.matched, (unsigned long long)mk);
+        }
 #pragma unroll
         for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
             if (o[k].task.kind != KIND_MATCH) continue;

@@ -163,8 +163,10 @@ StepOut own_out(const StepLayout& L, uint8_t* d) {
 // Enqueues one step. h_stage: pinned host memory of L.down_off + L.down_bytes
 // bytes whose upload section is filled; the download section receives the
 // results once the stream reaches the end of the step.
+// prof: the context whose kernel timing brackets the evaluation kernel
+// (roaring_multi), or null (the server, which never touches the context).
 rg_status step_enqueue(std::string* err_out, const rg_pool& pool, const StepLayout& L, uint8_t* d, const StepOut& o,
-                       uint8_t* h_stage, hipStream_t st) {
+                       uint8_t* h_stage, hipStream_t st, rg_ctx* prof = nullptr) {
     auto* queries = reinterpret_cast<KwQuery*>(d + L.o_queries);
     auto* ids = reinterpret_cast<uint32_t*>(d + L.o_ids);
     auto* cand = reinterpret_cast<uint64_t*>(d + L.o_cand);
@@ -202,7 +204,8 @@ rg_status step_enqueue(std::string* err_out, const rg_pool& pool, const StepLayo
     launch_kw_keys(a, st);
     launch_kw_bounds(a, st);
     if (L.S) launch_scan_u32_u64(ub, slot_off, L.S, 0, partials, totals, st);
-    launch_kw_eval(a, st);
+    if (prof) timed(prof, PROF_KWEVAL, true, L.S, st, [&] { launch_kw_eval(a, st); });
+    else launch_kw_eval(a, st);
     if (L.S) {
         launch_scan_nonzero_u64(res_card, out_idx, L.S, 0, partials, totals + 1, st);
         CompactArgs cp;
@@ -302,7 +305,7 @@ extern "C" rg_status roaring_multi(rg_ctx* c, int op, const rg_pool* pool, const
     StepOut o = mat ? StepOut{out->bm_begin, out->keys, out->types, out->card, out->size, out->off, out->payload,
                               out->bm_card, out->bm_wbytes}
                     : own_out(L, d);
-    if (rg_status s = step_enqueue(&c->err, *pool, L, d, o, h, st)) return s;
+    if (rg_status s = step_enqueue(&c->err, *pool, L, d, o, h, st, c)) return s;
     HIPCHK(c, hipStreamSynchronize(st));
     const uint64_t* totals = reinterpret_cast<const uint64_t*>(h + L.o_totals);
     const uint32_t err = *reinterpret_cast<const uint32_t*>(h + L.o_err);
