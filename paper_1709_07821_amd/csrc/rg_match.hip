@@ -460,6 +460,7 @@ struct FusedShared {
 __global__ void __launch_bounds__(256) k_count_fused(MatchArgs m, uint32_t* next_blk) {
     __shared__ FusedShared f;
     const uint32_t lane = lane_id();
+    uint64_t matched = 0;  // m.matched: this thread's matched candidates
     const uint64_t n_cand = uniform64(m.cand_off[m.n_pairs]);
     const uint64_t nblk = (n_cand + MATCH_SLOTS - 1) / MATCH_SLOTS;
     for (;;) {
@@ -471,19 +472,23 @@ __global__ void __launch_bounds__(256) k_count_fused(MatchArgs m, uint32_t* next
         }
         __syncthreads();
         const uint32_t blk = uniform(f.blk);
-        if (blk >= nblk) break;  // the same value in every thread: the whole workgroup leaves
+        if (blk >= nblk) {  // the same value in every thread: the whole workgroup leaves
+            if (m.matched) {
+                const uint64_t t = wave_sum_u64(matched);
+                if (lane == 0 && t) atomicAdd(m.matched, (unsigned long long)t);
+            }
+            break;
+        }
         SlotOutcome o[MATCH_PER_THREAD];
         match_block(m, n_cand, (uint64_t)blk * MATCH_SLOTS, f.cnt, f.pl_range, f.lwin, f.u.lkeys, o);
 #pragma unroll
         for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) wave_aggregate_add(m.acc, o[k].fused_pair, o[k].fused_inter);
         if (m.matched) {
-            // matched container pairs of the block: counted in place or listed below
-            uint32_t mk = 0;
+            // matched container pairs of the block (counted in place or listed
+            // below), summed per thread; one atomic per wave when the kernel ends
 #pragma unroll
             for (int k = 0; k < (int)MATCH_PER_THREAD; ++k)
-                mk += (o[k].task.kind == KIND_MATCH || o[k].fused_pair != NONE) ? 1u : 0u;
-            mk = wave_sum_u32(mk);
-            if (lane == 0 && mk) atomicAdd(m.matched, (unsigned long long)mk);
+                matched += (o[k].task.kind == KIND_MATCH || o[k].fused_pair != NONE) ? 1u : 0u;
         }
 #pragma unroll
         for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
