@@ -55,7 +55,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target single-core oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", type=int, default=2, help="pairs checked against the oracle before timing")
-    ap.add_argument("--workload", choices=("dense", "mixed", "array", "dense-mat", "batched", "serve"),
+    ap.add_argument("--workload", choices=("dense", "mixed", "array", "dense-mat", "batched", "serve", "dispatch"),
                     default="dense",
                     help="dense: the bitset-bandwidth headline; mixed / array: the small mixed and array-stress "
                          "pairs, materialised; batched: many uneven pairs, plan vs per-pair; serve: k-way "
@@ -91,7 +91,7 @@ def main():
         print(f"# copied {src.numel() * 8} bytes device to device", file=sys.stderr, flush=True)
         return None
     fn = {"dense": bench_dense, "mixed": bench_mixed, "array": bench_array, "dense-mat": bench_dense_mat,
-          "batched": bench_batched, "serve": bench_serve}[args.workload]
+          "batched": bench_batched, "serve": bench_serve, "dispatch": bench_dispatch}[args.workload]
     return fn(args)
 
 
@@ -760,6 +760,107 @@ def build_pool_threaded(gen, n, chunk=2000):
         for p in parts:
             p[k] = None
     return out
+
+
+# ---------------------------------------------------------------- learned dispatch
+
+def dispatch_training_set(ctx):
+    """Cost samples measured by the kernels on training pools (seeds not used
+    for evaluation): array stress, mixed bitmaps, array-bitset pairs."""
+    import numpy as np
+    import torch
+
+    import paper_1709_07821_amd as rg
+    import synth
+
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+    parts = []
+    for bs, ia, ib in (synth.array_stress(n_pairs=20000, seed=555),
+                       (lambda m: (m, *synth.consecutive_pairs(len(m))))(synth.mixed_small(n_bitmaps=40, seed=556)),
+                       synth.uniform_size_pairs(3000, 557, (500, 4096), (4097, 30000))):
+        P = rg.Pool.from_sets(bs.values, bs.offsets)
+        parts.append(rg.dispatch_samples(ctx, P, P, t(ia), t(ib)))
+    return tuple(torch.cat([p[i] for p in parts]) for i in range(3))
+
+
+def dispatch_eval_sets():
+    """Held-out evaluation pairs: name -> (BitmapSet, ia, ib)."""
+    import synth
+
+    mx = synth.mixed_small(n_bitmaps=100)
+    return {"array stress (1e5 pairs, Zipf sizes)": synth.array_stress(n_pairs=100000),
+            "mid-size arrays (9..62 vs 9..300 values, 5e4 pairs)": synth.uniform_size_pairs(50000, 558, (9, 62),
+                                                                                              (9, 300)),
+            "array-bitset (500..4096 vs 4097..30000 values, 2e4 pairs)":
+                synth.uniform_size_pairs(20000, 559, (500, 4096), (4097, 30000)),
+            "mixed small (99 successive pairs)": (mx, *synth.consecutive_pairs(len(mx)))}
+
+
+def bench_dispatch(args):
+    """What the learned dispatcher gains over the size-ratio heuristic it
+    replaces, on held-out pairs: the network is trained on kernel-measured
+    costs of other pools, installed, and the count-only batched call (|A n B|
+    per pair) is timed with heuristic, learned and the best hand-tuned
+    heuristic thresholds (thread-size threshold x galloping ratio grid);
+    results are identical in every case."""
+    import numpy as np
+    import torch
+
+    import paper_1709_07821_amd as rg
+
+    ctx = rg.Context(0)
+    t0 = time.perf_counter()
+    X, T, M = dispatch_training_set(ctx)
+    params, losses = rg.dispatch_train(ctx, X, T, M, epochs=30, batch=4096, lr=2e-3, seed=11)
+    losses = losses.cpu().numpy()
+    say(f"dispatcher: {X.shape[0]} samples, per variant {M.sum(0).tolist()}, loss {losses[0]:.3f} -> "
+        f"{losses[-1]:.3f}, {time.perf_counter() - t0:.1f} s")
+    rows = {}
+    for name, (bs, ia, ib) in dispatch_eval_sets().items():
+        P = rg.Pool.from_sets(bs.values, bs.offsets)
+        a = torch.from_numpy(ia.view(np.int32)).cuda()
+        b = torch.from_numpy(ib.view(np.int32)).cuda()
+        cards = torch.zeros(len(ia), dtype=torch.int64, device="cuda")
+
+        def run():
+            ctx.check(rg.roaring_batch(ctx, "and", P, P, a, b, rg.RG_FLAG_CARD, None, cards, None))
+
+        ctx.set_dispatch(rg.RG_DISPATCH_HEURISTIC)
+        ctx.set_thresholds(64, 8)
+        heur = time_steps(run, 10, 2)
+        ref = cards.clone()
+        best, best_set = heur, (64, 8)
+        for tm in (0, 4, 16, 32, 62):
+            for gr in (8, 16, 64, 256):
+                ctx.set_thresholds(gr, tm)
+                ms = time_steps(run, 10, 1)
+                assert torch.equal(cards, ref)
+                if ms < best:
+                    best, best_set = ms, (gr, tm)
+        ctx.set_thresholds(64, 8)
+        rg.dispatch_set_mlp(ctx, params)
+        learned = time_steps(run, 10, 2)
+        assert torch.equal(cards, ref), name
+        ctx.set_dispatch(rg.RG_DISPATCH_HEURISTIC)
+        rows[name] = {"pairs": len(ia), "heuristic_ms": round(heur * 1e3, 4), "learned_ms": round(learned * 1e3, 4),
+                      "tuned_heuristic_ms": round(best * 1e3, 4),
+                      "tuned_setting": {"gallop_ratio": best_set[0], "thread_max": best_set[1]},
+                      "gain_learned_vs_heuristic": round(heur / learned, 3),
+                      "learned_vs_tuned_heuristic": round(best / learned, 3)}
+        say(f"{name}: {rows[name]}")
+    first = next(iter(rows.values()))
+    line = {
+        "metric": "speedup of learned dispatch over the size-ratio heuristic, count-only batch, held-out pairs",
+        "value": first["gain_learned_vs_heuristic"], "unit": "x", "n_gpus": 1, "steps": 10, "warmup": 2,
+        "ms_per_step": first["learned_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "learned dispatch: 12-64-64-6 network trained on kernel-measured costs of array-"
+                               "stress, mixed and array-bitset pools (other seeds), evaluated on held-out pairs",
+                   "parallelism": "single GPU"},
+        "training_samples": int(X.shape[0]), "loss": [round(float(losses[0]), 3), round(float(losses[-1]), 3)],
+        "workloads": rows,
+    }
+    print(json.dumps(line), flush=True)
 
 
 # ---------------------------------------------------------------- serving

@@ -172,6 +172,25 @@ def array_stress(n_pairs: int = 100_000, seed: int = SEED_BASE + 1, s: float = 1
     return BitmapSet(vals, offs), ia, ia + 1
 
 
+def uniform_size_pairs(n_pairs: int, seed: int, a_range, b_range) -> tuple[BitmapSet, np.ndarray, np.ndarray]:
+    """Pairs of one-container bitmaps (key 0) with sizes uniform on the given
+    inclusive ranges (sizes above 4096 give bitset containers); bitmap 2p is
+    A_p, bitmap 2p+1 is B_p; values distinct uniform uint16, sorted."""
+    L = _load()
+    sizes = np.empty(2 * n_pairs, dtype=np.uint64)
+    for i in range(2 * n_pairs):
+        lo, hi = a_range if i % 2 == 0 else b_range
+        sizes[i] = lo + rand(seed, 1 << 44, i) % (hi - lo + 1)
+    offs = np.zeros(2 * n_pairs + 1, dtype=np.uint64)
+    np.cumsum(sizes, out=offs[1:])
+    vals = np.zeros(int(offs[-1]), dtype=np.uint32)
+    base = vals.ctypes.data
+    for i in range(2 * n_pairs):
+        L.synth_distinct_u16(seed, (1 << 45) + i, int(sizes[i]), 0, ctypes.cast(base + 4 * int(offs[i]), _u32p))
+    ia = np.arange(0, 2 * n_pairs, 2, dtype=np.uint32)
+    return BitmapSet(vals, offs), ia, ia + 1
+
+
 def random_pairs(n: int, n_pairs: int, seed: int, stream: int = 1 << 41):
     ia = np.zeros(n_pairs, dtype=np.uint32)
     ib = np.zeros(n_pairs, dtype=np.uint32)
