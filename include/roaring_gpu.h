@@ -253,6 +253,31 @@ rg_status roaring_batch_static(rg_ctx *ctx, int op, const rg_pool *A, const rg_p
  * between executions as long as every pair's candidate count (number of keys
  * of its smaller bitmap) does not. */
 typedef struct rg_plan rg_plan;
+/* A materialising plan (Section 5.7: a new result bitmap for every pair):
+ * the same, with flags holding RG_FLAG_MATERIALIZE (plus optional
+ * RG_FLAG_CARD / RG_FLAG_JACCARD) and the results built into `out`, result
+ * bitmap p = pair p. Creation reads every pair's result bounds back once and
+ * fails with RG_ECAPACITY (out->needed_* filled) when the arena is smaller than
+ * their sum; each execution is then sync-free and graph-capturable: result
+ * keys, payload bounds, one workgroup per result key, scan and compaction of
+ * the non-empty results, every wave's arena offsets carried on the device.
+ * All four operations go through the k-way kernels (two bitmaps per query,
+ * as roaring_or does). After an execution has completed, the arena holds the
+ * results; rg_plan_result synchronises `stream` and reads the container count
+ * and the end of the last payload slot; rg_plan_totals gives the device
+ * address of the same two values (uint64 [payload end, containers]) for
+ * callers that stay on the device. The arena and pools must stay valid and
+ * unmoved for the plan's life. rg_plan_tune leaves materialising plans as
+ * they are (nothing to tune). */
+rg_status rg_plan_create_mat(rg_ctx *ctx, int op, const rg_pool *A, const rg_pool *B, const uint32_t *d_ia,
+                             const uint32_t *d_ib, uint64_t n_pairs, uint32_t flags, rg_out *out, uint64_t *d_cards,
+                             double *d_jacc, rg_plan **plan, void *stream);
+rg_status rg_plan_result(rg_plan *plan, uint64_t *n_containers, uint64_t *payload_used, void *stream);
+rg_status rg_plan_totals(const rg_plan *plan, const uint64_t **d_totals);
+/* Largest number of candidate slots per wave of a batched call or plan
+ * (default 2^24, at most 2^30): smaller waves need less workspace and more
+ * launches. A wave always holds whole pairs. Results never change. */
+rg_status rg_set_wave_slots(rg_ctx *ctx, uint64_t max_slots);
 rg_status rg_plan_create(rg_ctx *ctx, int op, const rg_pool *A, const rg_pool *B, const uint32_t *d_ia,
                          const uint32_t *d_ib, uint64_t n_pairs, uint32_t flags, uint64_t *d_cards, double *d_jacc,
                          rg_plan **plan, void *stream);

@@ -43,7 +43,8 @@ EXPORTS = ["rg_create", "rg_destroy", "rg_last_error", "rg_set_dispatch", "rg_se
            "rg_mlp_forward", "rg_mlp_grad", "rg_mlp_adam", "rg_dispatch_sample", "rg_dispatch_train",
            "rg_dispatch_set_mlp", "rg_dispatch_table", "rg_sync", "rg_set_workspace", "rg_workspace_size",
            "roaring_jaccard_host", "rg_pool_init_dense", "roaring_batch_static",
-           "roaring_contains", "roaring_to_uint32", "rg_pool_check", "rg_pool_canonicalize"]
+           "roaring_contains", "roaring_to_uint32", "rg_pool_check", "rg_pool_canonicalize",
+           "rg_plan_create_mat", "rg_plan_result", "rg_plan_totals", "rg_set_wave_slots"]
 
 
 class RoaringError(RuntimeError):
@@ -151,6 +152,10 @@ def lib():
         L.roaring_contains.argtypes = [V, pool_p, V, V, U64, V, V]
         L.rg_pool_check.argtypes = [V, pool_p, U32, P(U64), V]
         L.rg_pool_canonicalize.argtypes = [V, pool_p, out_p, V]
+        L.rg_plan_create_mat.argtypes = [V, I, pool_p, pool_p, V, V, U64, U32, out_p, V, V, P(V), V]
+        L.rg_plan_result.argtypes = [V, P(U64), P(U64), V]
+        L.rg_plan_totals.argtypes = [V, P(V)]
+        L.rg_set_wave_slots.argtypes = [V, U64]
         L.roaring_to_uint32.argtypes = [V, pool_p, U32, U32, V, V, U64, P(U64), V]
         for nm in EXPORTS:
             if nm not in ("rg_destroy", "rg_last_error", "rg_plan_destroy"):
@@ -219,6 +224,10 @@ class Context:
     def sync(self, stream=None):
         """rg_sync: waits for the stream; raises what asynchronous calls found on the device."""
         self.check(lib().rg_sync(self.h, _stream(stream)))
+
+    def set_wave_slots(self, n: int):
+        """rg_set_wave_slots: most candidate slots per wave (results never change)."""
+        self.check(lib().rg_set_wave_slots(self.h, n))
 
     def set_workspace(self, buf=None):
         """rg_set_workspace over a device tensor (256-byte aligned; None: the context's own).
@@ -509,10 +518,13 @@ def rg_pool_digest(ctx: Context, pool: Pool, stream=None):
 
 
 class Plan:
-    """rg_plan: batched count-only execution, sync-free, graph-capturable, tunable.
+    """rg_plan: batched execution, sync-free, graph-capturable, tunable (count-only);
+    materialize=True makes a materialising plan (rg_plan_create_mat) whose results
+    land in self.out (an OutArena sized from the library's report).
     Keeps references to the pools, pair tensors and outputs it was made with."""
 
-    def __init__(self, ctx: Context, op, A: Pool, B: Pool, ia, ib, card=True, jaccard=False, stream=None):
+    def __init__(self, ctx: Context, op, A: Pool, B: Pool, ia, ib, card=True, jaccard=False, stream=None,
+                 materialize=False):
         torch = _torch()
         dev = A.bm_begin.device
         n = int(ia.numel())
@@ -523,9 +535,33 @@ class Plan:
         flags = (RG_FLAG_CARD if card else 0) | (RG_FLAG_JACCARD if jaccard else 0)
         h = ctypes.c_void_p()
         op = OPS[op] if isinstance(op, str) else op
-        ctx.check(lib().rg_plan_create(ctx.h, op, ctypes.byref(A.c), ctypes.byref(B.c), _ptr(ia), _ptr(ib), n, flags,
-                                       _ptr(self.cards), _ptr(self.jacc), ctypes.byref(h), _stream(stream)))
+        self.out = None
+        if materialize:
+            flags |= RG_FLAG_MATERIALIZE
+            out = OutArena(n, 0, 0, dev)
+            out.c.cap_containers = 0
+            out.c.cap_payload_bytes = 0
+            args = lambda o: (ctx.h, op, ctypes.byref(A.c), ctypes.byref(B.c), _ptr(ia), _ptr(ib), n, flags,
+                              ctypes.byref(o.c), _ptr(self.cards), _ptr(self.jacc), ctypes.byref(h), _stream(stream))
+            st = lib().rg_plan_create_mat(*args(out))
+            if st == RG_ECAPACITY:
+                out = OutArena(n, out.c.needed_containers, out.c.needed_payload_bytes, dev)
+                st = lib().rg_plan_create_mat(*args(out))
+            ctx.check(st)
+            self.out = out
+        else:
+            ctx.check(lib().rg_plan_create(ctx.h, op, ctypes.byref(A.c), ctypes.byref(B.c), _ptr(ia), _ptr(ib), n,
+                                           flags, _ptr(self.cards), _ptr(self.jacc), ctypes.byref(h),
+                                           _stream(stream)))
         self.h = h
+
+    def result(self, stream=None) -> Pool:
+        """rg_plan_result (synchronises): the materialised results as a Pool view of self.out."""
+        nc, pu = ctypes.c_uint64(), ctypes.c_uint64()
+        self.ctx.check(lib().rg_plan_result(self.h, ctypes.byref(nc), ctypes.byref(pu), _stream(stream)))
+        self.out.c.n_containers = nc.value
+        self.out.c.payload_used = pu.value
+        return self.out.as_pool()
 
     def execute(self, stream=None):
         self.ctx.check(lib().rg_plan_execute(self.h, _stream(stream)))

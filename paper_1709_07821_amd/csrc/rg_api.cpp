@@ -914,11 +914,28 @@ struct rg_plan {
     void* meta_mem = nullptr;
     const u32x4* metaA = nullptr;
     const u32x4* metaB = nullptr;
+    // materialising plans: results into `out` through the k-way kernels (two
+    // bitmaps per query), with the arena offsets carried from wave to wave on
+    // the device (totals[0] payload end, totals[1] containers written)
+    bool mat = false;
+    rg_out out{};
+    uint64_t* totals = nullptr;
+    uint32_t* ub = nullptr;
+    uint64_t* slot_off = nullptr;
+    uint8_t* res_type = nullptr;
+    uint32_t* res_size = nullptr;
+    uint64_t* out_idx = nullptr;
+    uint64_t* partials = nullptr;
+    KwQuery* kw_queries = nullptr;
+    uint32_t* kw_ids = nullptr;
 };
 
 namespace {
 
+void plan_enqueue_mat(rg_plan* p, hipStream_t st);
+
 void plan_enqueue(rg_plan* p, hipStream_t st) {
+    if (p->mat) return plan_enqueue_mat(p, st);
     PoolView pa = view(p->A), pb = view(p->B);
     pa.meta = p->metaA;  // the plan's records (its own, or the pools' when they carry them)
     pb.meta = p->metaB;
@@ -964,6 +981,70 @@ void plan_enqueue(rg_plan* p, hipStream_t st) {
                          (uint32_t)p->n_pairs,
                          (p->flags & RG_FLAG_CARD) ? p->d_cards : nullptr,
                          (p->flags & RG_FLAG_JACCARD) ? p->d_jacc : nullptr, st);
+}
+
+// Materialising plan: every wave through the k-way kernels, no host readback.
+void plan_enqueue_mat(rg_plan* p, hipStream_t st) {
+    const rg_out& o = p->out;
+    PoolView pa = view(p->A), pb = view(p->B);
+    launch_fill_u32(p->err, 0, 1, st);
+    launch_fill_u64(p->totals, 0, 2, st);
+    launch_fill_u64(o.bm_card, 0, p->n_pairs, st);
+    if (o.bm_wbytes) launch_fill_u64(o.bm_wbytes, 0, p->n_pairs, st);
+    const size_t nw = p->waves.size();
+    for (size_t w = 0; w < nw; ++w) {
+        const auto& wv = p->waves[w];
+        const bool last = w + 1 == nw;
+        if (!wv.C) {
+            launch_bm_begin(wv.cand_off, p->out_idx, 0, p->totals + 1, wv.np, wv.p0, o.bm_begin, last, st);
+            continue;
+        }
+        launch_kw_pair_queries(p->op, p->d_ia, p->d_ib, 0, 0, wv.p0, wv.np, wv.cand_off, p->kw_queries, p->kw_ids,
+                               st);
+        KwArgs ka;
+        ka.P0 = pa;
+        ka.P1 = pb;
+        ka.pair_base = (uint32_t)wv.p0;
+        ka.queries = p->kw_queries;
+        ka.n_queries = wv.np;
+        ka.ids = p->kw_ids;
+        ka.tasks = p->tasks;
+        ka.n_slots = wv.C;
+        ka.ub = p->ub;
+        ka.res_card = p->res_card;
+        ka.so = SlotOut{p->slot_off, o.payload, p->res_card, p->res_type, p->res_size, nullptr, nullptr};
+        ka.acc = nullptr;
+        ka.err = p->err;
+        launch_kw_keys(ka, st);
+        launch_kw_bounds(ka, st);
+        // slot payload offsets continue from the previous wave's payload end
+        launch_scan_u32_u64(p->ub, p->slot_off, wv.C, 0, p->partials, p->totals, st, p->totals);
+        launch_kw_eval(ka, st);
+        // output indices continue from the previous wave's container count
+        launch_scan_nonzero_u64(p->res_card, p->out_idx, wv.C, 0, p->partials, p->totals + 1, st, p->totals + 1);
+        CompactArgs cp;
+        cp.tasks = p->tasks;
+        cp.n_slots = wv.C;
+        cp.res_card = p->res_card;
+        cp.res_type = p->res_type;
+        cp.res_size = p->res_size;
+        cp.slot_off = p->slot_off;
+        cp.out_idx = p->out_idx;
+        cp.keys = o.keys;
+        cp.types = o.types;
+        cp.card = o.card;
+        cp.size = o.size;
+        cp.off = o.off;
+        cp.bm_card = o.bm_card;
+        cp.bm_wbytes = o.bm_wbytes;
+        cp.pair0 = wv.p0;
+        launch_compact(cp, st);
+        launch_bm_begin(wv.cand_off, p->out_idx, wv.C, p->totals + 1, wv.np, wv.p0, o.bm_begin, last, st);
+    }
+    if (p->flags & (RG_FLAG_CARD | RG_FLAG_JACCARD))
+        launch_mat_counts(p->op, o.bm_card, pa, pb, p->d_ia, p->d_ib, 0, 0, p->n_pairs,
+                          (p->flags & RG_FLAG_CARD) ? p->d_cards : nullptr,
+                          (p->flags & RG_FLAG_JACCARD) ? p->d_jacc : nullptr, st);
 }
 
 void plan_drop_graph(rg_plan* p) {
@@ -1123,6 +1204,161 @@ rg_status rg_plan_create(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, 
     return RG_OK;
 }
 
+rg_status rg_plan_create_mat(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const uint32_t* d_ia,
+                             const uint32_t* d_ib, uint64_t n_pairs, uint32_t flags, rg_out* out, uint64_t* d_cards,
+                             double* d_jacc, rg_plan** out_plan, void* stream) {
+    if (!c) return RG_EINVAL;
+    if (!out_plan) return fail(c, RG_EINVAL, "null plan pointer");
+    *out_plan = nullptr;
+    if (op < RG_AND || op > RG_ANDNOT) return fail(c, RG_EINVAL, "op must be RG_AND..RG_ANDNOT");
+    if (!pool_ok(A) || !pool_ok(B)) return fail(c, RG_EINVAL, "incomplete pool (null pointer)");
+    if (!(flags & RG_FLAG_MATERIALIZE)) return fail(c, RG_EINVAL, "rg_plan_create_mat needs RG_FLAG_MATERIALIZE");
+    if ((flags & RG_FLAG_CARD) && !d_cards) return fail(c, RG_EINVAL, "RG_FLAG_CARD needs d_cards");
+    if ((flags & RG_FLAG_JACCARD) && !d_jacc) return fail(c, RG_EINVAL, "RG_FLAG_JACCARD needs d_jacc");
+    if (!out || !out->bm_begin || !out->keys || !out->types || !out->card || !out->size || !out->off ||
+        !out->payload || !out->bm_card)
+        return fail(c, RG_EINVAL, "materialisation needs a complete rg_out");
+    if (n_pairs == 0 || n_pairs > 0xFFFFFFFFull || !d_ia || !d_ib)
+        return fail(c, RG_EINVAL, "a plan needs 1..2^32-1 pairs and device pair arrays");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    out->needed_containers = out->needed_payload_bytes = out->n_containers = out->payload_used = 0;
+    // per pair: result slots, payload bound and container bound, read back once
+    std::vector<uint32_t> h_cand(n_pairs), h_minc(n_pairs);
+    std::vector<uint64_t> h_bound(n_pairs);
+    {
+        const size_t pb = align256(4 * n_pairs) + align256(8 * n_pairs) + align256(4 * n_pairs) +
+                          align256(8 * n_pairs) + 256;
+        void* tmp = nullptr;
+        if (hipMalloc(&tmp, pb) != hipSuccess) return fail(c, RG_EDEVICE, "hipMalloc failed");
+        Bump b{(uint8_t*)tmp};
+        uint32_t* nc = b.take<uint32_t>(n_pairs);
+        uint64_t* bd = b.take<uint64_t>(n_pairs);
+        uint32_t* mc = b.take<uint32_t>(n_pairs);
+        long long* ac = b.take<long long>(n_pairs);
+        uint32_t* er = b.take<uint32_t>(1);
+        launch_fill_u32(er, 0, 1, st);
+        launch_pair_prep(op, true, view(*A), view(*B), A->n_bitmaps, B->n_bitmaps, d_ia, d_ib, 0, 0, n_pairs, nc, bd,
+                         mc, ac, er, st);
+        uint32_t h_err = 0;
+        hipError_t e1 = hipMemcpyAsync(h_cand.data(), nc, 4 * n_pairs, hipMemcpyDeviceToHost, st);
+        hipError_t e2 = hipMemcpyAsync(h_bound.data(), bd, 8 * n_pairs, hipMemcpyDeviceToHost, st);
+        hipError_t e3 = hipMemcpyAsync(h_minc.data(), mc, 4 * n_pairs, hipMemcpyDeviceToHost, st);
+        hipError_t e4 = hipMemcpyAsync(&h_err, er, 4, hipMemcpyDeviceToHost, st);
+        hipError_t e5 = hipStreamSynchronize(st);
+        (void)hipFree(tmp);
+        if (e1 || e2 || e3 || e4 || e5) return fail(c, RG_EDEVICE, "plan preparation failed");
+        if (h_err) return fail(c, RG_EINVAL, "pair index out of range of its pool");
+    }
+    uint64_t tb = 0, tcont = 0;
+    for (uint64_t q = 0; q < n_pairs; ++q) {
+        tb += h_bound[q];
+        tcont += h_minc[q];
+    }
+    out->needed_payload_bytes = tb;
+    out->needed_containers = tcont;
+    if (out->cap_payload_bytes < tb || out->cap_containers < tcont)
+        return fail(c, RG_ECAPACITY, "output arena too small");
+    rg_plan* p = new rg_plan();
+    p->ctx = c;
+    p->op = op;
+    p->flags = flags;
+    p->A = *A;
+    p->B = *B;
+    p->d_ia = d_ia;
+    p->d_ib = d_ib;
+    p->n_pairs = n_pairs;
+    p->d_cards = d_cards;
+    p->d_jacc = d_jacc;
+    p->mat = true;
+    p->out = *out;
+    auto cleanup = [&](rg_status s) {
+        if (p->mem) (void)hipFree(p->mem);
+        delete p;
+        return s;
+    };
+    std::vector<uint64_t> starts{0};
+    uint64_t accs = 0, P_max = 0;
+    for (uint64_t q = 0; q < n_pairs; ++q) {
+        if (accs + h_cand[q] > c->max_wave_slots && accs > 0) {
+            p->S_max = std::max(p->S_max, accs);
+            P_max = std::max(P_max, q - starts.back());
+            starts.push_back(q);
+            accs = 0;
+        }
+        accs += h_cand[q];
+    }
+    p->S_max = std::max(p->S_max, accs);
+    P_max = std::max(P_max, n_pairs - starts.back());
+    starts.push_back(n_pairs);
+    size_t offs_bytes = 0;
+    for (size_t w = 0; w + 1 < starts.size(); ++w) offs_bytes += align256(8 * (starts[w + 1] - starts[w] + 1));
+    const uint64_t S = std::max<uint64_t>(p->S_max, 1);
+    size_t total = offs_bytes + 2 * 256;  // + err, totals
+    for (size_t x : {sizeof(Task) * S, 4 * S, 8 * S, 4 * S, 1 * S, 4 * S, 8 * S, 8 * scan_partials_needed(S),
+                     sizeof(KwQuery) * P_max, 8 * P_max})
+        total += align256(x);
+    if (hipMalloc(&p->mem, total) != hipSuccess) return cleanup(fail(c, RG_EDEVICE, "hipMalloc failed"));
+    Bump b{(uint8_t*)p->mem};
+    p->err = b.take<uint32_t>(1);
+    p->totals = b.take<uint64_t>(2);
+    p->tasks = b.take<Task>(S);
+    p->ub = b.take<uint32_t>(S);
+    p->slot_off = b.take<uint64_t>(S);
+    p->res_card = b.take<uint32_t>(S);
+    p->res_type = b.take<uint8_t>(S);
+    p->res_size = b.take<uint32_t>(S);
+    p->out_idx = b.take<uint64_t>(S);
+    p->partials = b.take<uint64_t>(scan_partials_needed(S));
+    p->kw_queries = b.take<KwQuery>(P_max);
+    p->kw_ids = b.take<uint32_t>(2 * P_max);
+    std::vector<uint64_t> h_off;
+    for (size_t w = 0; w + 1 < starts.size(); ++w) {
+        rg_plan::Wave wv;
+        wv.p0 = starts[w];
+        wv.np = (uint32_t)(starts[w + 1] - starts[w]);
+        h_off.assign(wv.np + 1, 0);
+        for (uint32_t q = 0; q < wv.np; ++q) h_off[q + 1] = h_off[q] + h_cand[wv.p0 + q];
+        wv.C = h_off[wv.np];
+        wv.cand_off = b.take<uint64_t>(wv.np + 1);
+        if (hipMemcpy(wv.cand_off, h_off.data(), 8 * (wv.np + 1), hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(c, RG_EDEVICE, "plan upload failed"));
+        p->waves.push_back(wv);
+    }
+    *out_plan = p;
+    return RG_OK;
+}
+
+rg_status rg_plan_result(rg_plan* p, uint64_t* n_containers, uint64_t* payload_used, void* stream) {
+    if (!p) return RG_EINVAL;
+    rg_ctx* c = p->ctx;
+    if (!p->mat) return fail(c, RG_EINVAL, "rg_plan_result: the plan does not materialise");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    uint64_t h[2] = {0, 0};
+    uint32_t e = 0;
+    HIPCHK(c, hipMemcpyAsync(h, p->totals, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(&e, p->err, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (e) return fail(c, RG_EDEVICE, "result key set exceeded its bound (internal error)");
+    if (n_containers) *n_containers = h[1];
+    if (payload_used) *payload_used = h[0];
+    return RG_OK;
+}
+
+rg_status rg_plan_totals(const rg_plan* p, const uint64_t** d_totals) {
+    if (!p || !d_totals || !p->mat) return RG_EINVAL;
+    *d_totals = p->totals;
+    return RG_OK;
+}
+
+rg_status rg_set_wave_slots(rg_ctx* c, uint64_t max_slots) {
+    if (!c) return RG_EINVAL;
+    if (max_slots < 1 || max_slots > (1ull << 30)) return fail(c, RG_EINVAL, "rg_set_wave_slots: 1 <= slots <= 2^30");
+    c->max_wave_slots = max_slots;
+    return RG_OK;
+}
+
 rg_status rg_plan_execute(rg_plan* p, void* stream) {
     if (!p) return RG_EINVAL;
     rg_ctx* c = p->ctx;
@@ -1155,6 +1391,7 @@ rg_status rg_plan_capture(rg_plan* p, void* stream) {
 
 rg_status rg_plan_tune(rg_plan* p, void* stream, int reps) {
     if (!p) return RG_EINVAL;
+    if (p->mat) return RG_OK;  // the k-way kernels of materialising plans have no knobs to tune
     rg_ctx* c = p->ctx;
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;

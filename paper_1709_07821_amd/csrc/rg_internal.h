@@ -255,12 +255,14 @@ void launch_bin_layout(const uint32_t* blk_cnt, uint32_t nblk, uint64_t* blk_off
                        uint32_t* bin_info, uint32_t* next, hipStream_t st);
 void launch_bin_scatter(const Task* tasks, uint64_t n, const uint32_t* blk_cnt, const uint64_t* blk_off,
                         uint32_t* bin_lists, hipStream_t st);
-// exclusive scan of u32 into u64 with an added base; writes total to *total_out (device)
+// exclusive scan of u32 into u64 with an added base (plus *base_dev when
+// given, read on the device; it may be total_out itself); writes the total to
+// *total_out (device)
 void launch_scan_u32_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t base, uint64_t* partials,
-                         uint64_t* total_out, hipStream_t st);
+                         uint64_t* total_out, hipStream_t st, const uint64_t* base_dev = nullptr);
 // The same exclusive scan over (in[i] != 0): output positions of the non-empty results.
 void launch_scan_nonzero_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t base, uint64_t* partials,
-                             uint64_t* total_out, hipStream_t st);
+                             uint64_t* total_out, hipStream_t st, const uint64_t* base_dev = nullptr);
 size_t scan_partials_needed(uint64_t n);
 
 struct ComputeArgs {

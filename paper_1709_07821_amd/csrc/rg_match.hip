@@ -608,9 +608,11 @@ __global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t* in, uint64_
 }
 
 __global__ void __launch_bounds__(256) k_scan_partials(uint64_t* partials, uint64_t nb, uint64_t base,
-                                                       uint64_t* total_out) {
+                                                       const uint64_t* base_dev, uint64_t* total_out) {
     __shared__ uint64_t tmp[256];
-    uint64_t carry = base;
+    // base_dev may be total_out itself: it is read here, before any barrier,
+    // and written only at the end
+    uint64_t carry = base + (base_dev ? *base_dev : 0);
     for (uint64_t c0 = 0; c0 < nb; c0 += 256) {
         uint64_t i = c0 + threadIdx.x;
         uint64_t v = i < nb ? partials[i] : 0;
@@ -628,6 +630,7 @@ __global__ void __launch_bounds__(256) k_scan_partials(uint64_t* partials, uint6
         __syncthreads();
         carry += tot;
     }
+    __syncthreads();  // every thread has read base_dev before total_out is written
     if (threadIdx.x == 0 && total_out) *total_out = carry;
 }
 
@@ -665,9 +668,10 @@ __global__ void __launch_bounds__(256) k_scan_down(const uint32_t* in, uint64_t 
 
 // one tile: the whole scan in one workgroup (small inputs: one launch, not three)
 template <bool NZ>
-__global__ void __launch_bounds__(256) k_scan_single(const uint32_t* in, uint64_t n, uint64_t base, uint64_t* out,
-                                                     uint64_t* total_out) {
+__global__ void __launch_bounds__(256) k_scan_single(const uint32_t* in, uint64_t n, uint64_t base,
+                                                     const uint64_t* base_dev, uint64_t* out, uint64_t* total_out) {
     __shared__ uint64_t tmp[4];
+    base += base_dev ? *base_dev : 0;  // read before the barrier; total_out (maybe the same word) after it
     const uint64_t start = (uint64_t)threadIdx.x * SCAN_PER_THREAD;
     uint32_t v[SCAN_PER_THREAD];
     uint64_t s = 0;
@@ -696,31 +700,36 @@ __global__ void __launch_bounds__(256) k_scan_single(const uint32_t* in, uint64_
     if (threadIdx.x == 255 && total_out) *total_out = base + wbase + inc;
 }
 
+// total_out = base + *base_dev (an empty scan)
+__global__ void k_scan_empty(uint64_t base, const uint64_t* base_dev, uint64_t* total_out) {
+    *total_out = base + (base_dev ? *base_dev : 0);
+}
+
 template <bool NZ>
 static void launch_scan(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t base, uint64_t* partials,
-                        uint64_t* total_out, hipStream_t st) {
+                        uint64_t* total_out, hipStream_t st, const uint64_t* base_dev) {
     uint64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb == 0) {
-        if (total_out) hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, st, total_out, base, (uint64_t)1);
+        if (total_out) hipLaunchKernelGGL(k_scan_empty, dim3(1), dim3(1), 0, st, base, base_dev, total_out);
         return;
     }
     if (nb == 1) {
-        hipLaunchKernelGGL(k_scan_single<NZ>, dim3(1), dim3(256), 0, st, in, n, base, out, total_out);
+        hipLaunchKernelGGL(k_scan_single<NZ>, dim3(1), dim3(256), 0, st, in, n, base, base_dev, out, total_out);
         return;
     }
     hipLaunchKernelGGL(k_scan_reduce<NZ>, dim3((uint32_t)nb), dim3(256), 0, st, in, n, partials);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(256), 0, st, partials, nb, base, total_out);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(256), 0, st, partials, nb, base, base_dev, total_out);
     hipLaunchKernelGGL(k_scan_down<NZ>, dim3((uint32_t)nb), dim3(256), 0, st, in, n, partials, out);
 }
 
 void launch_scan_u32_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t base, uint64_t* partials,
-                         uint64_t* total_out, hipStream_t st) {
-    launch_scan<false>(in, out, n, base, partials, total_out, st);
+                         uint64_t* total_out, hipStream_t st, const uint64_t* base_dev) {
+    launch_scan<false>(in, out, n, base, partials, total_out, st, base_dev);
 }
 
 void launch_scan_nonzero_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t base, uint64_t* partials,
-                             uint64_t* total_out, hipStream_t st) {
-    launch_scan<true>(in, out, n, base, partials, total_out, st);
+                             uint64_t* total_out, hipStream_t st, const uint64_t* base_dev) {
+    launch_scan<true>(in, out, n, base, partials, total_out, st, base_dev);
 }
 
 }  // namespace rg

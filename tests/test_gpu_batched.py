@@ -248,3 +248,105 @@ def test_uneven_shape_eager_and_plan_match_oracle(rg, ctx):
                 assert np.array_equal(pl.cards.cpu().numpy().view(np.uint64), card), (op, rep)
                 assert np.array_equal(pl.jacc.cpu().numpy(), jac), (op, rep)
         pl.close()
+
+
+def _check_mat_result(rg, ctx, label, op, bs, ia, ib, pool, cards, jacc, full=True):
+    """Every pair's result bitmap against the oracle: fingerprint, and when full
+    the decoded values and container metadata; counts and Jaccard index."""
+    assert rg.rg_pool_validate(ctx, pool) == 0, (label, op)
+    dig = rg.rg_pool_digest(ctx, pool).cpu().numpy().view(np.uint64)
+    c = cards.cpu().numpy().view(np.uint64)
+    j = jacc.cpu().numpy()
+    card_e, dig_e, jac_e = oracle.pairs(op, bs.values, bs.offsets, bs.values, bs.offsets, ia, ib, want_digest=True,
+                                        want_jaccard=True)
+    assert np.array_equal(dig[:len(ia)], dig_e), (label, op)
+    assert np.array_equal(c, card_e) and np.array_equal(j, jac_e), (label, op)
+    if full:
+        h = pool.to_host()
+        for p in range(len(ia)):
+            exp = oracle.op(op, bs[int(ia[p])], bs[int(ib[p])])
+            got, meta = rgtest.decode_bitmap(h, p)
+            assert np.array_equal(got, exp), (label, op, p)
+            assert meta == rgtest.oracle_meta(oracle, exp), (label, op, p)
+
+
+@pytest.mark.parametrize("which", ["edges", "mixed", "array-stress"])
+def test_materialising_plan_replays_match_oracle(rg, ctx, which):
+    """A materialising plan captured in a hipGraph and replayed three times,
+    with eager calls of the same context in between and the arena wiped before
+    each replay: every replay's results equal the oracle's."""
+    import torch
+
+    label, bs, ia, ib = [w for w in _workloads() if w[0] == which][0]
+    ia, ib = ia.astype(np.uint32), ib.astype(np.uint32)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    tia, tib = _t(ia), _t(ib)
+    stream = torch.cuda.Stream()
+    for op in OPS:
+        _say(f"[mat plan {label}] op={op} pairs={len(ia)}")
+        pl = rg.Plan(ctx, op, P, P, tia, tib, card=True, jaccard=True, materialize=True, stream=stream)
+        with torch.cuda.stream(stream):
+            pl.capture(stream)
+            for rep in range(3):
+                for t in (pl.out.keys, pl.out.types, pl.out.card, pl.out.payload, pl.out.bm_begin):
+                    t.fill_(0x55)
+                pl.cards.zero_()
+                pl.jacc.zero_()
+                pl.execute(stream)
+                stream.synchronize()
+                # an eager call of the same context between replays
+                _, c2, _ = rg.batch(ctx, "xor", P, P, tia, tib, materialize=False, card=True)
+                torch.cuda.synchronize()
+                R = pl.result(stream)
+                _check_mat_result(rg, ctx, label, op, bs, ia, ib, R, pl.cards, pl.jacc, full=rep == 0)
+        pl.close()
+
+
+def test_materialising_plan_in_waves_uneven_shape(rg, ctx):
+    """The batched uneven shape materialised in arena-sized waves: the wave size
+    cut so that the plan runs in many waves, every pair's fingerprint, count and
+    Jaccard index against the oracle, for all four operations, and equal to the
+    eager materialising call."""
+    import torch
+
+    bs, ia, ib = _uneven_pool(n_bitmaps=128, n_pairs=600)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    tia, tib = _t(ia), _t(ib)
+    stream = torch.cuda.Stream()
+    ctx.set_wave_slots(20000)
+    try:
+        for op in OPS:
+            pl = rg.Plan(ctx, op, P, P, tia, tib, card=True, jaccard=True, materialize=True, stream=stream)
+            info = pl.info()
+            _say(f"[mat plan uneven] op={op} pairs={len(ia)} {info}")
+            assert info["waves"] > 3
+            with torch.cuda.stream(stream):
+                pl.capture(stream)
+                for rep in range(2):
+                    pl.execute(stream)
+                    stream.synchronize()
+                    R = pl.result(stream)
+                    _check_mat_result(rg, ctx, "uneven", op, bs, ia, ib, R, pl.cards, pl.jacc, full=False)
+            out, _, _ = rg.batch(ctx, op, P, P, tia, tib, materialize=True)
+            torch.cuda.synchronize()
+            d_eager = rg.rg_pool_digest(ctx, out.as_pool()).cpu().numpy()
+            d_plan = rg.rg_pool_digest(ctx, R).cpu().numpy()
+            assert np.array_equal(d_eager, d_plan), op
+            pl.close()
+    finally:
+        ctx.set_wave_slots(1 << 24)
+
+
+def test_materialising_plan_errors(rg, ctx):
+    bs = synth.mixed_small(n_bitmaps=5, seed=61)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    with pytest.raises(rg.RoaringError):  # pair index outside the pool
+        rg.Plan(ctx, "or", P, P, _t(np.array([0, 9], np.uint32)), _t(np.array([1, 1], np.uint32)), materialize=True)
+    ia, ib = _t(np.array([0, 1], np.uint32)), _t(np.array([1, 2], np.uint32))
+    out = rg.OutArena(2, 1, 16)
+    import ctypes
+
+    h = ctypes.c_void_p()
+    st = rg.lib().rg_plan_create_mat(ctx.h, 1, ctypes.byref(P.c), ctypes.byref(P.c), rg._ptr(ia), rg._ptr(ib), 2,
+                                     rg.RG_FLAG_MATERIALIZE, ctypes.byref(out.c), None, None, ctypes.byref(h), None)
+    assert st == rg.RG_ECAPACITY and out.c.needed_containers > 1 and out.c.needed_payload_bytes > 16
