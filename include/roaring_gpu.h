@@ -492,6 +492,44 @@ rg_status roaring_contains(rg_ctx *ctx, const rg_pool *P, const uint32_t *d_ids,
 rg_status roaring_to_uint32(rg_ctx *ctx, const rg_pool *P, uint32_t b0, uint32_t n, uint64_t *d_offsets,
                             uint32_t *d_values, uint64_t cap_values, uint64_t *needed_values, void *stream);
 
+/* ---- mutable bitmaps: in-place operations ---------------------------------
+ * The paper updates containers in place: values of an array are set, cleared
+ * or flipped in a bitset while its cardinality is kept (Section 3.2), and wide
+ * unions are built partly in place (Section 5.9). A mutable pool holds
+ * n_bitmaps bitmaps that change in place: every bitmap has a directory of all
+ * 65536 keys, and containers live in fixed 8 KiB slots (any P1 container fits,
+ * so a result is written back where its input was) taken from and returned to
+ * a device free list of n_slots slots. Memory: 256 KiB per bitmap plus
+ * 8 KiB + 25 B per slot, allocated by rg_mpool_create. Every bitmap starts
+ * empty; containers always stay in P1 form and each bitmap's cardinality is
+ * maintained by every operation (no recount).
+ *
+ * rg_mpool_op: M[b] op= P[src] (P an ordinary pool; union, intersection,
+ * symmetric difference, difference A \ B), asynchronous on `stream`. Only
+ * the keys of P[src] are visited (intersection also drops M[b]'s keys that
+ * P[src] lacks): a key in both is recomputed in M[b]'s slot, a key only in
+ * P[src] takes a free slot (union, symmetric difference), an empty result
+ * frees its slot. When the keys to insert outnumber the free slots the whole
+ * operation is skipped on the device (M[b] unchanged) and rg_mpool_status
+ * reports RG_ECAPACITY. rg_mpool_assign: M[b] = P[src]; rg_mpool_clear:
+ * M[b] = {}. rg_mpool_cards: copies the n_bitmaps maintained cardinalities
+ * (uint64) into d_cards (device, caller-owned), enqueued on `stream`.
+ * rg_mpool_status: synchronises `stream`, gives the free
+ * slots, and returns RG_ECAPACITY once if an operation was skipped since the
+ * last call. rg_mpool_export: bitmaps b0 .. b0+n-1 as an ordinary pool in
+ * `out` (P1, ascending keys; sizing as for roaring_batch with needed_*);
+ * synchronises. Calls on one mutable pool must be ordered (one stream, or
+ * the caller's synchronisation): they share its work lists. */
+typedef struct rg_mpool rg_mpool;
+rg_status rg_mpool_create(rg_ctx *ctx, uint32_t n_bitmaps, uint32_t n_slots, rg_mpool **mp);
+void rg_mpool_destroy(rg_mpool *mp);
+rg_status rg_mpool_op(rg_mpool *mp, int op, uint32_t b, const rg_pool *P, uint32_t src, void *stream);
+rg_status rg_mpool_assign(rg_mpool *mp, uint32_t b, const rg_pool *P, uint32_t src, void *stream);
+rg_status rg_mpool_clear(rg_mpool *mp, uint32_t b, void *stream);
+rg_status rg_mpool_cards(rg_mpool *mp, uint64_t *d_cards, void *stream);
+rg_status rg_mpool_status(rg_mpool *mp, uint32_t *free_slots, void *stream);
+rg_status rg_mpool_export(rg_mpool *mp, uint32_t b0, uint32_t n, rg_out *out, void *stream);
+
 /* ---- pools -------------------------------------------------------------- */
 
 /* Host-side pool construction from sorted values. Bitmap b holds

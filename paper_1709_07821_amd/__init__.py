@@ -44,7 +44,9 @@ EXPORTS = ["rg_create", "rg_destroy", "rg_last_error", "rg_set_dispatch", "rg_se
            "rg_dispatch_set_mlp", "rg_dispatch_table", "rg_sync", "rg_set_workspace", "rg_workspace_size",
            "roaring_jaccard_host", "rg_pool_init_dense", "roaring_batch_static",
            "roaring_contains", "roaring_to_uint32", "rg_pool_check", "rg_pool_canonicalize",
-           "rg_plan_create_mat", "rg_plan_result", "rg_plan_totals", "rg_set_wave_slots"]
+           "rg_plan_create_mat", "rg_plan_result", "rg_plan_totals", "rg_set_wave_slots",
+           "rg_mpool_create", "rg_mpool_destroy", "rg_mpool_op", "rg_mpool_assign", "rg_mpool_clear",
+           "rg_mpool_cards", "rg_mpool_status", "rg_mpool_export"]
 
 
 class RoaringError(RuntimeError):
@@ -156,9 +158,18 @@ def lib():
         L.rg_plan_result.argtypes = [V, P(U64), P(U64), V]
         L.rg_plan_totals.argtypes = [V, P(V)]
         L.rg_set_wave_slots.argtypes = [V, U64]
+        L.rg_mpool_create.argtypes = [V, U32, U32, P(V)]
+        L.rg_mpool_destroy.argtypes = [V]
+        L.rg_mpool_destroy.restype = None
+        L.rg_mpool_op.argtypes = [V, I, U32, pool_p, U32, V]
+        L.rg_mpool_assign.argtypes = [V, U32, pool_p, U32, V]
+        L.rg_mpool_clear.argtypes = [V, U32, V]
+        L.rg_mpool_cards.argtypes = [V, V, V]
+        L.rg_mpool_status.argtypes = [V, P(U32), V]
+        L.rg_mpool_export.argtypes = [V, U32, U32, out_p, V]
         L.roaring_to_uint32.argtypes = [V, pool_p, U32, U32, V, V, U64, P(U64), V]
         for nm in EXPORTS:
-            if nm not in ("rg_destroy", "rg_last_error", "rg_plan_destroy"):
+            if nm not in ("rg_destroy", "rg_last_error", "rg_plan_destroy", "rg_mpool_destroy"):
                 getattr(L, nm).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -672,6 +683,63 @@ def batch(ctx: Context, op, A: Pool, B: Pool, ia, ib, materialize=True, card=Fal
     if not done:
         ctx.check(roaring_batch(ctx, op, A, B, ia, ib, flags, out, cards, jacc, stream))
     return out, (cards[:n] if card else None), (jacc[:n] if jaccard else None)
+
+
+# ---------------------------------------------------------------- mutable bitmaps
+
+class MutablePool:
+    """rg_mpool: bitmaps changed in place (op=) with maintained cardinalities."""
+
+    def __init__(self, ctx: Context, n_bitmaps: int, n_slots: int):
+        h = ctypes.c_void_p()
+        ctx.check(lib().rg_mpool_create(ctx.h, n_bitmaps, n_slots, ctypes.byref(h)))
+        self.ctx, self.h, self.n_bitmaps, self.n_slots = ctx, h, n_bitmaps, n_slots
+
+    def op(self, op, b: int, P: Pool, src: int, stream=None):
+        op = OPS[op] if isinstance(op, str) else op
+        self.ctx.check(lib().rg_mpool_op(self.h, op, b, ctypes.byref(P.c), src, _stream(stream)))
+
+    def assign(self, b: int, P: Pool, src: int, stream=None):
+        self.ctx.check(lib().rg_mpool_assign(self.h, b, ctypes.byref(P.c), src, _stream(stream)))
+
+    def clear(self, b: int, stream=None):
+        self.ctx.check(lib().rg_mpool_clear(self.h, b, _stream(stream)))
+
+    def status(self, stream=None):
+        """(status code, free slots); synchronises."""
+        n = ctypes.c_uint32()
+        st = lib().rg_mpool_status(self.h, ctypes.byref(n), _stream(stream))
+        return st, int(n.value)
+
+    def cards(self, stream=None):
+        """The maintained cardinalities (device int64 tensor of n_bitmaps, viewed from uint64)."""
+        torch = _torch()
+        out = torch.empty(self.n_bitmaps, dtype=torch.int64, device="cuda")
+        self.ctx.check(lib().rg_mpool_cards(self.h, _ptr(out), _stream(stream)))
+        return out
+
+    def export(self, b0: int = 0, n: int | None = None, stream=None) -> OutArena:
+        n = self.n_bitmaps - b0 if n is None else n
+        out = OutArena(n, 0, 0)
+        out.c.cap_containers = 0
+        out.c.cap_payload_bytes = 0
+        st = lib().rg_mpool_export(self.h, b0, n, ctypes.byref(out.c), _stream(stream))
+        if st == RG_ECAPACITY:
+            out = OutArena(n, out.c.needed_containers, out.c.needed_payload_bytes)
+            st = lib().rg_mpool_export(self.h, b0, n, ctypes.byref(out.c), _stream(stream))
+        self.ctx.check(st)
+        return out
+
+    def close(self):
+        if self.h:
+            lib().rg_mpool_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------- k-way and serving
