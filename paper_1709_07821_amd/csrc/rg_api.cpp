@@ -385,6 +385,8 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
             ka.ub = ub;
             ka.res_card = res_card;
             ka.so = SlotOut{slot_off, out->payload, res_card, res_type, res_size, nullptr, nullptr};
+            ka.so.cap = out->cap_payload_bytes;
+            ka.so.err = d_err;
             ka.acc = nullptr;
             ka.err = d_err;
             launch_kw_keys(ka, st);
@@ -515,6 +517,9 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
             HIPCHK(c, hipStreamSynchronize(st));
             out_base = *reinterpret_cast<uint64_t*>(h_small + 66);
             pay_base = kw ? *reinterpret_cast<uint64_t*>(h_small + 64) : pay_end;
+            if (kw && (h_small[68] & 2u))
+                return fail(c, RG_ECAPACITY,
+                            "result payload exceeds the arena (pool cardinalities inconsistent with the payload)");
             if (kw && h_small[68]) return fail(c, RG_EDEVICE, "result key set exceeded its bound (internal error)");
         }
     }
@@ -1013,6 +1018,8 @@ void plan_enqueue_mat(rg_plan* p, hipStream_t st) {
         ka.ub = p->ub;
         ka.res_card = p->res_card;
         ka.so = SlotOut{p->slot_off, o.payload, p->res_card, p->res_type, p->res_size, nullptr, nullptr};
+        ka.so.cap = o.cap_payload_bytes;
+        ka.so.err = p->err;
         ka.acc = nullptr;
         ka.err = p->err;
         launch_kw_keys(ka, st);
@@ -1340,6 +1347,8 @@ rg_status rg_plan_result(rg_plan* p, uint64_t* n_containers, uint64_t* payload_u
     HIPCHK(c, hipMemcpyAsync(h, p->totals, 16, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipMemcpyAsync(&e, p->err, 4, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
+    if (e & 2u)
+        return fail(c, RG_ECAPACITY, "result payload exceeds the arena (pool cardinalities inconsistent with the payload)");
     if (e) return fail(c, RG_EDEVICE, "result key set exceeded its bound (internal error)");
     if (n_containers) *n_containers = h[1];
     if (payload_used) *payload_used = h[0];

@@ -129,6 +129,11 @@ __device__ inline uint32_t finalize_words(const uint64_t (&w)[4], uint32_t slot,
     const uint32_t c = (uint32_t)cr, r = (uint32_t)(cr >> 32);
     if (c == 0) return 0;
     const uint8_t type = p1_type(c, r);
+    const uint64_t nbytes = type == RG_ARRAY ? 2ull * c : type == RG_BITSET ? 8192ull : 4ull * r;
+    if (so.slot_off[slot] + nbytes > so.cap) {  // the same decision in every thread
+        if (tid == 0 && so.err) atomicOr(so.err, 2u);
+        return c;
+    }
     uint8_t* dst = so.payload + so.slot_off[slot];
     if (type == RG_BITSET) {
         u32x4* d4 = reinterpret_cast<u32x4*>(dst);

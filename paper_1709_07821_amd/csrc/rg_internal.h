@@ -83,6 +83,11 @@ struct SlotOut {
     uint32_t* res_size;
     uint32_t* redo_list;        // bitset pairs whose result is not a bitset
     uint32_t* redo_count;
+    // bytes of `payload`: a result that would end past it is not written (the
+    // slot stays empty) and bit 2 is set in *err - only a pool whose
+    // cardinalities disagree with its payload can get there
+    uint64_t cap = ~0ull;
+    uint32_t* err = nullptr;
 };
 
 // ---------------------------------------------------------------- helpers

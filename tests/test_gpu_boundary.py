@@ -187,3 +187,71 @@ def test_workspace_shared_across_streams(rg):
         g = res[1][0].cpu().numpy().astype(np.float64)
         assert np.abs(g - g0).max() <= 1e-4 * np.abs(g0).max() + 1e-7, order
     ctx.close()
+
+
+def test_materialised_calls_ignore_stale_workspace(rg):
+    """Materialising calls write every workspace slot they later read: on a
+    caller workspace filled with random bytes, then with 0xFF bytes, all four
+    operations give the oracle's results, one pool and two. (The first design
+    of materialised union and symmetric difference placed each key at its
+    merged position and left the slot after every matched key unwritten, so
+    those slots held what an earlier call had left there.)"""
+    import torch
+
+    ctx = rg.Context(0)
+    bs = synth.mixed_small(n_bitmaps=30, seed=34)
+    es = synth.BitmapSet.from_list(rgtest.edge_sets())
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    E = rg.Pool.from_sets(es.values, es.offsets)
+    ia, ib = synth.random_pairs(len(bs), 200, seed=34)
+    ja = (np.arange(60) % len(es)).astype(np.uint32)
+    jb = (np.arange(60) * 7 % len(bs)).astype(np.uint32)
+    ws = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(35)
+    for fill in ("random", "ones"):
+        for (A, B, xa, xb, sa, sb) in ((P, P, ia, ib, bs, bs), (E, P, ja, jb, es, bs)):
+            for op in OPS:
+                if fill == "random":
+                    ws.random_(0, 256, generator=gen)
+                else:
+                    ws.fill_(255)
+                torch.cuda.synchronize()
+                ctx.set_workspace(ws)
+                _say(f"[stale workspace] {fill} op={op} pairs={len(xa)}")
+                out, cards, jacc = rg.batch(ctx, op, A, B, _t(xa), _t(xb), materialize=True, card=True,
+                                            jaccard=True)
+                torch.cuda.synchronize()
+                ctx.set_workspace(None)
+                dig = rg.rg_pool_digest(ctx, out.as_pool()).cpu().numpy().view(np.uint64)
+                c = cards.cpu().numpy().view(np.uint64)
+                j = jacc.cpu().numpy()
+                ec, ed, ej = oracle.pairs(op, sa.values, sa.offsets, sb.values, sb.offsets, xa, xb, want_digest=True,
+                                          want_jaccard=True)
+                assert np.array_equal(dig[:len(xa)], ed), (fill, op)
+                assert np.array_equal(c, ec) and np.array_equal(j, ej), (fill, op)
+    ctx.close()
+
+
+def test_inconsistent_cardinality_is_a_capacity_error(rg):
+    """A caller-built pool whose stored cardinality understates a container's
+    values: materialised union through the k-way kernels finds the result
+    longer than its slot at the end of the arena and fails with
+    RG_ECAPACITY instead of writing past it."""
+    import torch
+
+    vals = np.arange(1000, 1200, 2, dtype=np.uint32)  # one array container of 100 values (100 runs)
+    n, nc, pb, h = rg.Pool.host_arrays(vals, np.array([0, len(vals)], np.uint64))
+    h["card"][0] = 50                       # understated
+    h["bm_card"][0] = 50
+    h["bm_wbytes"][0] = 112                 # roundup16(2 * 50)
+    e = rg.Pool.host_arrays(np.zeros(0, np.uint32), np.array([0, 0], np.uint64))[3]
+    A = rg.Pool.from_host_arrays(h)
+    B = rg.Pool.from_host_arrays(e)
+    ctx = rg.Context(0)
+    out = rg.OutArena(1, 1, 112)
+    ia = _t(np.array([0], np.uint32))
+    st = rg.roaring_batch(ctx, "or", A, B, ia, ia, rg.RG_FLAG_MATERIALIZE, out)
+    assert st == rg.RG_ECAPACITY, st
+    torch.cuda.synchronize()
+    ctx.close()
