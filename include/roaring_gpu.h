@@ -104,7 +104,16 @@ typedef struct rg_pool {
                                   records rg_pool_pack_meta writes. When set, key matching
                                   reads one record per matched container instead of the
                                   separate arrays; it must match the arrays. */
+    const uint8_t *key_index;  /* optional, may be NULL: [RG_KEY_INDEX_BYTES * n_bitmaps], the
+                                  key-presence index rg_pool_key_index writes. When set, key
+                                  matching finds a key of this pool's bitmaps with a bit test and
+                                  a popcount instead of a binary search; it must match keys. */
 } rg_pool;
+
+/* Bytes of the key-presence index per bitmap: 1024 uint64 words with bit
+ * (key & 63) of word (key >> 6) set for every key of the bitmap, then 1024
+ * uint16 ranks (keys of the bitmap in the words before each word). */
+#define RG_KEY_INDEX_BYTES 10240
 
 /* Caller-provided output arena (device pointers) for materialised results:
  * result bitmap p (one per pair) occupies containers [bm_begin[p],
@@ -237,19 +246,23 @@ rg_status roaring_batch_static(rg_ctx *ctx, int op, const rg_pool *A, const rg_p
 /* ---- batched count-only plans (pointer-stable, graph-capturable) --------
  * A plan fixes the pools, the pairs (d_ia/d_ib, device uint32), the op and the
  * outputs (d_cards uint64 and/or d_jacc binary64, one per pair). Creating it
- * reads the per-pair key-candidate counts back once (synchronising) and
- * allocates its own device memory. rg_plan_execute then enqueues the whole
- * batch on `stream` - per-pair seeds, key matching, binning by variant, one
- * persistent work-stealing kernel for all container pairs, count finishing -
- * with no host synchronisation and no allocation. rg_plan_capture records that
+ * checks the pair indices and reads the per-pair key-candidate counts back
+ * once (synchronising) and allocates its own device memory. rg_plan_execute
+ * then enqueues the whole batch on `stream` - per-pair seeds, a device scan of
+ * the candidate counts, one persistent work-stealing kernel that matches the
+ * keys of every pair and counts every matched container pair (workgroups take
+ * blocks of candidate keys from a counter), count finishing - with no host
+ * synchronisation and no allocation. rg_plan_capture records that
  * sequence into a hipGraph on a non-default stream; later executes replay it.
  * rg_plan_tune times the plan on its own data and keeps the fastest setting of
  * the thread-size threshold, the persistent grid size and the galloping ratio,
  * one after the other (results never change). The pools, pair arrays and
  * outputs must stay valid and unmoved for the plan's life. The pools' contents
  * must not change either: the plan keeps a packed copy of their container
- * metadata (16 bytes per container, made at creation; without the memory for
- * it the plan reads the pool arrays). The pair arrays' contents may change
+ * metadata (16 bytes per container) and, for pools with many keys per bitmap,
+ * their key-presence indexes (RG_KEY_INDEX_BYTES per bitmap), made at creation
+ * unless the pools carry them; without the memory for them the plan reads the
+ * pool arrays and searches the keys. The pair arrays' contents may change
  * between executions as long as every pair's candidate count (number of keys
  * of its smaller bitmap) does not. */
 typedef struct rg_plan rg_plan;
@@ -568,6 +581,16 @@ rg_status rg_pool_init_dense(rg_ctx *ctx, const rg_pool *pool, uint32_t n_keys, 
  * pool must then not change while meta is set. Not from the paper: a layout
  * choice for gathers on this GPU. Enqueued on `stream`, no synchronisation. */
 rg_status rg_pool_pack_meta(rg_ctx *ctx, const rg_pool *pool, uint32_t *d_meta, void *stream);
+
+/* Key-presence index of every bitmap of a pool (layout at RG_KEY_INDEX_BYTES)
+ * into d_index (device, caller-owned, RG_KEY_INDEX_BYTES * n_bitmaps bytes,
+ * 16-byte aligned). Setting pool.key_index = d_index lets key matching find a
+ * key in O(1) - the key-matching step turned into a bitset operation: the
+ * presence bit, then the container's index from the word's rank plus the
+ * popcount of the bits below. Count-only calls and plans build it in their own
+ * memory when the pools have many keys per bitmap; a pool that carries it is
+ * never indexed again. Enqueued on `stream`, no synchronisation. */
+rg_status rg_pool_key_index(rg_ctx *ctx, const rg_pool *pool, uint8_t *d_index, void *stream);
 
 /* Check every container of a device pool against the format rules above;
  * *n_bad (host) receives the number of offending containers. Synchronises.

@@ -27,6 +27,7 @@ RG_AND, RG_OR, RG_XOR, RG_ANDNOT = 0, 1, 2, 3
 OPS = {"and": RG_AND, "or": RG_OR, "xor": RG_XOR, "andnot": RG_ANDNOT}
 RG_FLAG_MATERIALIZE, RG_FLAG_CARD, RG_FLAG_JACCARD = 1, 2, 4
 RG_RULES_P1 = 1
+RG_KEY_INDEX_BYTES = 10240
 RG_DISPATCH_HEURISTIC, RG_DISPATCH_MLP, RG_DISPATCH_FIXED = 0, 1, 2
 RG_MLP_PARAMS, RG_MLP_TABLE = 5382, 374544
 VARIANTS = {"generic": 2, "merge": 3, "gallop": 4, "probe": 5, "runmerge": 6, "thread": 7}
@@ -46,7 +47,7 @@ EXPORTS = ["rg_create", "rg_destroy", "rg_last_error", "rg_set_dispatch", "rg_se
            "roaring_contains", "roaring_to_uint32", "rg_pool_check", "rg_pool_canonicalize",
            "rg_plan_create_mat", "rg_plan_result", "rg_plan_totals", "rg_set_wave_slots",
            "rg_mpool_create", "rg_mpool_destroy", "rg_mpool_op", "rg_mpool_assign", "rg_mpool_clear",
-           "rg_mpool_cards", "rg_mpool_status", "rg_mpool_export"]
+           "rg_mpool_cards", "rg_mpool_status", "rg_mpool_export", "rg_pool_key_index"]
 
 
 class RoaringError(RuntimeError):
@@ -60,7 +61,7 @@ class rg_pool(ctypes.Structure):
                 ("payload_bytes", ctypes.c_uint64), ("bm_begin", ctypes.c_void_p), ("keys", ctypes.c_void_p),
                 ("types", ctypes.c_void_p), ("card", ctypes.c_void_p), ("size", ctypes.c_void_p),
                 ("off", ctypes.c_void_p), ("payload", ctypes.c_void_p), ("bm_card", ctypes.c_void_p),
-                ("bm_wbytes", ctypes.c_void_p), ("meta", ctypes.c_void_p)]
+                ("bm_wbytes", ctypes.c_void_p), ("meta", ctypes.c_void_p), ("key_index", ctypes.c_void_p)]
 
 
 class rg_out(ctypes.Structure):
@@ -167,6 +168,7 @@ def lib():
         L.rg_mpool_cards.argtypes = [V, V, V]
         L.rg_mpool_status.argtypes = [V, P(U32), V]
         L.rg_mpool_export.argtypes = [V, U32, U32, out_p, V]
+        L.rg_pool_key_index.argtypes = [V, pool_p, V, V]
         L.roaring_to_uint32.argtypes = [V, pool_p, U32, U32, V, V, U64, P(U64), V]
         for nm in EXPORTS:
             if nm not in ("rg_destroy", "rg_last_error", "rg_plan_destroy", "rg_mpool_destroy"):
@@ -283,6 +285,15 @@ class Pool:
         self.meta = torch.empty(max(self.n_containers, 1) * 4, dtype=torch.int32, device=dev)
         ctx.check(lib().rg_pool_pack_meta(ctx.h, ctypes.byref(self._c), _ptr(self.meta), _stream(stream)))
         self._c.meta = _ptr(self.meta).value
+        return self
+
+    def key_index(self, ctx: "Context", stream=None):
+        """rg_pool_key_index into a tensor this pool keeps; sets the pool's key_index."""
+        torch = _torch()
+        dev = self.bm_begin.device if self.bm_begin is not None else torch.device("cuda")
+        self.kidx = torch.empty(max(self.n_bitmaps, 1) * RG_KEY_INDEX_BYTES, dtype=torch.uint8, device=dev)
+        ctx.check(lib().rg_pool_key_index(ctx.h, ctypes.byref(self._c), _ptr(self.kidx), _stream(stream)))
+        self._c.key_index = _ptr(self.kidx).value
         return self
 
     @staticmethod

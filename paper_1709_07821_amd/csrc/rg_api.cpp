@@ -166,6 +166,37 @@ rg_status run_count_async(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B,
             pb.meta = same ? ma : ma + A->n_containers;
         }
     }
+    // Key-presence indexes (10 KiB per bitmap) of pools with many keys per
+    // bitmap: key matching then finds each candidate key with a bit test and a
+    // popcount instead of a binary search. Without the memory the call searches.
+    {
+        const bool same = A->keys == B->keys && A->bm_begin == B->bm_begin;
+        const uint64_t nA = kidx_pays(A, n_pairs) ? A->n_bitmaps : 0, nB = (!same && kidx_pays(B, n_pairs)) ? B->n_bitmaps : 0;
+        if (nA + nB) {
+            void* km = nullptr;
+            bool ok = false;
+            const size_t need = (size_t)RG_KEY_INDEX_BYTES * (nA + nB);
+            if (sc.caller()) {
+                ok = align256(need) <= sc.left() && sc.take(WS_KIDX, need, &km) == RG_OK;
+            } else {
+                ok = grow_device(c, &c->ws_kidx, &c->ws_kidx_bytes, need) == RG_OK;
+                km = c->ws_kidx;
+                if (!ok) (void)hipGetLastError();
+            }
+            if (ok) {
+                uint8_t* kb = static_cast<uint8_t*>(km);
+                if (nA) {
+                    launch_key_index(view(*A), A->n_bitmaps, kb, st);
+                    pa.kidx = kb;
+                    if (same) pb.kidx = kb;
+                }
+                if (nB) {
+                    launch_key_index(view(*B), B->n_bitmaps, kb + (size_t)RG_KEY_INDEX_BYTES * nA, st);
+                    pb.kidx = kb + (size_t)RG_KEY_INDEX_BYTES * nA;
+                }
+            }
+        }
+    }
     launch_pair_prep(RG_AND, false, pa, pb, A->n_bitmaps, B->n_bitmaps, d_ia, d_ib, ia0, ib0, n_pairs, n_cand,
                      nullptr, nullptr, acc, async_err_word(c), st, next_blk);
     launch_scan_u32_u64(n_cand, cand_off, n_pairs, 0, partials, cand_off + n_pairs, st);
@@ -611,6 +642,9 @@ rg_status rg_workspace_size(rg_ctx* c, int op, uint32_t flags, const rg_pool* A,
         uint64_t nrec = 0;
         bool same = false;
         if (count_pack_pays(A, B, n_pairs, &nrec, &same)) b += align256(16 * nrec);
+        const bool same_k = A->keys == B->keys && A->bm_begin == B->bm_begin;
+        const uint64_t nk = (kidx_pays(A, n_pairs) ? A->n_bitmaps : 0) + ((!same_k && kidx_pays(B, n_pairs)) ? B->n_bitmaps : 0);
+        if (nk) b += align256((size_t)RG_KEY_INDEX_BYTES * nk);
         *bytes = b;
         return RG_OK;
     }
@@ -643,6 +677,7 @@ void rg_destroy(rg_ctx* c) {
     if (c->ws_pairs) (void)hipFree(c->ws_pairs);
     if (c->ws_wave) (void)hipFree(c->ws_wave);
     if (c->ws_meta) (void)hipFree(c->ws_meta);
+    if (c->ws_kidx) (void)hipFree(c->ws_kidx);
     if (c->ws_event) (void)hipEventDestroy(c->ws_event);
     if (c->small) (void)hipFree(c->small);
     if (c->host) (void)hipHostFree(c->host);
@@ -831,6 +866,16 @@ rg_status rg_pool_pack_meta(rg_ctx* c, const rg_pool* p, uint32_t* d_meta, void*
     return RG_OK;
 }
 
+rg_status rg_pool_key_index(rg_ctx* c, const rg_pool* p, uint8_t* d_index, void* stream) {
+    if (!c) return RG_EINVAL;
+    if (!pool_ok(p) || (!d_index && p->n_bitmaps)) return fail(c, RG_EINVAL, "incomplete pool or no d_index");
+    if (reinterpret_cast<uintptr_t>(d_index) & 15) return fail(c, RG_EINVAL, "d_index must be 16-byte aligned");
+    HIPCHK(c, hipSetDevice(c->device));
+    launch_key_index(view(*p), p->n_bitmaps, d_index, (hipStream_t)stream);
+    HIPCHK(c, hipGetLastError());
+    return RG_OK;
+}
+
 rg_status rg_pool_validate(rg_ctx* c, const rg_pool* p, uint64_t* n_bad, void* stream) {
     return rg_pool_check(c, p, RG_RULES_P1, n_bad, stream);
 }
@@ -894,19 +939,12 @@ struct rg_plan {
     std::vector<Wave> waves;
     void* mem = nullptr;
     uint32_t* n_cand = nullptr;
-    uint64_t* bound = nullptr;
-    uint32_t* min_cont = nullptr;
     long long* acc = nullptr;
     uint32_t* err = nullptr;
+    uint64_t* cand_all = nullptr;  // count plans: candidate offsets of all pairs (scanned on the device)
+    uint32_t* next = nullptr;      // count plans: the fused kernel's block counter
     Task* tasks = nullptr;
     uint32_t* res_card = nullptr;
-    uint32_t* lists = nullptr;
-    uint32_t* blk_cnt = nullptr;
-    uint64_t* blk_off = nullptr;
-    uint64_t* bpart = nullptr;
-    uint64_t* bin_total = nullptr;
-    uint32_t* bin_info = nullptr;
-    uint32_t* next = nullptr;
     uint64_t S_max = 0;
     uint32_t grid = 0;
     int dispatch_mode = RG_DISPATCH_HEURISTIC;
@@ -919,6 +957,10 @@ struct rg_plan {
     void* meta_mem = nullptr;
     const u32x4* metaA = nullptr;
     const u32x4* metaB = nullptr;
+    // key-presence indexes (the pools' own, or built at creation; null: none)
+    void* kidx_mem = nullptr;
+    const uint8_t* kidxA = nullptr;
+    const uint8_t* kidxB = nullptr;
     // materialising plans: results into `out` through the k-way kernels (two
     // bitmaps per query), with the arena offsets carried from wave to wave on
     // the device (totals[0] payload end, totals[1] containers written)
@@ -944,47 +986,35 @@ void plan_enqueue(rg_plan* p, hipStream_t st) {
     PoolView pa = view(p->A), pb = view(p->B);
     pa.meta = p->metaA;  // the plan's records (its own, or the pools' when they carry them)
     pb.meta = p->metaB;
+    pa.kidx = p->kidxA;
+    pb.kidx = p->kidxB;
     launch_fill_u32(p->err, 0, 1, st);
     // the plan accumulates |A n B| for every operation; the requested count
     // follows from the Section 5.9 identities in the last step
     launch_pair_prep(RG_AND, false, pa, pb, p->A.n_bitmaps, p->B.n_bitmaps, p->d_ia, p->d_ib, 0, 0, p->n_pairs,
-                     p->n_cand, p->bound, p->min_cont, p->acc, p->err, st);
-    for (const auto& w : p->waves) {
-        if (!w.C) continue;
-        MatchArgs m;
-        m.op = RG_AND;
-        m.materialize = false;
-        m.A = pa;
-        m.B = pb;
-        m.ia = p->d_ia;
-        m.ib = p->d_ib;
-        m.ia0 = 0;
-        m.ib0 = 0;
-        m.pair0 = w.p0;
-        m.n_pairs = w.np;
-        m.cand_off = w.cand_off;
-        m.n_cand = w.C;
-        m.tasks = p->tasks;
-        m.ub = nullptr;
-        m.res_card = p->res_card;
-        m.blk_cnt = p->blk_cnt;
-        m.dispatch_mode = p->dispatch_mode;
-        m.fixed_bin = p->fixed_bin;
-        m.gallop_ratio = p->gallop_ratio;
-        m.thread_max = p->thread_max;
-        m.mlp_table = p->ctx->mlp_table;
-        m.fuse_thread = true;
-        m.acc = p->acc;
-        launch_match(m, st);
-        launch_bin_layout(p->blk_cnt, match_blocks(w.C), p->blk_off, p->bpart, p->bin_total, p->bin_info, p->next,
-                          st);
-        launch_bin_scatter(p->tasks, w.C, p->blk_cnt, p->blk_off, p->lists, st);
-        PersistArgs a{pa, pb, p->tasks, p->lists, p->bin_info, p->next, p->acc};
-        launch_persist(a, p->grid, st);
-    }
+                     p->n_cand, nullptr, nullptr, p->acc, p->err, st, p->next);
+    launch_scan_u32_u64(p->n_cand, p->cand_all, p->n_pairs, 0, p->partials, p->cand_all + p->n_pairs, st);
+    MatchArgs m{};
+    m.op = RG_AND;
+    m.materialize = false;
+    m.A = pa;
+    m.B = pb;
+    m.ia = p->d_ia;
+    m.ib = p->d_ib;
+    m.pair0 = 0;
+    m.n_pairs = (uint32_t)p->n_pairs;
+    m.cand_off = p->cand_all;
+    m.n_cand = 0;  // read on the device
+    m.dispatch_mode = p->dispatch_mode;
+    m.fixed_bin = p->fixed_bin;
+    m.gallop_ratio = p->gallop_ratio;
+    m.thread_max = p->thread_max;
+    m.mlp_table = p->ctx->mlp_table;
+    m.fuse_thread = true;
+    m.acc = p->acc;
+    launch_count_fused(m, p->next, p->grid, st);
     launch_finish_counts(RG_AND, p->op, p->acc, pa, pb, p->A.n_bitmaps, p->B.n_bitmaps, p->d_ia, p->d_ib, 0, 0, 0,
-                         (uint32_t)p->n_pairs,
-                         (p->flags & RG_FLAG_CARD) ? p->d_cards : nullptr,
+                         (uint32_t)p->n_pairs, (p->flags & RG_FLAG_CARD) ? p->d_cards : nullptr,
                          (p->flags & RG_FLAG_JACCARD) ? p->d_jacc : nullptr, st);
 }
 
@@ -1098,12 +1128,13 @@ rg_status rg_plan_create(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, 
     p->thread_max = c->thread_max;
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
-    p->grid = (uint32_t)cus * 8;
+    p->grid = (uint32_t)cus * 4;
 
     // candidate counts: one preparation pass, read back once
     auto cleanup = [&](rg_status s) {
         if (p->mem) (void)hipFree(p->mem);
         if (p->meta_mem) (void)hipFree(p->meta_mem);
+        if (p->kidx_mem) (void)hipFree(p->kidx_mem);
         delete p;
         return s;
     };
@@ -1131,54 +1162,22 @@ rg_status rg_plan_create(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, 
             return cleanup(fail(c, RG_EDEVICE, "plan preparation failed"));
         if (h_err) return cleanup(fail(c, RG_EINVAL, "pair index out of range of its pool"));
     }
-    // waves
-    std::vector<uint64_t> starts{0};
-    uint64_t accs = 0;
-    for (uint64_t q = 0; q < n_pairs; ++q) {
-        if (accs + h_cand[q] > c->max_wave_slots && accs > 0) {
-            p->S_max = std::max(p->S_max, accs);
-            starts.push_back(q);
-            accs = 0;
-        }
-        accs += h_cand[q];
-    }
-    p->S_max = std::max(p->S_max, accs);
-    starts.push_back(n_pairs);
-    size_t offs_bytes = 0;
-    for (size_t w = 0; w + 1 < starts.size(); ++w) offs_bytes += align256(8 * (starts[w + 1] - starts[w] + 1));
-    const uint64_t S = std::max<uint64_t>(p->S_max, 1);
-    const uint64_t NB = (uint64_t)NBINS * match_blocks(S);
-    const size_t total = pair_bytes + offs_bytes + align256(sizeof(Task) * S) + 2 * align256(4 * S) + 6 * 256 +
-                         align256(4 * NB) + align256(8 * NB) + align256(8 * scan_partials_needed(NB));
+    // One launch of the fused match-and-count kernel takes every pair: the
+    // candidate offsets are scanned on the device at each execution, so the
+    // plan keeps only per-pair arrays.
+    uint64_t slots = 0;
+    for (uint64_t q = 0; q < n_pairs; ++q) slots += h_cand[q];
+    const size_t total = align256(4 * n_pairs) + align256(8 * n_pairs) + align256(8 * (n_pairs + 1)) +
+                         align256(8 * scan_partials_needed(n_pairs)) + 2 * 256;
     if (hipMalloc(&p->mem, total) != hipSuccess) return cleanup(fail(c, RG_EDEVICE, "hipMalloc failed"));
     Bump b{(uint8_t*)p->mem};
     p->n_cand = b.take<uint32_t>(n_pairs);
-    p->bound = b.take<uint64_t>(n_pairs);
-    p->min_cont = b.take<uint32_t>(n_pairs);
     p->acc = b.take<long long>(n_pairs);
+    p->cand_all = b.take<uint64_t>(n_pairs + 1);
+    p->partials = b.take<uint64_t>(scan_partials_needed(n_pairs));
     p->err = b.take<uint32_t>(1);
-    p->tasks = b.take<Task>(S);
-    p->res_card = b.take<uint32_t>(S);
-    p->lists = b.take<uint32_t>(S);
-    p->blk_cnt = b.take<uint32_t>(NB);
-    p->blk_off = b.take<uint64_t>(NB);
-    p->bpart = b.take<uint64_t>(scan_partials_needed(NB));
-    p->bin_total = b.take<uint64_t>(1);
-    p->bin_info = b.take<uint32_t>(2 * NBINS);
-    p->next = b.take<uint32_t>(NBINS);
-    std::vector<uint64_t> h_off;
-    for (size_t w = 0; w + 1 < starts.size(); ++w) {
-        rg_plan::Wave wv;
-        wv.p0 = starts[w];
-        wv.np = (uint32_t)(starts[w + 1] - starts[w]);
-        h_off.assign(wv.np + 1, 0);
-        for (uint32_t q = 0; q < wv.np; ++q) h_off[q + 1] = h_off[q] + h_cand[wv.p0 + q];
-        wv.C = h_off[wv.np];
-        wv.cand_off = b.take<uint64_t>(wv.np + 1);
-        if (hipMemcpy(wv.cand_off, h_off.data(), 8 * (wv.np + 1), hipMemcpyHostToDevice) != hipSuccess)
-            return cleanup(fail(c, RG_EDEVICE, "plan upload failed"));
-        p->waves.push_back(wv);
-    }
+    p->next = b.take<uint32_t>(1);
+    p->waves.push_back(rg_plan::Wave{0, (uint32_t)n_pairs, slots, p->cand_all});
     // Key matching reads every matched container's type, cardinality, size and
     // offset; the plan packs them into one 16-byte record per container once
     // (both pools, or one when A and B are the same pool). Without the memory
@@ -1204,6 +1203,32 @@ rg_status rg_plan_create(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, 
             } else {
                 p->meta_mem = nullptr;
                 (void)hipGetLastError();  // the failed allocation is not an error of the plan
+            }
+        }
+    }
+    // key-presence indexes of pools with many keys per bitmap
+    p->kidxA = A->key_index;
+    p->kidxB = B->key_index;
+    {
+        const bool same = A->keys == B->keys && A->bm_begin == B->bm_begin;
+        const uint64_t nA = kidx_pays(A, n_pairs) ? A->n_bitmaps : 0, nB = (!same && kidx_pays(B, n_pairs)) ? B->n_bitmaps : 0;
+        if (nA + nB) {
+            if (hipMalloc(&p->kidx_mem, (size_t)RG_KEY_INDEX_BYTES * (nA + nB)) == hipSuccess) {
+                uint8_t* kb = static_cast<uint8_t*>(p->kidx_mem);
+                if (nA) {
+                    launch_key_index(view(*A), A->n_bitmaps, kb, st);
+                    p->kidxA = kb;
+                    if (same) p->kidxB = kb;
+                }
+                if (nB) {
+                    launch_key_index(view(*B), B->n_bitmaps, kb + (size_t)RG_KEY_INDEX_BYTES * nA, st);
+                    p->kidxB = kb + (size_t)RG_KEY_INDEX_BYTES * nA;
+                }
+                if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+                    return cleanup(fail(c, RG_EDEVICE, "plan key indexing failed"));
+            } else {
+                p->kidx_mem = nullptr;
+                (void)hipGetLastError();
             }
         }
     }
@@ -1492,6 +1517,7 @@ void rg_plan_destroy(rg_plan* p) {
     plan_drop_graph(p);
     if (p->mem) (void)hipFree(p->mem);
     if (p->meta_mem) (void)hipFree(p->meta_mem);
+    if (p->kidx_mem) (void)hipFree(p->kidx_mem);
     delete p;
 }
 

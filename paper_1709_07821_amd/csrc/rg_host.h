@@ -23,6 +23,8 @@ struct rg_ctx {
     size_t host_bytes = 0;
     void* ws_meta = nullptr;   // packed container metadata of a large count-only call
     size_t ws_meta_bytes = 0;
+    void* ws_kidx = nullptr;   // key-presence indexes of a count-only call's pools
+    size_t ws_kidx_bytes = 0;
     // caller-owned device workspace (rg_set_workspace): when set, calls carve
     // their scratch out of it and never allocate device memory
     void* user_ws = nullptr;
@@ -166,7 +168,7 @@ constexpr size_t HOST_STAGING_BYTES = 1u << 20;
 // roaring_batch_static) the regions are carved from it in order and a region
 // that does not fit fails with RG_ECAPACITY (nothing is allocated); otherwise
 // each region is one of the context's own buffers, grown on demand.
-enum WsRegion { WS_PAIRS = 0, WS_WAVE = 1, WS_META = 2 };
+enum WsRegion { WS_PAIRS = 0, WS_WAVE = 1, WS_META = 2, WS_KIDX = 3 };
 struct Scratch {
     rg_ctx* c;
     uint8_t* fixed = nullptr;
@@ -210,8 +212,11 @@ inline rg_status Scratch::take(WsRegion r, size_t need, void** out) {
         used += need;
         return RG_OK;
     }
-    void** buf = r == WS_PAIRS ? &c->ws_pairs : r == WS_WAVE ? &c->ws_wave : &c->ws_meta;
-    size_t* cap = r == WS_PAIRS ? &c->ws_pairs_bytes : r == WS_WAVE ? &c->ws_wave_bytes : &c->ws_meta_bytes;
+    void** buf = r == WS_PAIRS ? &c->ws_pairs : r == WS_WAVE ? &c->ws_wave : r == WS_META ? &c->ws_meta : &c->ws_kidx;
+    size_t* cap = r == WS_PAIRS  ? &c->ws_pairs_bytes
+                  : r == WS_WAVE ? &c->ws_wave_bytes
+                  : r == WS_META ? &c->ws_meta_bytes
+                                 : &c->ws_kidx_bytes;
     if (rg_status s = grow_device(c, buf, cap, need)) return s;
     *out = *buf;
     return RG_OK;
@@ -248,7 +253,8 @@ struct Bump {
 
 inline PoolView view(const rg_pool& p) {
     return PoolView{p.bm_begin, p.keys,    p.types,     p.card,      p.size,
-                    p.off,      p.payload, p.bm_card,   p.bm_wbytes, reinterpret_cast<const u32x4*>(p.meta)};
+                    p.off,      p.payload, p.bm_card,   p.bm_wbytes, reinterpret_cast<const u32x4*>(p.meta),
+                    p.key_index};
 }
 
 inline bool pool_ok(const rg_pool* p) {
@@ -263,3 +269,16 @@ inline bool pool_ok(const rg_pool* p) {
 rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const uint32_t* d_ia,
                     const uint32_t* d_ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs, uint32_t flags, rg_out* out,
                     uint64_t* d_cards, double* d_jacc, hipStream_t st, bool single = false);
+
+// Whether a pool is worth a key-presence index for count-only matching over
+// n_pairs pairs: it has none, its bitmaps hold at least KIDX_MIN_MEAN_KEYS keys
+// on average, and the call is expected to look up more candidate keys (pairs x
+// the mean key count) than building the index reads keys (all of the pool's)
+// and writes index words (1024 per bitmap).
+inline bool kidx_pays(const rg_pool* P, uint64_t n_pairs) {
+    if (P->key_index || !P->n_bitmaps) return false;
+    const uint64_t mean = P->n_containers / P->n_bitmaps;
+    if (mean < KIDX_MIN_MEAN_KEYS) return false;
+    const double cand = (double)n_pairs * (double)mean;
+    return cand >= (double)P->n_containers + (double)KIDX_WORDS * (double)P->n_bitmaps;
+}

@@ -65,9 +65,18 @@ struct PoolView {
     // matching reads one record per side instead of four arrays, and no payload
     // for the smallest arrays. Null: use the arrays.
     const u32x4* meta;
+    // Optional: key-presence index, RG_KEY_INDEX_BYTES per bitmap (1024 u64
+    // presence words, then 1024 u16 ranks: keys in the words before each word).
+    // A key of bitmap b is found with one bit test and a popcount. Null: none.
+    const uint8_t* kidx;
 };
 
 constexpr uint32_t META_INLINE_MAX = 4;  // array values held in a packed record
+constexpr uint32_t KIDX_WORDS = 1024;
+// Whether count-only calls and plans build a key index for their pools: when a
+// bitmap has at least this many keys on average (fewer fit the LDS window).
+constexpr uint64_t KIDX_MIN_MEAN_KEYS = 1024;
+void launch_key_index(const PoolView& P, uint32_t n_bitmaps, uint8_t* out, hipStream_t st);
 // A count-only call packs its pools' metadata when it visits at least this many
 // candidate keys per container of the pools (packing costs one pass over them).
 constexpr uint64_t META_PACK_FACTOR = 4;
@@ -323,16 +332,6 @@ void launch_mat_counts(int op, const uint64_t* bm_card, PoolView A, PoolView B, 
                        const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs, uint64_t* d_cards,
                        double* d_jacc, hipStream_t st);
 
-// persistent work-stealing count kernel (batched plans)
-struct PersistArgs {
-    PoolView A, B;
-    const Task* tasks;
-    const uint32_t* lists;     // bin lists
-    const uint32_t* bin_info;  // [NBINS] counts, then [NBINS] offsets (device)
-    uint32_t* next;            // [NBINS] work counters, reset with the bin layout
-    long long* acc;
-};
-void launch_persist(const PersistArgs& a, uint32_t grid, hipStream_t st);
 
 // Which count variants may take a matched pair (forced and learned dispatch;
 // the generic variant takes any pair). A forced or learned thread-per-pair

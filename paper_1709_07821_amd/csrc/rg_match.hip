@@ -165,6 +165,25 @@ __device__ __forceinline__ uint8_t classify(int op, bool materialize, uint8_t ki
 
 constexpr uint32_t MATCH_LDS_KEYS = 4096;
 
+// LDS of key matching when a block's candidates all belong to one pair: the
+// searched side's keys in the candidates' range (window), or, with a key
+// index, its presence words and ranks over that range.
+union MatchLds {
+    uint16_t lkeys[MATCH_LDS_KEYS];
+    struct {
+        uint64_t words[KIDX_WORDS];
+        uint16_t rank[KIDX_WORDS];
+    } kx;
+};
+
+// Looks `key` up in the key index of one bitmap (presence word x, rank of the
+// word): its container's position among the bitmap's keys, or NONE.
+__device__ __forceinline__ uint32_t kidx_lookup(uint64_t x, uint32_t rank, uint16_t key) {
+    const uint32_t bit = key & 63u;
+    if (!((x >> bit) & 1ull)) return NONE;
+    return rank + (uint32_t)__popcll(x & ((1ull << bit) - 1ull));
+}
+
 // What matching decided for one candidate slot.
 struct SlotOutcome {
     Task task;
@@ -255,10 +274,23 @@ __device__ __forceinline__ void match_slot_global(const MatchArgs& m, uint64_t t
         const uint16_t* sk = a_small ? m.A.keys + a0 : m.B.keys + b0;
         const uint16_t* lk = a_small ? m.B.keys + b0 : m.A.keys + a0;
         const uint32_t nl = a_small ? KB : KA;
+        const uint8_t* lidx = a_small ? m.B.kidx : m.A.kidx;
         const uint16_t key = sk[u];
-        const uint32_t j = lower_bound_u16(lk, nl, key);
+        uint32_t j;
+        bool hit;
+        if (lidx) {
+            // key index of the searched bitmap: presence bit, then rank + popcount
+            const uint8_t* ix = lidx + (uint64_t)(a_small ? b : a) * RG_KEY_INDEX_BYTES;
+            const uint32_t wi = key >> 6;
+            j = kidx_lookup(reinterpret_cast<const uint64_t*>(ix)[wi],
+                            reinterpret_cast<const uint16_t*>(ix + 8 * KIDX_WORDS)[wi], key);
+            hit = j != NONE;
+        } else {
+            j = lower_bound_u16(lk, nl, key);
+            hit = j < nl && lk[j] == key;
+        }
         task.key = key;
-        if (j < nl && lk[j] == key) {
+        if (hit) {
             task.kind = KIND_MATCH;
             task.ia = (uint32_t)(a_small ? a0 + u : a0 + j);
             task.ib = (uint32_t)(a_small ? b0 + j : b0 + u);
@@ -287,8 +319,9 @@ __device__ __forceinline__ void match_slot_global(const MatchArgs& m, uint64_t t
 // the caller's: pl_range[2], lwin[2], lkeys[MATCH_LDS_KEYS]. Contains barriers;
 // the whole workgroup calls it.
 __device__ __forceinline__ void match_block(const MatchArgs& m, uint64_t n_cand, uint64_t t0, uint32_t* cnt,
-                                            uint32_t* pl_range, uint32_t* lwin, uint16_t* lkeys,
+                                            uint32_t* pl_range, uint32_t* lwin, MatchLds& lds,
                                             SlotOutcome (&o)[MATCH_PER_THREAD]) {
+    uint16_t* lkeys = lds.lkeys;
     if (threadIdx.x < NBINS) cnt[threadIdx.x] = 0;
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
     // the pairs of this block's first and last candidate bound every thread's
@@ -305,9 +338,9 @@ __device__ __forceinline__ void match_block(const MatchArgs& m, uint64_t n_cand,
     // of the other side lie in one window; stage that window in LDS and search
     // there instead of in global memory. Wave 0 finds the window's first index
     // (first key >= the first candidate), wave 1 its end (first key > the last).
-    bool staged = false;
+    bool staged = false, kstaged = false;
     uint64_t o_a0 = 0, o_b0 = 0, o_base = 0;
-    uint32_t o_p = 0, win_lo = 0, win_n = 0;
+    uint32_t o_p = 0, win_lo = 0, win_n = 0, w0 = 0;
     bool o_a_small = true;
     const uint16_t* o_sk = nullptr;
     if (!m.materialize && pl_lo == pl_hi) {
@@ -320,26 +353,45 @@ __device__ __forceinline__ void match_block(const MatchArgs& m, uint64_t n_cand,
         const uint16_t* sk = a_small ? m.A.keys + a0 : m.B.keys + b0;
         const uint16_t* lk = a_small ? m.B.keys + b0 : m.A.keys + a0;
         const uint32_t nl = a_small ? KB : KA;
+        const uint8_t* lidx = a_small ? m.B.kidx : m.A.kidx;
         const uint64_t base = uniform64(m.cand_off[pl_lo]);
-        if (wid < 2) {
-            const uint16_t key = (uint16_t)uniform(sk[(wid == 0 ? t0 : tl) - base]);
-            const uint32_t j = wid == 0 ? wave_partition_point(nl, lane, [&](uint32_t i) { return lk[i] < key; })
-                                        : wave_partition_point(nl, lane, [&](uint32_t i) { return lk[i] <= key; });
-            if (lane == 0) lwin[wid] = j;
-        }
-        __syncthreads();
-        const uint32_t lo = uniform(lwin[0]), hi = uniform(lwin[1]);
-        if (hi - lo <= MATCH_LDS_KEYS) {
-            staged = true;
-            for (uint32_t i = threadIdx.x; i < hi - lo; i += blockDim.x) lkeys[i] = lk[lo + i];
+        if (lidx) {
+            // The candidates are consecutive keys of the smaller side: stage the
+            // searched bitmap's presence words and ranks over their key range
+            // (at most 1024 words); each candidate is then a bit test and a
+            // popcount in LDS.
+            const uint32_t kf = uniform(sk[t0 - base]), kl = uniform(sk[tl - base]);
+            w0 = kf >> 6;
+            const uint32_t nw = (kl >> 6) - w0 + 1;
+            const uint8_t* ix = lidx + (uint64_t)(a_small ? b : a) * RG_KEY_INDEX_BYTES;
+            const uint64_t* iw = reinterpret_cast<const uint64_t*>(ix) + w0;
+            const uint16_t* ir = reinterpret_cast<const uint16_t*>(ix + 8 * KIDX_WORDS) + w0;
+            for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) {
+                lds.kx.words[i] = iw[i];
+                lds.kx.rank[i] = ir[i];
+            }
+            kstaged = true;
+        } else {
+            if (wid < 2) {
+                const uint16_t key = (uint16_t)uniform(sk[(wid == 0 ? t0 : tl) - base]);
+                const uint32_t j = wid == 0 ? wave_partition_point(nl, lane, [&](uint32_t i) { return lk[i] < key; })
+                                            : wave_partition_point(nl, lane, [&](uint32_t i) { return lk[i] <= key; });
+                if (lane == 0) lwin[wid] = j;
+            }
+            __syncthreads();
+            const uint32_t lo = uniform(lwin[0]), hi = uniform(lwin[1]);
+            if (hi - lo <= MATCH_LDS_KEYS) {
+                staged = true;
+                for (uint32_t i = threadIdx.x; i < hi - lo; i += blockDim.x) lkeys[i] = lk[lo + i];
+            }
+            win_lo = lo;
+            win_n = hi - lo;
         }
         __syncthreads();
         o_a0 = a0;
         o_b0 = b0;
         o_base = base;
         o_p = (uint32_t)p;
-        win_lo = lo;
-        win_n = hi - lo;
         o_a_small = a_small;
         o_sk = sk;
     }
@@ -354,7 +406,29 @@ __device__ __forceinline__ void match_block(const MatchArgs& m, uint64_t n_cand,
         o[k].fused_pair = NONE;
         o[k].fused_inter = 0;
     }
-    if (staged) {
+    if (kstaged) {
+#pragma unroll
+        for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
+            const uint64_t t = t0 + (uint64_t)k * 256 + threadIdx.x;
+            if (t >= n_cand) continue;
+            const uint64_t u = t - o_base;
+            const uint16_t key = o_sk[u];
+            const uint32_t wi = (uint32_t)(key >> 6) - w0;
+            const uint32_t j = kidx_lookup(lds.kx.words[wi], lds.kx.rank[wi], key);
+            Task& task = o[k].task;
+            task.pair = o_p;
+            task.key = key;
+            if (j != NONE) {
+                task.kind = KIND_MATCH;
+                task.ia = (uint32_t)(o_a_small ? o_a0 + u : o_a0 + j);
+                task.ib = (uint32_t)(o_a_small ? o_b0 + j : o_b0 + u);
+            }
+            o[k].slot = t;
+        }
+#pragma unroll
+        for (int k = 0; k < (int)MATCH_PER_THREAD; ++k)
+            if (o[k].slot != NONE) finish_slot(m, cnt, o[k]);
+    } else if (staged) {
         // every step for all of the thread's candidates before the next step
         uint32_t top = 0;
         if (win_n) top = 1u << (31 - __builtin_clz(win_n));
@@ -406,10 +480,10 @@ __device__ __forceinline__ void match_block(const MatchArgs& m, uint64_t n_cand,
 __global__ void __launch_bounds__(256) k_match(MatchArgs m) {
     __shared__ uint32_t cnt[NBINS];
     __shared__ uint32_t pl_range[2];
-    __shared__ uint16_t lkeys[MATCH_LDS_KEYS];
+    __shared__ MatchLds lds;
     __shared__ uint32_t lwin[2];  // first index of the staged window in the searched list, and its end
     SlotOutcome o[MATCH_PER_THREAD];
-    match_block(m, m.n_cand, (uint64_t)blockIdx.x * MATCH_SLOTS, cnt, pl_range, lwin, lkeys, o);
+    match_block(m, m.n_cand, (uint64_t)blockIdx.x * MATCH_SLOTS, cnt, pl_range, lwin, lds, o);
     if (m.fuse_thread) {
 #pragma unroll
         for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) wave_aggregate_add(m.acc, o[k].fused_pair, o[k].fused_inter);
@@ -448,8 +522,8 @@ void launch_match(const MatchArgs& m, hipStream_t st) {
 struct FusedShared {
     Task items[MATCH_SLOTS];  // workgroup items from the front, wave items from the back
     union {
-        WgShared sh;                   // processing
-        uint16_t lkeys[MATCH_LDS_KEYS];  // key matching's staged window
+        WgShared sh;    // processing
+        MatchLds m;     // key matching's staged window or key-index words
     } u;
     uint32_t cnt[NBINS];
     uint32_t pl_range[2];
@@ -480,7 +554,7 @@ __global__ void __launch_bounds__(256) k_count_fused(MatchArgs m, uint32_t* next
             break;
         }
         SlotOutcome o[MATCH_PER_THREAD];
-        match_block(m, n_cand, (uint64_t)blk * MATCH_SLOTS, f.cnt, f.pl_range, f.lwin, f.u.lkeys, o);
+        match_block(m, n_cand, (uint64_t)blk * MATCH_SLOTS, f.cnt, f.pl_range, f.lwin, f.u.m, o);
 #pragma unroll
         for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) wave_aggregate_add(m.acc, o[k].fused_pair, o[k].fused_inter);
         if (m.matched) {

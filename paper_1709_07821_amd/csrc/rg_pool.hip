@@ -257,4 +257,43 @@ void launch_pack_meta(const PoolView& P, uint64_t n, u32x4* out, hipStream_t st)
     if (n) hipLaunchKernelGGL(k_pack_meta, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, P, n, out);
 }
 
+// ------------------------------------------------------------------ key index
+// One workgroup per bitmap: the presence bit of every key, then each word's
+// rank (keys in the words before it) by a workgroup prefix sum of popcounts.
+__global__ void __launch_bounds__(256) k_key_index(PoolView P, uint8_t* out) {
+    __shared__ uint64_t w[KIDX_WORDS];
+    __shared__ uint32_t tmp[8];
+    const uint32_t b = blockIdx.x, tid = threadIdx.x;
+    for (uint32_t i = tid; i < KIDX_WORDS; i += 256) w[i] = 0;
+    __syncthreads();
+    const uint64_t s = P.bm_begin[b], e = P.bm_begin[b + 1];
+    for (uint64_t i = s + tid; i < e; i += 256) {
+        const uint32_t k = P.keys[i];
+        atomicOr(reinterpret_cast<unsigned long long*>(&w[k >> 6]), 1ull << (k & 63));
+    }
+    __syncthreads();
+    uint64_t x[4];
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        x[j] = w[4 * tid + j];
+        c += __popcll(x[j]);
+    }
+    uint32_t tot;
+    uint32_t r = block_excl_scan_u32(c, tmp, &tot);
+    uint8_t* o = out + (uint64_t)b * RG_KEY_INDEX_BYTES;
+    uint64_t* ow = reinterpret_cast<uint64_t*>(o);
+    uint16_t* orank = reinterpret_cast<uint16_t*>(o + 8 * KIDX_WORDS);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        ow[4 * tid + j] = x[j];
+        orank[4 * tid + j] = (uint16_t)r;
+        r += __popcll(x[j]);
+    }
+}
+
+void launch_key_index(const PoolView& P, uint32_t n_bitmaps, uint8_t* out, hipStream_t st) {
+    if (n_bitmaps) hipLaunchKernelGGL(k_key_index, dim3(n_bitmaps), dim3(256), 0, st, P, out);
+}
+
 }  // namespace rg

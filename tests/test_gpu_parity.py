@@ -398,7 +398,8 @@ def _key_matching_layouts():
 
 
 def test_key_matching_block_layouts(rg, ctx):
-    """Pairs of 65536-key bitmaps (more than 2^24 candidate slots: two waves,
+    """Pairs of 65536-key bitmaps (more than 2^24 candidate slots: two waves of
+    the materialising path, one launch of the fused count kernel;
     blocks inside one pair with no staged window) interleaved with empty,
     one-key and small pairs (blocks spanning many pairs, pairs without
     candidates); every count and Jaccard index, eager and as a plan, equals
@@ -423,7 +424,7 @@ def test_key_matching_block_layouts(rg, ctx):
         assert np.array_equal(c.cpu().numpy().view(np.uint64), exp), op
         assert np.array_equal(j.cpu().numpy(), jexp), op
         pl = rg.Plan(ctx, op, P, P, tia, tib, card=True, jaccard=True)
-        assert pl.info()["waves"] >= 2
+        assert pl.info()["slots"] > 1 << 24
         pl.execute()
         torch.cuda.synchronize()
         assert np.array_equal(pl.cards.cpu().numpy().view(np.uint64), exp), op
@@ -504,3 +505,61 @@ def test_array_stress_full_size_materialised(rg, ctx):
             got, meta = rgtest.decode_bitmap(h, int(p))
             assert np.array_equal(got, e) and meta == rgtest.oracle_meta(oracle, e), (op, p)
         del out, res, h
+
+
+def test_key_index_layout_and_matching(rg, ctx):
+    """The key-presence index (rg_pool_key_index) holds every key's bit and each
+    word's rank, as a numpy construction of the same layout; pools carrying it
+    (keys found by bit test and popcount, in LDS for single-pair blocks and in
+    global memory otherwise) give the oracle's counts and Jaccard indices,
+    eagerly and through a plan, with and without packed records."""
+    import torch
+
+    sets = rgtest.edge_sets() + [synth.mixed_small(n_bitmaps=16, seed=91)[i] for i in range(16)]
+    bs = synth.BitmapSet.from_list(sets)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    P.key_index(ctx)
+    torch.cuda.synchronize()
+    kx = P.kidx.cpu().numpy().reshape(len(bs), rg.RG_KEY_INDEX_BYTES)
+    h = P.to_host()
+    for b in range(len(bs)):
+        keys = h["keys"][int(h["bm_begin"][b]):int(h["bm_begin"][b + 1])].astype(np.int64)
+        words = np.zeros(1024, np.uint64)
+        np.bitwise_or.at(words, keys >> 6, np.left_shift(np.uint64(1), (keys & 63).astype(np.uint64)))
+        pc = np.array([bin(int(w)).count("1") for w in words], np.int64)
+        ranks = (np.cumsum(pc) - pc).astype(np.uint16)
+        assert np.array_equal(kx[b, :8192].view(np.uint64), words), b
+        assert np.array_equal(kx[b, 8192:].view(np.uint16), ranks), b
+    k = len(sets)
+    ia = np.repeat(np.arange(k), k).astype(np.uint32)
+    ib = np.tile(np.arange(k), k).astype(np.uint32)
+    tia, tib = _t(ia), _t(ib)
+    for packed in (False, True):
+        if packed:
+            P.pack_meta(ctx)
+        for op in OPS:
+            _say(f"[key index] packed={packed} op={op} pairs={len(ia)}")
+            exp, _, jexp = oracle.pairs(op, bs.values, bs.offsets, bs.values, bs.offsets, ia, ib, want_jaccard=True)
+            _, c, j = rg.batch(ctx, op, P, P, tia, tib, materialize=False, card=True, jaccard=True)
+            torch.cuda.synchronize()
+            assert np.array_equal(c.cpu().numpy().view(np.uint64), exp), (packed, op)
+            assert np.array_equal(j.cpu().numpy(), jexp), (packed, op)
+            pl = rg.Plan(ctx, op, P, P, tia, tib, card=True, jaccard=True)
+            pl.execute()
+            torch.cuda.synchronize()
+            assert np.array_equal(pl.cards.cpu().numpy().view(np.uint64), exp), (packed, op)
+            assert np.array_equal(pl.jacc.cpu().numpy(), jexp), (packed, op)
+            pl.close()
+    # the 65536-key layouts with an index (single-pair blocks staged in LDS)
+    lb = _key_matching_layouts()
+    L = rg.Pool.from_sets(lb.values, lb.offsets)
+    L.key_index(ctx)
+    rng = np.random.default_rng(92)
+    xa = rng.integers(0, len(lb), 300).astype(np.uint32)
+    xb = rng.integers(0, len(lb), 300).astype(np.uint32)
+    for op in OPS:
+        exp, _, jexp = oracle.pairs(op, lb.values, lb.offsets, lb.values, lb.offsets, xa, xb, want_jaccard=True)
+        _, c, j = rg.batch(ctx, op, L, L, _t(xa), _t(xb), materialize=False, card=True, jaccard=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(c.cpu().numpy().view(np.uint64), exp), op
+        assert np.array_equal(j.cpu().numpy(), jexp), op
