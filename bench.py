@@ -679,7 +679,8 @@ def bench_batched(args):
         alg = per_matched * matched
         mean_s = kf["ms"] / kf["launches"] / 1e3
         roof = {"bound": "hbm", "achieved": round(alg / mean_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(alg / mean_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(alg / mean_s / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic("k_count_fused_batched_uneven.md"),
                 "kernel": "k_count_fused (eager batched call)", "mean_launch_ms": round(mean_s * 1e3, 3),
                 "launches": int(kf["launches"]), "bytes_per_launch": int(alg),
                 "bytes_per_matched_pair": round(per_matched, 1),
@@ -1032,10 +1033,10 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per fused count launch from the committed FETCH_SIZE/WRITE_SIZE
+def measured_traffic(summary="k_count_fused_dense_bitsets.md"):
+    """HBM bytes per fused count launch from a committed FETCH_SIZE/WRITE_SIZE
     summary, or None when the kernel sources have changed since it was taken."""
-    prof = os.path.join(ROOT, "profiles", "k_count_fused_dense_bitsets.md")
+    prof = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(prof):
         return None
     text = open(prof).read()
