@@ -411,8 +411,14 @@ def bench_pairs_materialised(args, bs, ia, ib, workload, metric_config):
     out_bytes = {op: out_pay[op][0] + META_BYTES * out_pay[op][1] for op in OPS4}
     step_in = sum(in_bytes.values())
     matched = int(st["matched"].sum())
-    # roofline: k_kw_eval reads the containers of every result key and writes the result
-    kw = prof.get(("kway-eval", True))
+    # roofline: the k-way evaluation step (the one-wave array kernel and the
+    # workgroup kernel, one launch each per call) reads the containers of every
+    # result key of the union, symmetric difference and difference and writes
+    # the result; its duration is the two launches'
+    kw = dict(prof.get(("kway-eval", True)) or {"ms": 0.0, "launches": 0})
+    ks = prof.get(("kway-small", True))
+    if ks:
+        kw["ms"] += ks["ms"]
     roof = None
     if kw and kw["launches"]:
         kw_bytes = sum(float((st["payA"] + st["payB"]).sum()) for op in ("or", "xor")) + \
@@ -420,11 +426,14 @@ def bench_pairs_materialised(args, bs, ia, ib, workload, metric_config):
         kw_bytes *= args.steps
         ach = kw_bytes / (kw["ms"] / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_kw_eval",
+                "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
+                "kernel": "k_kw_small + k_kw_eval (k-way evaluation step)",
                 "mean_launch_ms": round(kw["ms"] / kw["launches"], 4), "launches": int(kw["launches"]),
                 "bytes_per_launch": int(kw_bytes / kw["launches"]),
                 "share_of_step": round(kw["ms"] / (dt_prof * 1e3 * args.steps), 3)}
-    kernels = {f"{k[0]}{'-mat' if k[1] else ''}": round(v["ms"] / args.steps, 4) for k, v in prof.items() if v["ms"]}
+    # class 3 materialised is the one-wave array kernel on intersections
+    kernels = {f"{'wave-array' if k == ('merge', True) else k[0]}{'-mat' if k[1] else ''}": round(v["ms"] / args.steps, 4)
+               for k, v in prof.items() if v["ms"]}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -946,9 +955,9 @@ def bench_serve(args):
         rows.append(row)
     best = max(r["batched"]["achieved_qps"] for r in rows)
 
-    # roofline of the evaluation kernel on queries of the same mix, one
-    # roaring_multi call each (k_kw_eval reads every container of each result
-    # key and writes the result): bytes from the host pool arrays
+    # roofline of the evaluation step on queries of the same mix, one
+    # roaring_multi call each (its kernels read every container of each result
+    # key and write the result): bytes from the host pool arrays
     roof, cpu = serve_roofline_and_cpu(args, ctx, P, h, make_queries(64), gen)
     line = {
         "metric": "queries/sec and p50/p99 latency, k-way AND/OR serving (continuous batching)",
@@ -993,7 +1002,10 @@ def serve_roofline_and_cpu(args, ctx, P, h, qs, gen):
         out, _ = rg.multi(ctx, op, P, d_ids, materialize=True, card=True)
         out_bytes += result_payload_bytes(out)[0]
     torch.cuda.synchronize()
-    kw = rg.profile_read(ctx).get(("kway-eval", True))
+    pr = rg.profile_read(ctx)
+    kw = dict(pr.get(("kway-eval", True)) or {"ms": 0.0, "launches": 0})
+    if pr.get(("kway-small", True)):  # queries of two bitmaps with an array side
+        kw["ms"] += pr[("kway-small", True)]["ms"]
     rg.profile_enable(ctx, False)
     roof = None
     if kw and kw["launches"]:
@@ -1001,7 +1013,8 @@ def serve_roofline_and_cpu(args, ctx, P, h, qs, gen):
         ach = tot / (kw["ms"] / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_kw_eval (one roaring_multi call per query, materialised)",
+                "kernel": "k_kw_small + k_kw_eval (k-way evaluation step; one roaring_multi call per query, "
+                          "materialised)",
                 "mean_launch_ms": round(kw["ms"] / kw["launches"], 4), "launches": int(kw["launches"]),
                 "bytes_per_launch": int(tot / kw["launches"]),
                 "sample": f"{len(qs)} queries of the mix, all materialised"}

@@ -9,7 +9,7 @@ LIB = os.path.join(HERE, "libroaring_gpu.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["rg_api.cpp", "rg_build_host.cpp", "rg_match.hip", "rg_bitset.hip", "rg_generic.hip",
            "rg_variants.hip", "rg_assemble.hip", "rg_pool.hip", "rg_kway.hip", "rg_serve.cpp", "rg_mlp.hip", "rg_dispatch.cpp",
-           "rg_access.hip", "rg_access_api.cpp", "rg_mutable.hip", "rg_mutable_api.cpp"]
+           "rg_access.hip", "rg_access_api.cpp", "rg_mutable.hip", "rg_mutable_api.cpp", "rg_small.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -420,9 +420,11 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
             ka.so.err = d_err;
             ka.acc = nullptr;
             ka.err = d_err;
+            ka.small = !(c->dispatch_mode == 2 && c->fixed_bin == BIN_GEN);
             launch_kw_keys(ka, st);
             launch_kw_bounds(ka, st);
             launch_scan_u32_u64(ub, slot_off, C, pay_base, partials, totals, st);
+            timed(c, PROF_KWSMALL, true, C, st, [&] { launch_kw_small(ka, st); });
             timed(c, PROF_KWEVAL, true, C, st, [&] { launch_kw_eval(ka, st); });
         } else {
             MatchArgs m;
@@ -501,7 +503,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
                 timed(c, b, mat, cnt[b], st, [&] {
                     switch (b) {
                     case BIN_BB: launch_bb(ca, st); break;
-                    case BIN_AA: launch_aa(ca, st); break;
+                    case BIN_AA: mat ? launch_small_list(ca, st) : launch_aa(ca, st); break;
                     case BIN_GALLOP: launch_gallop(ca, st); break;
                     case BIN_AB: launch_ab(ca, st); break;
                     case BIN_RR: launch_rr(ca, st); break;
@@ -1052,10 +1054,12 @@ void plan_enqueue_mat(rg_plan* p, hipStream_t st) {
         ka.so.err = p->err;
         ka.acc = nullptr;
         ka.err = p->err;
+        ka.small = !(p->ctx->dispatch_mode == 2 && p->ctx->fixed_bin == BIN_GEN);
         launch_kw_keys(ka, st);
         launch_kw_bounds(ka, st);
         // slot payload offsets continue from the previous wave's payload end
         launch_scan_u32_u64(p->ub, p->slot_off, wv.C, 0, p->partials, p->totals, st, p->totals);
+        launch_kw_small(ka, st);
         launch_kw_eval(ka, st);
         // output indices continue from the previous wave's container count
         launch_scan_nonzero_u64(p->res_card, p->out_idx, wv.C, 0, p->partials, p->totals + 1, st, p->totals + 1);

@@ -15,22 +15,46 @@
 
 namespace rg {
 
+// A pair's slots are consecutive, so the 64 slots of a wave belong to a few
+// runs of equal pair index: the per-bitmap totals are summed over each run
+// (segmented scan over the lanes) and added by its last lane, one atomic per
+// run instead of one per slot (thousands of slots of one pair otherwise
+// serialise on its two counters).
 __global__ void k_compact(CompactArgs c) {
-    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < c.n_slots;
-         s += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t card = c.res_card[s];
-        if (!card) continue;
-        const uint64_t i = c.out_idx[s];
-        const Task t = c.tasks[s];
-        c.keys[i] = t.key;
-        c.types[i] = c.res_type[s];
-        c.card[i] = card;
-        c.size[i] = c.res_size[s];
-        c.off[i] = c.slot_off[s];
-        atomicAdd(reinterpret_cast<unsigned long long*>(&c.bm_card[t.pair]), (unsigned long long)card);
-        if (c.bm_wbytes)
-            atomicAdd(reinterpret_cast<unsigned long long*>(&c.bm_wbytes[t.pair]),
-                      (unsigned long long)wbytes_of(card));
+    const uint32_t lane = lane_id();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < c.n_slots; base += stride) {
+        const uint64_t s = base + lane;
+        uint32_t card = 0, pair = 0xFFFFFFFFu;
+        if (s < c.n_slots) {
+            card = c.res_card[s];
+            const Task t = c.tasks[s];
+            pair = t.pair;
+            if (card) {
+                const uint64_t i = c.out_idx[s];
+                c.keys[i] = t.key;
+                c.types[i] = c.res_type[s];
+                c.card[i] = card;
+                c.size[i] = c.res_size[s];
+                c.off[i] = c.slot_off[s];
+            }
+        }
+        uint64_t sc = card, sw = card ? wbytes_of(card) : 0u;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint64_t uc = __shfl_up(sc, o), uw = __shfl_up(sw, o);
+            const uint32_t up = __shfl_up(pair, o);
+            if (lane >= (uint32_t)o && up == pair) {  // pairs do not decrease along the slots
+                sc += uc;
+                sw += uw;
+            }
+        }
+        const uint32_t next = __shfl_down(pair, 1);
+        const bool last = lane == 63 || next != pair;
+        if (last && pair != 0xFFFFFFFFu && sc) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&c.bm_card[pair]), (unsigned long long)sc);
+            if (c.bm_wbytes) atomicAdd(reinterpret_cast<unsigned long long*>(&c.bm_wbytes[pair]), (unsigned long long)sw);
+        }
     }
 }
 

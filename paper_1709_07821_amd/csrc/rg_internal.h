@@ -36,7 +36,8 @@ enum : uint8_t {
 // profile classes beyond the bins
 constexpr int PROF_FUSED = 10;  // the fused match-and-count kernel of asynchronous count-only calls
 constexpr int PROF_KWEVAL = 11; // k-way evaluation of materialised unions, differences, symmetric differences
-constexpr int NPROF = 12;
+constexpr int PROF_KWSMALL = 12; // the one-wave array kernel on k-way slots
+constexpr int NPROF = 13;
 
 struct Task {
     uint32_t pair;
@@ -300,6 +301,8 @@ void launch_gallop(const ComputeArgs& a, hipStream_t st);
 void launch_ab(const ComputeArgs& a, hipStream_t st);
 void launch_rr(const ComputeArgs& a, hipStream_t st);
 void launch_thread(const ComputeArgs& a, hipStream_t st);
+// materialised intersections listed in bin BIN_AA (small_mat_ok): one wave per pair
+void launch_small_list(const ComputeArgs& a, hipStream_t st);
 
 struct CompactArgs {
     const Task* tasks;
@@ -381,7 +384,33 @@ void launch_gather_rows(const float* X, const float* T, const uint8_t* M, const 
 void launch_accum_scaled(const float* x, float* acc, float scale, hipStream_t st);
 void launch_mlp_table(const float* P, uint8_t* table, hipStream_t st);
 
+// Materialised pairs built by the one-wave array kernels (rg_small.hip);
+// types 0 = absent (size 0). Union and symmetric difference: two arrays, or
+// one, with at most SMALL_MAX values together. Intersection: an array side
+// (with fewer values when both are arrays); the other side any container, an
+// array of at most SMALL_MAX values. Difference: an array first operand; the
+// second any container or absent, an array of at most SMALL_MAX values. Every
+// such result has at most SMALL_MAX values: an array or runs, never a bitset.
+constexpr uint32_t SMALL_MAX = 4096;
+constexpr uint32_t SMALL_LDS = SMALL_MAX + 8;  // values staged per wave (the second array starts 16-byte aligned)
+__host__ __device__ __forceinline__ bool small_mat_ok(int op, uint8_t ta, uint8_t tb, uint32_t sa, uint32_t sb) {
+    const bool aa = ta == RG_ARRAY, ba = tb == RG_ARRAY;
+    if (op == RG_OR || op == RG_XOR)
+        return (aa || ta == 0) && (ba || tb == 0) && (ta || tb) && (uint64_t)sa + sb <= SMALL_MAX;
+    if (op == RG_AND) {
+        if (aa && ba) return sa <= SMALL_MAX && sb <= SMALL_MAX;
+        return (aa && sa <= SMALL_MAX && tb != 0) || (ba && sb <= SMALL_MAX && ta != 0);
+    }
+    if (op == RG_ANDNOT) return aa && sa <= SMALL_MAX && (!ba || sb <= SMALL_MAX);
+    return false;
+}
+
 // k-way queries over one pool (rg_kway.hip)
+// Task.bin of a k-way result key whose containers are recorded in Task.ia
+// (first bitmap) and Task.ib (second), NONE where absent: queries of k <= 2.
+constexpr uint8_t KW_TASK_INDEXED = 1;
+// ... and whose result the one-wave array kernel builds (set by the bounds kernel)
+constexpr uint8_t KW_TASK_SMALL = 2;
 constexpr uint32_t KW_MATERIALIZE = 1u;  // KwQuery.flags: build the result containers
 constexpr uint32_t KW_MAX_K = 256;       // bitmaps per query (one lookup thread each)
 struct KwQuery {
@@ -408,11 +437,15 @@ struct KwArgs {
     SlotOut so;
     long long* acc;     // per query, count-only results
     uint32_t* err;      // set when a query's key set exceeds its slot range
+    uint32_t small = 1; // materialised results with an array side go to the one-wave kernel
 };
 void launch_kw_step_init(uint64_t* totals, uint32_t* err, long long* acc, uint64_t* bm_card, uint64_t* bm_wbytes,
                          uint32_t nq, hipStream_t st);
 void launch_kw_keys(const KwArgs& a, hipStream_t st);
 void launch_kw_bounds(const KwArgs& a, hipStream_t st);
+// the two evaluation kernels: the one-wave array kernel for the slots the
+// bounds kernel marked (rg_small.hip), the workgroup kernel for the others
+void launch_kw_small(const KwArgs& a, hipStream_t st);
 void launch_kw_eval(const KwArgs& a, hipStream_t st);
 void launch_kw_cards(const KwArgs& a, const uint64_t* bm_card, uint64_t* cards, hipStream_t st);
 // queries q < n_pairs for pairs pair0 + q (k = 2: A side, B side), slot ranges

@@ -8,12 +8,14 @@
 //   1. k_kw_keys: one workgroup per query builds the query's result key set as
 //      a 65536-bit LDS mask (AND of the bitmaps' key masks, or OR), writes the
 //      keys in ascending order as one task per result key, and marks the rest
-//      of the query's slot range empty.
+//      of the query's slot range empty (k_kw_keys_small: the same for queries
+//      of one or two bitmaps with few keys, one wave each).
 //   2. k_kw_bounds: one wave per slot looks the key up in the k bitmaps (one
 //      lane per bitmap) and bounds the result payload (AND: the smallest
 //      container, OR: the sum, both capped at a bitset) - the slot sizes of
-//      step 3.
-//   3. k_kw_eval: one workgroup per result key. Intersection: every container
+//      step 3. Materialised slots of one or two bitmaps with an array side
+//      (small_mat_ok) are marked for the one-wave array kernel (rg_small.hip).
+//   3. k_kw_eval: one workgroup per remaining result key. Intersection: every container
 //      is expanded into an LDS bitset and combined word by word, stopping once
 //      the running result is empty. Union, symmetric difference, difference:
 //      bitset containers are combined in registers (each thread owns four
@@ -28,9 +30,7 @@
 namespace rg {
 
 constexpr int KW_UNROLL = 4;  // independent loads in flight per thread in the key and fold passes
-// Task.bin of a k-way result key whose containers are recorded in Task.ia
-// (first bitmap) and Task.ib (second), NONE where absent: queries of k <= 2.
-constexpr uint8_t KW_TASK_INDEXED = 1;
+constexpr uint32_t KW_EVAL_CHUNK = 4;  // slots whose tasks the evaluation workgroup reads at once (measured: 1, 4, 16)
 
 __device__ __forceinline__ uint32_t kw_find_key(const uint64_t* bm_begin, const uint16_t* keys, uint32_t b,
                                                 uint16_t key) {
@@ -62,14 +62,145 @@ __device__ __forceinline__ PoolView kw_side(const KwArgs& a, bool second) {
 }
 
 // ---------------------------------------------------------------- 1. keys
-__global__ void __launch_bounds__(256) k_kw_keys(KwArgs a) {
+// Queries of one or two bitmaps with at most KW_KEYS_SMALL keys together are
+// built by k_kw_keys_small, one wave per query: the two sorted key lists,
+// staged in LDS, are walked in merged order (union and symmetric difference)
+// or the first list is filtered (intersection: keys the second list holds;
+// difference: all of them), 64 keys per round; a ballot gives each result key
+// its slot. The workgroup kernel below takes the other queries.
+constexpr uint32_t KW_KEYS_SMALL = 1024;
+constexpr uint32_t KW_KEYS_CHUNK = 8;  // most queries whose sizes the workgroup kernel reads at once
+
+__global__ void __launch_bounds__(256) k_kw_keys_small(KwArgs a) {
+    __shared__ uint16_t lk[4][KW_KEYS_SMALL + 8];
+    const uint32_t wid = threadIdx.x >> 6, lane = lane_id();
+    const uint32_t q = wave_index();
+    if (q >= a.n_queries) return;
+    const KwQuery Q = a.queries[q];
+    const uint32_t op = uniform(Q.op), k = uniform(Q.k), ids0 = uniform(Q.ids_off);
+    if (k > 2) return;
+    const uint64_t slot0 = uniform64(Q.slot0);
+    const uint32_t kbound = uniform(Q.kbound);
+    const uint32_t b0 = uniform(a.ids[ids0]);
+    const uint64_t s0 = uniform64(a.P0.bm_begin[b0]);
+    const uint32_t n0 = uniform((uint32_t)(a.P0.bm_begin[b0 + 1] - s0));
+    uint64_t s1 = 0;
+    uint32_t n1 = 0;
+    if (k == 2) {
+        const uint32_t b1 = uniform(a.ids[ids0 + 1]);
+        s1 = uniform64(a.P1.bm_begin[b1]);
+        n1 = uniform((uint32_t)(a.P1.bm_begin[b1 + 1] - s1));
+    }
+    if (n0 + n1 > KW_KEYS_SMALL) return;  // the workgroup kernel's
+    uint16_t* A = lk[wid];
+    uint16_t* B = lk[wid] + ((n0 + 7u) & ~7u);
+    for (uint32_t i = lane; i < n0; i += 64) A[i] = a.P0.keys[s0 + i];
+    for (uint32_t i = lane; i < n1; i += 64) B[i] = a.P1.keys[s1 + i];
+    __builtin_amdgcn_wave_barrier();
+    const bool merge = op == RG_OR || op == RG_XOR;
+    const uint32_t n = merge ? n0 + n1 : n0;
+    uint32_t pos = 0;
+    for (uint32_t base = 0; base < n; base += 64) {
+        const uint32_t p = base + lane;
+        bool keep = false;
+        uint32_t key = 0, ia = NONE, ib = NONE;
+        if (p < n) {
+            if (merge) {
+                // merge path: i = keys of the first list among the first p
+                uint32_t lo = p > n1 ? p - n1 : 0u, hi = p < n0 ? p : n0;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (A[mid] <= B[p - 1 - mid]) lo = mid + 1;
+                    else hi = mid;
+                }
+                const uint32_t i = lo, j = p - lo;
+                if (i < n0 && (j >= n1 || A[i] <= B[j])) {
+                    key = A[i];
+                    ia = (uint32_t)(s0 + i);
+                    if (j < n1 && B[j] == key) ib = (uint32_t)(s1 + j);
+                    keep = true;
+                } else {
+                    key = B[j];
+                    ib = (uint32_t)(s1 + j);
+                    keep = !(i > 0 && A[i - 1] == key);  // else listed with the first list's copy
+                }
+            } else {
+                key = A[p];
+                ia = (uint32_t)(s0 + p);
+                uint32_t lo = 0, hi = n1;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (B[mid] < key) lo = mid + 1;
+                    else hi = mid;
+                }
+                const bool in_b = lo < n1 && B[lo] == key;
+                if (in_b) ib = (uint32_t)(s1 + lo);
+                keep = op == RG_AND && k == 2 ? in_b : true;  // one bitmap: its own keys
+            }
+        }
+        const uint64_t bal = __ballot(keep);
+        const uint32_t at = pos + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+        if (keep && at < kbound) {
+            Task t;
+            t.pair = a.pair_base + q;
+            t.ia = ia;
+            t.ib = ib;
+            t.key = (uint16_t)key;
+            t.kind = KIND_MATCH;
+            t.bin = KW_TASK_INDEXED;
+            a.tasks[slot0 + at] = t;
+        }
+        pos += (uint32_t)__popcll(bal);
+    }
+    pos = uniform(pos);
+    for (uint32_t i = (pos < kbound ? pos : kbound) + lane; i < kbound; i += 64) {
+        Task t;
+        t.pair = a.pair_base + q;
+        t.ia = NONE;
+        t.ib = NONE;
+        t.key = 0;
+        t.kind = KIND_NOOP;
+        t.bin = 0;
+        a.tasks[slot0 + i] = t;
+    }
+    if (lane == 0 && pos > kbound) atomicOr(a.err, 1u);
+}
+
+__global__ void __launch_bounds__(256) k_kw_keys(KwArgs a, uint32_t chunk) {
     __shared__ uint64_t acc[1024];
     __shared__ uint64_t cur[1024];
     __shared__ uint32_t tmp[8];
     __shared__ uint64_t rs[KW_MAX_K];  // key-list start of each of the query's bitmaps
     __shared__ uint32_t rn[KW_MAX_K];  // and its length
     __shared__ uint32_t roff[KW_MAX_K + 1];  // exclusive prefix of the lengths (union pass)
-    const uint32_t q = blockIdx.x;
+    __shared__ uint32_t chunk_mask;
+    // chunks of `chunk` queries: whether each is the workgroup kernel's (more
+    // than two bitmaps, or more than KW_KEYS_SMALL keys) is read for the whole
+    // chunk at once, then those queries are built one after another
+    for (uint32_t c0 = blockIdx.x * chunk; c0 < a.n_queries; c0 += gridDim.x * chunk) {
+    bool big = false;
+    if (threadIdx.x < chunk && c0 + threadIdx.x < a.n_queries) {
+        const KwQuery Q = a.queries[c0 + threadIdx.x];
+        if (Q.k > 2) {
+            big = true;
+        } else {
+            const uint32_t b0 = a.ids[Q.ids_off];
+            uint64_t n = a.P0.bm_begin[b0 + 1] - a.P0.bm_begin[b0];
+            if (Q.k == 2) {
+                const uint32_t b1 = a.ids[Q.ids_off + 1];
+                n += a.P1.bm_begin[b1 + 1] - a.P1.bm_begin[b1];
+            }
+            big = n > KW_KEYS_SMALL;
+        }
+    }
+    const uint64_t bm = __ballot(big);  // wave 0 holds the chunk
+    if (threadIdx.x == 0) chunk_mask = (uint32_t)bm;
+    __syncthreads();
+    uint32_t todo = uniform(chunk_mask);
+    __syncthreads();  // read before the next chunk writes it
+    while (todo) {
+    const uint32_t q = c0 + (uint32_t)__builtin_ctz(todo);
+    todo &= todo - 1;
     const KwQuery Q = a.queries[q];
     const uint32_t op = uniform(Q.op), k = uniform(Q.k), ids0 = uniform(Q.ids_off);
     const uint64_t slot0 = uniform64(Q.slot0);
@@ -239,6 +370,9 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a) {
         a.tasks[slot0 + i] = t;
     }
     if (tid == 0 && total > kbound) atomicOr(a.err, 1u);
+    __syncthreads();  // LDS read before the next query's pass
+    }
+    }
 }
 
 // ---------------------------------------------------------------- 2. bounds
@@ -259,6 +393,7 @@ __global__ void __launch_bounds__(256) k_kw_bounds(KwArgs a) {
     if (s >= a.n_slots) return;  // wave-uniform
     const Task t = uniform_task(a.tasks, (uint32_t)s);
     uint32_t ub = 0;
+    bool small = false;
     if (t.kind == KIND_MATCH) {
         const KwQuery* Qp = a.queries + (t.pair - a.pair_base);
         const uint32_t flags = uniform(Qp->flags);
@@ -267,6 +402,7 @@ __global__ void __launch_bounds__(256) k_kw_bounds(KwArgs a) {
             // AND: the smallest container; OR, XOR: the sum; ANDNOT: the first
             uint64_t sum = 0;
             uint32_t mn = 0xFFFFFFFFu, first = 0;
+            uint32_t ty = 0, sz = 0;  // type and size of lane j's container (0: absent)
             for (uint32_t j0 = 0; j0 < k; j0 += 64) {
                 const uint32_t j = j0 + lane;
                 uint32_t cj = 0;
@@ -275,6 +411,10 @@ __global__ void __launch_bounds__(256) k_kw_bounds(KwArgs a) {
                     const uint32_t ci = t.bin == KW_TASK_INDEXED ? (j == 0 ? t.ia : t.ib)
                                                                  : kw_find_key(pv.bm_begin, pv.keys, a.ids[ids0 + j], t.key);
                     cj = ci == NONE ? 0u : pv.card[ci];
+                    if (ci != NONE && j0 == 0) {
+                        ty = pv.types[ci];
+                        sz = pv.size[ci];
+                    }
                 }
                 if (j0 == 0) first = __builtin_amdgcn_readlane(cj, 0);
                 sum += wave_sum_u64(cj);
@@ -283,11 +423,18 @@ __global__ void __launch_bounds__(256) k_kw_bounds(KwArgs a) {
             }
             const uint64_t bc = op == RG_AND ? (uint64_t)mn : op == RG_ANDNOT ? (uint64_t)first : sum;
             ub = wbytes_of(bc);
+            if (a.small && t.bin == KW_TASK_INDEXED) {
+                const uint32_t ta = __builtin_amdgcn_readlane(ty, 0), sa = __builtin_amdgcn_readlane(sz, 0);
+                const uint32_t tb = k > 1 ? __builtin_amdgcn_readlane(ty, 1) : 0u;
+                const uint32_t sb = k > 1 ? __builtin_amdgcn_readlane(sz, 1) : 0u;
+                small = small_mat_ok((int)op, (uint8_t)ta, (uint8_t)tb, sa, sb);
+            }
         }
     }
     if (lane == 0) {
         a.ub[s] = ub;
         a.res_card[s] = 0;
+        if (small) a.tasks[s].bin = KW_TASK_SMALL;
     }
 }
 
@@ -354,10 +501,26 @@ __global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
     __shared__ uint32_t cunits[KW_MAX_K + 1];  // exclusive prefix of the containers' unit counts
     __shared__ uint8_t ctype[KW_MAX_K];
     __shared__ uint64_t cpl[KW_MAX_K];         // payload address of each container
+    __shared__ uint32_t chunk_mask;
     const uint32_t tid = threadIdx.x;
-    for (uint64_t s = blockIdx.x; s < a.n_slots; s += gridDim.x) {
+    // chunks of KW_EVAL_CHUNK slots: their tasks are read at once, then the
+    // workgroup evaluates those that are its own (not empty, not the one-wave
+    // kernel's) one after another
+    for (uint64_t c0 = (uint64_t)blockIdx.x * KW_EVAL_CHUNK; c0 < a.n_slots; c0 += (uint64_t)gridDim.x * KW_EVAL_CHUNK) {
+    bool own = false;
+    if (tid < KW_EVAL_CHUNK && c0 + tid < a.n_slots) {
+        const Task t = a.tasks[c0 + tid];
+        own = t.kind == KIND_MATCH && t.bin != KW_TASK_SMALL;
+    }
+    const uint64_t ob = __ballot(own);  // wave 0 holds the chunk
+    if (tid == 0) chunk_mask = (uint32_t)ob;
+    __syncthreads();
+    uint32_t todo = uniform(chunk_mask);
+    __syncthreads();  // read before the next chunk writes it
+    while (todo) {
+        const uint64_t s = c0 + (uint32_t)__builtin_ctz(todo);
+        todo &= todo - 1;
         const Task t = uniform_task(a.tasks, (uint32_t)s);
-        if (t.kind != KIND_MATCH) continue;
         const uint32_t q = t.pair - a.pair_base;
         const KwQuery Q = a.queries[q];
         const uint32_t op = uniform(Q.op), k = uniform(Q.k), flags = uniform(Q.flags);
@@ -485,6 +648,7 @@ __global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
         }
         __syncthreads();
     }
+    }
 }
 
 // per-query cardinality of count-only and materialised queries alike
@@ -516,7 +680,14 @@ void launch_kw_step_init(uint64_t* totals, uint32_t* err, long long* acc, uint64
 }
 
 void launch_kw_keys(const KwArgs& a, hipStream_t st) {
-    if (a.n_queries) hipLaunchKernelGGL(k_kw_keys, dim3(a.n_queries), dim3(256), 0, st, a);
+    if (!a.n_queries) return;
+    hipLaunchKernelGGL(k_kw_keys_small, dim3((a.n_queries + 3) / 4), dim3(256), 0, st, a);
+    // a query per workgroup for small batches (each may be large); up to
+    // KW_KEYS_CHUNK for large ones, where most are the one-wave kernel's
+    uint32_t chunk = a.n_queries / 2048;
+    chunk = chunk < 1 ? 1u : chunk > KW_KEYS_CHUNK ? KW_KEYS_CHUNK : chunk;
+    const uint32_t g = (a.n_queries + chunk - 1) / chunk;
+    hipLaunchKernelGGL(k_kw_keys, dim3(g < 16384 ? g : 16384u), dim3(256), 0, st, a, chunk);
 }
 void launch_kw_bounds(const KwArgs& a, hipStream_t st) {
     if (a.n_slots)
@@ -524,7 +695,8 @@ void launch_kw_bounds(const KwArgs& a, hipStream_t st) {
 }
 void launch_kw_eval(const KwArgs& a, hipStream_t st) {
     if (!a.n_slots) return;
-    const uint32_t g = a.n_slots < 65536 ? (uint32_t)a.n_slots : 65536u;
+    const uint64_t nc = (a.n_slots + KW_EVAL_CHUNK - 1) / KW_EVAL_CHUNK;
+    const uint32_t g = nc < 65536 ? (uint32_t)nc : 65536u;
     hipLaunchKernelGGL(k_kw_eval, dim3(g), dim3(256), 0, st, a);
 }
 void launch_kw_cards(const KwArgs& a, const uint64_t* bm_card, uint64_t* cards, hipStream_t st) {

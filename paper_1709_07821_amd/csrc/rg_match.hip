@@ -145,7 +145,12 @@ __device__ __forceinline__ uint8_t classify(int op, bool materialize, uint8_t ki
                                             int fixed_bin, uint32_t gallop_ratio, uint32_t thread_max,
                                             const uint8_t* mlp_table) {
     if (ta == RG_BITSET && tb == RG_BITSET) return BIN_BB;
-    if (materialize) return BIN_GEN;  // specialised variants are count-only
+    // materialised: pairs with an array side are built by the one-wave array
+    // kernel (listed in BIN_AA; forcing BIN_GEN turns that off), the rest by
+    // the generic kernel
+    if (materialize)
+        return (mode != 2 || fixed_bin != BIN_GEN) && small_mat_ok(op, ta, tb, ca, cb) ? (uint8_t)BIN_AA
+                                                                                        : (uint8_t)BIN_GEN;
     if (mode == 2) return variant_applies(fixed_bin, ta, tb, ca, cb) ? (uint8_t)fixed_bin : (uint8_t)BIN_GEN;
     if (mode == 1 && mlp_table) return mlp_table[mlp_cell(ta, tb, ca, cb, ra, rb)];  // learned
     // heuristic: a small array side is probed by one thread (each value

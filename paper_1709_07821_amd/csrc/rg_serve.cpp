@@ -204,8 +204,13 @@ rg_status step_enqueue(std::string* err_out, const rg_pool& pool, const StepLayo
     launch_kw_keys(a, st);
     launch_kw_bounds(a, st);
     if (L.S) launch_scan_u32_u64(ub, slot_off, L.S, 0, partials, totals, st);
-    if (prof) timed(prof, PROF_KWEVAL, true, L.S, st, [&] { launch_kw_eval(a, st); });
-    else launch_kw_eval(a, st);
+    if (prof) {
+        timed(prof, PROF_KWSMALL, true, L.S, st, [&] { launch_kw_small(a, st); });
+        timed(prof, PROF_KWEVAL, true, L.S, st, [&] { launch_kw_eval(a, st); });
+    } else {
+        launch_kw_small(a, st);
+        launch_kw_eval(a, st);
+    }
     if (L.S) {
         launch_scan_nonzero_u64(res_card, out_idx, L.S, 0, partials, totals + 1, st);
         CompactArgs cp;
