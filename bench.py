@@ -411,14 +411,14 @@ def bench_pairs_materialised(args, bs, ia, ib, workload, metric_config):
     out_bytes = {op: out_pay[op][0] + META_BYTES * out_pay[op][1] for op in OPS4}
     step_in = sum(in_bytes.values())
     matched = int(st["matched"].sum())
-    # roofline: the k-way evaluation step (the one-wave array kernel and the
-    # workgroup kernel, one launch each per call) reads the containers of every
+    # roofline: the k-way evaluation step (the one-wave array and bitset kernels
+    # and the workgroup kernel, one launch each per call) reads the containers of every
     # result key of the union, symmetric difference and difference and writes
     # the result; its duration is the two launches'
     kw = dict(prof.get(("kway-eval", True)) or {"ms": 0.0, "launches": 0})
-    ks = prof.get(("kway-small", True))
-    if ks:
-        kw["ms"] += ks["ms"]
+    for extra in ("kway-small", "kway-bb"):
+        if prof.get((extra, True)):
+            kw["ms"] += prof[(extra, True)]["ms"]
     roof = None
     if kw and kw["launches"]:
         kw_bytes = sum(float((st["payA"] + st["payB"]).sum()) for op in ("or", "xor")) + \
@@ -427,7 +427,7 @@ def bench_pairs_materialised(args, bs, ia, ib, workload, metric_config):
         ach = kw_bytes / (kw["ms"] / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
-                "kernel": "k_kw_small + k_kw_eval (k-way evaluation step)",
+                "kernel": "k_kw_small + k_kw_bb + k_kw_eval (k-way evaluation step)",
                 "mean_launch_ms": round(kw["ms"] / kw["launches"], 4), "launches": int(kw["launches"]),
                 "bytes_per_launch": int(kw_bytes / kw["launches"]),
                 "share_of_step": round(kw["ms"] / (dt_prof * 1e3 * args.steps), 3)}
@@ -1004,8 +1004,9 @@ def serve_roofline_and_cpu(args, ctx, P, h, qs, gen):
     torch.cuda.synchronize()
     pr = rg.profile_read(ctx)
     kw = dict(pr.get(("kway-eval", True)) or {"ms": 0.0, "launches": 0})
-    if pr.get(("kway-small", True)):  # queries of two bitmaps with an array side
-        kw["ms"] += pr[("kway-small", True)]["ms"]
+    for extra in ("kway-small", "kway-bb"):  # queries of two bitmaps: one-wave kernels
+        if pr.get((extra, True)):
+            kw["ms"] += pr[(extra, True)]["ms"]
     rg.profile_enable(ctx, False)
     roof = None
     if kw and kw["launches"]:
@@ -1013,7 +1014,7 @@ def serve_roofline_and_cpu(args, ctx, P, h, qs, gen):
         ach = tot / (kw["ms"] / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_kw_small + k_kw_eval (k-way evaluation step; one roaring_multi call per query, "
+                "kernel": "k_kw_small + k_kw_bb + k_kw_eval (k-way evaluation step; one roaring_multi call per query, "
                           "materialised)",
                 "mean_launch_ms": round(kw["ms"] / kw["launches"], 4), "launches": int(kw["launches"]),
                 "bytes_per_launch": int(tot / kw["launches"]),

@@ -394,9 +394,10 @@ rg_status rg_dispatch_table(rg_ctx *ctx, uint8_t *h_table, uint64_t cap);
  * container pairs, counted by the kernel while timing is on),
  * 11 for the k-way evaluation of materialised unions, symmetric differences
  * and differences (items: result slots), 12 for the one-wave kernel that
- * builds those of their results with an array side (items: result slots
- * scanned); variant 3 (RG_V_MERGE) in materialising form is the same one-wave
- * kernel on the intersections that have an array side) in count-only
+ * builds those of their results with an array side, 13 for the one-wave
+ * kernel that builds their bitset results of bitset containers (items: result
+ * slots scanned); variant 3 (RG_V_MERGE) in materialising form is the one-wave
+ * array kernel on the intersections that have an array side) in count-only
  * (materialize = 0) or materialising form. Synchronises on the
  * recorded events; costs two events per launch. */
 rg_status rg_profile_enable(rg_ctx *ctx, int on);

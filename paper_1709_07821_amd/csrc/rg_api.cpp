@@ -425,6 +425,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
             launch_kw_bounds(ka, st);
             launch_scan_u32_u64(ub, slot_off, C, pay_base, partials, totals, st);
             timed(c, PROF_KWSMALL, true, C, st, [&] { launch_kw_small(ka, st); });
+            timed(c, PROF_KWBB, true, C, st, [&] { launch_kw_bb(ka, st); });
             timed(c, PROF_KWEVAL, true, C, st, [&] { launch_kw_eval(ka, st); });
         } else {
             MatchArgs m;
@@ -1060,6 +1061,7 @@ void plan_enqueue_mat(rg_plan* p, hipStream_t st) {
         // slot payload offsets continue from the previous wave's payload end
         launch_scan_u32_u64(p->ub, p->slot_off, wv.C, 0, p->partials, p->totals, st, p->totals);
         launch_kw_small(ka, st);
+        launch_kw_bb(ka, st);
         launch_kw_eval(ka, st);
         // output indices continue from the previous wave's container count
         launch_scan_nonzero_u64(p->res_card, p->out_idx, wv.C, 0, p->partials, p->totals + 1, st, p->totals + 1);

@@ -32,64 +32,82 @@ __global__ void __launch_bounds__(256) k_bb_count(ComputeArgs a) {
     }
 }
 
-// Materialising form (intersection): words in registers, run count, P1 type,
-// bitset results written from registers, other results to the redo list.
-template <int OP>
-__global__ void __launch_bounds__(256) k_bb_mat(ComputeArgs a) {
-    const uint32_t lane = lane_id();
-    const uint32_t w = wave_index();
-    if (w >= a.n) return;
-    const uint32_t slot = uniform(a.list[w]);
-    const Task t = uniform_task(a.tasks, slot);
-    const u32x4* pa = reinterpret_cast<const u32x4*>(a.A.payload + a.A.off[t.ia]);
-    const u32x4* pb = reinterpret_cast<const u32x4*>(a.B.payload + a.B.off[t.ib]);
+// Result words of one bitset pair in registers (see the word order above),
+// with their population count c and run count r summed over the wave. A side
+// given as nullptr is absent (all words zero).
+struct BbWords {
+    uint64_t lo[8], hi[8];
+    uint32_t c, r;
+};
+
+__device__ __forceinline__ uint64_t bb_op(int op, uint64_t x, uint64_t y) {
+    return op == RG_AND ? (x & y) : op == RG_OR ? (x | y) : op == RG_XOR ? (x ^ y) : (x & ~y);
+}
+
+__device__ __forceinline__ void bb_words(int op, const u32x4* pa, const u32x4* pb, uint32_t lane, BbWords& w) {
     u32x4 x[8], y[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        x[k] = __builtin_nontemporal_load(pa + k * 64 + lane);
-        y[k] = __builtin_nontemporal_load(pb + k * 64 + lane);
+        x[k] = pa ? __builtin_nontemporal_load(pa + k * 64 + lane) : u32x4{0, 0, 0, 0};
+        y[k] = pb ? __builtin_nontemporal_load(pb + k * 64 + lane) : u32x4{0, 0, 0, 0};
     }
-    uint64_t lo[8], hi[8];
     uint32_t c = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        uint64_t xa = (uint64_t)x[k].x | ((uint64_t)x[k].y << 32);
-        uint64_t xb = (uint64_t)x[k].z | ((uint64_t)x[k].w << 32);
-        uint64_t ya = (uint64_t)y[k].x | ((uint64_t)y[k].y << 32);
-        uint64_t yb = (uint64_t)y[k].z | ((uint64_t)y[k].w << 32);
-        lo[k] = apply_op<OP>(xa, ya);
-        hi[k] = apply_op<OP>(xb, yb);
-        c += __popcll(lo[k]) + __popcll(hi[k]);
+        const uint64_t xa = (uint64_t)x[k].x | ((uint64_t)x[k].y << 32);
+        const uint64_t xb = (uint64_t)x[k].z | ((uint64_t)x[k].w << 32);
+        const uint64_t ya = (uint64_t)y[k].x | ((uint64_t)y[k].y << 32);
+        const uint64_t yb = (uint64_t)y[k].z | ((uint64_t)y[k].w << 32);
+        w.lo[k] = bb_op(op, xa, ya);
+        w.hi[k] = bb_op(op, xb, yb);
+        c += __popcll(w.lo[k]) + __popcll(w.hi[k]);
     }
     // run starts: bit set and the bit below it (previous word's MSB for bit 0) clear
     uint32_t r = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        uint64_t prev = __shfl_up(hi[k], 1);
-        uint64_t wrap = k > 0 ? __shfl(hi[k > 0 ? k - 1 : 0], 63) : 0ull;
+        uint64_t prev = __shfl_up(w.hi[k], 1);
+        const uint64_t wrap = k > 0 ? __shfl(w.hi[k > 0 ? k - 1 : 0], 63) : 0ull;
         if (lane == 0) prev = wrap;
-        uint64_t s_lo = lo[k] & ~((lo[k] << 1) | (prev >> 63));
-        uint64_t s_hi = hi[k] & ~((hi[k] << 1) | (lo[k] >> 63));
+        const uint64_t s_lo = w.lo[k] & ~((w.lo[k] << 1) | (prev >> 63));
+        const uint64_t s_hi = w.hi[k] & ~((w.hi[k] << 1) | (w.lo[k] >> 63));
         r += __popcll(s_lo) + __popcll(s_hi);
     }
-    uint64_t cr = wave_sum_u64((uint64_t)c | ((uint64_t)r << 32));
-    c = (uint32_t)cr;
-    r = (uint32_t)(cr >> 32);
-    if (c == 0) return;  // empty result: slot stays empty
-    const uint8_t type = p1_type(c, r);
-    if (type == RG_BITSET) {
-        u32x4* dst = reinterpret_cast<u32x4*>(a.so.payload + a.so.slot_off[slot]);
+    const uint64_t cr = wave_sum_u64((uint64_t)c | ((uint64_t)r << 32));
+    w.c = (uint32_t)cr;
+    w.r = (uint32_t)(cr >> 32);
+}
+
+// writes the result words as an 8 KiB bitset container
+__device__ __forceinline__ void bb_store(const BbWords& w, uint8_t* dst8, uint32_t lane) {
+    u32x4* dst = reinterpret_cast<u32x4*>(dst8);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            u32x4 v;
-            v.x = (uint32_t)lo[k];
-            v.y = (uint32_t)(lo[k] >> 32);
-            v.z = (uint32_t)hi[k];
-            v.w = (uint32_t)(hi[k] >> 32);
-            __builtin_nontemporal_store(v, dst + k * 64 + lane);
-        }
+    for (int k = 0; k < 8; ++k) {
+        u32x4 v;
+        v.x = (uint32_t)w.lo[k];
+        v.y = (uint32_t)(w.lo[k] >> 32);
+        v.z = (uint32_t)w.hi[k];
+        v.w = (uint32_t)(w.hi[k] >> 32);
+        __builtin_nontemporal_store(v, dst + k * 64 + lane);
+    }
+}
+
+// Materialising form (intersection): words in registers, run count, P1 type,
+// bitset results written from registers, other results to the redo list.
+__global__ void __launch_bounds__(256) k_bb_mat(ComputeArgs a) {
+    const uint32_t lane = lane_id();
+    const uint32_t wv = wave_index();
+    if (wv >= a.n) return;
+    const uint32_t slot = uniform(a.list[wv]);
+    const Task t = uniform_task(a.tasks, slot);
+    BbWords w;
+    bb_words(a.op, reinterpret_cast<const u32x4*>(a.A.payload + a.A.off[t.ia]),
+             reinterpret_cast<const u32x4*>(a.B.payload + a.B.off[t.ib]), lane, w);
+    if (w.c == 0) return;  // empty result: slot stays empty
+    if (p1_type(w.c, w.r) == RG_BITSET) {
+        bb_store(w, a.so.payload + a.so.slot_off[slot], lane);
         if (lane == 0) {
-            a.so.res_card[slot] = c;
+            a.so.res_card[slot] = w.c;
             a.so.res_type[slot] = RG_BITSET;
             a.so.res_size[slot] = 1024;
         }
@@ -97,6 +115,68 @@ __global__ void __launch_bounds__(256) k_bb_mat(ComputeArgs a) {
         uint32_t pos = atomicAdd(a.so.redo_count, 1u);
         a.so.redo_list[pos] = slot;
     }
+}
+
+// k-way slots marked KW_TASK_BB (queries of one or two bitmaps whose
+// containers at the key are bitsets, or a bitset and nothing), BB_CHUNK slots
+// per wave: lane i loads slot i's task, op and payload offsets in parallel,
+// then the wave builds the slots' results one after another as k_bb_mat
+// does. A bitset result (or an empty one) is final: the task is marked
+// KW_TASK_DONE. Other results stay for the workgroup kernel.
+constexpr uint32_t BB_CHUNK = 8;
+
+__global__ void __launch_bounds__(256) k_kw_bb(KwArgs a) {
+    const uint32_t lane = lane_id();
+    const uint64_t step = (uint64_t)gridDim.x * 4 * BB_CHUNK;
+    for (uint64_t c0 = (uint64_t)wave_index() * BB_CHUNK; c0 < a.n_slots; c0 += step) {
+        bool mine = false;
+        uint32_t op = 0, has = 0;
+        uint64_t oa = 0, ob = 0;
+        if (lane < BB_CHUNK && c0 + lane < a.n_slots) {
+            const Task t = a.tasks[c0 + lane];
+            mine = t.kind == KIND_MATCH && t.bin == KW_TASK_BB;
+            if (mine) {
+                op = a.queries[t.pair - a.pair_base].op;
+                has = (t.ia != NONE ? 1u : 0u) | (t.ib != NONE ? 2u : 0u);
+                if (t.ia != NONE) oa = a.P0.off[t.ia];
+                if (t.ib != NONE) ob = a.P1.off[t.ib];
+            }
+        }
+        uint64_t m = __ballot(mine);
+        while (m) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(m);
+            m &= m - 1;
+            const uint32_t slot = (uint32_t)(c0 + l);
+            const uint32_t hl = __builtin_amdgcn_readlane(has, l);
+            const u32x4* pa = (hl & 1u) ? reinterpret_cast<const u32x4*>(a.P0.payload + readlane64(oa, l)) : nullptr;
+            const u32x4* pb = (hl & 2u) ? reinterpret_cast<const u32x4*>(a.P1.payload + readlane64(ob, l)) : nullptr;
+            BbWords w;
+            bb_words((int)__builtin_amdgcn_readlane(op, l), pa, pb, lane, w);
+            bool done = true;
+            if (w.c && p1_type(w.c, w.r) == RG_BITSET) {
+                const uint64_t soff = a.so.slot_off[slot];
+                if (soff + 8192 > a.so.cap) {
+                    if (lane == 0 && a.so.err) atomicOr(a.so.err, 2u);
+                } else {
+                    bb_store(w, a.so.payload + soff, lane);
+                    if (lane == 0) {
+                        a.so.res_card[slot] = w.c;
+                        a.so.res_type[slot] = RG_BITSET;
+                        a.so.res_size[slot] = 1024;
+                    }
+                }
+            } else if (w.c) {
+                done = false;  // an array or runs: the workgroup kernel's
+            }
+            if (done && lane == 0) a.tasks[slot].bin = KW_TASK_DONE;
+        }
+    }
+}
+
+void launch_kw_bb(const KwArgs& a, hipStream_t st) {
+    if (!a.n_slots || !a.small) return;
+    const uint64_t g = (a.n_slots + 4 * BB_CHUNK - 1) / (4 * BB_CHUNK);
+    hipLaunchKernelGGL(k_kw_bb, dim3(g < 16384 ? (uint32_t)g : 16384u), dim3(256), 0, st, a);
 }
 
 void launch_bb(const ComputeArgs& a, hipStream_t st) {
@@ -108,7 +188,7 @@ void launch_bb(const ComputeArgs& a, hipStream_t st) {
     if (!a.materialize) {
         hipLaunchKernelGGL(k_bb_count, grid, dim3(256), 0, st, a);
     } else {
-        hipLaunchKernelGGL((k_bb_mat<RG_AND>), grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_bb_mat, grid, dim3(256), 0, st, a);
     }
 }
 

@@ -37,7 +37,8 @@ enum : uint8_t {
 constexpr int PROF_FUSED = 10;  // the fused match-and-count kernel of asynchronous count-only calls
 constexpr int PROF_KWEVAL = 11; // k-way evaluation of materialised unions, differences, symmetric differences
 constexpr int PROF_KWSMALL = 12; // the one-wave array kernel on k-way slots
-constexpr int NPROF = 13;
+constexpr int PROF_KWBB = 13;    // the one-wave bitset kernel on k-way slots
+constexpr int NPROF = 14;
 
 struct Task {
     uint32_t pair;
@@ -113,6 +114,13 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgc
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
     uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// lane l's value, in every lane (l uniform)
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t l) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
     return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
@@ -411,6 +419,17 @@ __host__ __device__ __forceinline__ bool small_mat_ok(int op, uint8_t ta, uint8_
 constexpr uint8_t KW_TASK_INDEXED = 1;
 // ... and whose result the one-wave array kernel builds (set by the bounds kernel)
 constexpr uint8_t KW_TASK_SMALL = 2;
+// ... whose containers are bitsets (or one bitset, the other absent): the
+// one-wave bitset kernel builds the result when it is a bitset and then marks
+// the task KW_TASK_DONE; other results stay for the workgroup kernel
+constexpr uint8_t KW_TASK_BB = 3;
+constexpr uint8_t KW_TASK_DONE = 4;
+__host__ __device__ __forceinline__ bool bb_mat_ok(int op, uint8_t ta, uint8_t tb) {
+    if (ta == RG_BITSET && tb == RG_BITSET) return true;
+    if (ta == RG_BITSET && tb == 0) return op != RG_AND;             // A alone: union, xor, difference
+    if (ta == 0 && tb == RG_BITSET) return op == RG_OR || op == RG_XOR;  // B alone
+    return false;
+}
 constexpr uint32_t KW_MATERIALIZE = 1u;  // KwQuery.flags: build the result containers
 constexpr uint32_t KW_MAX_K = 256;       // bitmaps per query (one lookup thread each)
 struct KwQuery {
@@ -446,6 +465,7 @@ void launch_kw_bounds(const KwArgs& a, hipStream_t st);
 // the two evaluation kernels: the one-wave array kernel for the slots the
 // bounds kernel marked (rg_small.hip), the workgroup kernel for the others
 void launch_kw_small(const KwArgs& a, hipStream_t st);
+void launch_kw_bb(const KwArgs& a, hipStream_t st);
 void launch_kw_eval(const KwArgs& a, hipStream_t st);
 void launch_kw_cards(const KwArgs& a, const uint64_t* bm_card, uint64_t* cards, hipStream_t st);
 // queries q < n_pairs for pairs pair0 + q (k = 2: A side, B side), slot ranges

@@ -393,7 +393,7 @@ __global__ void __launch_bounds__(256) k_kw_bounds(KwArgs a) {
     if (s >= a.n_slots) return;  // wave-uniform
     const Task t = uniform_task(a.tasks, (uint32_t)s);
     uint32_t ub = 0;
-    bool small = false;
+    uint8_t mark = 0;  // KW_TASK_SMALL / KW_TASK_BB: the slot's one-wave kernel
     if (t.kind == KIND_MATCH) {
         const KwQuery* Qp = a.queries + (t.pair - a.pair_base);
         const uint32_t flags = uniform(Qp->flags);
@@ -427,14 +427,16 @@ __global__ void __launch_bounds__(256) k_kw_bounds(KwArgs a) {
                 const uint32_t ta = __builtin_amdgcn_readlane(ty, 0), sa = __builtin_amdgcn_readlane(sz, 0);
                 const uint32_t tb = k > 1 ? __builtin_amdgcn_readlane(ty, 1) : 0u;
                 const uint32_t sb = k > 1 ? __builtin_amdgcn_readlane(sz, 1) : 0u;
-                small = small_mat_ok((int)op, (uint8_t)ta, (uint8_t)tb, sa, sb);
+                mark = small_mat_ok((int)op, (uint8_t)ta, (uint8_t)tb, sa, sb) ? KW_TASK_SMALL
+                       : bb_mat_ok((int)op, (uint8_t)ta, (uint8_t)tb)       ? KW_TASK_BB
+                                                                            : 0;
             }
         }
     }
     if (lane == 0) {
         a.ub[s] = ub;
         a.res_card[s] = 0;
-        if (small) a.tasks[s].bin = KW_TASK_SMALL;
+        if (mark) a.tasks[s].bin = mark;
     }
 }
 
@@ -510,7 +512,7 @@ __global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
     bool own = false;
     if (tid < KW_EVAL_CHUNK && c0 + tid < a.n_slots) {
         const Task t = a.tasks[c0 + tid];
-        own = t.kind == KIND_MATCH && t.bin != KW_TASK_SMALL;
+        own = t.kind == KIND_MATCH && t.bin != KW_TASK_SMALL && t.bin != KW_TASK_DONE;
     }
     const uint64_t ob = __ballot(own);  // wave 0 holds the chunk
     if (tid == 0) chunk_mask = (uint32_t)ob;
@@ -526,7 +528,7 @@ __global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
         const uint32_t op = uniform(Q.op), k = uniform(Q.k), flags = uniform(Q.flags);
         const uint32_t ids0 = uniform(Q.ids_off);
         if (tid < k) {
-            if (t.bin == KW_TASK_INDEXED) {
+            if (t.bin == KW_TASK_INDEXED || t.bin == KW_TASK_BB) {
                 cidx[tid] = tid == 0 ? t.ia : t.ib;
             } else {
                 const uint64_t* bmb = tid ? a.P1.bm_begin : a.P0.bm_begin;

@@ -206,9 +206,11 @@ rg_status step_enqueue(std::string* err_out, const rg_pool& pool, const StepLayo
     if (L.S) launch_scan_u32_u64(ub, slot_off, L.S, 0, partials, totals, st);
     if (prof) {
         timed(prof, PROF_KWSMALL, true, L.S, st, [&] { launch_kw_small(a, st); });
+        timed(prof, PROF_KWBB, true, L.S, st, [&] { launch_kw_bb(a, st); });
         timed(prof, PROF_KWEVAL, true, L.S, st, [&] { launch_kw_eval(a, st); });
     } else {
         launch_kw_small(a, st);
+        launch_kw_bb(a, st);
         launch_kw_eval(a, st);
     }
     if (L.S) {

@@ -62,12 +62,6 @@ __device__ __forceinline__ void stage_u16(uint16_t* dst, const uint8_t* src, uin
     for (uint32_t i = (n8 << 3) + lane; i < n; i += 64) dst[i] = s16[i];
 }
 
-__device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t l) {
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
-    return (uint64_t)lo | ((uint64_t)hi << 32);
-}
-
 // lanes below this one
 __device__ __forceinline__ uint64_t lanes_below(uint32_t lane) { return (1ull << lane) - 1ull; }
 

@@ -1,10 +1,11 @@
-"""The one-wave array kernels of materialised results (pairs with an array
-side): containers built to hit each of their cases - merges at and just past
-the value limit, results that come out as runs across many 64-value rounds,
-absent sides, array-bitset and array-run filters in both operand orders,
-full 4096-value arrays - against the oracle, through the eager call (binned
-intersection and k-way path) and a materialising plan, and the same pairs with
-the one-wave kernels switched off."""
+"""The one-wave kernels of materialised results (pairs with an array side;
+pairs of bitsets): containers built to hit each of their cases - merges at and
+just past the value limit, results that come out as runs across many 64-value
+rounds, absent sides, array-bitset and array-run filters in both operand
+orders, full 4096-value arrays, bitset pairs whose results are bitsets, arrays,
+runs or empty, lone bitsets - against the oracle, through the eager call
+(binned intersection and k-way path) and a materialising plan, and the same
+pairs with the one-wave kernels switched off."""
 import sys
 
 import numpy as np
@@ -82,6 +83,15 @@ def case_sets():
         # pairs {4i, 4i+1}: the intersection with its shifted copy gives singletons
         13: (np.sort(np.concatenate([np.arange(0, 8000, 4), np.arange(1, 8000, 4)])),
              np.sort(np.concatenate([np.arange(1, 8000, 4), np.arange(2, 8000, 4)]))),
+        # two random bitsets: bitset results, and an intersection that is an array
+        14: (np.unique(rng.integers(0, 65536, 11000)), np.unique(rng.integers(0, 65536, 11000))),
+        # a bitset and itself less ten values: difference and symmetric difference of ten values
+        15: (bs15 := np.unique(rng.integers(0, 65536, 7000)), np.delete(bs15, np.arange(0, 5000, 500))),
+        # a bitset only in A, a bitset only in B
+        16: (np.unique(rng.integers(0, 65536, 9000)), None),
+        17: (None, np.unique(rng.integers(0, 65536, 9000))),
+        # evens and odds below 20000 (bitsets): union and symmetric difference are one run
+        18: (np.arange(0, 20000, 2), np.arange(1, 20000, 2)),
     }
     a, b = [], []
     for key, (pa, pb) in parts.items():
@@ -106,6 +116,9 @@ def _check_types(rg):
     assert ta[11] == A and tb[11] == R
     assert ta[12] == A and tb[12] == R and int(cb["runs"][cb["keys"].tolist().index(12)]) == 2047
     assert ta[9] == A and int(ca["card"][ca["keys"].tolist().index(9)]) == 4096
+    for key in (14, 15, 18):
+        assert ta[key] == B and tb[key] == B, key
+    assert ta[16] == B and tb[17] == B
 
 
 def test_cases_against_oracle(rg, ctx):
