@@ -24,7 +24,9 @@ four operations materialised with counts and Jaccard), array (1e5 array-array
 pairs, Zipf sizes, materialised), dense-mat (materialised dense pairs),
 batched (1e6 uneven pairs: plan, eager call, one call per pair, learned
 dispatch), serve (k-way queries over a 1e5-bitmap index under Poisson
-arrivals).
+arrivals), dispatch (learned vs heuristic variant choice on held-out pairs),
+wide (a 200-way union), access (batched membership and export to uint32),
+canonical (non-P1 pool to P1), inplace (op= on mutable bitmaps).
 """
 from __future__ import annotations
 
@@ -55,7 +57,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target single-core oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", type=int, default=2, help="pairs checked against the oracle before timing")
-    ap.add_argument("--workload", choices=("dense", "mixed", "array", "dense-mat", "batched", "serve", "dispatch"),
+    ap.add_argument("--workload", choices=("dense", "mixed", "array", "dense-mat", "batched", "serve", "dispatch",
+                                           "wide", "access", "canonical", "inplace"),
                     default="dense",
                     help="dense: the bitset-bandwidth headline; mixed / array: the small mixed and array-stress "
                          "pairs, materialised; batched: many uneven pairs, plan vs per-pair; serve: k-way "
@@ -70,6 +73,11 @@ def main():
     ap.add_argument("--per-pair-sample", type=int, default=500, help="batched: pairs timed one call each")
     ap.add_argument("--dispatch-pairs", type=int, default=300, help="batched: pairs whose costs train the dispatcher")
     ap.add_argument("--dispatch-epochs", type=int, default=10, help="batched: dispatcher training epochs")
+    ap.add_argument("--wide", type=int, default=200, help="wide: bitmaps in the union")
+    ap.add_argument("--access-bitmaps", type=int, default=1000, help="access: bitmaps in the pool")
+    ap.add_argument("--lookups", type=int, default=10000000, help="access: membership lookups per step")
+    ap.add_argument("--canon-bitmaps", type=int, default=1000, help="canonical: bitmaps in the pool")
+    ap.add_argument("--acc", type=int, default=16, help="inplace: mutable bitmaps")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES bytes (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -91,7 +99,8 @@ def main():
         print(f"# copied {src.numel() * 8} bytes device to device", file=sys.stderr, flush=True)
         return None
     fn = {"dense": bench_dense, "mixed": bench_mixed, "array": bench_array, "dense-mat": bench_dense_mat,
-          "batched": bench_batched, "serve": bench_serve, "dispatch": bench_dispatch}[args.workload]
+          "batched": bench_batched, "serve": bench_serve, "dispatch": bench_dispatch, "wide": bench_wide,
+          "access": bench_access, "canonical": bench_canonical, "inplace": bench_inplace}[args.workload]
     return fn(args)
 
 
@@ -924,7 +933,7 @@ def bench_serve(args):
     # correctness gate: a sample against the oracle (bitmaps regenerated on the host)
     sample = make_queries(12)
     srv = rg.Server(ctx, P, arena_bytes=4 << 30, max_batch=args.max_batch, max_inflight=2)
-    _, c_s, d_s = srv.replay(sample, np.zeros(len(sample), np.uint64))
+    _, c_s, d_s = srv.replay(sample, np.zeros(len(sample), np.uint64), digest=True)
     srv.stop()
     for i, (op, ids, mat) in enumerate(sample):
         e = oracle.kway(op, [gen(int(j)) for j in ids])
@@ -941,13 +950,14 @@ def bench_serve(args):
         for mode, mb, mi in (("batched", args.max_batch, 2), ("one_at_a_time", 1, 1)):
             srv = rg.Server(ctx, P, arena_bytes=4 << 30, max_batch=mb, max_inflight=mi)
             t = time.perf_counter()
-            lat, c, d = srv.replay(qs, arrival)
+            # served as a client would: cardinalities and result views, no fingerprints
+            lat, c, _ = srv.replay(qs, arrival)
             wall = time.perf_counter() - t
             st = srv.stop()
             if mode == "batched":
-                ref = (c, d)
+                ref = c
             else:
-                assert np.array_equal(c, ref[0]) and np.array_equal(d, ref[1]), "results differ between modes"
+                assert np.array_equal(c, ref), "cardinalities differ between modes"
             row[mode] = {"achieved_qps": round(n / wall, 1), "p50_us": round(float(np.percentile(lat, 50)) / 1e3, 1),
                          "p99_us": round(float(np.percentile(lat, 99)) / 1e3, 1),
                          "mean_batch": round(st["mean_batch"], 2), "steps": st["steps"]}
@@ -1027,6 +1037,334 @@ def serve_roofline_and_cpu(args, ctx, P, h, qs, gen):
                                  f"{len(tasks)} queries of the mix, k-way left fold of two-pointer merges",
                                  args.cpu_seconds)
     return roof, cpu
+
+
+# ---------------------------------------------------------------- wide union, access, canonical, in-place
+
+def _line(metric, value, unit, args, ms, config, extra, roof, cpu, dtype="u32"):
+    line = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+    line.update(extra)
+    line["roofline"] = roof
+    line["cpu_baseline"] = cpu
+    print(json.dumps(line), flush=True)
+
+
+def _kway_eval_ms(prof):
+    """ms and launches of the k-way evaluation step (the two one-wave kernels
+    and the workgroup kernel, one launch each per call)."""
+    ms = sum(prof[(c, True)]["ms"] for c in ("kway-small", "kway-bb", "kway-eval") if (c, True) in prof)
+    launches = prof[("kway-eval", True)]["launches"] if ("kway-eval", True) in prof else 0
+    return ms, launches
+
+
+def _event_ms(fn, reps):
+    """Mean device time of fn() over reps calls, HIP events on the current stream."""
+    import torch
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_wide(args):
+    """Wide union (Section 5.9, the union of all bitmaps of a collection;
+    Table 8's shape): one roaring_multi call over --wide bitmaps of the mixed
+    recipe, materialised with its cardinality; the count-only union beside it.
+    value = algorithmic input bytes (every container's payload + 19 B of
+    metadata) / time of the materialised union."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1709_07821_amd as rg
+    import synth
+
+    ctx = rg.Context(0)
+    k = args.wide
+    bs = synth.mixed_small(n_bitmaps=k, seed=synth.SEED_BASE + 7)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    h = rg.Pool.host_arrays(bs.values, bs.offsets)[3]
+    in_bytes = float(container_payload_bytes(h).sum()) + META_BYTES * len(h["keys"])
+    ids = torch.arange(k, dtype=torch.int32, device="cuda")
+    out, card = rg.multi(ctx, "or", P, ids, materialize=True, card=True)
+    torch.cuda.synchronize()
+    exp = oracle.kway("or", [bs[i] for i in range(k)])
+    dig = int(rg.rg_pool_digest(ctx, out.as_pool()).cpu().numpy().view(np.uint64)[0])
+    assert int(card.item()) == len(exp) and dig == oracle.digest(exp), "wide union differs from the oracle"
+    say(f"wide union of {k} bitmaps ({len(bs.values)} values, {len(h['keys'])} containers): "
+        f"{len(exp)} values, matches the oracle")
+    flags = rg.RG_FLAG_MATERIALIZE | rg.RG_FLAG_CARD
+
+    def step():
+        ctx.check(rg.roaring_multi(ctx, "or", P, ids, flags, out, card))
+
+    def step_count():
+        ctx.check(rg.roaring_multi(ctx, "or", P, ids, rg.RG_FLAG_CARD, None, card))
+
+    dt = time_steps(step, args.steps, args.warmup)
+    dtc = time_steps(step_count, args.steps, args.warmup)
+    rg.profile_enable(ctx, True)
+    rg.profile_reset(ctx)
+    time_steps(step, args.steps, 0)
+    prof = rg.profile_read(ctx)
+    rg.profile_enable(ctx, False)
+    out_pay, out_n = result_payload_bytes(out)
+    ms, launches = _kway_eval_ms(prof)
+    roof = None
+    if launches:
+        per = (in_bytes - META_BYTES * len(h["keys"]) + out_pay)
+        mean_s = ms / launches / 1e3
+        roof = {"bound": "hbm", "achieved": round(per / mean_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(per / mean_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_kw_eval (+ one-wave kernels; k-way evaluation step)",
+                "mean_launch_ms": round(mean_s * 1e3, 4), "launches": int(launches), "bytes_per_launch": int(per)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        lists = [bs[i] for i in range(k)]
+        cpu = cpu_baseline_tasks([lambda: oracle.kway("or", lists)], in_bytes, "GB/s",
+                                 f"the whole {k}-way union (left fold of two-way unions); the all-core rate runs "
+                                 f"independent copies of it side by side", args.cpu_seconds)
+    _line("input GB/s of a wide (k-way) union, materialised", round(in_bytes / dt / 1e9, 2), "GB/s", args,
+          dt * 1e3,
+          {"workload": f"wide union: {k} mixed bitmaps over [0, 2^26), 1e3..5e4 values, 40/30/30 sparse/dense/run; "
+                       f"one {k}-way OR materialised with its cardinality", "k": k,
+           "parallelism": "single GPU"},
+          {"union_values": len(exp), "result_containers": out_n, "count_only_ms": round(dtc * 1e3, 4),
+           "input_bytes": int(in_bytes)}, roof, cpu)
+
+
+def bench_access(args):
+    """Membership and export (Section 1 random access, Section 3.1 bitset to
+    values, Sections 5.5 and 5.6): --lookups (bitmap, value) membership tests,
+    half of them members, over a pool of --access-bitmaps mixed bitmaps; and the
+    export of the whole pool to sorted uint32. value = lookups/s; the export's
+    rate is reported beside it."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1709_07821_amd as rg
+    import synth
+
+    ctx = rg.Context(0)
+    nb = args.access_bitmaps
+    bs = synth.mixed_small(n_bitmaps=nb, seed=synth.SEED_BASE + 8)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    h = rg.Pool.host_arrays(bs.values, bs.offsets)[3]
+    rng = np.random.default_rng(synth.SEED_BASE + 9)
+    n = args.lookups
+    ids = rng.integers(0, nb, n).astype(np.uint32)
+    off = np.asarray(bs.offsets, np.int64)
+    member = rng.random(n) < 0.5
+    pick = off[ids] + (rng.random(n) * (off[ids + 1] - off[ids])).astype(np.int64)
+    xs = np.where(member, bs.values[np.minimum(pick, len(bs.values) - 1)],
+                  rng.integers(0, 1 << 26, n).astype(np.uint32)).astype(np.uint32)
+    d_ids = torch.from_numpy(ids.view(np.int32)).cuda()
+    d_xs = torch.from_numpy(xs.view(np.int32)).cuda()
+    d_out = torch.empty(n, dtype=torch.uint8, device="cuda")
+    ctx.check(rg.roaring_contains(ctx, P, d_ids, d_xs, d_out))
+    torch.cuda.synchronize()
+    m = min(n, 200000)
+    exp = oracle.contains_many(bs.values, bs.offsets, ids[:m], xs[:m])
+    assert np.array_equal(d_out[:m].cpu().numpy().astype(bool), exp.astype(bool)), "membership differs"
+    # export: offsets and values sized once, then timed into the same buffers
+    offsets, values = rg.to_uint32(ctx, P)
+    torch.cuda.synchronize()
+    assert np.array_equal(values.cpu().numpy().view(np.uint32), bs.values), "export differs from the input lists"
+    say(f"{m} lookups and the export of {nb} bitmaps ({len(bs.values)} values) match the oracle / the input")
+    nv = int(values.numel())
+
+    def look():
+        ctx.check(rg.roaring_contains(ctx, P, d_ids, d_xs, d_out))
+
+    def export():
+        st, _ = rg.roaring_to_uint32(ctx, P, 0, nb, offsets, values, nv)
+        ctx.check(st)
+
+    dt = time_steps(look, args.steps, args.warmup)
+    dte = time_steps(export, args.steps, args.warmup)
+    ms_look = _event_ms(look, args.steps)
+    ms_exp = _event_ms(export, args.steps)
+    pay = float(container_payload_bytes(h).sum())
+    exp_bytes = pay + META_BYTES * len(h["keys"]) + 4.0 * nv + 8.0 * (nb + 1)
+    look_bytes = 9.0 * n  # (bitmap, value) in, one byte out: the lookups' unavoidable traffic
+    roof = {"bound": "hbm", "achieved": round(look_bytes / (ms_look / 1e3) / 1e9, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(look_bytes / (ms_look / 1e3) / 1e9 / HBM_PEAK_GBS, 5), "traffic": None,
+            "kernel": "k_contains", "mean_launch_ms": round(ms_look, 4), "launches": args.steps,
+            "bytes_per_launch": int(look_bytes),
+            "note": "9 B per lookup; the key and container searches run in cache (latency-bound)"}
+    export_roof = {"bound": "hbm", "achieved": round(exp_bytes / (ms_exp / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                   "unit": "GB/s", "frac": round(exp_bytes / (ms_exp / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "kernel": "k_export_values (+ sizing kernels; one call)", "mean_call_ms": round(ms_exp, 4),
+                   "bytes_per_call": int(exp_bytes)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        ms_ = min(n, 1000000)
+        nt = cpu_threads()
+        chunk = max(1, ms_ // (4 * nt))
+        tasks = [(lambda s0=s0: oracle.contains_many(bs.values, bs.offsets, ids[s0:s0 + chunk], xs[s0:s0 + chunk]))
+                 for s0 in range(0, ms_, chunk)]
+        cpu = cpu_baseline_tasks(tasks, float(ms_), "lookups/s", f"{ms_} of the lookups (binary search over the "
+                                 f"sorted uint32 list)", args.cpu_seconds)
+    _line("membership lookups/s (batched contains); export values/s beside it", round(n / dt, 1), "lookups/s",
+          args, dt * 1e3,
+          {"workload": f"access: {nb} mixed bitmaps over [0, 2^26) ({len(bs.values)} values); {n} random "
+                       f"(bitmap, value) lookups, half members; export of the whole pool to sorted uint32",
+           "bitmaps": nb, "lookups": n, "parallelism": "single GPU"},
+          {"export_values_per_s": round(nv / dte, 1), "export_ms": round(dte * 1e3, 4), "export_values": nv,
+           "export_roofline": export_roof}, roof, cpu)
+
+
+def bench_canonical(args):
+    """Canonicalisation (Section 1: the least-memory container of every chunk;
+    Section 5.1: inputs run-optimised): a pool of --canon-bitmaps mixed bitmaps
+    stored in random well-formed forms (arrays of any length, bitsets of any
+    cardinality, runs cut into touching runs) rebuilt in P1 form.
+    value = algorithmic input bytes / time."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1709_07821_amd as rg
+    import synth
+    from tests import rgtest
+
+    ctx = rg.Context(0)
+    nb = args.canon_bitmaps
+    bs = synth.mixed_small(n_bitmaps=nb, seed=synth.SEED_BASE + 10)
+    sets = [bs[i] for i in range(nb)]
+    a = rgtest.noncanonical_arrays(sets, np.random.default_rng(synth.SEED_BASE + 11))
+    P = rg.Pool.from_host_arrays(a)
+    out = rg.canonicalize(ctx, P)
+    torch.cuda.synchronize()
+    dig = rg.rg_pool_digest(ctx, out.as_pool()).cpu().numpy().view(np.uint64)
+    for i in range(nb):
+        assert int(dig[i]) == oracle.digest(sets[i]), i
+    n_in = len(a["keys"])
+    pay_in = float(container_payload_bytes(a).sum())
+    in_bytes = pay_in + META_BYTES * n_in
+    say(f"{nb} bitmaps, {n_in} containers in random forms ({np.bincount(a['types'], minlength=4)[1:].tolist()} "
+        f"array/bitset/run): canonical forms match the oracle's fingerprints")
+
+    def step():
+        ctx.check(rg.lib().rg_pool_canonicalize(ctx.h, rg.ctypes.byref(P.c), rg.ctypes.byref(out.c), None))
+
+    dt = time_steps(step, args.steps, args.warmup)
+    rg.profile_enable(ctx, True)
+    rg.profile_reset(ctx)
+    time_steps(step, args.steps, 0)
+    prof = rg.profile_read(ctx)
+    rg.profile_enable(ctx, False)
+    out_pay, out_n = result_payload_bytes(out)
+    ms, launches = _kway_eval_ms(prof)
+    roof = None
+    if launches:
+        per = pay_in + out_pay
+        mean_s = ms / launches / 1e3
+        roof = {"bound": "hbm", "achieved": round(per / mean_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(per / mean_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_kw_small + k_kw_bb + k_kw_eval (k-way evaluation step, one-bitmap unions)",
+                "mean_launch_ms": round(mean_s * 1e3, 4), "launches": int(launches), "bytes_per_launch": int(per)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        nt = cpu_threads()
+        chunk = max(1, nb // (4 * nt))
+        tasks = [(lambda s0=s0: [oracle.containers(v) for v in sets[s0:s0 + chunk]]) for s0 in range(0, nb, chunk)]
+        cpu = cpu_baseline_tasks(tasks, in_bytes, "GB/s", f"the P1 container view of all {nb} bitmaps from their "
+                                 f"sorted lists", args.cpu_seconds)
+    _line("input GB/s of device canonicalisation (non-P1 pool to P1)", round(in_bytes / dt / 1e9, 2), "GB/s", args,
+          dt * 1e3,
+          {"workload": f"canonical: {nb} mixed bitmaps over [0, 2^26) stored in random well-formed forms "
+                       f"(1/3 arrays of any length, 1/3 bitsets, 1/3 runs cut into touching runs), rebuilt in P1 "
+                       f"form", "bitmaps": nb, "parallelism": "single GPU"},
+          {"containers_in": n_in, "containers_out": out_n, "containers_per_s": round(n_in / dt, 1)}, roof, cpu)
+
+
+def bench_inplace(args):
+    """In-place operations (Section 3.2: bits set, cleared, flipped with the
+    cardinality kept; Section 5.9's wide unions partly in place): --acc mutable
+    bitmaps, each changed by a fixed cycle of op= with bitmaps of a mixed pool
+    (union, intersection, symmetric difference, difference), every result and
+    cardinality checked against the oracle's fold after the timed steps.
+    value = operations/s."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1709_07821_amd as rg
+    import synth
+
+    ctx = rg.Context(0)
+    bs = synth.mixed_small(n_bitmaps=100, seed=synth.SEED_BASE + 12)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    h = rg.Pool.host_arrays(bs.values, bs.offsets)[3]
+    bb = h["bm_begin"].astype(np.int64)
+    pay = container_payload_bytes(h)
+    na = args.acc
+    M = rg.MutablePool(ctx, na, na * 1100)
+    state = []
+    for b in range(na):
+        M.assign(b, P, b)
+        state.append(bs[b])
+    rng = np.random.default_rng(synth.SEED_BASE + 13)
+    cycle = [("or", int(s)) for s in rng.integers(0, 100, 4)] + [("and", int(rng.integers(0, 100)))] + \
+            [("xor", int(rng.integers(0, 100))), ("andnot", int(rng.integers(0, 100)))] + \
+            [("or", int(s)) for s in rng.integers(0, 100, 1)]
+    ops_per_step = na * len(cycle)
+    step_bytes = float(sum(pay[bb[s]:bb[s + 1]].sum() + META_BYTES * (bb[s + 1] - bb[s]) for _, s in cycle)) * na
+    applied = 0
+
+    def step():
+        nonlocal applied
+        for op, s in cycle:
+            for b in range(na):
+                M.op(op, b, P, s)
+        applied += 1
+
+    dt = time_steps(step, args.steps, args.warmup)
+    st, free = M.status()
+    assert st == rg.RG_OK, st
+    for _ in range(applied):
+        for op, s in cycle:
+            state = [oracle.op(op, x, bs[s]) for x in state]
+    out = M.export()
+    hh = out.as_pool().to_host()
+    from tests import rgtest
+    cards = M.cards().cpu().numpy().view(np.uint64)
+    for b in range(na):
+        got, _ = rgtest.decode_bitmap(hh, b)
+        assert np.array_equal(got, state[b]) and int(cards[b]) == len(state[b]), b
+    say(f"{na} bitmaps after {applied} cycles of {len(cycle)} in-place ops each match the oracle's fold "
+        f"({free} free slots)")
+    ms_op = _event_ms(lambda: M.op("or", 0, P, cycle[0][1]), 20)
+    roof = {"bound": "hbm", "achieved": round(step_bytes / dt / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(step_bytes / dt / 1e9 / HBM_PEAK_GBS, 5), "traffic": None,
+            "kernel": "rg_mpool_op (classify, capacity check, evaluate, insert: one call per operation)",
+            "mean_call_ms": round(ms_op, 4), "bytes_per_step": int(step_bytes),
+            "note": "bytes: payload + metadata of the B operands; one operation is a few dependent launches"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        lists = [bs[b] for b in range(na)]
+
+        def fold(x=lists):
+            for op, s in cycle:
+                x = [oracle.op(op, y, bs[s]) for y in x]
+
+        cpu = cpu_baseline_tasks([fold], float(ops_per_step), "ops/s", f"one cycle of the {ops_per_step} "
+                                 f"operations on the initial bitmaps (two-pointer merges into new lists)",
+                                 args.cpu_seconds)
+    _line("in-place operations/s (A op= B with maintained cardinality)", round(ops_per_step / dt, 1), "ops/s", args,
+          dt * 1e3,
+          {"workload": f"inplace: {na} mutable bitmaps (starting as mixed bitmaps over [0, 2^26)), each changed by "
+                       f"a cycle of {len(cycle)} op= (or x5, and, xor, andnot) with bitmaps of a 100-bitmap mixed "
+                       f"pool", "accumulators": na, "parallelism": "single GPU"},
+          {"ops_per_step": ops_per_step, "input_gb_per_s": round(step_bytes / dt / 1e9, 3)}, roof, cpu)
 
 
 # ---------------------------------------------------------------- HBM byte counters
