@@ -330,7 +330,12 @@ def bench_dense(args):
                                "1e4 random pairs, |A op B| for AND/OR/XOR/ANDNOT + Jaccard",
                    "bitmaps": nb, "keys_per_bitmap": nk, "pairs": npairs, "parallelism": "single GPU"},
         "container_pairs_per_s": round(cps, 1),
+        # algorithmic input bytes of the step over the step time
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
+        # the counters' bytes (FETCH_SIZE + WRITE_SIZE, scaled) of the dominant
+        # kernel over its measured launch time, while they match its sources
+        "pct_hbm_peak_measured": (round(100 * roof["traffic"] / (roof["mean_launch_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS, 2)
+                                  if roof and roof["traffic"] else None),
         "roofline": roof,
         "cpu_baseline": cpu,
     }

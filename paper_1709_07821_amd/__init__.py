@@ -25,7 +25,7 @@ RG_OK, RG_EINVAL, RG_ECAPACITY, RG_EDEVICE, RG_EFORMAT, RG_ENOTSUP = 0, -1, -2, 
 RG_ARRAY, RG_BITSET, RG_RUN = 1, 2, 3
 RG_AND, RG_OR, RG_XOR, RG_ANDNOT = 0, 1, 2, 3
 OPS = {"and": RG_AND, "or": RG_OR, "xor": RG_XOR, "andnot": RG_ANDNOT}
-RG_FLAG_MATERIALIZE, RG_FLAG_CARD, RG_FLAG_JACCARD = 1, 2, 4
+RG_FLAG_MATERIALIZE, RG_FLAG_CARD, RG_FLAG_JACCARD, RG_FLAG_DIGEST = 1, 2, 4, 8
 RG_RULES_P1 = 1
 RG_KEY_INDEX_BYTES = 10240
 RG_DISPATCH_HEURISTIC, RG_DISPATCH_MLP, RG_DISPATCH_FIXED = 0, 1, 2
@@ -801,17 +801,18 @@ class Server:
         ctx.servers.add(self)
 
     @staticmethod
-    def _query(op, ids, materialize):
+    def _query(op, ids, materialize, digest=False):
         import numpy as np
 
         ids = np.ascontiguousarray(ids, dtype=np.uint32)
         q = rg_query(OPS[op] if isinstance(op, str) else op, len(ids),
                      ids.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
-                     RG_FLAG_MATERIALIZE if materialize else RG_FLAG_CARD)
+                     (RG_FLAG_MATERIALIZE if materialize else RG_FLAG_CARD) | (RG_FLAG_DIGEST if digest else 0))
         return q, ids
 
-    def submit(self, op, ids, materialize=False) -> int:
-        q, keep = self._query(op, ids, materialize)
+    def submit(self, op, ids, materialize=False, digest=False) -> int:
+        """digest: also compute the result's fingerprint (rg_result.digest)."""
+        q, keep = self._query(op, ids, materialize, digest)
         t = ctypes.c_uint64()
         self.ctx.check(lib().rg_serve_submit(self.h, ctypes.byref(q), 0, ctypes.byref(t)))
         return t.value
@@ -824,16 +825,17 @@ class Server:
     def release(self, ticket: int):
         self.ctx.check(lib().rg_serve_release(self.h, ticket))
 
-    def replay(self, queries, arrival_ns):
+    def replay(self, queries, arrival_ns, digest=False):
         """queries: list of (op, ids, materialize); arrival_ns: offsets from the start.
-        Returns (latency_ns, cards, digests) as numpy uint64 arrays."""
+        Returns (latency_ns, cards, digests) as numpy uint64 arrays (digests 0
+        unless digest=True)."""
         import numpy as np
 
         n = len(queries)
         arr = (rg_query * max(n, 1))()
         keep = []
         for i, (op, ids, mat) in enumerate(queries):
-            q, k = self._query(op, ids, mat)
+            q, k = self._query(op, ids, mat, digest)
             arr[i] = q
             keep.append(k)
         at = np.ascontiguousarray(arrival_ns, dtype=np.uint64)

@@ -166,9 +166,81 @@ __global__ void __launch_bounds__(256) k_kw_keys_small(KwArgs a) {
     if (lane == 0 && pos > kbound) atomicOr(a.err, 1u);
 }
 
+constexpr uint32_t KW_KEY_UNROLL = 16;  // keys per thread per round of a multi-bitmap key pass
+constexpr uint32_t KW_AND_GROUP = 4;    // bitmaps whose key masks an intersection fills at once
+
+// Sets the key bits of the query's bitmaps j0 .. j1-1 (key lists at rs[j],
+// rn[j]) in one pass over their concatenated lists: into masks[j - j0] when
+// per_bitmap, else all into masks[0]. Each thread takes KW_KEY_UNROLL
+// consecutive keys per round (their loads issued together); sorted lists put
+// most of them in one or two 64-key words, so the thread ORs their bits
+// together and issues one LDS atomic per word it touches (the keys of many
+// bitmaps over a small universe otherwise pile onto a few words). roff gets
+// the exclusive prefix of the lengths. Ends with a barrier.
+__device__ void kw_fill_keys(const KwArgs& a, const uint64_t* rs, const uint32_t* rn, uint32_t* roff, uint32_t j0,
+                             uint32_t j1, uint64_t (*masks)[1024], bool per_bitmap) {
+    const uint32_t tid = threadIdx.x, m = j1 - j0;
+    if (tid == 0) {
+        uint32_t o = 0;
+        for (uint32_t j = 0; j < m; ++j) {
+            roff[j] = o;
+            o += rn[j0 + j];
+        }
+        roff[m] = o;
+    }
+    __syncthreads();
+    const uint32_t total = uniform(roff[m]);
+    for (uint32_t base = 0; base < total; base += 256 * KW_KEY_UNROLL) {
+        const uint32_t i0 = base + tid * KW_KEY_UNROLL;
+        uint32_t jj = 0;  // the bitmap holding position i0 (a binary search over roff)
+        if (i0 < total) {
+            uint32_t lo = 0, hi = m - 1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) >> 1;
+                if (roff[mid] <= i0) lo = mid;
+                else hi = mid - 1;
+            }
+            jj = lo;
+        }
+        uint32_t key[KW_KEY_UNROLL], mi[KW_KEY_UNROLL];
+#pragma unroll
+        for (uint32_t r = 0; r < KW_KEY_UNROLL; ++r) {
+            const uint32_t i = i0 + r;
+            key[r] = 0xFFFFFFFFu;
+            mi[r] = 0;
+            if (i < total) {
+                while (roff[jj + 1] <= i) ++jj;  // i only grows, so jj only moves forward
+                const uint32_t j = j0 + jj;
+                const uint16_t* pkeys = j ? a.P1.keys : a.P0.keys;
+                key[r] = pkeys[rs[j] + (i - roff[jj])];
+                mi[r] = per_bitmap ? jj : 0u;
+            }
+        }
+        // runs of keys in the same word of the same mask: one atomic each
+        uint32_t cw = 0xFFFFFFFFu, cm = 0;
+        uint64_t bits = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < KW_KEY_UNROLL; ++r) {
+            if (key[r] == 0xFFFFFFFFu) continue;
+            const uint32_t w = key[r] >> 6;
+            if (w != cw || mi[r] != cm) {
+                if (bits) atomicOr(reinterpret_cast<unsigned long long*>(&masks[cm][cw]), bits);
+                cw = w;
+                cm = mi[r];
+                bits = 0;
+            }
+            bits |= 1ull << (key[r] & 63);
+        }
+        if (bits) atomicOr(reinterpret_cast<unsigned long long*>(&masks[cm][cw]), bits);
+    }
+    __syncthreads();
+}
+
 __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a, uint32_t chunk) {
-    __shared__ uint64_t acc[1024];
-    __shared__ uint64_t cur[1024];
+    __shared__ uint64_t accm[1][1024];
+    __shared__ uint64_t grp[KW_AND_GROUP][1024];  // key masks of a group of bitmaps (intersection)
+    uint64_t* acc = accm[0];
+    uint64_t* cur = grp[0];
     __shared__ uint32_t tmp[8];
     __shared__ uint64_t rs[KW_MAX_K];  // key-list start of each of the query's bitmaps
     __shared__ uint32_t rn[KW_MAX_K];  // and its length
@@ -247,63 +319,22 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a, uint32_t chunk) {
     } else if (op != RG_AND) {
         // a union of key sets: every key of every deciding bitmap sets its bit,
         // in one pass over the concatenated lists
-        if (tid == 0) {
-            uint32_t o = 0;
-            for (uint32_t j = 0; j < kk; ++j) {
-                roff[j] = o;
-                o += rn[j];
-            }
-            roff[kk] = o;
-        }
-        __syncthreads();
-        const uint32_t total_keys = uniform(roff[kk]);
-        uint32_t j = 0;
-        // KW_UNROLL keys per thread per round: their loads are issued together
-        for (uint32_t base = 0; base < total_keys; base += 256 * KW_UNROLL) {
-            uint32_t key[KW_UNROLL];
-#pragma unroll
-            for (int r = 0; r < KW_UNROLL; ++r) {
-                const uint32_t i = base + r * 256 + tid;
-                key[r] = 0xFFFFFFFFu;
-                if (i < total_keys) {
-                    while (roff[j + 1] <= i) ++j;  // i only grows, so j only moves forward
-                    const uint16_t* pkeys = j ? a.P1.keys : a.P0.keys;
-                    key[r] = pkeys[rs[j] + (i - roff[j])];
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < KW_UNROLL; ++r)
-                if (key[r] != 0xFFFFFFFFu)
-                    atomicOr(reinterpret_cast<unsigned long long*>(&acc[key[r] >> 6]), 1ull << (key[r] & 63));
-        }
-        __syncthreads();
+        kw_fill_keys(a, rs, rn, roff, 0, kk, accm, false);
     } else {
-        for (uint32_t j = 0; j < k; ++j) {
-            const uint16_t* pkeys = j ? a.P1.keys : a.P0.keys;
-            const uint64_t s0 = rs[j];
-            const uint32_t n = uniform(rn[j]);
-            uint64_t* dst = j == 0 ? acc : cur;
-            if (j) {
-                for (uint32_t i = tid; i < 1024; i += 256) cur[i] = 0;
-                __syncthreads();
-            }
-            for (uint32_t base = 0; base < n; base += 256 * KW_UNROLL) {
-                uint32_t key[KW_UNROLL];
-#pragma unroll
-                for (int r = 0; r < KW_UNROLL; ++r) {
-                    const uint32_t i = base + r * 256 + tid;
-                    key[r] = i < n ? pkeys[s0 + i] : 0xFFFFFFFFu;
-                }
-#pragma unroll
-                for (int r = 0; r < KW_UNROLL; ++r)
-                    if (key[r] != 0xFFFFFFFFu)
-                        atomicOr(reinterpret_cast<unsigned long long*>(&dst[key[r] >> 6]), 1ull << (key[r] & 63));
+        // intersection: the first bitmap's keys, then groups of KW_AND_GROUP
+        // bitmaps, each into its own mask in one pass, ANDed into the result
+        kw_fill_keys(a, rs, rn, roff, 0, 1, accm, false);
+        for (uint32_t j0 = 1; j0 < k; j0 += KW_AND_GROUP) {
+            const uint32_t j1 = j0 + KW_AND_GROUP < k ? j0 + KW_AND_GROUP : k;
+            for (uint32_t i = tid; i < (j1 - j0) * 1024; i += 256) grp[i >> 10][i & 1023] = 0;
+            __syncthreads();
+            kw_fill_keys(a, rs, rn, roff, j0, j1, grp, true);
+            for (uint32_t i = tid; i < 1024; i += 256) {
+                uint64_t x = acc[i];
+                for (uint32_t g = 0; g < j1 - j0; ++g) x &= grp[g][i];
+                acc[i] = x;
             }
             __syncthreads();
-            if (j) {
-                for (uint32_t i = tid; i < 1024; i += 256) acc[i] &= cur[i];
-                __syncthreads();
-            }
         }
     }
     // ascending keys: thread t owns words 4t..4t+3

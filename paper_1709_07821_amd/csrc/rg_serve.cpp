@@ -165,13 +165,14 @@ StepOut own_out(const StepLayout& L, uint8_t* d) {
 // results once the stream reaches the end of the step.
 // prof: the context whose kernel timing brackets the evaluation kernel
 // (roaring_multi), or null (the server, which never touches the context).
+// digest: the step's results get their fingerprints (some query asked).
 rg_status step_enqueue(std::string* err_out, const rg_pool& pool, const StepLayout& L, uint8_t* d, const StepOut& o,
-                       uint8_t* h_stage, hipStream_t st, rg_ctx* prof = nullptr) {
+                       uint8_t* h_stage, hipStream_t st, bool digest, rg_ctx* prof = nullptr) {
     auto* queries = reinterpret_cast<KwQuery*>(d + L.o_queries);
     auto* ids = reinterpret_cast<uint32_t*>(d + L.o_ids);
     auto* cand = reinterpret_cast<uint64_t*>(d + L.o_cand);
     auto* cards = reinterpret_cast<uint64_t*>(d + L.o_cards);
-    auto* digest = reinterpret_cast<uint64_t*>(d + L.o_digest);
+    auto* d_digest = reinterpret_cast<uint64_t*>(d + L.o_digest);
     auto* totals = reinterpret_cast<uint64_t*>(d + L.o_totals);
     auto* err = reinterpret_cast<uint32_t*>(d + L.o_err);
     auto* tasks = reinterpret_cast<Task*>(d + L.o_tasks);
@@ -239,7 +240,7 @@ rg_status step_enqueue(std::string* err_out, const rg_pool& pool, const StepLayo
     launch_kw_cards(a, o.bm_card, cards, st);
     rg_pool outp{L.nq, L.S, L.P, step_bm_begin, o.keys, o.types, o.card, o.size, o.off, o.payload, o.bm_card,
                  o.bm_wbytes};
-    launch_pool_digest_n(outp, totals + 1, digest, st);
+    if (digest) launch_pool_digest_n(outp, totals + 1, d_digest, st);
     STEPCHK(hipMemcpyAsync(h_stage + L.down_off, d + L.down_off, L.down_bytes, hipMemcpyDeviceToHost, st));
     STEPCHK(hipGetLastError());
     return RG_OK;
@@ -312,7 +313,7 @@ extern "C" rg_status roaring_multi(rg_ctx* c, int op, const rg_pool* pool, const
     StepOut o = mat ? StepOut{out->bm_begin, out->keys, out->types, out->card, out->size, out->off, out->payload,
                               out->bm_card, out->bm_wbytes}
                     : own_out(L, d);
-    if (rg_status s = step_enqueue(&c->err, *pool, L, d, o, h, st, c)) return s;
+    if (rg_status s = step_enqueue(&c->err, *pool, L, d, o, h, st, false, c)) return s;
     HIPCHK(c, hipStreamSynchronize(st));
     const uint64_t* totals = reinterpret_cast<const uint64_t*>(h + L.o_totals);
     const uint32_t err = *reinterpret_cast<const uint32_t*>(h + L.o_err);
@@ -489,7 +490,7 @@ void rg_server::retire_locked(Step* s) {
         e.done_ns = t_done;
         e.status = err ? RG_EDEVICE : RG_OK;
         e.card = cards[i];
-        e.digest = dig[i];
+        e.digest = (e.q.flags & RG_FLAG_DIGEST) ? dig[i] : 0;
         e.n_containers = bmb[i + 1] - bmb[i];
         e.c_end = bmb[i + 1];
         ++n_done;
@@ -544,8 +545,10 @@ void rg_server::run() {
                     std::vector<KwQuery> qs;
                     std::vector<uint32_t> ids;
                     uint64_t slot = 0;
+                    bool digest = false;
                     for (uint32_t i = 0; i < take.size(); ++i) {
                         Entry& e = *entries[take[i]];
+                        digest |= (e.q.flags & RG_FLAG_DIGEST) != 0;
                         e.step = s;
                         e.q_in_step = i;
                         qs.push_back(KwQuery{(uint32_t)e.q.op, e.q.k, (uint32_t)ids.size(),
@@ -560,7 +563,7 @@ void rg_server::run() {
                     sum_batch += take.size();
                     lk.unlock();
                     std::string step_err;
-                    rg_status st = step_enqueue(&step_err, pool, s->L, s->d, own_out(s->L, s->d), s->h, s->st);
+                    rg_status st = step_enqueue(&step_err, pool, s->L, s->d, own_out(s->L, s->d), s->h, s->st, digest);
                     if (st == RG_OK && hipEventCreateWithFlags(&s->done, hipEventDisableTiming) != hipSuccess)
                         st = RG_EDEVICE;
                     if (st == RG_OK && hipEventRecord(s->done, s->st) != hipSuccess) st = RG_EDEVICE;
