@@ -77,7 +77,7 @@ def main():
     ap.add_argument("--access-bitmaps", type=int, default=1000, help="access: bitmaps in the pool")
     ap.add_argument("--lookups", type=int, default=10000000, help="access: membership lookups per step")
     ap.add_argument("--canon-bitmaps", type=int, default=1000, help="canonical: bitmaps in the pool")
-    ap.add_argument("--acc", type=int, default=16, help="inplace: mutable bitmaps")
+    ap.add_argument("--acc", type=int, default=64, help="inplace: mutable bitmaps")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES bytes (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -1296,8 +1296,10 @@ def bench_inplace(args):
     cardinality kept; Section 5.9's wide unions partly in place): --acc mutable
     bitmaps, each changed by a fixed cycle of op= with bitmaps of a mixed pool
     (union, intersection, symmetric difference, difference), every result and
-    cardinality checked against the oracle's fold after the timed steps.
-    value = operations/s."""
+    cardinality checked against the oracle's fold after the timed steps. A step
+    is one cycle, each of its operations applied to all bitmaps in one batched
+    call (rg_mpool_op_batch); one call per operation (rg_mpool_op) is timed
+    beside it. value = operations/s of the batched calls."""
     import numpy as np
     import torch
 
@@ -1324,14 +1326,22 @@ def bench_inplace(args):
     ops_per_step = na * len(cycle)
     step_bytes = float(sum(pay[bb[s]:bb[s + 1]].sum() + META_BYTES * (bb[s + 1] - bb[s]) for _, s in cycle)) * na
     applied = 0
+    targets = np.arange(na, dtype=np.uint32)
 
-    def step():
+    def step_single():
         nonlocal applied
         for op, s in cycle:
             for b in range(na):
                 M.op(op, b, P, s)
         applied += 1
 
+    def step():
+        nonlocal applied
+        for op, s in cycle:
+            M.op_batch([op] * na, targets, P, [s] * na)
+        applied += 1
+
+    dt_single = time_steps(step_single, args.steps, args.warmup)
     dt = time_steps(step, args.steps, args.warmup)
     st, free = M.status()
     assert st == rg.RG_OK, st
@@ -1347,12 +1357,12 @@ def bench_inplace(args):
         assert np.array_equal(got, state[b]) and int(cards[b]) == len(state[b]), b
     say(f"{na} bitmaps after {applied} cycles of {len(cycle)} in-place ops each match the oracle's fold "
         f"({free} free slots)")
-    ms_op = _event_ms(lambda: M.op("or", 0, P, cycle[0][1]), 20)
+    ms_op = _event_ms(lambda: M.op_batch(["or"] * na, targets, P, [cycle[0][1]] * na), 20)
     roof = {"bound": "hbm", "achieved": round(step_bytes / dt / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(step_bytes / dt / 1e9 / HBM_PEAK_GBS, 5), "traffic": None,
-            "kernel": "rg_mpool_op (classify, capacity check, evaluate, insert: one call per operation)",
+            "kernel": "rg_mpool_op_batch (classify, capacity check, drop, evaluate, insert: six launches per batch)",
             "mean_call_ms": round(ms_op, 4), "bytes_per_step": int(step_bytes),
-            "note": "bytes: payload + metadata of the B operands; one operation is a few dependent launches"}
+            "note": "bytes: payload + metadata of the B operands; mean_call_ms: one batched union of every bitmap"}
     cpu = None
     if not args.no_cpu_baseline:
         lists = [bs[b] for b in range(na)]
@@ -1364,12 +1374,14 @@ def bench_inplace(args):
         cpu = cpu_baseline_tasks([fold], float(ops_per_step), "ops/s", f"one cycle of the {ops_per_step} "
                                  f"operations on the initial bitmaps (two-pointer merges into new lists)",
                                  args.cpu_seconds)
-    _line("in-place operations/s (A op= B with maintained cardinality)", round(ops_per_step / dt, 1), "ops/s", args,
+    _line("in-place operations/s (A op= B with maintained cardinality, batched)", round(ops_per_step / dt, 1), "ops/s",
+          args,
           dt * 1e3,
           {"workload": f"inplace: {na} mutable bitmaps (starting as mixed bitmaps over [0, 2^26)), each changed by "
                        f"a cycle of {len(cycle)} op= (or x5, and, xor, andnot) with bitmaps of a 100-bitmap mixed "
                        f"pool", "accumulators": na, "parallelism": "single GPU"},
-          {"ops_per_step": ops_per_step, "input_gb_per_s": round(step_bytes / dt / 1e9, 3)}, roof, cpu)
+          {"ops_per_step": ops_per_step, "input_gb_per_s": round(step_bytes / dt / 1e9, 3),
+           "one_call_per_op_ops_per_s": round(ops_per_step / dt_single, 1)}, roof, cpu)
 
 
 # ---------------------------------------------------------------- HBM byte counters

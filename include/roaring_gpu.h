@@ -80,6 +80,7 @@ typedef enum { RG_AND = 0, RG_OR = 1, RG_XOR = 2, RG_ANDNOT = 3 } rg_op;
 #define RG_FLAG_MATERIALIZE 1u /* build the result bitmaps into rg_out */
 #define RG_FLAG_CARD 2u        /* write |result| per pair into d_cards (uint64) */
 #define RG_FLAG_JACCARD 4u     /* write |A n B| / |A u B| per pair into d_jacc (binary64) */
+#define RG_FLAG_DIGEST 8u      /* serving queries: also compute the result's fingerprint */
 
 typedef struct rg_ctx rg_ctx;
 
@@ -426,7 +427,9 @@ rg_status roaring_multi(rg_ctx *ctx, int op, const rg_pool *pool, const uint32_t
  * roaring_multi) over k bitmap ids (host
  * array, copied at submission) of the server's pool; flags RG_FLAG_CARD
  * (count only) or RG_FLAG_MATERIALIZE (the result containers are built and
- * stay readable through rg_result.view until the query is released). */
+ * stay readable through rg_result.view until the query is released), plus
+ * RG_FLAG_DIGEST for the result's fingerprint in rg_result.digest (one more
+ * kernel in the query's step; without it digest is 0). */
 typedef struct rg_query {
     int op;
     uint32_t k;
@@ -438,7 +441,8 @@ typedef struct rg_result {
     int done;              /* 0: not finished yet (the other fields are unset) */
     int status;            /* RG_OK, or the failure of the step that ran it */
     uint64_t card;         /* |result| */
-    uint64_t digest;       /* fingerprint of the result's container form (0 for count-only) */
+    uint64_t digest;       /* fingerprint of the result's container form (RG_FLAG_DIGEST; 0 for
+                              count-only queries and queries without the flag) */
     uint64_t n_containers;
     uint64_t latency_ns;   /* arrival (or submission) to result-ready */
     rg_pool view;          /* materialised result as a one-bitmap window into the
@@ -541,6 +545,15 @@ typedef struct rg_mpool rg_mpool;
 rg_status rg_mpool_create(rg_ctx *ctx, uint32_t n_bitmaps, uint32_t n_slots, rg_mpool **mp);
 void rg_mpool_destroy(rg_mpool *mp);
 rg_status rg_mpool_op(rg_mpool *mp, int op, uint32_t b, const rg_pool *P, uint32_t src, void *stream);
+/* n operations at once: M[bitmaps[i]] ops[i]= P[srcs[i]] (host arrays, the
+ * bitmaps distinct: RG_EINVAL otherwise), run as device batches of up to 64
+ * operations, each in the same six launches whatever its size. The keys the
+ * batch's unions and symmetric differences insert are checked against the
+ * free slots for the batch as a whole: when they do not fit, the whole batch
+ * is skipped (its bitmaps unchanged) and rg_mpool_status reports
+ * RG_ECAPACITY. Results equal the operations applied one by one. */
+rg_status rg_mpool_op_batch(rg_mpool *mp, uint32_t n, const int *ops, const uint32_t *bitmaps, const rg_pool *P,
+                            const uint32_t *srcs, void *stream);
 rg_status rg_mpool_assign(rg_mpool *mp, uint32_t b, const rg_pool *P, uint32_t src, void *stream);
 rg_status rg_mpool_clear(rg_mpool *mp, uint32_t b, void *stream);
 rg_status rg_mpool_cards(rg_mpool *mp, uint64_t *d_cards, void *stream);

@@ -47,7 +47,7 @@ EXPORTS = ["rg_create", "rg_destroy", "rg_last_error", "rg_set_dispatch", "rg_se
            "roaring_contains", "roaring_to_uint32", "rg_pool_check", "rg_pool_canonicalize",
            "rg_plan_create_mat", "rg_plan_result", "rg_plan_totals", "rg_set_wave_slots",
            "rg_mpool_create", "rg_mpool_destroy", "rg_mpool_op", "rg_mpool_assign", "rg_mpool_clear",
-           "rg_mpool_cards", "rg_mpool_status", "rg_mpool_export", "rg_pool_key_index"]
+           "rg_mpool_cards", "rg_mpool_status", "rg_mpool_export", "rg_pool_key_index", "rg_mpool_op_batch"]
 
 
 class RoaringError(RuntimeError):
@@ -163,6 +163,7 @@ def lib():
         L.rg_mpool_destroy.argtypes = [V]
         L.rg_mpool_destroy.restype = None
         L.rg_mpool_op.argtypes = [V, I, U32, pool_p, U32, V]
+        L.rg_mpool_op_batch.argtypes = [V, U32, V, V, pool_p, V, V]
         L.rg_mpool_assign.argtypes = [V, U32, pool_p, U32, V]
         L.rg_mpool_clear.argtypes = [V, U32, V]
         L.rg_mpool_cards.argtypes = [V, V, V]
@@ -713,6 +714,17 @@ class MutablePool:
     def op(self, op, b: int, P: Pool, src: int, stream=None):
         op = OPS[op] if isinstance(op, str) else op
         self.ctx.check(lib().rg_mpool_op(self.h, op, b, ctypes.byref(P.c), src, _stream(stream)))
+
+    def op_batch(self, ops, bitmaps, P: Pool, srcs, stream=None):
+        """rg_mpool_op_batch: M[bitmaps[i]] ops[i]= P[srcs[i]], the bitmaps distinct."""
+        import numpy as np
+
+        o = np.ascontiguousarray([OPS[x] if isinstance(x, str) else x for x in ops], dtype=np.int32)
+        bm = np.ascontiguousarray(bitmaps, dtype=np.uint32)
+        sr = np.ascontiguousarray(srcs, dtype=np.uint32)
+        assert len(o) == len(bm) == len(sr)
+        self.ctx.check(lib().rg_mpool_op_batch(self.h, len(o), o.ctypes.data, bm.ctypes.data, ctypes.byref(P.c),
+                                               sr.ctypes.data, _stream(stream)))
 
     def assign(self, b: int, P: Pool, src: int, stream=None):
         self.ctx.check(lib().rg_mpool_assign(self.h, b, ctypes.byref(P.c), src, _stream(stream)))

@@ -24,12 +24,30 @@ struct MutView {
     uint32_t* present;     // [65536 x 2]: (container of B, slot of A) for keys in both
     uint32_t* absent;      // [65536]: containers of B whose key A lacks
     uint32_t* counts;      // [2]: entries of present, absent
+    // batches of operations on distinct bitmaps (launch_mut_batch)
+    uint64_t* bbase;       // [MUT_BATCH_MAX + 1]: exclusive prefix of the B operands' key counts
+    uint64_t* tbits;       // [MUT_BATCH_MAX * 65536 / 64]: per (operation, key of B), set when A lacks the key
+};
+
+constexpr uint32_t MUT_BATCH_MAX = 64;  // operations per device batch
+
+// one batch: M[b[i]] op[i]= P[src[i]] for i < n, the b[i] distinct (passed by value)
+struct MutBatch {
+    uint32_t n;
+    int32_t op[MUT_BATCH_MAX];
+    uint32_t b[MUT_BATCH_MAX];
+    uint32_t src[MUT_BATCH_MAX];
 };
 
 void launch_mut_init(const MutView& m, hipStream_t st);
 // M[b] op= P[src]: classify B's keys, check the free slots, drop / evaluate /
 // insert, adjusting bm_card[b] by each key's change of cardinality
 void launch_mut_op(const MutView& m, int op, uint32_t b, const rg_pool& P, uint32_t src, hipStream_t st);
+// a batch of operations on distinct bitmaps in six launches: the keys every
+// union / symmetric difference inserts are counted and checked against the
+// free slots for the whole batch (skipped as a whole, sticky error, when they
+// do not fit), then drop (intersections), evaluate, insert as for one op
+void launch_mut_batch(const MutView& m, const MutBatch& bt, const rg_pool& P, hipStream_t st);
 void launch_mut_clear(const MutView& m, uint32_t b, hipStream_t st);
 // export of bitmaps b0 .. b0+n-1: per bitmap container count and payload bytes
 void launch_mut_measure(const MutView& m, uint32_t b0, uint32_t n, uint64_t* cnt, uint64_t* bytes, hipStream_t st);

@@ -169,79 +169,90 @@ __device__ __forceinline__ void mut_fold(uint64_t* s, const uint8_t* pl, uint8_t
     __syncthreads();
 }
 
-__global__ void __launch_bounds__(256) k_mut_eval(MutView m, int op, uint32_t b, rg_pool P) {
-    __shared__ WgShared sh;
+// M[b]'s container in `slot` op= container j of P, in place (one workgroup):
+// A's container is expanded into LDS, B's applied (set / flip / clear per
+// value or run, word-wise for bitsets, AND through a second expansion), and
+// the P1 result written back into the same slot; an empty result frees it.
+// The bitmap's cardinality moves by the key's change.
+__device__ void mut_eval_one(const MutView& m, int op, uint32_t b, const rg_pool& P, uint32_t j, uint32_t slot,
+                             WgShared& sh) {
     const uint32_t tid = threadIdx.x;
-    if (uniform((uint32_t)m.ctl[3])) return;  // skipped: not enough free slots
-    const uint32_t n = uniform(m.counts[0]);
     const PoolView A = mut_view(m);
     const PoolView B = view_of(P);
     const SlotOut so{m.s_off, m.slab, m.s_card, m.s_type, m.s_size, nullptr, nullptr};
-    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const uint32_t j = uniform(m.present[2 * i]), slot = uniform(m.present[2 * i + 1]);
-        const uint32_t old_c = uniform(m.s_card[slot]);
-        const uint16_t key = (uint16_t)uniform(P.keys[j]);
-        expand_container(sh.sa, A, slot, sh);  // ends with a barrier
-        const uint8_t tb = (uint8_t)uniform(P.types[j]);
-        const uint32_t sb = uniform(P.size[j]);
-        const uint8_t* pb = P.payload + uniform64(P.off[j]);
-        uint64_t w[4];
-        if (op == RG_AND || tb == RG_BITSET) {
-            if (op == RG_AND) expand_container(sh.sb, B, j, sh);
-            const uint64_t* bw = op == RG_AND ? sh.sb : reinterpret_cast<const uint64_t*>(pb);
+    const uint32_t old_c = uniform(m.s_card[slot]);
+    const uint16_t key = (uint16_t)uniform(P.keys[j]);
+    expand_container(sh.sa, A, slot, sh);  // ends with a barrier
+    const uint8_t tb = (uint8_t)uniform(P.types[j]);
+    const uint32_t sb = uniform(P.size[j]);
+    const uint8_t* pb = P.payload + uniform64(P.off[j]);
+    uint64_t w[4];
+    if (op == RG_AND || tb == RG_BITSET) {
+        if (op == RG_AND) expand_container(sh.sb, B, j, sh);
+        const uint64_t* bw = op == RG_AND ? sh.sb : reinterpret_cast<const uint64_t*>(pb);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint64_t a = sh.sa[4 * tid + q], x = bw[4 * tid + q];
-                w[q] = op == RG_AND ? (a & x) : op == RG_OR ? (a | x) : op == RG_XOR ? (a ^ x) : (a & ~x);
-            }
-        } else {
-            if (op == RG_OR) mut_fold<0>(sh.sa, pb, tb, sb);
-            else if (op == RG_XOR) mut_fold<1>(sh.sa, pb, tb, sb);
-            else mut_fold<2>(sh.sa, pb, tb, sb);
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t a = sh.sa[4 * tid + q], x = bw[4 * tid + q];
+            w[q] = op == RG_AND ? (a & x) : op == RG_OR ? (a | x) : op == RG_XOR ? (a ^ x) : (a & ~x);
+        }
+    } else {
+        if (op == RG_OR) mut_fold<0>(sh.sa, pb, tb, sb);
+        else if (op == RG_XOR) mut_fold<1>(sh.sa, pb, tb, sb);
+        else mut_fold<2>(sh.sa, pb, tb, sb);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) w[q] = sh.sa[4 * tid + q];
-        }
-        // the result goes back into A's slot (8 KiB: any P1 container fits);
-        // A's payload was read into LDS above, so nothing still reads it
-        const uint32_t c = finalize_words(w, slot, so, sh.sa, sh.sb, sh);
-        if (tid == 0) {
-            if (c == 0) {
-                m.s_card[slot] = 0;
-                m.dir[(uint64_t)b * MUT_KEYS + key] = NONE;
-                mut_free(m, slot);
-            }
-            add_card(m, b, (long long)c - (long long)old_c);
-        }
-        __syncthreads();
+        for (int q = 0; q < 4; ++q) w[q] = sh.sa[4 * tid + q];
     }
+    // the result goes back into A's slot (8 KiB: any P1 container fits);
+    // A's payload was read into LDS above, so nothing still reads it
+    const uint32_t c = finalize_words(w, slot, so, sh.sa, sh.sb, sh);
+    if (tid == 0) {
+        if (c == 0) {
+            m.s_card[slot] = 0;
+            m.dir[(uint64_t)b * MUT_KEYS + key] = NONE;
+            mut_free(m, slot);
+        }
+        add_card(m, b, (long long)c - (long long)old_c);
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_mut_eval(MutView m, int op, uint32_t b, rg_pool P) {
+    __shared__ WgShared sh;
+    if (uniform((uint32_t)m.ctl[3])) return;  // skipped: not enough free slots
+    const uint32_t n = uniform(m.counts[0]);
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x)
+        mut_eval_one(m, op, b, P, uniform(m.present[2 * i]), uniform(m.present[2 * i + 1]), sh);
 }
 
 // union, symmetric difference: one wave per key A lacks takes a free slot and
 // copies B's container (already in P1 form)
+// container j of P copied into a free slot as M[b]'s container at its key (one wave)
+__device__ __forceinline__ void mut_insert_one(const MutView& m, uint32_t b, const rg_pool& P, uint32_t j,
+                                               uint32_t lane) {
+    uint32_t slot = 0;
+    if (lane == 0) slot = m.free_list[atomicSub(&m.ctl[0], 1) - 1];  // the check kept this >= 0
+    slot = __builtin_amdgcn_readlane(slot, 0);
+    const uint8_t t = (uint8_t)uniform(P.types[j]);
+    const uint32_t sz = uniform(P.size[j]), c = uniform(P.card[j]);
+    const uint32_t units = (payload_bytes_of(t, sz) + 15) / 16;
+    const u32x4* s4 = reinterpret_cast<const u32x4*>(P.payload + uniform64(P.off[j]));
+    u32x4* d4 = reinterpret_cast<u32x4*>(m.slab + (uint64_t)slot * MUT_SLOT_BYTES);
+    for (uint32_t u = lane; u < units; u += 64) d4[u] = s4[u];
+    if (lane == 0) {
+        m.s_type[slot] = t;
+        m.s_size[slot] = sz;
+        m.s_card[slot] = c;
+        m.dir[(uint64_t)b * MUT_KEYS + P.keys[j]] = slot;
+        add_card(m, b, (long long)c);
+    }
+}
+
 __global__ void __launch_bounds__(256) k_mut_insert(MutView m, uint32_t b, rg_pool P) {
     const uint32_t lane = lane_id();
     if (uniform((uint32_t)m.ctl[3])) return;
     const uint32_t n = uniform(m.counts[1]);
     const uint32_t nwaves = gridDim.x * 4;
-    for (uint32_t i = wave_index(); i < n; i += nwaves) {
-        const uint32_t j = uniform(m.absent[i]);
-        uint32_t slot = 0;
-        if (lane == 0) slot = m.free_list[atomicSub(&m.ctl[0], 1) - 1];  // the check kept this >= 0
-        slot = __builtin_amdgcn_readlane(slot, 0);
-        const uint8_t t = (uint8_t)uniform(P.types[j]);
-        const uint32_t sz = uniform(P.size[j]), c = uniform(P.card[j]);
-        const uint32_t units = (payload_bytes_of(t, sz) + 15) / 16;
-        const u32x4* s4 = reinterpret_cast<const u32x4*>(P.payload + uniform64(P.off[j]));
-        u32x4* d4 = reinterpret_cast<u32x4*>(m.slab + (uint64_t)slot * MUT_SLOT_BYTES);
-        for (uint32_t u = lane; u < units; u += 64) d4[u] = s4[u];
-        if (lane == 0) {
-            m.s_type[slot] = t;
-            m.s_size[slot] = sz;
-            m.s_card[slot] = c;
-            m.dir[(uint64_t)b * MUT_KEYS + P.keys[j]] = slot;
-            add_card(m, b, (long long)c);
-        }
-    }
+    for (uint32_t i = wave_index(); i < n; i += nwaves) mut_insert_one(m, b, P, uniform(m.absent[i]), lane);
 }
 
 void launch_mut_op(const MutView& m, int op, uint32_t b, const rg_pool& P, uint32_t src, hipStream_t st) {
@@ -251,6 +262,138 @@ void launch_mut_op(const MutView& m, int op, uint32_t b, const rg_pool& P, uint3
     if (op == RG_AND) hipLaunchKernelGGL(k_mut_and_drop, dim3(MUT_KEYS / 256), dim3(256), 0, st, m, b, P, src);
     hipLaunchKernelGGL(k_mut_eval, dim3(1024), dim3(256), 0, st, m, op, b, P);
     if (op == RG_OR || op == RG_XOR) hipLaunchKernelGGL(k_mut_insert, dim3(512), dim3(256), 0, st, m, b, P);
+}
+
+// ------------------------------------------------------------------ batches
+// Positions t < bbase[n] of a batch enumerate (operation i, key j of its B
+// operand): t - bbase[i] is j's position in P[src[i]]'s keys.
+__device__ __forceinline__ uint32_t batch_op_of(const MutBatch& bt, const uint64_t* bbase, uint64_t t) {
+    uint32_t lo = 0, hi = bt.n - 1;  // last i with bbase[i] <= t
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (bbase[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void k_mutb_prep(MutView m, MutBatch bt, rg_pool P) {
+    __shared__ uint64_t cnt[MUT_BATCH_MAX];
+    const uint32_t i = threadIdx.x;
+    if (i < bt.n) cnt[i] = P.bm_begin[bt.src[i] + 1] - P.bm_begin[bt.src[i]];
+    __syncthreads();
+    if (i == 0) {
+        uint64_t o = 0;
+        for (uint32_t q = 0; q < bt.n; ++q) {
+            m.bbase[q] = o;
+            o += cnt[q];
+        }
+        m.bbase[bt.n] = o;
+        m.ctl[2] = 0;
+        m.ctl[3] = 0;
+    }
+}
+
+// per (operation, key of B): whether A lacks the key (a bit in tbits, one
+// 64-bit word per wave and round), and the keys unions and symmetric
+// differences will insert (one atomic per wave)
+__global__ void __launch_bounds__(256) k_mutb_classify(MutView m, MutBatch bt, rg_pool P) {
+    const uint32_t lane = lane_id();
+    const uint64_t total = m.bbase[bt.n];
+    const uint64_t step = (uint64_t)gridDim.x * 4 * 64;
+    for (uint64_t t0 = (uint64_t)wave_index() * 64; t0 < total; t0 += step) {
+        const uint64_t t = t0 + lane;
+        bool absent = false, ins = false;
+        if (t < total) {
+            const uint32_t i = batch_op_of(bt, m.bbase, t);
+            const uint64_t j = P.bm_begin[bt.src[i]] + (t - m.bbase[i]);
+            absent = m.dir[(uint64_t)bt.b[i] * MUT_KEYS + P.keys[j]] == NONE;
+            ins = absent && (bt.op[i] == RG_OR || bt.op[i] == RG_XOR);
+        }
+        const uint64_t word = __ballot(absent);
+        const uint64_t ni = __popcll(__ballot(ins));
+        if (lane == 0) {
+            m.tbits[t0 >> 6] = word;
+            if (ni) atomicAdd(&m.ctl[2], (int32_t)ni);
+        }
+    }
+}
+
+// the batch's insertions must fit the free slots, else the batch is skipped
+__global__ void k_mutb_check(MutView m) {
+    if (m.ctl[2] > m.ctl[0]) {
+        m.ctl[3] = 1;
+        m.ctl[1] = 1;
+    }
+}
+
+// intersections: A's keys that B lacks become empty (blockIdx.y: the operation)
+__global__ void k_mutb_drop(MutView m, MutBatch bt, rg_pool P) {
+    __shared__ unsigned long long sum;
+    const uint32_t i = blockIdx.y;
+    if (bt.op[i] != RG_AND || uniform((uint32_t)m.ctl[3])) return;
+    if (threadIdx.x == 0) sum = 0;
+    __syncthreads();
+    const uint32_t b = bt.b[i], key = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t* dir = m.dir + (uint64_t)b * MUT_KEYS;
+    const uint32_t slot = dir[key];
+    if (slot != NONE) {
+        uint64_t lo = P.bm_begin[bt.src[i]], hi = P.bm_begin[bt.src[i] + 1];
+        const uint64_t e = hi;
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (P.keys[mid] < key) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo == e || P.keys[lo] != key) {
+            atomicAdd(&sum, (unsigned long long)m.s_card[slot]);
+            m.s_card[slot] = 0;
+            dir[key] = NONE;
+            mut_free(m, slot);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) add_card(m, b, -(long long)sum);
+}
+
+// keys A held before the batch: one workgroup each
+__global__ void __launch_bounds__(256) k_mutb_eval(MutView m, MutBatch bt, rg_pool P) {
+    __shared__ WgShared sh;
+    if (uniform((uint32_t)m.ctl[3])) return;
+    const uint64_t total = uniform64(m.bbase[bt.n]);
+    for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        if ((m.tbits[t >> 6] >> (t & 63)) & 1ull) continue;  // absent before the batch
+        const uint32_t i = uniform(batch_op_of(bt, m.bbase, t));
+        const uint32_t j = uniform((uint32_t)(P.bm_begin[bt.src[i]] + (t - m.bbase[i])));
+        const uint32_t slot = uniform(m.dir[(uint64_t)bt.b[i] * MUT_KEYS + P.keys[j]]);
+        mut_eval_one(m, bt.op[i], bt.b[i], P, j, slot, sh);
+    }
+}
+
+// keys A lacked before the batch (unions, symmetric differences): one wave each
+__global__ void __launch_bounds__(256) k_mutb_insert(MutView m, MutBatch bt, rg_pool P) {
+    const uint32_t lane = lane_id();
+    if (uniform((uint32_t)m.ctl[3])) return;
+    const uint64_t total = uniform64(m.bbase[bt.n]);
+    const uint64_t nwaves = (uint64_t)gridDim.x * 4;
+    for (uint64_t t = wave_index(); t < total; t += nwaves) {
+        if (!((m.tbits[t >> 6] >> (t & 63)) & 1ull)) continue;
+        const uint32_t i = uniform(batch_op_of(bt, m.bbase, t));
+        if (bt.op[i] != RG_OR && bt.op[i] != RG_XOR) continue;
+        mut_insert_one(m, bt.b[i], P, uniform((uint32_t)(P.bm_begin[bt.src[i]] + (t - m.bbase[i]))), lane);
+    }
+}
+
+void launch_mut_batch(const MutView& m, const MutBatch& bt, const rg_pool& P, hipStream_t st) {
+    if (!bt.n) return;
+    bool any_and = false;
+    for (uint32_t i = 0; i < bt.n; ++i) any_and |= bt.op[i] == RG_AND;
+    hipLaunchKernelGGL(k_mutb_prep, dim3(1), dim3(MUT_BATCH_MAX), 0, st, m, bt, P);
+    hipLaunchKernelGGL(k_mutb_classify, dim3(1024), dim3(256), 0, st, m, bt, P);
+    hipLaunchKernelGGL(k_mutb_check, dim3(1), dim3(1), 0, st, m);
+    if (any_and) hipLaunchKernelGGL(k_mutb_drop, dim3(MUT_KEYS / 256, bt.n), dim3(256), 0, st, m, bt, P);
+    hipLaunchKernelGGL(k_mutb_eval, dim3(2048), dim3(256), 0, st, m, bt, P);
+    hipLaunchKernelGGL(k_mutb_insert, dim3(1024), dim3(256), 0, st, m, bt, P);
 }
 
 // ------------------------------------------------------------------ clear

@@ -1,5 +1,8 @@
 // rg_mutable_api.cpp - C ABI of mutable pools: in-place A op= B with the
 // bitmaps' cardinalities maintained, over a device slot allocator.
+#include <algorithm>
+#include <vector>
+
 #include "rg_host.h"
 #include "rg_mutable.h"
 
@@ -40,7 +43,8 @@ rg_status rg_mpool_create(rg_ctx* c, uint32_t n_bitmaps, uint32_t n_slots, rg_mp
     size_t total = 0;
     for (size_t x : {4 * nd, (size_t)n_slots, 4 * (size_t)n_slots, 4 * (size_t)n_slots, 8 * (size_t)n_slots,
                      4 * (size_t)n_slots, (size_t)16, 8 * (size_t)n_bitmaps, 8 * (size_t)MUT_KEYS,
-                     4 * (size_t)MUT_KEYS, (size_t)8})
+                     4 * (size_t)MUT_KEYS, (size_t)8, 8 * (size_t)(MUT_BATCH_MAX + 1),
+                     8 * (size_t)MUT_BATCH_MAX * MUT_KEYS / 64})
         total += align256(x);
     if (hipMalloc(&mp->mem, total) != hipSuccess) {
         delete mp;
@@ -63,6 +67,8 @@ rg_status rg_mpool_create(rg_ctx* c, uint32_t n_bitmaps, uint32_t n_slots, rg_mp
     v.present = bp.take<uint32_t>(2 * (size_t)MUT_KEYS);
     v.absent = bp.take<uint32_t>(MUT_KEYS);
     v.counts = bp.take<uint32_t>(2);
+    v.bbase = bp.take<uint64_t>(MUT_BATCH_MAX + 1);
+    v.tbits = bp.take<uint64_t>((size_t)MUT_BATCH_MAX * MUT_KEYS / 64);
     v.slab = static_cast<uint8_t*>(mp->slab);
     launch_mut_init(v, nullptr);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess) {
@@ -92,6 +98,34 @@ rg_status rg_mpool_op(rg_mpool* mp, int op, uint32_t b, const rg_pool* P, uint32
     if (rg_status s = check_args(mp, b, P, src)) return s;
     HIPCHK(c, hipSetDevice(c->device));
     launch_mut_op(mp->v, op, b, *P, src, (hipStream_t)stream);
+    HIPCHK(c, hipGetLastError());
+    return RG_OK;
+}
+
+rg_status rg_mpool_op_batch(rg_mpool* mp, uint32_t n, const int* ops, const uint32_t* bitmaps, const rg_pool* P,
+                            const uint32_t* srcs, void* stream) {
+    if (!mp) return RG_EINVAL;
+    rg_ctx* c = mp->ctx;
+    if (n == 0) return RG_OK;
+    if (!ops || !bitmaps || !srcs) return fail(c, RG_EINVAL, "rg_mpool_op_batch: null operation arrays");
+    if (!P) return fail(c, RG_EINVAL, "null pool");
+    std::vector<uint8_t> seen(mp->v.n_bitmaps, 0);
+    for (uint32_t i = 0; i < n; ++i) {
+        if (ops[i] < RG_AND || ops[i] > RG_ANDNOT) return fail(c, RG_EINVAL, "op must be RG_AND..RG_ANDNOT");
+        if (rg_status s = check_args(mp, bitmaps[i], P, srcs[i])) return s;
+        if (seen[bitmaps[i]]++) return fail(c, RG_EINVAL, "rg_mpool_op_batch: a bitmap appears twice");
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    for (uint32_t i0 = 0; i0 < n; i0 += MUT_BATCH_MAX) {
+        MutBatch bt{};
+        bt.n = std::min<uint32_t>(MUT_BATCH_MAX, n - i0);
+        for (uint32_t i = 0; i < bt.n; ++i) {
+            bt.op[i] = ops[i0 + i];
+            bt.b[i] = bitmaps[i0 + i];
+            bt.src[i] = srcs[i0 + i];
+        }
+        launch_mut_batch(mp->v, bt, *P, (hipStream_t)stream);
+    }
     HIPCHK(c, hipGetLastError());
     return RG_OK;
 }

@@ -145,7 +145,7 @@ def test_server_results_alone_and_in_mix(rg, ctx):
     exp = _expect(bs, qs)
     # alone: one query per step, one step in flight
     alone = rg.Server(ctx, P, arena_bytes=256 << 20, max_batch=1, max_inflight=1)
-    lat, cards, dig = alone.replay(qs, np.zeros(len(qs), np.uint64))
+    lat, cards, dig = alone.replay(qs, np.zeros(len(qs), np.uint64), digest=True)
     st = alone.stop()
     _say(f"[serve alone] {st}")
     assert st["steps"] == len(qs)
@@ -153,17 +153,40 @@ def test_server_results_alone_and_in_mix(rg, ctx):
         assert cards[i] == c and dig[i] == d, ("alone", i)
     # in the mix: all arrive at once, batched, two steps in flight
     mix = rg.Server(ctx, P, arena_bytes=256 << 20, max_batch=16, max_inflight=2)
-    lat2, cards2, dig2 = mix.replay(qs, np.zeros(len(qs), np.uint64))
+    lat2, cards2, dig2 = mix.replay(qs, np.zeros(len(qs), np.uint64), digest=True)
     st2 = mix.stop()
     _say(f"[serve mix] {st2}")
     assert st2["mean_batch"] > 1.0
     assert np.array_equal(cards2, cards) and np.array_equal(dig2, dig)
     # spread arrivals (continuous batching while steps run)
     mix = rg.Server(ctx, P, arena_bytes=256 << 20, max_batch=8, max_inflight=2)
-    lat3, cards3, dig3 = mix.replay(qs, np.arange(len(qs), dtype=np.uint64) * 20000)
+    lat3, cards3, dig3 = mix.replay(qs, np.arange(len(qs), dtype=np.uint64) * 20000, digest=True)
     st3 = mix.stop()
     _say(f"[serve spread] {st3} p50={np.percentile(lat3, 50) / 1e3:.1f}us p99={np.percentile(lat3, 99) / 1e3:.1f}us")
     assert np.array_equal(cards3, cards) and np.array_equal(dig3, dig)
+
+
+def test_server_digest_only_when_asked(rg, ctx):
+    """Fingerprints are computed for the queries that ask for them (and
+    only the steps holding such a query run the fingerprint kernel); the
+    others read 0, with the same cardinalities."""
+    bs = overlapping_sets(n=12, seed=5)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    qs = [(op, ids, True) for op, ids in _queries(len(bs), 24, seed=29, kmax=6)]
+    exp = _expect(bs, qs)
+    srv = rg.Server(ctx, P, arena_bytes=64 << 20, max_batch=8, max_inflight=2)
+    try:
+        _, cards, dig = srv.replay(qs, np.zeros(len(qs), np.uint64))
+        assert [int(c) for c in cards] == [e[0] for e in exp]
+        assert not dig.any()
+        tickets = [srv.submit(op, ids, materialize=m, digest=i % 2 == 0) for i, (op, ids, m) in enumerate(qs)]
+        for i, t in enumerate(tickets):
+            r = srv.poll(t)
+            assert r.done and r.status == 0 and r.card == exp[i][0], i
+            assert r.digest == (exp[i][1] if i % 2 == 0 else 0), i
+            srv.release(t)
+    finally:
+        srv.stop()
 
 
 def test_server_views_and_small_arena(rg, ctx):
@@ -177,7 +200,7 @@ def test_server_views_and_small_arena(rg, ctx):
     exp = _expect(bs, qs)
     srv = rg.Server(ctx, P, arena_bytes=8 << 20, max_batch=4, max_inflight=2)
     try:
-        tickets = [srv.submit(op, ids, materialize=m) for op, ids, m in qs]
+        tickets = [srv.submit(op, ids, materialize=m, digest=True) for op, ids, m in qs]
         for i, t in enumerate(tickets):
             r = srv.poll(t, wait=True)
             assert r.done and r.status == 0 and r.card == exp[i][0] and r.digest == exp[i][1], i
@@ -216,7 +239,7 @@ def test_server_all_ops_while_context_busy(rg, ctx):
     tib = torch.from_numpy(ib.view(np.int32)).cuda()
     srv = rg.Server(ctx, P, arena_bytes=64 << 20, max_batch=8, max_inflight=2)
     try:
-        tickets = [srv.submit(op, ids, materialize=m) for op, ids, m in qs]
+        tickets = [srv.submit(op, ids, materialize=m, digest=True) for op, ids, m in qs]
         for rep in range(3):
             for op in ("and", "or", "xor", "andnot"):
                 _, c, _ = rg.batch(ctx, op, P, P, tia, tib, materialize=False, card=True)

@@ -1,7 +1,9 @@
 """In-place operations on mutable bitmaps (rg_mpool_*): sequences of A op= B
 against the oracle's fold of the same operations, the maintained
 cardinalities, the slot accounting of the device allocator, the capacity
-check that leaves a bitmap untouched, and a wide union built in place."""
+check that leaves a bitmap untouched, a wide union built in place, and
+batches of operations on distinct bitmaps (rg_mpool_op_batch) against the
+same fold."""
 import sys
 
 import numpy as np
@@ -131,4 +133,59 @@ def test_wide_union_in_place(rg, ctx):
     for i in range(0, 40, 3):
         exp = oracle.op("andnot", exp, bs[i])
     _check(rg, ctx, M, [exp], "wide union minus")
+    M.close()
+
+
+def test_batches_match_oracle(rg, ctx):
+    """Batches mixing all four operations (including symmetric differences
+    that empty keys and intersections that drop them), batches of more than
+    64 operations, and a bitmap's own value as operand, against the oracle."""
+    sets, bs = _sources()
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    rng = np.random.default_rng(84)
+    nb = 80
+    M = rg.MutablePool(ctx, nb, 100000)  # the fold peaks near 80 000 containers with a batch's insertions
+    expected = []
+    for b in range(nb):
+        s = int(rng.integers(len(sets)))
+        M.assign(b, P, s)
+        expected.append(sets[s])
+    for rnd in range(6):
+        n = int(rng.integers(1, nb + 1))
+        bms = rng.permutation(nb)[:n]
+        ops = [OPS[int(rng.integers(4))] for _ in range(n)]
+        srcs = [int(rng.integers(len(sets))) for _ in range(n)]
+        M.op_batch(ops, bms, P, srcs)
+        for op, b, s in zip(ops, bms, srcs):
+            expected[b] = oracle.op(op, expected[b], sets[s])
+        _say(f"[mutable batch] round {rnd}: {n} operations")
+        _check(rg, ctx, M, expected, f"batch {rnd}")
+    # every bitmap with a copy of itself: xor empties every key, then or restores
+    out = M.export()
+    R = out.as_pool()
+    M.op_batch(["xor"] * nb, np.arange(nb), R, np.arange(nb))
+    _check(rg, ctx, M, [np.zeros(0, np.uint32)] * nb, "xor self")
+    M.op_batch(["or"] * nb, np.arange(nb), R, np.arange(nb))
+    _check(rg, ctx, M, expected, "or back")
+    M.close()
+
+
+def test_batch_capacity_and_errors(rg, ctx):
+    """A batch whose insertions exceed the free slots is skipped as a whole;
+    a bitmap named twice in one call is refused."""
+    a = np.arange(0, 5 * 65536, 7, dtype=np.uint32)        # keys 0..4
+    b = np.arange(3 * 65536, 30 * 65536, 11, dtype=np.uint32)  # keys 3..29
+    bs = synth.BitmapSet.from_list([a, b])
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    M = rg.MutablePool(ctx, 2, 20)
+    M.assign(0, P, 0)
+    M.assign(1, P, 0)  # 10 slots in use, 10 free
+    M.op_batch(["or", "and"], [0, 1], P, [1, 1])  # the union needs 25 new slots
+    st, free = M.status()
+    assert st == rg.RG_ECAPACITY and free == 10
+    _check(rg, ctx, M, [a, a], "batch skipped")
+    M.op_batch(["and", "andnot"], [0, 1], P, [1, 1])
+    _check(rg, ctx, M, [oracle.op("and", a, b), oracle.op("andnot", a, b)], "and, andnot")
+    with pytest.raises(rg.RoaringError):
+        M.op_batch(["or", "or"], [0, 0], P, [0, 1])
     M.close()
