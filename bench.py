@@ -586,9 +586,7 @@ def bench_batched(args):
     ctx = rg.Context(0)
     seed = synth.SEED_BASE + 3
     t0 = time.time()
-    hot = synth.hot_keys(seed, 256, 1 << 16)
-    cards = [synth.lognormal_card(i, 1e4, 2.0, 10, 10 ** 7, seed) for i in range(args.pool)]
-    bs = build_sets_threaded(lambda i: synth.mixed_bitmap(seed, i, cards[i], 32, hot), args.pool)
+    bs = build_sets_threaded(batched_pool_gen(args.pool), args.pool)
     h = rg.Pool.host_arrays(bs.values, bs.offsets)[3]
     P = rg.Pool.from_host_arrays(h)
     ia, ib = synth.random_pairs(args.pool, args.batched_pairs, seed)
@@ -743,6 +741,30 @@ def bench_batched(args):
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def batched_pool_gen(n_pool):
+    """The batched workload's bitmap i (i < n_pool): mixed recipe over [0, 2^32)
+    with a 256-key hot set, cardinality lognormal (median 1e4, sigma 2, clipped
+    to [10, 1e7])."""
+    import synth
+
+    seed = synth.SEED_BASE + 3
+    hot = synth.hot_keys(seed, 256, 1 << 16)
+    cards = [synth.lognormal_card(i, 1e4, 2.0, 10, 10 ** 7, seed) for i in range(n_pool)]
+    return lambda i: synth.mixed_bitmap(seed, i, cards[i], 32, hot)
+
+
+def serve_index_gen(n_index):
+    """The serving index's bitmap i (i < n_index): mixed recipe over [0, 2^26)
+    with a 32-key hot set, cardinality lognormal (median 5e4, sigma 1, clipped
+    to [1e3, 1e6])."""
+    import synth
+
+    seed = synth.SEED_BASE + 4
+    hot = synth.hot_keys(seed, 32, 1 << 10)
+    cards = [synth.lognormal_card(i, 5e4, 1.0, 1000, 10 ** 6, seed) for i in range(n_index)]
+    return lambda i: synth.mixed_bitmap(seed, i, cards[i], 26, hot)
 
 
 def build_sets_threaded(gen, n):
@@ -907,12 +929,7 @@ def bench_serve(args):
     ctx = rg.Context(0)
     seed = synth.SEED_BASE + 4
     t0 = time.time()
-    hot = synth.hot_keys(seed, 32, 1 << 10)
-    cards = [synth.lognormal_card(i, 5e4, 1.0, 1000, 10 ** 6, seed) for i in range(args.index)]
-
-    def gen(i):
-        return synth.mixed_bitmap(seed, i, cards[i], 26, hot)
-
+    gen = serve_index_gen(args.index)
     h = build_pool_threaded(gen, args.index)
     P = rg.Pool.from_host_arrays(h)
     torch.cuda.synchronize()
