@@ -96,8 +96,8 @@ size_t mat_pair_bytes(uint64_t n_pairs) {
 size_t wave_bytes(uint64_t S, uint64_t P, bool kw) {
     const uint64_t nb = (uint64_t)NBINS * match_blocks(S);
     size_t b = 0;
-    for (size_t x : {sizeof(Task) * S, 4 * S, 8 * S, 4 * S, 1 * S, 4 * S, 8 * S, 4 * S, 4 * S})
-        b += align256(x);  // tasks, ub, slot_off, res_card, res_type, res_size, out_idx, lists, redo
+    for (size_t x : {sizeof(Task) * S, 4 * S, 8 * S, 4 * S, 1 * S, 4 * S, 8 * S, 4 * S})
+        b += align256(x);  // tasks, ub, slot_off, res_card, res_type, res_size, out_idx, lists
     b += align256(8 * (P + 1)) + align256(8 * scan_partials_needed(S)) + align256(4 * nb) + align256(8 * nb) +
          align256(8 * scan_partials_needed(nb));
     if (kw) b += align256(sizeof(KwQuery) * P) + align256(8 * P);
@@ -285,7 +285,6 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
     uint32_t* min_cont = bp.take<uint32_t>(n_pairs);
     long long* acc = bp.take<long long>(n_pairs);
     uint32_t* d_err = reinterpret_cast<uint32_t*>(c->small);
-    uint32_t* redo_count = d_err + 48;
     uint32_t* bin_info = d_err + 128;                              // [2 NBINS] counts, offsets
     uint64_t* bin_total = reinterpret_cast<uint64_t*>(d_err + 160);
     uint64_t* totals = reinterpret_cast<uint64_t*>(d_err + 64);  // [0] payload end, [1] container end
@@ -375,7 +374,6 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
     uint32_t* res_size = wb.take<uint32_t>(S_max);
     uint64_t* out_idx = wb.take<uint64_t>(S_max);
     uint32_t* bin_lists = wb.take<uint32_t>(S_max);
-    uint32_t* redo_list = wb.take<uint32_t>(S_max);
     uint64_t* cand_off = wb.take<uint64_t>(P_max + 1);
     uint64_t* partials = wb.take<uint64_t>(scan_partials_needed(S_max));
     uint32_t* blk_cnt = wb.take<uint32_t>((size_t)NBINS * match_blocks(S_max));
@@ -415,7 +413,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
             ka.n_slots = C;
             ka.ub = ub;
             ka.res_card = res_card;
-            ka.so = SlotOut{slot_off, out->payload, res_card, res_type, res_size, nullptr, nullptr};
+            ka.so = SlotOut{slot_off, out->payload, res_card, res_type, res_size};
             ka.so.cap = out->cap_payload_bytes;
             ka.so.err = d_err;
             ka.acc = nullptr;
@@ -471,7 +469,6 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
             // fails here, before any kernel writes past the arena
             if (mat && pay_end > out->cap_payload_bytes)
                 return fail(c, RG_ECAPACITY, "result payload exceeds the arena (pool bm_wbytes inconsistent with card)");
-            launch_fill_u32(redo_count, 0, 1, st);
 
             ComputeArgs ca;
             ca.cost = nullptr;
@@ -489,10 +486,10 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
             ca.A = pa;
             ca.B = pb;
             ca.tasks = tasks;
-            ca.n_dev = nullptr;
             ca.acc = acc;
             ca.pair0 = p0;
-            ca.so = SlotOut{slot_off, mat ? out->payload : nullptr, res_card, res_type, res_size, redo_list, redo_count};
+            ca.so = SlotOut{slot_off, mat ? out->payload : nullptr, res_card, res_type, res_size};
+            ca.so.cap = out ? out->cap_payload_bytes : ~0ull;
             for (int b = 0; b < NBINS; ++b) {
                 if (!cnt[b]) continue;
                 if (b == BIN_FUSED) {  // already counted by key matching
@@ -512,14 +509,6 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
                     default: launch_generic(ca, st); break;
                     }
                 });
-            }
-            if (mat && cnt[BIN_BB]) {
-                // bitset pairs whose result is an array or run container
-                ComputeArgs rd = ca;
-                rd.list = redo_list;
-                rd.n = std::min<uint32_t>(cnt[BIN_BB], 4096u);
-                rd.n_dev = redo_count;
-                timed(c, PROF_REDO, mat, 0, st, [&] { launch_generic(rd, st); });
             }
         }
         HIPCHK(c, hipGetLastError());
@@ -1050,7 +1039,7 @@ void plan_enqueue_mat(rg_plan* p, hipStream_t st) {
         ka.n_slots = wv.C;
         ka.ub = p->ub;
         ka.res_card = p->res_card;
-        ka.so = SlotOut{p->slot_off, o.payload, p->res_card, p->res_type, p->res_size, nullptr, nullptr};
+        ka.so = SlotOut{p->slot_off, o.payload, p->res_card, p->res_type, p->res_size};
         ka.so.cap = o.cap_payload_bytes;
         ka.so.err = p->err;
         ka.acc = nullptr;

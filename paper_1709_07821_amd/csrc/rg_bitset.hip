@@ -6,9 +6,11 @@
 // registers and counts them with the native per-lane popcount; the 64 lane
 // counts are summed across the wave. The count-only form stops there (16 KiB
 // read, 8 bytes of atomic add). The materialising form also counts the runs
-// of the result, decides the P1 type, and writes the 8 KiB bitset straight
-// from registers when the result is a bitset; the rare array/run results are
-// handed to the LDS kernel (redo list), which recomputes them.
+// of the result, decides the P1 type, and writes the result from registers:
+// the 8 KiB bitset as it is; an array by extracting the set bits (Section
+// 3.1: each lane's values go after the values of the words before its own,
+// a prefix sum over the lanes per step); runs from the run-start and run-end
+// masks, staged in LDS so that each run's start and end meet.
 //
 // Word order in registers: lane l, step k holds words 128k + 2l and
 // 128k + 2l + 1 (lo, hi), so the word preceding (k, l, lo) is (k, l-1, hi),
@@ -92,9 +94,97 @@ __device__ __forceinline__ void bb_store(const BbWords& w, uint8_t* dst8, uint32
     }
 }
 
+// exclusive prefix sum over the lanes, and the total
+__device__ __forceinline__ uint32_t bb_excl_sum(uint32_t v, uint32_t& total) {
+    const uint32_t incl = wave_incl_scan_u32(v);
+    total = uniform(__shfl(incl, 63));
+    return incl - v;
+}
+
+// writes the set bits of the word pair (x0, x1) = words wi, wi + 1 as 16-bit
+// values from position pos on
+__device__ __forceinline__ void bb_extract(uint64_t x0, uint64_t x1, uint32_t wi, uint16_t* d16, uint32_t pos) {
+    while (x0) {
+        d16[pos++] = (uint16_t)(wi * 64 + __builtin_ctzll(x0));
+        x0 &= x0 - 1;
+    }
+    while (x1) {
+        d16[pos++] = (uint16_t)((wi + 1) * 64 + __builtin_ctzll(x1));
+        x1 &= x1 - 1;
+    }
+}
+
+// Writes the result words as an array container (type RG_ARRAY, c <= 4096
+// values) or run container (RG_RUN, r <= 2048 runs) at dst. lds: this wave's
+// 2 x 2048 16-bit entries (run starts, run ends).
+__device__ void bb_store_sparse(const BbWords& w, uint8_t type, uint8_t* dst, uint16_t* lds, uint32_t lane) {
+    uint16_t* d16 = reinterpret_cast<uint16_t*>(dst);
+    if (type == RG_ARRAY) {
+        uint32_t base = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            uint32_t tot;
+            const uint32_t pre = bb_excl_sum(__popcll(w.lo[k]) + __popcll(w.hi[k]), tot);
+            bb_extract(w.lo[k], w.hi[k], 128 * k + 2 * lane, d16, base + pre);
+            base += tot;
+        }
+        return;
+    }
+    // run starts: bit set, the bit below clear; run ends: bit set, the bit above clear
+    uint16_t* ls = lds;
+    uint16_t* le = lds + 2048;
+    uint32_t bs = 0, be = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        uint64_t prev = __shfl_up(w.hi[k], 1);
+        const uint64_t wrap = k > 0 ? __shfl(w.hi[k > 0 ? k - 1 : 0], 63) : 0ull;
+        if (lane == 0) prev = wrap;
+        uint64_t next = __shfl_down(w.lo[k], 1);
+        const uint64_t wrap_n = k < 7 ? __shfl(w.lo[k < 7 ? k + 1 : 7], 0) : 0ull;
+        if (lane == 63) next = wrap_n;
+        const uint64_t st_lo = w.lo[k] & ~((w.lo[k] << 1) | (prev >> 63));
+        const uint64_t st_hi = w.hi[k] & ~((w.hi[k] << 1) | (w.lo[k] >> 63));
+        const uint64_t en_lo = w.lo[k] & ~((w.lo[k] >> 1) | (w.hi[k] << 63));
+        const uint64_t en_hi = w.hi[k] & ~((w.hi[k] >> 1) | (next << 63));
+        uint32_t ts, te;
+        const uint32_t ps = bb_excl_sum(__popcll(st_lo) + __popcll(st_hi), ts);
+        const uint32_t pe = bb_excl_sum(__popcll(en_lo) + __popcll(en_hi), te);
+        bb_extract(st_lo, st_hi, 128 * k + 2 * lane, ls, bs + ps);
+        bb_extract(en_lo, en_hi, 128 * k + 2 * lane, le, be + pe);
+        bs += ts;
+        be += te;
+    }
+    __builtin_amdgcn_wave_barrier();
+    uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
+    for (uint32_t i = lane; i < bs; i += 64) d32[i] = (uint32_t)ls[i] | ((uint32_t)(le[i] - ls[i]) << 16);
+    __builtin_amdgcn_wave_barrier();  // the LDS is read before the wave's next result
+}
+
+// Writes a non-empty result of the words in P1 form into slot `slot` (bitset
+// from registers, array or runs through bb_store_sparse) and records it;
+// false (nothing written, *err bit 2) when it would end past the arena.
+__device__ bool bb_store_result(const BbWords& w, uint32_t slot, const SlotOut& so, uint16_t* lds, uint32_t lane) {
+    const uint8_t type = p1_type(w.c, w.r);
+    const uint64_t nbytes = type == RG_ARRAY ? 2ull * w.c : type == RG_BITSET ? 8192ull : 4ull * w.r;
+    const uint64_t soff = so.slot_off[slot];
+    if (soff + nbytes > so.cap) {
+        if (lane == 0 && so.err) atomicOr(so.err, 2u);
+        return false;
+    }
+    if (type == RG_BITSET) bb_store(w, so.payload + soff, lane);
+    else bb_store_sparse(w, type, so.payload + soff, lds, lane);
+    if (lane == 0) {
+        so.res_card[slot] = w.c;
+        so.res_type[slot] = type;
+        so.res_size[slot] = type == RG_ARRAY ? w.c : type == RG_BITSET ? 1024u : w.r;
+    }
+    return true;
+}
+
 // Materialising form (intersection): words in registers, run count, P1 type,
-// bitset results written from registers, other results to the redo list.
+// the result written from registers.
 __global__ void __launch_bounds__(256) k_bb_mat(ComputeArgs a) {
+    __shared__ uint16_t lds[4][4096];
     const uint32_t lane = lane_id();
     const uint32_t wv = wave_index();
     if (wv >= a.n) return;
@@ -104,28 +194,18 @@ __global__ void __launch_bounds__(256) k_bb_mat(ComputeArgs a) {
     bb_words(a.op, reinterpret_cast<const u32x4*>(a.A.payload + a.A.off[t.ia]),
              reinterpret_cast<const u32x4*>(a.B.payload + a.B.off[t.ib]), lane, w);
     if (w.c == 0) return;  // empty result: slot stays empty
-    if (p1_type(w.c, w.r) == RG_BITSET) {
-        bb_store(w, a.so.payload + a.so.slot_off[slot], lane);
-        if (lane == 0) {
-            a.so.res_card[slot] = w.c;
-            a.so.res_type[slot] = RG_BITSET;
-            a.so.res_size[slot] = 1024;
-        }
-    } else if (lane == 0) {
-        uint32_t pos = atomicAdd(a.so.redo_count, 1u);
-        a.so.redo_list[pos] = slot;
-    }
+    bb_store_result(w, slot, a.so, lds[threadIdx.x >> 6], lane);
 }
 
 // k-way slots marked KW_TASK_BB (queries of one or two bitmaps whose
 // containers at the key are bitsets, or a bitset and nothing), BB_CHUNK slots
 // per wave: lane i loads slot i's task, op and payload offsets in parallel,
 // then the wave builds the slots' results one after another as k_bb_mat
-// does. A bitset result (or an empty one) is final: the task is marked
-// KW_TASK_DONE. Other results stay for the workgroup kernel.
+// does, in any P1 form, and marks each task KW_TASK_DONE.
 constexpr uint32_t BB_CHUNK = 8;
 
 __global__ void __launch_bounds__(256) k_kw_bb(KwArgs a) {
+    __shared__ uint16_t lds[4][4096];
     const uint32_t lane = lane_id();
     const uint64_t step = (uint64_t)gridDim.x * 4 * BB_CHUNK;
     for (uint64_t c0 = (uint64_t)wave_index() * BB_CHUNK; c0 < a.n_slots; c0 += step) {
@@ -152,23 +232,8 @@ __global__ void __launch_bounds__(256) k_kw_bb(KwArgs a) {
             const u32x4* pb = (hl & 2u) ? reinterpret_cast<const u32x4*>(a.P1.payload + readlane64(ob, l)) : nullptr;
             BbWords w;
             bb_words((int)__builtin_amdgcn_readlane(op, l), pa, pb, lane, w);
-            bool done = true;
-            if (w.c && p1_type(w.c, w.r) == RG_BITSET) {
-                const uint64_t soff = a.so.slot_off[slot];
-                if (soff + 8192 > a.so.cap) {
-                    if (lane == 0 && a.so.err) atomicOr(a.so.err, 2u);
-                } else {
-                    bb_store(w, a.so.payload + soff, lane);
-                    if (lane == 0) {
-                        a.so.res_card[slot] = w.c;
-                        a.so.res_type[slot] = RG_BITSET;
-                        a.so.res_size[slot] = 1024;
-                    }
-                }
-            } else if (w.c) {
-                done = false;  // an array or runs: the workgroup kernel's
-            }
-            if (done && lane == 0) a.tasks[slot].bin = KW_TASK_DONE;
+            if (w.c) bb_store_result(w, slot, a.so, lds[threadIdx.x >> 6], lane);
+            if (lane == 0) a.tasks[slot].bin = KW_TASK_DONE;
         }
     }
 }

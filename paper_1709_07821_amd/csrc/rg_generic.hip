@@ -5,8 +5,7 @@
 // containers, for which the paper gives no algorithm (Section 5.10, Section 6),
 // go through the ballot/prefix-XOR expansion of expand_container().
 //
-// One 256-thread workgroup per container pair, grid-stride over the list so
-// that a device-side count (the bitset redo list) can drive it.
+// One 256-thread workgroup per container pair, grid-stride over the list.
 #include "rg_count_dev.h"
 
 namespace rg {
@@ -14,7 +13,7 @@ namespace rg {
 template <int OP, bool MAT>
 __global__ void __launch_bounds__(256) k_generic(ComputeArgs a) {
     __shared__ WgShared sh;
-    const uint32_t n = a.n_dev ? uniform(*a.n_dev) : a.n;
+    const uint32_t n = a.n;
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
         const uint32_t slot = uniform(a.list[i]);
         const Task t = uniform_task(a.tasks, slot);
@@ -37,7 +36,6 @@ __global__ void __launch_bounds__(256) k_generic(ComputeArgs a) {
 
 void launch_generic(const ComputeArgs& a, hipStream_t st) {
     uint32_t grid = a.n;
-    if (a.n_dev) grid = a.n;  // caller passes the maximum possible count as n
     if (!grid) return;
     if (grid > 65536u) grid = 65536u;
     // count-only calls accumulate the intersection for every operation; the

@@ -29,7 +29,7 @@ enum : uint8_t {
     BIN_AB = 5,     // array op bitset (either order): probe / set / clear / flip
     BIN_RR = 6,     // run op run / run op array: interval merge
     BIN_THREAD = 7, // small array side: one thread per pair probes the other container
-    PROF_REDO = 8,  // no bin: profile class of the bitset pairs redone by the generic kernel
+    PROF_REDO = 8,  // no bin: unused (a class number kept for the C ABI's variant numbering)
     BIN_FUSED = 9,  // small array sides counted inside key matching (count-only); never listed
     NBINS = 10
 };
@@ -92,8 +92,6 @@ struct SlotOut {
     uint32_t* res_card;         // 0 = empty / no container
     uint8_t* res_type;
     uint32_t* res_size;
-    uint32_t* redo_list;        // bitset pairs whose result is not a bitset
-    uint32_t* redo_count;
     // bytes of `payload`: a result that would end past it is not written (the
     // slot stays empty) and bit 2 is set in *err - only a pool whose
     // cardinalities disagree with its payload can get there
@@ -295,7 +293,6 @@ struct ComputeArgs {
     const Task* tasks;
     const uint32_t* list;     // slot ids of this bin
     uint32_t n;
-    const uint32_t* n_dev;    // if non-null, the count is read on the device (redo list)
     long long* acc;           // count mode: per-pair (wave-local) accumulators
     uint64_t pair0;
     SlotOut so;
@@ -420,8 +417,7 @@ constexpr uint8_t KW_TASK_INDEXED = 1;
 // ... and whose result the one-wave array kernel builds (set by the bounds kernel)
 constexpr uint8_t KW_TASK_SMALL = 2;
 // ... whose containers are bitsets (or one bitset, the other absent): the
-// one-wave bitset kernel builds the result when it is a bitset and then marks
-// the task KW_TASK_DONE; other results stay for the workgroup kernel
+// one-wave bitset kernel builds the result and marks the task KW_TASK_DONE
 constexpr uint8_t KW_TASK_BB = 3;
 constexpr uint8_t KW_TASK_DONE = 4;
 __host__ __device__ __forceinline__ bool bb_mat_ok(int op, uint8_t ta, uint8_t tb) {

@@ -179,7 +179,7 @@ __device__ void mut_eval_one(const MutView& m, int op, uint32_t b, const rg_pool
     const uint32_t tid = threadIdx.x;
     const PoolView A = mut_view(m);
     const PoolView B = view_of(P);
-    const SlotOut so{m.s_off, m.slab, m.s_card, m.s_type, m.s_size, nullptr, nullptr};
+    const SlotOut so{m.s_off, m.slab, m.s_card, m.s_type, m.s_size};
     const uint32_t old_c = uniform(m.s_card[slot]);
     const uint16_t key = (uint16_t)uniform(P.keys[j]);
     expand_container(sh.sa, A, slot, sh);  // ends with a barrier

@@ -199,7 +199,7 @@ rg_status step_enqueue(std::string* err_out, const rg_pool& pool, const StepLayo
     a.n_slots = L.S;
     a.ub = ub;
     a.res_card = res_card;
-    a.so = SlotOut{slot_off, o.payload, res_card, res_type, res_size, nullptr, nullptr};
+    a.so = SlotOut{slot_off, o.payload, res_card, res_type, res_size};
     a.acc = acc;
     a.err = err;
     launch_kw_keys(a, st);
