@@ -396,10 +396,17 @@ void launch_mlp_table(const float* P, uint8_t* table, hipStream_t st);
 // array of at most SMALL_MAX values. Difference: an array first operand; the
 // second any container or absent, an array of at most SMALL_MAX values. Every
 // such result has at most SMALL_MAX values: an array or runs, never a bitset.
+// Also a lone run container (the other operand absent: union, symmetric
+// difference, difference by nothing), whose result is the container itself
+// in P1 form (touching runs merged; an array or a bitset when smaller).
 constexpr uint32_t SMALL_MAX = 4096;
 constexpr uint32_t SMALL_LDS = SMALL_MAX + 8;  // values staged per wave (the second array starts 16-byte aligned)
+__host__ __device__ __forceinline__ bool lone_run(int op, uint8_t ta, uint8_t tb) {
+    return (ta == RG_RUN && tb == 0 && op != RG_AND) || (ta == 0 && tb == RG_RUN && (op == RG_OR || op == RG_XOR));
+}
 __host__ __device__ __forceinline__ bool small_mat_ok(int op, uint8_t ta, uint8_t tb, uint32_t sa, uint32_t sb) {
     const bool aa = ta == RG_ARRAY, ba = tb == RG_ARRAY;
+    if (lone_run(op, ta, tb)) return true;
     if (op == RG_OR || op == RG_XOR)
         return (aa || ta == 0) && (ba || tb == 0) && (ta || tb) && (uint64_t)sa + sb <= SMALL_MAX;
     if (op == RG_AND) {

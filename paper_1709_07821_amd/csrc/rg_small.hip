@@ -211,11 +211,114 @@ __device__ void merge_pair(bool xor_op, const uint16_t* A, uint32_t ca, const ui
     }
 }
 
+// A lone run container R (the other operand absent) in P1 form (Section 1):
+// a first pass sums the values c and counts the merged runs (a run that
+// starts one past its predecessor's end continues it); then the P1 form is
+// written: merged runs (their starts and ends staged in LDS, paired by merged
+// run number), an array (each lane expands its runs at the prefix of the
+// lengths before them), or a bitset (the runs' bits set in an LDS bitset,
+// then copied out). lds: this wave's SMALL_LDS 16-bit entries (8 KiB + 16 B).
+__device__ void lone_runs(const SmallSide& R, uint32_t slot, const SlotOut& so, uint16_t* lds) {
+    const uint32_t lane = lane_id();
+    const uint32_t* rp = reinterpret_cast<const uint32_t*>(R.pl);
+    const uint32_t r = R.size;
+    uint32_t c = 0, rm = 0;
+    for (uint32_t base = 0; base < r; base += 64) {
+        const uint32_t i = base + lane;
+        uint32_t len = 0;
+        bool head = false;
+        if (i < r) {
+            const uint32_t pr = rp[i];
+            len = (pr >> 16) + 1;
+            head = i == 0 || ((rp[i - 1] & 0xFFFFu) + (rp[i - 1] >> 16) + 1u) != (pr & 0xFFFFu);
+        }
+        c += wave_sum_u32(len);
+        rm += (uint32_t)__popcll(__ballot(head));
+    }
+    c = uniform(c);
+    rm = uniform(rm);
+    if (c == 0) return;
+    const uint8_t type = p1_type(c, rm);
+    const uint64_t soff = so.slot_off[slot];
+    const uint64_t nbytes = type == RG_ARRAY ? 2ull * c : type == RG_BITSET ? 8192ull : 4ull * rm;
+    if (soff + nbytes > so.cap) {
+        if (lane == 0 && so.err) atomicOr(so.err, 2u);
+        return;
+    }
+    uint8_t* dst = so.payload + soff;
+    if (type == RG_RUN) {
+        // rm <= 2048 here: starts in lds[0, 2048), ends in lds[2048, 4096)
+        uint32_t hb = 0;  // merged runs started in earlier rounds
+        for (uint32_t base = 0; base < r; base += 64) {
+            const uint32_t i = base + lane;
+            bool head = false, tail = false;
+            uint32_t s = 0, e = 0;
+            if (i < r) {
+                const uint32_t pr = rp[i];
+                s = pr & 0xFFFFu;
+                e = s + (pr >> 16);
+                head = i == 0 || ((rp[i - 1] & 0xFFFFu) + (rp[i - 1] >> 16) + 1u) != s;
+                tail = i + 1 == r || (rp[i + 1] & 0xFFFFu) != e + 1u;
+            }
+            const uint64_t heads = __ballot(head);
+            const uint32_t upto = hb + (uint32_t)__popcll(heads & ((2ull << lane) - 1ull));  // heads at or before i
+            if (head) lds[upto - 1] = (uint16_t)s;
+            if (tail) lds[2048 + upto - 1] = (uint16_t)e;
+            hb += (uint32_t)__popcll(heads);
+        }
+        __builtin_amdgcn_wave_barrier();
+        uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
+        for (uint32_t j = lane; j < rm; j += 64)
+            d32[j] = (uint32_t)lds[j] | ((uint32_t)(lds[2048 + j] - lds[j]) << 16);
+    } else if (type == RG_ARRAY) {
+        uint16_t* d16 = reinterpret_cast<uint16_t*>(dst);
+        uint32_t cb = 0;  // values of earlier rounds
+        for (uint32_t base = 0; base < r; base += 64) {
+            const uint32_t i = base + lane;
+            uint32_t s = 0, len = 0;
+            if (i < r) {
+                s = rp[i] & 0xFFFFu;
+                len = (rp[i] >> 16) + 1;
+            }
+            uint32_t tot;
+            const uint32_t at = cb + wave_excl_sum(len, tot);
+            for (uint32_t q = 0; q < len; ++q) d16[at + q] = (uint16_t)(s + q);
+            cb += tot;
+        }
+    } else {
+        uint64_t* bits = reinterpret_cast<uint64_t*>(lds);  // 1024 words
+        for (uint32_t j = lane; j < 1024; j += 64) bits[j] = 0;
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t i = lane; i < r; i += 64) {
+            const uint32_t first = rp[i] & 0xFFFFu, last = first + (rp[i] >> 16);
+            for (uint32_t wi = first >> 6; wi <= last >> 6; ++wi) {
+                const uint32_t lo = wi == first >> 6 ? first & 63 : 0;
+                const uint32_t hi = wi == last >> 6 ? last & 63 : 63;
+                atomicOr(reinterpret_cast<unsigned long long*>(&bits[wi]), (~0ull << lo) & (~0ull >> (63 - hi)));
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        const u32x4* s4 = reinterpret_cast<const u32x4*>(bits);
+        u32x4* d4 = reinterpret_cast<u32x4*>(dst);
+        for (uint32_t j = lane; j < 512; j += 64) d4[j] = s4[j];
+    }
+    __builtin_amdgcn_wave_barrier();  // the LDS is read before the wave's next slot
+    if (lane == 0) {
+        so.res_card[slot] = c;
+        so.res_type[slot] = type;
+        so.res_size[slot] = type == RG_ARRAY ? c : type == RG_BITSET ? 1024u : rm;
+    }
+}
+
 // Builds the result of one pair into slot `slot` of `so`. `lds`: this wave's
 // SMALL_LDS 16-bit values, 16-byte aligned. Every lane of the wave calls it with the same
 // arguments.
 __device__ void small_pair(int op, SmallSide A, SmallSide B, uint32_t slot, const SlotOut& so, uint16_t* lds) {
     const uint32_t lane = lane_id();
+    if (lone_run(op, A.type, B.type)) {
+        lone_runs(A.type == RG_RUN ? A : B, slot, so, lds);
+        return;
+    }
     // Pairs come here by their cardinalities (small_mat_ok). A pool whose
     // array sizes disagree with them is malformed (rg_pool_validate reports
     // it); its sizes are cut to the staging area, so nothing is read or

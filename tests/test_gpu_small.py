@@ -3,7 +3,7 @@ pairs of bitsets): containers built to hit each of their cases - merges at and
 just past the value limit, results that come out as runs across many 64-value
 rounds, absent sides, array-bitset and array-run filters in both operand
 orders, full 4096-value arrays, bitset pairs whose results are bitsets, arrays,
-runs or empty, lone bitsets - against the oracle, through the eager call
+runs or empty, lone bitsets and lone run containers - against the oracle, through the eager call
 (binned intersection and k-way path) and a materialising plan, and the same
 pairs with the one-wave kernels switched off."""
 import sys
@@ -92,6 +92,11 @@ def case_sets():
         17: (None, np.unique(rng.integers(0, 65536, 9000))),
         # evens and odds below 20000 (bitsets): union and symmetric difference are one run
         18: (np.arange(0, 20000, 2), np.arange(1, 20000, 2)),
+        # evens below 40000 and the odds less every 13th: 1539 runs over 38462 values
+        19: (np.arange(0, 40000, 2), np.delete(np.arange(1, 40000, 2), np.arange(0, 20000, 13))),
+        # a run container only in A, one only in B (copied in P1 form)
+        20: (np.concatenate([np.arange(s, s + 20) for s in range(0, 4000, 40)]), None),
+        21: (None, np.arange(100, 60000)),
     }
     a, b = [], []
     for key, (pa, pb) in parts.items():
@@ -116,9 +121,10 @@ def _check_types(rg):
     assert ta[11] == A and tb[11] == R
     assert ta[12] == A and tb[12] == R and int(cb["runs"][cb["keys"].tolist().index(12)]) == 2047
     assert ta[9] == A and int(ca["card"][ca["keys"].tolist().index(9)]) == 4096
-    for key in (14, 15, 18):
+    for key in (14, 15, 18, 19):
         assert ta[key] == B and tb[key] == B, key
     assert ta[16] == B and tb[17] == B
+    assert ta[20] == R and tb[21] == R
 
 
 def test_cases_against_oracle(rg, ctx):
