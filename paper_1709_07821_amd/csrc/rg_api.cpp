@@ -110,13 +110,13 @@ uint64_t max_pair_slots(int op, bool mat) {
     return (op == RG_OR || op == RG_XOR) ? 131072 : 65536;
 }
 
-// Persistent grid of the fused count kernel: workgroups per CU that fit its
-// LDS, never more blocks than there can be candidate blocks (65536 keys per
-// pair at most).
+// Persistent grid of the fused count kernel: as many workgroups as are
+// resident at once, never more blocks than there can be candidate blocks
+// (65536 keys per pair at most).
 uint32_t fused_grid(rg_ctx* c, uint64_t n_pairs) {
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
-    const uint64_t cap = (uint64_t)cus * 4;
+    const uint64_t cap = (uint64_t)cus * count_fused_blocks_per_cu();
     const uint64_t most = n_pairs * (65536 / MATCH_SLOTS);
     return (uint32_t)std::max<uint64_t>(1, std::min(cap, most));
 }
@@ -1123,7 +1123,7 @@ rg_status rg_plan_create(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, 
     p->thread_max = c->thread_max;
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
-    p->grid = (uint32_t)cus * 4;
+    p->grid = (uint32_t)cus * count_fused_blocks_per_cu();
 
     // candidate counts: one preparation pass, read back once
     auto cleanup = [&](rg_status s) {
@@ -1453,7 +1453,9 @@ rg_status rg_plan_tune(rg_plan* p, void* stream, int reps) {
     // typical pool become workgroup merges, hundreds of times slower)
     std::vector<uint32_t> tvals = heur ? std::vector<uint32_t>{4, 16, 64} : std::vector<uint32_t>{};
     std::vector<uint32_t> gvals;
+    // multiples of the CUs, and the resident grid itself
     for (uint32_t f : {1u, 2u, 4u, 8u, 16u}) gvals.push_back((uint32_t)cus * f);
+    if (count_fused_blocks_per_cu() != 4u) gvals.push_back((uint32_t)cus * count_fused_blocks_per_cu());
     std::vector<uint32_t> rvals = heur ? std::vector<uint32_t>{8, 32, 128, 512} : std::vector<uint32_t>{};
     uint32_t* knobs[3] = {&p->thread_max, &p->grid, &p->gallop_ratio};
     const std::vector<uint32_t>* vals[3] = {&tvals, &gvals, &rvals};

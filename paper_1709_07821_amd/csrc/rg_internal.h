@@ -262,6 +262,7 @@ void launch_match(const MatchArgs& m, hipStream_t st);
 // persistent kernel (m.materialize false, m.fuse_thread true, m.pair0 0, m.cand_off
 // the exclusive scan over all pairs with the total at cand_off[n_pairs]).
 // *next_blk must be 0 at launch (k_pair_prep's zero_word).
+uint32_t count_fused_blocks_per_cu();
 void launch_count_fused(const MatchArgs& m, uint32_t* next_blk, uint32_t grid, hipStream_t st);
 // Binning without contended atomics: k_match leaves per-block bin counts; an
 // exclusive scan of them (bin-major) gives each block's place in each bin's
