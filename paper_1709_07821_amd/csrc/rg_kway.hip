@@ -190,18 +190,23 @@ __device__ void kw_fill_keys(const KwArgs& a, const uint64_t* rs, const uint32_t
     }
     __syncthreads();
     const uint32_t total = uniform(roff[m]);
+    // the bitmap holding the thread's current position and its range in the
+    // concatenated order, kept in registers: positions only grow, so the
+    // bitmap only moves forward (a few LDS reads per round, not one per key)
+    uint32_t jj = 0, lo_off = 0, hi_off = roff[1];
+    const uint16_t* src = nullptr;  // the bitmap's key list
+    auto enter = [&](uint32_t i) {
+        while (hi_off <= i) {
+            ++jj;
+            lo_off = hi_off;
+            hi_off = roff[jj + 1];
+        }
+        const uint32_t j = j0 + jj;
+        src = (j ? a.P1.keys : a.P0.keys) + rs[j];
+    };
     for (uint32_t base = 0; base < total; base += 256 * KW_KEY_UNROLL) {
         const uint32_t i0 = base + tid * KW_KEY_UNROLL;
-        uint32_t jj = 0;  // the bitmap holding position i0 (a binary search over roff)
-        if (i0 < total) {
-            uint32_t lo = 0, hi = m - 1;
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi + 1) >> 1;
-                if (roff[mid] <= i0) lo = mid;
-                else hi = mid - 1;
-            }
-            jj = lo;
-        }
+        if (i0 < total) enter(i0);
         uint32_t key[KW_KEY_UNROLL], mi[KW_KEY_UNROLL];
 #pragma unroll
         for (uint32_t r = 0; r < KW_KEY_UNROLL; ++r) {
@@ -209,10 +214,8 @@ __device__ void kw_fill_keys(const KwArgs& a, const uint64_t* rs, const uint32_t
             key[r] = 0xFFFFFFFFu;
             mi[r] = 0;
             if (i < total) {
-                while (roff[jj + 1] <= i) ++jj;  // i only grows, so jj only moves forward
-                const uint32_t j = j0 + jj;
-                const uint16_t* pkeys = j ? a.P1.keys : a.P0.keys;
-                key[r] = pkeys[rs[j] + (i - roff[jj])];
+                if (i >= hi_off) enter(i);
+                key[r] = src[i - lo_off];
                 mi[r] = per_bitmap ? jj : 0u;
             }
         }
