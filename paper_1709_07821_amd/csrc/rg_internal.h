@@ -435,7 +435,19 @@ __host__ __device__ __forceinline__ bool bb_mat_ok(int op, uint8_t ta, uint8_t t
     return false;
 }
 constexpr uint32_t KW_MATERIALIZE = 1u;  // KwQuery.flags: build the result containers
+// KwQuery.flags: the query's key set is built in parts (KwPart), one workgroup
+// each, combined in a key mask in device memory (KwQuery.pad = its index)
+constexpr uint32_t KW_SPLIT = 2u;
 constexpr uint32_t KW_MAX_K = 256;       // bitmaps per query (one lookup thread each)
+constexpr uint32_t KW_AND_GROUP = 4;     // bitmaps whose key masks an intersection fills at once
+constexpr uint32_t KW_PART_KEYS = 4096;  // keys per part of a split union or symmetric difference
+// One part of a split key pass: the query's bitmaps j0 .. j1-1.
+struct KwPart {
+    uint32_t q;     // query index
+    uint32_t j01;   // j0 | j1 << 16
+    uint32_t mi;    // key mask (and arrival counter) of the query
+    uint32_t n;     // parts of the query
+};
 struct KwQuery {
     uint32_t op;       // RG_AND, RG_OR, RG_XOR (fold of k) or RG_ANDNOT (first minus the others)
     uint32_t k;        // number of bitmaps, 1..KW_MAX_K
@@ -443,7 +455,7 @@ struct KwQuery {
     uint32_t flags;    // KW_MATERIALIZE or 0 (count only)
     uint64_t slot0;    // first slot of the query's range
     uint32_t kbound;   // slots in the range (bound on result containers)
-    uint32_t pad;
+    uint32_t pad;      // KW_SPLIT: the query's key mask index
 };
 static_assert(sizeof(KwQuery) == 32, "query record is 32 bytes");
 struct KwArgs {
@@ -461,9 +473,15 @@ struct KwArgs {
     long long* acc;     // per query, count-only results
     uint32_t* err;      // set when a query's key set exceeds its slot range
     uint32_t small = 1; // materialised results with an array side go to the one-wave kernel
+    const KwPart* parts = nullptr;  // parts of split key passes
+    uint32_t n_parts = 0;
+    uint64_t* kmask = nullptr;      // 1024 words per split query, zero before the key pass
+    uint32_t* kdone = nullptr;      // parts finished, per split query, zero before the key pass
 };
+// kmask / kdone: the split queries' key masks (n_masks x 1024 words) and arrival counters, zeroed
 void launch_kw_step_init(uint64_t* totals, uint32_t* err, long long* acc, uint64_t* bm_card, uint64_t* bm_wbytes,
-                         uint32_t nq, hipStream_t st);
+                         uint32_t nq, uint64_t* kmask, uint32_t* kdone, uint32_t n_masks, hipStream_t st);
+// the key pass: parts of split queries (when a.n_parts), then the others
 void launch_kw_keys(const KwArgs& a, hipStream_t st);
 void launch_kw_bounds(const KwArgs& a, hipStream_t st);
 // the two evaluation kernels: the one-wave array kernel for the slots the
@@ -477,9 +495,12 @@ void launch_kw_cards(const KwArgs& a, const uint64_t* bm_card, uint64_t* cards, 
 void launch_kw_pair_queries(int op, const uint32_t* ia, const uint32_t* ib, uint32_t ia0, uint32_t ib0,
                             uint64_t pair0, uint32_t n_pairs, const uint64_t* cand_off, KwQuery* queries,
                             uint32_t* ids, hipStream_t st, bool single = false);
-// out[3j..3j+2] = key count, payload bound, 1 (0, 0, 0 for an id outside the pool)
-void launch_kw_gather_meta(const uint64_t* bm_begin, const uint64_t* bm_wbytes, uint32_t n_bitmaps,
-                           const uint32_t* ids, uint32_t k, uint64_t* out, hipStream_t st);
+// out[4j..4j+3] = key count, payload bound, 1, first key | last key << 16 (all 0 for an id
+// outside the pool; the span 0 for a bitmap without keys). launch_kw_key_span: the span
+// of every bitmap of a pool.
+void launch_kw_gather_meta(const uint64_t* bm_begin, const uint16_t* keys, const uint64_t* bm_wbytes,
+                           uint32_t n_bitmaps, const uint32_t* ids, uint32_t k, uint64_t* out, hipStream_t st);
+void launch_kw_key_span(const uint64_t* bm_begin, const uint16_t* keys, uint32_t n, uint32_t* out, hipStream_t st);
 
 // pool utilities
 void launch_pool_recount(const rg_pool& p, hipStream_t st);

@@ -30,6 +30,7 @@
 namespace rg {
 
 constexpr int KW_UNROLL = 4;  // independent loads in flight per thread in the key and fold passes
+constexpr uint32_t KW_BS_BATCH = 8;    // bitset containers whose words a fold loads at once
 constexpr uint32_t KW_EVAL_CHUNK = 4;  // slots whose tasks the evaluation workgroup reads at once (measured: 1, 4, 16)
 
 __device__ __forceinline__ uint32_t kw_find_key(const uint64_t* bm_begin, const uint16_t* keys, uint32_t b,
@@ -167,7 +168,6 @@ __global__ void __launch_bounds__(256) k_kw_keys_small(KwArgs a) {
 }
 
 constexpr uint32_t KW_KEY_UNROLL = 16;  // keys per thread per round of a multi-bitmap key pass
-constexpr uint32_t KW_AND_GROUP = 4;    // bitmaps whose key masks an intersection fills at once
 
 // Sets the key bits of the query's bitmaps j0 .. j1-1 (key lists at rs[j],
 // rn[j]) in one pass over their concatenated lists: into masks[j - j0] when
@@ -239,6 +239,79 @@ __device__ void kw_fill_keys(const KwArgs& a, const uint64_t* rs, const uint32_t
     __syncthreads();
 }
 
+// Writes query q's result keys (the set bits of acc, ascending; thread t owns
+// words 4t..4t+3) as one task per key into its slot range, and no-op tasks into
+// the rest of the range. indexed (at most two bitmaps): acc and cur are the two
+// bitmaps' key masks, and each task records the positions of its containers.
+__device__ void kw_emit_tasks(const KwArgs& a, uint32_t q, uint32_t op, uint32_t k, uint64_t slot0, uint32_t kbound,
+                              const uint64_t* acc, const uint64_t* cur, const uint64_t* rs, bool indexed,
+                              uint32_t* tmp) {
+    const uint32_t tid = threadIdx.x;
+    uint64_t w[4], m0[4], m1[4];
+    uint32_t c = 0, c0 = 0, c1 = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        m0[j] = acc[4 * tid + j];
+        m1[j] = indexed && k == 2 ? cur[4 * tid + j] : 0ull;
+        w[j] = !indexed ? m0[j]
+               : k == 1 ? m0[j]
+               : op == RG_AND ? (m0[j] & m1[j]) : op == RG_ANDNOT ? m0[j] : (m0[j] | m1[j]);
+        c += __popcll(w[j]);
+        c0 += __popcll(m0[j]);
+        c1 += __popcll(m1[j]);
+    }
+    uint32_t total;
+    uint32_t pos = block_excl_scan_u32(c, tmp, &total);
+    // with recorded positions: ranks of this thread's first word in each key mask
+    uint32_t r0 = 0, r1 = 0, unused;
+    if (indexed) {
+        r0 = block_excl_scan_u32(c0, tmp, &unused);
+        r1 = block_excl_scan_u32(c1, tmp, &unused);
+    }
+    // total <= kbound holds by construction of the host bound; guard anyway
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        uint64_t x = w[j];
+        while (x) {
+            const uint32_t b = (uint32_t)__builtin_ctzll(x);
+            const uint32_t key = (4 * tid + j) * 64 + b;
+            x &= x - 1;
+            if (pos < kbound) {
+                Task t;
+                t.pair = a.pair_base + q;
+                t.ia = NONE;
+                t.ib = NONE;
+                t.key = (uint16_t)key;
+                t.kind = KIND_MATCH;
+                t.bin = 0;
+                if (indexed) {
+                    // container index = list start + number of the bitmap's keys below this one
+                    const uint64_t below = (1ull << b) - 1ull;
+                    if ((m0[j] >> b) & 1ull) t.ia = (uint32_t)(rs[0] + r0 + __popcll(m0[j] & below));
+                    if ((m1[j] >> b) & 1ull) t.ib = (uint32_t)(rs[1] + r1 + __popcll(m1[j] & below));
+                    t.bin = KW_TASK_INDEXED;
+                }
+                a.tasks[slot0 + pos] = t;
+            }
+            ++pos;
+        }
+        r0 += __popcll(m0[j]);
+        r1 += __popcll(m1[j]);
+    }
+    const uint32_t used = total < kbound ? total : kbound;
+    for (uint32_t i = used + tid; i < kbound; i += 256) {
+        Task t;
+        t.pair = a.pair_base + q;
+        t.ia = NONE;
+        t.ib = NONE;
+        t.key = 0;
+        t.kind = KIND_NOOP;
+        t.bin = 0;
+        a.tasks[slot0 + i] = t;
+    }
+    if (tid == 0 && total > kbound) atomicOr(a.err, 1u);
+}
+
 __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a, uint32_t chunk) {
     __shared__ uint64_t accm[1][1024];
     __shared__ uint64_t grp[KW_AND_GROUP][1024];  // key masks of a group of bitmaps (intersection)
@@ -256,7 +329,9 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a, uint32_t chunk) {
     bool big = false;
     if (threadIdx.x < chunk && c0 + threadIdx.x < a.n_queries) {
         const KwQuery Q = a.queries[c0 + threadIdx.x];
-        if (Q.k > 2) {
+        if (Q.flags & KW_SPLIT) {
+            big = false;  // built by k_kw_keys_part
+        } else if (Q.k > 2) {
             big = true;
         } else {
             const uint32_t b0 = a.ids[Q.ids_off];
@@ -340,72 +415,89 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a, uint32_t chunk) {
             __syncthreads();
         }
     }
-    // ascending keys: thread t owns words 4t..4t+3
-    uint64_t w[4], m0[4], m1[4];
-    uint32_t c = 0, c0 = 0, c1 = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        m0[j] = acc[4 * tid + j];
-        m1[j] = indexed && k == 2 ? cur[4 * tid + j] : 0ull;
-        w[j] = !indexed ? m0[j]
-               : k == 1 ? m0[j]
-               : op == RG_AND ? (m0[j] & m1[j]) : op == RG_ANDNOT ? m0[j] : (m0[j] | m1[j]);
-        c += __popcll(w[j]);
-        c0 += __popcll(m0[j]);
-        c1 += __popcll(m1[j]);
-    }
-    uint32_t total;
-    uint32_t pos = block_excl_scan_u32(c, tmp, &total);
-    // with recorded positions: ranks of this thread's first word in each key mask
-    uint32_t r0 = 0, r1 = 0, unused;
-    if (indexed) {
-        r0 = block_excl_scan_u32(c0, tmp, &unused);
-        r1 = block_excl_scan_u32(c1, tmp, &unused);
-    }
-    // total <= kbound holds by construction of the host bound; guard anyway
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        uint64_t x = w[j];
-        while (x) {
-            const uint32_t b = (uint32_t)__builtin_ctzll(x);
-            const uint32_t key = (4 * tid + j) * 64 + b;
-            x &= x - 1;
-            if (pos < kbound) {
-                Task t;
-                t.pair = a.pair_base + q;
-                t.ia = NONE;
-                t.ib = NONE;
-                t.key = (uint16_t)key;
-                t.kind = KIND_MATCH;
-                t.bin = 0;
-                if (indexed) {
-                    // container index = list start + number of the bitmap's keys below this one
-                    const uint64_t below = (1ull << b) - 1ull;
-                    if ((m0[j] >> b) & 1ull) t.ia = (uint32_t)(rs[0] + r0 + __popcll(m0[j] & below));
-                    if ((m1[j] >> b) & 1ull) t.ib = (uint32_t)(rs[1] + r1 + __popcll(m1[j] & below));
-                    t.bin = KW_TASK_INDEXED;
-                }
-                a.tasks[slot0 + pos] = t;
-            }
-            ++pos;
-        }
-        r0 += __popcll(m0[j]);
-        r1 += __popcll(m1[j]);
-    }
-    const uint32_t used = total < kbound ? total : kbound;
-    for (uint32_t i = used + tid; i < kbound; i += 256) {
-        Task t;
-        t.pair = a.pair_base + q;
-        t.ia = NONE;
-        t.ib = NONE;
-        t.key = 0;
-        t.kind = KIND_NOOP;
-        t.bin = 0;
-        a.tasks[slot0 + i] = t;
-    }
-    if (tid == 0 && total > kbound) atomicOr(a.err, 1u);
+    kw_emit_tasks(a, q, op, k, slot0, kbound, acc, cur, rs, indexed, tmp);
     __syncthreads();  // LDS read before the next query's pass
     }
+    }
+}
+
+
+// Split key passes (queries of many bitmaps, parts from the host): each
+// workgroup builds the key set of its part's bitmaps in LDS (union: every key;
+// intersection: keys of all of them) and ORs it into the query's key mask in
+// device memory (an intersection ORs the complement, so that a zeroed mask
+// serves both). The last part of a query to arrive (counted after a fence)
+// reads the mask back and writes the query's tasks, as k_kw_keys does.
+__global__ void __launch_bounds__(256) k_kw_keys_part(KwArgs a) {
+    __shared__ uint64_t accm[1][1024];
+    __shared__ uint64_t grp[KW_AND_GROUP][1024];
+    uint64_t* acc = accm[0];
+    __shared__ uint32_t tmp[8];
+    __shared__ uint64_t rs[KW_MAX_K];
+    __shared__ uint32_t rn[KW_MAX_K];
+    __shared__ uint32_t roff[KW_MAX_K + 1];
+    __shared__ uint32_t last;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t p = blockIdx.x; p < a.n_parts; p += gridDim.x) {
+        const KwPart P = a.parts[p];
+        const uint32_t q = uniform(P.q), j0 = uniform(P.j01 & 0xFFFFu);
+        const uint32_t mi = uniform(P.mi), n = uniform(P.n);
+        const KwQuery Q = a.queries[q];
+        const uint32_t op = uniform(Q.op), k = uniform(Q.k), ids0 = uniform(Q.ids_off);
+        uint32_t j1 = uniform(P.j01 >> 16);
+        // parts come from the host within these limits; a part outside them
+        // is cut to them (memory-safe) and reported
+        if (j1 > k || j0 >= j1 || (op == RG_AND && j1 - j0 > KW_AND_GROUP)) {
+            if (tid == 0) atomicOr(a.err, 1u);
+            j1 = j1 > k ? k : j1;
+            j1 = op == RG_AND && j1 > j0 + KW_AND_GROUP ? j0 + KW_AND_GROUP : j1;
+        }
+        for (uint32_t j = j0 + tid; j < j1; j += 256) {
+            const uint64_t* bmb = j ? a.P1.bm_begin : a.P0.bm_begin;
+            const uint32_t b = a.ids[ids0 + j];
+            const uint64_t s0 = bmb[b];
+            rs[j] = s0;
+            rn[j] = (uint32_t)(bmb[b + 1] - s0);
+        }
+        for (uint32_t i = tid; i < 1024; i += 256) acc[i] = 0;
+        __syncthreads();
+        if (j0 >= j1) {
+            // an empty part (only after a cut): adds no key, removes none
+            for (uint32_t i = tid; i < 1024; i += 256) acc[i] = op == RG_AND ? ~0ull : 0ull;
+            __syncthreads();
+        } else if (op != RG_AND) {
+            kw_fill_keys(a, rs, rn, roff, j0, j1, accm, false);
+        } else {
+            // at most KW_AND_GROUP bitmaps: one mask each, then their AND
+            for (uint32_t i = tid; i < (j1 - j0) * 1024; i += 256) grp[i >> 10][i & 1023] = 0;
+            __syncthreads();
+            kw_fill_keys(a, rs, rn, roff, j0, j1, grp, true);
+            for (uint32_t i = tid; i < 1024; i += 256) {
+                uint64_t x = ~0ull;
+                for (uint32_t g = 0; g < j1 - j0; ++g) x &= grp[g][i];
+                acc[i] = x;
+            }
+            __syncthreads();
+        }
+        uint64_t* gm = a.kmask + (uint64_t)mi * 1024;
+        for (uint32_t i = tid; i < 1024; i += 256) {
+            const uint64_t x = op == RG_AND ? ~acc[i] : acc[i];
+            if (x) atomicOr(reinterpret_cast<unsigned long long*>(&gm[i]), (unsigned long long)x);
+        }
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) last = atomicAdd(&a.kdone[mi], 1u) == n - 1 ? 1u : 0u;
+        __syncthreads();
+        if (uniform(last)) {
+            __threadfence();
+            for (uint32_t i = tid; i < 1024; i += 256) {
+                const uint64_t x = __hip_atomic_load(&gm[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                acc[i] = op == RG_AND ? ~x : x;
+            }
+            __syncthreads();
+            kw_emit_tasks(a, q, op, k, uniform64(Q.slot0), uniform(Q.kbound), acc, nullptr, rs, false, tmp);
+        }
+        __syncthreads();  // LDS read before the next part
     }
 }
 
@@ -537,6 +629,7 @@ __global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
     __shared__ uint32_t cunits[KW_MAX_K + 1];  // exclusive prefix of the containers' unit counts
     __shared__ uint8_t ctype[KW_MAX_K];
     __shared__ uint64_t cpl[KW_MAX_K];         // payload address of each container
+    __shared__ uint8_t bsl[KW_MAX_K];          // the bitset containers (union, symmetric difference, difference)
     __shared__ uint32_t chunk_mask;
     const uint32_t tid = threadIdx.x;
     // chunks of KW_EVAL_CHUNK slots: their tasks are read at once, then the
@@ -583,35 +676,57 @@ __global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
             // run containers then fold into the LDS bitset all at once with one
             // LDS atomic per value or run. No container waits for another.
             const uint32_t j0 = op == RG_ANDNOT ? 1u : 0u;
-            uint32_t units = 0;
+            // per container: its unit count (values or runs; 0 for a bitset),
+            // and for the bitsets their place in a list
+            uint32_t units = 0, isbs = 0;
             if (tid < k) {
                 ctype[tid] = 0;  // absent (or the first container of a difference)
                 const uint32_t ci = cidx[tid];
                 if (ci != NONE && tid >= j0) {
                     const PoolView pv = kw_side(a, tid != 0);
                     const uint8_t ty = pv.types[ci];
-                    units = ty == RG_BITSET ? 0u : pv.size[ci];
+                    isbs = ty == RG_BITSET ? 1u : 0u;
+                    units = isbs ? 0u : pv.size[ci];
                     ctype[tid] = ty;
                     cpl[tid] = reinterpret_cast<uint64_t>(pv.payload + pv.off[ci]);
                 }
             }
-            uint32_t total;
+            uint32_t total, nbs;
             const uint32_t pos = block_excl_scan_u32(units, sh.tmp, &total);
+            const uint32_t bpos = block_excl_scan_u32(isbs, sh.tmp, &nbs);
             if (tid < k) cunits[tid] = pos;
             if (tid == 0) cunits[k] = total;
+            if (isbs) bsl[bpos] = (uint8_t)tid;
             if (op == RG_ANDNOT) expand_container(sh.sa, a.P0, uniform(cidx[0]), sh);  // ends with a barrier
             else __syncthreads();
             uint64_t r[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) r[q] = op == RG_ANDNOT ? sh.sa[4 * tid + q] : 0ull;
-            for (uint32_t jj = j0; jj < k; ++jj) {
-                if (uniform(ctype[jj]) != RG_BITSET) continue;
-                const u32x4* src = reinterpret_cast<const u32x4*>(cpl[jj]) + 2 * tid;
-                const u32x4 v0 = src[0], v1 = src[1];
-                const uint64_t x[4] = {(uint64_t)v0.x | ((uint64_t)v0.y << 32), (uint64_t)v0.z | ((uint64_t)v0.w << 32),
-                                       (uint64_t)v1.x | ((uint64_t)v1.y << 32), (uint64_t)v1.z | ((uint64_t)v1.w << 32)};
+            // the bitsets, KW_BS_BATCH at a time with all their loads in flight
+            // (each operation is order-free across the containers it folds)
+            const uint32_t nb = uniform(nbs);
+            for (uint32_t b0 = 0; b0 < nb; b0 += KW_BS_BATCH) {
+                u32x4 v0[KW_BS_BATCH], v1[KW_BS_BATCH];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) r[q] = op == RG_OR ? (r[q] | x[q]) : op == RG_XOR ? (r[q] ^ x[q]) : (r[q] & ~x[q]);
+                for (uint32_t u = 0; u < KW_BS_BATCH; ++u) {
+                    if (b0 + u < nb) {
+                        const u32x4* src = reinterpret_cast<const u32x4*>(cpl[bsl[b0 + u]]) + 2 * tid;
+                        v0[u] = src[0];
+                        v1[u] = src[1];
+                    }
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < KW_BS_BATCH; ++u) {
+                    if (b0 + u < nb) {
+                        const uint64_t x[4] = {(uint64_t)v0[u].x | ((uint64_t)v0[u].y << 32),
+                                               (uint64_t)v0[u].z | ((uint64_t)v0[u].w << 32),
+                                               (uint64_t)v1[u].x | ((uint64_t)v1[u].y << 32),
+                                               (uint64_t)v1[u].z | ((uint64_t)v1[u].w << 32)};
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            r[q] = op == RG_OR ? (r[q] | x[q]) : op == RG_XOR ? (r[q] ^ x[q]) : (r[q] & ~x[q]);
+                    }
+                }
             }
             const uint32_t tu = uniform(total);
             if (tu == 0) {
@@ -697,7 +812,7 @@ __global__ void k_kw_cards(KwArgs a, const uint64_t* bm_card, uint64_t* cards) {
 // Zeroes what a step accumulates into, in one launch: two scan totals, the
 // error flag, and per query its count accumulator, cardinality and payload bound.
 __global__ void k_kw_step_init(uint64_t* totals, uint32_t* err, long long* acc, uint64_t* bm_card,
-                               uint64_t* bm_wbytes, uint32_t nq) {
+                               uint64_t* bm_wbytes, uint32_t nq, uint64_t* kmask, uint32_t* kdone, uint32_t n_masks) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < 2) totals[i] = 0;
     if (i == 0) *err = 0;
@@ -706,17 +821,22 @@ __global__ void k_kw_step_init(uint64_t* totals, uint32_t* err, long long* acc, 
         bm_card[i] = 0;
         bm_wbytes[i] = 0;
     }
+    if (i < n_masks * 1024u) kmask[i] = 0;
+    if (i < n_masks) kdone[i] = 0;
 }
 
 void launch_kw_step_init(uint64_t* totals, uint32_t* err, long long* acc, uint64_t* bm_card, uint64_t* bm_wbytes,
-                         uint32_t nq, hipStream_t st) {
-    const uint32_t n = nq > 2 ? nq : 2;
+                         uint32_t nq, uint64_t* kmask, uint32_t* kdone, uint32_t n_masks, hipStream_t st) {
+    uint32_t n = nq > 2 ? nq : 2;
+    n = n > n_masks * 1024u ? n : n_masks * 1024u;
     hipLaunchKernelGGL(k_kw_step_init, dim3((n + 255) / 256), dim3(256), 0, st, totals, err, acc, bm_card, bm_wbytes,
-                       nq);
+                       nq, kmask, kdone, n_masks);
 }
 
 void launch_kw_keys(const KwArgs& a, hipStream_t st) {
     if (!a.n_queries) return;
+    if (a.n_parts)
+        hipLaunchKernelGGL(k_kw_keys_part, dim3(a.n_parts < 16384 ? a.n_parts : 16384u), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_kw_keys_small, dim3((a.n_queries + 3) / 4), dim3(256), 0, st, a);
     // a query per workgroup for small batches (each may be large); up to
     // KW_KEYS_CHUNK for large ones, where most are the one-wave kernel's
@@ -775,27 +895,44 @@ void launch_kw_pair_queries(int op, const uint32_t* ia, const uint32_t* ib, uint
                            pair0, n_pairs, cand_off, queries, ids, (int)single);
 }
 
-// per id: key count, payload bound (bm_wbytes), and validity, for host-side bounds
-__global__ void k_kw_gather_meta(const uint64_t* bm_begin, const uint64_t* bm_wbytes, uint32_t n_bitmaps,
-                                 const uint32_t* ids, uint32_t k, uint64_t* out) {
+// first key | last key << 16 of a bitmap with keys (0 for one without)
+__device__ __forceinline__ uint32_t kw_span(const uint64_t* bm_begin, const uint16_t* keys, uint32_t b) {
+    const uint64_t s = bm_begin[b], e = bm_begin[b + 1];
+    return s < e ? (uint32_t)keys[s] | (uint32_t)keys[e - 1] << 16 : 0u;
+}
+
+// per id: key count, payload bound (bm_wbytes), validity and key span, for host-side bounds
+__global__ void k_kw_gather_meta(const uint64_t* bm_begin, const uint16_t* keys, const uint64_t* bm_wbytes,
+                                 uint32_t n_bitmaps, const uint32_t* ids, uint32_t k, uint64_t* out) {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= k) return;
     const uint32_t b = ids[j];
     if (b >= n_bitmaps) {
-        out[3 * j] = 0;
-        out[3 * j + 1] = 0;
-        out[3 * j + 2] = 0;
+        out[4 * j] = 0;
+        out[4 * j + 1] = 0;
+        out[4 * j + 2] = 0;
+        out[4 * j + 3] = 0;
         return;
     }
-    out[3 * j] = bm_begin[b + 1] - bm_begin[b];
-    out[3 * j + 1] = bm_wbytes[b];
-    out[3 * j + 2] = 1;
+    out[4 * j] = bm_begin[b + 1] - bm_begin[b];
+    out[4 * j + 1] = bm_wbytes[b];
+    out[4 * j + 2] = 1;
+    out[4 * j + 3] = kw_span(bm_begin, keys, b);
 }
 
-void launch_kw_gather_meta(const uint64_t* bm_begin, const uint64_t* bm_wbytes, uint32_t n_bitmaps,
-                           const uint32_t* ids, uint32_t k, uint64_t* out, hipStream_t st) {
-    if (k) hipLaunchKernelGGL(k_kw_gather_meta, dim3((k + 255) / 256), dim3(256), 0, st, bm_begin, bm_wbytes,
+void launch_kw_gather_meta(const uint64_t* bm_begin, const uint16_t* keys, const uint64_t* bm_wbytes,
+                           uint32_t n_bitmaps, const uint32_t* ids, uint32_t k, uint64_t* out, hipStream_t st) {
+    if (k) hipLaunchKernelGGL(k_kw_gather_meta, dim3((k + 255) / 256), dim3(256), 0, st, bm_begin, keys, bm_wbytes,
                               n_bitmaps, ids, k, out);
+}
+
+__global__ void k_kw_key_span(const uint64_t* bm_begin, const uint16_t* keys, uint32_t n, uint32_t* out) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < n) out[b] = kw_span(bm_begin, keys, b);
+}
+
+void launch_kw_key_span(const uint64_t* bm_begin, const uint16_t* keys, uint32_t n, uint32_t* out, hipStream_t st) {
+    if (n) hipLaunchKernelGGL(k_kw_key_span, dim3((n + 255) / 256), dim3(256), 0, st, bm_begin, keys, n, out);
 }
 
 }  // namespace rg

@@ -42,28 +42,76 @@ struct Bounds {
     uint64_t pbound = 0;  // result payload bytes (0 for count-only)
 };
 
-// meta[3j..3j+2] = key count, payload bound, valid flag of the query's j-th bitmap
+// meta[4j..4j+3] = key count, payload bound, valid flag and key span (first
+// key | last key << 16, when the count is not zero) of the query's j-th bitmap.
+// Result keys lie in the bitmaps' key lists (Section 1: a bitmap is its sorted
+// keys and their containers): a union or symmetric difference holds at most
+// every key between the smallest first key and the largest last key, an
+// intersection only keys between the largest first key and the smallest last
+// key, a difference only keys of its first bitmap. Each result container takes
+// at most 8 KiB, so the payload bound is also capped by the key bound.
 Bounds query_bounds(int op, uint32_t k, const uint64_t* meta, bool mat) {
     uint64_t kmin = ~0ull, ksum = 0, wmin = ~0ull, wsum = 0;
+    uint32_t lo_min = 65535, lo_max = 0, hi_min = 65535, hi_max = 0;  // over bitmaps with keys
     for (uint32_t j = 0; j < k; ++j) {
-        kmin = std::min(kmin, meta[3 * j]);
-        ksum += meta[3 * j];
-        wmin = std::min(wmin, meta[3 * j + 1]);
-        wsum += meta[3 * j + 1];
+        const uint64_t n = meta[4 * j];
+        kmin = std::min(kmin, n);
+        ksum += n;
+        wmin = std::min(wmin, meta[4 * j + 1]);
+        wsum += meta[4 * j + 1];
+        if (n) {
+            const uint32_t lo = (uint32_t)(meta[4 * j + 3] & 0xFFFF), hi = (uint32_t)(meta[4 * j + 3] >> 16 & 0xFFFF);
+            lo_min = std::min(lo_min, lo);
+            lo_max = std::max(lo_max, lo);
+            hi_min = std::min(hi_min, hi);
+            hi_max = std::max(hi_max, hi);
+        }
     }
     Bounds b;
     if (op == RG_AND) {
-        b.kbound = kmin;
+        b.kbound = kmin && hi_min >= lo_max ? std::min<uint64_t>(kmin, hi_min - lo_max + 1) : 0;
         b.pbound = wmin;
     } else if (op == RG_ANDNOT) {
         b.kbound = meta[0];
         b.pbound = meta[1];
     } else {
-        b.kbound = std::min<uint64_t>(ksum, 65536);
-        b.pbound = std::min<uint64_t>(wsum, 65536ull * 8192);
+        b.kbound = ksum ? std::min<uint64_t>(ksum, hi_max - lo_min + 1) : 0;
+        b.pbound = wsum;
     }
+    b.pbound = std::min<uint64_t>(b.pbound, b.kbound * 8192);
     if (!mat) b.pbound = 0;
     return b;
+}
+
+// Splits the key pass of query q (record Q, key count of its j-th bitmap at
+// nkeys[j * stride]) into parts of whole bitmaps for k_kw_keys_part: a union
+// or symmetric difference in parts of about KW_PART_KEYS keys, an
+// intersection in groups of KW_AND_GROUP bitmaps. With two parts or more the
+// query is marked KW_SPLIT with key mask *n_masks (then counted) and its parts
+// are appended; otherwise nothing changes. A difference's keys are its first
+// bitmap's: never split.
+void split_query(KwQuery* Q, uint32_t q, const uint64_t* nkeys, size_t stride, std::vector<KwPart>* parts,
+                 uint32_t* n_masks) {
+    const uint32_t k = Q->k;
+    if (k <= 2 || Q->op == RG_ANDNOT) return;
+    std::vector<uint32_t> cut{0};
+    uint64_t acc = 0;
+    for (uint32_t j = 0; j < k; ++j) {
+        const uint64_t n = nkeys[j * stride];
+        const bool full = Q->op == RG_AND ? j - cut.back() == KW_AND_GROUP : acc > 0 && acc + n > KW_PART_KEYS;
+        if (full) {
+            cut.push_back(j);
+            acc = 0;
+        }
+        acc += n;
+    }
+    cut.push_back(k);
+    const uint32_t n_parts = (uint32_t)cut.size() - 1;
+    if (n_parts < 2) return;
+    const uint32_t mi = (*n_masks)++;
+    for (uint32_t i = 0; i < n_parts; ++i) parts->push_back(KwPart{q, cut[i] | cut[i + 1] << 16, mi, n_parts});
+    Q->flags |= KW_SPLIT;
+    Q->pad = mi;
 }
 
 // Device layout of one step (each piece 256-byte aligned):
@@ -74,10 +122,11 @@ Bounds query_bounds(int op, uint32_t k, const uint64_t* meta, bool mat) {
 struct StepLayout {
     uint32_t nq = 0;
     uint64_t nids = 0, S = 0, P = 0;
+    uint32_t n_parts = 0, n_masks = 0;  // split key passes of the step (set when staged)
     bool own_out = true;
     size_t up_bytes = 0, down_off = 0, down_bytes = 0, total = 0;
     // offsets
-    size_t o_queries, o_ids, o_cand, o_cards, o_digest, o_bm_begin, o_totals, o_err, o_tasks, o_ub, o_slot_off,
+    size_t o_queries, o_ids, o_cand, o_parts, o_kmask, o_kdone, o_cards, o_digest, o_bm_begin, o_totals, o_err, o_tasks, o_ub, o_slot_off,
         o_res_card, o_res_type, o_res_size, o_out_idx, o_partials, o_acc, o_keys, o_types, o_card,
         o_size, o_off, o_payload, o_bm_card, o_bm_wbytes;
 
@@ -96,6 +145,7 @@ struct StepLayout {
         o_queries = take(sizeof(KwQuery) * nq);
         o_ids = take(4 * nids);
         o_cand = take(8 * (nq + 1));
+        o_parts = take(sizeof(KwPart) * nids);  // a part holds one bitmap or more
         up_bytes = u;
         down_off = u;
         o_cards = take(8 * nq);
@@ -113,6 +163,8 @@ struct StepLayout {
         o_out_idx = take(8 * S);
         o_partials = take(8 * scan_partials_needed(S));
         o_acc = take(8 * nq);
+        o_kmask = take(8192 * (size_t)nq);  // a split query's key mask
+        o_kdone = take(4 * nq);
         if (own) {
             o_keys = take(2 * S);
             o_types = take(S);
@@ -187,7 +239,9 @@ rg_status step_enqueue(std::string* err_out, const rg_pool& pool, const StepLayo
     auto* step_bm_begin = reinterpret_cast<uint64_t*>(d + L.o_bm_begin);
 
     STEPCHK(hipMemcpyAsync(d, h_stage, L.up_bytes, hipMemcpyHostToDevice, st));
-    launch_kw_step_init(totals, err, acc, o.bm_card, o.bm_wbytes, L.nq, st);
+    auto* kmask = reinterpret_cast<uint64_t*>(d + L.o_kmask);
+    auto* kdone = reinterpret_cast<uint32_t*>(d + L.o_kdone);
+    launch_kw_step_init(totals, err, acc, o.bm_card, o.bm_wbytes, L.nq, kmask, kdone, L.n_masks, st);
     KwArgs a;
     a.P0 = view(pool);
     a.P1 = a.P0;
@@ -202,6 +256,10 @@ rg_status step_enqueue(std::string* err_out, const rg_pool& pool, const StepLayo
     a.so = SlotOut{slot_off, o.payload, res_card, res_type, res_size};
     a.acc = acc;
     a.err = err;
+    a.parts = reinterpret_cast<const KwPart*>(d + L.o_parts);
+    a.n_parts = L.n_parts;
+    a.kmask = kmask;
+    a.kdone = kdone;
     launch_kw_keys(a, st);
     launch_kw_bounds(a, st);
     if (L.S) launch_scan_u32_u64(ub, slot_off, L.S, 0, partials, totals, st);
@@ -248,9 +306,10 @@ rg_status step_enqueue(std::string* err_out, const rg_pool& pool, const StepLayo
 
 // Fills the upload section of h_stage for queries q (host ids), slot ranges in query order.
 void stage_upload(const StepLayout& L, uint8_t* h_stage, const std::vector<KwQuery>& qs,
-                  const std::vector<uint32_t>& ids) {
+                  const std::vector<uint32_t>& ids, const std::vector<KwPart>& parts) {
     memcpy(h_stage + L.o_queries, qs.data(), sizeof(KwQuery) * qs.size());
     memcpy(h_stage + L.o_ids, ids.data(), 4 * ids.size());
+    if (!parts.empty()) memcpy(h_stage + L.o_parts, parts.data(), sizeof(KwPart) * parts.size());
     auto* cand = reinterpret_cast<uint64_t*>(h_stage + L.o_cand);
     for (size_t q = 0; q < qs.size(); ++q) cand[q] = qs[q].slot0;
     cand[qs.size()] = L.S;
@@ -278,14 +337,14 @@ extern "C" rg_status roaring_multi(rg_ctx* c, int op, const rg_pool* pool, const
     // per-id metadata -> host bounds (one small readback)
     Scratch sc(c);
     void* mbase = nullptr;
-    if (rg_status s = sc.take(WS_PAIRS, align256(24 * k) + 256, &mbase)) return s;
+    if (rg_status s = sc.take(WS_PAIRS, align256(32 * k) + 256, &mbase)) return s;
     auto* d_meta = reinterpret_cast<uint64_t*>(mbase);
-    auto* h_meta = reinterpret_cast<uint64_t*>(c->host);  // 24 k <= 6 KiB: the pinned staging
-    launch_kw_gather_meta(pool->bm_begin, pool->bm_wbytes, pool->n_bitmaps, d_ids, k, d_meta, st);
-    HIPCHK(c, hipMemcpyAsync(h_meta, d_meta, 24 * k, hipMemcpyDeviceToHost, st));
+    auto* h_meta = reinterpret_cast<uint64_t*>(c->host);  // 32 k <= 8 KiB: the pinned staging
+    launch_kw_gather_meta(pool->bm_begin, pool->keys, pool->bm_wbytes, pool->n_bitmaps, d_ids, k, d_meta, st);
+    HIPCHK(c, hipMemcpyAsync(h_meta, d_meta, 32 * k, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     for (uint32_t j = 0; j < k; ++j)
-        if (!h_meta[3 * j + 2]) return fail(c, RG_EINVAL, "roaring_multi: bitmap id out of range of the pool");
+        if (!h_meta[4 * j + 2]) return fail(c, RG_EINVAL, "roaring_multi: bitmap id out of range of the pool");
     const Bounds b = query_bounds(op, k, h_meta, mat);
     if (mat) {
         out->needed_containers = b.kbound;
@@ -297,8 +356,13 @@ extern "C" rg_status roaring_multi(rg_ctx* c, int op, const rg_pool* pool, const
     }
     std::vector<KwQuery> qs(1);
     qs[0] = KwQuery{(uint32_t)op, k, 0, mat ? KW_MATERIALIZE : 0u, 0, (uint32_t)b.kbound, 0};
+    std::vector<KwPart> parts;
+    uint32_t n_masks = 0;
+    split_query(&qs[0], 0, h_meta, 4, &parts, &n_masks);  // before h_meta's staging is reused
     StepLayout L;
     L.plan(1, k, b.kbound, mat ? b.pbound : 0, !mat);
+    L.n_parts = (uint32_t)parts.size();
+    L.n_masks = n_masks;
     void* wbase = nullptr;
     if (rg_status s = sc.take(WS_WAVE, L.total, &wbase)) return s;
     uint8_t* h = nullptr;
@@ -308,6 +372,7 @@ extern "C" rg_status roaring_multi(rg_ctx* c, int op, const rg_pool* pool, const
     HIPCHK(c, hipMemcpyAsync(h + L.o_ids, d_ids, 4ull * k, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     memcpy(h + L.o_queries, qs.data(), sizeof(KwQuery));
+    if (!parts.empty()) memcpy(h + L.o_parts, parts.data(), sizeof(KwPart) * parts.size());
     reinterpret_cast<uint64_t*>(h + L.o_cand)[0] = 0;
     reinterpret_cast<uint64_t*>(h + L.o_cand)[1] = L.S;
     StepOut o = mat ? StepOut{out->bm_begin, out->keys, out->types, out->card, out->size, out->off, out->payload,
@@ -411,6 +476,7 @@ struct rg_server {
     rg_ctx* c = nullptr;
     rg_pool pool{};
     std::vector<uint64_t> h_bm_begin, h_wbytes;
+    std::vector<uint32_t> h_span;  // first key | last key << 16 of every bitmap (with keys)
     uint8_t* arena = nullptr;
     ArenaAlloc alloc;
     uint32_t max_batch = 64, max_inflight = 2;
@@ -544,6 +610,9 @@ void rg_server::run() {
                     s->live = (uint32_t)take.size();
                     std::vector<KwQuery> qs;
                     std::vector<uint32_t> ids;
+                    std::vector<KwPart> parts;
+                    std::vector<uint64_t> nk;
+                    uint32_t n_masks = 0;
                     uint64_t slot = 0;
                     bool digest = false;
                     for (uint32_t i = 0; i < take.size(); ++i) {
@@ -554,11 +623,16 @@ void rg_server::run() {
                         qs.push_back(KwQuery{(uint32_t)e.q.op, e.q.k, (uint32_t)ids.size(),
                                              (e.q.flags & RG_FLAG_MATERIALIZE) ? KW_MATERIALIZE : 0u, slot,
                                              (uint32_t)e.b.kbound, 0});
+                        nk.resize(e.q.k);
+                        for (uint32_t j = 0; j < e.q.k; ++j) nk[j] = h_bm_begin[e.ids[j] + 1] - h_bm_begin[e.ids[j]];
+                        split_query(&qs.back(), i, nk.data(), 1, &parts, &n_masks);
                         ids.insert(ids.end(), e.ids.begin(), e.ids.end());
                         slot += e.b.kbound;
                     }
                     pending.erase(pending.begin(), pending.begin() + take.size());
-                    stage_upload(s->L, s->h, qs, ids);
+                    s->L.n_parts = (uint32_t)parts.size();
+                    s->L.n_masks = n_masks;
+                    stage_upload(s->L, s->h, qs, ids, parts);
                     ++n_steps;
                     sum_batch += take.size();
                     lk.unlock();
@@ -604,6 +678,7 @@ rg_status rg_serve_start(rg_ctx* c, const rg_pool* pool, uint64_t arena_bytes, u
     s->max_inflight = max_inflight;
     s->h_bm_begin.resize(pool->n_bitmaps + 1);
     s->h_wbytes.resize(std::max<uint32_t>(pool->n_bitmaps, 1));
+    s->h_span.resize(std::max<uint32_t>(pool->n_bitmaps, 1));
     auto cleanup = [&](rg_status st, const char* m) {
         for (uint8_t* p : s->pinned_free) (void)hipHostFree(p);
         if (s->arena) (void)hipFree(s->arena);
@@ -617,6 +692,16 @@ rg_status rg_serve_start(rg_ctx* c, const rg_pool* pool, uint64_t arena_bytes, u
         (pool->n_bitmaps && hipMemcpy(s->h_wbytes.data(), pool->bm_wbytes, 8ull * pool->n_bitmaps,
                                       hipMemcpyDeviceToHost) != hipSuccess))
         return cleanup(RG_EDEVICE, "rg_serve_start: pool metadata readback failed");
+    if (pool->n_bitmaps) {
+        void* d_span = nullptr;
+        if (hipMalloc(&d_span, 4ull * pool->n_bitmaps) != hipSuccess)
+            return cleanup(RG_EDEVICE, "rg_serve_start: key span buffer");
+        launch_kw_key_span(pool->bm_begin, pool->keys, pool->n_bitmaps, reinterpret_cast<uint32_t*>(d_span), nullptr);
+        const bool ok = hipMemcpy(s->h_span.data(), d_span, 4ull * pool->n_bitmaps, hipMemcpyDeviceToHost) ==
+                        hipSuccess;
+        (void)hipFree(d_span);
+        if (!ok) return cleanup(RG_EDEVICE, "rg_serve_start: key span readback failed");
+    }
     if (hipMalloc(&s->arena, arena_bytes) != hipSuccess) return cleanup(RG_EDEVICE, "rg_serve_start: arena");
     s->alloc.reset(arena_bytes);
     for (auto& x : s->streams)
@@ -644,12 +729,13 @@ rg_status rg_serve_submit(rg_server* s, const rg_query* q, uint64_t arrival_ns, 
     e->q = *q;
     e->ids.assign(q->ids, q->ids + q->k);
     e->q.ids = nullptr;
-    std::vector<uint64_t> meta(3 * q->k);
+    std::vector<uint64_t> meta(4 * q->k);
     for (uint32_t j = 0; j < q->k; ++j) {
         const uint32_t b = e->ids[j];
-        meta[3 * j] = s->h_bm_begin[b + 1] - s->h_bm_begin[b];
-        meta[3 * j + 1] = s->h_wbytes[b];
-        meta[3 * j + 2] = 1;
+        meta[4 * j] = s->h_bm_begin[b + 1] - s->h_bm_begin[b];
+        meta[4 * j + 1] = s->h_wbytes[b];
+        meta[4 * j + 2] = 1;
+        meta[4 * j + 3] = s->h_span[b];
     }
     e->b = query_bounds(q->op, q->k, meta.data(), q->flags & RG_FLAG_MATERIALIZE);
     e->arrival_ns = arrival_ns ? arrival_ns : now_ns();

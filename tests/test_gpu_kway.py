@@ -254,3 +254,67 @@ def test_server_all_ops_while_context_busy(rg, ctx):
     finally:
         st = srv.stop()
     _say(f"[serve all ops, busy context] {st}")
+
+
+def span_sets():
+    """Bitmaps built to exercise the key bounds (first and last key of each
+    bitmap: intersections of overlapping, disjoint and empty key ranges, unions
+    reaching key 65535) and the split key passes (unions of more than 4096 keys,
+    intersections of more than four bitmaps)."""
+    rng = np.random.default_rng(31)
+
+    def over(keys, per_key):
+        keys = np.asarray(keys, np.uint32)
+        lows = rng.integers(0, 65536, (len(keys), per_key)).astype(np.uint32)
+        return np.unique(((keys[:, None] << np.uint32(16)) | lows).ravel())
+
+    sets = [
+        over(np.arange(10, 21), 300),         # 0: keys 10..20
+        over(np.arange(15, 31), 5000),        # 1: keys 15..30 (bitsets)
+        over(np.arange(40, 51), 50),          # 2: keys 40..50
+        np.zeros(0, np.uint32),               # 3: empty
+        over(np.arange(65530, 65536), 20),    # 4: keys 65530..65535
+        over(np.arange(0, 6), 20),            # 5: keys 0..5
+    ]
+    # 6..11: 3000 keys each, one to three values per key, sharing half their keys
+    common = rng.choice(65536, 1500, replace=False)
+    for i in range(6):
+        own = rng.choice(65536, 1500, replace=False)
+        sets.append(np.unique(np.concatenate([over(common, 1 + i % 3), over(own, 1)])))
+    return synth.BitmapSet.from_list(sets)
+
+
+def test_multi_key_spans_and_split_passes(rg, ctx):
+    import torch
+
+    bs = span_sets()
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    u = lambda *ids: np.array(ids, np.uint32)
+    big = np.arange(6, 12, dtype=np.uint32)
+    qs = [
+        ("and", u(0, 1, 1)), ("and", u(0, 2, 1)), ("and", u(0, 3, 1)), ("and", u(1, 0, 1, 0, 1)),
+        ("or", u(4, 5, 0)), ("xor", u(4, 5, 4)), ("or", u(3, 3, 3)), ("or", u(3, 4, 3)),
+        ("or", big), ("xor", np.concatenate([big, big[:1]])), ("and", np.concatenate([big, big[:2]])),
+        ("and", np.concatenate([big, big[:3]])), ("andnot", u(6, 7, 8)), ("and", np.resize(big, 256)),
+        ("or", np.resize(np.arange(12, dtype=np.uint32), 256)), ("xor", np.resize(big, 255)),
+    ]
+    for op, ids in qs:
+        _say(f"[spans] op={op} k={len(ids)}")
+        exp = oracle.kway(op, [bs[int(i)] for i in ids])
+        tids = torch.from_numpy(ids.view(np.int32)).cuda()
+        out, card = rg.multi(ctx, op, P, tids, materialize=True, card=True)
+        torch.cuda.synchronize()
+        assert int(card[0].item()) == len(exp), (op, ids)
+        h = out.as_pool().to_host()
+        got, meta = rgtest.decode_bitmap(h, 0)
+        assert np.array_equal(got, exp), (op, ids)
+        assert meta == rgtest.oracle_meta(oracle, exp), (op, ids)
+    # the same queries through the server, batched (several split queries per step)
+    sq = [(op, ids, i % 3 != 2) for i, (op, ids) in enumerate(qs)]
+    exp = _expect(bs, sq)
+    srv = rg.Server(ctx, P, arena_bytes=256 << 20, max_batch=8, max_inflight=2)
+    _, cards, dig = srv.replay(sq, np.zeros(len(sq), np.uint64), digest=True)
+    st = srv.stop()
+    _say(f"[spans serve] {st}")
+    for i, (c, d) in enumerate(exp):
+        assert cards[i] == c and dig[i] == d, i
