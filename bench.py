@@ -65,7 +65,10 @@ def main():
                          "queries under Poisson arrivals, batched server vs one query at a time")
     ap.add_argument("--array-pairs", type=int, default=100000, help="array: pairs")
     ap.add_argument("--index", type=int, default=100000, help="serve: bitmaps in the index")
-    ap.add_argument("--rates", default="2000,5000,10000,20000,50000", help="serve: arrival rates (queries/s)")
+    ap.add_argument("--rates", default="2000,5000,10000,20000,50000,100000,200000",
+                    help="serve: arrival rates (queries/s)")
+    ap.add_argument("--one-max-rate", type=float, default=50000,
+                    help="serve: highest rate also run one query at a time (it saturates far below)")
     ap.add_argument("--duration", type=float, default=2.0, help="serve: seconds of arrivals per rate")
     ap.add_argument("--max-batch", type=int, default=256, help="serve: most queries per step (batched mode)")
     ap.add_argument("--pool", type=int, default=16384, help="batched: bitmaps in the pool")
@@ -74,6 +77,8 @@ def main():
     ap.add_argument("--dispatch-pairs", type=int, default=300, help="batched: pairs whose costs train the dispatcher")
     ap.add_argument("--dispatch-epochs", type=int, default=10, help="batched: dispatcher training epochs")
     ap.add_argument("--wide", type=int, default=200, help="wide: bitmaps in the union")
+    ap.add_argument("--key-index", type=int, default=1, choices=(0, 1),
+                    help="serve, wide: the pool carries key-presence indexes (built once, before timing)")
     ap.add_argument("--access-bitmaps", type=int, default=1000, help="access: bitmaps in the pool")
     ap.add_argument("--lookups", type=int, default=10000000, help="access: membership lookups per step")
     ap.add_argument("--canon-bitmaps", type=int, default=1000, help="canonical: bitmaps in the pool")
@@ -917,8 +922,11 @@ def bench_serve(args):
     32-key hot set), cardinality lognormal (median 5e4, sigma 1, clipped to
     [1e3, 1e6]). Mix: 40 % k-AND, 40 % k-OR (both materialised), 20 %
     count-only (half AND, half OR); k uniform in 2..32; ids uniform without
-    replacement. Each rate runs twice: the continuous-batching server (up to
-    --max-batch queries per step, two steps in flight) and one query at a time."""
+    replacement. Each rate runs the continuous-batching server (up to
+    --max-batch queries per step, two steps in flight) and, up to
+    --one-max-rate, one query at a time. Achieved rate = queries / the server's
+    span (replay start to the last completion; the client's marshalling of the
+    query list is outside it)."""
     import numpy as np
     import torch
 
@@ -933,9 +941,16 @@ def bench_serve(args):
     h = build_pool_threaded(gen, args.index)
     P = rg.Pool.from_host_arrays(h)
     torch.cuda.synchronize()
+    kidx_ms = None
+    if args.key_index:
+        t1 = time.time()
+        P.key_index(ctx)
+        torch.cuda.synchronize()
+        kidx_ms = (time.time() - t1) * 1e3
     n_values = int(h["bm_card"].sum())
     say(f"index of {args.index} bitmaps, {n_values} values, {P.c.n_containers} containers, "
-        f"{len(h['payload']) / 1e9:.1f} GB payload, built in {time.time() - t0:.1f} s")
+        f"{len(h['payload']) / 1e9:.1f} GB payload, built in {time.time() - t0:.1f} s"
+        + (f" (key-presence indexes {kidx_ms:.1f} ms)" if args.key_index else ""))
     rng = np.random.default_rng(seed)
 
     def make_queries(n):
@@ -969,12 +984,14 @@ def bench_serve(args):
         gaps = rng.exponential(1.0 / lam, n)
         arrival = (np.cumsum(gaps) * 1e9).astype(np.uint64)
         row = {"rate_qps": lam, "queries": n}
-        for mode, mb, mi in (("batched", args.max_batch, 2), ("one_at_a_time", 1, 1)):
+        modes = [("batched", args.max_batch, 2)] + ([("one_at_a_time", 1, 1)] if lam <= args.one_max_rate else [])
+        for mode, mb, mi in modes:
             srv = rg.Server(ctx, P, arena_bytes=4 << 30, max_batch=mb, max_inflight=mi)
-            t = time.perf_counter()
             # served as a client would: cardinalities and result views, no fingerprints
             lat, c, _ = srv.replay(qs, arrival)
-            wall = time.perf_counter() - t
+            # the server's span: from the replay's start (arrival offsets count
+            # from it) to the last completion, arrival + latency
+            wall = float((arrival + lat).max()) / 1e9
             st = srv.stop()
             if mode == "batched":
                 ref = c
@@ -999,8 +1016,9 @@ def bench_serve(args):
         "config": {"workload": f"serving: index of {args.index} mixed bitmaps over [0, 2^26) (lognormal card, median "
                                f"5e4, sigma 1), Poisson arrivals, 40% k-AND / 40% k-OR materialised, 20% "
                                f"count-only, k in 2..32", "index": args.index, "duration_s": args.duration,
-                   "parallelism": "single GPU"},
+                   "key_index": bool(args.key_index), "parallelism": "single GPU"},
         "index_values": n_values, "index_containers": int(P.c.n_containers),
+        "key_index_build_ms": None if kidx_ms is None else round(kidx_ms, 2),
         "rates": rows,
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -1129,6 +1147,18 @@ def bench_wide(args):
     def step_count():
         ctx.check(rg.roaring_multi(ctx, "or", P, ids, rg.RG_FLAG_CARD, None, card))
 
+    # without, then with the pool's key-presence indexes (built once)
+    dt_plain = time_steps(step, args.steps, args.warmup)
+    kidx_ms = None
+    if args.key_index:
+        t1 = time.time()
+        P.key_index(ctx)
+        torch.cuda.synchronize()
+        kidx_ms = (time.time() - t1) * 1e3
+        ctx.check(rg.roaring_multi(ctx, "or", P, ids, flags, out, card))
+        torch.cuda.synchronize()
+        dig2 = int(rg.rg_pool_digest(ctx, out.as_pool()).cpu().numpy().view(np.uint64)[0])
+        assert int(card.item()) == len(exp) and dig2 == dig, "wide union with key indexes differs"
     dt = time_steps(step, args.steps, args.warmup)
     dtc = time_steps(step_count, args.steps, args.warmup)
     rg.profile_enable(ctx, True)
@@ -1156,8 +1186,10 @@ def bench_wide(args):
           dt * 1e3,
           {"workload": f"wide union: {k} mixed bitmaps over [0, 2^26), 1e3..5e4 values, 40/30/30 sparse/dense/run; "
                        f"one {k}-way OR materialised with its cardinality", "k": k,
-           "parallelism": "single GPU"},
+           "key_index": bool(args.key_index), "parallelism": "single GPU"},
           {"union_values": len(exp), "result_containers": out_n, "count_only_ms": round(dtc * 1e3, 4),
+           "no_key_index_ms": round(dt_plain * 1e3, 4),
+           "key_index_build_ms": None if kidx_ms is None else round(kidx_ms, 2),
            "input_bytes": int(in_bytes)}, roof, cpu)
 
 

@@ -441,6 +441,7 @@ constexpr uint32_t KW_SPLIT = 2u;
 constexpr uint32_t KW_MAX_K = 256;       // bitmaps per query (one lookup thread each)
 constexpr uint32_t KW_AND_GROUP = 4;     // bitmaps whose key masks an intersection fills at once
 constexpr uint32_t KW_PART_KEYS = 4096;  // keys per part of a split union or symmetric difference
+constexpr uint32_t KW_PART_BITMAPS = 16; // bitmaps per part of a split key pass from presence indexes
 // One part of a split key pass: the query's bitmaps j0 .. j1-1.
 struct KwPart {
     uint32_t q;     // query index

@@ -33,9 +33,21 @@ constexpr int KW_UNROLL = 4;  // independent loads in flight per thread in the k
 constexpr uint32_t KW_BS_BATCH = 8;    // bitset containers whose words a fold loads at once
 constexpr uint32_t KW_EVAL_CHUNK = 4;  // slots whose tasks the evaluation workgroup reads at once (measured: 1, 4, 16)
 
-__device__ __forceinline__ uint32_t kw_find_key(const uint64_t* bm_begin, const uint16_t* keys, uint32_t b,
-                                                uint16_t key) {
+// The container of `key` in bitmap b (its global index), or NONE. With the
+// pool's key-presence index: the presence bit, then the word's rank plus the
+// popcount of the bits below (two independent loads); otherwise a binary
+// search of the bitmap's keys.
+__device__ __forceinline__ uint32_t kw_find_key(const uint64_t* bm_begin, const uint16_t* keys, const uint8_t* kidx,
+                                                uint32_t b, uint16_t key) {
     const uint64_t s = bm_begin[b], e = bm_begin[b + 1];
+    if (kidx) {
+        const uint8_t* ix = kidx + (uint64_t)b * RG_KEY_INDEX_BYTES;
+        const uint32_t wi = key >> 6, bit = key & 63u;
+        const uint64_t x = reinterpret_cast<const uint64_t*>(ix)[wi];
+        const uint32_t rank = reinterpret_cast<const uint16_t*>(ix + 8 * KIDX_WORDS)[wi];
+        if (!((x >> bit) & 1ull)) return NONE;
+        return (uint32_t)(s + rank + (uint32_t)__popcll(x & ((1ull << bit) - 1ull)));
+    }
     uint64_t lo = s, hi = e;
     while (lo < hi) {
         const uint64_t mid = (lo + hi) >> 1;
@@ -59,6 +71,7 @@ __device__ __forceinline__ PoolView kw_side(const KwArgs& a, bool second) {
     v.bm_card = second ? a.P1.bm_card : a.P0.bm_card;
     v.bm_wbytes = second ? a.P1.bm_wbytes : a.P0.bm_wbytes;
     v.meta = second ? a.P1.meta : a.P0.meta;
+    v.kidx = second ? a.P1.kidx : a.P0.kidx;
     return v;
 }
 
@@ -239,23 +252,80 @@ __device__ void kw_fill_keys(const KwArgs& a, const uint64_t* rs, const uint32_t
     __syncthreads();
 }
 
-// Writes query q's result keys (the set bits of acc, ascending; thread t owns
-// words 4t..4t+3) as one task per key into its slot range, and no-op tasks into
-// the rest of the range. indexed (at most two bitmaps): acc and cur are the two
-// bitmaps' key masks, and each task records the positions of its containers.
+// Key masks straight from the pools' key-presence indexes (1024 presence
+// words per bitmap, the key set as a bitset): thread t gets words 4t..4t+3 of
+// the AND (and_) or the OR of the presence words of the query's bitmaps
+// j0 .. j1-1, KW_BS_BATCH bitmaps' words in flight at a time.
+__device__ void kw_pres_words(const KwArgs& a, uint32_t ids0, uint32_t j0, uint32_t j1, bool and_,
+                              uint64_t (&r)[4]) {
+    const uint32_t tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = and_ ? ~0ull : 0ull;
+    for (uint32_t b0 = j0; b0 < j1; b0 += KW_BS_BATCH) {
+        u32x4 v0[KW_BS_BATCH], v1[KW_BS_BATCH];
+#pragma unroll
+        for (uint32_t u = 0; u < KW_BS_BATCH; ++u) {
+            const uint32_t j = b0 + u;
+            if (j < j1) {
+                const uint8_t* ix = (j ? a.P1.kidx : a.P0.kidx) + (uint64_t)a.ids[ids0 + j] * RG_KEY_INDEX_BYTES;
+                const u32x4* src = reinterpret_cast<const u32x4*>(ix) + 2 * tid;
+                v0[u] = src[0];
+                v1[u] = src[1];
+            }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < KW_BS_BATCH; ++u) {
+            if (b0 + u < j1) {
+                const uint64_t x[4] = {(uint64_t)v0[u].x | ((uint64_t)v0[u].y << 32),
+                                       (uint64_t)v0[u].z | ((uint64_t)v0[u].w << 32),
+                                       (uint64_t)v1[u].x | ((uint64_t)v1[u].y << 32),
+                                       (uint64_t)v1[u].z | ((uint64_t)v1[u].w << 32)};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) r[q] = and_ ? (r[q] & x[q]) : (r[q] | x[q]);
+            }
+        }
+    }
+}
+
+// Position of the r-th set bit (r < popcount) of x.
+__device__ __forceinline__ uint32_t kw_select_bit(uint64_t x, uint32_t r) {
+    uint32_t bit = 0;
+#pragma unroll
+    for (uint32_t w = 32; w >= 1; w >>= 1) {
+        const uint32_t c = (uint32_t)__popcll(x & ((1ull << w) - 1ull));
+        if (r >= c) {
+            r -= c;
+            x >>= w;
+            bit += w;
+        }
+    }
+    return bit;
+}
+
+// Writes query q's result keys (the set bits of the result words, ascending)
+// as one task per key into its slot range, and no-op tasks into the rest of the
+// range. The result words: acc, or with at most two bitmaps (indexed) the
+// combination of the two bitmaps' key masks acc and cur, and then each task
+// also records the positions of its containers. Keys are handed out by rank,
+// not by word: the per-word prefix counts go to LDS (wp: 3 x 1024 entries),
+// and thread t builds the tasks of ranks t, t + 256, ... (a binary search of
+// the prefixes, then the rank's bit in its word), so a key set packed into a
+// few words is spread over the whole workgroup.
 __device__ void kw_emit_tasks(const KwArgs& a, uint32_t q, uint32_t op, uint32_t k, uint64_t slot0, uint32_t kbound,
                               const uint64_t* acc, const uint64_t* cur, const uint64_t* rs, bool indexed,
-                              uint32_t* tmp) {
+                              uint32_t* tmp, uint16_t* wp) {
     const uint32_t tid = threadIdx.x;
+    const bool two = indexed && k == 2;
+    auto result_word = [&](uint64_t m0, uint64_t m1) {
+        return !indexed || k == 1 ? m0 : op == RG_AND ? (m0 & m1) : op == RG_ANDNOT ? m0 : (m0 | m1);
+    };
     uint64_t w[4], m0[4], m1[4];
     uint32_t c = 0, c0 = 0, c1 = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         m0[j] = acc[4 * tid + j];
-        m1[j] = indexed && k == 2 ? cur[4 * tid + j] : 0ull;
-        w[j] = !indexed ? m0[j]
-               : k == 1 ? m0[j]
-               : op == RG_AND ? (m0[j] & m1[j]) : op == RG_ANDNOT ? m0[j] : (m0[j] | m1[j]);
+        m1[j] = two ? cur[4 * tid + j] : 0ull;
+        w[j] = result_word(m0[j], m1[j]);
         c += __popcll(w[j]);
         c0 += __popcll(m0[j]);
         c1 += __popcll(m1[j]);
@@ -268,37 +338,47 @@ __device__ void kw_emit_tasks(const KwArgs& a, uint32_t q, uint32_t op, uint32_t
         r0 = block_excl_scan_u32(c0, tmp, &unused);
         r1 = block_excl_scan_u32(c1, tmp, &unused);
     }
-    // total <= kbound holds by construction of the host bound; guard anyway
+    // per-word exclusive prefixes (at most 65 472: the prefix of the last word)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        uint64_t x = w[j];
-        while (x) {
-            const uint32_t b = (uint32_t)__builtin_ctzll(x);
-            const uint32_t key = (4 * tid + j) * 64 + b;
-            x &= x - 1;
-            if (pos < kbound) {
-                Task t;
-                t.pair = a.pair_base + q;
-                t.ia = NONE;
-                t.ib = NONE;
-                t.key = (uint16_t)key;
-                t.kind = KIND_MATCH;
-                t.bin = 0;
-                if (indexed) {
-                    // container index = list start + number of the bitmap's keys below this one
-                    const uint64_t below = (1ull << b) - 1ull;
-                    if ((m0[j] >> b) & 1ull) t.ia = (uint32_t)(rs[0] + r0 + __popcll(m0[j] & below));
-                    if ((m1[j] >> b) & 1ull) t.ib = (uint32_t)(rs[1] + r1 + __popcll(m1[j] & below));
-                    t.bin = KW_TASK_INDEXED;
-                }
-                a.tasks[slot0 + pos] = t;
-            }
-            ++pos;
+        wp[4 * tid + j] = (uint16_t)pos;
+        pos += __popcll(w[j]);
+        if (indexed) {
+            wp[1024 + 4 * tid + j] = (uint16_t)r0;
+            wp[2048 + 4 * tid + j] = (uint16_t)r1;
+            r0 += __popcll(m0[j]);
+            r1 += __popcll(m1[j]);
         }
-        r0 += __popcll(m0[j]);
-        r1 += __popcll(m1[j]);
     }
+    __syncthreads();
+    // total <= kbound holds by construction of the host bound; guard anyway
     const uint32_t used = total < kbound ? total : kbound;
+    for (uint32_t p = tid; p < used; p += 256) {
+        // the last word whose prefix is <= p holds rank p
+        uint32_t lo = 0, hi = 1024;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (wp[mid] <= p) lo = mid;
+            else hi = mid;
+        }
+        const uint64_t x0 = acc[lo], x1 = two ? cur[lo] : 0ull;
+        const uint32_t b = kw_select_bit(result_word(x0, x1), p - wp[lo]);
+        Task t;
+        t.pair = a.pair_base + q;
+        t.ia = NONE;
+        t.ib = NONE;
+        t.key = (uint16_t)(lo * 64 + b);
+        t.kind = KIND_MATCH;
+        t.bin = 0;
+        if (indexed) {
+            // container index = list start + number of the bitmap's keys below this one
+            const uint64_t below = (1ull << b) - 1ull;
+            if ((x0 >> b) & 1ull) t.ia = (uint32_t)(rs[0] + wp[1024 + lo] + __popcll(x0 & below));
+            if ((x1 >> b) & 1ull) t.ib = (uint32_t)(rs[1] + wp[2048 + lo] + __popcll(x1 & below));
+            t.bin = KW_TASK_INDEXED;
+        }
+        a.tasks[slot0 + p] = t;
+    }
     for (uint32_t i = used + tid; i < kbound; i += 256) {
         Task t;
         t.pair = a.pair_base + q;
@@ -321,6 +401,7 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a, uint32_t chunk) {
     __shared__ uint64_t rs[KW_MAX_K];  // key-list start of each of the query's bitmaps
     __shared__ uint32_t rn[KW_MAX_K];  // and its length
     __shared__ uint32_t roff[KW_MAX_K + 1];  // exclusive prefix of the lengths (union pass)
+    __shared__ uint16_t wpre[3 * 1024];      // per-word key prefixes (task output)
     __shared__ uint32_t chunk_mask;
     // chunks of `chunk` queries: whether each is the workgroup kernel's (more
     // than two bitmaps, or more than KW_KEYS_SMALL keys) is read for the whole
@@ -362,7 +443,8 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a, uint32_t chunk) {
     // With at most two bitmaps each result key's containers are recorded in its
     // task (positions from the two key masks), so the later kernels need no search.
     const bool indexed = k <= 2;
-    for (uint32_t j = tid; j < (indexed ? k : kk); j += 256) {
+    const bool pres = a.P0.kidx != nullptr && a.P1.kidx != nullptr;  // key masks from presence indexes
+    for (uint32_t j = tid; (indexed || !pres) && j < (indexed ? k : kk); j += 256) {
         const uint64_t* bmb = j ? a.P1.bm_begin : a.P0.bm_begin;
         const uint32_t b = a.ids[ids0 + j];
         const uint64_t s0 = bmb[b];
@@ -371,7 +453,20 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a, uint32_t chunk) {
     }
     __syncthreads();
     // result keys: AND - in every bitmap; OR, XOR - in any; ANDNOT - the first bitmap's
-    if (indexed) {
+    if (pres) {
+        // the key masks are the presence words: acc = bitmap 0 and cur =
+        // bitmap 1 (at most two bitmaps), else the combination of the deciding ones
+        uint64_t r[4];
+        kw_pres_words(a, ids0, 0, indexed ? 1u : kk, op == RG_AND, r);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[4 * tid + q] = r[q];
+        if (indexed && k == 2) {
+            kw_pres_words(a, ids0, 1, 2, false, r);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cur[4 * tid + q] = r[q];
+        }
+        __syncthreads();
+    } else if (indexed) {
         // the key masks of both bitmaps, side by side: acc = bitmap 0, cur = bitmap 1
         for (uint32_t i = tid; i < 1024; i += 256) cur[i] = 0;
         __syncthreads();
@@ -415,7 +510,7 @@ __global__ void __launch_bounds__(256) k_kw_keys(KwArgs a, uint32_t chunk) {
             __syncthreads();
         }
     }
-    kw_emit_tasks(a, q, op, k, slot0, kbound, acc, cur, rs, indexed, tmp);
+    kw_emit_tasks(a, q, op, k, slot0, kbound, acc, cur, rs, indexed, tmp, wpre);
     __syncthreads();  // LDS read before the next query's pass
     }
     }
@@ -436,6 +531,7 @@ __global__ void __launch_bounds__(256) k_kw_keys_part(KwArgs a) {
     __shared__ uint64_t rs[KW_MAX_K];
     __shared__ uint32_t rn[KW_MAX_K];
     __shared__ uint32_t roff[KW_MAX_K + 1];
+    __shared__ uint16_t wpre[3 * 1024];
     __shared__ uint32_t last;
     const uint32_t tid = threadIdx.x;
     for (uint32_t p = blockIdx.x; p < a.n_parts; p += gridDim.x) {
@@ -445,14 +541,16 @@ __global__ void __launch_bounds__(256) k_kw_keys_part(KwArgs a) {
         const KwQuery Q = a.queries[q];
         const uint32_t op = uniform(Q.op), k = uniform(Q.k), ids0 = uniform(Q.ids_off);
         uint32_t j1 = uniform(P.j01 >> 16);
-        // parts come from the host within these limits; a part outside them
-        // is cut to them (memory-safe) and reported
-        if (j1 > k || j0 >= j1 || (op == RG_AND && j1 - j0 > KW_AND_GROUP)) {
+        const bool pres = a.P0.kidx != nullptr && a.P1.kidx != nullptr;
+        // parts come from the host within these limits (an intersection part
+        // without presence indexes: one LDS mask per bitmap); a part outside
+        // them is cut to them (memory-safe) and reported
+        if (j1 > k || j0 >= j1 || (!pres && op == RG_AND && j1 - j0 > KW_AND_GROUP)) {
             if (tid == 0) atomicOr(a.err, 1u);
             j1 = j1 > k ? k : j1;
-            j1 = op == RG_AND && j1 > j0 + KW_AND_GROUP ? j0 + KW_AND_GROUP : j1;
+            j1 = !pres && op == RG_AND && j1 > j0 + KW_AND_GROUP ? j0 + KW_AND_GROUP : j1;
         }
-        for (uint32_t j = j0 + tid; j < j1; j += 256) {
+        for (uint32_t j = j0 + tid; !pres && j < j1; j += 256) {
             const uint64_t* bmb = j ? a.P1.bm_begin : a.P0.bm_begin;
             const uint32_t b = a.ids[ids0 + j];
             const uint64_t s0 = bmb[b];
@@ -464,6 +562,12 @@ __global__ void __launch_bounds__(256) k_kw_keys_part(KwArgs a) {
         if (j0 >= j1) {
             // an empty part (only after a cut): adds no key, removes none
             for (uint32_t i = tid; i < 1024; i += 256) acc[i] = op == RG_AND ? ~0ull : 0ull;
+            __syncthreads();
+        } else if (pres) {
+            uint64_t r[4];
+            kw_pres_words(a, ids0, j0, j1, op == RG_AND, r);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[4 * tid + q] = r[q];
             __syncthreads();
         } else if (op != RG_AND) {
             kw_fill_keys(a, rs, rn, roff, j0, j1, accm, false);
@@ -495,7 +599,7 @@ __global__ void __launch_bounds__(256) k_kw_keys_part(KwArgs a) {
                 acc[i] = op == RG_AND ? ~x : x;
             }
             __syncthreads();
-            kw_emit_tasks(a, q, op, k, uniform64(Q.slot0), uniform(Q.kbound), acc, nullptr, rs, false, tmp);
+            kw_emit_tasks(a, q, op, k, uniform64(Q.slot0), uniform(Q.kbound), acc, nullptr, rs, false, tmp, wpre);
         }
         __syncthreads();  // LDS read before the next part
     }
@@ -535,7 +639,8 @@ __global__ void __launch_bounds__(256) k_kw_bounds(KwArgs a) {
                 if (j < k) {
                     const PoolView pv = kw_side(a, j != 0);
                     const uint32_t ci = t.bin == KW_TASK_INDEXED ? (j == 0 ? t.ia : t.ib)
-                                                                 : kw_find_key(pv.bm_begin, pv.keys, a.ids[ids0 + j], t.key);
+                                                                 : kw_find_key(pv.bm_begin, pv.keys, pv.kidx,
+                                                                               a.ids[ids0 + j], t.key);
                     cj = ci == NONE ? 0u : pv.card[ci];
                     if (ci != NONE && j0 == 0) {
                         ty = pv.types[ci];
@@ -660,7 +765,8 @@ __global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
             } else {
                 const uint64_t* bmb = tid ? a.P1.bm_begin : a.P0.bm_begin;
                 const uint16_t* pkeys = tid ? a.P1.keys : a.P0.keys;
-                cidx[tid] = kw_find_key(bmb, pkeys, a.ids[ids0 + tid], t.key);
+                const uint8_t* pidx = tid ? a.P1.kidx : a.P0.kidx;
+                cidx[tid] = kw_find_key(bmb, pkeys, pidx, a.ids[ids0 + tid], t.key);
             }
         }
         __syncthreads();

@@ -84,13 +84,14 @@ Bounds query_bounds(int op, uint32_t k, const uint64_t* meta, bool mat) {
 }
 
 // Splits the key pass of query q (record Q, key count of its j-th bitmap at
-// nkeys[j * stride]) into parts of whole bitmaps for k_kw_keys_part: a union
-// or symmetric difference in parts of about KW_PART_KEYS keys, an
-// intersection in groups of KW_AND_GROUP bitmaps. With two parts or more the
-// query is marked KW_SPLIT with key mask *n_masks (then counted) and its parts
-// are appended; otherwise nothing changes. A difference's keys are its first
-// bitmap's: never split.
-void split_query(KwQuery* Q, uint32_t q, const uint64_t* nkeys, size_t stride, std::vector<KwPart>* parts,
+// nkeys[j * stride]) into parts of whole bitmaps for k_kw_keys_part. With the
+// pool's key-presence index (pres) a part combines the presence words of up to
+// KW_PART_BITMAPS bitmaps; without it a union or symmetric difference is cut
+// into parts of about KW_PART_KEYS keys and an intersection into groups of
+// KW_AND_GROUP bitmaps. With two parts or more the query is marked KW_SPLIT
+// with key mask *n_masks (then counted) and its parts are appended; otherwise
+// nothing changes. A difference's keys are its first bitmap's: never split.
+void split_query(KwQuery* Q, uint32_t q, const uint64_t* nkeys, size_t stride, bool pres, std::vector<KwPart>* parts,
                  uint32_t* n_masks) {
     const uint32_t k = Q->k;
     if (k <= 2 || Q->op == RG_ANDNOT) return;
@@ -98,7 +99,9 @@ void split_query(KwQuery* Q, uint32_t q, const uint64_t* nkeys, size_t stride, s
     uint64_t acc = 0;
     for (uint32_t j = 0; j < k; ++j) {
         const uint64_t n = nkeys[j * stride];
-        const bool full = Q->op == RG_AND ? j - cut.back() == KW_AND_GROUP : acc > 0 && acc + n > KW_PART_KEYS;
+        const bool full = pres              ? j - cut.back() == KW_PART_BITMAPS
+                          : Q->op == RG_AND ? j - cut.back() == KW_AND_GROUP
+                                            : acc > 0 && acc + n > KW_PART_KEYS;
         if (full) {
             cut.push_back(j);
             acc = 0;
@@ -358,7 +361,7 @@ extern "C" rg_status roaring_multi(rg_ctx* c, int op, const rg_pool* pool, const
     qs[0] = KwQuery{(uint32_t)op, k, 0, mat ? KW_MATERIALIZE : 0u, 0, (uint32_t)b.kbound, 0};
     std::vector<KwPart> parts;
     uint32_t n_masks = 0;
-    split_query(&qs[0], 0, h_meta, 4, &parts, &n_masks);  // before h_meta's staging is reused
+    split_query(&qs[0], 0, h_meta, 4, pool->key_index != nullptr, &parts, &n_masks);  // before h_meta's staging is reused
     StepLayout L;
     L.plan(1, k, b.kbound, mat ? b.pbound : 0, !mat);
     L.n_parts = (uint32_t)parts.size();
@@ -625,7 +628,7 @@ void rg_server::run() {
                                              (uint32_t)e.b.kbound, 0});
                         nk.resize(e.q.k);
                         for (uint32_t j = 0; j < e.q.k; ++j) nk[j] = h_bm_begin[e.ids[j] + 1] - h_bm_begin[e.ids[j]];
-                        split_query(&qs.back(), i, nk.data(), 1, &parts, &n_masks);
+                        split_query(&qs.back(), i, nk.data(), 1, pool.key_index != nullptr, &parts, &n_masks);
                         ids.insert(ids.end(), e.ids.begin(), e.ids.end());
                         slot += e.b.kbound;
                     }

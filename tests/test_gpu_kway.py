@@ -70,12 +70,15 @@ def _workload(which):
     return synth.mixed_small(n_bitmaps=30)
 
 
+@pytest.mark.parametrize("kidx", [False, True], ids=["search", "key-index"])
 @pytest.mark.parametrize("which", ["overlapping", "edges", "mixed"])
-def test_multi_matches_oracle(rg, ctx, which):
+def test_multi_matches_oracle(rg, ctx, which, kidx):
     import torch
 
     bs = _workload(which)
     P = rg.Pool.from_sets(bs.values, bs.offsets)
+    if kidx:
+        P.key_index(ctx)
     qs = _queries(len(bs), 16, seed=11)
     # symmetric difference (parity of k) and difference (first minus the others)
     qs += _queries(len(bs), 8, seed=12, kmax=5, ops=("xor", "andnot"))
@@ -284,11 +287,14 @@ def span_sets():
     return synth.BitmapSet.from_list(sets)
 
 
-def test_multi_key_spans_and_split_passes(rg, ctx):
+@pytest.mark.parametrize("kidx", [False, True], ids=["search", "key-index"])
+def test_multi_key_spans_and_split_passes(rg, ctx, kidx):
     import torch
 
     bs = span_sets()
     P = rg.Pool.from_sets(bs.values, bs.offsets)
+    if kidx:
+        P.key_index(ctx)
     u = lambda *ids: np.array(ids, np.uint32)
     big = np.arange(6, 12, dtype=np.uint32)
     qs = [
@@ -299,7 +305,7 @@ def test_multi_key_spans_and_split_passes(rg, ctx):
         ("or", np.resize(np.arange(12, dtype=np.uint32), 256)), ("xor", np.resize(big, 255)),
     ]
     for op, ids in qs:
-        _say(f"[spans] op={op} k={len(ids)}")
+        _say(f"[spans kidx={kidx}] op={op} k={len(ids)}")
         exp = oracle.kway(op, [bs[int(i)] for i in ids])
         tids = torch.from_numpy(ids.view(np.int32)).cuda()
         out, card = rg.multi(ctx, op, P, tids, materialize=True, card=True)

@@ -46,13 +46,19 @@ def _t(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).cuda()
 
 
-def check_batch(rg, ctx, bs, ia, ib, ops=OPS, bs_b=None, label=""):
-    """Run each op on pairs (ia[p] of bs, ib[p] of bs_b) and compare everything with the oracle."""
+def check_batch(rg, ctx, bs, ia, ib, ops=OPS, bs_b=None, label="", key_index=(False, False)):
+    """Run each op on pairs (ia[p] of bs, ib[p] of bs_b) and compare everything
+    with the oracle. key_index: whether the A and the B pool carry key-presence
+    indexes."""
     import torch
 
     bs_b = bs if bs_b is None else bs_b
     A = rg.Pool.from_sets(bs.values, bs.offsets)
     B = A if bs_b is bs else rg.Pool.from_sets(bs_b.values, bs_b.offsets)
+    if key_index[0]:
+        A.key_index(ctx)
+    if key_index[1] and B is not A:
+        B.key_index(ctx)
     assert rg.rg_pool_validate(ctx, A) == 0
     assert rg.rg_pool_validate(ctx, B) == 0
     tia, tib = _t(ia), _t(ib)
@@ -563,3 +569,21 @@ def test_key_index_layout_and_matching(rg, ctx):
         torch.cuda.synchronize()
         assert np.array_equal(c.cpu().numpy().view(np.uint64), exp), op
         assert np.array_equal(j.cpu().numpy(), jexp), op
+
+
+@pytest.mark.parametrize("which", ["edges", "mixed"])
+def test_materialised_with_key_index(rg, ctx, which):
+    """Pools that carry key-presence indexes: the k-way kernels of union,
+    symmetric difference and difference take their key sets from the presence
+    words and find containers by bit test and rank; one pool, and an indexed
+    pool against one without."""
+    bs = synth.BitmapSet.from_list(rgtest.edge_sets()) if which == "edges" else synth.mixed_small(n_bitmaps=24, seed=95)
+    k = len(bs)
+    rng = np.random.default_rng(96)
+    ia = rng.integers(0, k, 120).astype(np.uint32)
+    ib = rng.integers(0, k, 120).astype(np.uint32)
+    check_batch(rg, ctx, bs, ia, ib, label=f"kidx-{which}", key_index=(True, True))
+    other = synth.mixed_small(n_bitmaps=12, seed=97)
+    ib2 = rng.integers(0, len(other), 120).astype(np.uint32)
+    check_batch(rg, ctx, bs, ia, ib2, bs_b=other, label=f"kidx-{which}-A", key_index=(True, False))
+    check_batch(rg, ctx, other, ib2, ia, bs_b=bs, label=f"kidx-{which}-B", key_index=(False, True))
