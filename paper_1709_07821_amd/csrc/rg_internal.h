@@ -474,6 +474,7 @@ struct KwArgs {
     long long* acc;     // per query, count-only results
     uint32_t* err;      // set when a query's key set exceeds its slot range
     uint32_t small = 1; // materialised results with an array side go to the one-wave kernel
+    uint32_t eval_chunk = 0;  // slots per evaluation workgroup chunk (1..64; 0: by the slot count)
     const KwPart* parts = nullptr;  // parts of split key passes
     uint32_t n_parts = 0;
     uint64_t* kmask = nullptr;      // 1024 words per split query, zero before the key pass

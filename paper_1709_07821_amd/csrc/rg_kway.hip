@@ -31,7 +31,13 @@ namespace rg {
 
 constexpr int KW_UNROLL = 4;  // independent loads in flight per thread in the key and fold passes
 constexpr uint32_t KW_BS_BATCH = 8;    // bitset containers whose words a fold loads at once
-constexpr uint32_t KW_EVAL_CHUNK = 4;  // slots whose tasks the evaluation workgroup reads at once (measured: 1, 4, 16)
+constexpr uint64_t KW_EVAL_FEW = 8192;  // slots up to which each gets its own evaluation workgroup
+// KwArgs.eval_chunk: slots whose tasks an evaluation workgroup reads at once
+// (at most 64; 0: chosen by the launcher). A chunk's keys are built one after
+// another, so chunks add their latencies: with few slots (at most
+// KW_EVAL_FEW, about what the GPU holds at once) every slot gets its own
+// workgroup; with many, chunks of 4 save workgroup starts and task reads
+// (measured on pairwise calls: 1, 4, 16; on k-way steps of 1e3 to 2.5e5 slots).
 
 // The container of `key` in bitmap b (its global index), or NONE. With the
 // pool's key-presence index: the presence bit, then the word's rank plus the
@@ -737,12 +743,13 @@ __global__ void __launch_bounds__(256) k_kw_eval(KwArgs a) {
     __shared__ uint8_t bsl[KW_MAX_K];          // the bitset containers (union, symmetric difference, difference)
     __shared__ uint32_t chunk_mask;
     const uint32_t tid = threadIdx.x;
-    // chunks of KW_EVAL_CHUNK slots: their tasks are read at once, then the
+    // chunks of eval_chunk slots: their tasks are read at once, then the
     // workgroup evaluates those that are its own (not empty, not the one-wave
     // kernel's) one after another
-    for (uint64_t c0 = (uint64_t)blockIdx.x * KW_EVAL_CHUNK; c0 < a.n_slots; c0 += (uint64_t)gridDim.x * KW_EVAL_CHUNK) {
+    const uint32_t chunk = a.eval_chunk;
+    for (uint64_t c0 = (uint64_t)blockIdx.x * chunk; c0 < a.n_slots; c0 += (uint64_t)gridDim.x * chunk) {
     bool own = false;
-    if (tid < KW_EVAL_CHUNK && c0 + tid < a.n_slots) {
+    if (tid < chunk && c0 + tid < a.n_slots) {
         const Task t = a.tasks[c0 + tid];
         own = t.kind == KIND_MATCH && t.bin != KW_TASK_SMALL && t.bin != KW_TASK_DONE;
     }
@@ -957,9 +964,13 @@ void launch_kw_bounds(const KwArgs& a, hipStream_t st) {
 }
 void launch_kw_eval(const KwArgs& a, hipStream_t st) {
     if (!a.n_slots) return;
-    const uint64_t nc = (a.n_slots + KW_EVAL_CHUNK - 1) / KW_EVAL_CHUNK;
+    const uint32_t chunk = a.eval_chunk == 0 ? (a.n_slots <= KW_EVAL_FEW ? 1u : 4u)
+                           : a.eval_chunk > 64 ? 64u : a.eval_chunk;
+    KwArgs b = a;
+    b.eval_chunk = chunk;
+    const uint64_t nc = (a.n_slots + chunk - 1) / chunk;
     const uint32_t g = nc < 65536 ? (uint32_t)nc : 65536u;
-    hipLaunchKernelGGL(k_kw_eval, dim3(g), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_kw_eval, dim3(g), dim3(256), 0, st, b);
 }
 void launch_kw_cards(const KwArgs& a, const uint64_t* bm_card, uint64_t* cards, hipStream_t st) {
     if (a.n_queries)
