@@ -483,8 +483,10 @@ struct KwArgs {
 // kmask / kdone: the split queries' key masks (n_masks x 1024 words) and arrival counters, zeroed
 void launch_kw_step_init(uint64_t* totals, uint32_t* err, long long* acc, uint64_t* bm_card, uint64_t* bm_wbytes,
                          uint32_t nq, uint64_t* kmask, uint32_t* kdone, uint32_t n_masks, hipStream_t st);
-// the key pass: parts of split queries (when a.n_parts), then the others
-void launch_kw_keys(const KwArgs& a, hipStream_t st);
+// the key pass: parts of split queries (when a.n_parts), then the others.
+// pairs: some query has at most two bitmaps (the one-wave key kernel's);
+// whole: some query of more is not split (the workgroup kernel's).
+void launch_kw_keys(const KwArgs& a, hipStream_t st, bool pairs = true, bool whole = true);
 void launch_kw_bounds(const KwArgs& a, hipStream_t st);
 // the two evaluation kernels: the one-wave array kernel for the slots the
 // bounds kernel marked (rg_small.hip), the workgroup kernel for the others

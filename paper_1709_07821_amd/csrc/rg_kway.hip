@@ -946,11 +946,12 @@ void launch_kw_step_init(uint64_t* totals, uint32_t* err, long long* acc, uint64
                        nq, kmask, kdone, n_masks);
 }
 
-void launch_kw_keys(const KwArgs& a, hipStream_t st) {
+void launch_kw_keys(const KwArgs& a, hipStream_t st, bool pairs, bool whole) {
     if (!a.n_queries) return;
     if (a.n_parts)
         hipLaunchKernelGGL(k_kw_keys_part, dim3(a.n_parts < 16384 ? a.n_parts : 16384u), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_kw_keys_small, dim3((a.n_queries + 3) / 4), dim3(256), 0, st, a);
+    if (pairs) hipLaunchKernelGGL(k_kw_keys_small, dim3((a.n_queries + 3) / 4), dim3(256), 0, st, a);
+    if (!pairs && !whole) return;
     // a query per workgroup for small batches (each may be large); up to
     // KW_KEYS_CHUNK for large ones, where most are the one-wave kernel's
     uint32_t chunk = a.n_queries / 2048;

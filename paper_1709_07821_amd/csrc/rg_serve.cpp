@@ -126,6 +126,7 @@ struct StepLayout {
     uint32_t nq = 0;
     uint64_t nids = 0, S = 0, P = 0;
     uint32_t n_parts = 0, n_masks = 0;  // split key passes of the step (set when staged)
+    bool pairs = true, whole = true;    // some query of <= 2 bitmaps / some unsplit one of more
     bool own_out = true;
     size_t up_bytes = 0, down_off = 0, down_bytes = 0, total = 0;
     // offsets
@@ -263,16 +264,23 @@ rg_status step_enqueue(std::string* err_out, const rg_pool& pool, const StepLayo
     a.n_parts = L.n_parts;
     a.kmask = kmask;
     a.kdone = kdone;
-    launch_kw_keys(a, st);
+    // the one-wave kernels take only queries of at most two bitmaps; skip
+    // their launches when the step has none (L.pairs), and the workgroup key
+    // kernel when every query of more bitmaps is split (L.whole)
+    launch_kw_keys(a, st, L.pairs, L.whole);
     launch_kw_bounds(a, st);
     if (L.S) launch_scan_u32_u64(ub, slot_off, L.S, 0, partials, totals, st);
     if (prof) {
-        timed(prof, PROF_KWSMALL, true, L.S, st, [&] { launch_kw_small(a, st); });
-        timed(prof, PROF_KWBB, true, L.S, st, [&] { launch_kw_bb(a, st); });
+        if (L.pairs) {
+            timed(prof, PROF_KWSMALL, true, L.S, st, [&] { launch_kw_small(a, st); });
+            timed(prof, PROF_KWBB, true, L.S, st, [&] { launch_kw_bb(a, st); });
+        }
         timed(prof, PROF_KWEVAL, true, L.S, st, [&] { launch_kw_eval(a, st); });
     } else {
-        launch_kw_small(a, st);
-        launch_kw_bb(a, st);
+        if (L.pairs) {
+            launch_kw_small(a, st);
+            launch_kw_bb(a, st);
+        }
         launch_kw_eval(a, st);
     }
     if (L.S) {
@@ -366,6 +374,8 @@ extern "C" rg_status roaring_multi(rg_ctx* c, int op, const rg_pool* pool, const
     L.plan(1, k, b.kbound, mat ? b.pbound : 0, !mat);
     L.n_parts = (uint32_t)parts.size();
     L.n_masks = n_masks;
+    L.pairs = k <= 2;
+    L.whole = k > 2 && !(qs[0].flags & KW_SPLIT);
     void* wbase = nullptr;
     if (rg_status s = sc.take(WS_WAVE, L.total, &wbase)) return s;
     uint8_t* h = nullptr;
@@ -635,6 +645,12 @@ void rg_server::run() {
                     pending.erase(pending.begin(), pending.begin() + take.size());
                     s->L.n_parts = (uint32_t)parts.size();
                     s->L.n_masks = n_masks;
+                    s->L.pairs = false;
+                    s->L.whole = false;
+                    for (const KwQuery& Q : qs) {
+                        s->L.pairs |= Q.k <= 2;
+                        s->L.whole |= Q.k > 2 && !(Q.flags & KW_SPLIT);
+                    }
                     stage_upload(s->L, s->h, qs, ids, parts);
                     ++n_steps;
                     sum_batch += take.size();
