@@ -420,7 +420,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
             ka.err = d_err;
             ka.small = !(c->dispatch_mode == 2 && c->fixed_bin == BIN_GEN);
             launch_kw_keys(ka, st);
-            launch_kw_bounds(ka, st);
+            launch_kw_bounds(ka, st, true);  // pairwise queries only
             launch_scan_u32_u64(ub, slot_off, C, pay_base, partials, totals, st);
             timed(c, PROF_KWSMALL, true, C, st, [&] { launch_kw_small(ka, st); });
             timed(c, PROF_KWBB, true, C, st, [&] { launch_kw_bb(ka, st); });
@@ -1046,7 +1046,7 @@ void plan_enqueue_mat(rg_plan* p, hipStream_t st) {
         ka.err = p->err;
         ka.small = !(p->ctx->dispatch_mode == 2 && p->ctx->fixed_bin == BIN_GEN);
         launch_kw_keys(ka, st);
-        launch_kw_bounds(ka, st);
+        launch_kw_bounds(ka, st, true);  // pairwise queries only
         // slot payload offsets continue from the previous wave's payload end
         launch_scan_u32_u64(p->ub, p->slot_off, wv.C, 0, p->partials, p->totals, st, p->totals);
         launch_kw_small(ka, st);

@@ -487,7 +487,8 @@ void launch_kw_step_init(uint64_t* totals, uint32_t* err, long long* acc, uint64
 // pairs: some query has at most two bitmaps (the one-wave key kernel's);
 // whole: some query of more is not split (the workgroup kernel's).
 void launch_kw_keys(const KwArgs& a, hipStream_t st, bool pairs = true, bool whole = true);
-void launch_kw_bounds(const KwArgs& a, hipStream_t st);
+// pairs_only: every query has at most two bitmaps (one thread per slot)
+void launch_kw_bounds(const KwArgs& a, hipStream_t st, bool pairs_only = false);
 // the two evaluation kernels: the one-wave array kernel for the slots the
 // bounds kernel marked (rg_small.hip), the workgroup kernel for the others
 void launch_kw_small(const KwArgs& a, hipStream_t st);

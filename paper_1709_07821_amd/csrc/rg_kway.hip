@@ -677,6 +677,48 @@ __global__ void __launch_bounds__(256) k_kw_bounds(KwArgs a) {
     }
 }
 
+// The same for calls whose queries all have at most two bitmaps (pairwise
+// materialisation): every task records its containers, so a slot needs no
+// search and one thread per slot does (a wave per slot would leave 62 of its
+// lanes idle).
+__global__ void __launch_bounds__(256) k_kw_bounds_pairs(KwArgs a) {
+    const uint64_t s = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= a.n_slots) return;
+    const Task t = a.tasks[s];
+    uint32_t ub = 0;
+    uint8_t mark = 0;
+    if (t.kind == KIND_MATCH && t.bin != KW_TASK_INDEXED) {
+        atomicOr(a.err, 1u);  // cannot happen: the key kernels index every pairwise task
+    } else if (t.kind == KIND_MATCH) {
+        const KwQuery& Q = a.queries[t.pair - a.pair_base];
+        if (Q.flags & KW_MATERIALIZE) {
+            const uint32_t op = Q.op, k = Q.k;
+            uint32_t ca = 0, cb = 0, sa = 0, sb = 0;
+            uint8_t ta = 0, tb = 0;
+            if (t.ia != NONE) {
+                ca = a.P0.card[t.ia];
+                ta = a.P0.types[t.ia];
+                sa = a.P0.size[t.ia];
+            }
+            if (k > 1 && t.ib != NONE) {
+                cb = a.P1.card[t.ib];
+                tb = a.P1.types[t.ib];
+                sb = a.P1.size[t.ib];
+            }
+            const uint64_t bc = op == RG_AND ? (uint64_t)(k > 1 ? (ca < cb ? ca : cb) : ca)
+                                : op == RG_ANDNOT ? (uint64_t)ca : (uint64_t)ca + cb;
+            ub = wbytes_of(bc);
+            if (a.small)
+                mark = small_mat_ok((int)op, ta, tb, sa, sb) ? KW_TASK_SMALL
+                       : bb_mat_ok((int)op, ta, tb)          ? KW_TASK_BB
+                                                             : 0;
+        }
+    }
+    a.ub[s] = ub;
+    a.res_card[s] = 0;
+    if (mark) a.tasks[s].bin = mark;
+}
+
 // ---------------------------------------------------------------- 3. evaluate
 // Folds a set of containers into the LDS bitset r with one read-modify-write
 // per unit: OP 0 sets bits (union), 1 flips them (symmetric difference: each
@@ -959,9 +1001,10 @@ void launch_kw_keys(const KwArgs& a, hipStream_t st, bool pairs, bool whole) {
     const uint32_t g = (a.n_queries + chunk - 1) / chunk;
     hipLaunchKernelGGL(k_kw_keys, dim3(g < 16384 ? g : 16384u), dim3(256), 0, st, a, chunk);
 }
-void launch_kw_bounds(const KwArgs& a, hipStream_t st) {
-    if (a.n_slots)
-        hipLaunchKernelGGL(k_kw_bounds, dim3((uint32_t)((a.n_slots + 3) / 4)), dim3(256), 0, st, a);
+void launch_kw_bounds(const KwArgs& a, hipStream_t st, bool pairs_only) {
+    if (!a.n_slots) return;
+    if (pairs_only) hipLaunchKernelGGL(k_kw_bounds_pairs, dim3((uint32_t)((a.n_slots + 255) / 256)), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(k_kw_bounds, dim3((uint32_t)((a.n_slots + 3) / 4)), dim3(256), 0, st, a);
 }
 void launch_kw_eval(const KwArgs& a, hipStream_t st) {
     if (!a.n_slots) return;

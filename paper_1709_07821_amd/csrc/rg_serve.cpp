@@ -127,6 +127,7 @@ struct StepLayout {
     uint64_t nids = 0, S = 0, P = 0;
     uint32_t n_parts = 0, n_masks = 0;  // split key passes of the step (set when staged)
     bool pairs = true, whole = true;    // some query of <= 2 bitmaps / some unsplit one of more
+    bool big = true;                    // some query of more than 2 bitmaps
     bool own_out = true;
     size_t up_bytes = 0, down_off = 0, down_bytes = 0, total = 0;
     // offsets
@@ -268,7 +269,7 @@ rg_status step_enqueue(std::string* err_out, const rg_pool& pool, const StepLayo
     // their launches when the step has none (L.pairs), and the workgroup key
     // kernel when every query of more bitmaps is split (L.whole)
     launch_kw_keys(a, st, L.pairs, L.whole);
-    launch_kw_bounds(a, st);
+    launch_kw_bounds(a, st, !L.big);
     if (L.S) launch_scan_u32_u64(ub, slot_off, L.S, 0, partials, totals, st);
     if (prof) {
         if (L.pairs) {
@@ -376,6 +377,7 @@ extern "C" rg_status roaring_multi(rg_ctx* c, int op, const rg_pool* pool, const
     L.n_masks = n_masks;
     L.pairs = k <= 2;
     L.whole = k > 2 && !(qs[0].flags & KW_SPLIT);
+    L.big = k > 2;
     void* wbase = nullptr;
     if (rg_status s = sc.take(WS_WAVE, L.total, &wbase)) return s;
     uint8_t* h = nullptr;
@@ -647,9 +649,11 @@ void rg_server::run() {
                     s->L.n_masks = n_masks;
                     s->L.pairs = false;
                     s->L.whole = false;
+                    s->L.big = false;
                     for (const KwQuery& Q : qs) {
                         s->L.pairs |= Q.k <= 2;
                         s->L.whole |= Q.k > 2 && !(Q.flags & KW_SPLIT);
+                        s->L.big |= Q.k > 2;
                     }
                     stage_upload(s->L, s->h, qs, ids, parts);
                     ++n_steps;
