@@ -401,7 +401,9 @@ void launch_mlp_table(const float* P, uint8_t* table, hipStream_t st);
 // difference, difference by nothing), whose result is the container itself
 // in P1 form (touching runs merged; an array or a bitset when smaller).
 constexpr uint32_t SMALL_MAX = 4096;
-constexpr uint32_t SMALL_LDS = SMALL_MAX + 8;  // values staged per wave (the second array starts 16-byte aligned)
+// values staged per wave: 8 KiB, so that a workgroup of four waves takes 32 KiB
+// of LDS and five workgroups fit on a compute unit
+constexpr uint32_t SMALL_LDS = SMALL_MAX;
 __host__ __device__ __forceinline__ bool lone_run(int op, uint8_t ta, uint8_t tb) {
     return (ta == RG_RUN && tb == 0 && op != RG_AND) || (ta == 0 && tb == RG_RUN && (op == RG_OR || op == RG_XOR));
 }

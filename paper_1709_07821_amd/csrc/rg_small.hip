@@ -217,7 +217,7 @@ __device__ void merge_pair(bool xor_op, const uint16_t* A, uint32_t ca, const ui
 // written: merged runs (their starts and ends staged in LDS, paired by merged
 // run number), an array (each lane expands its runs at the prefix of the
 // lengths before them), or a bitset (the runs' bits set in an LDS bitset,
-// then copied out). lds: this wave's SMALL_LDS 16-bit entries (8 KiB + 16 B).
+// then copied out). lds: this wave's SMALL_LDS 16-bit entries (8 KiB).
 __device__ void lone_runs(const SmallSide& R, uint32_t slot, const SlotOut& so, uint16_t* lds) {
     const uint32_t lane = lane_id();
     const uint32_t* rp = reinterpret_cast<const uint32_t*>(R.pl);
@@ -332,9 +332,19 @@ __device__ void small_pair(int op, SmallSide A, SmallSide B, uint32_t slot, cons
     j.keep_in = op == RG_AND;
     j.y_lds = false;
     if (j.merge) {
-        uint16_t* lb = lds + ((A.size + 7u) & ~7u);  // 16-byte aligned
+        // B after A, 16-byte aligned for the vector copy when that still fits
+        // in SMALL_LDS entries; otherwise (A + B within 7 of the limit) right
+        // after A, copied value by value
+        const uint32_t ob = (A.size + 7u) & ~7u;
+        const bool aligned = ob + B.size <= SMALL_LDS;
+        uint16_t* lb = lds + (aligned ? ob : A.size);
         stage_u16(lds, A.pl, A.size, lane);
-        stage_u16(lb, B.pl, B.size, lane);
+        if (aligned) {
+            stage_u16(lb, B.pl, B.size, lane);
+        } else {
+            const uint16_t* s16 = reinterpret_cast<const uint16_t*>(B.pl);
+            for (uint32_t i = lane; i < B.size; i += 64) lb[i] = s16[i];
+        }
         __builtin_amdgcn_wave_barrier();
         merge_pair(j.xor_op, lds, A.size, lb, B.size, slot, so);
         return;
