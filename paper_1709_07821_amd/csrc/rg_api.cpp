@@ -288,6 +288,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
     uint32_t* bin_info = d_err + 128;                              // [2 NBINS] counts, offsets
     uint64_t* bin_total = reinterpret_cast<uint64_t*>(d_err + 160);
     uint64_t* totals = reinterpret_cast<uint64_t*>(d_err + 64);  // [0] payload end, [1] container end
+    uint64_t* pair_totals = reinterpret_cast<uint64_t*>(d_err + 256);  // launch_pair_totals' four sums
 
     // Count-only calls accumulate |A n B| for every operation and convert at
     // the end (Section 5.9 identities): the kernels then depend on the
@@ -296,30 +297,24 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
     launch_fill_u32(d_err, 0, 1, st);
     launch_pair_prep(kop, mat, pa, pb, A->n_bitmaps, B->n_bitmaps, d_ia, d_ib, ia0, ib0, n_pairs, n_cand, bound,
                      min_cont, acc, d_err, st);
-    const size_t host_pairs = align256(4 * n_pairs) + align256(8 * n_pairs) + align256(4 * n_pairs);
+    const size_t host_pairs = align256(4 * n_pairs);
     uint8_t* hbase = nullptr;
     if (rg_status s = host_buffer(c, host_pairs + 4096 + align256(8 * (n_pairs + 1)) + 512, &hbase)) return s;
     Bump hb{hbase};
-    uint32_t* h_cand = hb.take<uint32_t>(n_pairs);
-    uint64_t* h_bound = hb.take<uint64_t>(n_pairs);
-    uint32_t* h_minc = hb.take<uint32_t>(n_pairs);
+    uint32_t* h_cand = hb.take<uint32_t>(n_pairs);  // per-pair slots, read back only for waves of pairs
     uint32_t* h_small = hb.take<uint32_t>(1024);
     uint64_t* h_coff = hb.take<uint64_t>(n_pairs + 1);
-    HIPCHK(c, hipMemcpyAsync(h_cand, n_cand, 4 * n_pairs, hipMemcpyDeviceToHost, st));
-    if (mat) {
-        HIPCHK(c, hipMemcpyAsync(h_bound, bound, 8 * n_pairs, hipMemcpyDeviceToHost, st));
-        HIPCHK(c, hipMemcpyAsync(h_minc, min_cont, 4 * n_pairs, hipMemcpyDeviceToHost, st));
-    }
+    // sizing from device-side sums (a few words back, not the per-pair arrays)
+    launch_pair_totals(n_cand, mat ? bound : nullptr, mat ? min_cont : nullptr, n_pairs, pair_totals, st);
+    HIPCHK(c, hipMemcpyAsync(h_small + 256, pair_totals, 32, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipMemcpyAsync(h_small, d_err, 4, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     if (h_small[0]) return fail(c, RG_EINVAL, "pair index out of range of its pool");
+    const uint64_t* h_tot = reinterpret_cast<const uint64_t*>(h_small + 256);
+    const uint64_t total_cand = h_tot[0], most_cand = h_tot[3];
 
     if (mat) {
-        uint64_t tb = 0, tcont = 0;
-        for (uint64_t p = 0; p < n_pairs; ++p) {
-            tb += h_bound[p];
-            tcont += h_minc[p];
-        }
+        const uint64_t tb = h_tot[1], tcont = h_tot[2];
         out->needed_payload_bytes = tb;
         out->needed_containers = tcont;
         if (out->cap_payload_bytes < tb || out->cap_containers < tcont)
@@ -340,26 +335,36 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
             else hi = mid - 1;
         }
         S_cap = lo;
-        uint64_t most = 0;
-        for (uint64_t p = 0; p < n_pairs; ++p) most = std::max<uint64_t>(most, h_cand[p]);
-        if (most > S_cap)
+        if (most_cand > S_cap)
             return fail(c, RG_ECAPACITY,
                         "workspace too small for one pair's candidate slots (rg_workspace_size gives enough)");
     }
+    // one wave when every candidate slot fits (its pair offsets scanned on the
+    // device); otherwise waves of whole pairs planned from the per-pair counts
+    const bool one_wave = total_cand <= S_cap;
     std::vector<uint64_t> wstart{0};
-    uint64_t accs = 0, S_max = 0, P_max = 0;
-    for (uint64_t p = 0; p < n_pairs; ++p) {
-        if (accs + h_cand[p] > S_cap && accs > 0) {
-            S_max = std::max(S_max, accs);
-            P_max = std::max(P_max, p - wstart.back());
-            wstart.push_back(p);
-            accs = 0;
+    uint64_t S_max = 0, P_max = 0;
+    if (one_wave) {
+        S_max = total_cand;
+        P_max = n_pairs;
+        wstart.push_back(n_pairs);
+    } else {
+        HIPCHK(c, hipMemcpyAsync(h_cand, n_cand, 4 * n_pairs, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        uint64_t accs = 0;
+        for (uint64_t p = 0; p < n_pairs; ++p) {
+            if (accs + h_cand[p] > S_cap && accs > 0) {
+                S_max = std::max(S_max, accs);
+                P_max = std::max(P_max, p - wstart.back());
+                wstart.push_back(p);
+                accs = 0;
+            }
+            accs += h_cand[p];
         }
-        accs += h_cand[p];
+        S_max = std::max(S_max, accs);
+        P_max = std::max(P_max, n_pairs - wstart.back());
+        wstart.push_back(n_pairs);
     }
-    S_max = std::max(S_max, accs);
-    P_max = std::max(P_max, n_pairs - wstart.back());
-    wstart.push_back(n_pairs);
 
     // materialised OR / XOR / ANDNOT run through the k-way path (two bitmaps
     // per query): key set per pair, then one workgroup per result key
@@ -375,7 +380,7 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
     uint64_t* out_idx = wb.take<uint64_t>(S_max);
     uint32_t* bin_lists = wb.take<uint32_t>(S_max);
     uint64_t* cand_off = wb.take<uint64_t>(P_max + 1);
-    uint64_t* partials = wb.take<uint64_t>(scan_partials_needed(S_max));
+    uint64_t* partials = wb.take<uint64_t>(scan_partials_needed(std::max(S_max, P_max)));
     uint32_t* blk_cnt = wb.take<uint32_t>((size_t)NBINS * match_blocks(S_max));
     uint64_t* blk_off = wb.take<uint64_t>((size_t)NBINS * match_blocks(S_max));
     uint64_t* bpart = wb.take<uint64_t>(scan_partials_needed((uint64_t)NBINS * match_blocks(S_max)));
@@ -387,11 +392,17 @@ rg_status run_batch(rg_ctx* c, int op, const rg_pool* A, const rg_pool* B, const
     for (size_t w = 0; w < nw; ++w) {
         const uint64_t p0 = wstart[w], p1 = wstart[w + 1];
         const uint32_t np = (uint32_t)(p1 - p0);
-        h_coff[0] = 0;
-        for (uint32_t q = 0; q < np; ++q) h_coff[q + 1] = h_coff[q] + h_cand[p0 + q];
-        const uint64_t C = h_coff[np];
+        uint64_t C;
+        if (one_wave) {
+            C = total_cand;
+            launch_scan_u32_u64(n_cand, cand_off, np, 0, partials, cand_off + np, st);
+        } else {
+            h_coff[0] = 0;
+            for (uint32_t q = 0; q < np; ++q) h_coff[q + 1] = h_coff[q] + h_cand[p0 + q];
+            C = h_coff[np];
+            HIPCHK(c, hipMemcpyAsync(cand_off, h_coff, 8 * (np + 1), hipMemcpyHostToDevice, st));
+        }
         const bool last = w + 1 == nw;
-        HIPCHK(c, hipMemcpyAsync(cand_off, h_coff, 8 * (np + 1), hipMemcpyHostToDevice, st));
         if (C == 0) {
             if (mat) {
                 launch_fill_u64(totals + 1, out_base, 1, st);

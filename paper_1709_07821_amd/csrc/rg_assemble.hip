@@ -83,6 +83,45 @@ void launch_bm_begin(const uint64_t* cand_off, const uint64_t* out_idx, uint64_t
                        out_total, n_pairs, pair0, bm_begin, (int)last_wave);
 }
 
+// Sums over the pairs of a batched call, for the host's sizing without reading
+// the per-pair arrays back: out[0] candidate slots, out[1] result payload
+// bound, out[2] result containers bound, out[3] the most slots of one pair
+// (bound and min_cont may be null: count-only). out is zeroed by the launcher.
+__global__ void __launch_bounds__(256) k_pair_totals(const uint32_t* n_cand, const uint64_t* bound,
+                                                     const uint32_t* min_cont, uint64_t n, uint64_t* out) {
+    uint64_t c = 0, b = 0, m = 0, most = 0;
+    for (uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (uint64_t)gridDim.x * 256) {
+        const uint64_t x = n_cand[p];
+        c += x;
+        most = x > most ? x : most;
+        if (bound) b += bound[p];
+        if (min_cont) m += min_cont[p];
+    }
+    c = wave_sum_u64(c);
+    b = wave_sum_u64(b);
+    m = wave_sum_u64(m);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t y = __shfl_xor(most, o);
+        most = y > most ? y : most;
+    }
+    if (lane_id() == 0) {
+        if (c) atomicAdd(reinterpret_cast<unsigned long long*>(&out[0]), (unsigned long long)c);
+        if (b) atomicAdd(reinterpret_cast<unsigned long long*>(&out[1]), (unsigned long long)b);
+        if (m) atomicAdd(reinterpret_cast<unsigned long long*>(&out[2]), (unsigned long long)m);
+        if (most) atomicMax(reinterpret_cast<unsigned long long*>(&out[3]), (unsigned long long)most);
+    }
+}
+
+void launch_pair_totals(const uint32_t* n_cand, const uint64_t* bound, const uint32_t* min_cont, uint64_t n,
+                        uint64_t* out, hipStream_t st) {
+    launch_fill_u64(out, 0, 4, st);
+    if (!n) return;
+    const uint64_t g = (n + 2047) / 2048;  // about eight pairs per thread
+    hipLaunchKernelGGL(k_pair_totals, dim3(g < 1024 ? (uint32_t)g : 1024u), dim3(256), 0, st, n_cand, bound,
+                       min_cont, n, out);
+}
+
 // |A n B| from |A op B| and the stored totals
 __device__ __forceinline__ uint64_t inter_from(int op, uint64_t card, uint64_t na, uint64_t nb) {
     if (op == RG_AND) return card;

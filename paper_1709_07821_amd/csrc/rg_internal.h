@@ -252,6 +252,10 @@ struct MatchArgs {
 };
 
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st);
+// out[0..3] = sum of n_cand, sum of bound, sum of min_cont (either may be
+// null), max of n_cand over n pairs
+void launch_pair_totals(const uint32_t* n_cand, const uint64_t* bound, const uint32_t* min_cont, uint64_t n,
+                        uint64_t* out, hipStream_t st);
 void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t st);
 void launch_pair_prep(int op, bool materialize, PoolView A, PoolView B, uint32_t nA, uint32_t nB,
                       const uint32_t* ia, const uint32_t* ib, uint32_t ia0, uint32_t ib0, uint64_t n_pairs,

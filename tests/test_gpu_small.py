@@ -1,9 +1,10 @@
 """The one-wave kernels of materialised results (pairs with an array side;
 pairs of bitsets): containers built to hit each of their cases - merges at and
-just past the value limit, results that come out as runs across many 64-value
-rounds, absent sides, array-bitset and array-run filters in both operand
-orders, full 4096-value arrays, bitset pairs whose results are bitsets, arrays,
-runs or empty, lone bitsets and lone run containers - against the oracle, through the eager call
+just past the value limit, merges whose second operand cannot start aligned,
+results that come out as runs across many 64-value rounds, absent sides,
+array-bitset and array-run filters in both operand orders, full 4096-value
+arrays, bitset pairs whose results are bitsets, arrays, runs or empty, lone
+bitsets and lone run containers - against the oracle, through the eager call
 (binned intersection and k-way path) and a materialising plan, and the same
 pairs with the one-wave kernels switched off."""
 import sys
@@ -97,6 +98,9 @@ def case_sets():
         # a run container only in A, one only in B (copied in P1 form)
         20: (np.concatenate([np.arange(s, s + 20) for s in range(0, 4000, 40)]), None),
         21: (None, np.arange(100, 60000)),
+        # 2001 + 2095 = 4096 values: the second array cannot start 16-byte aligned
+        # in the wave's 4096 staging entries (staged value by value)
+        22: (ev[:2001], ev[:2095] + 1),
     }
     a, b = [], []
     for key, (pa, pb) in parts.items():
