@@ -98,8 +98,9 @@ size_t wave_bytes(uint64_t S, uint64_t P, bool kw) {
     size_t b = 0;
     for (size_t x : {sizeof(Task) * S, 4 * S, 8 * S, 4 * S, 1 * S, 4 * S, 8 * S, 4 * S})
         b += align256(x);  // tasks, ub, slot_off, res_card, res_type, res_size, out_idx, lists
-    b += align256(8 * (P + 1)) + align256(8 * scan_partials_needed(S)) + align256(4 * nb) + align256(8 * nb) +
-         align256(8 * scan_partials_needed(nb));
+    // scan partials serve the slot scans (S) and the pair-offset scan (P)
+    b += align256(8 * (P + 1)) + align256(8 * scan_partials_needed(std::max(S, P))) + align256(4 * nb) +
+         align256(8 * nb) + align256(8 * scan_partials_needed(nb));
     if (kw) b += align256(sizeof(KwQuery) * P) + align256(8 * P);
     return b;
 }

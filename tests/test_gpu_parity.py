@@ -587,3 +587,34 @@ def test_materialised_with_key_index(rg, ctx, which):
     ib2 = rng.integers(0, len(other), 120).astype(np.uint32)
     check_batch(rg, ctx, bs, ia, ib2, bs_b=other, label=f"kidx-{which}-A", key_index=(True, False))
     check_batch(rg, ctx, other, ib2, ia, bs_b=bs, label=f"kidx-{which}-B", key_index=(False, True))
+
+
+def test_materialised_many_empty_pairs(rg, ctx):
+    """Far more pairs than candidate slots (2e5 pairs of empty bitmaps around
+    a few non-empty ones): the device scan of the pair offsets runs over every
+    pair, so its workspace is sized by the pair count as well as the slots."""
+    import torch
+
+    rng = np.random.default_rng(98)
+    sets = [np.zeros(0, np.uint32), np.unique(rng.integers(0, 1 << 20, 300)).astype(np.uint32),
+            np.unique(rng.integers(0, 1 << 20, 50)).astype(np.uint32)]
+    bs = synth.BitmapSet.from_list(sets)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    n = 200_000
+    ia = np.zeros(n, np.uint32)
+    ib = np.zeros(n, np.uint32)
+    ia[[0, 77_777, n - 1]] = [1, 2, 1]
+    ib[[0, 77_777, n - 1]] = [2, 1, 1]
+    for op in OPS:
+        _say(f"[many empty] op={op} pairs={n}")
+        out, cards, _ = rg.batch(ctx, op, P, P, _t(ia), _t(ib), materialize=True, card=True)
+        torch.cuda.synchronize()
+        c = cards.cpu().numpy().view(np.uint64)
+        h = out.as_pool().to_host()
+        for p in (0, 1, 77_777, n - 2, n - 1):
+            exp = oracle.op(op, sets[int(ia[p])], sets[int(ib[p])])
+            assert int(c[p]) == len(exp), (op, p)
+            got, meta = rgtest.decode_bitmap(h, p)
+            assert np.array_equal(got, exp) and meta == rgtest.oracle_meta(oracle, exp), (op, p)
+        assert int(c.astype(np.int64).sum()) == sum(len(oracle.op(op, sets[int(ia[p])], sets[int(ib[p])]))
+                                                    for p in (0, 77_777, n - 1))
