@@ -471,6 +471,95 @@ __device__ __forceinline__ void match_block(const MatchArgs& m, uint64_t n_cand,
 #pragma unroll
         for (int k = 0; k < (int)MATCH_PER_THREAD; ++k)
             if (o[k].slot != NONE) finish_slot(m, cnt, o[k]);
+    } else if (!m.materialize && m.A.kidx && m.B.kidx && pl_hi - pl_lo < MATCH_LDS_KEYS / 2) {
+        // Count-only block over several pairs with key indexes on both sides:
+        // the pairs' candidate offsets (relative to the first pair's) are staged
+        // in LDS, and each step - pair search, pair and bitmap records, the
+        // candidate key, the presence word and rank - is issued for all of the
+        // thread's candidates before the next, so that their loads overlap.
+        uint32_t* rel = reinterpret_cast<uint32_t*>(lds.lkeys);
+        const uint32_t nr = pl_hi - pl_lo + 1;
+        const uint64_t base = uniform64(m.cand_off[pl_lo]);
+        for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) rel[i] = (uint32_t)(m.cand_off[pl_lo + i] - base);
+        __syncthreads();
+        const uint32_t top = 1u << (31 - __builtin_clz(nr));
+        bool live[MATCH_PER_THREAD];
+        uint32_t tg[MATCH_PER_THREAD], pos[MATCH_PER_THREAD];
+#pragma unroll
+        for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
+            const uint64_t t = t0 + (uint64_t)k * 256 + threadIdx.x;
+            live[k] = t < n_cand;
+            tg[k] = live[k] ? (uint32_t)(t - base) : 0u;
+            pos[k] = 0;
+        }
+        // largest pos with rel[pos] <= tg (rel[0] = 0)
+        for (uint32_t step = top; step; step >>= 1) {
+#pragma unroll
+            for (int k = 0; k < (int)MATCH_PER_THREAD; ++k)
+                if (pos[k] + step < nr && rel[pos[k] + step] <= tg[k]) pos[k] += step;
+        }
+        uint32_t av[MATCH_PER_THREAD], bv[MATCH_PER_THREAD];
+#pragma unroll
+        for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
+            const uint64_t p = m.pair0 + pl_lo + pos[k];
+            av[k] = live[k] ? (m.ia ? m.ia[p] : m.ia0) : 0u;
+            bv[k] = live[k] ? (m.ib ? m.ib[p] : m.ib0) : 0u;
+        }
+        uint64_t a0[MATCH_PER_THREAD], b0[MATCH_PER_THREAD];
+        uint32_t KA[MATCH_PER_THREAD], KB[MATCH_PER_THREAD];
+#pragma unroll
+        for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
+            a0[k] = b0[k] = 0;
+            KA[k] = KB[k] = 0;
+            if (live[k]) {
+                a0[k] = m.A.bm_begin[av[k]];
+                b0[k] = m.B.bm_begin[bv[k]];
+                KA[k] = (uint32_t)(m.A.bm_begin[av[k] + 1] - a0[k]);
+                KB[k] = (uint32_t)(m.B.bm_begin[bv[k] + 1] - b0[k]);
+            }
+        }
+        uint16_t key[MATCH_PER_THREAD];
+        uint32_t u[MATCH_PER_THREAD];
+#pragma unroll
+        for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
+            u[k] = tg[k] - rel[pos[k]];
+            key[k] = 0;
+            if (live[k]) key[k] = KA[k] <= KB[k] ? m.A.keys[a0[k] + u[k]] : m.B.keys[b0[k] + u[k]];
+        }
+        uint64_t xw[MATCH_PER_THREAD];
+        uint32_t xr[MATCH_PER_THREAD];
+#pragma unroll
+        for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
+            xw[k] = 0;
+            xr[k] = 0;
+            if (live[k]) {
+                // the key index of the side with more keys (the searched one)
+                const bool a_small = KA[k] <= KB[k];
+                const uint8_t* ix = (a_small ? m.B.kidx : m.A.kidx) +
+                                    (uint64_t)(a_small ? bv[k] : av[k]) * RG_KEY_INDEX_BYTES;
+                const uint32_t wi = key[k] >> 6;
+                xw[k] = reinterpret_cast<const uint64_t*>(ix)[wi];
+                xr[k] = reinterpret_cast<const uint16_t*>(ix + 8 * KIDX_WORDS)[wi];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
+            if (!live[k]) continue;
+            const bool a_small = KA[k] <= KB[k];
+            const uint32_t j = kidx_lookup(xw[k], xr[k], key[k]);
+            Task& task = o[k].task;
+            task.pair = (uint32_t)(m.pair0 + pl_lo + pos[k]);
+            task.key = key[k];
+            if (j != NONE) {
+                task.kind = KIND_MATCH;
+                task.ia = (uint32_t)(a_small ? a0[k] + u[k] : a0[k] + j);
+                task.ib = (uint32_t)(a_small ? b0[k] + j : b0[k] + u[k]);
+            }
+            o[k].slot = t0 + (uint64_t)k * 256 + threadIdx.x;
+        }
+#pragma unroll
+        for (int k = 0; k < (int)MATCH_PER_THREAD; ++k)
+            if (o[k].slot != NONE) finish_slot(m, cnt, o[k]);
     } else {
 #pragma unroll
         for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
