@@ -505,26 +505,32 @@ __device__ __forceinline__ void match_block(const MatchArgs& m, uint64_t n_cand,
             av[k] = live[k] ? (m.ia ? m.ia[p] : m.ia0) : 0u;
             bv[k] = live[k] ? (m.ib ? m.ib[p] : m.ib0) : 0u;
         }
-        uint64_t a0[MATCH_PER_THREAD], b0[MATCH_PER_THREAD];
-        uint32_t KA[MATCH_PER_THREAD], KB[MATCH_PER_THREAD];
+        // per candidate from here: the first container of its smaller side
+        // (whose keys are the candidates) and of the searched side, the
+        // searched bitmap, and which side is the smaller
+        uint64_t sb[MATCH_PER_THREAD], lb[MATCH_PER_THREAD];
+        uint32_t sid[MATCH_PER_THREAD];
+        bool asm_[MATCH_PER_THREAD];
 #pragma unroll
         for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
-            a0[k] = b0[k] = 0;
-            KA[k] = KB[k] = 0;
+            sb[k] = lb[k] = 0;
+            sid[k] = 0;
+            asm_[k] = true;
             if (live[k]) {
-                a0[k] = m.A.bm_begin[av[k]];
-                b0[k] = m.B.bm_begin[bv[k]];
-                KA[k] = (uint32_t)(m.A.bm_begin[av[k] + 1] - a0[k]);
-                KB[k] = (uint32_t)(m.B.bm_begin[bv[k] + 1] - b0[k]);
+                const uint64_t a0 = m.A.bm_begin[av[k]], a1 = m.A.bm_begin[av[k] + 1];
+                const uint64_t b0 = m.B.bm_begin[bv[k]], b1 = m.B.bm_begin[bv[k] + 1];
+                asm_[k] = a1 - a0 <= b1 - b0;
+                sb[k] = asm_[k] ? a0 : b0;
+                lb[k] = asm_[k] ? b0 : a0;
+                sid[k] = asm_[k] ? bv[k] : av[k];
             }
         }
         uint16_t key[MATCH_PER_THREAD];
-        uint32_t u[MATCH_PER_THREAD];
 #pragma unroll
         for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
-            u[k] = tg[k] - rel[pos[k]];
+            tg[k] -= rel[pos[k]];  // the candidate's position in its pair
             key[k] = 0;
-            if (live[k]) key[k] = KA[k] <= KB[k] ? m.A.keys[a0[k] + u[k]] : m.B.keys[b0[k] + u[k]];
+            if (live[k]) key[k] = asm_[k] ? m.A.keys[sb[k] + tg[k]] : m.B.keys[sb[k] + tg[k]];
         }
         uint64_t xw[MATCH_PER_THREAD];
         uint32_t xr[MATCH_PER_THREAD];
@@ -534,9 +540,7 @@ __device__ __forceinline__ void match_block(const MatchArgs& m, uint64_t n_cand,
             xr[k] = 0;
             if (live[k]) {
                 // the key index of the side with more keys (the searched one)
-                const bool a_small = KA[k] <= KB[k];
-                const uint8_t* ix = (a_small ? m.B.kidx : m.A.kidx) +
-                                    (uint64_t)(a_small ? bv[k] : av[k]) * RG_KEY_INDEX_BYTES;
+                const uint8_t* ix = (asm_[k] ? m.B.kidx : m.A.kidx) + (uint64_t)sid[k] * RG_KEY_INDEX_BYTES;
                 const uint32_t wi = key[k] >> 6;
                 xw[k] = reinterpret_cast<const uint64_t*>(ix)[wi];
                 xr[k] = reinterpret_cast<const uint16_t*>(ix + 8 * KIDX_WORDS)[wi];
@@ -545,15 +549,14 @@ __device__ __forceinline__ void match_block(const MatchArgs& m, uint64_t n_cand,
 #pragma unroll
         for (int k = 0; k < (int)MATCH_PER_THREAD; ++k) {
             if (!live[k]) continue;
-            const bool a_small = KA[k] <= KB[k];
             const uint32_t j = kidx_lookup(xw[k], xr[k], key[k]);
             Task& task = o[k].task;
             task.pair = (uint32_t)(m.pair0 + pl_lo + pos[k]);
             task.key = key[k];
             if (j != NONE) {
                 task.kind = KIND_MATCH;
-                task.ia = (uint32_t)(a_small ? a0[k] + u[k] : a0[k] + j);
-                task.ib = (uint32_t)(a_small ? b0[k] + j : b0[k] + u[k]);
+                task.ia = (uint32_t)(asm_[k] ? sb[k] + tg[k] : lb[k] + j);
+                task.ib = (uint32_t)(asm_[k] ? lb[k] + j : sb[k] + tg[k]);
             }
             o[k].slot = t0 + (uint64_t)k * 256 + threadIdx.x;
         }
