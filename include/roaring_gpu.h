@@ -108,7 +108,8 @@ typedef struct rg_pool {
     const uint8_t *key_index;  /* optional, may be NULL: [RG_KEY_INDEX_BYTES * n_bitmaps], the
                                   key-presence index rg_pool_key_index writes. When set, key
                                   matching finds a key of this pool's bitmaps with a bit test and
-                                  a popcount instead of a binary search; it must match keys. */
+                                  a popcount instead of a binary search, and k-way queries take
+                                  their key sets from the presence words; it must match keys. */
 } rg_pool;
 
 /* Bytes of the key-presence index per bitmap: 1024 uint64 words with bit
@@ -416,10 +417,14 @@ rg_status rg_profile_read(rg_ctx *ctx, int variant, int materialize, double *tot
  * built directly from the k input containers of its key. flags:
  * RG_FLAG_MATERIALIZE (result bitmap 0 of `out`, which needs bm_wbytes) and/or
  * RG_FLAG_CARD (cardinality into d_card[0], device uint64). Output sizing as
- * for the pairwise calls (RG_ECAPACITY with needed_*): at most min_i K_i (AND),
- * min(65536, sum_i K_i) (OR, XOR) or K_1 (ANDNOT) containers, and the matching
- * min / sum / first of the bm_wbytes bytes.
- * Synchronises on `stream` (one small readback of the ids' key counts). */
+ * for the pairwise calls (RG_ECAPACITY with needed_*), from each bitmap's key
+ * count K_i and first and last key: at most min_i K_i and the keys between
+ * the largest first key and the smallest last key (AND; none when that range
+ * is empty), min(sum_i K_i, the keys between the smallest first key and the
+ * largest last key) (OR, XOR) or K_1 (ANDNOT) containers, and payload bytes
+ * at most the matching min / sum / first of the bm_wbytes and 8192 per
+ * container. Synchronises on `stream` (one small readback of the ids' key
+ * counts, payload bounds and key spans). */
 rg_status roaring_multi(rg_ctx *ctx, int op, const rg_pool *pool, const uint32_t *d_ids, uint32_t k, uint32_t flags,
                         rg_out *out, uint64_t *d_card, void *stream);
 
@@ -466,7 +471,10 @@ typedef struct rg_server rg_server;
  * queries arriving while steps run join the next step, and up to max_inflight
  * (1 or 2) steps are on the GPU at once, on two streams. max_batch = 1 and
  * max_inflight = 1 serve one query at a time. The pool must stay valid and
- * unchanged while the server runs. The server thread uses its own buffers,
+ * unchanged while the server runs; its per-bitmap key counts, payload bounds
+ * and first and last keys are read back here (query bounds as for
+ * roaring_multi), and a key_index on it is used as in roaring_multi. The
+ * server thread uses its own buffers,
  * streams and error record, never the context's, so the caller may go on
  * using ctx for other calls meanwhile (a failed step is reported by
  * rg_serve_poll and rg_serve_stop). */
