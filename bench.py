@@ -1054,7 +1054,7 @@ def serve_roofline_and_cpu(args, ctx, P, h, qs, gen):
     torch.cuda.synchronize()
     pr = rg.profile_read(ctx)
     kw = dict(pr.get(("kway-eval", True)) or {"ms": 0.0, "launches": 0})
-    for extra in ("kway-small", "kway-bb"):  # queries of two bitmaps: one-wave kernels
+    for extra in ("kway-small", "kway-bb", "kway-wave"):  # the one-wave kernels
         if pr.get((extra, True)):
             kw["ms"] += pr[(extra, True)]["ms"]
     rg.profile_enable(ctx, False)
@@ -1094,7 +1094,7 @@ def _line(metric, value, unit, args, ms, config, extra, roof, cpu, dtype="u32"):
 def _kway_eval_ms(prof):
     """ms and launches of the k-way evaluation step (the two one-wave kernels
     and the workgroup kernel, one launch each per call)."""
-    ms = sum(prof[(c, True)]["ms"] for c in ("kway-small", "kway-bb", "kway-eval") if (c, True) in prof)
+    ms = sum(prof[(c, True)]["ms"] for c in ("kway-small", "kway-bb", "kway-wave", "kway-eval") if (c, True) in prof)
     launches = prof[("kway-eval", True)]["launches"] if ("kway-eval", True) in prof else 0
     return ms, launches
 

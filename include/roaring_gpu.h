@@ -397,8 +397,9 @@ rg_status rg_dispatch_table(rg_ctx *ctx, uint8_t *h_table, uint64_t cap);
  * 11 for the k-way evaluation of materialised unions, symmetric differences
  * and differences (items: result slots), 12 for the one-wave kernel that
  * builds those of their results with an array side, 13 for the one-wave
- * kernel that builds their bitset results of bitset containers (items: result
- * slots scanned); variant 3 (RG_V_MERGE) in materialising form is the one-wave
+ * kernel that builds their bitset results of bitset containers, 14 for the
+ * one-wave fold of k-way unions and symmetric differences of up to 64 bitmaps
+ * (items: result slots scanned); variant 3 (RG_V_MERGE) in materialising form is the one-wave
  * array kernel on the intersections that have an array side) in count-only
  * (materialize = 0) or materialising form. Synchronises on the
  * recorded events; costs two events per launch. */

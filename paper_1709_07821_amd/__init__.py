@@ -646,10 +646,11 @@ class Plan:
 
 # rg_profile_read classes (kernel variants; 3 in materialising form is the
 # one-wave array kernel on intersections, 12 the same kernel on k-way slots,
-# 13 the one-wave bitset kernel on k-way slots)
+# 13 the one-wave bitset kernel on k-way slots, 14 the one-wave fold of k-way
+# unions and symmetric differences)
 PROFILE_CLASSES = {0: "bb", 1: "unused", 2: "generic", 3: "merge", 4: "gallop", 5: "probe", 6: "runmerge",
                    7: "thread", 8: "bb-redo", 9: "thread-fused", 10: "count-fused", 11: "kway-eval",
-                   12: "kway-small", 13: "kway-bb"}
+                   12: "kway-small", 13: "kway-bb", 14: "kway-wave"}
 
 
 def profile_enable(ctx: Context, on: bool = True):

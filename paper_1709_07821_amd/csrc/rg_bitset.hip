@@ -46,6 +46,8 @@ __device__ __forceinline__ uint64_t bb_op(int op, uint64_t x, uint64_t y) {
     return op == RG_AND ? (x & y) : op == RG_OR ? (x | y) : op == RG_XOR ? (x ^ y) : (x & ~y);
 }
 
+__device__ __forceinline__ void bb_count(BbWords& w, uint32_t lane);
+
 __device__ __forceinline__ void bb_words(int op, const u32x4* pa, const u32x4* pb, uint32_t lane, BbWords& w) {
     u32x4 x[8], y[8];
 #pragma unroll
@@ -53,7 +55,6 @@ __device__ __forceinline__ void bb_words(int op, const u32x4* pa, const u32x4* p
         x[k] = pa ? __builtin_nontemporal_load(pa + k * 64 + lane) : u32x4{0, 0, 0, 0};
         y[k] = pb ? __builtin_nontemporal_load(pb + k * 64 + lane) : u32x4{0, 0, 0, 0};
     }
-    uint32_t c = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const uint64_t xa = (uint64_t)x[k].x | ((uint64_t)x[k].y << 32);
@@ -62,8 +63,16 @@ __device__ __forceinline__ void bb_words(int op, const u32x4* pa, const u32x4* p
         const uint64_t yb = (uint64_t)y[k].z | ((uint64_t)y[k].w << 32);
         w.lo[k] = bb_op(op, xa, ya);
         w.hi[k] = bb_op(op, xb, yb);
-        c += __popcll(w.lo[k]) + __popcll(w.hi[k]);
     }
+    bb_count(w, lane);
+}
+
+// The result's cardinality w.c and run count w.r from the words in registers
+// (lane l holds words 128k + 2l and 128k + 2l + 1 of the bitset in lo[k], hi[k]).
+__device__ __forceinline__ void bb_count(BbWords& w, uint32_t lane) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c += __popcll(w.lo[k]) + __popcll(w.hi[k]);
     // run starts: bit set and the bit below it (previous word's MSB for bit 0) clear
     uint32_t r = 0;
 #pragma unroll
@@ -236,6 +245,187 @@ __global__ void __launch_bounds__(256) k_kw_bb(KwArgs a) {
             if (lane == 0) a.tasks[slot].bin = KW_TASK_DONE;
         }
     }
+}
+
+// Unions and symmetric differences of more than two bitmaps (k <= 64 per
+// result key, slots marked KW_TASK_WAVE by the bounds kernel), one wave per
+// result key: lane j finds the key's container in bitmap j (presence bit and
+// rank, or binary search); bitset containers are combined in registers, two at
+// a time with all their loads in flight; the values and runs of array and run
+// containers are set (union) or flipped (symmetric difference) in the wave's
+// 8 KiB LDS bitset, WAVE_UNROLL units per lane per round, each lane finding
+// its unit's container by a search over the lanes' unit offsets. The LDS words
+// then join the register words, and the P1 result is written from registers
+// (bb_store_result) or, count-only, its cardinality added to the query's.
+// Against the workgroup kernel: no block barriers, and four keys per
+// workgroup's LDS instead of one.
+constexpr uint32_t WAVE_CHUNK = 8;  // most slots whose tasks a wave reads at once
+constexpr int WAVE_UNROLL = 4;
+
+// exclusive prefix sum over the wave's lanes, and the total
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t& total) {
+    const uint32_t incl = wave_incl_scan_u32(v);
+    total = uniform((uint32_t)__shfl((int)incl, 63));
+    return incl - v;
+}
+
+// lane j's 64-bit value, j chosen per lane
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, uint32_t j) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, (int)j);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), (int)j);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+__global__ void __launch_bounds__(256) k_kw_wave(KwArgs a, uint32_t chunk) {
+    __shared__ uint64_t bits[4][1024];
+    const uint32_t lane = lane_id();
+    uint64_t* L = bits[threadIdx.x >> 6];
+    const uint64_t step = (uint64_t)gridDim.x * 4 * chunk;
+    for (uint64_t c0 = (uint64_t)wave_index() * chunk; c0 < a.n_slots; c0 += step) {
+        bool mine = false;
+        uint32_t pair = 0, key = 0;
+        if (lane < chunk && c0 + lane < a.n_slots) {
+            const Task t = a.tasks[c0 + lane];
+            mine = t.kind == KIND_MATCH && t.bin == KW_TASK_WAVE;
+            pair = t.pair;
+            key = t.key;
+        }
+        uint64_t m = __ballot(mine);
+        while (m) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(m);
+            m &= m - 1;
+            const uint32_t slot = (uint32_t)(c0 + l);
+            const uint32_t q = __builtin_amdgcn_readlane(pair, l) - a.pair_base;
+            const uint16_t kk = (uint16_t)__builtin_amdgcn_readlane(key, l);
+            const KwQuery& Q = a.queries[q];
+            const uint32_t op = uniform(Q.op), k = uniform(Q.k), ids0 = uniform(Q.ids_off);
+            const bool mat = (uniform(Q.flags) & KW_MATERIALIZE) != 0;
+            const bool xr = op == RG_XOR;
+            // lane j: the key's container in bitmap j
+            uint32_t ty = 0, sz = 0;
+            uint64_t off = 0;
+            if (lane < k) {
+                const bool second = lane != 0;
+                const uint32_t ci = kw_find_key(second ? a.P1.bm_begin : a.P0.bm_begin, second ? a.P1.keys : a.P0.keys,
+                                                second ? a.P1.kidx : a.P0.kidx, a.ids[ids0 + lane], kk);
+                if (ci != NONE) {
+                    ty = second ? a.P1.types[ci] : a.P0.types[ci];
+                    sz = second ? a.P1.size[ci] : a.P0.size[ci];
+                    // the payload's address
+                    off = reinterpret_cast<uint64_t>((second ? a.P1.payload : a.P0.payload) +
+                                                     (second ? a.P1.off[ci] : a.P0.off[ci]));
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) L[lane + 64 * i] = 0;
+            // bitsets, combined in registers
+            BbWords w;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) w.lo[i] = w.hi[i] = 0;
+            uint64_t bm = __ballot(ty == RG_BITSET);
+            while (bm) {
+                const uint32_t j0 = (uint32_t)__builtin_ctzll(bm);
+                bm &= bm - 1;
+                const bool two = bm != 0;
+                const uint32_t j1 = two ? (uint32_t)__builtin_ctzll(bm) : j0;
+                if (two) bm &= bm - 1;
+                const u32x4* p0 = reinterpret_cast<const u32x4*>(readlane64(off, j0));
+                const u32x4* p1 = reinterpret_cast<const u32x4*>(readlane64(off, j1));
+                u32x4 x[8], y[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    x[i] = __builtin_nontemporal_load(p0 + i * 64 + lane);
+                    y[i] = two ? __builtin_nontemporal_load(p1 + i * 64 + lane) : u32x4{0, 0, 0, 0};
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const uint64_t xa = (uint64_t)x[i].x | ((uint64_t)x[i].y << 32);
+                    const uint64_t xb = (uint64_t)x[i].z | ((uint64_t)x[i].w << 32);
+                    const uint64_t ya = (uint64_t)y[i].x | ((uint64_t)y[i].y << 32);
+                    const uint64_t yb = (uint64_t)y[i].z | ((uint64_t)y[i].w << 32);
+                    w.lo[i] = xr ? (w.lo[i] ^ xa ^ ya) : (w.lo[i] | xa | ya);
+                    w.hi[i] = xr ? (w.hi[i] ^ xb ^ yb) : (w.hi[i] | xb | yb);
+                }
+            }
+            // array values and runs, into the LDS bitset
+            const uint32_t units = (ty == RG_ARRAY || ty == RG_RUN) ? sz : 0u;
+            uint32_t total;
+            const uint32_t upos = wave_excl_scan(units, total);
+            __builtin_amdgcn_wave_barrier();  // the LDS bitset is cleared
+            for (uint32_t base = 0; base < total; base += 64 * WAVE_UNROLL) {
+                uint32_t raw[WAVE_UNROLL];
+                bool run[WAVE_UNROLL], live[WAVE_UNROLL];
+#pragma unroll
+                for (int r = 0; r < WAVE_UNROLL; ++r) {
+                    const uint32_t u = base + r * 64 + lane;
+                    // the unit's container: the last lane whose offset is <= u
+                    uint32_t j = 0;
+#pragma unroll
+                    for (uint32_t sstep = 32; sstep; sstep >>= 1)
+                        if ((uint32_t)__shfl((int)upos, (int)(j + sstep)) <= u) j += sstep;
+                    const uint32_t tj = (uint32_t)__shfl((int)ty, (int)j);
+                    const uint64_t oj = shfl_u64(off, j);
+                    const uint32_t loc = u - (uint32_t)__shfl((int)upos, (int)j);
+                    live[r] = u < total;
+                    run[r] = tj == RG_RUN;
+                    raw[r] = 0;
+                    if (live[r]) {
+                        const uint8_t* pl = reinterpret_cast<const uint8_t*>(oj);
+                        raw[r] = run[r] ? reinterpret_cast<const uint32_t*>(pl)[loc]
+                                        : (uint32_t)reinterpret_cast<const uint16_t*>(pl)[loc];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < WAVE_UNROLL; ++r) {
+                    if (!live[r]) continue;
+                    if (!run[r]) {
+                        unsigned long long* dst = reinterpret_cast<unsigned long long*>(&L[raw[r] >> 6]);
+                        const unsigned long long bit = 1ull << (raw[r] & 63);
+                        if (xr) atomicXor(dst, bit);
+                        else atomicOr(dst, bit);
+                    } else {
+                        // (a run past the chunk's end in a malformed pool stops at its end)
+                        const uint32_t first = raw[r] & 0xFFFFu, end = first + (raw[r] >> 16);
+                        const uint32_t last = end < 65535u ? end : 65535u;
+                        for (uint32_t wi = first >> 6; wi <= last >> 6; ++wi) {
+                            const uint32_t lo = wi == first >> 6 ? first & 63 : 0;
+                            const uint32_t hi = wi == last >> 6 ? last & 63 : 63;
+                            const unsigned long long mask = (~0ull << lo) & (~0ull >> (63 - hi));
+                            unsigned long long* dst = reinterpret_cast<unsigned long long*>(&L[wi]);
+                            if (xr) atomicXor(dst, mask);
+                            else atomicOr(dst, mask);
+                        }
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();  // every unit is in the LDS bitset
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const uint64_t la = L[2 * (i * 64 + lane)], lb = L[2 * (i * 64 + lane) + 1];
+                w.lo[i] = xr ? (w.lo[i] ^ la) : (w.lo[i] | la);
+                w.hi[i] = xr ? (w.hi[i] ^ lb) : (w.hi[i] | lb);
+            }
+            __builtin_amdgcn_wave_barrier();  // the LDS is read before the output step reuses it
+            bb_count(w, lane);
+            if (mat) {
+                if (w.c) bb_store_result(w, slot, a.so, reinterpret_cast<uint16_t*>(L), lane);
+            } else if (lane == 0 && w.c) {
+                atomicAdd(reinterpret_cast<unsigned long long*>(&a.acc[q]), (unsigned long long)w.c);
+            }
+            if (lane == 0) a.tasks[slot].bin = KW_TASK_DONE;
+            __builtin_amdgcn_wave_barrier();  // the LDS is free for the next key
+        }
+    }
+}
+
+void launch_kw_wave(const KwArgs& a, hipStream_t st) {
+    if (!a.n_slots || !a.wave) return;
+    // a wave's slots are built one after another: as many per wave as it
+    // takes to give every resident wave (about 3072) work, at most WAVE_CHUNK
+    uint64_t chunk = a.n_slots / 3072;
+    chunk = chunk < 1 ? 1 : chunk > WAVE_CHUNK ? WAVE_CHUNK : chunk;
+    const uint64_t g = (a.n_slots + 4 * chunk - 1) / (4 * chunk);
+    hipLaunchKernelGGL(k_kw_wave, dim3(g < 16384 ? (uint32_t)g : 16384u), dim3(256), 0, st, a, (uint32_t)chunk);
 }
 
 void launch_kw_bb(const KwArgs& a, hipStream_t st) {

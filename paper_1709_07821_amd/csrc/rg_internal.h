@@ -38,7 +38,8 @@ constexpr int PROF_FUSED = 10;  // the fused match-and-count kernel of asynchron
 constexpr int PROF_KWEVAL = 11; // k-way evaluation of materialised unions, differences, symmetric differences
 constexpr int PROF_KWSMALL = 12; // the one-wave array kernel on k-way slots
 constexpr int PROF_KWBB = 13;    // the one-wave bitset kernel on k-way slots
-constexpr int NPROF = 14;
+constexpr int PROF_KWWAVE = 14;  // the one-wave fold of k-way unions and symmetric differences
+constexpr int NPROF = 15;
 
 struct Task {
     uint32_t pair;
@@ -434,6 +435,15 @@ constexpr uint8_t KW_TASK_SMALL = 2;
 // one-wave bitset kernel builds the result and marks the task KW_TASK_DONE
 constexpr uint8_t KW_TASK_BB = 3;
 constexpr uint8_t KW_TASK_DONE = 4;
+// ... of a union or symmetric difference of more than two bitmaps with at most
+// KW_WAVE_MAX_K bitmaps: one wave folds the key's containers (k_kw_wave) and
+// marks the task KW_TASK_DONE
+constexpr uint8_t KW_TASK_WAVE = 5;
+constexpr uint32_t KW_WAVE_MAX_K = 64;
+// steps with more slots use k_kw_wave (measured on serving steps: past about
+// 32 queries of 1024 result keys the wave fold serves more queries per second,
+// below it the workgroup kernel has the lower latency)
+constexpr uint64_t KW_WAVE_MIN_SLOTS = 32768;
 __host__ __device__ __forceinline__ bool bb_mat_ok(int op, uint8_t ta, uint8_t tb) {
     if (ta == RG_BITSET && tb == RG_BITSET) return true;
     if (ta == RG_BITSET && tb == 0) return op != RG_AND;             // A alone: union, xor, difference
@@ -481,11 +491,36 @@ struct KwArgs {
     uint32_t* err;      // set when a query's key set exceeds its slot range
     uint32_t small = 1; // materialised results with an array side go to the one-wave kernel
     uint32_t eval_chunk = 0;  // slots per evaluation workgroup chunk (1..64; 0: by the slot count)
+    uint32_t wave = 0;        // unions and symmetric differences of many bitmaps go to k_kw_wave
     const KwPart* parts = nullptr;  // parts of split key passes
     uint32_t n_parts = 0;
     uint64_t* kmask = nullptr;      // 1024 words per split query, zero before the key pass
     uint32_t* kdone = nullptr;      // parts finished, per split query, zero before the key pass
 };
+// The container of `key` in bitmap b (its global index), or NONE. With the
+// pool's key-presence index: the presence bit, then the word's rank plus the
+// popcount of the bits below (two independent loads); otherwise a binary
+// search of the bitmap's keys.
+__device__ __forceinline__ uint32_t kw_find_key(const uint64_t* bm_begin, const uint16_t* keys, const uint8_t* kidx,
+                                                uint32_t b, uint16_t key) {
+    const uint64_t s = bm_begin[b], e = bm_begin[b + 1];
+    if (kidx) {
+        const uint8_t* ix = kidx + (uint64_t)b * RG_KEY_INDEX_BYTES;
+        const uint32_t wi = key >> 6, bit = key & 63u;
+        const uint64_t x = reinterpret_cast<const uint64_t*>(ix)[wi];
+        const uint32_t rank = reinterpret_cast<const uint16_t*>(ix + 8 * KIDX_WORDS)[wi];
+        if (!((x >> bit) & 1ull)) return NONE;
+        return (uint32_t)(s + rank + (uint32_t)__popcll(x & ((1ull << bit) - 1ull)));
+    }
+    uint64_t lo = s, hi = e;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < e && keys[lo] == key) ? (uint32_t)lo : NONE;
+}
+
 // kmask / kdone: the split queries' key masks (n_masks x 1024 words) and arrival counters, zeroed
 void launch_kw_step_init(uint64_t* totals, uint32_t* err, long long* acc, uint64_t* bm_card, uint64_t* bm_wbytes,
                          uint32_t nq, uint64_t* kmask, uint32_t* kdone, uint32_t n_masks, hipStream_t st);
@@ -499,6 +534,7 @@ void launch_kw_bounds(const KwArgs& a, hipStream_t st, bool pairs_only = false);
 // bounds kernel marked (rg_small.hip), the workgroup kernel for the others
 void launch_kw_small(const KwArgs& a, hipStream_t st);
 void launch_kw_bb(const KwArgs& a, hipStream_t st);
+void launch_kw_wave(const KwArgs& a, hipStream_t st);
 void launch_kw_eval(const KwArgs& a, hipStream_t st);
 void launch_kw_cards(const KwArgs& a, const uint64_t* bm_card, uint64_t* cards, hipStream_t st);
 // queries q < n_pairs for pairs pair0 + q (k = 2: A side, B side), slot ranges

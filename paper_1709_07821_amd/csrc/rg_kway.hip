@@ -39,30 +39,6 @@ constexpr uint64_t KW_EVAL_FEW = 8192;  // slots up to which each gets its own e
 // workgroup; with many, chunks of 4 save workgroup starts and task reads
 // (measured on pairwise calls: 1, 4, 16; on k-way steps of 1e3 to 2.5e5 slots).
 
-// The container of `key` in bitmap b (its global index), or NONE. With the
-// pool's key-presence index: the presence bit, then the word's rank plus the
-// popcount of the bits below (two independent loads); otherwise a binary
-// search of the bitmap's keys.
-__device__ __forceinline__ uint32_t kw_find_key(const uint64_t* bm_begin, const uint16_t* keys, const uint8_t* kidx,
-                                                uint32_t b, uint16_t key) {
-    const uint64_t s = bm_begin[b], e = bm_begin[b + 1];
-    if (kidx) {
-        const uint8_t* ix = kidx + (uint64_t)b * RG_KEY_INDEX_BYTES;
-        const uint32_t wi = key >> 6, bit = key & 63u;
-        const uint64_t x = reinterpret_cast<const uint64_t*>(ix)[wi];
-        const uint32_t rank = reinterpret_cast<const uint16_t*>(ix + 8 * KIDX_WORDS)[wi];
-        if (!((x >> bit) & 1ull)) return NONE;
-        return (uint32_t)(s + rank + (uint32_t)__popcll(x & ((1ull << bit) - 1ull)));
-    }
-    uint64_t lo = s, hi = e;
-    while (lo < hi) {
-        const uint64_t mid = (lo + hi) >> 1;
-        if (keys[mid] < key) lo = mid + 1;
-        else hi = mid;
-    }
-    return (lo < e && keys[lo] == key) ? (uint32_t)lo : NONE;
-}
-
 // The pool of a query's j-th bitmap, selected field by field (plain pointer
 // selects; no address arithmetic on the kernel-argument block).
 __device__ __forceinline__ PoolView kw_side(const KwArgs& a, bool second) {
@@ -629,10 +605,18 @@ __global__ void __launch_bounds__(256) k_kw_bounds(KwArgs a) {
     if (s >= a.n_slots) return;  // wave-uniform
     const Task t = uniform_task(a.tasks, (uint32_t)s);
     uint32_t ub = 0;
-    uint8_t mark = 0;  // KW_TASK_SMALL / KW_TASK_BB: the slot's one-wave kernel
+    uint8_t mark = 0;  // KW_TASK_SMALL / KW_TASK_BB / KW_TASK_WAVE: the slot's one-wave kernel
     if (t.kind == KIND_MATCH) {
         const KwQuery* Qp = a.queries + (t.pair - a.pair_base);
         const uint32_t flags = uniform(Qp->flags);
+        {
+            // unions and symmetric differences of more than two bitmaps (tasks
+            // without recorded containers), at most KW_WAVE_MAX_K of them:
+            // folded by one wave, materialised or counted
+            const uint32_t op = uniform(Qp->op), k = uniform(Qp->k);
+            if (a.wave && t.bin != KW_TASK_INDEXED && (op == RG_OR || op == RG_XOR) && k <= KW_WAVE_MAX_K)
+                mark = KW_TASK_WAVE;
+        }
         if (flags & KW_MATERIALIZE) {
             const uint32_t op = uniform(Qp->op), k = uniform(Qp->k), ids0 = uniform(Qp->ids_off);
             // AND: the smallest container; OR, XOR: the sum; ANDNOT: the first

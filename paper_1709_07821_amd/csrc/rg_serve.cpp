@@ -265,9 +265,14 @@ rg_status step_enqueue(std::string* err_out, const rg_pool& pool, const StepLayo
     a.n_parts = L.n_parts;
     a.kmask = kmask;
     a.kdone = kdone;
-    // the one-wave kernels take only queries of at most two bitmaps; skip
-    // their launches when the step has none (L.pairs), and the workgroup key
-    // kernel when every query of more bitmaps is split (L.whole)
+    // Steps of many slots fold unions and symmetric differences of up to 64
+    // bitmaps by one wave per result key (more keys in flight: throughput);
+    // smaller steps keep one workgroup per key (four times the lanes per key:
+    // latency)
+    a.wave = L.big && L.S > KW_WAVE_MIN_SLOTS;
+    // the one-wave array and bitset kernels take only queries of at most two
+    // bitmaps; skip their launches when the step has none (L.pairs), and the
+    // workgroup key kernel when every query of more bitmaps is split (L.whole)
     launch_kw_keys(a, st, L.pairs, L.whole);
     launch_kw_bounds(a, st, !L.big);
     if (L.S) launch_scan_u32_u64(ub, slot_off, L.S, 0, partials, totals, st);
@@ -276,12 +281,14 @@ rg_status step_enqueue(std::string* err_out, const rg_pool& pool, const StepLayo
             timed(prof, PROF_KWSMALL, true, L.S, st, [&] { launch_kw_small(a, st); });
             timed(prof, PROF_KWBB, true, L.S, st, [&] { launch_kw_bb(a, st); });
         }
+        if (a.wave) timed(prof, PROF_KWWAVE, true, L.S, st, [&] { launch_kw_wave(a, st); });
         timed(prof, PROF_KWEVAL, true, L.S, st, [&] { launch_kw_eval(a, st); });
     } else {
         if (L.pairs) {
             launch_kw_small(a, st);
             launch_kw_bb(a, st);
         }
+        if (a.wave) launch_kw_wave(a, st);
         launch_kw_eval(a, st);
     }
     if (L.S) {

@@ -324,3 +324,33 @@ def test_multi_key_spans_and_split_passes(rg, ctx, kidx):
     _say(f"[spans serve] {st}")
     for i, (c, d) in enumerate(exp):
         assert cards[i] == c and dig[i] == d, i
+
+
+@pytest.mark.parametrize("kidx", [False, True], ids=["search", "key-index"])
+def test_server_wave_fold_large_steps(rg, ctx, kidx):
+    """Steps of more than 8192 slots fold unions and symmetric differences of up
+    to 64 bitmaps one wave per result key (k_kw_wave): 64 such queries (k from
+    3 to 64, materialised and count-only) in steps of up to 64, against the
+    oracle, and the same queries one at a time (workgroup evaluation)."""
+    bs = overlapping_sets(n=40, seed=17)
+    P = rg.Pool.from_sets(bs.values, bs.offsets)
+    if kidx:
+        P.key_index(ctx)
+    rng = np.random.default_rng(41)
+    qs = []
+    for i in range(64):
+        k = int(rng.integers(3, 65))
+        ids = rng.choice(len(bs), size=k, replace=k > len(bs)).astype(np.uint32)
+        qs.append((("or", "xor")[i % 2], ids, i % 3 != 2))
+    exp = _expect(bs, qs)
+    big = rg.Server(ctx, P, arena_bytes=512 << 20, max_batch=64, max_inflight=1)
+    _, cards, dig = big.replay(qs, np.zeros(len(qs), np.uint64), digest=True)
+    st = big.stop()
+    _say(f"[wave fold kidx={kidx}] {st}")
+    assert st["mean_batch"] > 8  # most queries ran in large steps
+    for i, (c, d) in enumerate(exp):
+        assert cards[i] == c and dig[i] == d, ("batched", i)
+    one = rg.Server(ctx, P, arena_bytes=512 << 20, max_batch=1, max_inflight=1)
+    _, cards1, dig1 = one.replay(qs, np.zeros(len(qs), np.uint64), digest=True)
+    one.stop()
+    assert np.array_equal(cards1, cards) and np.array_equal(dig1, dig)
