@@ -48,13 +48,17 @@ __device__ __forceinline__ uint64_t bb_op(int op, uint64_t x, uint64_t y) {
 
 __device__ __forceinline__ void bb_count(BbWords& w, uint32_t lane);
 
-__device__ __forceinline__ void bb_words(int op, const u32x4* pa, const u32x4* pb, uint32_t lane, BbWords& w) {
-    u32x4 x[8], y[8];
+// the lane's 16 words of a bitset container (zeros for an absent one)
+__device__ __forceinline__ void bb_load(const u32x4* p, uint32_t lane, u32x4 (&x)[8]) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        x[k] = pa ? __builtin_nontemporal_load(pa + k * 64 + lane) : u32x4{0, 0, 0, 0};
-        y[k] = pb ? __builtin_nontemporal_load(pb + k * 64 + lane) : u32x4{0, 0, 0, 0};
-    }
+    for (int k = 0; k < 8; ++k) x[k] = p ? __builtin_nontemporal_load(p + k * 64 + lane) : u32x4{0, 0, 0, 0};
+}
+
+// A's words already loaded (x), B's loaded here, combined by op
+__device__ __forceinline__ void bb_words_x(int op, const u32x4 (&x)[8], const u32x4* pb, uint32_t lane,
+                                           BbWords& w) {
+    u32x4 y[8];
+    bb_load(pb, lane, y);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const uint64_t xa = (uint64_t)x[k].x | ((uint64_t)x[k].y << 32);
@@ -65,6 +69,12 @@ __device__ __forceinline__ void bb_words(int op, const u32x4* pa, const u32x4* p
         w.hi[k] = bb_op(op, xb, yb);
     }
     bb_count(w, lane);
+}
+
+__device__ __forceinline__ void bb_words(int op, const u32x4* pa, const u32x4* pb, uint32_t lane, BbWords& w) {
+    u32x4 x[8];
+    bb_load(pa, lane, x);
+    bb_words_x(op, x, pb, lane, w);
 }
 
 // The result's cardinality w.c and run count w.r from the words in registers
@@ -232,15 +242,30 @@ __global__ void __launch_bounds__(256) k_kw_bb(KwArgs a) {
             }
         }
         uint64_t m = __ballot(mine);
+        // software pipeline: the next slot's A-side words are loaded while the
+        // current slot's result is built and written
+        auto a_words = [&](uint32_t l) {
+            const uint32_t hl = __builtin_amdgcn_readlane(has, l);
+            return (hl & 1u) ? reinterpret_cast<const u32x4*>(a.P0.payload + readlane64(oa, l)) : nullptr;
+        };
+        u32x4 xn[8];
+        uint32_t ln = m ? (uint32_t)__builtin_ctzll(m) : 0u;
+        if (m) bb_load(a_words(ln), lane, xn);
         while (m) {
-            const uint32_t l = (uint32_t)__builtin_ctzll(m);
+            const uint32_t l = ln;
             m &= m - 1;
+            u32x4 x[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) x[k] = xn[k];
+            if (m) {
+                ln = (uint32_t)__builtin_ctzll(m);
+                bb_load(a_words(ln), lane, xn);
+            }
             const uint32_t slot = (uint32_t)(c0 + l);
             const uint32_t hl = __builtin_amdgcn_readlane(has, l);
-            const u32x4* pa = (hl & 1u) ? reinterpret_cast<const u32x4*>(a.P0.payload + readlane64(oa, l)) : nullptr;
             const u32x4* pb = (hl & 2u) ? reinterpret_cast<const u32x4*>(a.P1.payload + readlane64(ob, l)) : nullptr;
             BbWords w;
-            bb_words((int)__builtin_amdgcn_readlane(op, l), pa, pb, lane, w);
+            bb_words_x((int)__builtin_amdgcn_readlane(op, l), x, pb, lane, w);
             if (w.c) bb_store_result(w, slot, a.so, lds[threadIdx.x >> 6], lane);
             if (lane == 0) a.tasks[slot].bin = KW_TASK_DONE;
         }
