@@ -413,9 +413,13 @@ def bench_pairs_materialised(args, bs, ia, ib, workload, metric_config):
         assert np.array_equal(jaccs[op].cpu().numpy(), j_exp), op
     say(f"{n} pairs x 4 ops materialised: counts, fingerprints and Jaccard match the oracle")
 
+    # the timed calls write into the arenas and output vectors of the gate
+    # (a caller preallocates them; the library call does all the work)
+    mat_flags = rg.RG_FLAG_MATERIALIZE | rg.RG_FLAG_CARD | rg.RG_FLAG_JACCARD
+
     def step():
         for op in OPS4:
-            rg.batch(ctx, op, P, P, tia, tib, materialize=True, card=True, jaccard=True, out=arenas[op])
+            ctx.check(rg.roaring_batch(ctx, op, P, P, tia, tib, mat_flags, arenas[op], cards[op], jaccs[op]))
 
     dt = time_steps(step, args.steps, args.warmup)
     rg.profile_enable(ctx, True)
@@ -537,8 +541,9 @@ def bench_dense_mat(args):
     tia = torch.from_numpy(ia.view(np.int32)).to(dev)
     tib = torch.from_numpy(ib.view(np.int32)).to(dev)
     arenas = {}
+    cards = {}
     for op in rg.OPS:
-        arenas[op], _, _ = rg.batch(ctx, op, P, P, tia, tib, materialize=True, card=True)
+        arenas[op], cards[op], _ = rg.batch(ctx, op, P, P, tia, tib, materialize=True, card=True)
     torch.cuda.synchronize()
     # correctness gate: two pairs of every op against the oracle (fingerprints)
     for op in rg.OPS:
@@ -551,7 +556,8 @@ def bench_dense_mat(args):
 
     def step():
         for op in rg.OPS:
-            rg.batch(ctx, op, P, P, tia, tib, materialize=True, card=True, out=arenas[op])
+            ctx.check(rg.roaring_batch(ctx, op, P, P, tia, tib, rg.RG_FLAG_MATERIALIZE | rg.RG_FLAG_CARD, arenas[op],
+                                       cards[op]))
 
     dt = time_steps(step, args.steps, args.warmup)
     in_bytes = 4 * npairs * nk * 2 * 8192
