@@ -259,6 +259,32 @@ def test_server_all_ops_while_context_busy(rg, ctx):
     _say(f"[serve all ops, busy context] {st}")
 
 
+def _kway_bounds(op, sets):
+    """The result bounds of a k-way query written out from the bitmaps: keys
+    between the extreme first and last keys (union, symmetric difference) or
+    the inner ones (intersection), capped by the key counts; payload bytes
+    capped by 8 KiB per container."""
+    keys = [np.unique(np.asarray(v, np.uint64) >> np.uint64(16)) for v in sets]
+    wb = []
+    for v in sets:
+        c = oracle.containers(np.asarray(v, np.uint32))
+        wb.append(int(sum(((min(8192, 2 * int(x)) + 15) // 16) * 16 for x in c["card"])))
+    nk = [len(k) for k in keys]
+    nonempty = [k for k in keys if len(k)]
+    if op == "and":
+        kb = 0
+        if all(nk):
+            lo, hi = max(int(k[0]) for k in keys), min(int(k[-1]) for k in keys)
+            kb = min(min(nk), hi - lo + 1) if hi >= lo else 0
+        pb = min(wb)
+    elif op == "andnot":
+        kb, pb = nk[0], wb[0]
+    else:
+        kb = min(sum(nk), max(int(k[-1]) for k in nonempty) - min(int(k[0]) for k in nonempty) + 1) if nonempty else 0
+        pb = sum(wb)
+    return kb, min(pb, kb * 8192)
+
+
 def span_sets():
     """Bitmaps built to exercise the key bounds (first and last key of each
     bitmap: intersections of overlapping, disjoint and empty key ranges, unions
@@ -311,6 +337,10 @@ def test_multi_key_spans_and_split_passes(rg, ctx, kidx):
         out, card = rg.multi(ctx, op, P, tids, materialize=True, card=True)
         torch.cuda.synchronize()
         assert int(card[0].item()) == len(exp), (op, ids)
+        # the arena the call asked for: result-container and payload bounds
+        # from each bitmap's key count, first and last key and payload bound
+        kb, pb = _kway_bounds(op, [bs[int(i)] for i in ids])
+        assert (int(out.c.needed_containers), int(out.c.needed_payload_bytes)) == (kb, pb), (op, ids)
         h = out.as_pool().to_host()
         got, meta = rgtest.decode_bitmap(h, 0)
         assert np.array_equal(got, exp), (op, ids)
