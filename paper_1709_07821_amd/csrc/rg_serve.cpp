@@ -358,10 +358,14 @@ extern "C" rg_status roaring_multi(rg_ctx* c, int op, const rg_pool* pool, const
     void* mbase = nullptr;
     if (rg_status s = sc.take(WS_PAIRS, align256(32 * k) + 256, &mbase)) return s;
     auto* d_meta = reinterpret_cast<uint64_t*>(mbase);
-    auto* h_meta = reinterpret_cast<uint64_t*>(c->host);  // 32 k <= 8 KiB: the pinned staging
+    // the pinned staging: 32 k <= 8 KiB of metadata, then the ids (both in one readback)
+    auto* h_meta = reinterpret_cast<uint64_t*>(c->host);
+    auto* h_ids = reinterpret_cast<uint32_t*>(h_meta + 4 * k);
     launch_kw_gather_meta(pool->bm_begin, pool->keys, pool->bm_wbytes, pool->n_bitmaps, d_ids, k, d_meta, st);
     HIPCHK(c, hipMemcpyAsync(h_meta, d_meta, 32 * k, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(h_ids, d_ids, 4ull * k, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
+    const std::vector<uint32_t> ids(h_ids, h_ids + k);  // the staging is reused below
     for (uint32_t j = 0; j < k; ++j)
         if (!h_meta[4 * j + 2]) return fail(c, RG_EINVAL, "roaring_multi: bitmap id out of range of the pool");
     const Bounds b = query_bounds(op, k, h_meta, mat);
@@ -391,8 +395,7 @@ extern "C" rg_status roaring_multi(rg_ctx* c, int op, const rg_pool* pool, const
     if (rg_status s = host_buffer(c, L.down_off + L.down_bytes + 256, &h)) return s;
     auto* d = reinterpret_cast<uint8_t*>(wbase);
     // the ids into the staging copy (the step uploads the whole section)
-    HIPCHK(c, hipMemcpyAsync(h + L.o_ids, d_ids, 4ull * k, hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
+    memcpy(h + L.o_ids, ids.data(), 4ull * k);
     memcpy(h + L.o_queries, qs.data(), sizeof(KwQuery));
     if (!parts.empty()) memcpy(h + L.o_parts, parts.data(), sizeof(KwPart) * parts.size());
     reinterpret_cast<uint64_t*>(h + L.o_cand)[0] = 0;
